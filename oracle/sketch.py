@@ -1,0 +1,79 @@
+"""Algorithm 1, step 1: the sketch Y = Omega [A b] (oracle, test use only).
+
+Definition (Section 2 and Algorithm 1; the sketch of [A b] rather than of A
+alone is this build's reading of how Q^T Omega b in Algorithm 2's
+sketch-and-solve start is obtained without forming Q):
+
+    M   = [A b] * diag(2^e)                 (Section 3.2 column scaling; e = 0 for
+                                             bf16, f32 and f64)
+    M_q = T_1 + ... + T_terms,  T_t = fl_us(M - T_1 - ... - T_{t-1})
+                                            (A "stored in precision u_s";
+                                             terms > 1 is a multi-term split)
+    S_q = fl_us(fl_32(S))                   (entries of S: ``philox.gaussian_block``;
+                                             the f64 sketch uses S unrounded)
+    Y   = (1/sqrt(s)) * (S_q M_q) * diag(2^-e)
+
+computed here with exact binary64 operands and a binary64 matrix product.
+"""
+
+import numpy as np
+
+from . import formats, philox
+
+
+def quantised_gaussian_block(seed, prob, k0, k1, i0, i1, fmt):
+    """S entries rounded as the sketch format requires (float64 array)."""
+    z = philox.gaussian_block(seed, prob, k0, k1, i0, i1)
+    if fmt == "f64":
+        return z
+    z32 = z.astype(np.float32).astype(np.float64)
+    return formats.round_to(z32, fmt)
+
+
+def scaled_operand(At: np.ndarray, b: np.ndarray, fmt: str, terms: int, colscale: bool):
+    """(M_q, e): the quantised, column-scaled [A b] (m x (n+1)) and the exponents."""
+    m, n = At.shape[1], At.shape[0]
+    M = np.empty((m, n + 1))
+    M[:, :n] = At.T
+    M[:, n] = b
+    e = formats.column_exponents(M, fmt) if colscale else np.zeros(n + 1, dtype=np.int32)
+    Ms = M * np.ldexp(1.0, e.astype(np.int64))[None, :]
+    if fmt == "f64":
+        return Ms, e
+    Mq = np.sum(formats.split_terms(Ms, fmt, terms), axis=0)
+    return Mq, e
+
+
+def sketch(At: np.ndarray, b: np.ndarray, s: int, seed: int, prob: int = 0, fmt: str = "f64",
+           terms: int = 1, colscale: bool = False, chunk: int = 4096):
+    """Y = Omega [A b] as defined in the module docstring.
+
+    Returns (Y (s x (n+1)) float64, e (n+1) int32).
+    """
+    Mq, e = scaled_operand(At, b, fmt, terms, colscale)
+    m = Mq.shape[0]
+    Y = np.zeros((s, Mq.shape[1]))
+    for i0 in range(0, m, chunk):
+        i1 = min(m, i0 + chunk)
+        S = quantised_gaussian_block(seed, prob, 0, s, i0, i1, fmt)
+        Y += S @ Mq[i0:i1]
+    Y *= 1.0 / np.sqrt(s)
+    Y *= np.ldexp(1.0, -e.astype(np.int64))[None, :]
+    return Y, e
+
+
+def sketch_rows(At, b, s, seed, rows, prob=0, fmt="f64", terms=1, colscale=False, chunk=65536):
+    """Selected rows Y[rows, :] of the same sketch (each costs m (n+1) flops)."""
+    Mq, e = scaled_operand(At, b, fmt, terms, colscale)
+    m = Mq.shape[0]
+    out = np.zeros((len(rows), Mq.shape[1]))
+    for t, k in enumerate(rows):
+        acc = np.zeros(Mq.shape[1])
+        for i0 in range(0, m, chunk):
+            i1 = min(m, i0 + chunk)
+            S = quantised_gaussian_block(seed, prob, k, k + 1, i0, i1, fmt)
+            acc += S[0] @ Mq[i0:i1]
+        out[t] = acc
+    out *= 1.0 / np.sqrt(s)
+    out *= np.ldexp(1.0, -e.astype(np.int64))[None, :]
+    return out
