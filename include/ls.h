@@ -1,0 +1,202 @@
+/*
+ * ls.h -- C ABI of libls: sketch-preconditioned least squares on one MI355X.
+ *
+ * Method: Carson and Dauzickaite, "Mixed precision sketching for
+ * least-squares problems and its application in GMRES-based iterative
+ * refinement".  Problem (Section 1, eq. LS_problem): min_x ||b - A x||_2 with
+ * A dense, m x n, full rank, m >= n.  Algorithm 1 builds R from a sketch,
+ * Algorithm 2 runs preconditioned LSQR and then refinement on the augmented
+ * system [I A; A^T 0][r; x] = [b; 0] with split-preconditioned FGMRES.
+ *
+ * Conventions for every entry point:
+ *  - Matrices are column major: element (i, j) of a matrix with leading
+ *    dimension ld is at offset i + j * ld.
+ *  - Pointers named as device pointers must be device memory of the current
+ *    HIP device; the library never allocates or frees them.  Scratch space is
+ *    the caller's workspace (size from ls_workspace_size), device memory,
+ *    256-byte aligned.
+ *  - `stream` is a hipStream_t (passed as void*); NULL is the default stream.
+ *    All work is enqueued on it.  Entry points that iterate synchronise the
+ *    stream at their convergence checks and before returning, so their
+ *    outputs and statistics are valid on return.  ls_sketch, ls_qr_r and
+ *    ls_omega do not synchronise.
+ *  - Errors are returned as negative status codes; nothing aborts or throws
+ *    across the ABI.  ls_strerror(code) gives a message.
+ *  - Calls that share a workspace must not overlap in time.
+ */
+#ifndef LS_H
+#define LS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Floating-point formats (unit roundoffs in Section 5: 2^-53 double, 2^-24
+ * single, 2^-11 half; bf16 2^-8, e4m3 2^-4).  LS_FP64X2 is a double-double
+ * accumulation format used only for the refinement residual (u_r). */
+typedef enum {
+  LS_FP64 = 0,
+  LS_FP32 = 1,
+  LS_FP16 = 2,
+  LS_BF16 = 3,
+  LS_FP8E4M3 = 4,
+  LS_FP64X2 = 5
+} ls_prec_t;
+
+enum {
+  LS_OK = 0,
+  LS_NOT_CONVERGED = 1,   /* outputs hold the last iterate (Section 5's "-" entries) */
+  LS_E_ARG = -1,          /* bad size, pointer, leading dimension or precision choice */
+  LS_E_WORKSPACE = -2,    /* workspace smaller than ls_workspace_size reports */
+  LS_E_HIP = -3,          /* a HIP runtime call failed */
+  LS_E_SINGULAR = -4,     /* zero or non-finite diagonal in R: A is rank deficient in u_s */
+  LS_E_NONFINITE = -5,    /* NaN or Inf met in an iterate */
+  LS_E_UNSUPPORTED = -6   /* combination not implemented in this build */
+};
+
+/* One least-squares problem (Section 1).  A: device, m x n column major,
+ * lda >= m.  b: device, length m.  Both stored in `store` (LS_FP32 or
+ * LS_FP64); Section 5 stores A and b in the working precision. */
+typedef struct {
+  int64_t m, n;
+  ls_prec_t store;
+  const void *A;
+  int64_t lda;
+  const void *b;
+} ls_problem_t;
+
+/* Precisions of Algorithms 1 and 2 (Sections 3 and 4):
+ *  u_s  sketch (Algorithm 1 step 1): LS_FP64 or LS_BF16
+ *  u_qr QR of the sketch (Algorithm 1 step 2): LS_FP32 or LS_FP64
+ *  u    working precision of LSQR, FGMRES and the stored x, r: LS_FP32 or LS_FP64
+ *  u_r  refinement residual and R^-T g (Algorithm 2 lines 5-6): LS_FP64 or LS_FP64X2
+ *  u_A, u_L, u_R  products with Atilde, M_L^-1, M_R^-1 inside FGMRES: LS_FP32 or LS_FP64,
+ *       not coarser than u.  The Arnoldi process itself runs in binary64. */
+typedef struct {
+  ls_prec_t u_s, u_qr, u, u_r, u_A, u_L, u_R;
+} ls_precs_t;
+
+/* Sketch options (Section 2: Gaussian embedding, s = c n with small c;
+ * Section 5 uses s = 4n).  Omega = S / sqrt(s), S[k, i] drawn from the
+ * Philox4x32-10 block with counter (i / 4, k, prob_id, 0) and key
+ * (seed mod 2^32, seed / 2^32) by Box-Muller on 23-bit uniforms.
+ * terms: A (and b) are represented in u_s as a sum of `terms` rounded parts
+ * (1 = a plain cast; 2 or 3 recover binary32 accuracy on the same MFMA). */
+typedef struct {
+  int64_t s;         /* sketch rows, s >= n + 1; 0 selects 4n */
+  uint64_t seed;
+  uint32_t prob_id;
+  int32_t terms;     /* 1..3 for LS_BF16; 1 for LS_FP64 */
+} ls_sketch_opts_t;
+
+/* Iteration control (Section 5): LSQR at most 2n iterations, tolerance 1e-6
+ * (u single) or 1e-12 (u double); FGMRES at most 50 iterations with the same
+ * tolerance; at most 30 refinement steps.  Zero fields select those defaults.
+ * lsir_tol: refinement stops once ||dx|| <= lsir_tol ||x|| and
+ * ||dr|| <= lsir_tol ||r|| (default 4u).  fallback != 0 repeats the
+ * refinement with u_A = u_L = u_R = binary64 and at most 80 FGMRES iterations
+ * when it has not converged (Section 5). */
+typedef struct {
+  double lsqr_tol;
+  int32_t lsqr_maxit;
+  double fgmres_tol;
+  int32_t fgmres_maxit;
+  int32_t lsir_maxit;
+  double lsir_tol;
+  int32_t fallback;
+  int32_t check_every;   /* iterations between host convergence checks (default 8) */
+} ls_iter_opts_t;
+
+/* Results and timings of one call. */
+typedef struct {
+  int32_t status;
+  int32_t lsqr_its;
+  int32_t lsir_its;
+  int32_t fgmres_its_total;
+  int32_t fallback_used;
+  double lsqr_normr;      /* LSQR estimate of ||b - A x0|| */
+  double lsqr_normar;     /* LSQR estimate of ||(A R^-1)^T (b - A x0)|| */
+  double lsqr_normB;      /* LSQR estimate of ||A R^-1||_F */
+  double lsir_dx_rel;     /* last ||dx|| / ||x|| */
+  double lsir_dr_rel;     /* last ||dr|| / ||r|| */
+  double ms_sketch, ms_qr, ms_lsqr, ms_lsir;
+} ls_stats_t;
+
+/* Fill the defaults described above for a problem with n columns and
+ * working precision u. */
+void ls_default_iter_opts(int64_t n, ls_prec_t u, ls_iter_opts_t *opts);
+
+/* Bytes of workspace ls_solve needs for this problem and these options
+ * (the individual entry points need no more than that).  Returns LS_OK or
+ * LS_E_ARG. */
+int ls_workspace_size(const ls_problem_t *P, const ls_sketch_opts_t *so,
+                      const ls_precs_t *pr, const ls_iter_opts_t *io, size_t *bytes);
+
+/* Algorithm 1 step 1 on [A b]: Y = Omega [A b], s x (n+1), binary64,
+ * column major with leading dimension ldy >= s (device).  Column n is
+ * Omega b, which Algorithm 2's sketch-and-solve start needs.  With u_s =
+ * LS_BF16 the entries of S are rounded to bf16 from binary32 Box-Muller
+ * values, A and b are represented as `terms` bf16 parts, products run on
+ * MFMA with binary32 accumulation over chunks of rows of A and the chunks
+ * are summed in binary64.  With u_s = LS_FP64 everything is binary64. */
+int ls_sketch(const ls_problem_t *P, const ls_sketch_opts_t *so, ls_prec_t u_s,
+              double *Y, int64_t ldy, void *ws, size_t ws_bytes, void *stream);
+
+/* Algorithm 1 step 2: economic Householder QR of Y (s x ncols, binary64,
+ * device, overwritten) in precision u_qr, returning only R: ncols x ncols
+ * upper triangular with positive diagonal, binary64, leading dimension
+ * ldr (device; the strictly lower part is set to zero).  With Y = Omega[A b]
+ * and ncols = n + 1, R[0:n, 0:n] is the preconditioner and R[0:n, n] is
+ * Q^T Omega b (Algorithm 2, sketch-and-solve start). */
+int ls_qr_r(int64_t s, int64_t ncols, ls_prec_t u_qr, double *Y, int64_t ldy,
+            double *R, int64_t ldr, void *ws, size_t ws_bytes, void *stream);
+
+/* Algorithm 2 line 1: LSQR on A R^-1 (right preconditioning, Paige and
+ * Saunders' recurrences) in precision u, started from x (device, length n,
+ * binary64 in and out; typically x^s = R^-1 Q^T Omega b).  R: device, n x n
+ * upper triangular, binary64, leading dimension ldr.  Stops when
+ * ||r|| <= tol ||b|| or ||B^T r|| <= tol ||B||_F,est ||r||, or after
+ * lsqr_maxit iterations (then LS_NOT_CONVERGED).  stats may be NULL. */
+int ls_lsqr_precond(const ls_problem_t *P, const double *R, int64_t ldr, ls_prec_t u,
+                    double *x, const ls_iter_opts_t *io, ls_stats_t *stats,
+                    void *ws, size_t ws_bytes, void *stream);
+
+/* Algorithm 2 lines 2-10: refinement on the augmented system with
+ * split-preconditioned FGMRES (M_L^-1 = diag(I, R^-T), M_R^-1 = diag(I, R^-1)).
+ * x: device, length n, binary64, in and out.  r: device, length m, binary64,
+ * out (and in when r_given != 0; otherwise r = b - A x is formed first,
+ * Algorithm 2 line 2).  stats may be NULL. */
+int ls_lsir_gmres(const ls_problem_t *P, const double *R, int64_t ldr, const ls_precs_t *pr,
+                  double *x, double *r, int r_given, const ls_iter_opts_t *io,
+                  ls_stats_t *stats, void *ws, size_t ws_bytes, void *stream);
+
+/* The whole method: sketch, R, x^s, LSQR, refinement.  x (n) and r (m):
+ * device, binary64, out.  stats may be NULL. */
+int ls_solve(const ls_problem_t *P, const ls_sketch_opts_t *so, const ls_precs_t *pr,
+             const ls_iter_opts_t *io, double *x, double *r, ls_stats_t *stats,
+             void *ws, size_t ws_bytes, void *stream);
+
+/* The sketch operator itself, for checks and small problems: S[k, i] for
+ * k < s, i < m as defined under ls_sketch_opts_t, rounded as the sketch in
+ * format fmt (LS_FP64 or LS_BF16) uses it, unscaled (Omega = S / sqrt(s)).
+ * S: device, binary64, s x m column major, lds >= s.  Does not synchronise. */
+int ls_omega(uint64_t seed, uint32_t prob_id, int64_t s, int64_t m, ls_prec_t fmt,
+             double *S, int64_t lds, void *stream);
+
+/* Raw Philox4x32-10 blocks for counters (c0 + t, c1, c2, c3), t < count,
+ * key (k0, k1): out (device, uint32, 4 * count words, block t at 4t).
+ * Does not synchronise. */
+int ls_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
+              int64_t count, uint32_t *out, void *stream);
+
+/* Static text for a status code. */
+const char *ls_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LS_H */

@@ -1,0 +1,27 @@
+"""Sketch-preconditioned mixed-precision least squares on one MI355X (gfx950).
+
+The method (Carson and Dauzickaite): sketch [A b] with a Gaussian embedding
+(Algorithm 1 step 1), take the R factor of a Householder QR of the sketch
+(step 2), run LSQR right-preconditioned with R from the sketch-and-solve
+point (Algorithm 2 line 1) and refine x and r on the augmented system with
+split-preconditioned FGMRES (lines 2-10).  All of it runs in libls.so
+(hand-written HIP); this package is its Python binding.
+"""
+
+from .api import (  # noqa: F401
+    Solver,
+    iter_opts,
+    ls_lsir_gmres,
+    ls_lsqr_precond,
+    ls_omega,
+    ls_philox,
+    ls_qr_r,
+    ls_sketch,
+    ls_solve,
+    precs,
+    problem,
+    sketch_opts,
+    workspace,
+    workspace_size,
+)
+from ._binding import LsError, load  # noqa: F401

@@ -1,0 +1,362 @@
+// C ABI of libls: argument checking, workspace carving and the stage drivers.
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace {
+
+using namespace ls;
+
+bool prec_is(ls_prec_t p, ls_prec_t a, ls_prec_t b) { return p == a || p == b; }
+
+int check_problem(const ls_problem_t* P) {
+  if (!P || !P->A || !P->b) return LS_E_ARG;
+  if (P->n < 1 || P->m < P->n || P->lda < P->m) return LS_E_ARG;
+  if (!prec_is(P->store, LS_FP32, LS_FP64)) return LS_E_ARG;
+  if (P->n > 2048 || P->m > ((int64_t)1 << 31) - 4096) return LS_E_UNSUPPORTED;
+  return LS_OK;
+}
+
+int64_t sketch_rows(const ls_problem_t* P, const ls_sketch_opts_t* so) {
+  return (so && so->s > 0) ? so->s : 4 * P->n;
+}
+
+int check_sketch(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s) {
+  if (!so) return LS_E_ARG;
+  const int64_t s = sketch_rows(P, so);
+  if (s < P->n + 1) return LS_E_ARG;
+  if (s > 8192) return LS_E_UNSUPPORTED;
+  if (u_s == LS_BF16) {
+    if (so->terms < 1 || so->terms > 3) return LS_E_ARG;
+    if (P->store != LS_FP32) return LS_E_UNSUPPORTED;
+  } else if (u_s == LS_FP64) {
+    if (so->terms > 1) return LS_E_ARG;
+  } else {
+    return LS_E_UNSUPPORTED;
+  }
+  return LS_OK;
+}
+
+ls_iter_opts_t fill_opts(const ls_iter_opts_t* io, int64_t n, ls_prec_t u) {
+  ls_iter_opts_t d;
+  ls_default_iter_opts(n, u, &d);
+  if (!io) return d;
+  ls_iter_opts_t o = *io;
+  if (o.lsqr_tol <= 0) o.lsqr_tol = d.lsqr_tol;
+  if (o.lsqr_maxit <= 0) o.lsqr_maxit = d.lsqr_maxit;
+  if (o.fgmres_tol <= 0) o.fgmres_tol = d.fgmres_tol;
+  if (o.fgmres_maxit <= 0) o.fgmres_maxit = d.fgmres_maxit;
+  if (o.lsir_maxit <= 0) o.lsir_maxit = d.lsir_maxit;
+  if (o.lsir_tol <= 0) o.lsir_tol = d.lsir_tol;
+  if (o.check_every <= 0) o.check_every = d.check_every;
+  return o;
+}
+
+int check_precs(const ls_precs_t* pr) {
+  if (!pr) return LS_E_ARG;
+  if (!prec_is(pr->u, LS_FP32, LS_FP64)) return LS_E_UNSUPPORTED;
+  if (!prec_is(pr->u_qr, LS_FP32, LS_FP64)) return LS_E_UNSUPPORTED;
+  if (!prec_is(pr->u_r, LS_FP64, LS_FP64X2)) return LS_E_UNSUPPORTED;
+  const ls_prec_t ps[3] = {pr->u_A, pr->u_L, pr->u_R};
+  for (ls_prec_t p : ps) {
+    if (!prec_is(p, LS_FP32, LS_FP64)) return LS_E_UNSUPPORTED;
+    if (pr->u == LS_FP64 && p == LS_FP32) return LS_E_ARG;   // not coarser than u
+  }
+  if (pr->u_A != pr->u_L || pr->u_A != pr->u_R) return LS_E_UNSUPPORTED;
+  return LS_OK;
+}
+
+// x = W c with W upper triangular n x n (ld n): x^s = R^-1 (Q^T Omega b).
+__global__ __launch_bounds__(256) void k_trmv_f64(const double* __restrict__ W, int64_t n, const double* __restrict__ c,
+                                                  double* __restrict__ x) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= n) return;
+  double acc = 0.0;
+  for (int64_t j = r; j < n; ++j) acc += W[r + j * n] * c[j];
+  x[r] = acc;
+}
+
+struct Inv {
+  double* W;
+  float* W32;
+  int* flag;
+  size_t bytes;
+};
+
+Inv inv_carve(char* ws, int64_t n) {
+  Inv v{};
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    char* q = ws ? ws + off : nullptr;
+    off += ls_align256(b);
+    return q;
+  };
+  v.W = reinterpret_cast<double*>(take(8 * (size_t)n * n));
+  v.W32 = reinterpret_cast<float*>(take(4 * (size_t)n * n));
+  v.flag = reinterpret_cast<int*>(take(256));
+  v.bytes = off;
+  return v;
+}
+
+size_t iter_bytes(const ls_problem_t* P, const ls_precs_t* pr, const ls_iter_opts_t* io) {
+  const int ncu = device_cu_count();
+  size_t a = lsqr_workspace(P, pr->u, ncu);
+  ls_precs_t p64 = *pr;
+  p64.u_A = p64.u_L = p64.u_R = LS_FP64;
+  int kmax = io->fgmres_maxit;
+  if (io->fallback && kmax < 80) kmax = 80;
+  size_t b = lsir_workspace(P, pr, io->fgmres_maxit, ncu);
+  size_t c = lsir_workspace(P, &p64, kmax, ncu);
+  size_t m = a > b ? a : b;
+  return m > c ? m : c;
+}
+
+// Make R^-1 available: W (binary64) and its binary32 copy.
+int make_inverse(const double* R, int64_t ldr, int64_t n, const Inv& v, hipStream_t st) {
+  LS_HIP_TRY(hipMemsetAsync(v.flag, 0, sizeof(int), st));
+  LS_TRY(trinv_run(R, ldr, n, v.W, n, v.W32, v.flag, st));
+  int flag = 0;
+  LS_HIP_TRY(hipMemcpyAsync(&flag, v.flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  LS_HIP_TRY(hipStreamSynchronize(st));
+  return flag ? LS_E_SINGULAR : LS_OK;
+}
+
+struct Timer {
+  hipEvent_t e[5];
+  bool ok = false;
+  Timer() {
+    ok = true;
+    for (auto& x : e)
+      if (hipEventCreate(&x) != hipSuccess) ok = false;
+  }
+  ~Timer() {
+    for (auto& x : e) (void)hipEventDestroy(x);
+  }
+  void mark(int i, hipStream_t st) {
+    if (ok) (void)hipEventRecord(e[i], st);
+  }
+  double ms(int a, int b) {
+    float t = 0.f;
+    if (!ok || hipEventElapsedTime(&t, e[a], e[b]) != hipSuccess) return 0.0;
+    return (double)t;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+void ls_default_iter_opts(int64_t n, ls_prec_t u, ls_iter_opts_t* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  const bool dbl = (u == LS_FP64);
+  o->lsqr_tol = dbl ? 1e-12 : 1e-6;
+  o->lsqr_maxit = (int32_t)(2 * n);
+  o->fgmres_tol = dbl ? 1e-12 : 1e-6;
+  o->fgmres_maxit = 50;
+  o->lsir_maxit = 30;
+  o->lsir_tol = 4.0 * (dbl ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24));
+  o->fallback = 0;
+  o->check_every = 8;
+}
+
+const char* ls_strerror(int s) {
+  switch (s) {
+    case LS_OK: return "success";
+    case LS_NOT_CONVERGED: return "iteration limit reached before the stopping test held";
+    case LS_E_ARG: return "invalid argument";
+    case LS_E_WORKSPACE: return "workspace too small";
+    case LS_E_HIP: return "HIP runtime error";
+    case LS_E_SINGULAR: return "R has a zero or non-finite diagonal entry (rank-deficient sketch)";
+    case LS_E_NONFINITE: return "non-finite value in an iterate";
+    case LS_E_UNSUPPORTED: return "combination not supported by this build";
+    default: return "unknown status";
+  }
+}
+
+int ls_workspace_size(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t* pr,
+                      const ls_iter_opts_t* io_in, size_t* bytes) {
+  if (!bytes) return LS_E_ARG;
+  LS_TRY(check_problem(P));
+  LS_TRY(check_precs(pr));
+  LS_TRY(check_sketch(P, so, pr->u_s));
+  const ls_iter_opts_t io = fill_opts(io_in, P->n, pr->u);
+  const int64_t n = P->n, s = sketch_rows(P, so);
+  const SketchPlan sp = sketch_plan(P->m, n, s, pr->u_s, so->terms);
+  size_t fixed = ls_align256(8 * (size_t)s * (n + 1))          // Y
+                 + ls_align256(8 * (size_t)(n + 1) * (n + 1))    // R_aug
+                 + inv_carve(nullptr, n).bytes                   // R^-1
+                 + ls_align256(8 * (size_t)(P->m + n));          // saved x0, r0 for the fallback
+  size_t scratch = sp.operand_bytes + sp.partial_bytes;
+  const size_t q = qr_workspace(s, n + 1, pr->u_qr);
+  if (q > scratch) scratch = q;
+  const size_t it = iter_bytes(P, pr, &io);
+  if (it > scratch) scratch = it;
+  *bytes = fixed + scratch;
+  return LS_OK;
+}
+
+int ls_sketch(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s, double* Y, int64_t ldy, void* ws,
+              size_t ws_bytes, void* stream) {
+  LS_TRY(check_problem(P));
+  LS_TRY(check_sketch(P, so, u_s));
+  const int64_t s = sketch_rows(P, so);
+  if (!Y || ldy < s) return LS_E_ARG;
+  const SketchPlan sp = sketch_plan(P->m, P->n, s, u_s, so->terms);
+  if (!ws || ws_bytes < sp.operand_bytes + sp.partial_bytes) return LS_E_WORKSPACE;
+  return sketch_run(P, so, u_s, sp, s, Y, ldy, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
+}
+
+int ls_qr_r(int64_t s, int64_t ncols, ls_prec_t u_qr, double* Y, int64_t ldy, double* R, int64_t ldr, void* ws,
+            size_t ws_bytes, void* stream) {
+  if (!Y || !R || ncols < 1 || s < ncols || ldy < s || ldr < ncols) return LS_E_ARG;
+  if (!prec_is(u_qr, LS_FP32, LS_FP64)) return LS_E_UNSUPPORTED;
+  const size_t need = qr_workspace(s, ncols, u_qr) + 256;
+  if (!ws || ws_bytes < need) return LS_E_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  int* flag = reinterpret_cast<int*>(w);
+  LS_HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), st));
+  LS_TRY(qr_run(s, ncols, u_qr, Y, ldy, R, ldr, w + 256, ws_bytes - 256, flag, ncols, st));
+  int h = 0;
+  LS_HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  LS_HIP_TRY(hipStreamSynchronize(st));
+  return h ? LS_E_SINGULAR : LS_OK;
+}
+
+int ls_lsqr_precond(const ls_problem_t* P, const double* R, int64_t ldr, ls_prec_t u, double* x,
+                    const ls_iter_opts_t* io_in, ls_stats_t* stats, void* ws, size_t ws_bytes, void* stream) {
+  LS_TRY(check_problem(P));
+  if (!R || !x || ldr < P->n) return LS_E_ARG;
+  if (!prec_is(u, LS_FP32, LS_FP64)) return LS_E_UNSUPPORTED;
+  const ls_iter_opts_t io = fill_opts(io_in, P->n, u);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Inv inv = inv_carve(static_cast<char*>(ws), P->n);
+  const size_t need = inv.bytes + lsqr_workspace(P, u, device_cu_count());
+  if (!ws || ws_bytes < need) return LS_E_WORKSPACE;
+  LS_TRY(make_inverse(R, ldr, P->n, inv, st));
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  const int rc = lsqr_device(P, inv.W, inv.W32, P->n, u, x, &io, stats, static_cast<char*>(ws) + inv.bytes,
+                             ws_bytes - inv.bytes, st);
+  if (stats) stats->status = rc;
+  return rc;
+}
+
+int ls_lsir_gmres(const ls_problem_t* P, const double* R, int64_t ldr, const ls_precs_t* pr, double* x, double* r,
+                  int r_given, const ls_iter_opts_t* io_in, ls_stats_t* stats, void* ws, size_t ws_bytes,
+                  void* stream) {
+  LS_TRY(check_problem(P));
+  LS_TRY(check_precs(pr));
+  if (!R || !x || !r || ldr < P->n) return LS_E_ARG;
+  const ls_iter_opts_t io = fill_opts(io_in, P->n, pr->u);
+  if (io.fgmres_maxit > 95) return LS_E_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Inv inv = inv_carve(static_cast<char*>(ws), P->n);
+  const size_t need = inv.bytes + lsir_workspace(P, pr, io.fgmres_maxit, device_cu_count());
+  if (!ws || ws_bytes < need) return LS_E_WORKSPACE;
+  LS_TRY(make_inverse(R, ldr, P->n, inv, st));
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  const int rc = lsir_device(P, inv.W, inv.W32, P->n, pr, x, r, r_given, &io, stats,
+                             static_cast<char*>(ws) + inv.bytes, ws_bytes - inv.bytes, st);
+  if (stats) stats->status = rc;
+  return rc;
+}
+
+int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t* pr, const ls_iter_opts_t* io_in,
+             double* x, double* r, ls_stats_t* stats, void* ws, size_t ws_bytes, void* stream) {
+  LS_TRY(check_problem(P));
+  LS_TRY(check_precs(pr));
+  LS_TRY(check_sketch(P, so, pr->u_s));
+  if (!x || !r) return LS_E_ARG;
+  size_t need = 0;
+  LS_TRY(ls_workspace_size(P, so, pr, io_in, &need));
+  if (!ws || ws_bytes < need) return LS_E_WORKSPACE;
+  const ls_iter_opts_t io = fill_opts(io_in, P->n, pr->u);
+  if (io.fgmres_maxit > 95) return LS_E_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t m = P->m, n = P->n, s = sketch_rows(P, so);
+  ls_stats_t local;
+  ls_stats_t* S = stats ? stats : &local;
+  std::memset(S, 0, sizeof(*S));
+
+  char* base = static_cast<char*>(ws);
+  size_t off = 0;
+  double* Y = reinterpret_cast<double*>(base + off);
+  off += ls_align256(8 * (size_t)s * (n + 1));
+  double* Raug = reinterpret_cast<double*>(base + off);
+  off += ls_align256(8 * (size_t)(n + 1) * (n + 1));
+  const Inv inv = inv_carve(base + off, n);
+  off += inv.bytes;
+  double* saved = reinterpret_cast<double*>(base + off);
+  off += ls_align256(8 * (size_t)(m + n));
+  char* scratch = base + off;
+  const size_t scratch_bytes = ws_bytes - off;
+
+  Timer tm;
+  tm.mark(0, st);
+  // Algorithm 1 step 1
+  const SketchPlan sp = sketch_plan(m, n, s, pr->u_s, so->terms);
+  LS_TRY(sketch_run(P, so, pr->u_s, sp, s, Y, s, scratch, st));
+  tm.mark(1, st);
+  // Algorithm 1 step 2, then x^s = R^-1 (Q^T Omega b)
+  LS_HIP_TRY(hipMemsetAsync(inv.flag, 0, sizeof(int), st));
+  LS_TRY(qr_run(s, n + 1, pr->u_qr, Y, s, Raug, n + 1, scratch, scratch_bytes, inv.flag, n, st));
+  LS_TRY(trinv_run(Raug, n + 1, n, inv.W, n, inv.W32, inv.flag, st));
+  hipLaunchKernelGGL(k_trmv_f64, dim3((unsigned)ls_cdiv(n, 256)), dim3(256), 0, st, inv.W, n, Raug + n * (n + 1), x);
+  int flag = 0;
+  LS_HIP_TRY(hipMemcpyAsync(&flag, inv.flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  LS_HIP_TRY(hipStreamSynchronize(st));
+  tm.mark(2, st);
+  if (flag) {
+    S->status = LS_E_SINGULAR;
+    return LS_E_SINGULAR;
+  }
+  // Algorithm 2 line 1
+  int rc = lsqr_device(P, inv.W, inv.W32, n, pr->u, x, &io, S, scratch, scratch_bytes, st);
+  tm.mark(3, st);
+  if (rc < 0) {
+    S->status = rc;
+    return rc;
+  }
+  // Algorithm 2 lines 2-10
+  if (io.fallback) {
+    LS_HIP_TRY(hipMemcpyAsync(saved, x, 8 * (size_t)n, hipMemcpyDeviceToDevice, st));
+  }
+  rc = lsir_device(P, inv.W, inv.W32, n, pr, x, r, 0, &io, S, scratch, scratch_bytes, st);
+  if (rc == LS_NOT_CONVERGED && io.fallback) {
+    // Section 5: rerun the refinement with u_A = u_L = u_R = binary64 and up to 80 FGMRES iterations.
+    ls_precs_t p2 = *pr;
+    p2.u_A = p2.u_L = p2.u_R = LS_FP64;
+    ls_iter_opts_t io2 = io;
+    io2.fgmres_maxit = 80;
+    LS_HIP_TRY(hipMemcpyAsync(x, saved, 8 * (size_t)n, hipMemcpyDeviceToDevice, st));
+    S->fallback_used = 1;
+    rc = lsir_device(P, inv.W, inv.W32, n, &p2, x, r, 0, &io2, S, scratch, scratch_bytes, st);
+  }
+  tm.mark(4, st);
+  LS_HIP_TRY(hipStreamSynchronize(st));
+  S->ms_sketch = tm.ms(0, 1);
+  S->ms_qr = tm.ms(1, 2);
+  S->ms_lsqr = tm.ms(2, 3);
+  S->ms_lsir = tm.ms(3, 4);
+  S->status = rc;
+  return rc;
+}
+
+int ls_omega(uint64_t seed, uint32_t prob_id, int64_t s, int64_t m, ls_prec_t fmt, double* S, int64_t lds,
+             void* stream) {
+  if (!S || s < 1 || m < 1 || lds < s || s > 65535) return LS_E_ARG;
+  if (!prec_is(fmt, LS_FP64, LS_BF16)) return LS_E_UNSUPPORTED;
+  return omega_run(seed, prob_id, s, m, fmt, S, lds, static_cast<hipStream_t>(stream));
+}
+
+int ls_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1, int64_t count,
+              uint32_t* out, void* stream) {
+  if (!out || count < 0) return LS_E_ARG;
+  if (count == 0) return LS_OK;
+  return philox_run(c0, c1, c2, c3, k0, k1, count, out, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,138 @@
+// Shared device/host helpers for libls (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/ls.h"
+
+#define LS_WAVE 64
+
+// ---------------------------------------------------------------- status plumbing
+#define LS_HIP_TRY(expr)                                  \
+  do {                                                    \
+    hipError_t e_ = (expr);                               \
+    if (e_ != hipSuccess) return LS_E_HIP;                \
+  } while (0)
+
+#define LS_TRY(expr)                                      \
+  do {                                                    \
+    int s_ = (expr);                                      \
+    if (s_ < 0) return s_;                                \
+  } while (0)
+
+__host__ __device__ static inline size_t ls_align256(size_t x) { return (x + 255) & ~(size_t)255; }
+__host__ __device__ static inline int64_t ls_cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------- Philox4x32-10
+// Salmon et al. (SC'11): ten rounds of two 32x32->64 multiplications on
+// counter words 0 and 2, XOR of the high halves with the other two words and
+// the round key, word permutation; the key advances by the Weyl constants.
+__device__ __forceinline__ void ls_philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2,
+                                                 uint32_t& c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+// Uniform in (0, 1) from the top 23 bits of a word: (2 (w >> 9) + 1) 2^-24,
+// exact in binary32.
+__device__ __forceinline__ float ls_u01f(uint32_t w) {
+  return (float)((w >> 9) * 2u + 1u) * 5.9604644775390625e-8f;
+}
+__device__ __forceinline__ double ls_u01d(uint32_t w) {
+  return (double)((w >> 9) * 2u + 1u) * 5.9604644775390625e-8;
+}
+
+// Box-Muller in binary32 with the hardware transcendental units:
+// v_log_f32 is log2, v_sin/v_cos take the angle in revolutions.
+__device__ __forceinline__ void ls_box_muller_f32(uint32_t w0, uint32_t w1, float& z0, float& z1) {
+  const float u0 = ls_u01f(w0);
+  const float u1 = ls_u01f(w1);
+  const float rad = __builtin_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u0));
+  z0 = rad * __builtin_amdgcn_cosf(u1);
+  z1 = rad * __builtin_amdgcn_sinf(u1);
+}
+
+// Box-Muller in binary64 (library log/sqrt/sincospi).
+__device__ __forceinline__ void ls_box_muller_f64(uint32_t w0, uint32_t w1, double& z0, double& z1) {
+  const double u0 = ls_u01d(w0);
+  const double u1 = ls_u01d(w1);
+  const double rad = sqrt(-2.0 * log(u0));
+  double s, c;
+  sincospi(2.0 * u1, &s, &c);
+  z0 = rad * c;
+  z1 = rad * s;
+}
+
+// Round binary32 to bf16 (nearest, ties to even); returns the bit pattern.
+__device__ __forceinline__ uint16_t ls_f32_to_bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);   // NaN stays NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float ls_bf16_bits_to_f32(uint16_t h) {
+  return __uint_as_float(((uint32_t)h) << 16);
+}
+
+// ---------------------------------------------------------------- reductions
+template <typename T>
+__device__ __forceinline__ T ls_wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over a block of NT threads (NT multiple of 64); result valid in all threads.
+template <typename T, int NT>
+__device__ __forceinline__ T ls_block_sum(T v, T* sh /* NT/64 entries */) {
+  v = ls_wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  T s = 0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) s += sh[i];
+  return s;
+}
+
+// Double-double helpers (Knuth's two-sum and an FMA two-product).  These
+// error-free transformations need every product and sum rounded exactly as
+// written, so floating-point contraction is switched off inside them.
+struct ls_dd {
+  double hi, lo;
+};
+__device__ __forceinline__ ls_dd ls_two_sum(double a, double b) {
+#pragma clang fp contract(off)
+  double s = a + b;
+  double bb = s - a;
+  double e = (a - (s - bb)) + (b - bb);
+  return {s, e};
+}
+__device__ __forceinline__ ls_dd ls_dd_add(ls_dd a, ls_dd b) {
+#pragma clang fp contract(off)
+  ls_dd s = ls_two_sum(a.hi, b.hi);
+  double lo = s.lo + a.lo + b.lo;
+  return ls_two_sum(s.hi, lo);
+}
+__device__ __forceinline__ ls_dd ls_dd_fma(ls_dd acc, double a, double b) {
+#pragma clang fp contract(off)
+  double p = a * b;
+  double pe = fma(a, b, -p);
+  ls_dd s = ls_two_sum(acc.hi, p);
+  double lo = s.lo + acc.lo + pe;
+  return ls_two_sum(s.hi, lo);
+}

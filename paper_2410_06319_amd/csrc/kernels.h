@@ -1,0 +1,77 @@
+// Internal interfaces between the host drivers and the kernel files of libls.
+#pragma once
+
+#include "common.h"
+
+namespace ls {
+
+// ------------------------------------------------------------------ sketch
+struct SketchPlan {
+  int64_t ncols;          // n + 1
+  int64_t s_pad;          // s rounded up to 64 (rows of S per block: 4 waves x 16)
+  int64_t n_pad;          // n + 1 rounded up to the column tile
+  int64_t m_pad;          // rows of the packed operand (kchunk * nsplit)
+  int64_t kchunk;         // rows of A per K-split
+  int64_t nsplit;         // number of K-splits (partial sums combined in binary64)
+  int nb;                 // 16-column MFMA blocks per wave
+  int kstep;              // rows of A per MFMA step
+  int terms;
+  size_t operand_bytes;   // packed [A b]
+  size_t partial_bytes;   // per-split partial sketches
+};
+
+SketchPlan sketch_plan(int64_t m, int64_t n, int64_t s, ls_prec_t u_s, int terms);
+int sketch_run(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s, const SketchPlan& p,
+               int64_t s, double* Y, int64_t ldy, char* ws, hipStream_t st);
+int omega_run(uint64_t seed, uint32_t prob, int64_t s, int64_t m, ls_prec_t fmt, double* S, int64_t lds,
+              hipStream_t st);
+int philox_run(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1, int64_t count,
+               uint32_t* out, hipStream_t st);
+
+// ------------------------------------------------------------------ QR and R^-1
+size_t qr_workspace(int64_t s, int64_t ncols, ls_prec_t u_qr);
+// check_cols: leading diagonal entries of R tested for zero / non-finite values.
+int qr_run(int64_t s, int64_t ncols, ls_prec_t u_qr, double* Y, int64_t ldy, double* R, int64_t ldr,
+           char* ws, size_t ws_bytes, int* d_flag, int64_t check_cols, hipStream_t st);
+// W = R^-1 (n x n upper, binary64, ldw) and, if W32 != NULL, its binary32 copy (ld n).
+int trinv_run(const double* R, int64_t ldr, int64_t n, double* W, int64_t ldw, float* W32, int* d_flag,
+              hipStream_t st);
+
+// ------------------------------------------------------------------ iterations
+// Per-device-call scalar state of LSQR (binary64; two parity copies of the
+// recurrence so that all blocks of a kernel read the previous copy while
+// block 0 writes the next one).
+struct LsqrRec {
+  double alpha, rhobar, phibar, normB2, phi_over_rho, theta_over_rho;
+  double normr, normar, normB;
+  int32_t its, done, stop, pad;
+};
+struct LsqrState {
+  LsqrRec rec[2];
+  double beta;     // beta_{i+1}, written by the reduction kernel
+  double normb;
+  int32_t flag;    // nonzero: non-finite value met
+  int32_t pad;
+};
+
+struct FgState {
+  double beta;                 // ||s||
+  double relres;
+  int32_t k;                   // Arnoldi columns in the solution
+  int32_t done;
+  int32_t breakdown;
+  int32_t pad;
+};
+
+int lsqr_device(const ls_problem_t* P, const double* W, const float* W32, int64_t ldw, ls_prec_t u, double* x,
+                const ls_iter_opts_t* io, ls_stats_t* stats, char* ws, size_t ws_bytes, hipStream_t st);
+size_t lsqr_workspace(const ls_problem_t* P, ls_prec_t u, int ncu);
+
+int lsir_device(const ls_problem_t* P, const double* W, const float* W32, int64_t ldw, const ls_precs_t* pr,
+                double* x, double* r, int r_given, const ls_iter_opts_t* io, ls_stats_t* stats, char* ws,
+                size_t ws_bytes, hipStream_t st);
+size_t lsir_workspace(const ls_problem_t* P, const ls_precs_t* pr, int fgmres_maxit, int ncu);
+
+int device_cu_count();
+
+}  // namespace ls

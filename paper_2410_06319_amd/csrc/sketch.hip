@@ -1,0 +1,328 @@
+// Algorithm 1 step 1: the Gaussian sketch Y = Omega [A b] on gfx950.
+//
+// Omega = S / sqrt(s) is never stored: every wave regenerates the S entries
+// it multiplies from Philox4x32-10 (counter (i/4, k, prob, 0), key = seed)
+// directly in the MFMA A-operand layout.  [A b] is first packed into a
+// zero-padded operand of the sketch format ("A stored in precision u_s",
+// Algorithm 1's input); for bf16 it may be split into several bf16 terms
+// whose sum reproduces the binary32 data more closely.  Products run on
+// MFMA with binary32 (bf16 path) or binary64 (f64 path) accumulation over a
+// chunk of rows of A; the chunk partial sums are added in binary64.
+#include "common.h"
+#include "kernels.h"
+
+typedef __bf16 ls_bf16x8 __attribute__((__vector_size__(8 * sizeof(__bf16))));
+typedef float ls_floatx4 __attribute__((ext_vector_type(4)));
+typedef double ls_doublex4 __attribute__((ext_vector_type(4)));
+typedef uint32_t ls_u32x4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ packing
+// Tt[t][j][i] (t < terms, j < n_pad, i < m_pad), bf16 bits: part t of
+// column j of [A b]; zero outside i < m, j <= n.
+__global__ __launch_bounds__(256) void k_pack_bf16(const float* __restrict__ A, int64_t lda,
+                                                   const float* __restrict__ b, int64_t m, int64_t n,
+                                                   int terms, uint16_t* __restrict__ Tt,
+                                                   int64_t m_pad, int64_t n_pad) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (i >= m_pad || j >= n_pad) return;
+  float x = 0.0f;
+  if (i < m) {
+    if (j < n) x = A[i + j * lda];
+    else if (j == n) x = b[i];
+  }
+  const int64_t term_stride = m_pad * n_pad;
+  for (int t = 0; t < terms; ++t) {
+    const uint16_t h = ls_f32_to_bf16_bits(x);
+    Tt[t * term_stride + j * m_pad + i] = h;
+    x = x - ls_bf16_bits_to_f32(h);   // exact (Sterbenz)
+  }
+}
+
+template <typename TA>
+__global__ __launch_bounds__(256) void k_pack_f64(const TA* __restrict__ A, int64_t lda,
+                                                  const TA* __restrict__ b, int64_t m, int64_t n,
+                                                  double* __restrict__ M, int64_t m_pad, int64_t n_pad) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (i >= m_pad || j >= n_pad) return;
+  double x = 0.0;
+  if (i < m) {
+    if (j < n) x = (double)A[i + j * lda];
+    else if (j == n) x = (double)b[i];
+  }
+  M[j * m_pad + i] = x;
+}
+
+// ------------------------------------------------------------------ bf16 MFMA sketch
+// Block: 4 waves; wave w owns S rows [64 bx + 16 w, +16) and all 16*NB
+// columns of the block's column tile.  One K-step is 32 rows of A.
+// v_mfma_f32_16x16x32_bf16 operands: lane l supplies row (l % 16) of S and
+// column (l % 16) of the packed operand, at the 8 consecutive K indices
+// 8 (l / 16) .. +7 of the step; the product sums over the same K set on
+// both sides.  Result: lane l holds D[4 (l/16) + r][l % 16], r < 4.
+template <int NB, int TERMS>
+__global__ __launch_bounds__(256) void k_sketch_bf16(const uint16_t* __restrict__ Tt, int64_t m_pad,
+                                                     int64_t n_pad, int64_t kchunk, uint32_t key0,
+                                                     uint32_t key1, uint32_t prob,
+                                                     float* __restrict__ Yp, int64_t s_pad) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const uint32_t srow = (uint32_t)(blockIdx.x * 64 + wave * 16 + (lane & 15));
+  const int64_t col0 = (int64_t)blockIdx.y * (16 * NB);
+  const int64_t kb0 = (int64_t)blockIdx.z * kchunk;
+  const int64_t kb1 = (kb0 + kchunk < m_pad) ? kb0 + kchunk : m_pad;
+  const int kq = (lane >> 4) * 8;
+  const int64_t term_stride = m_pad * n_pad;
+  const uint16_t* colp = Tt + (col0 + (lane & 15)) * m_pad + kq;
+
+  ls_floatx4 acc[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) acc[nb] = ls_floatx4{0.f, 0.f, 0.f, 0.f};
+
+  for (int64_t k = kb0; k < kb1; k += 32) {
+    const uint32_t q = (uint32_t)((k + kq) >> 2);
+    uint32_t a0 = q, a1 = srow, a2 = prob, a3 = 0u;
+    uint32_t c0 = q + 1u, c1 = srow, c2 = prob, c3 = 0u;
+    ls_philox4x32_10(a0, a1, a2, a3, key0, key1);
+    ls_philox4x32_10(c0, c1, c2, c3, key0, key1);
+    float z[8];
+    ls_box_muller_f32(a0, a1, z[0], z[1]);
+    ls_box_muller_f32(a2, a3, z[2], z[3]);
+    ls_box_muller_f32(c0, c1, z[4], z[5]);
+    ls_box_muller_f32(c2, c3, z[6], z[7]);
+    ls_u32x4 sw;
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+      sw[p] = (uint32_t)ls_f32_to_bf16_bits(z[2 * p]) | ((uint32_t)ls_f32_to_bf16_bits(z[2 * p + 1]) << 16);
+    const ls_bf16x8 sfrag = __builtin_bit_cast(ls_bf16x8, sw);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+#pragma unroll
+      for (int t = 0; t < TERMS; ++t) {
+        const ls_u32x4 bw = *reinterpret_cast<const ls_u32x4*>(colp + t * term_stride + nb * 16 * m_pad + k);
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sfrag, __builtin_bit_cast(ls_bf16x8, bw),
+                                                           acc[nb], 0, 0, 0);
+      }
+    }
+  }
+  float* out = Yp + (int64_t)blockIdx.z * s_pad * n_pad;
+  const int64_t r0 = (int64_t)blockIdx.x * 64 + wave * 16 + 4 * (lane >> 4);
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int64_t c = col0 + nb * 16 + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[(r0 + r) + c * s_pad] = acc[nb][r];
+  }
+}
+
+// ------------------------------------------------------------------ f64 MFMA sketch
+// v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
+// result lane l holds D[(l/16) + 4 r][l % 16] (rows interleaved, unlike the
+// bf16 layout above).  Within a 16-row block of A the
+// four steps t use K index kb + 4 (l/16) + t, so one Philox block (4 samples
+// of one S row) serves the lane's four steps.
+template <int NB>
+__global__ __launch_bounds__(256) void k_sketch_f64(const double* __restrict__ M, int64_t m_pad,
+                                                    int64_t n_pad, int64_t kchunk, uint32_t key0,
+                                                    uint32_t key1, uint32_t prob,
+                                                    double* __restrict__ Yp, int64_t s_pad) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const uint32_t srow = (uint32_t)(blockIdx.x * 64 + wave * 16 + (lane & 15));
+  const int64_t col0 = (int64_t)blockIdx.y * (16 * NB);
+  const int64_t kb0 = (int64_t)blockIdx.z * kchunk;
+  const int64_t kb1 = (kb0 + kchunk < m_pad) ? kb0 + kchunk : m_pad;
+  const int kq = (lane >> 4) * 4;
+  const double* colp = M + (col0 + (lane & 15)) * m_pad + kq;
+
+  ls_doublex4 acc[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) acc[nb] = ls_doublex4{0.0, 0.0, 0.0, 0.0};
+
+  for (int64_t k = kb0; k < kb1; k += 16) {
+    uint32_t a0 = (uint32_t)((k + kq) >> 2), a1 = srow, a2 = prob, a3 = 0u;
+    ls_philox4x32_10(a0, a1, a2, a3, key0, key1);
+    double z[4];
+    ls_box_muller_f64(a0, a1, z[0], z[1]);
+    ls_box_muller_f64(a2, a3, z[2], z[3]);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const double* p = colp + nb * 16 * m_pad + k;
+      const double b0 = p[0], b1 = p[1], b2 = p[2], b3 = p[3];
+      acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(z[0], b0, acc[nb], 0, 0, 0);
+      acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(z[1], b1, acc[nb], 0, 0, 0);
+      acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(z[2], b2, acc[nb], 0, 0, 0);
+      acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(z[3], b3, acc[nb], 0, 0, 0);
+    }
+  }
+  double* out = Yp + (int64_t)blockIdx.z * s_pad * n_pad;
+  const int64_t r0 = (int64_t)blockIdx.x * 64 + wave * 16 + (lane >> 4);
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int64_t c = col0 + nb * 16 + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[(r0 + 4 * r) + c * s_pad] = acc[nb][r];
+  }
+}
+
+// ------------------------------------------------------------------ chunk combine
+// Y[k + j ldy] = scale * sum_z Yp[z][k + j s_pad], summed in binary64 in
+// chunk order (deterministic).
+template <typename TP>
+__global__ __launch_bounds__(256) void k_sketch_combine(const TP* __restrict__ Yp, int64_t s_pad,
+                                                        int64_t n_pad, int nsplit, int64_t s,
+                                                        int64_t ncols, double scale,
+                                                        double* __restrict__ Y, int64_t ldy) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (k >= s || j >= ncols) return;
+  double acc = 0.0;
+  for (int z = 0; z < nsplit; ++z) acc += (double)Yp[(int64_t)z * s_pad * n_pad + k + j * s_pad];
+  Y[k + j * ldy] = acc * scale;
+}
+
+// ------------------------------------------------------------------ Omega itself
+// S[k + i lds] for k < s, i < m: one Philox block per thread (4 consecutive i).
+__global__ __launch_bounds__(256) void k_omega(uint32_t key0, uint32_t key1, uint32_t prob,
+                                               int64_t s, int64_t m, int fmt,
+                                               double* __restrict__ S, int64_t lds) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;   // quad index along m
+  const int64_t k = blockIdx.y;
+  if (4 * q >= m || k >= s) return;
+  uint32_t c0 = (uint32_t)q, c1 = (uint32_t)k, c2 = prob, c3 = 0u;
+  ls_philox4x32_10(c0, c1, c2, c3, key0, key1);
+  double z[4];
+  if (fmt == LS_FP64) {
+    ls_box_muller_f64(c0, c1, z[0], z[1]);
+    ls_box_muller_f64(c2, c3, z[2], z[3]);
+  } else {
+    float zf[4];
+    ls_box_muller_f32(c0, c1, zf[0], zf[1]);
+    ls_box_muller_f32(c2, c3, zf[2], zf[3]);
+    for (int t = 0; t < 4; ++t) z[t] = (double)ls_bf16_bits_to_f32(ls_f32_to_bf16_bits(zf[t]));
+  }
+  for (int t = 0; t < 4; ++t) {
+    const int64_t i = 4 * q + t;
+    if (i < m) S[k + i * lds] = z[t];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                uint32_t k0, uint32_t k1, int64_t count,
+                                                uint32_t* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= count) return;
+  uint32_t a = c0 + (uint32_t)t, b = c1, c = c2, d = c3;
+  ls_philox4x32_10(a, b, c, d, k0, k1);
+  out[4 * t + 0] = a;
+  out[4 * t + 1] = b;
+  out[4 * t + 2] = c;
+  out[4 * t + 3] = d;
+}
+
+// ------------------------------------------------------------------ host side
+namespace ls {
+
+SketchPlan sketch_plan(int64_t m, int64_t n, int64_t s, ls_prec_t u_s, int terms) {
+  SketchPlan p{};
+  p.ncols = n + 1;
+  p.s_pad = ls_cdiv(s, 64) * 64;
+  if (u_s == LS_BF16) {
+    p.nb = 16;
+    p.kstep = 32;
+  } else {
+    p.nb = 8;
+    p.kstep = 16;
+  }
+  p.n_pad = ls_cdiv(p.ncols, 16 * p.nb) * 16 * p.nb;
+  // Split K so that the grid holds roughly 2 blocks per compute unit.
+  const int64_t tiles = (p.s_pad / 64) * (p.n_pad / (16 * p.nb));
+  int64_t nsplit = ls_cdiv(512, tiles);
+  const int64_t ksteps = ls_cdiv(m, p.kstep);
+  if (nsplit > ksteps) nsplit = ksteps;
+  if (nsplit < 1) nsplit = 1;
+  if (nsplit > 64) nsplit = 64;
+  p.kchunk = ls_cdiv(ksteps, nsplit) * p.kstep;
+  p.nsplit = ls_cdiv(m, p.kchunk);
+  if (p.nsplit < 1) p.nsplit = 1;
+  p.m_pad = p.kchunk * p.nsplit;
+  p.terms = (u_s == LS_BF16) ? terms : 1;
+  const size_t elt = (u_s == LS_BF16) ? 2 : 8;
+  p.operand_bytes = ls_align256((size_t)p.terms * p.m_pad * p.n_pad * elt);
+  p.partial_bytes = ls_align256((size_t)p.nsplit * p.s_pad * p.n_pad * ((u_s == LS_BF16) ? 4 : 8));
+  return p;
+}
+
+int sketch_run(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s, const SketchPlan& p,
+               int64_t s, double* Y, int64_t ldy, char* ws, hipStream_t st) {
+  const uint32_t key0 = (uint32_t)(so->seed & 0xffffffffu);
+  const uint32_t key1 = (uint32_t)(so->seed >> 32);
+  char* operand = ws;
+  char* partial = ws + p.operand_bytes;
+  const dim3 gpack((unsigned)ls_cdiv(p.m_pad, 256), (unsigned)p.n_pad);
+  const dim3 gsk((unsigned)(p.s_pad / 64), (unsigned)(p.n_pad / (16 * p.nb)), (unsigned)p.nsplit);
+  const dim3 gcomb((unsigned)ls_cdiv(s, 256), (unsigned)p.ncols);
+  const double scale = 1.0 / sqrt((double)s);
+  if (u_s == LS_BF16) {
+    if (P->store != LS_FP32) return LS_E_UNSUPPORTED;
+    uint16_t* Tt = reinterpret_cast<uint16_t*>(operand);
+    hipLaunchKernelGGL(k_pack_bf16, gpack, dim3(256), 0, st, (const float*)P->A, P->lda,
+                       (const float*)P->b, P->m, P->n, p.terms, Tt, p.m_pad, p.n_pad);
+    float* Yp = reinterpret_cast<float*>(partial);
+    switch (p.terms) {
+      case 1:
+        hipLaunchKernelGGL((k_sketch_bf16<16, 1>), gsk, dim3(256), 0, st, Tt, p.m_pad, p.n_pad, p.kchunk,
+                           key0, key1, so->prob_id, Yp, p.s_pad);
+        break;
+      case 2:
+        hipLaunchKernelGGL((k_sketch_bf16<16, 2>), gsk, dim3(256), 0, st, Tt, p.m_pad, p.n_pad, p.kchunk,
+                           key0, key1, so->prob_id, Yp, p.s_pad);
+        break;
+      case 3:
+        hipLaunchKernelGGL((k_sketch_bf16<16, 3>), gsk, dim3(256), 0, st, Tt, p.m_pad, p.n_pad, p.kchunk,
+                           key0, key1, so->prob_id, Yp, p.s_pad);
+        break;
+      default:
+        return LS_E_ARG;
+    }
+    hipLaunchKernelGGL(k_sketch_combine<float>, gcomb, dim3(256), 0, st, Yp, p.s_pad, p.n_pad,
+                       (int)p.nsplit, s, p.ncols, scale, Y, ldy);
+  } else if (u_s == LS_FP64) {
+    double* M = reinterpret_cast<double*>(operand);
+    if (P->store == LS_FP64)
+      hipLaunchKernelGGL(k_pack_f64<double>, gpack, dim3(256), 0, st, (const double*)P->A, P->lda,
+                         (const double*)P->b, P->m, P->n, M, p.m_pad, p.n_pad);
+    else
+      hipLaunchKernelGGL(k_pack_f64<float>, gpack, dim3(256), 0, st, (const float*)P->A, P->lda,
+                         (const float*)P->b, P->m, P->n, M, p.m_pad, p.n_pad);
+    double* Yp = reinterpret_cast<double*>(partial);
+    hipLaunchKernelGGL((k_sketch_f64<8>), gsk, dim3(256), 0, st, M, p.m_pad, p.n_pad, p.kchunk, key0,
+                       key1, so->prob_id, Yp, p.s_pad);
+    hipLaunchKernelGGL(k_sketch_combine<double>, gcomb, dim3(256), 0, st, Yp, p.s_pad, p.n_pad,
+                       (int)p.nsplit, s, p.ncols, scale, Y, ldy);
+  } else {
+    return LS_E_UNSUPPORTED;
+  }
+  LS_HIP_TRY(hipGetLastError());
+  return LS_OK;
+}
+
+int omega_run(uint64_t seed, uint32_t prob, int64_t s, int64_t m, ls_prec_t fmt, double* S, int64_t lds,
+              hipStream_t st) {
+  const dim3 g((unsigned)ls_cdiv(ls_cdiv(m, 4), 256), (unsigned)s);
+  hipLaunchKernelGGL(k_omega, g, dim3(256), 0, st, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32),
+                     prob, s, m, (int)fmt, S, lds);
+  LS_HIP_TRY(hipGetLastError());
+  return LS_OK;
+}
+
+int philox_run(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1, int64_t count,
+               uint32_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_philox, dim3((unsigned)ls_cdiv(count, 256)), dim3(256), 0, st, c0, c1, c2, c3, k0, k1,
+                     count, out);
+  LS_HIP_TRY(hipGetLastError());
+  return LS_OK;
+}
+
+}  // namespace ls

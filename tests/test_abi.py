@@ -1,0 +1,55 @@
+"""The C ABI library loads and exports every function include/ls.h declares
+(CPU only: no compute call is made)."""
+
+import os
+import re
+import subprocess
+
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "ls.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ls_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("ls_sketch", "ls_qr_r", "ls_lsqr_precond", "ls_lsir_gmres", "ls_solve",
+                     "ls_workspace_size", "ls_strerror"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2410_06319_amd import _binding
+    lib = _binding.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) == set(_binding.SIGNATURES)
+    out = subprocess.run(["nm", "-D", "--defined-only", _binding.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (ls_[a-z_0-9]+)$", out, flags=re.M))
+    assert set(declared_functions()) <= exported
+
+
+def test_strerror_covers_status_codes():
+    from paper_2410_06319_amd import _binding
+    lib = _binding.load()
+    for code in (0, 1, -1, -2, -3, -4, -5, -6):
+        assert lib.ls_strerror(code) and lib.ls_strerror(code) != b"unknown status"
+
+
+def test_default_options_follow_section_5():
+    import ctypes
+    from paper_2410_06319_amd import _binding
+    lib = _binding.load()
+    o = _binding.IterOpts()
+    lib.ls_default_iter_opts(100, _binding.FP32, ctypes.byref(o))
+    assert (o.lsqr_tol, o.lsqr_maxit, o.fgmres_tol, o.fgmres_maxit, o.lsir_maxit) == (1e-6, 200, 1e-6, 50, 30)
+    lib.ls_default_iter_opts(100, _binding.FP64, ctypes.byref(o))
+    assert (o.lsqr_tol, o.fgmres_tol) == (1e-12, 1e-12)
+    assert o.lsir_tol == pytest.approx(4 * 2.0 ** -53)

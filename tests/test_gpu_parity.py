@@ -1,0 +1,252 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Every input is seeded and synthetic (lsdata); expected values come from the
+oracle only.  Tolerances are stated next to each comparison with the
+arithmetic that fixes them.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from lsdata import make_problem
+from oracle import formats, lsir as olsir, lsqr as olsqr, philox as ophilox, qr as oqr, refsolve, sketch as osketch
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def L():
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    import paper_2410_06319_amd as lib
+    lib.load()
+    return lib
+
+
+def dev(x, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def sync_print(*a):
+    print(*a, flush=True)
+
+
+# ------------------------------------------------------------------ random stream
+def test_philox_bit_exact(L):
+    rng = np.random.default_rng(1)
+    for _ in range(4):
+        c = [int(v) for v in rng.integers(0, 2 ** 32, 4)]
+        k = [int(v) for v in rng.integers(0, 2 ** 32, 2)]
+        c[0] = min(c[0], 2 ** 32 - 5000)
+        got = host(L.ls_philox(c[0], c[1], c[2], c[3], k[0], k[1], 4096))
+        ref = np.stack(ophilox.philox4x32_10(np.arange(c[0], c[0] + 4096, dtype=np.uint64), c[1], c[2], c[3],
+                                             k[0], k[1]), axis=1).astype(np.int64)
+        assert np.array_equal(got, ref)
+
+
+def test_omega_f64_matches_oracle(L):
+    seed, s, m = 2410063190, 37, 1003          # ragged: m not a multiple of 4
+    S = host(L.ls_omega(seed, s, m, fmt="f64", prob_id=5)).T
+    ref = ophilox.gaussian_block(seed, 5, 0, s, 0, m)
+    # binary64 Box-Muller on both sides; library log/sincospi within a few ulp
+    assert np.max(np.abs(S - ref)) <= 1e-13
+
+
+def test_omega_bf16_matches_oracle(L):
+    seed, s, m = 77, 64, 4096
+    S = host(L.ls_omega(seed, s, m, fmt="bf16")).T
+    ref = osketch.quantised_gaussian_block(seed, 0, 0, s, 0, m, "bf16")
+    # Both round a binary32 Box-Muller value to bf16; the GPU's binary32 value
+    # comes from the hardware log2/sin/cos (a few ulp), so a value within a few
+    # binary32 ulp of a bf16 rounding boundary may round the other way.  Such
+    # entries differ by exactly one bf16 ulp and are rare (expected ~ 2^-14).
+    diff = S != ref
+    frac = diff.mean()
+    sync_print("bf16 Omega entries differing by one ulp:", int(diff.sum()), "of", diff.size)
+    assert frac < 2e-3
+    if diff.any():
+        ulp = np.ldexp(1.0, np.floor(np.log2(np.abs(ref[diff]))).astype(int) - 7)
+        assert np.all(np.abs(S[diff] - ref[diff]) <= ulp * 1.0000001)
+
+
+# ------------------------------------------------------------------ sketch
+def _sketch_gpu(L, P, s, seed, u_s, terms):
+    At = dev(P.At)
+    b = dev(P.b)
+    return host(L.ls_sketch(At, b, s, seed=seed, u_s=u_s, terms=terms)).T
+
+
+@pytest.mark.parametrize("m,n,s", [(2000, 50, 200), (3001, 13, 77)])
+def test_sketch_f64_matches_oracle(L, m, n, s):
+    P = make_problem(m, n, 1e2, seed=11, store="f64")
+    Y = _sketch_gpu(L, P, s, 2410063190, "f64", 1)
+    ref, _ = osketch.sketch(P.At, P.b, s, 2410063190)
+    # binary64 products summed in a different order: |dY| <= few * m * u64 * (|S||M|)/sqrt(s)
+    M = np.abs(np.column_stack([P.A(), P.b]))
+    S = np.abs(ophilox.gaussian_block(2410063190, 0, 0, s, 0, m))
+    bound = (S @ M) / math.sqrt(s)
+    assert np.all(np.abs(Y - ref) <= 4 * 2.0 ** -53 * math.sqrt(m) * bound + 1e-300)
+
+
+@pytest.mark.parametrize("terms", [1, 2, 3])
+@pytest.mark.parametrize("m,n,s", [(5003, 37, 100), (20000, 300, 1200)])
+def test_sketch_bf16_matches_oracle(L, terms, m, n, s):
+    P = make_problem(m, n, 1e3, seed=12, store="f32")
+    Y = _sketch_gpu(L, P, s, 99, "bf16", terms)
+    ref, _ = osketch.sketch(P.At, P.b, s, 99, fmt="bf16", terms=terms)
+    Mq, _ = osketch.scaled_operand(P.At, P.b, "bf16", terms, False)
+    Sq = np.abs(osketch.quantised_gaussian_block(99, 0, 0, s, 0, m, "bf16"))
+    bound = (Sq @ np.abs(Mq)) / math.sqrt(s)
+    # binary32 MFMA accumulation over a row chunk (error <= chunk * u32 * bound,
+    # in practice ~ sqrt(chunk) u32) plus rare one-ulp bf16 entries of S
+    # (|dS| <= 2^-8 |S|, a few per million entries).
+    err = np.abs(Y - ref) / bound
+    sync_print(f"bf16 sketch terms={terms}: max err/bound {err.max():.3e}, median {np.median(err):.3e}")
+    assert np.median(err) < 1e-6
+    assert err.max() < 2e-3
+
+
+def test_sketch_bf16_split_reaches_binary32_accuracy(L):
+    # the multi-term representation: the bf16 x 2 sketch is as close to the
+    # exact sketch as binary32 data allows (relative ~ 2^-16 vs 2^-8 for one term)
+    P = make_problem(8000, 20, 1e2, seed=13, store="f32")
+    exact, _ = osketch.sketch(P.At, P.b, 84, 5, fmt="f64")
+    Sq = osketch.quantised_gaussian_block(5, 0, 0, 84, 0, 8000, "bf16")
+    M = np.column_stack([P.A(), P.b.astype(np.float64)])
+    exact_q = Sq @ M / math.sqrt(84)        # exact product with the bf16-rounded Omega
+    errs = []
+    for terms in (1, 2):
+        Y = _sketch_gpu(L, P, 84, 5, "bf16", terms)
+        errs.append(np.linalg.norm(Y - exact_q) / np.linalg.norm(exact_q))
+    sync_print("bf16 sketch error vs exact operands, terms 1/2:", errs)
+    assert errs[0] < 8 * 2.0 ** -8 and errs[1] < 8 * 2.0 ** -16
+    assert np.linalg.norm(exact_q - exact) / np.linalg.norm(exact) < 2.0 ** -6
+
+
+# ------------------------------------------------------------------ QR
+@pytest.mark.parametrize("u_qr", ["f64", "f32"])
+@pytest.mark.parametrize("s,ncols,kappa", [(200, 51, 1e2), (2000, 501, 1e2), (1111, 97, 1e4)])
+def test_qr_r_matches_oracle(L, u_qr, s, ncols, kappa):
+    P = make_problem(s, ncols, kappa, seed=14, store="f64")
+    Y = P.A()                                       # s x ncols with known conditioning
+    Rref = oqr.householder_r(Y)
+    Rt = L.ls_qr_r(dev(np.ascontiguousarray(Y.T)), u_qr=u_qr)
+    R = host(Rt).T
+    assert np.all(np.diag(R) > 0) and np.all(np.tril(R, -1) == 0)
+    u = 2.0 ** -53 if u_qr == "f64" else U32
+    # backward error of Householder QR: ||Y^T Y - R^T R|| <= c n u ||Y||^2
+    G = Y.T @ Y
+    assert np.linalg.norm(R.T @ R - G) <= 20 * ncols * u * np.linalg.norm(Y, 2) ** 2
+    # forward: R_hat R^-1 = I + Gamma with ||Gamma|| <~ c sqrt(n) u kappa (Section 3.1 proof)
+    Gam = np.linalg.solve(Rref.T, R.T).T - np.eye(ncols)
+    assert np.linalg.norm(Gam, 2) <= 10 * math.sqrt(ncols) * u * kappa
+
+
+def test_qr_r_rank_deficient_is_reported(L):
+    Y = np.random.default_rng(3).standard_normal((100, 8))
+    Y[:, 5] = 0.0
+    with pytest.raises(L.LsError) as e:
+        L.ls_qr_r(dev(np.ascontiguousarray(Y.T)), u_qr="f64")
+    assert e.value.code == -4
+
+
+# ------------------------------------------------------------------ LSQR
+def _oracle_R(P, s, seed):
+    Y, _ = osketch.sketch(P.At, P.b, s, seed)
+    Raug = oqr.householder_r(Y)
+    return Raug[:P.n, :P.n], oqr.sketch_and_solve(Raug)
+
+
+@pytest.mark.parametrize("store,u", [("f64", "f64"), ("f32", "f32"), ("f32", "f64")])
+def test_lsqr_iterates_match_oracle(L, store, u):
+    P = make_problem(3000, 40, 1e3, seed=15, store=store)
+    R, xs = _oracle_R(P, 160, 3)
+    for k in (1, 5, 17):
+        x = dev(xs.copy())
+        rc, st = L.ls_lsqr_precond(dev(P.At), dev(P.b), dev(np.ascontiguousarray(R.T)), x, u=u,
+                                   lsqr_tol=1e-300, lsqr_maxit=k)
+        xr, info = olsqr.lsqr_precond(P.At, P.b, R, xs, tol=0.0, maxit=k)
+        got = host(x)
+        assert st["lsqr_its"] == k
+        # same recurrences: binary64 agrees to rounding; binary32 vectors differ
+        # by O(k u32 kappa(A R^-1)) relative
+        tol = 1e-11 if u == "f64" else 2e-4
+        assert np.linalg.norm(got - xr) <= tol * np.linalg.norm(xr)
+        assert abs(st["lsqr_normr"] - info["normr"]) <= tol * 10 * info["normr"]
+
+
+def test_lsqr_converges_like_oracle(L):
+    P = make_problem(20000, 100, 1e4, seed=16, store="f32")
+    R, xs = _oracle_R(P, 400, 4)
+    x = dev(xs.copy())
+    rc, st = L.ls_lsqr_precond(dev(P.At), dev(P.b), dev(np.ascontiguousarray(R.T)), x, u="f32")
+    _, info = olsqr.lsqr_precond(P.At, P.b, R, xs, tol=1e-6, maxit=200)
+    sync_print("LSQR its gpu/oracle:", st["lsqr_its"], info["its"])
+    assert rc == 0 and abs(st["lsqr_its"] - info["its"]) <= 2
+
+
+# ------------------------------------------------------------------ refinement
+@pytest.mark.parametrize("store,u,u_r,target", [("f64", "f64", "f64x2", 1e-13), ("f32", "f32", "f64", 6e-6)])
+def test_lsir_reaches_target_from_oracle_start(L, store, u, u_r, target):
+    P = make_problem(6000, 60, 1e4, seed=17, store=store)
+    R, xs = _oracle_R(P, 240, 6)
+    x0, _ = olsqr.lsqr_precond(P.At, P.b, R, xs, tol=1e-6, maxit=120)
+    xr, rr, _ = refsolve.ref_solve(P.At, P.b)
+    x = dev(x0.copy())
+    r = torch.empty(P.m, dtype=torch.float64, device="cuda")
+    pr = L.precs(u_s="f64", u_qr="f64", u=u, u_r=u_r)
+    rc, st = L.ls_lsir_gmres(dev(P.At), dev(P.b), dev(np.ascontiguousarray(R.T)), x, r, pr=pr,
+                             lsir_tol=(target / 4))
+    ex, er = refsolve.forward_errors(host(x), host(r), xr, rr)
+    ox, orr, oinfo = olsir.lsir(P.At, P.b, R, x0, tol=target / 4, fgmres_tol=1e-6 if u == "f32" else 1e-12,
+                                u_r="ld" if u_r == "f64x2" else "f64")
+    oex, oer = refsolve.forward_errors(ox, orr, xr, rr)
+    sync_print(f"LSIR {store}/{u}/{u_r}: gpu its {st['lsir_its']} fgmres {st['fgmres_its_total']} "
+               f"err x {ex:.2e} r {er:.2e}; oracle its {oinfo['its']} {oinfo['fgmres_its']} x {oex:.2e} r {oer:.2e}")
+    assert rc == 0
+    assert ex <= target and er <= target
+
+
+# ------------------------------------------------------------------ whole method
+def test_solve_fp64_workload_reaches_1e13(L):
+    P = make_problem(2000, 50, 1e2, seed=2410063190, store="f64")
+    xr, rr, _ = refsolve.ref_solve(P.At, P.b)
+    pr = L.precs(u_s="f64", u_qr="f64", u="f64", u_r="f64x2")
+    x, r, rc, st = L.ls_solve(dev(P.At), dev(P.b), s=200, seed=2410063190, pr=pr, lsqr_tol=1e-14,
+                              lsir_tol=1e-15)
+    ex, er = refsolve.forward_errors(host(x), host(r), xr, rr)
+    sync_print("fp64 solve:", st, ex, er)
+    assert rc == 0 and ex <= 1e-13 and er <= 1e-13
+
+
+def test_solve_mixed_bf16_reaches_6e6(L):
+    P = make_problem(20000, 100, 1e4, seed=2410064190, store="f32")
+    xr, rr, _ = refsolve.ref_solve(P.At, P.b)
+    pr = L.precs(u_s="bf16", u_qr="f32", u="f32", u_r="f64")
+    x, r, rc, st = L.ls_solve(dev(P.At), dev(P.b), s=400, seed=7, terms=2, pr=pr, lsir_tol=6e-6)
+    ex, er = refsolve.forward_errors(host(x), host(r), xr, rr)
+    sync_print("mixed solve:", st, ex, er)
+    assert rc == 0 and ex <= 6e-6 and er <= 6e-6
+
+
+def test_solve_rejects_bad_arguments(L):
+    P = make_problem(100, 10, 10.0, seed=1, store="f32")
+    At, b = dev(P.At), dev(P.b)
+    with pytest.raises(L.LsError) as e:
+        L.ls_solve(At, b, s=5, seed=1, terms=2, pr=L.precs())          # s < n + 1
+    assert e.value.code == -1
+    with pytest.raises(L.LsError) as e:
+        L.ls_solve(At, b, s=40, seed=1, terms=4, pr=L.precs())         # terms out of range
+    assert e.value.code == -1
