@@ -108,6 +108,7 @@ typedef struct {
   double lsir_tol;
   int32_t fallback;
   int32_t check_every;   /* iterations between host convergence checks (default 8) */
+  int32_t profile;       /* nonzero: time the main kernels with HIP events (see ls_stats_t) */
 } ls_iter_opts_t;
 
 /* Results and timings of one call. */
@@ -123,6 +124,14 @@ typedef struct {
   double lsir_dx_rel;     /* last ||dx|| / ||x|| */
   double lsir_dr_rel;     /* last ||dr|| / ||r|| */
   double ms_sketch, ms_qr, ms_lsqr, ms_lsir;
+  /* With profile != 0: summed device time and launch count of the main
+   * kernels, by class: 0 sketch MFMA, 1 LSQR pass over A, 2 FGMRES pass
+   * over A, 3 refinement residual pass over A, 4 Gram-Schmidt sweeps. */
+  double kernel_ms[5];
+  int32_t kernel_launches[5];
+  /* Algorithmic work of those launches: flops for class 0, bytes that the
+   * operation must move to or from HBM for classes 1-4. */
+  double kernel_work[5];
 } ls_stats_t;
 
 /* Fill the defaults described above for a problem with n columns and

@@ -33,7 +33,7 @@ class IterOpts(ctypes.Structure):
     _fields_ = [("lsqr_tol", ctypes.c_double), ("lsqr_maxit", ctypes.c_int32),
                 ("fgmres_tol", ctypes.c_double), ("fgmres_maxit", ctypes.c_int32),
                 ("lsir_maxit", ctypes.c_int32), ("lsir_tol", ctypes.c_double),
-                ("fallback", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+                ("fallback", ctypes.c_int32), ("check_every", ctypes.c_int32), ("profile", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -42,10 +42,18 @@ class Stats(ctypes.Structure):
                 ("lsqr_normr", ctypes.c_double), ("lsqr_normar", ctypes.c_double),
                 ("lsqr_normB", ctypes.c_double), ("lsir_dx_rel", ctypes.c_double),
                 ("lsir_dr_rel", ctypes.c_double), ("ms_sketch", ctypes.c_double),
-                ("ms_qr", ctypes.c_double), ("ms_lsqr", ctypes.c_double), ("ms_lsir", ctypes.c_double)]
+                ("ms_qr", ctypes.c_double), ("ms_lsqr", ctypes.c_double), ("ms_lsir", ctypes.c_double),
+                ("kernel_ms", ctypes.c_double * 5), ("kernel_launches", ctypes.c_int32 * 5),
+                ("kernel_work", ctypes.c_double * 5)]
+
+    KERNEL_CLASSES = ("sketch_mfma", "lsqr_pass", "fgmres_pass", "lsir_resid_pass", "cgs_sweep")
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        arrays = ("kernel_ms", "kernel_launches", "kernel_work")
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in arrays}
+        for a in arrays:
+            d[a] = dict(zip(self.KERNEL_CLASSES, list(getattr(self, a))))
+        return d
 
 
 P = ctypes.POINTER

@@ -160,6 +160,7 @@ void ls_default_iter_opts(int64_t n, ls_prec_t u, ls_iter_opts_t* o) {
   o->lsir_tol = 4.0 * (dbl ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24));
   o->fallback = 0;
   o->check_every = 8;
+  o->profile = 0;
 }
 
 const char* ls_strerror(int s) {
@@ -206,6 +207,7 @@ int ls_sketch(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s, 
   if (!Y || ldy < s) return LS_E_ARG;
   const SketchPlan sp = sketch_plan(P->m, P->n, s, u_s, so->terms);
   if (!ws || ws_bytes < sp.operand_bytes + sp.partial_bytes) return LS_E_WORKSPACE;
+  prof_reset(false);
   return sketch_run(P, so, u_s, sp, s, Y, ldy, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
 }
 
@@ -238,9 +240,14 @@ int ls_lsqr_precond(const ls_problem_t* P, const double* R, int64_t ldr, ls_prec
   if (!ws || ws_bytes < need) return LS_E_WORKSPACE;
   LS_TRY(make_inverse(R, ldr, P->n, inv, st));
   if (stats) std::memset(stats, 0, sizeof(*stats));
+  prof_reset(io.profile != 0);
   const int rc = lsqr_device(P, inv.W, inv.W32, P->n, u, x, &io, stats, static_cast<char*>(ws) + inv.bytes,
                              ws_bytes - inv.bytes, st);
-  if (stats) stats->status = rc;
+  if (stats) {
+    stats->status = rc;
+    if (io.profile && hipStreamSynchronize(st) == hipSuccess) prof_collect(stats);
+  }
+  prof_reset(false);
   return rc;
 }
 
@@ -258,9 +265,14 @@ int ls_lsir_gmres(const ls_problem_t* P, const double* R, int64_t ldr, const ls_
   if (!ws || ws_bytes < need) return LS_E_WORKSPACE;
   LS_TRY(make_inverse(R, ldr, P->n, inv, st));
   if (stats) std::memset(stats, 0, sizeof(*stats));
+  prof_reset(io.profile != 0);
   const int rc = lsir_device(P, inv.W, inv.W32, P->n, pr, x, r, r_given, &io, stats,
                              static_cast<char*>(ws) + inv.bytes, ws_bytes - inv.bytes, st);
-  if (stats) stats->status = rc;
+  if (stats) {
+    stats->status = rc;
+    if (io.profile && hipStreamSynchronize(st) == hipSuccess) prof_collect(stats);
+  }
+  prof_reset(false);
   return rc;
 }
 
@@ -294,6 +306,7 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
   char* scratch = base + off;
   const size_t scratch_bytes = ws_bytes - off;
 
+  prof_reset(io.profile != 0);
   Timer tm;
   tm.mark(0, st);
   // Algorithm 1 step 1
@@ -341,6 +354,8 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
   S->ms_qr = tm.ms(1, 2);
   S->ms_lsqr = tm.ms(2, 3);
   S->ms_lsir = tm.ms(3, 4);
+  if (io.profile) prof_collect(S);
+  prof_reset(false);
   S->status = rc;
   return rc;
 }

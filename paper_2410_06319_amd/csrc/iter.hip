@@ -934,6 +934,7 @@ int lsqr_typed(const ls_problem_t* P, const T* Wt, int64_t ldw, double* x, const
   hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(kThreads), 0, st, reinterpret_cast<char*>(w.st), sizeof(LsqrState));
   hipLaunchKernelGGL(k_cast_vec<T>, dim3((unsigned)ls_cdiv(n, kThreads)), dim3(kThreads), 0, st, x, p, n);
   auto pass = [&](int par, int init) {
+    prof_begin(kProfLsqrPass, st);
     switch (rb) {
       case 32:
         hipLaunchKernelGGL((k_lsqr_pass<TA, T, 32>), dim3(G), dim3(kThreads), lds, st, A, P->lda, m, n, vec_ok, p, u,
@@ -948,6 +949,8 @@ int lsqr_typed(const ls_problem_t* P, const T* Wt, int64_t ldw, double* x, const
                            b, w.st, par, init, tpart, w.nupart, w.nbpart);
         break;
     }
+    // A once, u read and written, p read, t written
+    prof_end(kProfLsqrPass, st, (double)m * n * sizeof(TA) + 2.0 * m * sizeof(T) + 2.0 * n * sizeof(T));
   };
   const dim3 gred((unsigned)ls_cdiv(n, 64));
   const dim3 gv((unsigned)Gv);
@@ -1132,6 +1135,7 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TP* Wp, int64_t ldw
   std::vector<double> up(4 * (size_t)d.Gd);
   for (its = 1; its <= io->lsir_maxit; ++its) {
     // lines 5-6: f, g, h in u_r
+    prof_begin(kProfResidPass, st);
     switch (d.rbr) {
       case 32:
         hipLaunchKernelGGL((k_lsir_resid<TA, DD, 32>), dim3(d.G), dim3(kThreads), lds_r, st, A, P->lda, m, n, vec_ok, b,
@@ -1146,6 +1150,8 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TP* Wp, int64_t ldw
                            r, x, w.V, w.rt_hi, w.rt_lo, w.w2part);
         break;
     }
+    // A and b once, r read, f written, x read, g written
+    prof_end(kProfResidPass, st, (double)m * n * sizeof(TA) + (double)m * sizeof(TA) + 16.0 * m + 16.0 * n);
     hipLaunchKernelGGL(k_lsir_g<DD>, dim3((unsigned)ls_cdiv(n, 64)), dim3(kThreads), 0, st, w.rt_hi, w.rt_lo, d.G, n,
                        w.gvec);
     hipLaunchKernelGGL(k_lsir_h<DD>, dim3((unsigned)d.Gh), dim3(kThreads), 0, st, W, n, n, m, w.gvec, w.V,
@@ -1158,6 +1164,7 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TP* Wp, int64_t ldw
       const int Gw = (j == 0) ? d.G + d.Gh : d.Gd;
       hipLaunchKernelGGL(k_fg_a<TP>, dim3((unsigned)(nrb_norm + nwb)), dim3(kThreads), 0, st, F, m, n, j, d.kmax, Wp,
                          ldwp, w.w2part, Gw, tol, 0, nrb_norm);
+      prof_begin(kProfFgPass, st);
       switch (d.rbp) {
         case 32:
           hipLaunchKernelGGL((k_fg_pass<TA, TP, 32>), dim3(d.G), dim3(kThreads), lds_p, st, A, P->lda, m, n, vec_ok, F,
@@ -1172,14 +1179,20 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TP* Wp, int64_t ldw
                              j, tpart, w.hpart);
           break;
       }
+      // A once, v_j read, w written, z read, t written, V_r(:, 0:j) for the fused dots
+      prof_end(kProfFgPass, st,
+               (double)m * n * sizeof(TA) + 16.0 * m + 8.0 * n + (double)n * sizeof(TP) + 8.0 * (j + 1) * m);
       const int ncb = (int)ls_cdiv(n, 64);
       hipLaunchKernelGGL(k_fg_reduce<TP>, dim3((unsigned)(ncb + j + 1)), dim3(kThreads), 0, st, tpart, w.hpart, d.G, n,
                          j, ncb, w.tbuf, w.h1r, w.st);
       hipLaunchKernelGGL(k_fg_c<TP>, dim3((unsigned)d.Gc), dim3(1024), 0, st, Wp, ldwp, n, m, w.tbuf, F, j, w.hxpart);
+      prof_begin(kProfCgs, st);
       hipLaunchKernelGGL(k_cgs, dim3((unsigned)d.Gd), dim3(kThreads), 0, st, F, m, n, j, d.kmax, w.h1r, w.hxpart, d.Gc,
                          w.h2part, d.Gd, 0, w.h2part, w.w2part);
       hipLaunchKernelGGL(k_cgs, dim3((unsigned)d.Gd), dim3(kThreads), 0, st, F, m, n, j, d.kmax, w.h1r, w.hxpart, d.Gc,
                          w.h2part, d.Gd, 1, w.h2part, w.w2part);
+      // two sweeps over V(:, 0:j), each reading and writing w
+      prof_end(kProfCgs, st, 2.0 * 8.0 * (j + 1) * (double)(m + n) + 4.0 * 8.0 * (double)(m + n));
       if ((j + 1) % check == 0) {
         LS_HIP_TRY(hipMemcpyAsync(&S, w.st, sizeof(FgState), hipMemcpyDeviceToHost, st));
         LS_HIP_TRY(hipStreamSynchronize(st));

@@ -75,3 +75,13 @@ size_t lsir_workspace(const ls_problem_t* P, const ls_precs_t* pr, int fgmres_ma
 int device_cu_count();
 
 }  // namespace ls
+
+namespace ls {
+// Optional per-kernel timing with HIP events (enabled per call through
+// ls_iter_opts_t.profile).  Not thread-safe: one profiled call at a time.
+enum ProfClass { kProfSketch = 0, kProfLsqrPass = 1, kProfFgPass = 2, kProfResidPass = 3, kProfCgs = 4 };
+void prof_reset(bool on);
+void prof_begin(int cls, hipStream_t st);
+void prof_end(int cls, hipStream_t st, double work);   // work: algorithmic flops or bytes
+void prof_collect(ls_stats_t* stats);   // after the stream has been synchronised
+}  // namespace ls

@@ -270,6 +270,7 @@ int sketch_run(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s,
     hipLaunchKernelGGL(k_pack_bf16, gpack, dim3(256), 0, st, (const float*)P->A, P->lda,
                        (const float*)P->b, P->m, P->n, p.terms, Tt, p.m_pad, p.n_pad);
     float* Yp = reinterpret_cast<float*>(partial);
+    prof_begin(kProfSketch, st);
     switch (p.terms) {
       case 1:
         hipLaunchKernelGGL((k_sketch_bf16<16, 1>), gsk, dim3(256), 0, st, Tt, p.m_pad, p.n_pad, p.kchunk,
@@ -286,6 +287,7 @@ int sketch_run(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s,
       default:
         return LS_E_ARG;
     }
+    prof_end(kProfSketch, st, 2.0 * (double)s * (double)P->m * (double)(P->n + 1));
     hipLaunchKernelGGL(k_sketch_combine<float>, gcomb, dim3(256), 0, st, Yp, p.s_pad, p.n_pad,
                        (int)p.nsplit, s, p.ncols, scale, Y, ldy);
   } else if (u_s == LS_FP64) {
@@ -297,8 +299,10 @@ int sketch_run(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s,
       hipLaunchKernelGGL(k_pack_f64<float>, gpack, dim3(256), 0, st, (const float*)P->A, P->lda,
                          (const float*)P->b, P->m, P->n, M, p.m_pad, p.n_pad);
     double* Yp = reinterpret_cast<double*>(partial);
+    prof_begin(kProfSketch, st);
     hipLaunchKernelGGL((k_sketch_f64<8>), gsk, dim3(256), 0, st, M, p.m_pad, p.n_pad, p.kchunk, key0,
                        key1, so->prob_id, Yp, p.s_pad);
+    prof_end(kProfSketch, st, 2.0 * (double)s * (double)P->m * (double)(P->n + 1));
     hipLaunchKernelGGL(k_sketch_combine<double>, gcomb, dim3(256), 0, st, Yp, p.s_pad, p.n_pad,
                        (int)p.nsplit, s, p.ncols, scale, Y, ldy);
   } else {
