@@ -113,6 +113,13 @@ size_t iter_bytes(const ls_problem_t* P, const ls_precs_t* pr, const ls_iter_opt
   return m > c ? m : c;
 }
 
+// A second, binary64 copy of B is needed when FGMRES works in binary64 but
+// LSQR in binary32 (u_A = FP64 with u = FP32, or the binary64 fallback).
+bool second_b(const ls_precs_t* pr, const ls_iter_opts_t* io) {
+  if (pr->u != LS_FP32) return false;
+  return pr->u_A == LS_FP64 || io->fallback != 0;
+}
+
 // Make R^-1 available: W (binary64) and its binary32 copy.
 int make_inverse(const double* R, int64_t ldr, int64_t n, const Inv& v, hipStream_t st) {
   LS_HIP_TRY(hipMemsetAsync(v.flag, 0, sizeof(int), st));
@@ -189,7 +196,9 @@ int ls_workspace_size(const ls_problem_t* P, const ls_sketch_opts_t* so, const l
   size_t fixed = ls_align256(8 * (size_t)s * (n + 1))          // Y
                  + ls_align256(8 * (size_t)(n + 1) * (n + 1))    // R_aug
                  + inv_carve(nullptr, n).bytes                   // R^-1
-                 + ls_align256(8 * (size_t)(P->m + n));          // saved x0, r0 for the fallback
+                 + ls_align256(8 * (size_t)(P->m + n))           // saved x0 for the fallback
+                 + b_bytes(P, pr->u)                             // B = A R^-1 for LSQR
+                 + (second_b(pr, &io) ? b_bytes(P, LS_FP64) : 0); // binary64 B for FGMRES
   size_t scratch = sp.operand_bytes + sp.partial_bytes;
   const size_t q = qr_workspace(s, n + 1, pr->u_qr);
   if (q > scratch) scratch = q;
@@ -235,14 +244,18 @@ int ls_lsqr_precond(const ls_problem_t* P, const double* R, int64_t ldr, ls_prec
   if (!prec_is(u, LS_FP32, LS_FP64)) return LS_E_UNSUPPORTED;
   const ls_iter_opts_t io = fill_opts(io_in, P->n, u);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const Inv inv = inv_carve(static_cast<char*>(ws), P->n);
-  const size_t need = inv.bytes + lsqr_workspace(P, u, device_cu_count());
+  char* base = static_cast<char*>(ws);
+  const Inv inv = inv_carve(base, P->n);
+  const size_t bb = b_bytes(P, u);
+  const size_t need = inv.bytes + bb + lsqr_workspace(P, u, device_cu_count());
   if (!ws || ws_bytes < need) return LS_E_WORKSPACE;
   LS_TRY(make_inverse(R, ldr, P->n, inv, st));
+  void* Bm = base + inv.bytes;
+  LS_TRY(form_b(P, inv.W, inv.W32, u, Bm, st));
   if (stats) std::memset(stats, 0, sizeof(*stats));
   prof_reset(io.profile != 0);
-  const int rc = lsqr_device(P, inv.W, inv.W32, P->n, u, x, &io, stats, static_cast<char*>(ws) + inv.bytes,
-                             ws_bytes - inv.bytes, st);
+  const int rc = lsqr_device(P, R, ldr, inv.W, Bm, u, x, &io, stats, base + inv.bytes + bb,
+                             ws_bytes - inv.bytes - bb, st);
   if (stats) {
     stats->status = rc;
     if (io.profile && hipStreamSynchronize(st) == hipSuccess) prof_collect(stats);
@@ -260,14 +273,18 @@ int ls_lsir_gmres(const ls_problem_t* P, const double* R, int64_t ldr, const ls_
   const ls_iter_opts_t io = fill_opts(io_in, P->n, pr->u);
   if (io.fgmres_maxit > 95) return LS_E_ARG;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const Inv inv = inv_carve(static_cast<char*>(ws), P->n);
-  const size_t need = inv.bytes + lsir_workspace(P, pr, io.fgmres_maxit, device_cu_count());
+  char* base = static_cast<char*>(ws);
+  const Inv inv = inv_carve(base, P->n);
+  const size_t bb = b_bytes(P, pr->u_A);
+  const size_t need = inv.bytes + bb + lsir_workspace(P, pr, io.fgmres_maxit, device_cu_count());
   if (!ws || ws_bytes < need) return LS_E_WORKSPACE;
   LS_TRY(make_inverse(R, ldr, P->n, inv, st));
+  void* Bm = base + inv.bytes;
+  LS_TRY(form_b(P, inv.W, inv.W32, pr->u_A, Bm, st));
   if (stats) std::memset(stats, 0, sizeof(*stats));
   prof_reset(io.profile != 0);
-  const int rc = lsir_device(P, inv.W, inv.W32, P->n, pr, x, r, r_given, &io, stats,
-                             static_cast<char*>(ws) + inv.bytes, ws_bytes - inv.bytes, st);
+  const int rc = lsir_device(P, inv.W, Bm, pr, x, r, r_given, &io, stats, base + inv.bytes + bb,
+                             ws_bytes - inv.bytes - bb, st);
   if (stats) {
     stats->status = rc;
     if (io.profile && hipStreamSynchronize(st) == hipSuccess) prof_collect(stats);
@@ -303,6 +320,13 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
   off += inv.bytes;
   double* saved = reinterpret_cast<double*>(base + off);
   off += ls_align256(8 * (size_t)(m + n));
+  void* B1 = base + off;                       // B in the working precision u
+  off += b_bytes(P, pr->u);
+  void* B2 = nullptr;                          // binary64 B for FGMRES when needed
+  if (second_b(pr, &io)) {
+    B2 = base + off;
+    off += b_bytes(P, LS_FP64);
+  }
   char* scratch = base + off;
   const size_t scratch_bytes = ws_bytes - off;
 
@@ -326,8 +350,9 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
     S->status = LS_E_SINGULAR;
     return LS_E_SINGULAR;
   }
-  // Algorithm 2 line 1
-  int rc = lsqr_device(P, inv.W, inv.W32, n, pr->u, x, &io, S, scratch, scratch_bytes, st);
+  // the preconditioned operator B = A R^-1, then Algorithm 2 line 1
+  LS_TRY(form_b(P, inv.W, inv.W32, pr->u, B1, st));
+  int rc = lsqr_device(P, Raug, n + 1, inv.W, B1, pr->u, x, &io, S, scratch, scratch_bytes, st);
   tm.mark(3, st);
   if (rc < 0) {
     S->status = rc;
@@ -337,7 +362,12 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
   if (io.fallback) {
     LS_HIP_TRY(hipMemcpyAsync(saved, x, 8 * (size_t)n, hipMemcpyDeviceToDevice, st));
   }
-  rc = lsir_device(P, inv.W, inv.W32, n, pr, x, r, 0, &io, S, scratch, scratch_bytes, st);
+  void* Bfg = B1;
+  if (pr->u_A != pr->u) {
+    LS_TRY(form_b(P, inv.W, inv.W32, pr->u_A, B2, st));
+    Bfg = B2;
+  }
+  rc = lsir_device(P, inv.W, Bfg, pr, x, r, 0, &io, S, scratch, scratch_bytes, st);
   if (rc == LS_NOT_CONVERGED && io.fallback) {
     // Section 5: rerun the refinement with u_A = u_L = u_R = binary64 and up to 80 FGMRES iterations.
     ls_precs_t p2 = *pr;
@@ -346,7 +376,9 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
     io2.fgmres_maxit = 80;
     LS_HIP_TRY(hipMemcpyAsync(x, saved, 8 * (size_t)n, hipMemcpyDeviceToDevice, st));
     S->fallback_used = 1;
-    rc = lsir_device(P, inv.W, inv.W32, n, &p2, x, r, 0, &io2, S, scratch, scratch_bytes, st);
+    void* B64 = (pr->u == LS_FP64) ? B1 : B2;
+    if (Bfg != B64) LS_TRY(form_b(P, inv.W, inv.W32, LS_FP64, B64, st));
+    rc = lsir_device(P, inv.W, B64, &p2, x, r, 0, &io2, S, scratch, scratch_bytes, st);
   }
   tm.mark(4, st);
   LS_HIP_TRY(hipStreamSynchronize(st));

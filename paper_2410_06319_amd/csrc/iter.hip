@@ -1,17 +1,23 @@
 // Algorithm 2 on gfx950: LSQR right-preconditioned with R (line 1) and
 // augmented-system refinement with split-preconditioned FGMRES (lines 2-10).
 //
-// R^-1 is applied through the explicit upper-triangular W = R^-1 (formed once
-// in binary64), so every preconditioner application is a parallel triangular
-// matrix-vector product.  The products with A are HBM-bound; each iteration
-// reads A once: a block of RB rows of A (all n columns) is staged in LDS and
-// used for both the row products (A p) and the column products (A^T u).
-// Column products are per-block partial sums reduced by a second kernel in a
-// fixed order, so results are reproducible run to run.
+// The preconditioned operator B = A R^-1 is formed once per call (an MFMA
+// GEMM with the explicit upper-triangular W = R^-1).  LSQR then works on
+// min ||b - B z|| with x = W z, and FGMRES on the split-preconditioned
+// augmented matrix, which is exactly [I B; B^T 0]; R^-1 is applied only to
+// the final corrections.  The refinement residuals (lines 5-6) use A itself.
+//
+// Every iteration reads B once: a block of RB rows (all n columns) is
+// prefetched into registers while the previous block, staged in LDS, is used
+// for both the row products (B v) and the column products (B^T u).  Each
+// block of threads owns a contiguous range of row blocks.  Column products
+// are per-block partial sums, stored column-major (partial[c * G + block]) so
+// that a wave reduces one column with coalesced loads, in a fixed order.
 //
 // Scalars live in device memory; kernels of one iteration are enqueued back
-// to back and the host only reads a convergence flag every few iterations.
+// to back and the host reads a convergence flag every few iterations.
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -21,8 +27,12 @@ namespace ls {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kMaxVecLoads = 16;   // 16-byte loads per thread held in flight for one row block
+constexpr int kMaxTile = 12;       // Krylov-tile values per thread in the FGMRES pass (RB (j+1) <= 3072)
 
-// ------------------------------------------------------------------ helpers
+typedef float ls_float4v __attribute__((ext_vector_type(4)));
+typedef double ls_double4v __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ double* align8(void* p) {
   return reinterpret_cast<double*>(((uintptr_t)p + 7) & ~(uintptr_t)7);
 }
@@ -32,101 +42,289 @@ __device__ __forceinline__ T block_sum256(T v, T* sh) {
   return ls_block_sum<T, kThreads>(v, sh);
 }
 
-// Stage rows [i0, i0+RB) x columns [0, n) of A into As[j * (RB+1) + r] (type T).
-template <typename TA, typename T, int RB>
-__device__ __forceinline__ void load_rows(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n, int64_t i0,
-                                          bool vec_ok, T* __restrict__ As) {
-  constexpr int LDR = RB + 1;
-  constexpr int V = 16 / (int)sizeof(TA);
-  static_assert(RB % V == 0, "row block must hold whole vectors");
-  if (vec_ok && i0 + RB <= m) {
-    constexpr int PER = RB / V;
-    const int total = (int)n * PER;
-    for (int idx = threadIdx.x; idx < total; idx += kThreads) {
-      const int j = idx / PER;
-      const int q = idx - j * PER;
-      const TA* src = A + i0 + q * V + (int64_t)j * lda;
-      T* dst = As + j * LDR + q * V;
-      if constexpr (V == 4) {
-        const float4 v = *reinterpret_cast<const float4*>(src);
-        dst[0] = (T)v.x;
-        dst[1] = (T)v.y;
-        dst[2] = (T)v.z;
-        dst[3] = (T)v.w;
-      } else {
-        const double2 v = *reinterpret_cast<const double2*>(src);
-        dst[0] = (T)v.x;
-        dst[1] = (T)v.y;
-      }
-    }
-  } else {
-    const int total = (int)n * RB;
-    for (int idx = threadIdx.x; idx < total; idx += kThreads) {
-      const int j = idx / RB;
-      const int r = idx - j * RB;
-      const int64_t i = i0 + r;
-      As[j * LDR + r] = (i < m) ? (T)A[i + (int64_t)j * lda] : T(0);
-    }
-  }
+// Sum of part[0..G) by one wave (all lanes get the result).
+__device__ __forceinline__ double wave_sum_array(const double* __restrict__ part, int G, int lane) {
+  double s = 0.0;
+  for (int g = lane; g < G; g += 64) s += part[g];
+  return ls_wave_sum(s);
 }
 
-// q[r] = sum_j As[j][r] * vec[j] for r < RB, via RB x (256/RB) thread layout.
+// ------------------------------------------------------------------ row-block staging
+// A block of RB rows x n columns of a column-major matrix M (ld), loaded with
+// 16-byte vectors into registers (vec path: every row in range, aligned) and
+// stored to LDS as Ms[j * (RB+1) + r].
 template <typename T, int RB>
-__device__ __forceinline__ T rows_times_vec(const T* __restrict__ As, const T* __restrict__ vec, int64_t n,
+struct RowBlock {
+  static constexpr int V = 16 / (int)sizeof(T);
+  static constexpr int PER = RB / V;       // vectors per column segment
+  using vec_t = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+  vec_t reg[kMaxVecLoads];
+  bool full;
+
+  __device__ __forceinline__ void load(const T* __restrict__ M, int64_t ld, int64_t m, int64_t n, int64_t i0,
+                                       bool vec_ok) {
+    full = vec_ok && (i0 + RB <= m);
+    if (!full) return;
+    const int total = (int)n * PER;
+#pragma unroll
+    for (int q = 0; q < kMaxVecLoads; ++q) {
+      const int idx = threadIdx.x + q * kThreads;
+      if (idx < total) {
+        const int j = idx / PER;
+        const int p = idx - j * PER;
+        reg[q] = *reinterpret_cast<const vec_t*>(M + i0 + p * V + (int64_t)j * ld);
+      }
+    }
+  }
+
+  __device__ __forceinline__ void store(const T* __restrict__ M, int64_t ld, int64_t m, int64_t n, int64_t i0,
+                                        T* __restrict__ Ms) const {
+    constexpr int LDR = RB + 1;
+    if (full) {
+      const int total = (int)n * PER;
+#pragma unroll
+      for (int q = 0; q < kMaxVecLoads; ++q) {
+        const int idx = threadIdx.x + q * kThreads;
+        if (idx < total) {
+          const int j = idx / PER;
+          const int p = idx - j * PER;
+          T* dst = Ms + j * LDR + p * V;
+          if constexpr (V == 4) {
+            dst[0] = reg[q].x;
+            dst[1] = reg[q].y;
+            dst[2] = reg[q].z;
+            dst[3] = reg[q].w;
+          } else {
+            dst[0] = reg[q].x;
+            dst[1] = reg[q].y;
+          }
+        }
+      }
+    } else {
+      const int total = (int)n * RB;
+      for (int idx = threadIdx.x; idx < total; idx += kThreads) {
+        const int j = idx / RB;
+        const int r = idx - j * RB;
+        const int64_t i = i0 + r;
+        Ms[j * LDR + r] = (i < m) ? M[i + (int64_t)j * ld] : T(0);
+      }
+    }
+  }
+};
+
+// q[r] = sum_j Ms[j][r] * vec[j] for r < RB (RB x (256/RB) thread layout).
+template <typename T, int RB>
+__device__ __forceinline__ T rows_times_vec(const T* __restrict__ Ms, const T* __restrict__ vec, int64_t n,
                                             T* __restrict__ red) {
   constexpr int LDR = RB + 1;
   constexpr int G1 = kThreads / RB;
   const int r = threadIdx.x % RB;
   const int g = threadIdx.x / RB;
-  T acc = 0;
-  for (int j = g; j < n; j += G1) acc += As[j * LDR + r] * vec[j];
-  red[g * RB + r] = acc;
+  T a0 = 0, a1 = 0;
+  int j = g;
+  for (; j + G1 < n; j += 2 * G1) {
+    a0 += Ms[j * LDR + r] * vec[j];
+    a1 += Ms[(j + G1) * LDR + r] * vec[j + G1];
+  }
+  if (j < n) a0 += Ms[j * LDR + r] * vec[j];
+  red[g * RB + r] = a0 + a1;
   __syncthreads();
   T q = 0;
   if (threadIdx.x < RB) {
-#pragma unroll 4
+#pragma unroll
     for (int gg = 0; gg < G1; ++gg) q += red[gg * RB + threadIdx.x];
   }
   return q;   // valid in threads < RB
 }
 
-// ================================================================== LSQR
-// One pass over A:  u <- A p - coef * u  (coef = alpha_i / beta_i), partial
-// ||u||^2, partial t = A^T u.  Init mode: u <- b - A x0 (p holds -x0, coef = -1,
-// the old u is b) and partial ||b||^2.
-template <typename TA, typename T, int RB>
-__global__ __launch_bounds__(kThreads) void k_lsqr_pass(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n,
-                                                        int vec_ok, const T* __restrict__ p, T* __restrict__ u,
-                                                        const TA* __restrict__ b, const LsqrState* __restrict__ st,
-                                                        int par, int init, T* __restrict__ tpart,
+// Range of row blocks owned by block `bx` of G.
+__device__ __forceinline__ void row_range(int64_t nrb, int G, int bx, int64_t& b0, int64_t& b1) {
+  b0 = (nrb * bx) / G;
+  b1 = (nrb * (bx + 1)) / G;
+}
+
+// ================================================================== B = A W
+// MFMA 16x16x4 (binary32 or binary64).  Block tile 64 x 64, K step 16; wave w
+// owns rows 32 (w & 1) .. +32 and columns 32 (w >> 1) .. +32 (2 x 2 MFMA tiles).
+// W is upper triangular: column tile [j0, j0+64) needs K < j0 + 64 only.
+__device__ __forceinline__ ls_float4v mfma4(float a, float b, ls_float4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ ls_double4v mfma4(double a, double b, ls_double4v c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// Row of the D element held in slot r of lane l: binary32 rows are blocked,
+// binary64 rows interleaved.
+template <typename T>
+__device__ __forceinline__ int mfma_drow(int lane, int r) {
+  return (sizeof(T) == 4) ? 4 * (lane >> 4) + r : (lane >> 4) + 4 * r;
+}
+
+template <typename TA, typename T>
+__global__ __launch_bounds__(kThreads) void k_form_b(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                                                     const T* __restrict__ W, T* __restrict__ B, int64_t ldb) {
+  using acc_t = typename std::conditional<sizeof(T) == 4, ls_float4v, ls_double4v>::type;
+  __shared__ T As[16][64 + 1];   // As[k][i]
+  __shared__ T Ws[16][64 + 1];   // Ws[k][j]
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  const int64_t j0 = (int64_t)blockIdx.y * 64;
+  const int64_t kend = (j0 + 64 < n) ? j0 + 64 : n;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  acc_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  for (int64_t k0 = 0; k0 < kend; k0 += 16) {
+    __syncthreads();
+    for (int idx = t; idx < 16 * 64; idx += kThreads) {
+      const int kk = idx / 64, ii = idx % 64;       // A tile: column kk, row ii (coalesced over ii)
+      const int64_t gi = i0 + ii, gk = k0 + kk;
+      As[kk][ii] = (gi < m && gk < n) ? (T)A[gi + gk * lda] : T(0);
+      const int jj = idx / 16, k2 = idx % 16;       // W tile: column jj, row k2 (coalesced over k2)
+      const int64_t gj = j0 + jj, gk2 = k0 + k2;
+      Ws[k2][jj] = (gj < n && gk2 < n) ? W[gk2 + gj * n] : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int kk = ks * 4 + (lane >> 4);
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const T av = As[kk][wr + a * 16 + (lane & 15)];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = mfma4(av, Ws[kk][wc + b * 16 + (lane & 15)], acc[a][b]);
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int64_t gj = j0 + wc + b * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gi = i0 + wr + a * 16 + mfma_drow<T>(lane, r);
+        if (gi < m && gj < n) B[gi + gj * ldb] = acc[a][b][r];
+      }
+    }
+}
+
+// out = W v (+ v2) for upper-triangular W (n x n, ld): 16 rows x 16 column groups per block.
+template <typename TW, typename TV>
+__global__ __launch_bounds__(kThreads) void k_trmv(const TW* __restrict__ W, int64_t ldw, int64_t n,
+                                                   const TV* __restrict__ v, const TV* __restrict__ v2,
+                                                   double* __restrict__ out) {
+  __shared__ double red[16][17];
+  const int r = threadIdx.x & 15, cg = threadIdx.x >> 4;
+  const int64_t row = (int64_t)blockIdx.x * 16 + r;
+  double acc = 0.0;
+  if (row < n) {
+    for (int64_t j = row + cg; j < n; j += 16) {
+      const double vj = (double)v[j] + (v2 ? (double)v2[j] : 0.0);
+      acc += (double)W[row + j * ldw] * vj;
+    }
+  }
+  red[cg][r] = acc;
+  __syncthreads();
+  if (cg == 0 && row < n) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) s += red[q][r];
+    out[row] = s;
+  }
+}
+
+template <typename TO, typename TI>
+__global__ __launch_bounds__(kThreads) void k_cast(const TI* __restrict__ a, TO* __restrict__ b, int64_t n, TO sign) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) b[i] = sign * (TO)a[i];
+}
+
+__global__ void k_zero_bytes(char* p, size_t nbytes) {
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nbytes; i += (size_t)gridDim.x * kThreads) p[i] = 0;
+}
+
+// ================================================================== LSQR on B
+// Carried state C_i (written by the column kernel of iteration i-1).
+// Iteration i:  pass:   u_{i+1} = B v_i / alpha_i - (alpha_i / beta_i) u_i  (unnormalised u)
+//               column: beta_{i+1}, rotation i, w_i, y, v_{i+1} = B^T u / beta - (beta/alpha) v_i
+struct LsqrRec {
+  double c, s;        // rotation of iteration i-1 (init: c = -1, s = 0)
+  double rho;         // rho_{i-1}
+  double phibar;      // phibar_i
+  double normB2;      // sum over k < i of alpha_k^2 + beta_{k+1}^2
+  double beta;        // beta_i
+  double alpha_prev;  // alpha_{i-1}
+  double normr, normar, normB;
+  int32_t its, done, stop, pad;
+};
+struct LsqrState {
+  LsqrRec rec[2];
+  double normb;
+  int32_t flag, pad;
+};
+
+template <typename T, int RB>
+__global__ __launch_bounds__(kThreads) void k_lsqr_pass(const T* __restrict__ B, int64_t ldb, int64_t m, int64_t n,
+                                                        int vec_ok, const T* __restrict__ v,
+                                                        const double* __restrict__ nvpart, int Gv,
+                                                        T* __restrict__ u, const LsqrState* __restrict__ st, int par,
+                                                        int init, T* __restrict__ tpart,
                                                         double* __restrict__ nupart, double* __restrict__ nbpart) {
   if (!init && st->rec[par].done) return;
   extern __shared__ __align__(16) char smem[];
   constexpr int LDR = RB + 1;
-  T* As = reinterpret_cast<T*>(smem);
-  T* ps = As + n * LDR;
-  T* tacc = ps + n;
+  T* Ms = reinterpret_cast<T*>(smem);
+  T* vs = Ms + n * LDR;
+  T* tacc = vs + n;
   T* uu = tacc + n;
   T* red = uu + RB;
   double* dsh = align8(red + kThreads);
-  const T coef = init ? T(-1) : (T)(st->rec[par].alpha / st->beta);
+  const int lane = threadIdx.x & 63;
+  T scale = 1, coef = -1;
+  if (!init) {
+    const double alpha = sqrt(wave_sum_array(nvpart, Gv, lane));
+    scale = (T)(1.0 / alpha);
+    coef = (T)(alpha / st->rec[par].beta);
+  }
   for (int j = threadIdx.x; j < n; j += kThreads) {
-    ps[j] = init ? -p[j] : p[j];
+    vs[j] = v[j] * scale;
     tacc[j] = 0;
   }
   double nu = 0.0, nb = 0.0;
   const int64_t nrb = ls_cdiv(m, RB);
-  for (int64_t rb = blockIdx.x; rb < nrb; rb += gridDim.x) {
+  int64_t b0, b1;
+  row_range(nrb, gridDim.x, blockIdx.x, b0, b1);
+  RowBlock<T, RB> blk;
+  T pre_u = 0;   // u of this thread's row in the next block (threads < RB)
+  auto load_u = [&](int64_t i0) {
+    if (threadIdx.x < RB) {
+      const int64_t i = i0 + threadIdx.x;
+      pre_u = (i < m) ? u[i] : T(0);
+    }
+  };
+  if (b0 < b1) {
+    blk.load(B, ldb, m, n, b0 * RB, vec_ok != 0);
+    load_u(b0 * RB);
+  }
+  for (int64_t rb = b0; rb < b1; ++rb) {
     const int64_t i0 = rb * RB;
     __syncthreads();
-    load_rows<TA, T, RB>(A, lda, m, n, i0, vec_ok != 0, As);
+    blk.store(B, ldb, m, n, i0, Ms);
+    const T uo = pre_u;
     __syncthreads();
-    const T q = rows_times_vec<T, RB>(As, ps, n, red);
+    if (rb + 1 < b1) {   // next block in flight during the compute below
+      blk.load(B, ldb, m, n, i0 + RB, vec_ok != 0);
+      load_u(i0 + RB);
+    }
+    const T q = rows_times_vec<T, RB>(Ms, vs, n, red);
     if (threadIdx.x < RB) {
       const int64_t i = i0 + threadIdx.x;
       T un = 0;
       if (i < m) {
-        const T uo = init ? (T)b[i] : u[i];
         un = q - coef * uo;
         u[i] = un;
         if (init) nb += (double)uo * (double)uo;
@@ -138,12 +336,12 @@ __global__ __launch_bounds__(kThreads) void k_lsqr_pass(const TA* __restrict__ A
     for (int j = threadIdx.x; j < n; j += kThreads) {
       T acc = 0;
 #pragma unroll 8
-      for (int r = 0; r < RB; ++r) acc += As[j * LDR + r] * uu[r];
+      for (int r = 0; r < RB; ++r) acc += Ms[j * LDR + r] * uu[r];
       tacc[j] += acc;
     }
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < n; j += kThreads) tpart[(int64_t)blockIdx.x * n + j] = tacc[j];
+  for (int j = threadIdx.x; j < n; j += kThreads) tpart[(int64_t)j * gridDim.x + blockIdx.x] = tacc[j];
   nu = block_sum256(nu, dsh);
   nb = block_sum256(nb, dsh + 4);
   if (threadIdx.x == 0) {
@@ -152,163 +350,157 @@ __global__ __launch_bounds__(kThreads) void k_lsqr_pass(const TA* __restrict__ A
   }
 }
 
-// beta = sqrt(sum nupart); t[j] = (sum_g tpart[g][j]) / beta.  Block: 64 columns x 4 groups.
+// Column kernel, one wave per column (4 per block).  Reads rec[par] (C_i),
+// block 0 writes rec[par ^ 1] (C_{i+1}).  Init: v_1 = B^T u_1 / beta_1.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_lsqr_reduce(const T* __restrict__ tpart, int G, int64_t n,
-                                                          const double* __restrict__ nupart,
-                                                          const double* __restrict__ nbpart, LsqrState* st, int par,
-                                                          int init, T* __restrict__ t) {
-  if (!init && st->rec[par].done) return;
-  __shared__ double dsh[8];
-  __shared__ T red[4][64];
-  double s = 0.0, sb = 0.0;
-  for (int g = threadIdx.x; g < G; g += kThreads) {
-    s += nupart[g];
-    if (init) sb += nbpart[g];
-  }
-  s = block_sum256(s, dsh);
-  sb = block_sum256(sb, dsh + 4);
-  const double beta = sqrt(s);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    st->beta = beta;
-    if (init) st->normb = sqrt(sb);
-    if (!isfinite(beta)) st->flag = 1;
-  }
-  const int c = threadIdx.x & 63;
-  const int gg = threadIdx.x >> 6;
-  const int64_t j = (int64_t)blockIdx.x * 64 + c;
-  T acc = 0;
-  if (j < n)
-    for (int g = gg; g < G; g += 4) acc += tpart[(int64_t)g * n + j];
-  red[gg][c] = acc;
-  __syncthreads();
-  if (gg == 0 && j < n) {
-    const T tot = red[0][c] + red[1][c] + red[2][c] + red[3][c];
-    t[j] = (beta > 0.0) ? (T)(tot / (T)beta) : T(0);
-  }
-}
-
-// v <- W^T t - (beta_{i+1} / alpha_i) v   (init: v <- W^T t); partial ||v||^2.
-// One wave per column j: v_j = sum_{i <= j} W[i + j ldw] t[i].
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_lsqr_vupdate(const T* __restrict__ W, int64_t ldw, int64_t n,
-                                                           const T* __restrict__ t, T* __restrict__ v,
-                                                           const LsqrState* __restrict__ st, int par, int init,
-                                                           double* __restrict__ nvpart) {
-  if (!init && st->rec[par].done) return;
+__global__ __launch_bounds__(kThreads) void k_lsqr_col(int64_t n, const T* __restrict__ tpart, int G,
+                                                       const double* __restrict__ nupart,
+                                                       const double* __restrict__ nbpart,
+                                                       const double* __restrict__ nvpart_in, int Gv,
+                                                       double* __restrict__ nvpart_out, LsqrState* st, int par,
+                                                       int init, int it, double tol, T* __restrict__ v,
+                                                       T* __restrict__ w, double* __restrict__ y) {
   __shared__ double dsh[4];
+  const LsqrRec R = st->rec[par];
+  if (!init && R.done) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->rec[par ^ 1] = R;
+    return;
+  }
   const int lane = threadIdx.x & 63;
-  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t col = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const double beta = sqrt(wave_sum_array(nupart, G, lane));          // beta_{i+1}
+  LsqrRec N = R;
+  double alpha = 0.0, xw = 0.0, yw = 0.0, vcoef = 0.0;
+  bool done = false;
+  if (init) {
+    N.c = -1.0;
+    N.s = 0.0;
+    N.rho = 1.0;
+    N.phibar = beta;
+    N.normB2 = 0.0;
+    N.beta = beta;
+    N.alpha_prev = 0.0;
+    N.its = 0;
+    N.stop = (beta == 0.0) ? 4 : 0;
+    done = N.stop != 0;
+    N.done = done ? 1 : 0;
+  } else {
+    alpha = sqrt(wave_sum_array(nvpart_in, Gv, lane));                // alpha_i
+    const double rhobar = -R.c * alpha;
+    const double theta = R.s * alpha;
+    // stopping tests of iteration i-1 (they need alpha_i)
+    if (it > 1) {
+      N.normr = R.phibar;
+      N.normar = R.phibar * alpha * fabs(R.c);
+      N.normB = sqrt(R.normB2);
+      N.its = it - 1;
+      int stop = 0;
+      if (N.normr <= tol * st->normb) stop = 1;
+      else if (N.normar <= tol * N.normB * N.normr) stop = 2;
+      else if (alpha == 0.0) stop = 4;
+      if (stop) {
+        N.stop = stop;
+        N.done = 1;
+        done = true;
+      }
+    }
+    if (!done) {
+      N.normB2 = R.normB2 + alpha * alpha + beta * beta;
+      const double rho = hypot(rhobar, beta);
+      const double c = rhobar / rho;
+      const double sn = beta / rho;
+      const double phi = c * R.phibar;
+      N.phibar = sn * R.phibar;
+      N.c = c;
+      N.s = sn;
+      N.rho = rho;
+      N.beta = beta;
+      N.alpha_prev = alpha;
+      N.its = it;
+      xw = (it == 1) ? 0.0 : theta / R.rho;        // w_i = v_i - (theta_i / rho_{i-1}) w_{i-1}
+      yw = phi / rho;                              // y += (phi_i / rho_i) w_i
+      vcoef = beta / alpha;                        // v_{i+1} = t - (beta_{i+1} / alpha_i) v_i
+      if (!isfinite(yw) || !isfinite(xw) || !isfinite(vcoef)) {
+        N.stop = 5;
+        N.done = 1;
+        done = true;
+      } else if (beta == 0.0) {
+        N.stop = 4;   // exact solution reached after this update
+      }
+    }
+  }
   double contrib = 0.0;
-  if (j < n) {
-    const T* wc = W + j * ldw;
+  if (!done && col < n) {
+    const T* tp = tpart + col * G;
     T acc = 0;
-    for (int64_t i = lane; i <= j; i += 64) acc += wc[i] * t[i];
+    for (int g = lane; g < G; g += 64) acc += tp[g];
     acc = ls_wave_sum(acc);
     if (lane == 0) {
-      T vn = acc;
-      if (!init) vn -= (T)(st->beta / st->rec[par].alpha) * v[j];
-      v[j] = vn;
+      const T t = (beta > 0.0) ? (T)(acc / (T)beta) : T(0);
+      T vn;
+      if (init) {
+        vn = t;
+      } else {
+        const T vo = v[col];
+        const T wi = vo * (T)(1.0 / alpha) - (T)xw * w[col];
+        w[col] = wi;
+        y[col] += yw * (double)wi;
+        vn = t - (T)vcoef * vo;
+      }
+      v[col] = vn;
       contrib = (double)vn * (double)vn;
     }
   }
   contrib = block_sum256(contrib, dsh);
-  if (threadIdx.x == 0) nvpart[blockIdx.x] = contrib;
-}
-
-// Start of iteration `it`: alpha_it = ||v||, the plane rotation of iteration
-// it-1, the stopping tests, x <- x + (phi/rho) what, then p = W v / alpha and
-// what <- p - (theta/rho) what.  Reads rec[par], writes rec[par ^ 1].
-// Block: 64 rows of W; its 4 waves split the columns.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_lsqr_step(const T* __restrict__ W, int64_t ldw, int64_t n,
-                                                        const T* __restrict__ v, const double* __restrict__ nvpart,
-                                                        int Gv, LsqrState* st, int par, int it, int final_step,
-                                                        double tol, int maxit, T* __restrict__ p,
-                                                        T* __restrict__ what, double* __restrict__ x) {
-  __shared__ double dsh[4];
-  __shared__ T red[4][64];
-  const LsqrRec R = st->rec[par];
-  if (R.done) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->rec[par ^ 1] = R;
-    return;
-  }
-  double s = 0.0;
-  for (int g = threadIdx.x; g < Gv; g += kThreads) s += nvpart[g];
-  s = block_sum256(s, dsh);
-  const double alpha = sqrt(s);
-  const double beta = st->beta;
-  LsqrRec N = R;
-  double xcoef = 0.0, wcoef = 0.0;
-  int stop = 0;
-  if (it == 1) {
-    N.rhobar = alpha;
-    N.phibar = beta;
-    N.normB2 = 0.0;
-    N.normr = beta;
-    if (beta == 0.0) stop = 4;
-  } else {
-    N.normB2 = R.normB2 + R.alpha * R.alpha + beta * beta;
-    const double rho = hypot(R.rhobar, beta);
-    const double c = R.rhobar / rho;
-    const double sn = beta / rho;
-    const double theta = sn * alpha;
-    N.rhobar = -c * alpha;
-    const double phi = c * R.phibar;
-    N.phibar = sn * R.phibar;
-    xcoef = phi / rho;
-    wcoef = theta / rho;
-    N.normr = N.phibar;
-    N.normar = N.phibar * alpha * fabs(c);
-    N.normB = sqrt(N.normB2);
-    N.its = it - 1;
-    if (N.normr <= tol * st->normb) stop = 1;
-    else if (N.normar <= tol * N.normB * N.normr) stop = 2;
-    else if (beta == 0.0 || alpha == 0.0) stop = 4;
-    else if (final_step || it - 1 >= maxit) stop = 3;
-    if (!isfinite(xcoef) || !isfinite(wcoef)) {
-      stop = 5;
-      xcoef = 0.0;
-    }
-  }
-  N.alpha = alpha;
-  N.phi_over_rho = xcoef;
-  N.theta_over_rho = wcoef;
-  const bool done = stop != 0;
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int64_t r = (int64_t)blockIdx.x * 64 + lane;
-  T acc = 0;
-  if (!done && r < n) {
-    const int64_t r0 = (int64_t)blockIdx.x * 64;
-    for (int64_t j = r0 + wv; j < n; j += 4) acc += W[r + j * ldw] * v[j];
-  }
-  red[wv][lane] = acc;
-  __syncthreads();
-  if (wv == 0 && r < n) {
-    if (it > 1) x[r] = (double)((T)x[r] + (T)xcoef * what[r]);
-    if (!done) {
-      const T pr = (red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane]) / (T)alpha;
-      p[r] = pr;
-      what[r] = (it == 1) ? pr : pr - (T)wcoef * what[r];
-    }
-  }
+  if (threadIdx.x == 0) nvpart_out[blockIdx.x] = contrib;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    N.done = done ? 1 : 0;
-    N.stop = stop;
-    if (stop == 5) st->flag = 1;
+    if (init) {
+      double sb = 0.0;
+      for (int g = 0; g < G; ++g) sb += nbpart[g];
+      st->normb = sqrt(sb);
+    }
+    if (N.stop == 4 && !init) N.done = 1;
+    if (N.stop == 5) st->flag = 1;
     st->rec[par ^ 1] = N;
   }
 }
 
-template <typename TO>
-__global__ __launch_bounds__(kThreads) void k_cast_vec(const double* __restrict__ a, TO* __restrict__ b, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i < n) b[i] = (TO)a[i];
-}
-
-__global__ void k_zero_bytes(char* p, size_t nbytes) {
-  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nbytes; i += (size_t)gridDim.x * kThreads) p[i] = 0;
+// Final: stopping data of the last iteration (needs alpha_{k+1}) and x = W (z0 + y).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_lsqr_finish(const double* __restrict__ W, int64_t n,
+                                                          const double* __restrict__ z0,
+                                                          const double* __restrict__ y,
+                                                          const double* __restrict__ nvpart, int Gv,
+                                                          LsqrState* st, int par, int it, double* __restrict__ x) {
+  __shared__ double red[16][17];
+  const int lane = threadIdx.x & 63;
+  if (blockIdx.x == 0 && threadIdx.x < 64) {
+    const double alpha = sqrt(wave_sum_array(nvpart, Gv, lane));
+    if (lane == 0) {
+      LsqrRec R = st->rec[par];
+      if (!R.done) {
+        R.normr = R.phibar;
+        R.normar = R.phibar * alpha * fabs(R.c);
+        R.normB = sqrt(R.normB2);
+        R.its = it;
+        R.stop = 3;
+      }
+      st->rec[par] = R;
+    }
+  }
+  const int r = threadIdx.x & 15, cg = threadIdx.x >> 4;
+  const int64_t row = (int64_t)blockIdx.x * 16 + r;
+  double acc = 0.0;
+  if (row < n)
+    for (int64_t j = row + cg; j < n; j += 16) acc += W[row + j * n] * (z0[j] + y[j]);
+  red[cg][r] = acc;
+  __syncthreads();
+  if (cg == 0 && row < n) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) s += red[q][r];
+    x[row] = (double)(T)s;
+  }
 }
 
 // ================================================================== refinement
@@ -323,13 +515,19 @@ __global__ __launch_bounds__(kThreads) void k_resid_u(const TA* __restrict__ A, 
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= m) return;
-  T acc = 0;
-  for (int64_t j = 0; j < n; ++j) acc += (T)A[i + j * lda] * xs[j];
-  r[i] = (double)((T)b[i] - acc);
+  T a0 = 0, a1 = 0;
+  int64_t j = 0;
+  for (; j + 1 < n; j += 2) {
+    a0 += (T)A[i + j * lda] * xs[j];
+    a1 += (T)A[i + (j + 1) * lda] * xs[j + 1];
+  }
+  if (j < n) a0 += (T)A[i + j * lda] * xs[j];
+  r[i] = (double)((T)b[i] - (a0 + a1));
 }
 
 // Line 5 in u_r: f = b - r - A x (rows, written to V[:, 0]) and partial
-// t = A^T r; binary64, or double-double accumulation when DD.
+// g = A^T r (column-major partials); binary64, or double-double when DD.
+// A is staged as stored (TA) and widened when used.
 template <typename TA, bool DD, int RB>
 __global__ __launch_bounds__(kThreads) void k_lsir_resid(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n,
                                                          int vec_ok, const TA* __restrict__ b,
@@ -339,8 +537,8 @@ __global__ __launch_bounds__(kThreads) void k_lsir_resid(const TA* __restrict__ 
   extern __shared__ __align__(16) char smem[];
   constexpr int LDR = RB + 1;
   constexpr int G1 = kThreads / RB;
-  double* As = reinterpret_cast<double*>(smem);
-  double* xs = As + n * LDR;
+  TA* Ms = reinterpret_cast<TA*>(smem);
+  double* xs = align8(Ms + n * LDR);
   double* thi = xs + n;
   double* tlo = thi + n;
   double* rr = tlo + n;
@@ -354,18 +552,23 @@ __global__ __launch_bounds__(kThreads) void k_lsir_resid(const TA* __restrict__ 
   }
   double fn = 0.0;
   const int64_t nrb = ls_cdiv(m, RB);
-  for (int64_t rb = blockIdx.x; rb < nrb; rb += gridDim.x) {
+  int64_t b0, b1;
+  row_range(nrb, gridDim.x, blockIdx.x, b0, b1);
+  RowBlock<TA, RB> blk;
+  if (b0 < b1) blk.load(A, lda, m, n, b0 * RB, vec_ok != 0);
+  for (int64_t rb = b0; rb < b1; ++rb) {
     const int64_t i0 = rb * RB;
     __syncthreads();
-    load_rows<TA, double, RB>(A, lda, m, n, i0, vec_ok != 0, As);
+    blk.store(A, lda, m, n, i0, Ms);
     __syncthreads();
+    if (rb + 1 < b1) blk.load(A, lda, m, n, i0 + RB, vec_ok != 0);
     {
       const int rw = threadIdx.x % RB;
       const int g = threadIdx.x / RB;
       ls_dd acc{0.0, 0.0};
       for (int j = g; j < n; j += G1) {
-        if (DD) acc = ls_dd_fma(acc, As[j * LDR + rw], xs[j]);
-        else acc.hi += As[j * LDR + rw] * xs[j];
+        if (DD) acc = ls_dd_fma(acc, (double)Ms[j * LDR + rw], xs[j]);
+        else acc.hi += (double)Ms[j * LDR + rw] * xs[j];
       }
       rhi[g * RB + rw] = acc.hi;
       rlo[g * RB + rw] = acc.lo;
@@ -397,58 +600,49 @@ __global__ __launch_bounds__(kThreads) void k_lsir_resid(const TA* __restrict__ 
     for (int j = threadIdx.x; j < n; j += kThreads) {
       if (DD) {
         ls_dd acc{thi[j], tlo[j]};
-        for (int rw = 0; rw < RB; ++rw) acc = ls_dd_fma(acc, As[j * LDR + rw], rr[rw]);
+        for (int rw = 0; rw < RB; ++rw) acc = ls_dd_fma(acc, (double)Ms[j * LDR + rw], rr[rw]);
         thi[j] = acc.hi;
         tlo[j] = acc.lo;
       } else {
         double acc = 0.0;
-        for (int rw = 0; rw < RB; ++rw) acc += As[j * LDR + rw] * rr[rw];
+        for (int rw = 0; rw < RB; ++rw) acc += (double)Ms[j * LDR + rw] * rr[rw];
         thi[j] += acc;
       }
     }
   }
   __syncthreads();
   for (int j = threadIdx.x; j < n; j += kThreads) {
-    tpart_hi[(int64_t)blockIdx.x * n + j] = thi[j];
-    tpart_lo[(int64_t)blockIdx.x * n + j] = tlo[j];
+    tpart_hi[(int64_t)j * gridDim.x + blockIdx.x] = thi[j];
+    tpart_lo[(int64_t)j * gridDim.x + blockIdx.x] = tlo[j];
   }
   fn = block_sum256(fn, dsh);
   if (threadIdx.x == 0) fpart[blockIdx.x] = fn;
 }
 
-// g = -(sum of column partials), then h = W^T g (line 6) into V[m:, 0]; partial ||h||^2.
-// Block: 4 waves, one column each; each wave first needs g[0..j]: g is formed
-// by a preceding reduction into gbuf.
+// g = -(A^T r) from the column partials; one wave per column.
 template <bool DD>
 __global__ __launch_bounds__(kThreads) void k_lsir_g(const double* __restrict__ tpart_hi,
                                                      const double* __restrict__ tpart_lo, int G, int64_t n,
                                                      double* __restrict__ g) {
-  __shared__ double rh[4][64];
-  __shared__ double rl[4][64];
-  const int c = threadIdx.x & 63;
-  const int gg = threadIdx.x >> 6;
-  const int64_t j = (int64_t)blockIdx.x * 64 + c;
+  const int lane = threadIdx.x & 63;
+  const int64_t col = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (col >= n) return;
   ls_dd acc{0.0, 0.0};
-  if (j < n)
-    for (int q = gg; q < G; q += 4) {
-      if (DD) acc = ls_dd_add(acc, ls_dd{tpart_hi[(int64_t)q * n + j], tpart_lo[(int64_t)q * n + j]});
-      else acc.hi += tpart_hi[(int64_t)q * n + j];
-    }
-  rh[gg][c] = acc.hi;
-  rl[gg][c] = acc.lo;
-  __syncthreads();
-  if (gg == 0 && j < n) {
-    ls_dd t{0.0, 0.0};
-    for (int q = 0; q < 4; ++q) {
-      if (DD) t = ls_dd_add(t, ls_dd{rh[q][c], rl[q][c]});
-      else t.hi += rh[q][c];
-    }
-    g[j] = -(t.hi + t.lo);
+  for (int q = lane; q < G; q += 64) {
+    if (DD) acc = ls_dd_add(acc, ls_dd{tpart_hi[col * G + q], tpart_lo[col * G + q]});
+    else acc.hi += tpart_hi[col * G + q];
   }
+  for (int off = 32; off > 0; off >>= 1) {
+    const ls_dd o{__shfl_xor(acc.hi, off, 64), __shfl_xor(acc.lo, off, 64)};
+    if (DD) acc = ls_dd_add(acc, o);
+    else acc.hi += o.hi;
+  }
+  if (lane == 0) g[col] = -(acc.hi + acc.lo);
 }
 
+// h = W^T g (line 6) into V[m:, 0]; partial ||h||^2.  One wave per column.
 template <bool DD>
-__global__ __launch_bounds__(kThreads) void k_lsir_h(const double* __restrict__ W, int64_t ldw, int64_t n, int64_t m,
+__global__ __launch_bounds__(kThreads) void k_lsir_h(const double* __restrict__ W, int64_t n, int64_t m,
                                                      const double* __restrict__ g, double* __restrict__ V,
                                                      double* __restrict__ hpart) {
   __shared__ double dsh[4];
@@ -456,13 +650,12 @@ __global__ __launch_bounds__(kThreads) void k_lsir_h(const double* __restrict__ 
   const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   double contrib = 0.0;
   if (j < n) {
-    const double* wc = W + j * ldw;
+    const double* wc = W + j * n;
     ls_dd acc{0.0, 0.0};
     for (int64_t i = lane; i <= j; i += 64) {
       if (DD) acc = ls_dd_fma(acc, wc[i], g[i]);
       else acc.hi += wc[i] * g[i];
     }
-    // wave sum of the (hi, lo) pairs
     for (int off = 32; off > 0; off >>= 1) {
       const ls_dd o{__shfl_xor(acc.hi, off, 64), __shfl_xor(acc.lo, off, 64)};
       if (DD) acc = ls_dd_add(acc, o);
@@ -478,35 +671,41 @@ __global__ __launch_bounds__(kThreads) void k_lsir_h(const double* __restrict__ 
   if (threadIdx.x == 0) hpart[blockIdx.x] = contrib;
 }
 
-// ------------------------------------------------------------------ FGMRES
+// ------------------------------------------------------------------ FGMRES on [I B; B^T 0]
 struct FgPtrs {
-  double* V;        // (m + n) x (kmax + 1), ld ldv
+  double* V;        // (m + n) x (kmax + 1), ld ldv; column j stored unnormalised until iteration j
   int64_t ldv;
-  double* Z;        // n x kmax  (M_R^-1 applied to the x part)
   double* H;        // (kmax + 1) x kmax, ld kmax + 1
   double* cs;
   double* sn;
   double* g;
-  double* hj;       // current subdiagonal norm
+  double* hj;       // norm used to normalise the current column
   FgState* st;
 };
 
-// Column j: h = ||w|| from partials (j = 0: beta = ||s||), Givens rotation for
-// column j-1 and the convergence test (block 0), normalisation of V_r[:, j]
-// (blocks < nrb) and z = W (V_x[:, j] / h) (remaining blocks; skipped in the
-// final call).  V_x[:, j] itself is normalised by the next kernel.
-template <typename TP>
-__global__ __launch_bounds__(kThreads) void k_fg_a(FgPtrs F, int64_t m, int64_t n, int j, int kmax,
-                                                   const TP* __restrict__ W, int64_t ldw,
-                                                   const double* __restrict__ w2part, int Gw, double tol,
-                                                   int final_step, int nrb) {
-  __shared__ double dsh[4];
-  __shared__ TP red[4][64];
+// Column j: h = ||w|| from partials (j = 0: beta = ||s||); block 0 applies
+// the Givens rotations to column j-1 and tests convergence.  Then, per row
+// block of B: v_r = V_r[:, j] / h (written back normalised), w_r = v_r + B v_x
+// -> V_r[:, j+1], partial t = B^T v_r, partial h1_r[c] = V_r[:, c] . w_r.
+template <typename TB, int RB>
+__global__ __launch_bounds__(kThreads) void k_fg_pass(const TB* __restrict__ B, int64_t ldb, int64_t m, int64_t n,
+                                                      int vec_ok, FgPtrs F, int j, int kmax,
+                                                      const double* __restrict__ w2part, int Gw, double tol,
+                                                      int final_step, TB* __restrict__ tpart,
+                                                      double* __restrict__ hpart) {
   if (F.st->done) return;
-  double s = 0.0;
-  for (int q = threadIdx.x; q < Gw; q += kThreads) s += w2part[q];
-  s = block_sum256(s, dsh);
-  const double h = sqrt(s);
+  extern __shared__ __align__(16) char smem[];
+  constexpr int LDR = RB + 1;
+  TB* Ms = reinterpret_cast<TB*>(smem);
+  TB* vs = Ms + n * LDR;
+  TB* tacc = vs + n;
+  TB* uu = tacc + n;
+  TB* red = uu + RB;
+  double* wv = align8(red + kThreads);
+  double* hacc = wv + RB;     // j + 1 entries
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const double h = sqrt(wave_sum_array(w2part, Gw, lane));
   const int64_t ldh = kmax + 1;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     FgState S = *F.st;
@@ -553,70 +752,61 @@ __global__ __launch_bounds__(kThreads) void k_fg_a(FgPtrs F, int64_t m, int64_t 
   if (h == 0.0 || !isfinite(h) || final_step || j >= kmax) return;
   const double inv = 1.0 / h;
   double* vj = F.V + (int64_t)j * F.ldv;
-  if ((int)blockIdx.x < nrb) {
-    for (int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x; i < m && i < ((int64_t)blockIdx.x + 1) * 1024;
-         i += kThreads)
-      vj[i] *= inv;
-    return;
-  }
-  const int bx = blockIdx.x - nrb;
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int64_t r = (int64_t)bx * 64 + lane;
-  TP acc = 0;
-  if (r < n) {
-    const int64_t r0 = (int64_t)bx * 64;
-    for (int64_t c = r0 + wv; c < n; c += 4) acc += W[r + c * ldw] * (TP)(vj[m + c] * inv);
-  }
-  red[wv][lane] = acc;
-  __syncthreads();
-  if (wv == 0 && r < n) F.Z[r + (int64_t)j * n] = (double)(red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane]);
-}
-
-// One pass over A for column j:  w_r = v_r + A z  -> V[:, j+1] (rows < m),
-// partial t = A^T v_r, partial h1_r[c] = V_r[:, c] . w_r (c <= j), stored
-// column-major hpart[c * G + block].  Block 0 also normalises V_x[:, j].
-template <typename TA, typename TP, int RB>
-__global__ __launch_bounds__(kThreads) void k_fg_pass(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n,
-                                                      int vec_ok, FgPtrs F, int j, TP* __restrict__ tpart,
-                                                      double* __restrict__ hpart) {
-  if (F.st->done) return;
-  extern __shared__ __align__(16) char smem[];
-  constexpr int LDR = RB + 1;
-  TP* As = reinterpret_cast<TP*>(smem);
-  TP* zs = As + n * LDR;
-  TP* tacc = zs + n;
-  TP* uu = tacc + n;
-  TP* red = uu + RB;
-  double* wv = align8(red + kThreads);
-  double* hacc = wv + RB;     // j + 1 entries
-  const double* vj = F.V + (int64_t)j * F.ldv;
   double* w = F.V + (int64_t)(j + 1) * F.ldv;
-  if (blockIdx.x == 0) {
-    const double inv = 1.0 / *F.hj;
-    double* vx = F.V + (int64_t)j * F.ldv + m;
-    for (int64_t c = threadIdx.x; c < n; c += kThreads) vx[c] *= inv;
-  }
   for (int c = threadIdx.x; c < n; c += kThreads) {
-    zs[c] = (TP)F.Z[c + (int64_t)j * n];
+    vs[c] = (TB)(vj[m + c] * inv);
     tacc[c] = 0;
   }
   for (int c = threadIdx.x; c <= j; c += kThreads) hacc[c] = 0.0;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
   const int64_t nrb = ls_cdiv(m, RB);
-  for (int64_t rb = blockIdx.x; rb < nrb; rb += gridDim.x) {
-    const int64_t i0 = rb * RB;
-    __syncthreads();
-    load_rows<TA, TP, RB>(A, lda, m, n, i0, vec_ok != 0, As);
-    __syncthreads();
-    const TP q = rows_times_vec<TP, RB>(As, zs, n, red);
+  int64_t b0, b1;
+  row_range(nrb, gridDim.x, blockIdx.x, b0, b1);
+  // The block's tile V_r[i0:i0+RB, 0:j+1] for the fused dots: element
+  // idx = t + 256 q is row idx % RB, Krylov column idx / RB; groups of RB
+  // consecutive threads share a column.  Column j is read unnormalised and scaled.
+  const int ntile = RB * (j + 1);
+  double vt[kMaxTile];
+  auto load_tile = [&](int64_t i0) {
+#pragma unroll
+    for (int q = 0; q < kMaxTile; ++q) {
+      const int idx = threadIdx.x + q * kThreads;
+      const int64_t i = i0 + (idx % RB);
+      const int c = idx / RB;
+      vt[q] = (idx < ntile && i < m) ? F.V[i + (int64_t)c * F.ldv] : 0.0;
+    }
+  };
+  double pre_v = 0.0;   // V_r[i, j] of this thread's row in the next block (threads < RB)
+  auto load_v = [&](int64_t i0) {
     if (threadIdx.x < RB) {
       const int64_t i = i0 + threadIdx.x;
-      TP vr = 0;
+      pre_v = (i < m) ? vj[i] : 0.0;
+    }
+  };
+  RowBlock<TB, RB> blk;
+  if (b0 < b1) {
+    blk.load(B, ldb, m, n, b0 * RB, vec_ok != 0);
+    load_v(b0 * RB);
+    load_tile(b0 * RB);
+  }
+  for (int64_t rb = b0; rb < b1; ++rb) {
+    const int64_t i0 = rb * RB;
+    __syncthreads();
+    blk.store(B, ldb, m, n, i0, Ms);
+    const double vold = pre_v;
+    __syncthreads();
+    if (rb + 1 < b1) {
+      blk.load(B, ldb, m, n, i0 + RB, vec_ok != 0);
+      load_v(i0 + RB);
+    }
+    const TB q = rows_times_vec<TB, RB>(Ms, vs, n, red);
+    if (threadIdx.x < RB) {
+      const int64_t i = i0 + threadIdx.x;
+      TB vr = 0;
       double wr = 0.0;
       if (i < m) {
-        vr = (TP)vj[i];
+        const double vn = vold * inv;
+        vj[i] = vn;
+        vr = (TB)vn;
         wr = (double)(vr + q);
         w[i] = wr;
       }
@@ -624,161 +814,192 @@ __global__ __launch_bounds__(kThreads) void k_fg_pass(const TA* __restrict__ A, 
       wv[threadIdx.x] = wr;
     }
     __syncthreads();
-    for (int c = threadIdx.x; c < n; c += kThreads) {
-      TP acc = 0;
-#pragma unroll 8
-      for (int rw = 0; rw < RB; ++rw) acc += As[c * LDR + rw] * uu[rw];
-      tacc[c] += acc;
+    // h1 (r part) from the prefetched tile, then start loading the next tile
+#pragma unroll
+    for (int q = 0; q < kMaxTile; ++q) {
+      const int idx = threadIdx.x + q * kThreads;
+      const int c = idx / RB;
+      double prod = (idx < ntile) ? vt[q] * wv[idx % RB] * ((c == j) ? inv : 1.0) : 0.0;
+#pragma unroll
+      for (int off = RB / 2; off > 0; off >>= 1) prod += __shfl_xor(prod, off, 64);
+      if (idx < ntile && (idx % RB) == 0) hacc[c] += prod;
     }
-    // h1 (r part): wave per Krylov column, lanes over the block's rows
-    for (int c = wave; c <= j; c += 4) {
-      double prod = 0.0;
-      if (lane < RB && i0 + lane < m) prod = F.V[i0 + lane + (int64_t)c * F.ldv] * wv[lane];
-      prod = ls_wave_sum(prod);
-      if (lane == 0) hacc[c] += prod;
+    if (rb + 1 < b1) load_tile(i0 + RB);
+    for (int c = threadIdx.x; c < n; c += kThreads) {
+      TB acc = 0;
+#pragma unroll 8
+      for (int rw = 0; rw < RB; ++rw) acc += Ms[c * LDR + rw] * uu[rw];
+      tacc[c] += acc;
     }
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < n; c += kThreads) tpart[(int64_t)blockIdx.x * n + c] = tacc[c];
+  for (int c = threadIdx.x; c < n; c += kThreads) tpart[(int64_t)c * gridDim.x + blockIdx.x] = tacc[c];
   for (int c = threadIdx.x; c <= j; c += kThreads) hpart[(int64_t)c * gridDim.x + blockIdx.x] = hacc[c];
 }
 
-// t[c] = sum_g tpart[g][c] (blocks < ncb, 64 columns each) and
-// h1r[c] = sum_g hpart[c][g] (remaining blocks, one Krylov column each).
-template <typename TP>
-__global__ __launch_bounds__(kThreads) void k_fg_reduce(const TP* __restrict__ tpart, const double* __restrict__ hpart,
-                                                        int G, int64_t n, int j, int ncb, double* __restrict__ t,
-                                                        double* __restrict__ h1r, const FgState* st) {
-  if (st->done) return;
-  __shared__ TP red[4][64];
-  __shared__ double dsh[4];
-  if ((int)blockIdx.x < ncb) {
-    const int c = threadIdx.x & 63;
-    const int gg = threadIdx.x >> 6;
-    const int64_t col = (int64_t)blockIdx.x * 64 + c;
-    TP acc = 0;
-    if (col < n)
-      for (int q = gg; q < G; q += 4) acc += tpart[(int64_t)q * n + col];
-    red[gg][c] = acc;
-    __syncthreads();
-    if (gg == 0 && col < n) t[col] = (double)(red[0][c] + red[1][c] + red[2][c] + red[3][c]);
-    return;
-  }
-  const int c = blockIdx.x - ncb;
-  if (c > j) return;
-  double s = 0.0;
-  for (int q = threadIdx.x; q < G; q += kThreads) s += hpart[(int64_t)c * G + q];
-  s = block_sum256(s, dsh);
-  if (threadIdx.x == 0) h1r[c] = s;
-}
-
-// w_x = W^T t (M_L^-1 on the x part) -> V[m:, j+1]; partial h1_x[c] over the
-// block's 16 columns, stored column-major hxpart[c * G + block].
-template <typename TP>
-__global__ __launch_bounds__(1024) void k_fg_c(const TP* __restrict__ W, int64_t ldw, int64_t n, int64_t m,
-                                               const double* __restrict__ t, FgPtrs F, int j,
-                                               double* __restrict__ hxpart) {
+// Blocks < ncb (16 columns each, one wave per column): w_x = B^T v_r from the
+// column partials -> V[m:, j+1], normalise V[m:, j], partial h1_x[c] over the
+// block's columns.  Remaining blocks: h1_r[c] = sum of the pass partials.
+template <typename TB>
+__global__ __launch_bounds__(1024) void k_fg_col(int64_t m, int64_t n, const TB* __restrict__ tpart, int G,
+                                                 const double* __restrict__ hpart, FgPtrs F, int j, int ncb,
+                                                 double* __restrict__ hxpart, double* __restrict__ h1r) {
   if (F.st->done) return;
   __shared__ double wx[16];
+  __shared__ double vjx[16];
   const int lane = threadIdx.x & 63;
   const int wvi = threadIdx.x >> 6;
+  if ((int)blockIdx.x >= ncb) {
+    const int c = blockIdx.x - ncb;
+    if (c > j || wvi != 0) return;
+    const double s = wave_sum_array(hpart + (int64_t)c * G, G, lane);
+    if (lane == 0) h1r[c] = s;
+    return;
+  }
   const int64_t col = (int64_t)blockIdx.x * 16 + wvi;
+  const double inv = 1.0 / *F.hj;
   double* w = F.V + (int64_t)(j + 1) * F.ldv;
-  double val = 0.0;
+  double* vj = F.V + (int64_t)j * F.ldv;
+  double val = 0.0, vn = 0.0;
   if (col < n) {
-    const TP* wc = W + col * ldw;
-    TP acc = 0;
-    for (int64_t i = lane; i <= col; i += 64) acc += wc[i] * (TP)t[i];
+    const TB* tp = tpart + col * G;
+    TB acc = 0;
+    for (int g = lane; g < G; g += 64) acc += tp[g];
     acc = ls_wave_sum(acc);
     val = (double)acc;
-    if (lane == 0) w[m + col] = val;
+    vn = vj[m + col] * inv;
   }
-  if (lane == 0) wx[wvi] = val;
+  __syncthreads();   // every wave has read V[m:, j] before it is overwritten
+  if (col < n && lane == 0) {
+    w[m + col] = val;
+    vj[m + col] = vn;
+  }
+  if (lane == 0) {
+    wx[wvi] = val;
+    vjx[wvi] = vn;
+  }
   __syncthreads();
   for (int c = threadIdx.x; c <= j; c += 1024) {
     double s = 0.0;
     for (int q = 0; q < 16; ++q) {
       const int64_t cc = (int64_t)blockIdx.x * 16 + q;
-      if (cc < n) s += F.V[m + cc + (int64_t)c * F.ldv] * wx[q];
+      if (cc < n) s += ((c == j) ? vjx[q] : F.V[m + cc + (int64_t)c * F.ldv]) * wx[q];
     }
     hxpart[(int64_t)c * gridDim.x + blockIdx.x] = s;
   }
 }
 
-// Classical Gram-Schmidt sweep over rows [1024 b, 1024 (b+1)) of w = V[:, j+1]:
-//   hsum[c] = h_in[c] (+ sum of x-part partials in the first sweep);
-//   w <- w - V[:, 0:j+1] hsum;  partial dots V[:, c] . w (second=0) or partial ||w||^2 (second=1).
-// Block 0 records hsum in column j of H (first sweep) or adds it (second sweep).
-__global__ __launch_bounds__(kThreads) void k_cgs(FgPtrs F, int64_t m, int64_t n, int j, int kmax,
-                                                  const double* __restrict__ h_in, const double* __restrict__ hx,
-                                                  int Gx, const double* __restrict__ h2part, int G2, int second,
-                                                  double* __restrict__ out_part, double* __restrict__ w2part) {
+// sum_{c <= j} V[i + c ldv] h[c] with eight independent loads in flight.
+__device__ __forceinline__ double vrow_dot(const double* __restrict__ V, int64_t ldv, int64_t i, int j,
+                                           const double* __restrict__ h) {
+  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int c = 0;
+  for (; c + 8 <= j + 1; c += 8) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = V[i + (int64_t)(c + q) * ldv];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] += v[q] * h[c + q];
+  }
+  for (; c <= j; ++c) a[0] += V[i + (int64_t)c * ldv] * h[c];
+  return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
+// First Gram-Schmidt sweep over rows [256 b, 256 b + 256) of w = V[:, j+1]:
+// h1[c] = h1r[c] + sum of x-part partials; w <- w - V[:, 0:j+1] h1; partial
+// h2[c] = V[:, c] . w.  Block 0 records h1 in column j of H.
+__global__ __launch_bounds__(kThreads) void k_cgs1(FgPtrs F, int64_t m, int64_t n, int j, int kmax,
+                                                   const double* __restrict__ h1r, const double* __restrict__ hx,
+                                                   int Gx, double* __restrict__ h2part) {
   if (F.st->done) return;
   __shared__ double hs[96];
-  __shared__ double wsh[1024];
-  __shared__ double dsh[4];
-  const int64_t rows = m + n;
-  for (int c = threadIdx.x; c <= j; c += kThreads) {
-    double s = 0.0;
-    if (!second) {
-      s = h_in[c];
-      for (int q = 0; q < Gx; ++q) s += hx[(int64_t)c * Gx + q];
-    } else {
-      for (int q = 0; q < G2; ++q) s += h2part[(int64_t)c * G2 + q];
-    }
-    hs[c] = s;
-  }
-  __syncthreads();
-  if (blockIdx.x == 0 && threadIdx.x <= j) {
-    double* Hc = F.H + (int64_t)j * (kmax + 1);
-    if (!second) Hc[threadIdx.x] = hs[threadIdx.x];
-    else Hc[threadIdx.x] += hs[threadIdx.x];
-  }
-  double* w = F.V + (int64_t)(j + 1) * F.ldv;
-  const int64_t base = (int64_t)blockIdx.x * 1024;
-  double nrm = 0.0;
-  for (int q = 0; q < 4; ++q) {
-    const int li = q * kThreads + threadIdx.x;
-    const int64_t i = base + li;
-    double wi = 0.0;
-    if (i < rows) {
-      wi = w[i];
-      for (int c = 0; c <= j; ++c) wi -= F.V[i + (int64_t)c * F.ldv] * hs[c];
-      w[i] = wi;
-      nrm += wi * wi;
-    }
-    wsh[li] = wi;
-  }
-  __syncthreads();
-  if (second) {
-    nrm = block_sum256(nrm, dsh);
-    if (threadIdx.x == 0) w2part[blockIdx.x] = nrm;
-    return;
-  }
+  __shared__ double wsh[kThreads];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   for (int c = wave; c <= j; c += 4) {
-    double prod = 0.0;
-    const double* vc = F.V + (int64_t)c * F.ldv;
-    for (int q = 0; q < 16; ++q) {
-      const int li = q * 64 + lane;
-      const int64_t i = base + li;
-      if (i < rows) prod += vc[i] * wsh[li];
+    const double s = wave_sum_array(hx + (int64_t)c * Gx, Gx, lane);
+    if (lane == 0) hs[c] = h1r[c] + s;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x <= j) F.H[(int64_t)j * (kmax + 1) + threadIdx.x] = hs[threadIdx.x];
+  const int64_t rows = m + n;
+  double* w = F.V + (int64_t)(j + 1) * F.ldv;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  double wi = 0.0;
+  if (i < rows) {
+    wi = w[i] - vrow_dot(F.V, F.ldv, i, j, hs);
+    w[i] = wi;
+  }
+  wsh[threadIdx.x] = wi;
+  __syncthreads();
+  // partial dots: wave per Krylov column, four columns' loads issued together
+  const int64_t base = (int64_t)blockIdx.x * kThreads;
+  for (int c0 = wave; c0 <= j; c0 += 16) {
+    double prod[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) {
+      const int c = c0 + 4 * cc;
+      if (c <= j) {
+        const double* vc = F.V + (int64_t)c * F.ldv + base;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int li = q * 64 + lane;
+          if (base + li < rows) prod[cc] += vc[li] * wsh[li];
+        }
+      }
     }
-    prod = ls_wave_sum(prod);
-    if (lane == 0) out_part[(int64_t)c * gridDim.x + blockIdx.x] = prod;
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) {
+      const int c = c0 + 4 * cc;
+      const double t = ls_wave_sum(prod[cc]);
+      if (c <= j && lane == 0) h2part[(int64_t)c * gridDim.x + blockIdx.x] = t;
+    }
   }
 }
 
-// Correction of one refinement step: y = H(0:k,0:k)^-1 g(0:k) (every block),
-// dr = V_r y, dx = Z y; r += dr and x += dx rounded to the working precision
-// TU; partial sums of ||dr||^2, ||dx||^2, ||r||^2, ||x||^2 -> part[4 * block + q].
+// h2[c] = sum of the sweep partials (one wave per c); H(c, j) += h2[c].
+__global__ __launch_bounds__(64) void k_cgs_reduce(FgPtrs F, int j, int kmax, const double* __restrict__ h2part, int G2,
+                                                   double* __restrict__ h2) {
+  if (F.st->done) return;
+  const int c = blockIdx.x;
+  if (c > j) return;
+  const double s = wave_sum_array(h2part + (int64_t)c * G2, G2, threadIdx.x);
+  if (threadIdx.x == 0) {
+    h2[c] = s;
+    F.H[(int64_t)j * (kmax + 1) + c] += s;
+  }
+}
+
+// Second sweep: w <- w - V[:, 0:j+1] h2; partial ||w||^2.
+__global__ __launch_bounds__(kThreads) void k_cgs2(FgPtrs F, int64_t m, int64_t n, int j,
+                                                   const double* __restrict__ h2, double* __restrict__ w2part) {
+  if (F.st->done) return;
+  __shared__ double hs[96];
+  __shared__ double dsh[4];
+  for (int c = threadIdx.x; c <= j; c += kThreads) hs[c] = h2[c];
+  __syncthreads();
+  const int64_t rows = m + n;
+  double* w = F.V + (int64_t)(j + 1) * F.ldv;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  double nrm = 0.0;
+  if (i < rows) {
+    const double wi = w[i] - vrow_dot(F.V, F.ldv, i, j, hs);
+    w[i] = wi;
+    nrm = wi * wi;
+  }
+  nrm = block_sum256(nrm, dsh);
+  if (threadIdx.x == 0) w2part[blockIdx.x] = nrm;
+}
+
+// Correction of one refinement step: y = H(0:k,0:k)^-1 g(0:k) (every block);
+// rows < m: dr = V_r y, r += dr (working precision TU), partial norms;
+// rows >= m: dz = V_x y -> dz buffer.
 template <typename TU>
 __global__ __launch_bounds__(kThreads) void k_fg_update(FgPtrs F, int64_t m, int64_t n, int kmax,
-                                                        double* __restrict__ r, double* __restrict__ x,
+                                                        double* __restrict__ r, double* __restrict__ dz,
                                                         double* __restrict__ part) {
   __shared__ double y[128];
-  __shared__ double dsh[16];
+  __shared__ double dsh[8];
   const int k = F.st->k;
   const int64_t ldh = kmax + 1;
   for (int i = threadIdx.x; i < k; i += kThreads) y[i] = F.g[i];
@@ -790,30 +1011,56 @@ __global__ __launch_bounds__(kThreads) void k_fg_update(FgPtrs F, int64_t m, int
     for (int t = threadIdx.x; t < i; t += kThreads) y[t] -= F.H[t + (int64_t)i * ldh] * yi;
   }
   __syncthreads();
-  const int64_t rows = m + n;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int q = 0; q < 4; ++q) {
-    const int64_t i = (int64_t)blockIdx.x * 1024 + q * kThreads + threadIdx.x;
-    if (i >= rows) continue;
-    double d = 0.0;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  double a0 = 0.0, a1 = 0.0;
+  if (i < m + n) {
+    const double d = (k > 0) ? vrow_dot(F.V, F.ldv, i, k - 1, y) : 0.0;
     if (i < m) {
-      for (int c = 0; c < k; ++c) d += F.V[i + (int64_t)c * F.ldv] * y[c];
       const double rn = (double)((TU)r[i] + (TU)d);
       r[i] = rn;
-      acc[0] += d * d;
-      acc[2] += rn * rn;
+      a0 = d * d;
+      a1 = rn * rn;
     } else {
-      const int64_t ix = i - m;
-      for (int c = 0; c < k; ++c) d += F.Z[ix + (int64_t)c * n] * y[c];
-      const double xn = (double)((TU)x[ix] + (TU)d);
-      x[ix] = xn;
-      acc[1] += d * d;
-      acc[3] += xn * xn;
+      dz[i - m] = d;
     }
   }
-  for (int q = 0; q < 4; ++q) {
-    const double s = block_sum256(acc[q], dsh + 4 * q);
-    if (threadIdx.x == 0) part[4 * (int64_t)blockIdx.x + q] = s;
+  a0 = block_sum256(a0, dsh);
+  a1 = block_sum256(a1, dsh + 4);
+  if (threadIdx.x == 0) {
+    part[2 * (int64_t)blockIdx.x] = a0;
+    part[2 * (int64_t)blockIdx.x + 1] = a1;
+  }
+}
+
+// dx = W dz (R^-1 on the x part of the correction), x += dx (TU); partial norms.
+template <typename TU>
+__global__ __launch_bounds__(kThreads) void k_fg_dx(const double* __restrict__ W, int64_t n,
+                                                    const double* __restrict__ dz, double* __restrict__ x,
+                                                    double* __restrict__ part) {
+  __shared__ double red[16][17];
+  __shared__ double dsh[8];
+  const int r = threadIdx.x & 15, cg = threadIdx.x >> 4;
+  const int64_t row = (int64_t)blockIdx.x * 16 + r;
+  double acc = 0.0;
+  if (row < n)
+    for (int64_t j = row + cg; j < n; j += 16) acc += W[row + j * n] * dz[j];
+  red[cg][r] = acc;
+  __syncthreads();
+  double a0 = 0.0, a1 = 0.0;
+  if (cg == 0 && row < n) {
+    double d = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) d += red[q][r];
+    const double xn = (double)((TU)x[row] + (TU)d);
+    x[row] = xn;
+    a0 = d * d;
+    a1 = xn * xn;
+  }
+  a0 = block_sum256(a0, dsh);
+  a1 = block_sum256(a1, dsh + 4);
+  if (threadIdx.x == 0) {
+    part[2 * (int64_t)blockIdx.x] = a0;
+    part[2 * (int64_t)blockIdx.x + 1] = a1;
   }
 }
 
@@ -830,20 +1077,36 @@ size_t device_lds_limit() {
   return cached;
 }
 
-int pick_rb(int64_t n, size_t elt) {
-  // LDS budget ~ 72 KB per block so that two blocks share a compute unit,
-  // capped by what the device grants one block.
-  size_t budget = 72 * 1024;
-  const size_t lim = device_lds_limit();
-  if (lim < budget + 1024) budget = lim - 1024;
-  if ((size_t)n * 33 * elt + 4 * (size_t)n * elt + 8192 <= budget) return 32;
-  if ((size_t)n * 17 * elt + 4 * (size_t)n * elt + 8192 <= budget) return 16;
-  return 8;
+// Rows per block for a pass over an n-column matrix of element size elt:
+// the block must fit the LDS budget and the register prefetch buffer.
+int pick_rb(int64_t n, size_t elt, size_t extra_lds) {
+  const size_t budget = device_lds_limit() - 1024;
+  const int cands[3] = {32, 16, 8};
+  for (int rb : cands) {
+    const size_t lds = (size_t)n * (rb + 1) * elt + 2 * (size_t)n * elt + extra_lds + 4096;
+    const size_t regs_needed = (size_t)rb * n * elt;                // bytes per block
+    const size_t regs_avail = (size_t)kMaxVecLoads * 16 * kThreads;
+    if (lds <= budget && regs_needed <= regs_avail) return rb;
+  }
+  return 0;
 }
 
-bool vec_aligned(const void* A, int64_t lda, size_t elt) {
+bool vec_aligned(const void* M, int64_t ld, size_t elt) {
   const size_t v = 16 / elt;
-  return ((uintptr_t)A % 16 == 0) && (lda % (int64_t)v == 0);
+  return ((uintptr_t)M % 16 == 0) && (ld % (int64_t)v == 0);
+}
+
+template <typename T>
+size_t pass_lds(int64_t n, int rb, int extra_doubles) {
+  return ((size_t)n * (rb + 1) + 2 * (size_t)n + rb + kThreads) * sizeof(T) + 8 * ((size_t)extra_doubles + 8) + 16;
+}
+
+int pass_grid(int64_t m, int rb, int ncu) {
+  const int64_t nrb = ls_cdiv(m, rb);
+  int64_t G = 2 * (int64_t)ncu;
+  if (G > nrb) G = nrb;
+  if (G < 1) G = 1;
+  return (int)G;
 }
 
 }  // namespace
@@ -860,19 +1123,45 @@ int device_cu_count() {
   return cached;
 }
 
+// B = A W (W binary64 n x n, ld n; W32 its binary32 copy), binary32 or binary64.
+int form_b(const ls_problem_t* P, const double* W, const float* W32, ls_prec_t tb, void* Bout, hipStream_t st) {
+  const dim3 g((unsigned)ls_cdiv(P->m, 64), (unsigned)ls_cdiv(P->n, 64));
+  if (tb == LS_FP32) {
+    if (P->store == LS_FP32)
+      hipLaunchKernelGGL((k_form_b<float, float>), g, dim3(kThreads), 0, st, (const float*)P->A, P->lda, P->m, P->n,
+                         W32, (float*)Bout, P->m);
+    else
+      hipLaunchKernelGGL((k_form_b<double, float>), g, dim3(kThreads), 0, st, (const double*)P->A, P->lda, P->m, P->n,
+                         W32, (float*)Bout, P->m);
+  } else {
+    if (P->store == LS_FP32)
+      hipLaunchKernelGGL((k_form_b<float, double>), g, dim3(kThreads), 0, st, (const float*)P->A, P->lda, P->m, P->n,
+                         W, (double*)Bout, P->m);
+    else
+      hipLaunchKernelGGL((k_form_b<double, double>), g, dim3(kThreads), 0, st, (const double*)P->A, P->lda, P->m,
+                         P->n, W, (double*)Bout, P->m);
+  }
+  LS_HIP_TRY(hipGetLastError());
+  return LS_OK;
+}
+
+size_t b_bytes(const ls_problem_t* P, ls_prec_t tb) {
+  return ls_align256((size_t)P->m * P->n * (tb == LS_FP32 ? 4 : 8));
+}
+
 // ================================================================== LSQR driver
 namespace {
 struct LsqrWs {
   LsqrState* st;
-  char* p;
-  char* u;
-  char* t;
   char* v;
-  char* what;
+  char* u;
+  char* w;
+  double* y;
+  double* z0;
   char* tpart;
   double* nupart;
   double* nbpart;
-  double* nvpart;
+  double* nvpart[2];
   size_t bytes;
 };
 
@@ -885,112 +1174,106 @@ LsqrWs lsqr_carve(char* ws, const ls_problem_t* P, size_t elt, int G, int Gv) {
     return q;
   };
   w.st = reinterpret_cast<LsqrState*>(take(sizeof(LsqrState)));
-  w.p = take(elt * P->n);
-  w.u = take(elt * P->m);
-  w.t = take(elt * P->n);
   w.v = take(elt * P->n);
-  w.what = take(elt * P->n);
+  w.u = take(elt * P->m);
+  w.w = take(elt * P->n);
+  w.y = reinterpret_cast<double*>(take(8 * (size_t)P->n));
+  w.z0 = reinterpret_cast<double*>(take(8 * (size_t)P->n));
   w.tpart = take(elt * P->n * (size_t)G);
   w.nupart = reinterpret_cast<double*>(take(8 * (size_t)G));
   w.nbpart = reinterpret_cast<double*>(take(8 * (size_t)G));
-  w.nvpart = reinterpret_cast<double*>(take(8 * (size_t)Gv));
+  w.nvpart[0] = reinterpret_cast<double*>(take(8 * (size_t)Gv));
+  w.nvpart[1] = reinterpret_cast<double*>(take(8 * (size_t)Gv));
   w.bytes = off;
   return w;
 }
 
-int lsqr_grid(const ls_problem_t* P, int rb, int ncu) {
-  const int64_t nrb = ls_cdiv(P->m, rb);
-  int64_t G = 2 * (int64_t)ncu;
-  if (G > nrb) G = nrb;
-  if (G < 1) G = 1;
-  return (int)G;
-}
-
-template <typename TA, typename T>
-int lsqr_typed(const ls_problem_t* P, const T* Wt, int64_t ldw, double* x, const ls_iter_opts_t* io,
-               ls_stats_t* stats, char* ws, size_t ws_bytes, hipStream_t st) {
+template <typename T>
+int lsqr_typed(const ls_problem_t* P, const double* R, int64_t ldr, const double* W, const T* Bm, double* x,
+               const ls_iter_opts_t* io, ls_stats_t* stats, char* ws, size_t ws_bytes, hipStream_t st) {
   const int64_t m = P->m, n = P->n;
-  const int rb = pick_rb(n, sizeof(T));
+  const int rb = pick_rb(n, sizeof(T), 0);
+  if (rb == 0) return LS_E_UNSUPPORTED;
   const int ncu = device_cu_count();
-  const int G = lsqr_grid(P, rb, ncu);
+  const int G = pass_grid(m, rb, ncu);
   const int Gv = (int)ls_cdiv(n, 4);
   LsqrWs w = lsqr_carve(ws, P, sizeof(T), G, Gv);
   if (w.bytes > ws_bytes) return LS_E_WORKSPACE;
-  const TA* A = static_cast<const TA*>(P->A);
-  const TA* b = static_cast<const TA*>(P->b);
-  T* p = reinterpret_cast<T*>(w.p);
-  T* u = reinterpret_cast<T*>(w.u);
-  T* t = reinterpret_cast<T*>(w.t);
   T* v = reinterpret_cast<T*>(w.v);
-  T* what = reinterpret_cast<T*>(w.what);
+  T* u = reinterpret_cast<T*>(w.u);
+  T* wv = reinterpret_cast<T*>(w.w);
   T* tpart = reinterpret_cast<T*>(w.tpart);
-  const int vec_ok = vec_aligned(A, P->lda, sizeof(TA)) ? 1 : 0;
-  const size_t lds = ((size_t)n * (rb + 1) + 2 * (size_t)n + rb + kThreads) * sizeof(T) + 8 * sizeof(double) + 16;
+  const int vec_ok = vec_aligned(Bm, m, sizeof(T)) ? 1 : 0;
+  const size_t lds = pass_lds<T>(n, rb, 0);
   if (lds > device_lds_limit()) return LS_E_UNSUPPORTED;
   const int maxit = io->lsqr_maxit;
   const double tol = io->lsqr_tol;
   const int check = io->check_every > 0 ? io->check_every : 8;
+  const dim3 gcol((unsigned)Gv);
+  const dim3 gn((unsigned)ls_cdiv(n, 16));
 
-  hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(kThreads), 0, st, reinterpret_cast<char*>(w.st), sizeof(LsqrState));
-  hipLaunchKernelGGL(k_cast_vec<T>, dim3((unsigned)ls_cdiv(n, kThreads)), dim3(kThreads), 0, st, x, p, n);
-  auto pass = [&](int par, int init) {
+  hipLaunchKernelGGL(k_zero_bytes, dim3(4), dim3(kThreads), 0, st, reinterpret_cast<char*>(w.st), sizeof(LsqrState));
+  hipLaunchKernelGGL(k_zero_bytes, dim3(4), dim3(kThreads), 0, st, reinterpret_cast<char*>(w.y), 8 * (size_t)n);
+  hipLaunchKernelGGL(k_zero_bytes, dim3(4), dim3(kThreads), 0, st, w.w, sizeof(T) * (size_t)n);
+  // z0 = R x0 (so that A x0 = B z0), v <- -z0, u <- b
+  hipLaunchKernelGGL((k_trmv<double, double>), gn, dim3(kThreads), 0, st, R, ldr, n, x, (const double*)nullptr, w.z0);
+  hipLaunchKernelGGL((k_cast<T, double>), dim3((unsigned)ls_cdiv(n, kThreads)), dim3(kThreads), 0, st, w.z0, v, n,
+                     T(-1));
+  if (P->store == LS_FP32)
+    hipLaunchKernelGGL((k_cast<T, float>), dim3((unsigned)ls_cdiv(m, kThreads)), dim3(kThreads), 0, st,
+                       (const float*)P->b, u, m, T(1));
+  else
+    hipLaunchKernelGGL((k_cast<T, double>), dim3((unsigned)ls_cdiv(m, kThreads)), dim3(kThreads), 0, st,
+                       (const double*)P->b, u, m, T(1));
+  auto pass = [&](int par, int init, const double* nvp) {
     prof_begin(kProfLsqrPass, st);
     switch (rb) {
       case 32:
-        hipLaunchKernelGGL((k_lsqr_pass<TA, T, 32>), dim3(G), dim3(kThreads), lds, st, A, P->lda, m, n, vec_ok, p, u,
-                           b, w.st, par, init, tpart, w.nupart, w.nbpart);
+        hipLaunchKernelGGL((k_lsqr_pass<T, 32>), dim3(G), dim3(kThreads), lds, st, Bm, m, m, n, vec_ok, v, nvp, Gv, u,
+                           w.st, par, init, tpart, w.nupart, w.nbpart);
         break;
       case 16:
-        hipLaunchKernelGGL((k_lsqr_pass<TA, T, 16>), dim3(G), dim3(kThreads), lds, st, A, P->lda, m, n, vec_ok, p, u,
-                           b, w.st, par, init, tpart, w.nupart, w.nbpart);
+        hipLaunchKernelGGL((k_lsqr_pass<T, 16>), dim3(G), dim3(kThreads), lds, st, Bm, m, m, n, vec_ok, v, nvp, Gv, u,
+                           w.st, par, init, tpart, w.nupart, w.nbpart);
         break;
       default:
-        hipLaunchKernelGGL((k_lsqr_pass<TA, T, 8>), dim3(G), dim3(kThreads), lds, st, A, P->lda, m, n, vec_ok, p, u,
-                           b, w.st, par, init, tpart, w.nupart, w.nbpart);
+        hipLaunchKernelGGL((k_lsqr_pass<T, 8>), dim3(G), dim3(kThreads), lds, st, Bm, m, m, n, vec_ok, v, nvp, Gv, u,
+                           w.st, par, init, tpart, w.nupart, w.nbpart);
         break;
     }
-    // A once, u read and written, p read, t written
-    prof_end(kProfLsqrPass, st, (double)m * n * sizeof(TA) + 2.0 * m * sizeof(T) + 2.0 * n * sizeof(T));
+    // B once, u read and written, v read, t written
+    prof_end(kProfLsqrPass, st, (double)m * n * sizeof(T) + 2.0 * m * sizeof(T) + 2.0 * n * sizeof(T));
   };
-  const dim3 gred((unsigned)ls_cdiv(n, 64));
-  const dim3 gv((unsigned)Gv);
-  const dim3 gstep((unsigned)ls_cdiv(n, 64));
-  // init: u = b - A x0, beta_1, t = A^T u / beta_1, v = W^T t
-  pass(1, 1);
-  hipLaunchKernelGGL(k_lsqr_reduce<T>, gred, dim3(kThreads), 0, st, tpart, G, n, w.nupart, w.nbpart, w.st, 1, 1, t);
-  hipLaunchKernelGGL(k_lsqr_vupdate<T>, gv, dim3(kThreads), 0, st, Wt, ldw, n, t, v, w.st, 1, 1, w.nvpart);
-  int it = 1;
-  int last_par_written = 0;
+  // init: u_1 = b - B z0, beta_1, v_1 = B^T u_1 / beta_1; C_1 -> rec[1]
+  pass(1, 1, w.nvpart[0]);
+  hipLaunchKernelGGL(k_lsqr_col<T>, gcol, dim3(kThreads), 0, st, n, tpart, G, w.nupart, w.nbpart, w.nvpart[1], Gv,
+                     w.nvpart[0], w.st, 0, 1, 0, tol, v, wv, w.y);
+  int it = 1, cur = 0;   // nvpart[cur] holds ||v_it||^2 partials
   LsqrRec rec{};
-  bool done = false;
   for (; it <= maxit; ++it) {
-    const int rd = it & 1, wr = rd ^ 1;
-    hipLaunchKernelGGL(k_lsqr_step<T>, gstep, dim3(kThreads), 0, st, Wt, ldw, n, v, w.nvpart, Gv, w.st, rd, it, 0,
-                       tol, maxit, p, what, x);
-    last_par_written = wr;
-    pass(wr, 0);
-    hipLaunchKernelGGL(k_lsqr_reduce<T>, gred, dim3(kThreads), 0, st, tpart, G, n, w.nupart, w.nbpart, w.st, wr, 0, t);
-    hipLaunchKernelGGL(k_lsqr_vupdate<T>, gv, dim3(kThreads), 0, st, Wt, ldw, n, t, v, w.st, wr, 0, w.nvpart);
+    const int par = it & 1;
+    pass(par, 0, w.nvpart[cur]);
+    hipLaunchKernelGGL(k_lsqr_col<T>, gcol, dim3(kThreads), 0, st, n, tpart, G, w.nupart, w.nbpart, w.nvpart[cur], Gv,
+                       w.nvpart[cur ^ 1], w.st, par, 0, it, tol, v, wv, w.y);
+    cur ^= 1;
     if (it % check == 0) {
-      LS_HIP_TRY(hipMemcpyAsync(&rec, &w.st->rec[wr], sizeof(LsqrRec), hipMemcpyDeviceToHost, st));
+      LS_HIP_TRY(hipMemcpyAsync(&rec, &w.st->rec[par ^ 1], sizeof(LsqrRec), hipMemcpyDeviceToHost, st));
       LS_HIP_TRY(hipStreamSynchronize(st));
       if (rec.done) {
-        done = true;
+        ++it;
         break;
       }
     }
   }
-  if (!done) {
-    const int rd = last_par_written;
-    hipLaunchKernelGGL(k_lsqr_step<T>, gstep, dim3(kThreads), 0, st, Wt, ldw, n, v, w.nvpart, Gv, w.st, rd,
-                       (it > maxit ? maxit + 1 : it + 1), 1, tol, maxit, p, what, x);
-    last_par_written = rd ^ 1;
-  }
+  const int last = it - 1;                 // last column kernel launched
+  const int fpar = (last + 1) & 1;         // rec written by it
+  hipLaunchKernelGGL(k_lsqr_finish<T>, dim3((unsigned)ls_cdiv(n, 16)), dim3(kThreads), 0, st, W, n, w.z0, w.y,
+                     w.nvpart[cur], Gv, w.st, fpar, last, x);
   LsqrState S;
   LS_HIP_TRY(hipMemcpyAsync(&S, w.st, sizeof(LsqrState), hipMemcpyDeviceToHost, st));
   LS_HIP_TRY(hipStreamSynchronize(st));
   LS_HIP_TRY(hipGetLastError());
-  rec = S.rec[last_par_written];
+  rec = S.rec[fpar];
   if (stats) {
     stats->lsqr_its = rec.its;
     stats->lsqr_normr = rec.normr;
@@ -1004,21 +1287,15 @@ int lsqr_typed(const ls_problem_t* P, const T* Wt, int64_t ldw, double* x, const
 
 size_t lsqr_workspace(const ls_problem_t* P, ls_prec_t u, int ncu) {
   const size_t elt = (u == LS_FP32) ? 4 : 8;
-  const int rb = pick_rb(P->n, elt);
-  return lsqr_carve(nullptr, P, elt, lsqr_grid(P, rb, ncu), (int)ls_cdiv(P->n, 4)).bytes;
+  int rb = pick_rb(P->n, elt, 0);
+  if (rb == 0) rb = 8;
+  return lsqr_carve(nullptr, P, elt, pass_grid(P->m, rb, ncu), (int)ls_cdiv(P->n, 4)).bytes;
 }
 
-int lsqr_device(const ls_problem_t* P, const double* W, const float* W32, int64_t ldw, ls_prec_t u, double* x,
-                const ls_iter_opts_t* io, ls_stats_t* stats, char* ws, size_t ws_bytes, hipStream_t st) {
-  if (u == LS_FP32) {
-    if (!W32) return LS_E_ARG;
-    if (P->store == LS_FP32) return lsqr_typed<float, float>(P, W32, P->n, x, io, stats, ws, ws_bytes, st);
-    return lsqr_typed<double, float>(P, W32, P->n, x, io, stats, ws, ws_bytes, st);
-  }
-  if (u == LS_FP64) {
-    if (P->store == LS_FP32) return lsqr_typed<float, double>(P, W, ldw, x, io, stats, ws, ws_bytes, st);
-    return lsqr_typed<double, double>(P, W, ldw, x, io, stats, ws, ws_bytes, st);
-  }
+int lsqr_device(const ls_problem_t* P, const double* R, int64_t ldr, const double* W, const void* Bm, ls_prec_t u,
+                double* x, const ls_iter_opts_t* io, ls_stats_t* stats, char* ws, size_t ws_bytes, hipStream_t st) {
+  if (u == LS_FP32) return lsqr_typed<float>(P, R, ldr, W, (const float*)Bm, x, io, stats, ws, ws_bytes, st);
+  if (u == LS_FP64) return lsqr_typed<double>(P, R, ldr, W, (const double*)Bm, x, io, stats, ws, ws_bytes, st);
   return LS_E_UNSUPPORTED;
 }
 
@@ -1028,27 +1305,48 @@ struct LsirWs {
   FgState* st;
   double* V;
   int64_t ldv;
-  double* Z;
   double* H;
   double* cs;
   double* sn;
   double* g;
   double* hj;
-  char* tpart;        // G x n (TP)
+  char* tpart;        // n x G (TB), column-major partials
   double* hpart;      // (kmax+1) x G
-  double* tbuf;       // n
   double* h1r;        // kmax + 1
   double* hxpart;     // (kmax+1) x Gc
   double* h2part;     // (kmax+1) x Gd
-  double* w2part;     // max(G + Gh, Gd)
-  double* rt_hi;      // G x n
-  double* rt_lo;      // G x n
+  double* h2;         // kmax + 1
+  double* w2part;     // max(Gr + Gh, Gd)
+  double* rt_hi;      // n x Gr
+  double* rt_lo;      // n x Gr
   double* gvec;       // n
-  double* upart;      // 4 x Gd
+  double* dz;         // n
+  double* upart;      // 2 x (Gd + Gn)
   size_t bytes;
 };
 
-LsirWs lsir_carve(char* ws, const ls_problem_t* P, int kmax, int G, int Gc, int Gd, int Gh) {
+struct LsirDims {
+  int kmax, rbp, rbr, G, Gr, Gc, Gd, Gh, Gn;
+};
+
+LsirDims lsir_dims(const ls_problem_t* P, size_t tb_elt, size_t ta_elt, int fgmres_maxit, int ncu) {
+  LsirDims d{};
+  d.kmax = fgmres_maxit;
+  d.rbp = pick_rb(P->n, tb_elt, 8 * (size_t)(fgmres_maxit + 40));
+  const size_t resid_extra = 8 * (3 * (size_t)P->n + 2 * kThreads + 64);
+  d.rbr = pick_rb(P->n, ta_elt, resid_extra > 2 * (size_t)P->n * ta_elt ? resid_extra - 2 * (size_t)P->n * ta_elt : 0);
+  if (d.rbp == 0) d.rbp = 8;
+  if (d.rbr == 0) d.rbr = 8;
+  d.G = pass_grid(P->m, d.rbp, ncu);
+  d.Gr = pass_grid(P->m, d.rbr, ncu);
+  d.Gc = (int)ls_cdiv(P->n, 16);
+  d.Gd = (int)ls_cdiv(P->m + P->n, kThreads);
+  d.Gh = (int)ls_cdiv(P->n, 4);
+  d.Gn = (int)ls_cdiv(P->n, 16);
+  return d;
+}
+
+LsirWs lsir_carve(char* ws, const ls_problem_t* P, const LsirDims& d, size_t tb_elt) {
   LsirWs w{};
   size_t off = 0;
   auto take = [&](size_t b) {
@@ -1057,142 +1355,118 @@ LsirWs lsir_carve(char* ws, const ls_problem_t* P, int kmax, int G, int Gc, int 
     return q;
   };
   const int64_t m = P->m, n = P->n;
+  const int kmax = d.kmax;
   w.ldv = m + n;
   w.st = reinterpret_cast<FgState*>(take(sizeof(FgState)));
   w.V = reinterpret_cast<double*>(take(8 * (size_t)w.ldv * (kmax + 1)));
-  w.Z = reinterpret_cast<double*>(take(8 * (size_t)n * kmax));
   w.H = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1) * kmax));
   w.cs = reinterpret_cast<double*>(take(8 * (size_t)kmax));
   w.sn = reinterpret_cast<double*>(take(8 * (size_t)kmax));
   w.g = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1)));
   w.hj = reinterpret_cast<double*>(take(8));
-  w.tpart = take(8 * (size_t)G * n);
-  w.hpart = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1) * G));
-  w.tbuf = reinterpret_cast<double*>(take(8 * (size_t)n));
+  w.tpart = take(tb_elt * (size_t)d.G * n);
+  w.hpart = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1) * d.G));
   w.h1r = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1)));
-  w.hxpart = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1) * Gc));
-  w.h2part = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1) * Gd));
-  const int w2n = (G + Gh > Gd) ? G + Gh : Gd;
+  w.hxpart = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1) * d.Gc));
+  w.h2part = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1) * d.Gd));
+  w.h2 = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1)));
+  const int w2n = (d.Gr + d.Gh > d.Gd) ? d.Gr + d.Gh : d.Gd;
   w.w2part = reinterpret_cast<double*>(take(8 * (size_t)w2n));
-  w.rt_hi = reinterpret_cast<double*>(take(8 * (size_t)G * n));
-  w.rt_lo = reinterpret_cast<double*>(take(8 * (size_t)G * n));
+  w.rt_hi = reinterpret_cast<double*>(take(8 * (size_t)d.Gr * n));
+  w.rt_lo = reinterpret_cast<double*>(take(8 * (size_t)d.Gr * n));
   w.gvec = reinterpret_cast<double*>(take(8 * (size_t)n));
-  w.upart = reinterpret_cast<double*>(take(8 * 4 * (size_t)Gd));
+  w.dz = reinterpret_cast<double*>(take(8 * (size_t)n));
+  w.upart = reinterpret_cast<double*>(take(8 * 2 * (size_t)(d.Gd + d.Gn)));
   w.bytes = off;
   return w;
 }
 
-struct LsirDims {
-  int kmax, rbp, rbr, G, Gc, Gd, Gh;
-};
-
-LsirDims lsir_dims(const ls_problem_t* P, size_t tp_elt, int fgmres_maxit, int ncu) {
-  LsirDims d{};
-  d.kmax = fgmres_maxit;
-  d.rbp = pick_rb(P->n, tp_elt);
-  d.rbr = pick_rb(P->n, 8);
-  int64_t G = 2 * (int64_t)ncu;
-  const int64_t nrb = ls_cdiv(P->m, d.rbr < d.rbp ? d.rbr : d.rbp);
-  if (G > nrb) G = nrb;
-  if (G < 1) G = 1;
-  d.G = (int)G;
-  d.Gc = (int)ls_cdiv(P->n, 16);
-  d.Gd = (int)ls_cdiv(P->m + P->n, 1024);
-  d.Gh = (int)ls_cdiv(P->n, 4);
-  return d;
-}
-
-template <typename TA, typename TP, typename TU, bool DD>
-int lsir_typed(const ls_problem_t* P, const double* W, const TP* Wp, int64_t ldwp, double* x, double* r,
-               int r_given, const ls_iter_opts_t* io, ls_stats_t* stats, char* ws, size_t ws_bytes,
-               hipStream_t st, int fg_maxit) {
+template <typename TA, typename TB, typename TU, bool DD>
+int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, double* r, int r_given,
+               const ls_iter_opts_t* io, ls_stats_t* stats, char* ws, size_t ws_bytes, hipStream_t st,
+               int fg_maxit) {
   const int64_t m = P->m, n = P->n;
   const int ncu = device_cu_count();
-  const LsirDims d = lsir_dims(P, sizeof(TP), fg_maxit, ncu);
-  if (d.kmax > 120) return LS_E_ARG;
-  LsirWs w = lsir_carve(ws, P, d.kmax, d.G, d.Gc, d.Gd, d.Gh);
+  const LsirDims d = lsir_dims(P, sizeof(TB), sizeof(TA), fg_maxit, ncu);
+  if (d.kmax > 95) return LS_E_ARG;
+  LsirWs w = lsir_carve(ws, P, d, sizeof(TB));
   if (w.bytes > ws_bytes) return LS_E_WORKSPACE;
-  FgPtrs F{w.V, w.ldv, w.Z, w.H, w.cs, w.sn, w.g, w.hj, w.st};
+  FgPtrs F{w.V, w.ldv, w.H, w.cs, w.sn, w.g, w.hj, w.st};
   const TA* A = static_cast<const TA*>(P->A);
   const TA* b = static_cast<const TA*>(P->b);
-  const int vec_ok = vec_aligned(A, P->lda, sizeof(TA)) ? 1 : 0;
-  TP* tpart = reinterpret_cast<TP*>(w.tpart);
+  const int vec_a = vec_aligned(A, P->lda, sizeof(TA)) ? 1 : 0;
+  const int vec_b = vec_aligned(Bm, m, sizeof(TB)) ? 1 : 0;
+  TB* tpart = reinterpret_cast<TB*>(w.tpart);
   const int check = io->check_every > 0 ? io->check_every : 8;
   const double tol = io->fgmres_tol;
   const double lsir_tol = io->lsir_tol;
-  const int nrb_norm = (int)ls_cdiv(m, 1024);
-  const int nwb = (int)ls_cdiv(n, 64);
-  const size_t lds_r = ((size_t)n * (d.rbr + 1) + 3 * (size_t)n + d.rbr + 2 * kThreads + 8) * 8;
-  const size_t lds_p =
-      ((size_t)n * (d.rbp + 1) + 2 * (size_t)n + d.rbp + kThreads) * sizeof(TP) + ((size_t)d.rbp + d.kmax + 2) * 8 + 16;
-
+  const size_t lds_r = ((size_t)n * (d.rbr + 1)) * sizeof(TA) + 8 * (3 * (size_t)n + d.rbr + 2 * kThreads + 8) + 16;
+  const size_t lds_p = pass_lds<TB>(n, d.rbp, d.rbp + d.kmax + 2);
   if (lds_r > device_lds_limit() || lds_p > device_lds_limit()) return LS_E_UNSUPPORTED;
+  const int ncb = (int)d.Gc;
+
   if (!r_given)
     hipLaunchKernelGGL((k_resid_u<TA, TU>), dim3((unsigned)ls_cdiv(m, kThreads)), dim3(kThreads), n * sizeof(TU), st, A,
                        P->lda, m, n, b, x, r);
   int total_fg = 0, its = 0, status = LS_NOT_CONVERGED;
   double dx_rel = 0.0, dr_rel = 0.0;
-  std::vector<double> up(4 * (size_t)d.Gd);
+  std::vector<double> up(2 * (size_t)(d.Gd + d.Gn));
   for (its = 1; its <= io->lsir_maxit; ++its) {
     // lines 5-6: f, g, h in u_r
     prof_begin(kProfResidPass, st);
     switch (d.rbr) {
       case 32:
-        hipLaunchKernelGGL((k_lsir_resid<TA, DD, 32>), dim3(d.G), dim3(kThreads), lds_r, st, A, P->lda, m, n, vec_ok, b,
-                           r, x, w.V, w.rt_hi, w.rt_lo, w.w2part);
+        hipLaunchKernelGGL((k_lsir_resid<TA, DD, 32>), dim3(d.Gr), dim3(kThreads), lds_r, st, A, P->lda, m, n, vec_a,
+                           b, r, x, w.V, w.rt_hi, w.rt_lo, w.w2part);
         break;
       case 16:
-        hipLaunchKernelGGL((k_lsir_resid<TA, DD, 16>), dim3(d.G), dim3(kThreads), lds_r, st, A, P->lda, m, n, vec_ok, b,
-                           r, x, w.V, w.rt_hi, w.rt_lo, w.w2part);
+        hipLaunchKernelGGL((k_lsir_resid<TA, DD, 16>), dim3(d.Gr), dim3(kThreads), lds_r, st, A, P->lda, m, n, vec_a,
+                           b, r, x, w.V, w.rt_hi, w.rt_lo, w.w2part);
         break;
       default:
-        hipLaunchKernelGGL((k_lsir_resid<TA, DD, 8>), dim3(d.G), dim3(kThreads), lds_r, st, A, P->lda, m, n, vec_ok, b,
-                           r, x, w.V, w.rt_hi, w.rt_lo, w.w2part);
+        hipLaunchKernelGGL((k_lsir_resid<TA, DD, 8>), dim3(d.Gr), dim3(kThreads), lds_r, st, A, P->lda, m, n, vec_a,
+                           b, r, x, w.V, w.rt_hi, w.rt_lo, w.w2part);
         break;
     }
     // A and b once, r read, f written, x read, g written
     prof_end(kProfResidPass, st, (double)m * n * sizeof(TA) + (double)m * sizeof(TA) + 16.0 * m + 16.0 * n);
-    hipLaunchKernelGGL(k_lsir_g<DD>, dim3((unsigned)ls_cdiv(n, 64)), dim3(kThreads), 0, st, w.rt_hi, w.rt_lo, d.G, n,
+    hipLaunchKernelGGL(k_lsir_g<DD>, dim3((unsigned)ls_cdiv(n, 4)), dim3(kThreads), 0, st, w.rt_hi, w.rt_lo, d.Gr, n,
                        w.gvec);
-    hipLaunchKernelGGL(k_lsir_h<DD>, dim3((unsigned)d.Gh), dim3(kThreads), 0, st, W, n, n, m, w.gvec, w.V,
-                       w.w2part + d.G);
+    hipLaunchKernelGGL(k_lsir_h<DD>, dim3((unsigned)d.Gh), dim3(kThreads), 0, st, W, n, m, w.gvec, w.V,
+                       w.w2part + d.Gr);
     hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(kThreads), 0, st, reinterpret_cast<char*>(w.st), sizeof(FgState));
-    // line 7: FGMRES
+    // line 7: FGMRES on [I B; B^T 0]
     int j = 0;
     FgState S{};
     for (; j < d.kmax; ++j) {
-      const int Gw = (j == 0) ? d.G + d.Gh : d.Gd;
-      hipLaunchKernelGGL(k_fg_a<TP>, dim3((unsigned)(nrb_norm + nwb)), dim3(kThreads), 0, st, F, m, n, j, d.kmax, Wp,
-                         ldwp, w.w2part, Gw, tol, 0, nrb_norm);
+      const int Gw = (j == 0) ? d.Gr + d.Gh : d.Gd;
       prof_begin(kProfFgPass, st);
       switch (d.rbp) {
         case 32:
-          hipLaunchKernelGGL((k_fg_pass<TA, TP, 32>), dim3(d.G), dim3(kThreads), lds_p, st, A, P->lda, m, n, vec_ok, F,
-                             j, tpart, w.hpart);
+          hipLaunchKernelGGL((k_fg_pass<TB, 32>), dim3(d.G), dim3(kThreads), lds_p, st, Bm, m, m, n, vec_b, F, j,
+                             d.kmax, w.w2part, Gw, tol, 0, tpart, w.hpart);
           break;
         case 16:
-          hipLaunchKernelGGL((k_fg_pass<TA, TP, 16>), dim3(d.G), dim3(kThreads), lds_p, st, A, P->lda, m, n, vec_ok, F,
-                             j, tpart, w.hpart);
+          hipLaunchKernelGGL((k_fg_pass<TB, 16>), dim3(d.G), dim3(kThreads), lds_p, st, Bm, m, m, n, vec_b, F, j,
+                             d.kmax, w.w2part, Gw, tol, 0, tpart, w.hpart);
           break;
         default:
-          hipLaunchKernelGGL((k_fg_pass<TA, TP, 8>), dim3(d.G), dim3(kThreads), lds_p, st, A, P->lda, m, n, vec_ok, F,
-                             j, tpart, w.hpart);
+          hipLaunchKernelGGL((k_fg_pass<TB, 8>), dim3(d.G), dim3(kThreads), lds_p, st, Bm, m, m, n, vec_b, F, j,
+                             d.kmax, w.w2part, Gw, tol, 0, tpart, w.hpart);
           break;
       }
-      // A once, v_j read, w written, z read, t written, V_r(:, 0:j) for the fused dots
+      // B once, v_j read and written, w written, v_x read, t written, V_r(:, 0:j) for the fused dots
       prof_end(kProfFgPass, st,
-               (double)m * n * sizeof(TA) + 16.0 * m + 8.0 * n + (double)n * sizeof(TP) + 8.0 * (j + 1) * m);
-      const int ncb = (int)ls_cdiv(n, 64);
-      hipLaunchKernelGGL(k_fg_reduce<TP>, dim3((unsigned)(ncb + j + 1)), dim3(kThreads), 0, st, tpart, w.hpart, d.G, n,
-                         j, ncb, w.tbuf, w.h1r, w.st);
-      hipLaunchKernelGGL(k_fg_c<TP>, dim3((unsigned)d.Gc), dim3(1024), 0, st, Wp, ldwp, n, m, w.tbuf, F, j, w.hxpart);
+               (double)m * n * sizeof(TB) + 24.0 * m + 8.0 * n + (double)n * sizeof(TB) + 8.0 * (j + 1) * m);
+      hipLaunchKernelGGL(k_fg_col<TB>, dim3((unsigned)(ncb + j + 1)), dim3(1024), 0, st, m, n, tpart, d.G, w.hpart, F,
+                         j, ncb, w.hxpart, w.h1r);
       prof_begin(kProfCgs, st);
-      hipLaunchKernelGGL(k_cgs, dim3((unsigned)d.Gd), dim3(kThreads), 0, st, F, m, n, j, d.kmax, w.h1r, w.hxpart, d.Gc,
-                         w.h2part, d.Gd, 0, w.h2part, w.w2part);
-      hipLaunchKernelGGL(k_cgs, dim3((unsigned)d.Gd), dim3(kThreads), 0, st, F, m, n, j, d.kmax, w.h1r, w.hxpart, d.Gc,
-                         w.h2part, d.Gd, 1, w.h2part, w.w2part);
-      // two sweeps over V(:, 0:j), each reading and writing w
-      prof_end(kProfCgs, st, 2.0 * 8.0 * (j + 1) * (double)(m + n) + 4.0 * 8.0 * (double)(m + n));
+      hipLaunchKernelGGL(k_cgs1, dim3((unsigned)d.Gd), dim3(kThreads), 0, st, F, m, n, j, d.kmax, w.h1r, w.hxpart, d.Gc,
+                         w.h2part);
+      hipLaunchKernelGGL(k_cgs_reduce, dim3((unsigned)(j + 1)), dim3(64), 0, st, F, j, d.kmax, w.h2part, d.Gd, w.h2);
+      hipLaunchKernelGGL(k_cgs2, dim3((unsigned)d.Gd), dim3(kThreads), 0, st, F, m, n, j, w.h2, w.w2part);
+      // V(:, 0:j) read three times (first sweep twice, second once), w read and written twice
+      prof_end(kProfCgs, st, 3.0 * 8.0 * (j + 1) * (double)(m + n) + 4.0 * 8.0 * (double)(m + n));
       if ((j + 1) % check == 0) {
         LS_HIP_TRY(hipMemcpyAsync(&S, w.st, sizeof(FgState), hipMemcpyDeviceToHost, st));
         LS_HIP_TRY(hipStreamSynchronize(st));
@@ -1200,20 +1474,28 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TP* Wp, int64_t ldw
       }
     }
     // final Givens step for the last column (no-op when already done)
-    hipLaunchKernelGGL(k_fg_a<TP>, dim3((unsigned)(nrb_norm + nwb)), dim3(kThreads), 0, st, F, m, n,
-                       (j < d.kmax ? j + 1 : d.kmax), d.kmax, Wp, ldwp, w.w2part, d.Gd, tol, 1, nrb_norm);
-    hipLaunchKernelGGL(k_fg_update<TU>, dim3((unsigned)d.Gd), dim3(kThreads), 0, st, F, m, n, d.kmax, r, x, w.upart);
+    hipLaunchKernelGGL((k_fg_pass<TB, 8>), dim3(1), dim3(kThreads), lds_p, st, Bm, m, m, n, vec_b, F,
+                       (j < d.kmax ? j + 1 : d.kmax), d.kmax, w.w2part, d.Gd, tol, 1, tpart, w.hpart);
+    hipLaunchKernelGGL(k_fg_update<TU>, dim3((unsigned)d.Gd), dim3(kThreads), 0, st, F, m, n, d.kmax, r, w.dz, w.upart);
+    hipLaunchKernelGGL(k_fg_dx<TU>, dim3((unsigned)d.Gn), dim3(kThreads), 0, st, W, n, w.dz, x,
+                       w.upart + 2 * (size_t)d.Gd);
     LS_HIP_TRY(hipMemcpyAsync(&S, w.st, sizeof(FgState), hipMemcpyDeviceToHost, st));
-    LS_HIP_TRY(hipMemcpyAsync(up.data(), w.upart, 8 * 4 * (size_t)d.Gd, hipMemcpyDeviceToHost, st));
+    LS_HIP_TRY(hipMemcpyAsync(up.data(), w.upart, 8 * 2 * (size_t)(d.Gd + d.Gn), hipMemcpyDeviceToHost, st));
     LS_HIP_TRY(hipStreamSynchronize(st));
     LS_HIP_TRY(hipGetLastError());
     if (S.breakdown == 2) return LS_E_NONFINITE;
     total_fg += S.k;
-    double nd[4] = {0, 0, 0, 0};
-    for (int g = 0; g < d.Gd; ++g)
-      for (int q = 0; q < 4; ++q) nd[q] += up[4 * (size_t)g + q];
-    dr_rel = sqrt(nd[0]) / (sqrt(nd[2]) > 0 ? sqrt(nd[2]) : 1.0);
-    dx_rel = sqrt(nd[1]) / (sqrt(nd[3]) > 0 ? sqrt(nd[3]) : 1.0);
+    double nr[2] = {0, 0}, nx[2] = {0, 0};
+    for (int g = 0; g < d.Gd; ++g) {
+      nr[0] += up[2 * (size_t)g];
+      nr[1] += up[2 * (size_t)g + 1];
+    }
+    for (int g = 0; g < d.Gn; ++g) {
+      nx[0] += up[2 * (size_t)(d.Gd + g)];
+      nx[1] += up[2 * (size_t)(d.Gd + g) + 1];
+    }
+    dr_rel = sqrt(nr[0]) / (nr[1] > 0 ? sqrt(nr[1]) : 1.0);
+    dx_rel = sqrt(nx[0]) / (nx[1] > 0 ? sqrt(nx[1]) : 1.0);
     if (!std::isfinite(dr_rel) || !std::isfinite(dx_rel)) return LS_E_NONFINITE;
     if (dx_rel <= lsir_tol && dr_rel <= lsir_tol) {
       status = LS_OK;
@@ -1232,48 +1514,47 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TP* Wp, int64_t ldw
 }  // namespace
 
 size_t lsir_workspace(const ls_problem_t* P, const ls_precs_t* pr, int fgmres_maxit, int ncu) {
-  const size_t tp = (pr->u_A == LS_FP64) ? 8 : 4;
-  const LsirDims d = lsir_dims(P, tp, fgmres_maxit, ncu);
-  return lsir_carve(nullptr, P, d.kmax, d.G, d.Gc, d.Gd, d.Gh).bytes;
+  const size_t tb = (pr->u_A == LS_FP64) ? 8 : 4;
+  const size_t ta = (P->store == LS_FP64) ? 8 : 4;
+  const LsirDims d = lsir_dims(P, tb, ta, fgmres_maxit, ncu);
+  return lsir_carve(nullptr, P, d, tb).bytes;
 }
 
-int lsir_device(const ls_problem_t* P, const double* W, const float* W32, int64_t ldw, const ls_precs_t* pr,
-                double* x, double* r, int r_given, const ls_iter_opts_t* io, ls_stats_t* stats, char* ws,
-                size_t ws_bytes, hipStream_t st) {
-  const ls_prec_t tp = pr->u_A;
-  if (pr->u_L != tp || pr->u_R != tp) return LS_E_UNSUPPORTED;
+int lsir_device(const ls_problem_t* P, const double* W, const void* Bm, const ls_precs_t* pr, double* x, double* r,
+                int r_given, const ls_iter_opts_t* io, ls_stats_t* stats, char* ws, size_t ws_bytes,
+                hipStream_t st) {
+  const ls_prec_t tb = pr->u_A;
+  if (pr->u_L != tb || pr->u_R != tb) return LS_E_UNSUPPORTED;
   const bool dd = pr->u_r == LS_FP64X2;
   if (!dd && pr->u_r != LS_FP64) return LS_E_UNSUPPORTED;
   const bool u32 = pr->u == LS_FP32;
   if (!u32 && pr->u != LS_FP64) return LS_E_UNSUPPORTED;
-  if (u32 == false && tp == LS_FP32) return LS_E_ARG;   // products not coarser than u
+  if (!u32 && tb == LS_FP32) return LS_E_ARG;   // products not coarser than u
   const int kmax = io->fgmres_maxit;
-#define LS_LSIR_CALL(TA, TP_, TU, DD_, WP, LDWP) \
-  return lsir_typed<TA, TP_, TU, DD_>(P, W, WP, LDWP, x, r, r_given, io, stats, ws, ws_bytes, st, kmax)
+#define LS_LSIR_CALL(TA, TB_, TU, DD_) \
+  return lsir_typed<TA, TB_, TU, DD_>(P, W, (const TB_*)Bm, x, r, r_given, io, stats, ws, ws_bytes, st, kmax)
   if (P->store == LS_FP32) {
-    if (tp == LS_FP32) {
-      if (!W32) return LS_E_ARG;
-      if (dd) LS_LSIR_CALL(float, float, float, true, W32, P->n);
-      LS_LSIR_CALL(float, float, float, false, W32, P->n);
+    if (tb == LS_FP32) {
+      if (dd) LS_LSIR_CALL(float, float, float, true);
+      LS_LSIR_CALL(float, float, float, false);
     }
     if (u32) {
-      if (dd) LS_LSIR_CALL(float, double, float, true, W, ldw);
-      LS_LSIR_CALL(float, double, float, false, W, ldw);
+      if (dd) LS_LSIR_CALL(float, double, float, true);
+      LS_LSIR_CALL(float, double, float, false);
     }
-    if (dd) LS_LSIR_CALL(float, double, double, true, W, ldw);
-    LS_LSIR_CALL(float, double, double, false, W, ldw);
+    if (dd) LS_LSIR_CALL(float, double, double, true);
+    LS_LSIR_CALL(float, double, double, false);
   } else {
-    if (tp == LS_FP32) {
-      if (!W32) return LS_E_ARG;
-      if (dd) LS_LSIR_CALL(double, float, float, true, W32, P->n);
-      LS_LSIR_CALL(double, float, float, false, W32, P->n);
+    if (tb == LS_FP32) {
+      if (dd) LS_LSIR_CALL(double, float, float, true);
+      LS_LSIR_CALL(double, float, float, false);
     }
     if (u32) {
-      if (dd) LS_LSIR_CALL(double, double, float, true, W, ldw);
-      LS_LSIR_CALL(double, double, float, false, W, ldw);
+      if (dd) LS_LSIR_CALL(double, double, float, true);
+      LS_LSIR_CALL(double, double, float, false);
     }
-    if (dd) LS_LSIR_CALL(double, double, double, true, W, ldw);
-    LS_LSIR_CALL(double, double, double, false, W, ldw);
+    if (dd) LS_LSIR_CALL(double, double, double, true);
+    LS_LSIR_CALL(double, double, double, false);
   }
 #undef LS_LSIR_CALL
 }

@@ -38,22 +38,6 @@ int trinv_run(const double* R, int64_t ldr, int64_t n, double* W, int64_t ldw, f
               hipStream_t st);
 
 // ------------------------------------------------------------------ iterations
-// Per-device-call scalar state of LSQR (binary64; two parity copies of the
-// recurrence so that all blocks of a kernel read the previous copy while
-// block 0 writes the next one).
-struct LsqrRec {
-  double alpha, rhobar, phibar, normB2, phi_over_rho, theta_over_rho;
-  double normr, normar, normB;
-  int32_t its, done, stop, pad;
-};
-struct LsqrState {
-  LsqrRec rec[2];
-  double beta;     // beta_{i+1}, written by the reduction kernel
-  double normb;
-  int32_t flag;    // nonzero: non-finite value met
-  int32_t pad;
-};
-
 struct FgState {
   double beta;                 // ||s||
   double relres;
@@ -63,13 +47,19 @@ struct FgState {
   int32_t pad;
 };
 
-int lsqr_device(const ls_problem_t* P, const double* W, const float* W32, int64_t ldw, ls_prec_t u, double* x,
-                const ls_iter_opts_t* io, ls_stats_t* stats, char* ws, size_t ws_bytes, hipStream_t st);
+// B = A W with W = R^-1 (binary64 n x n, ld n; W32 its binary32 copy), in precision tb.
+int form_b(const ls_problem_t* P, const double* W, const float* W32, ls_prec_t tb, void* Bout, hipStream_t st);
+size_t b_bytes(const ls_problem_t* P, ls_prec_t tb);
+
+// LSQR on B = A R^-1 from x (in/out): R (ldr) maps x0 to z0 = R x0, W maps z back.
+int lsqr_device(const ls_problem_t* P, const double* R, int64_t ldr, const double* W, const void* Bm, ls_prec_t u,
+                double* x, const ls_iter_opts_t* io, ls_stats_t* stats, char* ws, size_t ws_bytes, hipStream_t st);
 size_t lsqr_workspace(const ls_problem_t* P, ls_prec_t u, int ncu);
 
-int lsir_device(const ls_problem_t* P, const double* W, const float* W32, int64_t ldw, const ls_precs_t* pr,
-                double* x, double* r, int r_given, const ls_iter_opts_t* io, ls_stats_t* stats, char* ws,
-                size_t ws_bytes, hipStream_t st);
+// Refinement with FGMRES on [I B; B^T 0]; B in precision u_A.
+int lsir_device(const ls_problem_t* P, const double* W, const void* Bm, const ls_precs_t* pr, double* x, double* r,
+                int r_given, const ls_iter_opts_t* io, ls_stats_t* stats, char* ws, size_t ws_bytes,
+                hipStream_t st);
 size_t lsir_workspace(const ls_problem_t* P, const ls_precs_t* pr, int fgmres_maxit, int ncu);
 
 int device_cu_count();

@@ -20,24 +20,43 @@ constexpr int kRowChunk = 256;
 
 // Sum each of v[0..NB) over the 64 lanes of a wave with a transposed
 // butterfly: after it, the returned value is the full sum of index `idx`.
+// The loops run over a compile-time step count so that every register index
+// is a constant after unrolling.
+template <int NB>
+struct Log2 {
+  static constexpr int value = (NB <= 1) ? 0 : 1 + Log2<NB / 2>::value;
+};
+template <>
+struct Log2<1> {
+  static constexpr int value = 0;
+};
+
 template <typename T, int NB>
 __device__ __forceinline__ T wave_multi_sum(T (&v)[NB], int lane, int& idx) {
-  int off = 32;
+  constexpr int L = Log2<NB>::value;
   int base = 0;
 #pragma unroll
-  for (int h = NB / 2; h >= 1; h >>= 1) {
+  for (int step = 0; step < L; ++step) {
+    const int off = 32 >> step;
+    const int h = NB >> (step + 1);
     const bool up = (lane & off) != 0;
+    // lane choice as an exact blend (factors 1 and 0): a select here would be
+    // folded into a run-time register index, which compiles to select chains
+    const T fu = up ? T(1) : T(0);
+    const T fl = T(1) - fu;
 #pragma unroll
-    for (int q = 0; q < h; ++q) {
-      const T send = up ? v[q] : v[q + h];
-      const T keep = up ? v[q + h] : v[q];
-      v[q] = keep + __shfl_xor(send, off, 64);
+    for (int q = 0; q < NB / 2; ++q) {
+      if (q < h) {
+        const T send = v[q] * fu + v[q + h] * fl;
+        const T keep = v[q + h] * fu + v[q] * fl;
+        v[q] = keep + __shfl_xor(send, off, 64);
+      }
     }
     if (up) base += h;
-    off >>= 1;
   }
   T s = v[0];
-  for (; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+#pragma unroll
+  for (int off = 32 >> L; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
   idx = base;
   return s;
 }
