@@ -69,13 +69,12 @@ int check_precs(const ls_precs_t* pr) {
 }
 
 // x = W c with W upper triangular n x n (ld n): x^s = R^-1 (Q^T Omega b).
-__global__ __launch_bounds__(256) void k_trmv_f64(const double* __restrict__ W, int64_t n, const double* __restrict__ c,
-                                                  double* __restrict__ x) {
-  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (r >= n) return;
-  double acc = 0.0;
-  for (int64_t j = r; j < n; ++j) acc += W[r + j * n] * c[j];
-  x[r] = acc;
+__global__ __launch_bounds__(kUtThreads) void k_trmv_f64(const double* __restrict__ W, int64_t n,
+                                                         const double* __restrict__ c, double* __restrict__ x) {
+  __shared__ double red[32 * 33];
+  const double v = ls_utmv_row(W, n, n, [&](int64_t j) { return c[j]; }, red);
+  const int64_t row = (int64_t)blockIdx.x * 32 + threadIdx.x;
+  if (threadIdx.x < 32 && row < n) x[row] = v;
 }
 
 struct Inv {
@@ -341,7 +340,7 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
   LS_HIP_TRY(hipMemsetAsync(inv.flag, 0, sizeof(int), st));
   LS_TRY(qr_run(s, n + 1, pr->u_qr, Y, s, Raug, n + 1, scratch, scratch_bytes, inv.flag, n, st));
   LS_TRY(trinv_run(Raug, n + 1, n, inv.W, n, inv.W32, inv.flag, st));
-  hipLaunchKernelGGL(k_trmv_f64, dim3((unsigned)ls_cdiv(n, 256)), dim3(256), 0, st, inv.W, n, Raug + n * (n + 1), x);
+  hipLaunchKernelGGL(k_trmv_f64, dim3((unsigned)ls_cdiv(n, 32)), dim3(kUtThreads), 0, st, inv.W, n, Raug + n * (n + 1), x);
   int flag = 0;
   LS_HIP_TRY(hipMemcpyAsync(&flag, inv.flag, sizeof(int), hipMemcpyDeviceToHost, st));
   LS_HIP_TRY(hipStreamSynchronize(st));

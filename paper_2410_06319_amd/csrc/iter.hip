@@ -28,10 +28,39 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kMaxVecLoads = 16;   // 16-byte loads per thread held in flight for one row block
-constexpr int kMaxTile = 12;       // Krylov-tile values per thread in the FGMRES pass (RB (j+1) <= 3072)
+constexpr int kMaxKrylov = 96;     // Arnoldi columns per FGMRES cycle (kmax + 1)
+constexpr int kMaxPanQ = 16;       // 16-byte loads per lane for one panel of B (n <= 1024)
 
 typedef float ls_float4v __attribute__((ext_vector_type(4)));
 typedef double ls_double4v __attribute__((ext_vector_type(4)));
+typedef double ls_double2v __attribute__((ext_vector_type(2)));
+
+// Panel layout of B: panels of PR = 16 / sizeof(T) rows, one 16-byte vector per
+// column.  Panel p holds rows [PR p, PR p + PR) of all n columns, column after
+// column: row i of column c is element PR n (i / PR) + PR c + i % PR.  Rows
+// past m in the last panel are zero.  A wave reads a panel with fully
+// coalesced 1 KB loads (lane l, load q: column l + 64 q).
+template <typename T>
+struct PanVec;
+template <>
+struct PanVec<float> {
+  static constexpr int PR = 4;
+  using type = ls_float4v;
+};
+template <>
+struct PanVec<double> {
+  static constexpr int PR = 2;
+  using type = ls_double2v;
+};
+
+// Butterfly sum over the wave; every lane ends with the same bits (each step
+// adds the same two numbers in every lane of a pair).
+template <typename T>
+__device__ __forceinline__ T wave_allsum(T v) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
 
 __device__ __forceinline__ double* align8(void* p) {
   return reinterpret_cast<double*>(((uintptr_t)p + 7) & ~(uintptr_t)7);
@@ -112,31 +141,6 @@ struct RowBlock {
   }
 };
 
-// q[r] = sum_j Ms[j][r] * vec[j] for r < RB (RB x (256/RB) thread layout).
-template <typename T, int RB>
-__device__ __forceinline__ T rows_times_vec(const T* __restrict__ Ms, const T* __restrict__ vec, int64_t n,
-                                            T* __restrict__ red) {
-  constexpr int LDR = RB + 1;
-  constexpr int G1 = kThreads / RB;
-  const int r = threadIdx.x % RB;
-  const int g = threadIdx.x / RB;
-  T a0 = 0, a1 = 0;
-  int j = g;
-  for (; j + G1 < n; j += 2 * G1) {
-    a0 += Ms[j * LDR + r] * vec[j];
-    a1 += Ms[(j + G1) * LDR + r] * vec[j + G1];
-  }
-  if (j < n) a0 += Ms[j * LDR + r] * vec[j];
-  red[g * RB + r] = a0 + a1;
-  __syncthreads();
-  T q = 0;
-  if (threadIdx.x < RB) {
-#pragma unroll
-    for (int gg = 0; gg < G1; ++gg) q += red[gg * RB + threadIdx.x];
-  }
-  return q;   // valid in threads < RB
-}
-
 // Range of row blocks owned by block `bx` of G.
 __device__ __forceinline__ void row_range(int64_t nrb, int G, int bx, int64_t& b0, int64_t& b1) {
   b0 = (nrb * bx) / G;
@@ -162,7 +166,7 @@ __device__ __forceinline__ int mfma_drow(int lane, int r) {
 
 template <typename TA, typename T>
 __global__ __launch_bounds__(kThreads) void k_form_b(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n,
-                                                     const T* __restrict__ W, T* __restrict__ B, int64_t ldb) {
+                                                     const T* __restrict__ W, T* __restrict__ B) {
   using acc_t = typename std::conditional<sizeof(T) == 4, ls_float4v, ls_double4v>::type;
   __shared__ T As[16][64 + 1];   // As[k][i]
   __shared__ T Ws[16][64 + 1];   // Ws[k][j]
@@ -199,42 +203,36 @@ __global__ __launch_bounds__(kThreads) void k_form_b(const TA* __restrict__ A, i
       }
     }
   }
+  // panel layout; rows in [m, mp) of the last panel are written as zeros
+  constexpr int PR = PanVec<T>::PR;
+  const int64_t mp = ls_cdiv(m, PR) * PR;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       const int64_t gj = j0 + wc + b * 16 + (lane & 15);
+      if (gj >= n) continue;
+      if constexpr (sizeof(T) == 4) {
+        // binary32: the lane's four rows are one aligned group of PR = 4 rows
+        const int64_t gi = i0 + wr + a * 16 + mfma_drow<T>(lane, 0);
+        if (gi < mp) *reinterpret_cast<ls_float4v*>(B + (gi / PR) * PR * n + gj * PR) = acc[a][b];
+      } else {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t gi = i0 + wr + a * 16 + mfma_drow<T>(lane, r);
-        if (gi < m && gj < n) B[gi + gj * ldb] = acc[a][b][r];
+        for (int r = 0; r < 4; ++r) {
+          const int64_t gi = i0 + wr + a * 16 + mfma_drow<T>(lane, r);
+          if (gi < mp) B[(gi / PR) * PR * n + gj * PR + (gi % PR)] = acc[a][b][r];
+        }
       }
     }
 }
 
-// out = W v (+ v2) for upper-triangular W (n x n, ld): 16 rows x 16 column groups per block.
-template <typename TW, typename TV>
-__global__ __launch_bounds__(kThreads) void k_trmv(const TW* __restrict__ W, int64_t ldw, int64_t n,
-                                                   const TV* __restrict__ v, const TV* __restrict__ v2,
-                                                   double* __restrict__ out) {
-  __shared__ double red[16][17];
-  const int r = threadIdx.x & 15, cg = threadIdx.x >> 4;
-  const int64_t row = (int64_t)blockIdx.x * 16 + r;
-  double acc = 0.0;
-  if (row < n) {
-    for (int64_t j = row + cg; j < n; j += 16) {
-      const double vj = (double)v[j] + (v2 ? (double)v2[j] : 0.0);
-      acc += (double)W[row + j * ldw] * vj;
-    }
-  }
-  red[cg][r] = acc;
-  __syncthreads();
-  if (cg == 0 && row < n) {
-    double s = 0.0;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) s += red[q][r];
-    out[row] = s;
-  }
+// out = W v for upper-triangular W (n x n, ld).
+__global__ __launch_bounds__(kUtThreads) void k_trmv(const double* __restrict__ W, int64_t ldw, int64_t n,
+                                                     const double* __restrict__ v, double* __restrict__ out) {
+  __shared__ double red[32 * 33];
+  const double s = ls_utmv_row(W, ldw, n, [&](int64_t j) { return v[j]; }, red);
+  const int64_t row = (int64_t)blockIdx.x * 32 + threadIdx.x;
+  if (threadIdx.x < 32 && row < n) out[row] = s;
 }
 
 template <typename TO, typename TI>
@@ -267,86 +265,119 @@ struct LsqrState {
   int32_t flag, pad;
 };
 
-template <typename T, int RB>
-__global__ __launch_bounds__(kThreads) void k_lsqr_pass(const T* __restrict__ B, int64_t ldb, int64_t m, int64_t n,
-                                                        int vec_ok, const T* __restrict__ v,
-                                                        const double* __restrict__ nvpart, int Gv,
-                                                        T* __restrict__ u, const LsqrState* __restrict__ st, int par,
-                                                        int init, T* __restrict__ tpart,
-                                                        double* __restrict__ nupart, double* __restrict__ nbpart) {
+// Pass of iteration i over the panels of B (one wave streams a contiguous
+// range of panels, the next panel in flight while the current one is used):
+// per panel, the row sums B v are reduced across the wave, giving the panel's
+// rows of u_{i+1}; every lane then adds those rows' contribution to its own
+// columns of B^T u_{i+1}.  Column partials are summed over the block's waves
+// in a fixed order.  Init: u_1 = b - B z0 (v = -z0, coef = -1).
+template <typename T, int Q>
+__global__ __launch_bounds__(kThreads) void k_lsqr_pan(const T* __restrict__ Bp, int64_t npan, int64_t m, int64_t n,
+                                                       const T* __restrict__ v, const double* __restrict__ nvpart,
+                                                       int Gv, T* __restrict__ u, const LsqrState* __restrict__ st,
+                                                       int par, int init, T* __restrict__ tpart,
+                                                       double* __restrict__ nupart, double* __restrict__ nbpart) {
   if (!init && st->rec[par].done) return;
-  extern __shared__ __align__(16) char smem[];
-  constexpr int LDR = RB + 1;
-  T* Ms = reinterpret_cast<T*>(smem);
-  T* vs = Ms + n * LDR;
-  T* tacc = vs + n;
-  T* uu = tacc + n;
-  T* red = uu + RB;
-  double* dsh = align8(red + kThreads);
+  using vec_t = typename PanVec<T>::type;
+  constexpr int PR = PanVec<T>::PR;
+  __shared__ T cred[64 * Q];
+  __shared__ double dsh[8];
   const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
   T scale = 1, coef = -1;
   if (!init) {
     const double alpha = sqrt(wave_sum_array(nvpart, Gv, lane));
     scale = (T)(1.0 / alpha);
     coef = (T)(alpha / st->rec[par].beta);
   }
-  for (int j = threadIdx.x; j < n; j += kThreads) {
-    vs[j] = v[j] * scale;
-    tacc[j] = 0;
+  T vl[Q], creg[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t c = lane + 64 * q;
+    vl[q] = (c < n) ? v[c] * scale : T(0);
+    creg[q] = 0;
   }
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  int64_t p0, p1;
+  row_range(npan, (int)nw, blockIdx.x * 4 + wave, p0, p1);
   double nu = 0.0, nb = 0.0;
-  const int64_t nrb = ls_cdiv(m, RB);
-  int64_t b0, b1;
-  row_range(nrb, gridDim.x, blockIdx.x, b0, b1);
-  RowBlock<T, RB> blk;
-  T pre_u = 0;   // u of this thread's row in the next block (threads < RB)
-  auto load_u = [&](int64_t i0) {
-    if (threadIdx.x < RB) {
-      const int64_t i = i0 + threadIdx.x;
-      pre_u = (i < m) ? u[i] : T(0);
+  vec_t cur[Q];
+  vec_t uo;
+  auto load = [&](int64_t p, vec_t* dst, vec_t& uu) {
+    const T* base = Bp + p * (PR * n);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t c = lane + 64 * q;
+      dst[q] = (c < n) ? *reinterpret_cast<const vec_t*>(base + c * PR) : vec_t{};
+    }
+    const int64_t i0 = p * PR;
+    if (i0 + PR <= m) {
+      uu = *reinterpret_cast<const vec_t*>(u + i0);
+    } else {
+#pragma unroll
+      for (int k = 0; k < PR; ++k) uu[k] = (i0 + k < m) ? u[i0 + k] : T(0);
     }
   };
-  if (b0 < b1) {
-    blk.load(B, ldb, m, n, b0 * RB, vec_ok != 0);
-    load_u(b0 * RB);
-  }
-  for (int64_t rb = b0; rb < b1; ++rb) {
-    const int64_t i0 = rb * RB;
-    __syncthreads();
-    blk.store(B, ldb, m, n, i0, Ms);
-    const T uo = pre_u;
-    __syncthreads();
-    if (rb + 1 < b1) {   // next block in flight during the compute below
-      blk.load(B, ldb, m, n, i0 + RB, vec_ok != 0);
-      load_u(i0 + RB);
+  if (p0 < p1) load(p0, cur, uo);
+  for (int64_t p = p0; p < p1; ++p) {
+    vec_t nxt[Q];
+    vec_t un_o;
+    if (p + 1 < p1) load(p + 1, nxt, un_o);
+    const int64_t i0 = p * PR;
+    T s[PR];
+#pragma unroll
+    for (int k = 0; k < PR; ++k) s[k] = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int k = 0; k < PR; ++k) s[k] += cur[q][k] * vl[q];
+    vec_t un;
+#pragma unroll
+    for (int k = 0; k < PR; ++k) {
+      const T sk = wave_allsum(s[k]);
+      un[k] = (i0 + k < m) ? sk - coef * uo[k] : T(0);
     }
-    const T q = rows_times_vec<T, RB>(Ms, vs, n, red);
-    if (threadIdx.x < RB) {
-      const int64_t i = i0 + threadIdx.x;
-      T un = 0;
-      if (i < m) {
-        un = q - coef * uo;
-        u[i] = un;
-        if (init) nb += (double)uo * (double)uo;
+    if (lane == 0) {
+      if (i0 + PR <= m) {
+        *reinterpret_cast<vec_t*>(u + i0) = un;
+      } else {
+#pragma unroll
+        for (int k = 0; k < PR; ++k)
+          if (i0 + k < m) u[i0 + k] = un[k];
       }
-      uu[threadIdx.x] = un;
-      nu += (double)un * (double)un;
+#pragma unroll
+      for (int k = 0; k < PR; ++k) {
+        nu += (double)un[k] * (double)un[k];
+        if (init) nb += (double)uo[k] * (double)uo[k];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int k = 0; k < PR; ++k) creg[q] += cur[q][k] * un[k];
+    if (p + 1 < p1) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) cur[q] = nxt[q];
+      uo = un_o;
+    }
+  }
+  // column partials of the block's four waves, summed in wave order
+  for (int wv = 0; wv < 4; ++wv) {
+    if (wave == wv) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) cred[lane + 64 * q] = (wv ? cred[lane + 64 * q] : T(0)) + creg[q];
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < n; j += kThreads) {
-      T acc = 0;
-#pragma unroll 8
-      for (int r = 0; r < RB; ++r) acc += Ms[j * LDR + r] * uu[r];
-      tacc[j] += acc;
-    }
+  }
+  for (int64_t c = threadIdx.x; c < n; c += kThreads) tpart[c * gridDim.x + blockIdx.x] = cred[c];
+  if (lane == 0) {
+    dsh[wave] = nu;
+    dsh[4 + wave] = nb;
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < n; j += kThreads) tpart[(int64_t)j * gridDim.x + blockIdx.x] = tacc[j];
-  nu = block_sum256(nu, dsh);
-  nb = block_sum256(nb, dsh + 4);
   if (threadIdx.x == 0) {
-    nupart[blockIdx.x] = nu;
-    if (init) nbpart[blockIdx.x] = nb;
+    nupart[blockIdx.x] = (dsh[0] + dsh[1]) + (dsh[2] + dsh[3]);
+    if (init) nbpart[blockIdx.x] = (dsh[4] + dsh[5]) + (dsh[6] + dsh[7]);
   }
 }
 
@@ -467,12 +498,12 @@ __global__ __launch_bounds__(kThreads) void k_lsqr_col(int64_t n, const T* __res
 
 // Final: stopping data of the last iteration (needs alpha_{k+1}) and x = W (z0 + y).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_lsqr_finish(const double* __restrict__ W, int64_t n,
+__global__ __launch_bounds__(kUtThreads) void k_lsqr_finish(const double* __restrict__ W, int64_t n,
                                                           const double* __restrict__ z0,
                                                           const double* __restrict__ y,
                                                           const double* __restrict__ nvpart, int Gv,
                                                           LsqrState* st, int par, int it, double* __restrict__ x) {
-  __shared__ double red[16][17];
+  __shared__ double red[32 * 33];
   const int lane = threadIdx.x & 63;
   if (blockIdx.x == 0 && threadIdx.x < 64) {
     const double alpha = sqrt(wave_sum_array(nvpart, Gv, lane));
@@ -488,19 +519,9 @@ __global__ __launch_bounds__(kThreads) void k_lsqr_finish(const double* __restri
       st->rec[par] = R;
     }
   }
-  const int r = threadIdx.x & 15, cg = threadIdx.x >> 4;
-  const int64_t row = (int64_t)blockIdx.x * 16 + r;
-  double acc = 0.0;
-  if (row < n)
-    for (int64_t j = row + cg; j < n; j += 16) acc += W[row + j * n] * (z0[j] + y[j]);
-  red[cg][r] = acc;
-  __syncthreads();
-  if (cg == 0 && row < n) {
-    double s = 0.0;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) s += red[q][r];
-    x[row] = (double)(T)s;
-  }
+  const double v = ls_utmv_row(W, n, n, [&](int64_t j) { return z0[j] + y[j]; }, red);
+  const int64_t row = (int64_t)blockIdx.x * 32 + threadIdx.x;
+  if (threadIdx.x < 32 && row < n) x[row] = (double)(T)v;
 }
 
 // ================================================================== refinement
@@ -684,25 +705,23 @@ struct FgPtrs {
 };
 
 // Column j: h = ||w|| from partials (j = 0: beta = ||s||); block 0 applies
-// the Givens rotations to column j-1 and tests convergence.  Then, per row
-// block of B: v_r = V_r[:, j] / h (written back normalised), w_r = v_r + B v_x
-// -> V_r[:, j+1], partial t = B^T v_r, partial h1_r[c] = V_r[:, c] . w_r.
-template <typename TB, int RB>
-__global__ __launch_bounds__(kThreads) void k_fg_pass(const TB* __restrict__ B, int64_t ldb, int64_t m, int64_t n,
-                                                      int vec_ok, FgPtrs F, int j, int kmax,
-                                                      const double* __restrict__ w2part, int Gw, double tol,
-                                                      int final_step, TB* __restrict__ tpart,
-                                                      double* __restrict__ hpart) {
+// the Givens rotations to column j-1 and tests convergence.  Then, per panel
+// of B (one wave per contiguous panel range, next panel in flight):
+// v_r = V_r[:, j] / h (written back normalised), w_r = v_r + B v_x ->
+// V_r[:, j+1], the lanes' column partials of t = B^T v_r, and partial
+// h1_r[c] = V_r[:, c] . w_r for c <= j (lane l: panel row l % PR, Krylov
+// columns l / PR + (64 / PR) t).
+template <typename TB, int Q>
+__global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, int64_t npan, int64_t m, int64_t n,
+                                                     FgPtrs F, int j, int kmax, const double* __restrict__ w2part,
+                                                     int Gw, double tol, int final_step, TB* __restrict__ tpart,
+                                                     double* __restrict__ hpart) {
   if (F.st->done) return;
-  extern __shared__ __align__(16) char smem[];
-  constexpr int LDR = RB + 1;
-  TB* Ms = reinterpret_cast<TB*>(smem);
-  TB* vs = Ms + n * LDR;
-  TB* tacc = vs + n;
-  TB* uu = tacc + n;
-  TB* red = uu + RB;
-  double* wv = align8(red + kThreads);
-  double* hacc = wv + RB;     // j + 1 entries
+  using vec_t = typename PanVec<TB>::type;
+  constexpr int PR = PanVec<TB>::PR;
+  constexpr int TM = (kMaxKrylov * PR + 63) / 64;
+  __shared__ TB cred[64 * Q];
+  __shared__ double hred[kMaxKrylov];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const double h = sqrt(wave_sum_array(w2part, Gw, lane));
@@ -753,88 +772,120 @@ __global__ __launch_bounds__(kThreads) void k_fg_pass(const TB* __restrict__ B, 
   const double inv = 1.0 / h;
   double* vj = F.V + (int64_t)j * F.ldv;
   double* w = F.V + (int64_t)(j + 1) * F.ldv;
-  for (int c = threadIdx.x; c < n; c += kThreads) {
-    vs[c] = (TB)(vj[m + c] * inv);
-    tacc[c] = 0;
-  }
-  for (int c = threadIdx.x; c <= j; c += kThreads) hacc[c] = 0.0;
-  const int64_t nrb = ls_cdiv(m, RB);
-  int64_t b0, b1;
-  row_range(nrb, gridDim.x, blockIdx.x, b0, b1);
-  // The block's tile V_r[i0:i0+RB, 0:j+1] for the fused dots: element
-  // idx = t + 256 q is row idx % RB, Krylov column idx / RB; groups of RB
-  // consecutive threads share a column.  Column j is read unnormalised and scaled.
-  const int ntile = RB * (j + 1);
-  double vt[kMaxTile];
-  auto load_tile = [&](int64_t i0) {
+  TB vl[Q], creg[Q];
 #pragma unroll
-    for (int q = 0; q < kMaxTile; ++q) {
-      const int idx = threadIdx.x + q * kThreads;
-      const int64_t i = i0 + (idx % RB);
-      const int c = idx / RB;
-      vt[q] = (idx < ntile && i < m) ? F.V[i + (int64_t)c * F.ldv] : 0.0;
-    }
-  };
-  double pre_v = 0.0;   // V_r[i, j] of this thread's row in the next block (threads < RB)
-  auto load_v = [&](int64_t i0) {
-    if (threadIdx.x < RB) {
-      const int64_t i = i0 + threadIdx.x;
-      pre_v = (i < m) ? vj[i] : 0.0;
-    }
-  };
-  RowBlock<TB, RB> blk;
-  if (b0 < b1) {
-    blk.load(B, ldb, m, n, b0 * RB, vec_ok != 0);
-    load_v(b0 * RB);
-    load_tile(b0 * RB);
+  for (int q = 0; q < Q; ++q) {
+    const int64_t c = lane + 64 * q;
+    vl[q] = (c < n) ? (TB)(vj[m + c] * inv) : TB(0);
+    creg[q] = 0;
   }
-  for (int64_t rb = b0; rb < b1; ++rb) {
-    const int64_t i0 = rb * RB;
-    __syncthreads();
-    blk.store(B, ldb, m, n, i0, Ms);
-    const double vold = pre_v;
-    __syncthreads();
-    if (rb + 1 < b1) {
-      blk.load(B, ldb, m, n, i0 + RB, vec_ok != 0);
-      load_v(i0 + RB);
+  const int nt = (j + 1) * PR;         // (row, Krylov column) slots of one panel
+  const int kr = lane & (PR - 1);      // this lane's panel row in the dot slots
+  double hacc[TM];
+#pragma unroll
+  for (int t = 0; t < TM; ++t) hacc[t] = 0.0;
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  int64_t p0, p1;
+  row_range(npan, (int)nw, blockIdx.x * 4 + wave, p0, p1);
+  vec_t cur[Q];
+  double vro[PR], vt[TM];
+  auto load = [&](int64_t p, vec_t* dst, double* vr_, double* vt_) {
+    const TB* base = Bp + p * (PR * n);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t c = lane + 64 * q;
+      dst[q] = (c < n) ? *reinterpret_cast<const vec_t*>(base + c * PR) : vec_t{};
     }
-    const TB q = rows_times_vec<TB, RB>(Ms, vs, n, red);
-    if (threadIdx.x < RB) {
-      const int64_t i = i0 + threadIdx.x;
-      TB vr = 0;
-      double wr = 0.0;
-      if (i < m) {
-        const double vn = vold * inv;
-        vj[i] = vn;
-        vr = (TB)vn;
-        wr = (double)(vr + q);
-        w[i] = wr;
+    const int64_t i0 = p * PR;
+#pragma unroll
+    for (int k = 0; k < PR; ++k) vr_[k] = (i0 + k < m) ? vj[i0 + k] : 0.0;
+    const int64_t i = i0 + kr;
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      const int sl = lane + 64 * t;
+      const int c = sl / PR;
+      vt_[t] = (sl < nt && c < j && i < m) ? F.V[i + (int64_t)c * F.ldv] : 0.0;
+    }
+  };
+  if (p0 < p1) load(p0, cur, vro, vt);
+  for (int64_t p = p0; p < p1; ++p) {
+    vec_t nxt[Q];
+    double vrn[PR], vtn[TM];
+    if (p + 1 < p1) load(p + 1, nxt, vrn, vtn);
+    const int64_t i0 = p * PR;
+    double vr[PR];
+    TB vrt[PR], s[PR];
+#pragma unroll
+    for (int k = 0; k < PR; ++k) {
+      vr[k] = vro[k] * inv;
+      vrt[k] = (TB)vr[k];
+      s[k] = 0;
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int k = 0; k < PR; ++k) s[k] += cur[q][k] * vl[q];
+    double wr[PR];
+#pragma unroll
+    for (int k = 0; k < PR; ++k) {
+      const TB sk = wave_allsum(s[k]);
+      wr[k] = (i0 + k < m) ? (double)(vrt[k] + sk) : 0.0;
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < PR; ++k)
+        if (i0 + k < m) {
+          vj[i0 + k] = vr[k];
+          w[i0 + k] = wr[k];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int k = 0; k < PR; ++k) creg[q] += cur[q][k] * vrt[k];
+    double wk = wr[0], vk = vr[0];
+#pragma unroll
+    for (int k = 1; k < PR; ++k)
+      if (kr == k) {
+        wk = wr[k];
+        vk = vr[k];
       }
-      uu[threadIdx.x] = vr;
-      wv[threadIdx.x] = wr;
-    }
-    __syncthreads();
-    // h1 (r part) from the prefetched tile, then start loading the next tile
 #pragma unroll
-    for (int q = 0; q < kMaxTile; ++q) {
-      const int idx = threadIdx.x + q * kThreads;
-      const int c = idx / RB;
-      double prod = (idx < ntile) ? vt[q] * wv[idx % RB] * ((c == j) ? inv : 1.0) : 0.0;
-#pragma unroll
-      for (int off = RB / 2; off > 0; off >>= 1) prod += __shfl_xor(prod, off, 64);
-      if (idx < ntile && (idx % RB) == 0) hacc[c] += prod;
+    for (int t = 0; t < TM; ++t) {
+      const int sl = lane + 64 * t;
+      const int c = sl / PR;
+      hacc[t] += ((c == j) ? vk : vt[t]) * ((sl < nt) ? wk : 0.0);
     }
-    if (rb + 1 < b1) load_tile(i0 + RB);
-    for (int c = threadIdx.x; c < n; c += kThreads) {
-      TB acc = 0;
-#pragma unroll 8
-      for (int rw = 0; rw < RB; ++rw) acc += Ms[c * LDR + rw] * uu[rw];
-      tacc[c] += acc;
+    if (p + 1 < p1) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) cur[q] = nxt[q];
+#pragma unroll
+      for (int k = 0; k < PR; ++k) vro[k] = vrn[k];
+#pragma unroll
+      for (int t = 0; t < TM; ++t) vt[t] = vtn[t];
     }
   }
-  __syncthreads();
-  for (int c = threadIdx.x; c < n; c += kThreads) tpart[(int64_t)c * gridDim.x + blockIdx.x] = tacc[c];
-  for (int c = threadIdx.x; c <= j; c += kThreads) hpart[(int64_t)c * gridDim.x + blockIdx.x] = hacc[c];
+  // dot slots: sum the PR lanes of each Krylov column
+#pragma unroll
+  for (int t = 0; t < TM; ++t)
+#pragma unroll
+    for (int off = 1; off < PR; off <<= 1) hacc[t] += __shfl_xor(hacc[t], off, 64);
+  for (int wv = 0; wv < 4; ++wv) {
+    if (wave == wv) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) cred[lane + 64 * q] = (wv ? cred[lane + 64 * q] : TB(0)) + creg[q];
+      if (kr == 0) {
+#pragma unroll
+        for (int t = 0; t < TM; ++t) {
+          const int sl = lane + 64 * t;
+          if (sl < nt) hred[sl / PR] = (wv ? hred[sl / PR] : 0.0) + hacc[t];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int64_t c = threadIdx.x; c < n; c += kThreads) tpart[c * gridDim.x + blockIdx.x] = cred[c];
+  for (int c = threadIdx.x; c <= j; c += kThreads) hpart[(int64_t)c * gridDim.x + blockIdx.x] = hred[c];
 }
 
 // Blocks < ncb (16 columns each, one wave per column): w_x = B^T v_r from the
@@ -1034,33 +1085,26 @@ __global__ __launch_bounds__(kThreads) void k_fg_update(FgPtrs F, int64_t m, int
 
 // dx = W dz (R^-1 on the x part of the correction), x += dx (TU); partial norms.
 template <typename TU>
-__global__ __launch_bounds__(kThreads) void k_fg_dx(const double* __restrict__ W, int64_t n,
-                                                    const double* __restrict__ dz, double* __restrict__ x,
-                                                    double* __restrict__ part) {
-  __shared__ double red[16][17];
-  __shared__ double dsh[8];
-  const int r = threadIdx.x & 15, cg = threadIdx.x >> 4;
-  const int64_t row = (int64_t)blockIdx.x * 16 + r;
-  double acc = 0.0;
-  if (row < n)
-    for (int64_t j = row + cg; j < n; j += 16) acc += W[row + j * n] * dz[j];
-  red[cg][r] = acc;
-  __syncthreads();
+__global__ __launch_bounds__(kUtThreads) void k_fg_dx(const double* __restrict__ W, int64_t n,
+                                                      const double* __restrict__ dz, double* __restrict__ x,
+                                                      double* __restrict__ part) {
+  __shared__ double red[32 * 33];
+  const double d = ls_utmv_row(W, n, n, [&](int64_t j) { return dz[j]; }, red);
+  const int64_t row = (int64_t)blockIdx.x * 32 + threadIdx.x;
   double a0 = 0.0, a1 = 0.0;
-  if (cg == 0 && row < n) {
-    double d = 0.0;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) d += red[q][r];
+  if (threadIdx.x < 32 && row < n) {
     const double xn = (double)((TU)x[row] + (TU)d);
     x[row] = xn;
     a0 = d * d;
     a1 = xn * xn;
   }
-  a0 = block_sum256(a0, dsh);
-  a1 = block_sum256(a1, dsh + 4);
-  if (threadIdx.x == 0) {
-    part[2 * (int64_t)blockIdx.x] = a0;
-    part[2 * (int64_t)blockIdx.x + 1] = a1;
+  if (threadIdx.x < 64) {   // rows of the block live in the first wave
+    a0 = ls_wave_sum(a0);
+    a1 = ls_wave_sum(a1);
+    if (threadIdx.x == 0) {
+      part[2 * (int64_t)blockIdx.x] = a0;
+      part[2 * (int64_t)blockIdx.x + 1] = a1;
+    }
   }
 }
 
@@ -1096,17 +1140,44 @@ bool vec_aligned(const void* M, int64_t ld, size_t elt) {
   return ((uintptr_t)M % 16 == 0) && (ld % (int64_t)v == 0);
 }
 
-template <typename T>
-size_t pass_lds(int64_t n, int rb, int extra_doubles) {
-  return ((size_t)n * (rb + 1) + 2 * (size_t)n + rb + kThreads) * sizeof(T) + 8 * ((size_t)extra_doubles + 8) + 16;
-}
-
 int pass_grid(int64_t m, int rb, int ncu) {
   const int64_t nrb = ls_cdiv(m, rb);
   int64_t G = 2 * (int64_t)ncu;
   if (G > nrb) G = nrb;
   if (G < 1) G = 1;
   return (int)G;
+}
+
+// Loads per lane for one panel: the smallest power of two with 64 Q >= n.
+int pan_q(int64_t n) {
+  int q = 1;
+  while (64 * (int64_t)q < n) q *= 2;
+  return q;
+}
+
+int64_t pan_count(int64_t m, size_t elt) { return ls_cdiv(m, (int64_t)(16 / elt)); }
+
+// Resident waves per SIMD targeted by the panel passes (LS_PASS_WAVES, 1..8).
+int pan_occ() {
+  static int occ = 0;
+  if (occ == 0) {
+    occ = 2;
+    if (const char* e = getenv("LS_PASS_WAVES")) {
+      const int v = atoi(e);
+      if (v >= 1 && v <= 8) occ = v;
+    }
+  }
+  return occ;
+}
+
+// Blocks of four waves for a pass over npan panels: at most pan_occ() waves
+// per SIMD, every wave given the same number of panels (k or k - 1).
+int pan_grid(int64_t npan, int ncu) {
+  const int64_t nwmax = (int64_t)pan_occ() * 4 * ncu;
+  const int64_t k = ls_cdiv(npan, nwmax);
+  const int64_t nw = ls_cdiv(npan, k);
+  const int64_t g = ls_cdiv(nw, 4);
+  return (int)(g < 1 ? 1 : g);
 }
 
 }  // namespace
@@ -1129,24 +1200,25 @@ int form_b(const ls_problem_t* P, const double* W, const float* W32, ls_prec_t t
   if (tb == LS_FP32) {
     if (P->store == LS_FP32)
       hipLaunchKernelGGL((k_form_b<float, float>), g, dim3(kThreads), 0, st, (const float*)P->A, P->lda, P->m, P->n,
-                         W32, (float*)Bout, P->m);
+                         W32, (float*)Bout);
     else
       hipLaunchKernelGGL((k_form_b<double, float>), g, dim3(kThreads), 0, st, (const double*)P->A, P->lda, P->m, P->n,
-                         W32, (float*)Bout, P->m);
+                         W32, (float*)Bout);
   } else {
     if (P->store == LS_FP32)
       hipLaunchKernelGGL((k_form_b<float, double>), g, dim3(kThreads), 0, st, (const float*)P->A, P->lda, P->m, P->n,
-                         W, (double*)Bout, P->m);
+                         W, (double*)Bout);
     else
       hipLaunchKernelGGL((k_form_b<double, double>), g, dim3(kThreads), 0, st, (const double*)P->A, P->lda, P->m,
-                         P->n, W, (double*)Bout, P->m);
+                         P->n, W, (double*)Bout);
   }
   LS_HIP_TRY(hipGetLastError());
   return LS_OK;
 }
 
 size_t b_bytes(const ls_problem_t* P, ls_prec_t tb) {
-  return ls_align256((size_t)P->m * P->n * (tb == LS_FP32 ? 4 : 8));
+  const size_t elt = (tb == LS_FP32) ? 4 : 8;
+  return ls_align256((size_t)pan_count(P->m, elt) * (16 / elt) * P->n * elt);
 }
 
 // ================================================================== LSQR driver
@@ -1188,14 +1260,22 @@ LsqrWs lsqr_carve(char* ws, const ls_problem_t* P, size_t elt, int G, int Gv) {
   return w;
 }
 
+template <typename T, int Q>
+void lsqr_pan_launch(int G, hipStream_t st, const T* Bm, int64_t npan, int64_t m, int64_t n, const T* v,
+                     const double* nvp, int Gv, T* u, const LsqrState* S, int par, int init, T* tpart,
+                     double* nupart, double* nbpart) {
+  hipLaunchKernelGGL((k_lsqr_pan<T, Q>), dim3(G), dim3(kThreads), 0, st, Bm, npan, m, n, v, nvp, Gv, u, S, par, init,
+                     tpart, nupart, nbpart);
+}
+
 template <typename T>
 int lsqr_typed(const ls_problem_t* P, const double* R, int64_t ldr, const double* W, const T* Bm, double* x,
                const ls_iter_opts_t* io, ls_stats_t* stats, char* ws, size_t ws_bytes, hipStream_t st) {
   const int64_t m = P->m, n = P->n;
-  const int rb = pick_rb(n, sizeof(T), 0);
-  if (rb == 0) return LS_E_UNSUPPORTED;
+  if (n > 64 * kMaxPanQ) return LS_E_UNSUPPORTED;
   const int ncu = device_cu_count();
-  const int G = pass_grid(m, rb, ncu);
+  const int64_t npan = pan_count(m, sizeof(T));
+  const int G = pan_grid(npan, ncu);
   const int Gv = (int)ls_cdiv(n, 4);
   LsqrWs w = lsqr_carve(ws, P, sizeof(T), G, Gv);
   if (w.bytes > ws_bytes) return LS_E_WORKSPACE;
@@ -1203,20 +1283,18 @@ int lsqr_typed(const ls_problem_t* P, const double* R, int64_t ldr, const double
   T* u = reinterpret_cast<T*>(w.u);
   T* wv = reinterpret_cast<T*>(w.w);
   T* tpart = reinterpret_cast<T*>(w.tpart);
-  const int vec_ok = vec_aligned(Bm, m, sizeof(T)) ? 1 : 0;
-  const size_t lds = pass_lds<T>(n, rb, 0);
-  if (lds > device_lds_limit()) return LS_E_UNSUPPORTED;
+  const int q = pan_q(n);
   const int maxit = io->lsqr_maxit;
   const double tol = io->lsqr_tol;
   const int check = io->check_every > 0 ? io->check_every : 8;
   const dim3 gcol((unsigned)Gv);
-  const dim3 gn((unsigned)ls_cdiv(n, 16));
+  const dim3 gut((unsigned)ls_cdiv(n, 32));
 
   hipLaunchKernelGGL(k_zero_bytes, dim3(4), dim3(kThreads), 0, st, reinterpret_cast<char*>(w.st), sizeof(LsqrState));
   hipLaunchKernelGGL(k_zero_bytes, dim3(4), dim3(kThreads), 0, st, reinterpret_cast<char*>(w.y), 8 * (size_t)n);
   hipLaunchKernelGGL(k_zero_bytes, dim3(4), dim3(kThreads), 0, st, w.w, sizeof(T) * (size_t)n);
   // z0 = R x0 (so that A x0 = B z0), v <- -z0, u <- b
-  hipLaunchKernelGGL((k_trmv<double, double>), gn, dim3(kThreads), 0, st, R, ldr, n, x, (const double*)nullptr, w.z0);
+  hipLaunchKernelGGL(k_trmv, gut, dim3(kUtThreads), 0, st, R, ldr, n, x, w.z0);
   hipLaunchKernelGGL((k_cast<T, double>), dim3((unsigned)ls_cdiv(n, kThreads)), dim3(kThreads), 0, st, w.z0, v, n,
                      T(-1));
   if (P->store == LS_FP32)
@@ -1227,20 +1305,17 @@ int lsqr_typed(const ls_problem_t* P, const double* R, int64_t ldr, const double
                        (const double*)P->b, u, m, T(1));
   auto pass = [&](int par, int init, const double* nvp) {
     prof_begin(kProfLsqrPass, st);
-    switch (rb) {
-      case 32:
-        hipLaunchKernelGGL((k_lsqr_pass<T, 32>), dim3(G), dim3(kThreads), lds, st, Bm, m, m, n, vec_ok, v, nvp, Gv, u,
-                           w.st, par, init, tpart, w.nupart, w.nbpart);
-        break;
-      case 16:
-        hipLaunchKernelGGL((k_lsqr_pass<T, 16>), dim3(G), dim3(kThreads), lds, st, Bm, m, m, n, vec_ok, v, nvp, Gv, u,
-                           w.st, par, init, tpart, w.nupart, w.nbpart);
-        break;
-      default:
-        hipLaunchKernelGGL((k_lsqr_pass<T, 8>), dim3(G), dim3(kThreads), lds, st, Bm, m, m, n, vec_ok, v, nvp, Gv, u,
-                           w.st, par, init, tpart, w.nupart, w.nbpart);
-        break;
+#define LS_LSQR_PAN(QQ)                                                                                        \
+  lsqr_pan_launch<T, QQ>(G, st, Bm, npan, m, n, v, nvp, Gv, u, w.st, par, init, tpart, w.nupart, w.nbpart); \
+  break
+    switch (q) {
+      case 1: LS_LSQR_PAN(1);
+      case 2: LS_LSQR_PAN(2);
+      case 4: LS_LSQR_PAN(4);
+      case 8: LS_LSQR_PAN(8);
+      default: LS_LSQR_PAN(16);
     }
+#undef LS_LSQR_PAN
     // B once, u read and written, v read, t written
     prof_end(kProfLsqrPass, st, (double)m * n * sizeof(T) + 2.0 * m * sizeof(T) + 2.0 * n * sizeof(T));
   };
@@ -1267,7 +1342,7 @@ int lsqr_typed(const ls_problem_t* P, const double* R, int64_t ldr, const double
   }
   const int last = it - 1;                 // last column kernel launched
   const int fpar = (last + 1) & 1;         // rec written by it
-  hipLaunchKernelGGL(k_lsqr_finish<T>, dim3((unsigned)ls_cdiv(n, 16)), dim3(kThreads), 0, st, W, n, w.z0, w.y,
+  hipLaunchKernelGGL(k_lsqr_finish<T>, gut, dim3(kUtThreads), 0, st, W, n, w.z0, w.y,
                      w.nvpart[cur], Gv, w.st, fpar, last, x);
   LsqrState S;
   LS_HIP_TRY(hipMemcpyAsync(&S, w.st, sizeof(LsqrState), hipMemcpyDeviceToHost, st));
@@ -1287,9 +1362,7 @@ int lsqr_typed(const ls_problem_t* P, const double* R, int64_t ldr, const double
 
 size_t lsqr_workspace(const ls_problem_t* P, ls_prec_t u, int ncu) {
   const size_t elt = (u == LS_FP32) ? 4 : 8;
-  int rb = pick_rb(P->n, elt, 0);
-  if (rb == 0) rb = 8;
-  return lsqr_carve(nullptr, P, elt, pass_grid(P->m, rb, ncu), (int)ls_cdiv(P->n, 4)).bytes;
+  return lsqr_carve(nullptr, P, elt, pan_grid(pan_count(P->m, elt), ncu), (int)ls_cdiv(P->n, 4)).bytes;
 }
 
 int lsqr_device(const ls_problem_t* P, const double* R, int64_t ldr, const double* W, const void* Bm, ls_prec_t u,
@@ -1326,23 +1399,30 @@ struct LsirWs {
 };
 
 struct LsirDims {
-  int kmax, rbp, rbr, G, Gr, Gc, Gd, Gh, Gn;
+  int kmax, rbr, G, Gr, Gc, Gd, Gh, Gn;
+  int64_t npan;   // panels of B
 };
+
+template <typename TB, int Q>
+void fg_pan_launch(int G, hipStream_t st, const TB* Bm, int64_t npan, int64_t m, int64_t n, const FgPtrs& F, int j,
+                   int kmax, const double* w2part, int Gw, double tol, int final_step, TB* tpart, double* hpart) {
+  hipLaunchKernelGGL((k_fg_pan<TB, Q>), dim3(G), dim3(kThreads), 0, st, Bm, npan, m, n, F, j, kmax, w2part, Gw, tol,
+                     final_step, tpart, hpart);
+}
 
 LsirDims lsir_dims(const ls_problem_t* P, size_t tb_elt, size_t ta_elt, int fgmres_maxit, int ncu) {
   LsirDims d{};
   d.kmax = fgmres_maxit;
-  d.rbp = pick_rb(P->n, tb_elt, 8 * (size_t)(fgmres_maxit + 40));
   const size_t resid_extra = 8 * (3 * (size_t)P->n + 2 * kThreads + 64);
   d.rbr = pick_rb(P->n, ta_elt, resid_extra > 2 * (size_t)P->n * ta_elt ? resid_extra - 2 * (size_t)P->n * ta_elt : 0);
-  if (d.rbp == 0) d.rbp = 8;
   if (d.rbr == 0) d.rbr = 8;
-  d.G = pass_grid(P->m, d.rbp, ncu);
+  d.npan = pan_count(P->m, tb_elt);
+  d.G = pan_grid(d.npan, ncu);
   d.Gr = pass_grid(P->m, d.rbr, ncu);
   d.Gc = (int)ls_cdiv(P->n, 16);
   d.Gd = (int)ls_cdiv(P->m + P->n, kThreads);
   d.Gh = (int)ls_cdiv(P->n, 4);
-  d.Gn = (int)ls_cdiv(P->n, 16);
+  d.Gn = (int)ls_cdiv(P->n, 32);
   return d;
 }
 
@@ -1388,26 +1468,39 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
   const int64_t m = P->m, n = P->n;
   const int ncu = device_cu_count();
   const LsirDims d = lsir_dims(P, sizeof(TB), sizeof(TA), fg_maxit, ncu);
-  if (d.kmax > 95) return LS_E_ARG;
+  if (d.kmax > kMaxKrylov - 1) return LS_E_ARG;
+  if (n > 64 * kMaxPanQ) return LS_E_UNSUPPORTED;
   LsirWs w = lsir_carve(ws, P, d, sizeof(TB));
   if (w.bytes > ws_bytes) return LS_E_WORKSPACE;
   FgPtrs F{w.V, w.ldv, w.H, w.cs, w.sn, w.g, w.hj, w.st};
   const TA* A = static_cast<const TA*>(P->A);
   const TA* b = static_cast<const TA*>(P->b);
   const int vec_a = vec_aligned(A, P->lda, sizeof(TA)) ? 1 : 0;
-  const int vec_b = vec_aligned(Bm, m, sizeof(TB)) ? 1 : 0;
+  const int q = pan_q(n);
   TB* tpart = reinterpret_cast<TB*>(w.tpart);
   const int check = io->check_every > 0 ? io->check_every : 8;
   const double tol = io->fgmres_tol;
   const double lsir_tol = io->lsir_tol;
   const size_t lds_r = ((size_t)n * (d.rbr + 1)) * sizeof(TA) + 8 * (3 * (size_t)n + d.rbr + 2 * kThreads + 8) + 16;
-  const size_t lds_p = pass_lds<TB>(n, d.rbp, d.rbp + d.kmax + 2);
-  if (lds_r > device_lds_limit() || lds_p > device_lds_limit()) return LS_E_UNSUPPORTED;
+  if (lds_r > device_lds_limit()) return LS_E_UNSUPPORTED;
   const int ncb = (int)d.Gc;
 
   if (!r_given)
     hipLaunchKernelGGL((k_resid_u<TA, TU>), dim3((unsigned)ls_cdiv(m, kThreads)), dim3(kThreads), n * sizeof(TU), st, A,
                        P->lda, m, n, b, x, r);
+  auto fg_pass = [&](int j, int Gw, int final_step, int grid) {
+#define LS_FG_PAN(QQ)                                                                                               \
+  fg_pan_launch<TB, QQ>(grid, st, Bm, d.npan, m, n, F, j, d.kmax, w.w2part, Gw, tol, final_step, tpart, w.hpart); \
+  break
+    switch (q) {
+      case 1: LS_FG_PAN(1);
+      case 2: LS_FG_PAN(2);
+      case 4: LS_FG_PAN(4);
+      case 8: LS_FG_PAN(8);
+      default: LS_FG_PAN(16);
+    }
+#undef LS_FG_PAN
+  };
   int total_fg = 0, its = 0, status = LS_NOT_CONVERGED;
   double dx_rel = 0.0, dr_rel = 0.0;
   std::vector<double> up(2 * (size_t)(d.Gd + d.Gn));
@@ -1441,20 +1534,7 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
     for (; j < d.kmax; ++j) {
       const int Gw = (j == 0) ? d.Gr + d.Gh : d.Gd;
       prof_begin(kProfFgPass, st);
-      switch (d.rbp) {
-        case 32:
-          hipLaunchKernelGGL((k_fg_pass<TB, 32>), dim3(d.G), dim3(kThreads), lds_p, st, Bm, m, m, n, vec_b, F, j,
-                             d.kmax, w.w2part, Gw, tol, 0, tpart, w.hpart);
-          break;
-        case 16:
-          hipLaunchKernelGGL((k_fg_pass<TB, 16>), dim3(d.G), dim3(kThreads), lds_p, st, Bm, m, m, n, vec_b, F, j,
-                             d.kmax, w.w2part, Gw, tol, 0, tpart, w.hpart);
-          break;
-        default:
-          hipLaunchKernelGGL((k_fg_pass<TB, 8>), dim3(d.G), dim3(kThreads), lds_p, st, Bm, m, m, n, vec_b, F, j,
-                             d.kmax, w.w2part, Gw, tol, 0, tpart, w.hpart);
-          break;
-      }
+      fg_pass(j, Gw, 0, d.G);
       // B once, v_j read and written, w written, v_x read, t written, V_r(:, 0:j) for the fused dots
       prof_end(kProfFgPass, st,
                (double)m * n * sizeof(TB) + 24.0 * m + 8.0 * n + (double)n * sizeof(TB) + 8.0 * (j + 1) * m);
@@ -1474,10 +1554,9 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
       }
     }
     // final Givens step for the last column (no-op when already done)
-    hipLaunchKernelGGL((k_fg_pass<TB, 8>), dim3(1), dim3(kThreads), lds_p, st, Bm, m, m, n, vec_b, F,
-                       (j < d.kmax ? j + 1 : d.kmax), d.kmax, w.w2part, d.Gd, tol, 1, tpart, w.hpart);
+    fg_pass(j < d.kmax ? j + 1 : d.kmax, d.Gd, 1, 1);
     hipLaunchKernelGGL(k_fg_update<TU>, dim3((unsigned)d.Gd), dim3(kThreads), 0, st, F, m, n, d.kmax, r, w.dz, w.upart);
-    hipLaunchKernelGGL(k_fg_dx<TU>, dim3((unsigned)d.Gn), dim3(kThreads), 0, st, W, n, w.dz, x,
+    hipLaunchKernelGGL(k_fg_dx<TU>, dim3((unsigned)d.Gn), dim3(kUtThreads), 0, st, W, n, w.dz, x,
                        w.upart + 2 * (size_t)d.Gd);
     LS_HIP_TRY(hipMemcpyAsync(&S, w.st, sizeof(FgState), hipMemcpyDeviceToHost, st));
     LS_HIP_TRY(hipMemcpyAsync(up.data(), w.upart, 8 * 2 * (size_t)(d.Gd + d.Gn), hipMemcpyDeviceToHost, st));

@@ -169,10 +169,13 @@ def _oracle_R(P, s, seed):
     return Raug[:P.n, :P.n], oqr.sketch_and_solve(Raug)
 
 
+# shapes: 4-row binary32 / 2-row binary64 panels with and without a ragged last
+# panel, and n covering one to sixteen 64-column loads per lane
+@pytest.mark.parametrize("m,n", [(3000, 40), (3001, 40), (5003, 500), (1802, 700)])
 @pytest.mark.parametrize("store,u", [("f64", "f64"), ("f32", "f32"), ("f32", "f64")])
-def test_lsqr_iterates_match_oracle(L, store, u):
-    P = make_problem(3000, 40, 1e3, seed=15, store=store)
-    R, xs = _oracle_R(P, 160, 3)
+def test_lsqr_iterates_match_oracle(L, store, u, m, n):
+    P = make_problem(m, n, 1e3, seed=15, store=store)
+    R, xs = _oracle_R(P, max(160, 2 * n), 3)
     for k in (1, 5, 17):
         x = dev(xs.copy())
         rc, st = L.ls_lsqr_precond(dev(P.At), dev(P.b), dev(np.ascontiguousarray(R.T)), x, u=u,
@@ -198,10 +201,11 @@ def test_lsqr_converges_like_oracle(L):
 
 
 # ------------------------------------------------------------------ refinement
+@pytest.mark.parametrize("m,n", [(6000, 60), (6003, 60), (4001, 300)])
 @pytest.mark.parametrize("store,u,u_r,target", [("f64", "f64", "f64x2", 1e-13), ("f32", "f32", "f64", 6e-6)])
-def test_lsir_reaches_target_from_oracle_start(L, store, u, u_r, target):
-    P = make_problem(6000, 60, 1e4, seed=17, store=store)
-    R, xs = _oracle_R(P, 240, 6)
+def test_lsir_reaches_target_from_oracle_start(L, store, u, u_r, target, m, n):
+    P = make_problem(m, n, 1e4, seed=17, store=store)
+    R, xs = _oracle_R(P, 4 * n, 6)
     x0, _ = olsqr.lsqr_precond(P.At, P.b, R, xs, tol=1e-6, maxit=120)
     xr, rr, _ = refsolve.ref_solve(P.At, P.b)
     x = dev(x0.copy())
