@@ -1182,6 +1182,8 @@ int pan_grid(int64_t npan, int ncu) {
 
 }  // namespace
 
+int device_lds_bytes() { return (int)device_lds_limit(); }
+
 int device_cu_count() {
   static int cached = 0;
   if (cached == 0) {

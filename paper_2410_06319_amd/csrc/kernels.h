@@ -8,14 +8,18 @@ namespace ls {
 // ------------------------------------------------------------------ sketch
 struct SketchPlan {
   int64_t ncols;          // n + 1
-  int64_t s_pad;          // s rounded up to 64 (rows of S per block: 4 waves x 16)
+  int64_t s_pad;          // s rounded up to the rows of S per block
   int64_t n_pad;          // n + 1 rounded up to the column tile
   int64_t m_pad;          // rows of the packed operand (kchunk * nsplit)
   int64_t kchunk;         // rows of A per K-split
   int64_t nsplit;         // number of K-splits (partial sums combined in binary64)
-  int nb;                 // 16-column MFMA blocks per wave
+  int nb;                 // binary64 path: 16-column MFMA blocks per wave
   int kstep;              // rows of A per MFMA step
   int terms;
+  int64_t bn;             // bf16 path: columns per block
+  int64_t ns, nn;         // bf16 path: row tiles of S (128 rows), column tiles
+  int64_t nkb;            // bf16 path: K-blocks of 32 rows in the packed operand
+  int64_t kb_per_split;   // bf16 path: K-blocks per split
   size_t operand_bytes;   // packed [A b]
   size_t partial_bytes;   // per-split partial sketches
 };
@@ -63,6 +67,7 @@ int lsir_device(const ls_problem_t* P, const double* W, const void* Bm, const ls
 size_t lsir_workspace(const ls_problem_t* P, const ls_precs_t* pr, int fgmres_maxit, int ncu);
 
 int device_cu_count();
+int device_lds_bytes();   // LDS available to one block
 
 }  // namespace ls
 

@@ -1,13 +1,21 @@
 // Algorithm 1 step 1: the Gaussian sketch Y = Omega [A b] on gfx950.
 //
-// Omega = S / sqrt(s) is never stored: every wave regenerates the S entries
-// it multiplies from Philox4x32-10 (counter (i/4, k, prob, 0), key = seed)
-// directly in the MFMA A-operand layout.  [A b] is first packed into a
-// zero-padded operand of the sketch format ("A stored in precision u_s",
-// Algorithm 1's input); for bf16 it may be split into several bf16 terms
-// whose sum reproduces the binary32 data more closely.  Products run on
-// MFMA with binary32 (bf16 path) or binary64 (f64 path) accumulation over a
-// chunk of rows of A; the chunk partial sums are added in binary64.
+// Omega = S / sqrt(s) is never stored: S entries are regenerated from
+// Philox4x32-10 (counter (i/4, k, prob, 0), key = seed) where they are
+// multiplied.  [A b] is first packed into a zero-padded operand of the sketch
+// format ("A stored in precision u_s", Algorithm 1's input); for bf16 it may
+// be split into several bf16 terms whose sum reproduces the binary32 data more
+// closely.  Products run on MFMA with binary32 (bf16 path) or binary64 (f64
+// path) accumulation over a chunk of rows of A; the chunk partial sums are
+// added in binary64.
+//
+// bf16 path: a block of 8 waves owns 128 rows of S and BN columns of [A b].
+// Every K-step of 32 rows, the block generates its 128 x 32 tile of S once
+// (each Gaussian is drawn once per column tile) and stages the TERMS x BN x 32
+// operand tile, both in LDS; wave (wr, wc) multiplies rows 64 wr .. +64 by
+// columns wc BN/4 .. +BN/4.  LDS rows of 32 bf16 (four 16-byte quarters) are
+// stored with the quarter index XORed with bits 2..3 of the row, so that the
+// 16 lanes of each MFMA operand read hit distinct banks.
 #include "common.h"
 #include "kernels.h"
 
@@ -17,8 +25,12 @@ typedef double ls_doublex4 __attribute__((ext_vector_type(4)));
 typedef uint32_t ls_u32x4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ packing
-// Tt[t][j][i] (t < terms, j < n_pad, i < m_pad), bf16 bits: part t of
-// column j of [A b]; zero outside i < m, j <= n.
+// K-panel layout of the bf16 operand: for term t and K-block kb (rows
+// 32 kb .. 32 kb + 31 of [A b]) the n_pad columns follow each other with
+// their 32 values contiguous: element (i, j) of term t sits at
+// ((t nkb + i / 32) n_pad + j) 32 + i % 32, nkb = m_pad / 32.  Zero outside
+// i < m, j <= n.  The parts satisfy x = T_0 + T_1 + ... + rest, each T_t the
+// bf16 rounding of what is left (exact differences in binary32).
 __global__ __launch_bounds__(256) void k_pack_bf16(const float* __restrict__ A, int64_t lda,
                                                    const float* __restrict__ b, int64_t m, int64_t n,
                                                    int terms, uint16_t* __restrict__ Tt,
@@ -31,10 +43,11 @@ __global__ __launch_bounds__(256) void k_pack_bf16(const float* __restrict__ A, 
     if (j < n) x = A[i + j * lda];
     else if (j == n) x = b[i];
   }
-  const int64_t term_stride = m_pad * n_pad;
+  const int64_t nkb = m_pad / 32;
+  const int64_t pos = ((i >> 5) * n_pad + j) * 32 + (i & 31);
   for (int t = 0; t < terms; ++t) {
     const uint16_t h = ls_f32_to_bf16_bits(x);
-    Tt[t * term_stride + j * m_pad + i] = h;
+    Tt[t * nkb * n_pad * 32 + pos] = h;
     x = x - ls_bf16_bits_to_f32(h);   // exact (Sterbenz)
   }
 }
@@ -55,64 +68,144 @@ __global__ __launch_bounds__(256) void k_pack_f64(const TA* __restrict__ A, int6
 }
 
 // ------------------------------------------------------------------ bf16 MFMA sketch
-// Block: 4 waves; wave w owns S rows [64 bx + 16 w, +16) and all 16*NB
-// columns of the block's column tile.  One K-step is 32 rows of A.
 // v_mfma_f32_16x16x32_bf16 operands: lane l supplies row (l % 16) of S and
 // column (l % 16) of the packed operand, at the 8 consecutive K indices
-// 8 (l / 16) .. +7 of the step; the product sums over the same K set on
-// both sides.  Result: lane l holds D[4 (l/16) + r][l % 16], r < 4.
-template <int NB, int TERMS>
-__global__ __launch_bounds__(256) void k_sketch_bf16(const uint16_t* __restrict__ Tt, int64_t m_pad,
-                                                     int64_t n_pad, int64_t kchunk, uint32_t key0,
-                                                     uint32_t key1, uint32_t prob,
-                                                     float* __restrict__ Yp, int64_t s_pad) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const uint32_t srow = (uint32_t)(blockIdx.x * 64 + wave * 16 + (lane & 15));
-  const int64_t col0 = (int64_t)blockIdx.y * (16 * NB);
-  const int64_t kb0 = (int64_t)blockIdx.z * kchunk;
-  const int64_t kb1 = (kb0 + kchunk < m_pad) ? kb0 + kchunk : m_pad;
-  const int kq = (lane >> 4) * 8;
-  const int64_t term_stride = m_pad * n_pad;
-  const uint16_t* colp = Tt + (col0 + (lane & 15)) * m_pad + kq;
+// 8 (l / 16) .. +7 of the step (one 16-byte quarter); the product sums over
+// the same K set on both sides.  Result: lane l holds D[4 (l/16) + r][l % 16].
+constexpr int kSkThreads = 512;
+constexpr int kSkRows = 128;   // rows of S per block
 
-  ls_floatx4 acc[NB];
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb) acc[nb] = ls_floatx4{0.f, 0.f, 0.f, 0.f};
+// 16-byte slot of quarter q of LDS row r (rows of 32 bf16 = 4 quarters).
+__device__ __forceinline__ int sk_slot(int r, int q) { return r * 4 + (q ^ ((r >> 2) & 3)); }
 
-  for (int64_t k = kb0; k < kb1; k += 32) {
-    const uint32_t q = (uint32_t)((k + kq) >> 2);
+template <int BN, int TERMS>
+__global__ __launch_bounds__(kSkThreads) void k_sketch_bf16(const uint16_t* __restrict__ Tt, int64_t nkb,
+                                                            int64_t n_pad, int64_t kb_per_split, int ns,
+                                                            int nn, uint32_t key0, uint32_t key1,
+                                                            uint32_t prob, float* __restrict__ Yp,
+                                                            int64_t s_pad) {
+  constexpr int CT = BN / 64;                  // 16-column tiles per wave
+  // column tiles whose operand fragments are held in registers at once
+  constexpr int HALF = (TERMS >= 3 && CT >= 4) ? CT / 4 : (CT >= 2) ? CT / 2 : 1;
+  constexpr int BQ = TERMS * BN * 4;           // 16-byte quarters of the operand tile
+  constexpr int BPT = (BQ + kSkThreads - 1) / kSkThreads;
+  __shared__ ls_u32x4 As[kSkRows * 4];
+  __shared__ ls_u32x4 Bs[TERMS * BN * 4];
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wave = t >> 6;
+  const int wr = wave & 1, wc = wave >> 1;
+  // blocks of one (K-split, column tile) group run on one XCD (block b -> XCD b % 8)
+  const int b = blockIdx.x;
+  const int rest = b >> 3;
+  const int grp = (rest / ns) * 8 + (b & 7);
+  const int st = rest % ns;
+  const int z = grp / nn;
+  const int ntile = grp % nn;
+  const int64_t row0 = (int64_t)st * kSkRows;
+  const int64_t col0 = (int64_t)ntile * BN;
+  const int64_t kb0 = (int64_t)z * kb_per_split;
+  const int64_t kb1 = (kb0 + kb_per_split < nkb) ? kb0 + kb_per_split : nkb;
+
+  // S generation: thread t draws row t % 128, quarter t / 128 of the K-step
+  const int grow = t & (kSkRows - 1);
+  const int gq = t >> 7;
+  const uint32_t srow = (uint32_t)(row0 + grow);
+  auto gen = [&](int64_t kb) -> ls_u32x4 {
+    const uint32_t q = (uint32_t)((kb * 32 + 8 * gq) >> 2);
     uint32_t a0 = q, a1 = srow, a2 = prob, a3 = 0u;
     uint32_t c0 = q + 1u, c1 = srow, c2 = prob, c3 = 0u;
     ls_philox4x32_10(a0, a1, a2, a3, key0, key1);
     ls_philox4x32_10(c0, c1, c2, c3, key0, key1);
-    float z[8];
-    ls_box_muller_f32(a0, a1, z[0], z[1]);
-    ls_box_muller_f32(a2, a3, z[2], z[3]);
-    ls_box_muller_f32(c0, c1, z[4], z[5]);
-    ls_box_muller_f32(c2, c3, z[6], z[7]);
-    ls_u32x4 sw;
+    float zz[8];
+    ls_box_muller_f32(a0, a1, zz[0], zz[1]);
+    ls_box_muller_f32(a2, a3, zz[2], zz[3]);
+    ls_box_muller_f32(c0, c1, zz[4], zz[5]);
+    ls_box_muller_f32(c2, c3, zz[6], zz[7]);
+    ls_u32x4 w;
 #pragma unroll
     for (int p = 0; p < 4; ++p)
-      sw[p] = (uint32_t)ls_f32_to_bf16_bits(z[2 * p]) | ((uint32_t)ls_f32_to_bf16_bits(z[2 * p + 1]) << 16);
-    const ls_bf16x8 sfrag = __builtin_bit_cast(ls_bf16x8, sw);
+      w[p] = (uint32_t)ls_f32_to_bf16_bits(zz[2 * p]) | ((uint32_t)ls_f32_to_bf16_bits(zz[2 * p + 1]) << 16);
+    return w;
+  };
+  // operand tile: quarter p = t + 512 u is (term, column, quarter) = (p / (4 BN), (p / 4) % BN, p % 4)
+  const int64_t term_stride = nkb * n_pad * 32;
+  auto loadb = [&](int64_t kb, ls_u32x4 (&reg)[BPT]) {
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
+    for (int u = 0; u < BPT; ++u) {
+      const int p = t + kSkThreads * u;
+      if (p < BQ) {
+        const int term = p / (4 * BN);
+        const int c = (p >> 2) % BN;
+        const int q = p & 3;
+        reg[u] = *reinterpret_cast<const ls_u32x4*>(Tt + term * term_stride + (kb * n_pad + col0 + c) * 32 + 8 * q);
+      }
+    }
+  };
+  auto storeb = [&](const ls_u32x4 (&reg)[BPT]) {
 #pragma unroll
-      for (int t = 0; t < TERMS; ++t) {
-        const ls_u32x4 bw = *reinterpret_cast<const ls_u32x4*>(colp + t * term_stride + nb * 16 * m_pad + k);
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sfrag, __builtin_bit_cast(ls_bf16x8, bw),
-                                                           acc[nb], 0, 0, 0);
+    for (int u = 0; u < BPT; ++u) {
+      const int p = t + kSkThreads * u;
+      if (p < BQ) {
+        const int term = p / (4 * BN);
+        const int c = (p >> 2) % BN;
+        Bs[term * BN * 4 + sk_slot(c, p & 3)] = reg[u];
+      }
+    }
+  };
+
+  ls_floatx4 acc[4][CT];
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = ls_floatx4{0.f, 0.f, 0.f, 0.f};
+
+  ls_u32x4 sreg = ls_u32x4{0u, 0u, 0u, 0u};
+  ls_u32x4 breg[BPT];
+  if (kb0 < kb1) {
+    sreg = gen(kb0);
+    loadb(kb0, breg);
+  }
+  const int fq = lane >> 4;   // operand quarter of this lane
+  for (int64_t kb = kb0; kb < kb1; ++kb) {
+    __syncthreads();   // the previous step's operands have been read
+    As[sk_slot(grow, gq)] = sreg;
+    storeb(breg);
+    __syncthreads();
+    if (kb + 1 < kb1) {   // next step's operand loads in flight and its S drawn during the products
+      loadb(kb + 1, breg);
+      sreg = gen(kb + 1);
+    }
+#pragma unroll
+    for (int h = 0; h < CT; h += HALF) {
+      ls_bf16x8 bf[HALF][TERMS];
+#pragma unroll
+      for (int ct = 0; ct < HALF; ++ct) {
+        const int c = wc * (BN / 4) + (h + ct) * 16 + (lane & 15);
+#pragma unroll
+        for (int tm = 0; tm < TERMS; ++tm) bf[ct][tm] = __builtin_bit_cast(ls_bf16x8, Bs[tm * BN * 4 + sk_slot(c, fq)]);
+      }
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) {
+        const int r = wr * 64 + rt * 16 + (lane & 15);
+        const ls_bf16x8 af = __builtin_bit_cast(ls_bf16x8, As[sk_slot(r, fq)]);
+#pragma unroll
+        for (int ct = 0; ct < HALF; ++ct)
+#pragma unroll
+          for (int tm = 0; tm < TERMS; ++tm)
+            acc[rt][h + ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf[ct][tm], acc[rt][h + ct], 0, 0, 0);
       }
     }
   }
-  float* out = Yp + (int64_t)blockIdx.z * s_pad * n_pad;
-  const int64_t r0 = (int64_t)blockIdx.x * 64 + wave * 16 + 4 * (lane >> 4);
+  float* out = Yp + (int64_t)z * s_pad * n_pad;
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    const int64_t c = col0 + nb * 16 + (lane & 15);
+  for (int rt = 0; rt < 4; ++rt) {
+    const int64_t r = row0 + wr * 64 + rt * 16 + 4 * (lane >> 4);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) out[(r0 + r) + c * s_pad] = acc[nb][r];
+    for (int ct = 0; ct < CT; ++ct) {
+      const int64_t c = col0 + wc * (BN / 4) + ct * 16 + (lane & 15);
+      *reinterpret_cast<ls_floatx4*>(out + r + c * s_pad) = acc[rt][ct];
+    }
   }
 }
 
@@ -227,14 +320,33 @@ namespace ls {
 SketchPlan sketch_plan(int64_t m, int64_t n, int64_t s, ls_prec_t u_s, int terms) {
   SketchPlan p{};
   p.ncols = n + 1;
-  p.s_pad = ls_cdiv(s, 64) * 64;
+  p.terms = (u_s == LS_BF16) ? terms : 1;
   if (u_s == LS_BF16) {
-    p.nb = 16;
+    p.bn = (p.ncols <= 128) ? 128 : (p.ncols <= 256) ? 256 : 512;
+    p.nn = ls_cdiv(p.ncols, p.bn);
+    p.n_pad = p.nn * p.bn;
+    p.ns = ls_cdiv(s, kSkRows);
+    p.s_pad = p.ns * kSkRows;
     p.kstep = 32;
-  } else {
-    p.nb = 8;
-    p.kstep = 16;
+    // about one block per compute unit; (column tiles x K-splits) a multiple
+    // of 8 so that each XCD receives whole groups
+    const int64_t kbn = ls_cdiv(m, 32);
+    int64_t nsplit = ls_cdiv(device_cu_count(), p.ns * p.nn);
+    if (nsplit > kbn) nsplit = kbn;
+    if (nsplit < 1) nsplit = 1;
+    while ((p.nn * nsplit) % 8) ++nsplit;
+    p.kb_per_split = ls_cdiv(kbn, nsplit);
+    p.nsplit = nsplit;
+    p.nkb = p.kb_per_split * nsplit;
+    p.m_pad = p.nkb * 32;
+    p.kchunk = p.kb_per_split * 32;
+    p.operand_bytes = ls_align256((size_t)p.terms * p.m_pad * p.n_pad * 2);
+    p.partial_bytes = ls_align256((size_t)p.nsplit * p.s_pad * p.n_pad * 4);
+    return p;
   }
+  p.s_pad = ls_cdiv(s, 64) * 64;
+  p.nb = 8;
+  p.kstep = 16;
   p.n_pad = ls_cdiv(p.ncols, 16 * p.nb) * 16 * p.nb;
   // Split K so that the grid holds roughly 2 blocks per compute unit.
   const int64_t tiles = (p.s_pad / 64) * (p.n_pad / (16 * p.nb));
@@ -247,10 +359,8 @@ SketchPlan sketch_plan(int64_t m, int64_t n, int64_t s, ls_prec_t u_s, int terms
   p.nsplit = ls_cdiv(m, p.kchunk);
   if (p.nsplit < 1) p.nsplit = 1;
   p.m_pad = p.kchunk * p.nsplit;
-  p.terms = (u_s == LS_BF16) ? terms : 1;
-  const size_t elt = (u_s == LS_BF16) ? 2 : 8;
-  p.operand_bytes = ls_align256((size_t)p.terms * p.m_pad * p.n_pad * elt);
-  p.partial_bytes = ls_align256((size_t)p.nsplit * p.s_pad * p.n_pad * ((u_s == LS_BF16) ? 4 : 8));
+  p.operand_bytes = ls_align256((size_t)p.m_pad * p.n_pad * 8);
+  p.partial_bytes = ls_align256((size_t)p.nsplit * p.s_pad * p.n_pad * 8);
   return p;
 }
 
@@ -261,7 +371,7 @@ int sketch_run(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s,
   char* operand = ws;
   char* partial = ws + p.operand_bytes;
   const dim3 gpack((unsigned)ls_cdiv(p.m_pad, 256), (unsigned)p.n_pad);
-  const dim3 gsk((unsigned)(p.s_pad / 64), (unsigned)(p.n_pad / (16 * p.nb)), (unsigned)p.nsplit);
+  const dim3 gsk((unsigned)(p.s_pad / 64), (unsigned)(p.n_pad / (16 * p.nb ? 16 * p.nb : 1)), (unsigned)p.nsplit);
   const dim3 gcomb((unsigned)ls_cdiv(s, 256), (unsigned)p.ncols);
   const double scale = 1.0 / sqrt((double)s);
   if (u_s == LS_BF16) {
@@ -270,23 +380,22 @@ int sketch_run(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s,
     hipLaunchKernelGGL(k_pack_bf16, gpack, dim3(256), 0, st, (const float*)P->A, P->lda,
                        (const float*)P->b, P->m, P->n, p.terms, Tt, p.m_pad, p.n_pad);
     float* Yp = reinterpret_cast<float*>(partial);
+    const size_t lds = (size_t)(kSkRows * 4 + p.terms * p.bn * 4) * 16;
+    if (lds > (size_t)device_lds_bytes()) return LS_E_UNSUPPORTED;
+    const dim3 gb((unsigned)(p.ns * p.nn * p.nsplit));
     prof_begin(kProfSketch, st);
-    switch (p.terms) {
-      case 1:
-        hipLaunchKernelGGL((k_sketch_bf16<16, 1>), gsk, dim3(256), 0, st, Tt, p.m_pad, p.n_pad, p.kchunk,
-                           key0, key1, so->prob_id, Yp, p.s_pad);
-        break;
-      case 2:
-        hipLaunchKernelGGL((k_sketch_bf16<16, 2>), gsk, dim3(256), 0, st, Tt, p.m_pad, p.n_pad, p.kchunk,
-                           key0, key1, so->prob_id, Yp, p.s_pad);
-        break;
-      case 3:
-        hipLaunchKernelGGL((k_sketch_bf16<16, 3>), gsk, dim3(256), 0, st, Tt, p.m_pad, p.n_pad, p.kchunk,
-                           key0, key1, so->prob_id, Yp, p.s_pad);
-        break;
-      default:
-        return LS_E_ARG;
+#define LS_SK(BN_, T_)                                                                                       \
+  hipLaunchKernelGGL((k_sketch_bf16<BN_, T_>), gb, dim3(kSkThreads), 0, st, Tt, p.nkb, p.n_pad, p.kb_per_split, \
+                     (int)p.ns, (int)p.nn, key0, key1, so->prob_id, Yp, p.s_pad)
+    if (p.terms < 1 || p.terms > 3) return LS_E_ARG;
+    if (p.bn == 128) {
+      if (p.terms == 1) LS_SK(128, 1); else if (p.terms == 2) LS_SK(128, 2); else LS_SK(128, 3);
+    } else if (p.bn == 256) {
+      if (p.terms == 1) LS_SK(256, 1); else if (p.terms == 2) LS_SK(256, 2); else LS_SK(256, 3);
+    } else {
+      if (p.terms == 1) LS_SK(512, 1); else if (p.terms == 2) LS_SK(512, 2); else LS_SK(512, 3);
     }
+#undef LS_SK
     prof_end(kProfSketch, st, 2.0 * (double)s * (double)P->m * (double)(P->n + 1));
     hipLaunchKernelGGL(k_sketch_combine<float>, gcomb, dim3(256), 0, st, Yp, p.s_pad, p.n_pad,
                        (int)p.nsplit, s, p.ncols, scale, Y, ldy);
