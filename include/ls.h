@@ -155,7 +155,8 @@ int ls_sketch(const ls_problem_t *P, const ls_sketch_opts_t *so, ls_prec_t u_s,
               double *Y, int64_t ldy, void *ws, size_t ws_bytes, void *stream);
 
 /* Algorithm 1 step 2: economic Householder QR of Y (s x ncols, binary64,
- * device, overwritten) in precision u_qr, returning only R: ncols x ncols
+ * device, left unchanged: the factorisation runs on a copy in the workspace)
+ * in precision u_qr, returning only R: ncols x ncols
  * upper triangular with positive diagonal, binary64, leading dimension
  * ldr (device; the strictly lower part is set to zero).  With Y = Omega[A b]
  * and ncols = n + 1, R[0:n, 0:n] is the preconditioner and R[0:n, n] is

@@ -4,19 +4,28 @@
 // Blocked right-looking Householder QR (compact WY, LAPACK's forward
 // column-wise convention H = I - V T V^T):
 //   * a panel of NB columns is factored by one 1024-thread block that keeps
-//     the panel in registers (RPT rows per thread) and builds T on the fly;
-//   * the trailing columns are updated as C <- C - V (T^T (V^T C)) by two
-//     grid-wide kernels (partial V^T C over row chunks, then the update).
+//     the panel in registers (RPT rows per thread) and builds T on the fly,
+//     with one block-wide reduction per column;
+//   * trailing columns are updated as C <- C - V (T^T (V^T C)) on MFMA, 16
+//     columns per block;
+//   * one launch per panel with look-ahead: while block 0 updates and
+//     factors the next panel, the other blocks update the rest.
 // Reflectors follow the usual choice beta = -sign(x_1) ||x||; at the end
 // the rows of R are multiplied by the signs of its diagonal so diag(R) > 0.
+#include <type_traits>
+#include <utility>
+
 #include "common.h"
 #include "kernels.h"
 
+typedef float ls_qr_f4 __attribute__((ext_vector_type(4)));
+typedef double ls_qr_d4 __attribute__((ext_vector_type(4)));
+typedef double ls_qr_d2 __attribute__((ext_vector_type(2)));
+
 namespace {
 
-constexpr int kQrThreads = 1024;
-constexpr int kColBlock = 32;
-constexpr int kRowChunk = 256;
+constexpr int kQrThreads = 512;      // block size of the QR kernels
+constexpr int kPanelThreads = 256;   // threads that hold the panel (the other waves only join barriers)
 
 // Sum each of v[0..NB) over the 64 lanes of a wave with a transposed
 // butterfly: after it, the returned value is the full sum of index `idx`.
@@ -31,228 +40,470 @@ struct Log2<1> {
   static constexpr int value = 0;
 };
 
+// f(std::integral_constant<int, 0>{}), ..., f(std::integral_constant<int, N - 1>{}):
+// an unrolled loop whose index is a compile-time constant in every copy.
+template <typename F, int... C>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, C...>) {
+  (f(std::integral_constant<int, C>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Cross-lane moves within a wave without LDS.  v_permlane32_swap(x, y)
+// returns {x on lanes 0..31 with y's lanes 0..31 on lanes 32..63, x's lanes
+// 32..63 on lanes 0..31 with y on lanes 32..63}; v_permlane16_swap does the
+// same for the 16-lane halves of each 32-lane half.  DPP row_ror:8 reads lane
+// l ^ 8, row_half_mirror lane l ^ 7, quad_perm [2,3,0,1] and [1,0,3,2] lanes
+// l ^ 2 and l ^ 1 (all within rows of 16 lanes).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f(double x) {
+  const long long u = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffll), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+// r0 + r1 of the 32- or 16-lane swap of (a, b): on lanes with the bit clear
+// a summed with its partner's a, on the others b summed with its partner's b.
+template <int BIT>
+__device__ __forceinline__ float swap_add(float a, float b) {
+  const unsigned int ua = __builtin_bit_cast(unsigned int, a), ub = __builtin_bit_cast(unsigned int, b);
+  const auto r = (BIT == 5) ? __builtin_amdgcn_permlane32_swap(ua, ub, false, false)
+                            : __builtin_amdgcn_permlane16_swap(ua, ub, false, false);
+  return __builtin_bit_cast(float, (unsigned int)r[0]) + __builtin_bit_cast(float, (unsigned int)r[1]);
+}
+template <int BIT>
+__device__ __forceinline__ double swap_add(double a, double b) {
+  const unsigned long long ua = __builtin_bit_cast(unsigned long long, a);
+  const unsigned long long ub = __builtin_bit_cast(unsigned long long, b);
+  const unsigned int alo = (unsigned int)ua, ahi = (unsigned int)(ua >> 32);
+  const unsigned int blo = (unsigned int)ub, bhi = (unsigned int)(ub >> 32);
+  const auto rl = (BIT == 5) ? __builtin_amdgcn_permlane32_swap(alo, blo, false, false)
+                             : __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+  const auto rh = (BIT == 5) ? __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false)
+                             : __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+  const double r0 = __builtin_bit_cast(double, ((unsigned long long)(unsigned int)rh[0] << 32) | (unsigned int)rl[0]);
+  const double r1 = __builtin_bit_cast(double, ((unsigned long long)(unsigned int)rh[1] << 32) | (unsigned int)rl[1]);
+  return r0 + r1;
+}
+// DPP control of the partner lane for a lane bit below 4 (xor 8, xor 7, xor 2, xor 1).
+template <int BIT>
+struct DppCtrl {
+  static constexpr int value = (BIT == 3) ? 0x128 : (BIT == 2) ? 0x141 : (BIT == 1) ? 0x4E : 0xB1;
+};
+
+// Sum each of v[0..NB) over the 64 lanes of a wave with a transposed
+// butterfly: the halving steps pair lanes that differ in bit 5, 4, 3, then
+// (through the 8-lane mirror) bit 2; the kept half follows the lane's bit,
+// so lane l ends with index idx = its bits 5.. as a binary number.  The
+// remaining low bits are plain sums.  Every pairing is an exchange between
+// the two lanes, so both see the same two addends.
 template <typename T, int NB>
 __device__ __forceinline__ T wave_multi_sum(T (&v)[NB], int lane, int& idx) {
   constexpr int L = Log2<NB>::value;
+  static_assert(L <= 4, "at most 16 values");
   int base = 0;
+  static_for<L>([&](auto stc) {
+    constexpr int step = decltype(stc)::value;
+    constexpr int bit = 5 - step;
+    constexpr int h = NB >> (step + 1);
+    const bool up = ((lane >> bit) & 1) != 0;
+    if constexpr (bit >= 4) {
 #pragma unroll
-  for (int step = 0; step < L; ++step) {
-    const int off = 32 >> step;
-    const int h = NB >> (step + 1);
-    const bool up = (lane & off) != 0;
-    // lane choice as an exact blend (factors 1 and 0): a select here would be
-    // folded into a run-time register index, which compiles to select chains
-    const T fu = up ? T(1) : T(0);
-    const T fl = T(1) - fu;
+      for (int q = 0; q < h; ++q) v[q] = swap_add<bit>(v[q], v[q + h]);
+    } else {
+      // exact blend (factors 1 and 0) rather than a select, which the compiler
+      // would turn into a run-time register index
+      const T fu = up ? T(1) : T(0);
+      const T fl = T(1) - fu;
 #pragma unroll
-    for (int q = 0; q < NB / 2; ++q) {
-      if (q < h) {
+      for (int q = 0; q < h; ++q) {
         const T send = v[q] * fu + v[q + h] * fl;
         const T keep = v[q + h] * fu + v[q] * fl;
-        v[q] = keep + __shfl_xor(send, off, 64);
+        v[q] = keep + dpp_f<DppCtrl<bit>::value>(send);
       }
     }
     if (up) base += h;
-  }
+  });
   T s = v[0];
-#pragma unroll
-  for (int off = 32 >> L; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+  static_for<6 - L>([&](auto stc) {
+    constexpr int bit = 5 - L - decltype(stc)::value;
+    if constexpr (bit >= 4) s = swap_add<bit>(s, s);
+    else s = s + dpp_f<DppCtrl<bit>::value>(s);
+  });
   idx = base;
   return s;
+}
+
+// Panel factorisation with one block reduction per column.  For column c
+// with x = its rows li >= c (x0 = row c), one reduction gives
+//   d[c] = sum_{li > c} x_li^2  and  d[q] = sum_{li > c} P(li, q) x_li  (q != c);
+// with row c of the panel broadcast through LDS this is everything the step
+// needs: beta = -sign(x0) sqrt(x0^2 + d[c]), tau = (beta - x0) / beta,
+// v = [1; x_{>c} / (x0 - beta)], and since v(li) = x_li scal below row c,
+//   v . y_b = y_b(c) + scal d[b]   (later columns b > c),
+//   v_a . v = v_a(c) + scal d[a]   (earlier reflectors a < c, for T).
+// The kPanelThreads panel threads hold RPT consecutive rows each (li =
+// RPT tid + r), read and written as 16-byte vectors; Y is the internal
+// working copy, whose leading dimension is a multiple of 4 with zero rows
+// between s and ldy.
+template <typename T>
+struct QrVec;
+template <>
+struct QrVec<float> {
+  using type = ls_qr_f4;
+  static constexpr int W = 4;
+};
+template <>
+struct QrVec<double> {
+  using type = ls_qr_d2;
+  static constexpr int W = 2;
+};
+
+__device__ __forceinline__ float qr_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double qr_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float qr_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double qr_rcp(double x) { return 1.0 / x; }
+
+template <typename T, int RPT, int NB>
+__device__ __forceinline__ void qr_panel_body(T* __restrict__ Y, int64_t ldy, int64_t s, int64_t j0, int nb,
+                                              T* __restrict__ tau, T* __restrict__ Tm) {
+  constexpr int PW = kPanelThreads / 64;
+  using vec_t = typename QrVec<T>::type;
+  constexpr int VW = QrVec<T>::W;
+  static_assert(RPT % VW == 0, "rows per thread must fill whole vectors");
+  __shared__ __align__(16) T red[2][PW][NB];   // wave partials, by column parity
+  __shared__ T rowc[2][NB];                    // row c of the panel, by column parity
+  __shared__ T Gs[NB][NB];                     // Gs[c][b] = v_b . v_c (b < c)
+  __shared__ T taus[NB];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  const bool act = tid < kPanelThreads;
+  constexpr int lowmask = 64 / NB - 1;
+  const int64_t i0 = j0 + (int64_t)RPT * tid;   // first row of this thread
+
+  T P[RPT][NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+#pragma unroll
+    for (int r = 0; r < RPT; r += VW) {
+      vec_t v{};
+      if (act && c < nb && i0 + r < ldy) v = *reinterpret_cast<const vec_t*>(Y + (i0 + r) + (j0 + c) * ldy);
+#pragma unroll
+      for (int e = 0; e < VW; ++e) P[r + e][c] = v[e];
+    }
+  }
+
+  static_for<NB>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    constexpr int cown = c / RPT, cslot = c % RPT;   // thread and slot holding row c
+    if (c < nb) {
+      const int par = c & 1;
+      if (act) {
+        T part[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) part[q] = 0;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+          const int li = RPT * tid + r;
+          if (li > c) {
+            const T x = P[r][c];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) part[q] += P[r][q] * x;
+          }
+        }
+        if (tid == cown) {
+#pragma unroll
+          for (int q = 0; q < NB; ++q) rowc[par][q] = P[cslot][q];
+        }
+        int idx;
+        const T wsum = wave_multi_sum<T, NB>(part, lane, idx);
+        if ((lane & lowmask) == 0) red[par][wv][idx] = wsum;
+      }
+      __syncthreads();
+      if (act) {
+        // every thread adds the wave partials itself (same order everywhere)
+        T dots[NB];
+#pragma unroll
+        for (int q = 0; q < NB; q += VW) {
+          vec_t acc = *reinterpret_cast<const vec_t*>(&red[par][0][q]);
+#pragma unroll
+          for (int w = 1; w < PW; ++w) acc += *reinterpret_cast<const vec_t*>(&red[par][w][q]);
+#pragma unroll
+          for (int e = 0; e < VW; ++e) dots[q + e] = acc[e];
+        }
+        const T ss = dots[c];
+        const T x0 = rowc[par][c];
+        T beta, tauc, scal;
+        if (ss == T(0)) {
+          tauc = 0;
+          beta = x0;
+          scal = 0;
+        } else {
+          const T nrm = qr_sqrt(x0 * x0 + ss);
+          beta = (x0 >= T(0)) ? -nrm : nrm;
+          tauc = (beta - x0) * qr_rcp(beta);
+          scal = qr_rcp(x0 - beta);
+        }
+        // inner products with the earlier reflectors, for T after the loop
+        if (tid < c) {
+          T dt = red[par][0][tid];
+#pragma unroll
+          for (int w = 1; w < PW; ++w) dt += red[par][w][tid];
+          Gs[c][tid] = rowc[par][tid] + scal * dt;
+        }
+        if (tid == 0) {
+          tau[j0 + c] = tauc;
+          taus[c] = tauc;
+        }
+        // v_c in place of x, then H_c applied to the later panel columns
+        T coef[NB];
+#pragma unroll
+        for (int bq = c + 1; bq < NB; ++bq) coef[bq] = tauc * (rowc[par][bq] + scal * dots[bq]);
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+          const int li = RPT * tid + r;
+          if (li > c) P[r][c] *= scal;
+          if (li >= c) {
+            const T vc = (li == c) ? T(1) : P[r][c];
+#pragma unroll
+            for (int bq = c + 1; bq < NB; ++bq) P[r][bq] -= coef[bq] * vc;
+          }
+        }
+        if (tid == cown) P[cslot][c] = beta;
+      }
+    }
+  });
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      if (c < nb) {
+#pragma unroll
+        for (int r = 0; r < RPT; r += VW) {
+          if (i0 + r < ldy) {
+            vec_t v;
+#pragma unroll
+            for (int e = 0; e < VW; ++e) v[e] = P[r + e][c];
+            *reinterpret_cast<vec_t*>(Y + (i0 + r) + (j0 + c) * ldy) = v;
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // T (upper triangular, H_0 ... H_{nb-1} = I - V T V^T): lane a of wave 0
+  // computes row a, T(a, a) = tau_a and, for c > a,
+  // T(a, c) = -tau_c sum_{b = a}^{c-1} T(a, b) (v_b . v_c); row a needs only itself.
+  if (tid < NB) {
+    const int a = tid;
+    T row[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      T v = 0;
+      if (c < nb && a < nb) {
+        if (c == a) {
+          v = taus[c];
+        } else if (c > a) {
+          T acc = 0;
+#pragma unroll
+          for (int bq = 0; bq < NB; ++bq)
+            if (bq >= a && bq < c) acc += row[bq] * Gs[c][bq];
+          v = -taus[c] * acc;
+        }
+      }
+      row[c] = v;
+    }
+#pragma unroll
+    for (int c = 0; c < NB; ++c) Tm[a + c * NB] = row[c];
+  }
 }
 
 template <typename T, int RPT, int NB>
 __global__ __launch_bounds__(kQrThreads) void k_qr_panel(T* __restrict__ Y, int64_t ldy, int64_t s, int64_t j0,
                                                           int nb, T* __restrict__ tau, T* __restrict__ Tm) {
-  __shared__ T red[kQrThreads / 64][NB];
-  __shared__ T dots[NB];
-  __shared__ T bsum[kQrThreads / 64];
-  __shared__ T x0s;
-  __shared__ T Ts[NB][NB];   // Ts[col][row] = T(row, col)
+  qr_panel_body<T, RPT, NB>(Y, ldy, s, j0, nb, tau, Tm);
+}
+
+__device__ __forceinline__ ls_qr_f4 qr_mfma(float a, float b, ls_qr_f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ ls_qr_d4 qr_mfma(double a, double b, ls_qr_d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// Row of the 16 x 16 MFMA result held in slot r of lane l (binary32 rows are
+// blocked, binary64 rows interleaved); the column is l % 16.
+template <typename T>
+__device__ __forceinline__ int qr_drow(int lane, int r) {
+  return (sizeof(T) == 4) ? 4 * (lane >> 4) + r : (lane >> 4) + 4 * r;
+}
+
+// Apply the nb0 reflectors of the panel starting at j0 (V unit lower
+// trapezoidal below row j0, T upper triangular, Tm[a + c NB] = T(a, c)) to the
+// cw <= 16 columns c0.. of Y: C <- C - V (T^T (V^T C)).  One block of
+// kQrThreads threads.  Rows j0 .. s - 1 are taken in chunks of kUpdRows: the
+// chunk's 16 columns of V and of C are read with 16-byte loads (the next
+// chunk's in flight during the products) and staged in LDS.  W = V^T C on
+// MFMA 16x16x4 (wave w sums rows 32 w .. 32 w + 31 of each chunk; the wave
+// partials are added in wave order); W2 = T^T W; then a second sweep over the
+// chunks computes V W2 (wave w: two 16-row tiles) and subtracts it from C.
+constexpr int kUpdRows = 256;
+
+template <typename T, int NB>
+__device__ __forceinline__ void qr_update16(T* __restrict__ Y, int64_t ldy, int64_t s, int64_t j0, int nb0,
+                                            const T* __restrict__ Tm, int64_t c0, int cw) {
+  using acc_t = typename std::conditional<sizeof(T) == 4, ls_qr_f4, ls_qr_d4>::type;
+  using vec_t = typename QrVec<T>::type;
+  constexpr int VW = QrVec<T>::W;
+  constexpr int QV = kUpdRows / VW;             // vectors per column segment
+  constexpr int PT = 32 * QV / kQrThreads;      // vectors per thread per chunk (16 V + 16 C columns)
+  static_assert(PT * kQrThreads == 32 * QV, "chunk vectors must divide among the threads");
+  __shared__ T Vs[kUpdRows][17];
+  __shared__ T Cs[kUpdRows][17];
+  __shared__ T part[kQrThreads / 64][16][17];
+  __shared__ T Ws[16][17];
+  __shared__ T W2s[16][17];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wv = tid >> 6;
-  constexpr int lowmask = 64 / NB - 1;
+  const int wave = tid >> 6;
+  const int cl = lane & 15;
+  const int64_t nch = ls_cdiv(s - j0, kUpdRows);
 
-  T P[RPT][NB];
+  // vector u of this thread: p = tid + kQrThreads u, column k = p / QV (k < 16:
+  // V column k, else C column k - 16), rows VW (p % QV) .. of the chunk
+  auto load = [&](int64_t r0, vec_t (&reg)[PT]) {
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    const int64_t i = j0 + tid + (int64_t)kQrThreads * r;
+    for (int u = 0; u < PT; ++u) {
+      const int p = tid + kQrThreads * u;
+      const int k = p / QV;
+      const int64_t i = r0 + VW * (p % QV);
+      const bool isv = k < 16;
+      const int64_t col = isv ? j0 + k : c0 + (k - 16);
+      const bool ok = (isv ? k < nb0 : (k - 16) < cw) && i < ldy;
+      reg[u] = ok ? *reinterpret_cast<const vec_t*>(Y + i + col * ldy) : vec_t{};
+    }
+  };
+  auto stage = [&](int64_t r0, const vec_t (&reg)[PT]) {
 #pragma unroll
-    for (int c = 0; c < NB; ++c) P[r][c] = (i < s && c < nb) ? Y[i + (j0 + c) * ldy] : T(0);
-  }
-
+    for (int u = 0; u < PT; ++u) {
+      const int p = tid + kQrThreads * u;
+      const int k = p / QV;
+      const int rl = VW * (p % QV);
 #pragma unroll
-  for (int c = 0; c < NB; ++c) {
-    if (c < nb) {
-      // ---- reflector for column c: x = rows li >= c of the column
-      T ss = 0;
-#pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        const int li = tid + kQrThreads * r;
-        if (li > c) ss += P[r][c] * P[r][c];
-      }
-      ss = ls_block_sum<T, kQrThreads>(ss, bsum);
-      if (tid == c) x0s = P[0][c];
-      __syncthreads();
-      const T x0 = x0s;
-      T beta, tauc, scal;
-      if (ss == T(0)) {
-        tauc = 0;
-        beta = x0;
-        scal = 0;
-      } else {
-        const T nrm = sqrt(x0 * x0 + ss);
-        beta = (x0 >= T(0)) ? -nrm : nrm;
-        tauc = (beta - x0) / beta;
-        scal = T(1) / (x0 - beta);
-      }
-#pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        const int li = tid + kQrThreads * r;
-        if (li > c) P[r][c] *= scal;
-      }
-      if (tid == c) P[0][c] = beta;
-
-      // ---- dots: v_a . v_c (a < c) and v_c . y_b (b > c), rows li >= c
-      T part[NB];
-#pragma unroll
-      for (int q = 0; q < NB; ++q) part[q] = 0;
-#pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        const int li = tid + kQrThreads * r;
-        if (li >= c) {
-          const T vc = (li == c) ? T(1) : P[r][c];
-#pragma unroll
-          for (int q = 0; q < NB; ++q)
-            if (q != c) part[q] += P[r][q] * vc;
-        }
-      }
-      int idx;
-      const T wsum = wave_multi_sum<T, NB>(part, lane, idx);
-      __syncthreads();
-      if ((lane & lowmask) == 0) red[wv][idx] = wsum;
-      __syncthreads();
-      if (tid < NB) {
-        T acc = 0;
-#pragma unroll
-        for (int w = 0; w < kQrThreads / 64; ++w) acc += red[w][tid];
-        dots[tid] = acc;
-      }
-      __syncthreads();
-      // ---- column c of T: T(0:c, c) = -tau_c T(0:c, 0:c) (V(:,0:c)^T v_c), T(c, c) = tau_c
-      if (tid < c) {
-        T acc = 0;
-        for (int b = tid; b < c; ++b) acc += Ts[b][tid] * dots[b];
-        Ts[c][tid] = -tauc * acc;
-      }
-      if (tid == c) Ts[c][c] = tauc;
-      if (tid == 0) tau[j0 + c] = tauc;
-      // ---- apply H_c to the later panel columns
-#pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        const int li = tid + kQrThreads * r;
-        if (li >= c) {
-          const T vc = (li == c) ? T(1) : P[r][c];
-#pragma unroll
-          for (int b = c + 1; b < NB; ++b) P[r][b] -= tauc * dots[b] * vc;
+      for (int e = 0; e < VW; ++e) {
+        if (k < 16) {
+          const int64_t i = r0 + rl + e, d = j0 + k;
+          Vs[rl + e][k] = (k < nb0) ? ((i > d) ? reg[u][e] : ((i == d) ? T(1) : T(0))) : T(0);
+        } else {
+          Cs[rl + e][k - 16] = reg[u][e];
         }
       }
     }
-  }
+  };
+
+  vec_t reg[PT];
+  acc_t acc = acc_t{0, 0, 0, 0};
+  if (nch > 0) load(j0, reg);
+  for (int64_t ch = 0; ch < nch; ++ch) {
+    const int64_t r0 = j0 + ch * kUpdRows;
+    __syncthreads();
+    stage(r0, reg);
+    __syncthreads();
+    if (ch + 1 < nch) load(r0 + kUpdRows, reg);
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    const int64_t i = j0 + tid + (int64_t)kQrThreads * r;
-    if (i < s) {
-#pragma unroll
-      for (int c = 0; c < NB; ++c)
-        if (c < nb) Y[i + (j0 + c) * ldy] = P[r][c];
+    for (int kk = 0; kk < 8; ++kk) {
+      const int k = 32 * wave + 4 * kk + (lane >> 4);
+      acc = qr_mfma(Vs[k][cl], Cs[k][cl], acc);
     }
   }
-  __syncthreads();
-  for (int o = tid; o < NB * NB; o += kQrThreads) {
-    const int a = o % NB, c = o / NB;
-    Tm[o] = (a <= c && c < nb) ? Ts[c][a] : T(0);
-  }
-}
-
-// V(i, a) of the current panel (unit lower trapezoidal, stored below the diagonal).
-template <typename T>
-__device__ __forceinline__ T panel_v(const T* Y, int64_t ldy, int64_t s, int64_t j0, int nb, int64_t i, int a) {
-  if (a >= nb || i >= s) return T(0);
-  const int64_t d = j0 + a;
-  if (i == d) return T(1);
-  if (i > d) return Y[i + d * ldy];
-  return T(0);
-}
-
-// Wp[(x * nrc + y) * NB * 32 + a * 32 + c] = sum over rows of chunk y of V(i, a) C(i, c).
-template <typename T, int NB>
-__global__ __launch_bounds__(256) void k_qr_wpart(const T* __restrict__ Y, int64_t ldy, int64_t s, int64_t j0,
-                                                  int nb, int64_t c_begin, int64_t ncols, T* __restrict__ Wp) {
-  __shared__ T Vs[kRowChunk][NB + 1];
-  __shared__ T Cs[kRowChunk][kColBlock + 1];
-  const int t = threadIdx.x;
-  const int64_t i = j0 + (int64_t)blockIdx.y * kRowChunk + t;
-  const int64_t cc0 = c_begin + (int64_t)blockIdx.x * kColBlock;
 #pragma unroll
-  for (int a = 0; a < NB; ++a) Vs[t][a] = panel_v(Y, ldy, s, j0, nb, i, a);
-  for (int c = 0; c < kColBlock; ++c)
-    Cs[t][c] = (i < s && cc0 + c < ncols) ? Y[i + (cc0 + c) * ldy] : T(0);
+  for (int r = 0; r < 4; ++r) part[wave][qr_drow<T>(lane, r)][cl] = acc[r];
   __syncthreads();
-  const int nrc = gridDim.y;
-  T* out = Wp + ((int64_t)blockIdx.x * nrc + blockIdx.y) * NB * kColBlock;
-  for (int o = t; o < NB * kColBlock; o += 256) {
-    const int a = o / kColBlock, c = o % kColBlock;
-    T acc = 0;
-    for (int r = 0; r < kRowChunk; ++r) acc += Vs[r][a] * Cs[r][c];
-    out[o] = acc;
+  if (tid < 256) {
+    const int a = tid >> 4, c = tid & 15;
+    T w = 0;
+#pragma unroll
+    for (int q = 0; q < kQrThreads / 64; ++q) w += part[q][a][c];
+    Ws[a][c] = w;
+  }
+  __syncthreads();
+  if (tid < 256) {
+    const int a = tid >> 4, c = tid & 15;
+    T w2 = 0;
+    if (a < nb0)
+      for (int q = 0; q <= a; ++q) w2 += Tm[q + a * NB] * Ws[q][c];
+    W2s[a][c] = w2;
+  }
+  if (nch > 0) load(j0, reg);
+  for (int64_t ch = 0; ch < nch; ++ch) {
+    const int64_t r0 = j0 + ch * kUpdRows;
+    __syncthreads();
+    stage(r0, reg);
+    __syncthreads();
+    if (ch + 1 < nch) load(r0 + kUpdRows, reg);
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
+      const int it = 16 * (2 * wave + tt);
+      acc_t d = acc_t{0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int a = 4 * kk + (lane >> 4);
+        d = qr_mfma(Vs[it + cl][a], W2s[a][cl], d);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Cs[it + qr_drow<T>(lane, r)][cl] -= d[r];
+    }
+    __syncthreads();
+    // the chunk of C back to Y (the C vectors of this thread)
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+      const int p = tid + kQrThreads * u;
+      const int k = p / QV;
+      const int rl = VW * (p % QV);
+      const int64_t i = r0 + rl;
+      if (k >= 16 && (k - 16) < cw && i < ldy) {
+        vec_t v;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) v[e] = Cs[rl + e][k - 16];
+        *reinterpret_cast<vec_t*>(Y + i + (c0 + (k - 16)) * ldy) = v;
+      }
+    }
   }
 }
 
-template <typename T, int NB>
-__global__ __launch_bounds__(256) void k_qr_apply(T* __restrict__ Y, int64_t ldy, int64_t s, int64_t j0, int nb,
-                                                  int64_t c_begin, int64_t ncols, const T* __restrict__ Wp,
-                                                  const T* __restrict__ Tm) {
-  __shared__ T W[NB][kColBlock];
-  __shared__ T W2[NB][kColBlock];
-  const int t = threadIdx.x;
-  const int nrc = gridDim.y;
-  const T* in = Wp + (int64_t)blockIdx.x * nrc * NB * kColBlock;
-  for (int o = t; o < NB * kColBlock; o += 256) {
-    T acc = 0;
-    for (int y = 0; y < nrc; ++y) acc += in[(int64_t)y * NB * kColBlock + o];
-    W[o / kColBlock][o % kColBlock] = acc;
-  }
-  __syncthreads();
-  for (int o = t; o < NB * kColBlock; o += 256) {
-    const int a = o / kColBlock, c = o % kColBlock;
-    T acc = 0;
-    for (int b = 0; b <= a; ++b) acc += Tm[b + a * NB] * W[b][c];   // (T^T W)(a, c)
-    W2[a][c] = acc;
-  }
-  __syncthreads();
-  const int64_t i = j0 + (int64_t)blockIdx.y * kRowChunk + t;
-  if (i >= s) return;
-  T v[NB];
-#pragma unroll
-  for (int a = 0; a < NB; ++a) v[a] = panel_v(Y, ldy, s, j0, nb, i, a);
-  const int64_t cc0 = c_begin + (int64_t)blockIdx.x * kColBlock;
-  for (int c = 0; c < kColBlock; ++c) {
-    if (cc0 + c >= ncols) break;
-    T acc = 0;
-#pragma unroll
-    for (int a = 0; a < NB; ++a) acc += v[a] * W2[a][c];
-    Y[i + (cc0 + c) * ldy] -= acc;
+// One step of the blocked factorisation with look-ahead.  The panel at j0
+// (nb0 columns, T in Tprev) is factored already.  Block 0 applies it to the
+// next panel (columns j1 .. j1 + nb1 - 1) and factors that panel (T into
+// Tnext); blocks b >= 1 apply it to the 16 columns jt + 16 (b - 1) .. of the
+// trailing matrix, which the next panel's reflectors reach in the next step.
+template <typename T, int RPT, int NB>
+__global__ __launch_bounds__(kQrThreads) void k_qr_step(T* __restrict__ Y, int64_t ldy, int64_t s, int64_t ncols,
+                                                         int64_t j0, int nb0, const T* __restrict__ Tprev,
+                                                         int64_t j1, int nb1, T* __restrict__ tau,
+                                                         T* __restrict__ Tnext, int64_t jt) {
+  if (blockIdx.x == 0) {
+    qr_update16<T, NB>(Y, ldy, s, j0, nb0, Tprev, j1, nb1);
+    __syncthreads();   // the next panel's updated columns are read back below
+    qr_panel_body<T, RPT, NB>(Y, ldy, s, j1, nb1, tau, Tnext);
+  } else {
+    const int64_t c0 = jt + 16 * (int64_t)(blockIdx.x - 1);
+    const int cw = (int)((ncols - c0 < 16) ? ncols - c0 : 16);
+    qr_update16<T, NB>(Y, ldy, s, j0, nb0, Tprev, c0, cw);
   }
 }
 
+// Z(0:rows, 0:cols) = X, rows >= valid set to zero.
 template <typename TI, typename TO>
 __global__ __launch_bounds__(256) void k_copy_cols(const TI* __restrict__ X, int64_t ldx, TO* __restrict__ Z,
-                                                   int64_t ldz, int64_t rows, int64_t cols) {
+                                                   int64_t ldz, int64_t rows, int64_t valid, int64_t cols) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t j = blockIdx.y;
-  if (i < rows && j < cols) Z[i + j * ldz] = (TO)X[i + j * ldx];
+  if (i < rows && j < cols) Z[i + j * ldz] = (i < valid) ? (TO)X[i + j * ldx] : TO(0);
 }
 
 // R = diag(sign(diag)) * triu(Y(0:ncols, 0:ncols)); flags a zero or non-finite
@@ -300,21 +551,19 @@ __global__ __launch_bounds__(256) void k_to_f32(const double* __restrict__ W, in
 
 template <typename T, int RPT, int NB>
 int qr_blocked(T* Y, int64_t ldy, int64_t s, int64_t ncols, char* ws, hipStream_t st) {
-  const int64_t ncb_max = ls_cdiv(ncols, kColBlock);
-  const int64_t nrc_max = ls_cdiv(s, kRowChunk);
   T* tau = reinterpret_cast<T*>(ws);
-  T* Tm = reinterpret_cast<T*>(ws + ls_align256(sizeof(T) * ncols));
-  T* Wp = reinterpret_cast<T*>(ws + ls_align256(sizeof(T) * ncols) + ls_align256(sizeof(T) * NB * NB));
-  (void)ncb_max;
-  (void)nrc_max;
-  for (int64_t j0 = 0; j0 < ncols; j0 += NB) {
-    const int nb = (int)((ncols - j0 < NB) ? (ncols - j0) : NB);
-    hipLaunchKernelGGL((k_qr_panel<T, RPT, NB>), dim3(1), dim3(kQrThreads), 0, st, Y, ldy, s, j0, nb, tau, Tm);
-    const int64_t c_begin = j0 + nb;
-    if (c_begin >= ncols) break;
-    const dim3 g((unsigned)ls_cdiv(ncols - c_begin, kColBlock), (unsigned)ls_cdiv(s - j0, kRowChunk));
-    hipLaunchKernelGGL((k_qr_wpart<T, NB>), g, dim3(256), 0, st, Y, ldy, s, j0, nb, c_begin, ncols, Wp);
-    hipLaunchKernelGGL((k_qr_apply<T, NB>), g, dim3(256), 0, st, Y, ldy, s, j0, nb, c_begin, ncols, Wp, Tm);
+  T* Tm = reinterpret_cast<T*>(ws + ls_align256(sizeof(T) * ncols));   // two NB x NB buffers
+  const int nbf = (int)((ncols < NB) ? ncols : NB);
+  hipLaunchKernelGGL((k_qr_panel<T, RPT, NB>), dim3(1), dim3(kQrThreads), 0, st, Y, ldy, s, (int64_t)0, nbf, tau, Tm);
+  int k = 0;
+  for (int64_t j0 = 0; j0 + NB < ncols; j0 += NB, ++k) {
+    const int nb0 = NB;
+    const int64_t j1 = j0 + NB;
+    const int nb1 = (int)((ncols - j1 < NB) ? ncols - j1 : NB);
+    const int64_t jt = j1 + nb1;
+    const unsigned ntr = (unsigned)ls_cdiv(ncols - jt, 16);
+    hipLaunchKernelGGL((k_qr_step<T, RPT, NB>), dim3(1 + ntr), dim3(kQrThreads), 0, st, Y, ldy, s, ncols, j0, nb0,
+                       Tm + (k & 1) * NB * NB, j1, nb1, tau, Tm + ((k + 1) & 1) * NB * NB, jt);
   }
   LS_HIP_TRY(hipGetLastError());
   return LS_OK;
@@ -322,19 +571,19 @@ int qr_blocked(T* Y, int64_t ldy, int64_t s, int64_t ncols, char* ws, hipStream_
 
 template <typename T>
 int qr_dispatch(T* Y, int64_t ldy, int64_t s, int64_t ncols, char* ws, hipStream_t st) {
-  // Panel width chosen so that RPT x NB panel values stay in registers
-  // (1024-thread blocks allow 128 VGPRs per lane).
-  const int64_t rpt = ls_cdiv(s, kQrThreads);
+  // Panel width chosen so that RPT x NB panel values stay in registers of the
+  // kPanelThreads panel threads (512-thread blocks allow 256 VGPRs per lane).
+  const int64_t rpt = ls_cdiv(s, kPanelThreads);
   if constexpr (sizeof(T) == 4) {
-    if (rpt <= 1) return qr_blocked<T, 1, 16>(Y, ldy, s, ncols, ws, st);
-    if (rpt <= 2) return qr_blocked<T, 2, 16>(Y, ldy, s, ncols, ws, st);
-    if (rpt <= 4) return qr_blocked<T, 4, 8>(Y, ldy, s, ncols, ws, st);
-    if (rpt <= 8) return qr_blocked<T, 8, 4>(Y, ldy, s, ncols, ws, st);
+    if (rpt <= 4) return qr_blocked<T, 4, 16>(Y, ldy, s, ncols, ws, st);
+    if (rpt <= 8) return qr_blocked<T, 8, 16>(Y, ldy, s, ncols, ws, st);
+    if (rpt <= 16) return qr_blocked<T, 16, 8>(Y, ldy, s, ncols, ws, st);
+    if (rpt <= 32) return qr_blocked<T, 32, 4>(Y, ldy, s, ncols, ws, st);
   } else {
-    if (rpt <= 1) return qr_blocked<T, 1, 8>(Y, ldy, s, ncols, ws, st);
-    if (rpt <= 2) return qr_blocked<T, 2, 8>(Y, ldy, s, ncols, ws, st);
-    if (rpt <= 4) return qr_blocked<T, 4, 4>(Y, ldy, s, ncols, ws, st);
-    if (rpt <= 8) return qr_blocked<T, 8, 2>(Y, ldy, s, ncols, ws, st);
+    if (rpt <= 4) return qr_blocked<T, 4, 8>(Y, ldy, s, ncols, ws, st);
+    if (rpt <= 8) return qr_blocked<T, 8, 8>(Y, ldy, s, ncols, ws, st);
+    if (rpt <= 16) return qr_blocked<T, 16, 4>(Y, ldy, s, ncols, ws, st);
+    if (rpt <= 32) return qr_blocked<T, 32, 2>(Y, ldy, s, ncols, ws, st);
   }
   return LS_E_UNSUPPORTED;
 }
@@ -343,31 +592,37 @@ int qr_dispatch(T* Y, int64_t ldy, int64_t s, int64_t ncols, char* ws, hipStream
 
 namespace ls {
 
+// Leading dimension of the internal working copy of Y.
+static int64_t qr_ldw(int64_t s) { return ls_cdiv(s, 4) * 4; }
+
 size_t qr_workspace(int64_t s, int64_t ncols, ls_prec_t u_qr) {
   const size_t elt = (u_qr == LS_FP32) ? 4 : 8;
   size_t b = 0;
-  if (u_qr == LS_FP32) b += ls_align256(elt * (size_t)s * ncols);      // binary32 working copy
+  b += ls_align256(elt * (size_t)qr_ldw(s) * ncols);                    // working copy
   b += ls_align256(elt * ncols);                                         // tau
-  b += ls_align256(elt * 16 * 16);                                       // T
-  b += ls_align256(elt * (size_t)ls_cdiv(ncols, kColBlock) * ls_cdiv(s, kRowChunk) * 16 * kColBlock);
+  b += ls_align256(elt * 2 * 16 * 16);                                   // T of two consecutive panels
   return b;
 }
 
 int qr_run(int64_t s, int64_t ncols, ls_prec_t u_qr, double* Y, int64_t ldy, double* R, int64_t ldr, char* ws,
            size_t ws_bytes, int* d_flag, int64_t check_cols, hipStream_t st) {
   if (ws_bytes < qr_workspace(s, ncols, u_qr)) return LS_E_WORKSPACE;
-  if (s > 8 * (int64_t)kQrThreads) return LS_E_UNSUPPORTED;
+  if (s > 32 * (int64_t)kPanelThreads) return LS_E_UNSUPPORTED;
+  const int64_t ldw = qr_ldw(s);
   const dim3 gfin((unsigned)ls_cdiv(ncols, 256), (unsigned)ncols);
+  const dim3 gcp((unsigned)ls_cdiv(ldw, 256), (unsigned)ncols);
   if (u_qr == LS_FP32) {
     float* Yw = reinterpret_cast<float*>(ws);
-    char* rest = ws + ls_align256(4 * (size_t)s * ncols);
-    hipLaunchKernelGGL((k_copy_cols<double, float>), dim3((unsigned)ls_cdiv(s, 256), (unsigned)ncols), dim3(256), 0,
-                       st, Y, ldy, Yw, s, s, ncols);
-    LS_TRY(qr_dispatch<float>(Yw, s, s, ncols, rest, st));
-    hipLaunchKernelGGL(k_qr_finish<float>, gfin, dim3(256), 0, st, Yw, s, ncols, check_cols, R, ldr, d_flag);
+    char* rest = ws + ls_align256(4 * (size_t)ldw * ncols);
+    hipLaunchKernelGGL((k_copy_cols<double, float>), gcp, dim3(256), 0, st, Y, ldy, Yw, ldw, ldw, s, ncols);
+    LS_TRY(qr_dispatch<float>(Yw, ldw, s, ncols, rest, st));
+    hipLaunchKernelGGL(k_qr_finish<float>, gfin, dim3(256), 0, st, Yw, ldw, ncols, check_cols, R, ldr, d_flag);
   } else if (u_qr == LS_FP64) {
-    LS_TRY(qr_dispatch<double>(Y, ldy, s, ncols, ws, st));
-    hipLaunchKernelGGL(k_qr_finish<double>, gfin, dim3(256), 0, st, Y, ldy, ncols, check_cols, R, ldr, d_flag);
+    double* Yw = reinterpret_cast<double*>(ws);
+    char* rest = ws + ls_align256(8 * (size_t)ldw * ncols);
+    hipLaunchKernelGGL((k_copy_cols<double, double>), gcp, dim3(256), 0, st, Y, ldy, Yw, ldw, ldw, s, ncols);
+    LS_TRY(qr_dispatch<double>(Yw, ldw, s, ncols, rest, st));
+    hipLaunchKernelGGL(k_qr_finish<double>, gfin, dim3(256), 0, st, Yw, ldw, ncols, check_cols, R, ldr, d_flag);
   } else {
     return LS_E_UNSUPPORTED;
   }
