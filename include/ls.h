@@ -107,7 +107,12 @@ typedef struct {
   int32_t lsir_maxit;
   double lsir_tol;
   int32_t fallback;
-  int32_t check_every;   /* iterations between host convergence checks (default 8) */
+  int32_t check_every;   /* LSQR / FGMRES iterations the host keeps queued ahead of
+                            the last one the device has reached (default 3); the
+                            device reports progress and convergence through a slot
+                            of pinned host memory, which the library allocates once
+                            per device (one page); without it the host synchronises
+                            every check_every iterations */
   int32_t profile;       /* nonzero: time the main kernels with HIP events (see ls_stats_t) */
 } ls_iter_opts_t;
 

@@ -165,7 +165,7 @@ void ls_default_iter_opts(int64_t n, ls_prec_t u, ls_iter_opts_t* o) {
   o->lsir_maxit = 30;
   o->lsir_tol = 4.0 * (dbl ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24));
   o->fallback = 0;
-  o->check_every = 8;
+  o->check_every = 3;
   o->profile = 0;
 }
 

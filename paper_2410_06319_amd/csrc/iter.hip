@@ -16,7 +16,10 @@
 //
 // Scalars live in device memory; kernels of one iteration are enqueued back
 // to back and the host reads a convergence flag every few iterations.
+#include <atomic>
 #include <cmath>
+#include <cstring>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -265,6 +268,18 @@ struct LsqrState {
   int32_t flag, pad;
 };
 
+// Progress of a call, written by the kernels that test convergence into
+// pinned host memory and polled by the host (so that it can keep a few
+// iterations queued instead of synchronising to read the state).
+struct Progress {
+  int32_t lsqr_it, lsqr_done, fg_j, fg_done;
+  int32_t pad[12];
+};
+
+__device__ __forceinline__ void progress_put(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Pass of iteration i over the panels of B (one wave streams a contiguous
 // range of panels, the next panel in flight while the current one is used):
 // per panel, the row sums B v are reduced across the wave, giving the panel's
@@ -390,11 +405,18 @@ __global__ __launch_bounds__(kThreads) void k_lsqr_col(int64_t n, const T* __res
                                                        const double* __restrict__ nvpart_in, int Gv,
                                                        double* __restrict__ nvpart_out, LsqrState* st, int par,
                                                        int init, int it, double tol, T* __restrict__ v,
-                                                       T* __restrict__ w, double* __restrict__ y) {
+                                                       T* __restrict__ w, double* __restrict__ y,
+                                                       Progress* prog) {
   __shared__ double dsh[4];
   const LsqrRec R = st->rec[par];
   if (!init && R.done) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->rec[par ^ 1] = R;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->rec[par ^ 1] = R;
+      if (prog) {
+        progress_put(&prog->lsqr_done, 1);
+        progress_put(&prog->lsqr_it, it);
+      }
+    }
     return;
   }
   const int lane = threadIdx.x & 63;
@@ -493,6 +515,10 @@ __global__ __launch_bounds__(kThreads) void k_lsqr_col(int64_t n, const T* __res
     if (N.stop == 4 && !init) N.done = 1;
     if (N.stop == 5) st->flag = 1;
     st->rec[par ^ 1] = N;
+    if (prog) {
+      progress_put(&prog->lsqr_done, N.done ? 1 : 0);
+      progress_put(&prog->lsqr_it, it);
+    }
   }
 }
 
@@ -715,7 +741,7 @@ template <typename TB, int Q>
 __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, int64_t npan, int64_t m, int64_t n,
                                                      FgPtrs F, int j, int kmax, const double* __restrict__ w2part,
                                                      int Gw, double tol, int final_step, TB* __restrict__ tpart,
-                                                     double* __restrict__ hpart) {
+                                                     double* __restrict__ hpart, Progress* prog) {
   if (F.st->done) return;
   using vec_t = typename PanVec<TB>::type;
   constexpr int PR = PanVec<TB>::PR;
@@ -767,6 +793,10 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
       }
     }
     *F.st = S;
+    if (prog && !final_step) {
+      progress_put(&prog->fg_done, S.done ? 1 : 0);
+      progress_put(&prog->fg_j, j);
+    }
   }
   if (h == 0.0 || !isfinite(h) || final_step || j >= kmax) return;
   const double inv = 1.0 / h;
@@ -1196,6 +1226,76 @@ int device_cu_count() {
   return cached;
 }
 
+namespace {
+// ------------------------------------------------------------------ progress slots
+// One page of pinned, device-mapped, coherent host memory per device, split
+// into slots handed out round-robin to calls.  Kernels store into a slot with
+// system-scope stores; the host polls it.  Null when such memory is not
+// available (the drivers then synchronise to read the state).
+constexpr int kProgressSlots = 64;
+constexpr int kMaxDevices = 64;
+struct ProgressPool {
+  std::mutex mu;
+  bool tried = false;
+  Progress* host = nullptr;
+  Progress* dev = nullptr;
+  std::atomic<unsigned> next{0};
+};
+
+ProgressPool& progress_pool(int dev) {
+  static ProgressPool pools[kMaxDevices];
+  return pools[(dev >= 0 && dev < kMaxDevices) ? dev : 0];
+}
+
+void progress_acquire(Progress** host, Progress** devp) {
+  *host = nullptr;
+  *devp = nullptr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return;
+  ProgressPool& p = progress_pool(dev);
+  {
+    std::lock_guard<std::mutex> g(p.mu);
+    if (!p.tried) {
+      p.tried = true;
+      void* h = nullptr;
+      if (hipHostMalloc(&h, sizeof(Progress) * kProgressSlots,
+                        hipHostMallocMapped | hipHostMallocPortable | hipHostMallocCoherent) == hipSuccess) {
+        void* d = nullptr;
+        if (hipHostGetDevicePointer(&d, h, 0) == hipSuccess && d) {
+          memset(h, 0, sizeof(Progress) * kProgressSlots);
+          p.host = static_cast<Progress*>(h);
+          p.dev = static_cast<Progress*>(d);
+        } else {
+          (void)hipHostFree(h);
+        }
+      } else {
+        (void)hipGetLastError();   // clear the failed allocation's error
+      }
+    }
+  }
+  if (!p.host) return;
+  const unsigned k = p.next.fetch_add(1) % kProgressSlots;
+  *host = p.host + k;
+  *devp = p.dev + k;
+}
+
+void progress_set(int32_t* f, int32_t v) { __atomic_store_n(f, v, __ATOMIC_RELEASE); }
+
+// Waits until *val >= target or *done.  Returns 1 when done was seen, 0 when
+// the target was reached, -1 when the stream went idle with neither (the slot
+// is not being updated).
+int progress_wait(int32_t* val, int32_t* done, int target, hipStream_t st) {
+  for (unsigned spin = 0;; ++spin) {
+    if (__atomic_load_n(done, __ATOMIC_ACQUIRE)) return 1;
+    if (__atomic_load_n(val, __ATOMIC_ACQUIRE) >= target) return 0;
+    if ((spin & 255u) == 255u && hipStreamQuery(st) == hipSuccess) {
+      if (__atomic_load_n(done, __ATOMIC_ACQUIRE)) return 1;
+      return (__atomic_load_n(val, __ATOMIC_ACQUIRE) >= target) ? 0 : -1;
+    }
+  }
+}
+}  // namespace
+
 // B = A W (W binary64 n x n, ld n; W32 its binary32 copy), binary32 or binary64.
 int form_b(const ls_problem_t* P, const double* W, const float* W32, ls_prec_t tb, void* Bout, hipStream_t st) {
   const dim3 g((unsigned)ls_cdiv(P->m, 64), (unsigned)ls_cdiv(P->n, 64));
@@ -1323,26 +1423,37 @@ int lsqr_typed(const ls_problem_t* P, const double* R, int64_t ldr, const double
   };
   // init: u_1 = b - B z0, beta_1, v_1 = B^T u_1 / beta_1; C_1 -> rec[1]
   pass(1, 1, w.nvpart[0]);
+  Progress *prog = nullptr, *dprog = nullptr;
+  progress_acquire(&prog, &dprog);
+  if (prog) {
+    progress_set(&prog->lsqr_it, -1);
+    progress_set(&prog->lsqr_done, 0);
+  }
   hipLaunchKernelGGL(k_lsqr_col<T>, gcol, dim3(kThreads), 0, st, n, tpart, G, w.nupart, w.nbpart, w.nvpart[1], Gv,
-                     w.nvpart[0], w.st, 0, 1, 0, tol, v, wv, w.y);
+                     w.nvpart[0], w.st, 0, 1, 0, tol, v, wv, w.y, dprog);
   int it = 1, cur = 0;   // nvpart[cur] holds ||v_it||^2 partials
+  int last = 0;          // last column kernel launched
   LsqrRec rec{};
   for (; it <= maxit; ++it) {
     const int par = it & 1;
     pass(par, 0, w.nvpart[cur]);
     hipLaunchKernelGGL(k_lsqr_col<T>, gcol, dim3(kThreads), 0, st, n, tpart, G, w.nupart, w.nbpart, w.nvpart[cur], Gv,
-                       w.nvpart[cur ^ 1], w.st, par, 0, it, tol, v, wv, w.y);
+                       w.nvpart[cur ^ 1], w.st, par, 0, it, tol, v, wv, w.y, dprog);
     cur ^= 1;
+    last = it;
+    // at most `check` iterations in flight; stop queueing once converged
+    if (prog) {
+      const int rc = progress_wait(&prog->lsqr_it, &prog->lsqr_done, it - check + 1, st);
+      if (rc == 1) break;
+      if (rc == 0) continue;
+      prog = nullptr;   // the slot is not updated: read the state instead from now on
+    }
     if (it % check == 0) {
       LS_HIP_TRY(hipMemcpyAsync(&rec, &w.st->rec[par ^ 1], sizeof(LsqrRec), hipMemcpyDeviceToHost, st));
       LS_HIP_TRY(hipStreamSynchronize(st));
-      if (rec.done) {
-        ++it;
-        break;
-      }
+      if (rec.done) break;
     }
   }
-  const int last = it - 1;                 // last column kernel launched
   const int fpar = (last + 1) & 1;         // rec written by it
   hipLaunchKernelGGL(k_lsqr_finish<T>, gut, dim3(kUtThreads), 0, st, W, n, w.z0, w.y,
                      w.nvpart[cur], Gv, w.st, fpar, last, x);
@@ -1407,9 +1518,10 @@ struct LsirDims {
 
 template <typename TB, int Q>
 void fg_pan_launch(int G, hipStream_t st, const TB* Bm, int64_t npan, int64_t m, int64_t n, const FgPtrs& F, int j,
-                   int kmax, const double* w2part, int Gw, double tol, int final_step, TB* tpart, double* hpart) {
+                   int kmax, const double* w2part, int Gw, double tol, int final_step, TB* tpart, double* hpart,
+                   Progress* prog) {
   hipLaunchKernelGGL((k_fg_pan<TB, Q>), dim3(G), dim3(kThreads), 0, st, Bm, npan, m, n, F, j, kmax, w2part, Gw, tol,
-                     final_step, tpart, hpart);
+                     final_step, tpart, hpart, prog);
 }
 
 LsirDims lsir_dims(const ls_problem_t* P, size_t tb_elt, size_t ta_elt, int fgmres_maxit, int ncu) {
@@ -1490,9 +1602,12 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
   if (!r_given)
     hipLaunchKernelGGL((k_resid_u<TA, TU>), dim3((unsigned)ls_cdiv(m, kThreads)), dim3(kThreads), n * sizeof(TU), st, A,
                        P->lda, m, n, b, x, r);
+  Progress *prog = nullptr, *dprog = nullptr;
+  progress_acquire(&prog, &dprog);
   auto fg_pass = [&](int j, int Gw, int final_step, int grid) {
-#define LS_FG_PAN(QQ)                                                                                               \
-  fg_pan_launch<TB, QQ>(grid, st, Bm, d.npan, m, n, F, j, d.kmax, w.w2part, Gw, tol, final_step, tpart, w.hpart); \
+#define LS_FG_PAN(QQ)                                                                                              \
+  fg_pan_launch<TB, QQ>(grid, st, Bm, d.npan, m, n, F, j, d.kmax, w.w2part, Gw, tol, final_step, tpart, w.hpart, \
+                        dprog);                                                                                    \
   break
     switch (q) {
       case 1: LS_FG_PAN(1);
@@ -1533,6 +1648,10 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
     // line 7: FGMRES on [I B; B^T 0]
     int j = 0;
     FgState S{};
+    if (prog) {   // the previous cycle has been synchronised: no kernel writes the slot now
+      progress_set(&prog->fg_j, -1);
+      progress_set(&prog->fg_done, 0);
+    }
     for (; j < d.kmax; ++j) {
       const int Gw = (j == 0) ? d.Gr + d.Gh : d.Gd;
       prof_begin(kProfFgPass, st);
@@ -1549,6 +1668,14 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
       hipLaunchKernelGGL(k_cgs2, dim3((unsigned)d.Gd), dim3(kThreads), 0, st, F, m, n, j, w.h2, w.w2part);
       // V(:, 0:j) read three times (first sweep twice, second once), w read and written twice
       prof_end(kProfCgs, st, 3.0 * 8.0 * (j + 1) * (double)(m + n) + 4.0 * 8.0 * (double)(m + n));
+      // at most `check` iterations in flight; stop queueing once converged
+      if (prog) {
+        const int rc = progress_wait(&prog->fg_j, &prog->fg_done, j - check + 1, st);
+        if (rc == 1) break;
+        if (rc == 0) continue;
+        prog = nullptr;   // the slot is not updated: read the state instead from now on
+        dprog = nullptr;
+      }
       if ((j + 1) % check == 0) {
         LS_HIP_TRY(hipMemcpyAsync(&S, w.st, sizeof(FgState), hipMemcpyDeviceToHost, st));
         LS_HIP_TRY(hipStreamSynchronize(st));
