@@ -30,7 +30,6 @@ namespace ls {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kMaxVecLoads = 16;   // 16-byte loads per thread held in flight for one row block
 constexpr int kMaxKrylov = 96;     // Arnoldi columns per FGMRES cycle (kmax + 1)
 constexpr int kMaxPanQ = 16;       // 16-byte loads per lane for one panel of B (n <= 1024)
 
@@ -80,69 +79,6 @@ __device__ __forceinline__ double wave_sum_array(const double* __restrict__ part
   for (int g = lane; g < G; g += 64) s += part[g];
   return ls_wave_sum(s);
 }
-
-// ------------------------------------------------------------------ row-block staging
-// A block of RB rows x n columns of a column-major matrix M (ld), loaded with
-// 16-byte vectors into registers (vec path: every row in range, aligned) and
-// stored to LDS as Ms[j * (RB+1) + r].
-template <typename T, int RB>
-struct RowBlock {
-  static constexpr int V = 16 / (int)sizeof(T);
-  static constexpr int PER = RB / V;       // vectors per column segment
-  using vec_t = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
-  vec_t reg[kMaxVecLoads];
-  bool full;
-
-  __device__ __forceinline__ void load(const T* __restrict__ M, int64_t ld, int64_t m, int64_t n, int64_t i0,
-                                       bool vec_ok) {
-    full = vec_ok && (i0 + RB <= m);
-    if (!full) return;
-    const int total = (int)n * PER;
-#pragma unroll
-    for (int q = 0; q < kMaxVecLoads; ++q) {
-      const int idx = threadIdx.x + q * kThreads;
-      if (idx < total) {
-        const int j = idx / PER;
-        const int p = idx - j * PER;
-        reg[q] = *reinterpret_cast<const vec_t*>(M + i0 + p * V + (int64_t)j * ld);
-      }
-    }
-  }
-
-  __device__ __forceinline__ void store(const T* __restrict__ M, int64_t ld, int64_t m, int64_t n, int64_t i0,
-                                        T* __restrict__ Ms) const {
-    constexpr int LDR = RB + 1;
-    if (full) {
-      const int total = (int)n * PER;
-#pragma unroll
-      for (int q = 0; q < kMaxVecLoads; ++q) {
-        const int idx = threadIdx.x + q * kThreads;
-        if (idx < total) {
-          const int j = idx / PER;
-          const int p = idx - j * PER;
-          T* dst = Ms + j * LDR + p * V;
-          if constexpr (V == 4) {
-            dst[0] = reg[q].x;
-            dst[1] = reg[q].y;
-            dst[2] = reg[q].z;
-            dst[3] = reg[q].w;
-          } else {
-            dst[0] = reg[q].x;
-            dst[1] = reg[q].y;
-          }
-        }
-      }
-    } else {
-      const int total = (int)n * RB;
-      for (int idx = threadIdx.x; idx < total; idx += kThreads) {
-        const int j = idx / RB;
-        const int r = idx - j * RB;
-        const int64_t i = i0 + r;
-        Ms[j * LDR + r] = (i < m) ? M[i + (int64_t)j * ld] : T(0);
-      }
-    }
-  }
-};
 
 // Range of row blocks owned by block `bx` of G.
 __device__ __forceinline__ void row_range(int64_t nrb, int G, int bx, int64_t& b0, int64_t& b1) {
@@ -551,116 +487,216 @@ __global__ __launch_bounds__(kUtThreads) void k_lsqr_finish(const double* __rest
 }
 
 // ================================================================== refinement
+// Passes over A itself (column-major, as stored).  A block of 256 threads
+// owns 256 rows: lane l of every wave holds rows 4 l .. 4 l + 3 (one 16-byte
+// load of binary32 A per column, two of binary64), and wave w takes the
+// columns of the w-th quarter of [0, n), sixteen at a time (sixteen loads in
+// flight).  Row sums are added over the four waves in LDS at the end.
+constexpr int kResRows = 256;
+
+template <typename TA>
+__device__ __forceinline__ void load_rows4(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t i0, int64_t j,
+                                           bool vec, double (&a)[4]) {
+  const TA* p = A + i0 + j * lda;
+  if (vec) {
+    if constexpr (sizeof(TA) == 4) {
+      const ls_float4v v = *reinterpret_cast<const ls_float4v*>(p);
+      a[0] = v[0];
+      a[1] = v[1];
+      a[2] = v[2];
+      a[3] = v[3];
+    } else {
+      const ls_double2v v0 = *reinterpret_cast<const ls_double2v*>(p);
+      const ls_double2v v1 = *reinterpret_cast<const ls_double2v*>(p + 2);
+      a[0] = v0[0];
+      a[1] = v0[1];
+      a[2] = v1[0];
+      a[3] = v1[1];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a[k] = (i0 + k < m) ? (double)p[k] : 0.0;
+  }
+}
+
+// Accumulator of the refinement residual: binary64, or double-double.
+template <bool DD>
+struct RAcc {
+  double hi = 0.0, lo = 0.0;
+  __device__ __forceinline__ void fma(double a, double b) {
+    if constexpr (DD) {
+      const ls_dd t = ls_dd_fma(ls_dd{hi, lo}, a, b);
+      hi = t.hi;
+      lo = t.lo;
+    } else {
+      hi += a * b;
+    }
+  }
+  __device__ __forceinline__ void add(const RAcc& o) {
+    if constexpr (DD) {
+      const ls_dd t = ls_dd_add(ls_dd{hi, lo}, ls_dd{o.hi, o.lo});
+      hi = t.hi;
+      lo = t.lo;
+    } else {
+      hi += o.hi;
+    }
+  }
+  __device__ __forceinline__ RAcc xor_lane(int m) const {
+    RAcc r;
+    r.hi = __shfl_xor(hi, m, 64);
+    if constexpr (DD) r.lo = __shfl_xor(lo, m, 64);
+    return r;
+  }
+  // this value if f == 1, o if f == 0 (exact for finite values)
+  __device__ __forceinline__ RAcc blend(const RAcc& o, double f) const {
+    RAcc r;
+    r.hi = hi * f + o.hi * (1.0 - f);
+    if constexpr (DD) r.lo = lo * f + o.lo * (1.0 - f);
+    return r;
+  }
+};
+
+// Transposed butterfly over the wave for 16 accumulators: lane l ends with
+// the wave total of index ((l >> 5) & 1) 8 + ((l >> 4) & 1) 4 + ((l >> 3) & 1) 2 + ((l >> 2) & 1).
+template <bool DD>
+__device__ __forceinline__ RAcc<DD> racc_multi_sum16(RAcc<DD> (&v)[16], int lane, int& idx) {
+  int base = 0;
+#pragma unroll
+  for (int step = 0; step < 4; ++step) {
+    const int off = 32 >> step;
+    const int h = 8 >> step;
+    const double fu = (lane & off) ? 1.0 : 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (q < h) {
+        const RAcc<DD> send = v[q].blend(v[q + h], fu);
+        RAcc<DD> keep = v[q + h].blend(v[q], fu);
+        keep.add(send.xor_lane(off));
+        v[q] = keep;
+      }
+    }
+    if (lane & off) base += h;
+  }
+  RAcc<DD> s = v[0];
+  s.add(s.xor_lane(2));
+  s.add(s.xor_lane(1));
+  idx = base;
+  return s;
+}
+
 // r = b - A x in precision T (Algorithm 2 line 2).
 template <typename TA, typename T>
 __global__ __launch_bounds__(kThreads) void k_resid_u(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n,
-                                                      const TA* __restrict__ b, const double* __restrict__ x,
-                                                      double* __restrict__ r) {
-  extern __shared__ __align__(16) char smem[];
-  T* xs = reinterpret_cast<T*>(smem);
-  for (int j = threadIdx.x; j < n; j += kThreads) xs[j] = (T)x[j];
-  __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= m) return;
-  T a0 = 0, a1 = 0;
-  int64_t j = 0;
-  for (; j + 1 < n; j += 2) {
-    a0 += (T)A[i + j * lda] * xs[j];
-    a1 += (T)A[i + (j + 1) * lda] * xs[j + 1];
+                                                      int vec_ok, const TA* __restrict__ b,
+                                                      const double* __restrict__ x, double* __restrict__ r) {
+  __shared__ T rs[4][kResRows];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * kResRows + 4 * lane;
+  const bool vec = vec_ok && i0 + 4 <= m;
+  const int64_t jq = ls_cdiv(n, 4);
+  const int64_t j0 = wave * jq, j1 = (j0 + jq < n) ? j0 + jq : n;
+  T acc[4] = {0, 0, 0, 0};
+  for (int64_t jb = j0; jb < j1; jb += 16) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int64_t j = jb + q;
+      if (j < j1 && i0 < m) {
+        double a[4];
+        load_rows4(A, lda, m, i0, j, vec, a);
+        const T xj = (T)x[j];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] += (T)a[k] * xj;
+      }
+    }
   }
-  if (j < n) a0 += (T)A[i + j * lda] * xs[j];
-  r[i] = (double)((T)b[i] - (a0 + a1));
+#pragma unroll
+  for (int k = 0; k < 4; ++k) rs[wave][4 * lane + k] = acc[k];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * kResRows + threadIdx.x;
+  if (i < m) {
+    const int t = threadIdx.x;
+    r[i] = (double)((T)b[i] - ((rs[0][t] + rs[1][t]) + (rs[2][t] + rs[3][t])));
+  }
 }
 
-// Line 5 in u_r: f = b - r - A x (rows, written to V[:, 0]) and partial
-// g = A^T r (column-major partials); binary64, or double-double when DD.
-// A is staged as stored (TA) and widened when used.
-template <typename TA, bool DD, int RB>
+// Line 5 in u_r: f = b - r - A x (rows, written to V[:, 0]) and g = A^T r as
+// per-block column partials (tpart[c G + block], hi and lo parts), binary64
+// or double-double; A and b are used exactly as stored.
+template <typename TA, bool DD>
 __global__ __launch_bounds__(kThreads) void k_lsir_resid(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n,
                                                          int vec_ok, const TA* __restrict__ b,
                                                          const double* __restrict__ r, const double* __restrict__ x,
                                                          double* __restrict__ V, double* __restrict__ tpart_hi,
                                                          double* __restrict__ tpart_lo, double* __restrict__ fpart) {
-  extern __shared__ __align__(16) char smem[];
-  constexpr int LDR = RB + 1;
-  constexpr int G1 = kThreads / RB;
-  TA* Ms = reinterpret_cast<TA*>(smem);
-  double* xs = align8(Ms + n * LDR);
-  double* thi = xs + n;
-  double* tlo = thi + n;
-  double* rr = tlo + n;
-  double* rhi = rr + RB;
-  double* rlo = rhi + kThreads;
-  double* dsh = rlo + kThreads;
-  for (int j = threadIdx.x; j < n; j += kThreads) {
-    xs[j] = x[j];
-    thi[j] = 0.0;
-    tlo[j] = 0.0;
-  }
-  double fn = 0.0;
-  const int64_t nrb = ls_cdiv(m, RB);
-  int64_t b0, b1;
-  row_range(nrb, gridDim.x, blockIdx.x, b0, b1);
-  RowBlock<TA, RB> blk;
-  if (b0 < b1) blk.load(A, lda, m, n, b0 * RB, vec_ok != 0);
-  for (int64_t rb = b0; rb < b1; ++rb) {
-    const int64_t i0 = rb * RB;
-    __syncthreads();
-    blk.store(A, lda, m, n, i0, Ms);
-    __syncthreads();
-    if (rb + 1 < b1) blk.load(A, lda, m, n, i0 + RB, vec_ok != 0);
-    {
-      const int rw = threadIdx.x % RB;
-      const int g = threadIdx.x / RB;
-      ls_dd acc{0.0, 0.0};
-      for (int j = g; j < n; j += G1) {
-        if (DD) acc = ls_dd_fma(acc, (double)Ms[j * LDR + rw], xs[j]);
-        else acc.hi += (double)Ms[j * LDR + rw] * xs[j];
-      }
-      rhi[g * RB + rw] = acc.hi;
-      rlo[g * RB + rw] = acc.lo;
-    }
-    __syncthreads();
-    if (threadIdx.x < RB) {
-      const int64_t i = i0 + threadIdx.x;
-      double ri = 0.0;
-      if (i < m) {
-        ri = r[i];
-        double f;
-        if (DD) {
-          ls_dd q{0.0, 0.0};
-          for (int gg = 0; gg < G1; ++gg) q = ls_dd_add(q, ls_dd{rhi[gg * RB + threadIdx.x], rlo[gg * RB + threadIdx.x]});
-          ls_dd fb = ls_two_sum((double)b[i], -ri);
-          fb = ls_dd_add(fb, ls_dd{-q.hi, -q.lo});
-          f = fb.hi + fb.lo;
-        } else {
-          double q = 0.0;
-          for (int gg = 0; gg < G1; ++gg) q += rhi[gg * RB + threadIdx.x];
-          f = ((double)b[i] - ri) - q;
+  __shared__ double rsh[4][kResRows], rsl[4][kResRows];
+  __shared__ double dsh[4];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int G = gridDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * kResRows + 4 * lane;
+  const bool vec = vec_ok && i0 + 4 <= m;
+  const int64_t jq = ls_cdiv(n, 4);
+  const int64_t j0 = wave * jq, j1 = (j0 + jq < n) ? j0 + jq : n;
+  double rv[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) rv[k] = (i0 + k < m) ? r[i0 + k] : 0.0;
+  RAcc<DD> racc[4];
+  for (int64_t jb = j0; jb < j1; jb += 16) {
+    RAcc<DD> cp[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int64_t j = jb + q;
+      if (j < j1 && i0 < m) {
+        double a[4];
+        load_rows4(A, lda, m, i0, j, vec, a);
+        const double xj = x[j];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          racc[k].fma(a[k], xj);
+          cp[q].fma(a[k], rv[k]);
         }
-        V[i] = f;
-        fn += f * f;
-      }
-      rr[threadIdx.x] = ri;
-    }
-    __syncthreads();
-    for (int j = threadIdx.x; j < n; j += kThreads) {
-      if (DD) {
-        ls_dd acc{thi[j], tlo[j]};
-        for (int rw = 0; rw < RB; ++rw) acc = ls_dd_fma(acc, (double)Ms[j * LDR + rw], rr[rw]);
-        thi[j] = acc.hi;
-        tlo[j] = acc.lo;
-      } else {
-        double acc = 0.0;
-        for (int rw = 0; rw < RB; ++rw) acc += (double)Ms[j * LDR + rw] * rr[rw];
-        thi[j] += acc;
       }
     }
+    int idx;
+    const RAcc<DD> tot = racc_multi_sum16<DD>(cp, lane, idx);
+    const int64_t c = jb + idx;
+    if ((lane & 3) == 0 && c < j1) {
+      tpart_hi[c * G + blockIdx.x] = tot.hi;
+      if (DD) tpart_lo[c * G + blockIdx.x] = tot.lo;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    rsh[wave][4 * lane + k] = racc[k].hi;
+    rsl[wave][4 * lane + k] = racc[k].lo;
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < n; j += kThreads) {
-    tpart_hi[(int64_t)j * gridDim.x + blockIdx.x] = thi[j];
-    tpart_lo[(int64_t)j * gridDim.x + blockIdx.x] = tlo[j];
+  const int t = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * kResRows + t;
+  double fn = 0.0;
+  if (i < m) {
+    RAcc<DD> q;
+    q.hi = rsh[0][t];
+    q.lo = rsl[0][t];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) {
+      RAcc<DD> o;
+      o.hi = rsh[w][t];
+      o.lo = rsl[w][t];
+      q.add(o);
+    }
+    const double ri = r[i];
+    double f;
+    if (DD) {
+      ls_dd fb = ls_two_sum((double)b[i], -ri);
+      fb = ls_dd_add(fb, ls_dd{-q.hi, -q.lo});
+      f = fb.hi + fb.lo;
+    } else {
+      f = ((double)b[i] - ri) - q.hi;
+    }
+    V[i] = f;
+    fn = f * f;
   }
   fn = block_sum256(fn, dsh);
   if (threadIdx.x == 0) fpart[blockIdx.x] = fn;
@@ -1151,31 +1187,11 @@ size_t device_lds_limit() {
   return cached;
 }
 
-// Rows per block for a pass over an n-column matrix of element size elt:
-// the block must fit the LDS budget and the register prefetch buffer.
-int pick_rb(int64_t n, size_t elt, size_t extra_lds) {
-  const size_t budget = device_lds_limit() - 1024;
-  const int cands[3] = {32, 16, 8};
-  for (int rb : cands) {
-    const size_t lds = (size_t)n * (rb + 1) * elt + 2 * (size_t)n * elt + extra_lds + 4096;
-    const size_t regs_needed = (size_t)rb * n * elt;                // bytes per block
-    const size_t regs_avail = (size_t)kMaxVecLoads * 16 * kThreads;
-    if (lds <= budget && regs_needed <= regs_avail) return rb;
-  }
-  return 0;
-}
-
+// 16-byte vector loads of a column-major matrix are possible (base aligned,
+// leading dimension a multiple of the vector length).
 bool vec_aligned(const void* M, int64_t ld, size_t elt) {
   const size_t v = 16 / elt;
   return ((uintptr_t)M % 16 == 0) && (ld % (int64_t)v == 0);
-}
-
-int pass_grid(int64_t m, int rb, int ncu) {
-  const int64_t nrb = ls_cdiv(m, rb);
-  int64_t G = 2 * (int64_t)ncu;
-  if (G > nrb) G = nrb;
-  if (G < 1) G = 1;
-  return (int)G;
 }
 
 // Loads per lane for one panel: the smallest power of two with 64 Q >= n.
@@ -1512,7 +1528,7 @@ struct LsirWs {
 };
 
 struct LsirDims {
-  int kmax, rbr, G, Gr, Gc, Gd, Gh, Gn;
+  int kmax, G, Gr, Gc, Gd, Gh, Gn;
   int64_t npan;   // panels of B
 };
 
@@ -1527,12 +1543,10 @@ void fg_pan_launch(int G, hipStream_t st, const TB* Bm, int64_t npan, int64_t m,
 LsirDims lsir_dims(const ls_problem_t* P, size_t tb_elt, size_t ta_elt, int fgmres_maxit, int ncu) {
   LsirDims d{};
   d.kmax = fgmres_maxit;
-  const size_t resid_extra = 8 * (3 * (size_t)P->n + 2 * kThreads + 64);
-  d.rbr = pick_rb(P->n, ta_elt, resid_extra > 2 * (size_t)P->n * ta_elt ? resid_extra - 2 * (size_t)P->n * ta_elt : 0);
-  if (d.rbr == 0) d.rbr = 8;
+
   d.npan = pan_count(P->m, tb_elt);
   d.G = pan_grid(d.npan, ncu);
-  d.Gr = pass_grid(P->m, d.rbr, ncu);
+  d.Gr = (int)ls_cdiv(P->m, kResRows);
   d.Gc = (int)ls_cdiv(P->n, 16);
   d.Gd = (int)ls_cdiv(P->m + P->n, kThreads);
   d.Gh = (int)ls_cdiv(P->n, 4);
@@ -1595,13 +1609,11 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
   const int check = io->check_every > 0 ? io->check_every : 8;
   const double tol = io->fgmres_tol;
   const double lsir_tol = io->lsir_tol;
-  const size_t lds_r = ((size_t)n * (d.rbr + 1)) * sizeof(TA) + 8 * (3 * (size_t)n + d.rbr + 2 * kThreads + 8) + 16;
-  if (lds_r > device_lds_limit()) return LS_E_UNSUPPORTED;
   const int ncb = (int)d.Gc;
 
   if (!r_given)
-    hipLaunchKernelGGL((k_resid_u<TA, TU>), dim3((unsigned)ls_cdiv(m, kThreads)), dim3(kThreads), n * sizeof(TU), st, A,
-                       P->lda, m, n, b, x, r);
+    hipLaunchKernelGGL((k_resid_u<TA, TU>), dim3((unsigned)d.Gr), dim3(kThreads), 0, st, A, P->lda, m, n, vec_a, b, x,
+                       r);
   Progress *prog = nullptr, *dprog = nullptr;
   progress_acquire(&prog, &dprog);
   auto fg_pass = [&](int j, int Gw, int final_step, int grid) {
@@ -1624,20 +1636,8 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
   for (its = 1; its <= io->lsir_maxit; ++its) {
     // lines 5-6: f, g, h in u_r
     prof_begin(kProfResidPass, st);
-    switch (d.rbr) {
-      case 32:
-        hipLaunchKernelGGL((k_lsir_resid<TA, DD, 32>), dim3(d.Gr), dim3(kThreads), lds_r, st, A, P->lda, m, n, vec_a,
-                           b, r, x, w.V, w.rt_hi, w.rt_lo, w.w2part);
-        break;
-      case 16:
-        hipLaunchKernelGGL((k_lsir_resid<TA, DD, 16>), dim3(d.Gr), dim3(kThreads), lds_r, st, A, P->lda, m, n, vec_a,
-                           b, r, x, w.V, w.rt_hi, w.rt_lo, w.w2part);
-        break;
-      default:
-        hipLaunchKernelGGL((k_lsir_resid<TA, DD, 8>), dim3(d.Gr), dim3(kThreads), lds_r, st, A, P->lda, m, n, vec_a,
-                           b, r, x, w.V, w.rt_hi, w.rt_lo, w.w2part);
-        break;
-    }
+    hipLaunchKernelGGL((k_lsir_resid<TA, DD>), dim3((unsigned)d.Gr), dim3(kThreads), 0, st, A, P->lda, m, n, vec_a, b,
+                       r, x, w.V, w.rt_hi, w.rt_lo, w.w2part);
     // A and b once, r read, f written, x read, g written
     prof_end(kProfResidPass, st, (double)m * n * sizeof(TA) + (double)m * sizeof(TA) + 16.0 * m + 16.0 * n);
     hipLaunchKernelGGL(k_lsir_g<DD>, dim3((unsigned)ls_cdiv(n, 4)), dim3(kThreads), 0, st, w.rt_hi, w.rt_lo, d.Gr, n,
