@@ -89,7 +89,10 @@ typedef struct {
   int64_t s;         /* sketch rows, s >= n + 1; 0 selects 4n */
   uint64_t seed;
   uint32_t prob_id;
-  int32_t terms;     /* 1..3 for LS_BF16; 1 for LS_FP64 */
+  int32_t terms;     /* 1..3 for LS_BF16, LS_FP16, LS_FP8E4M3; 1 for LS_FP64 */
+  int32_t col_scale; /* Section 3.2 column scaling by powers of two: 0 = on for
+                        LS_FP16 and LS_FP8E4M3 (whose range is narrow), off
+                        otherwise; 1 = on; -1 = off */
 } ls_sketch_opts_t;
 
 /* Iteration control (Section 5): LSQR at most 2n iterations, tolerance 1e-6
@@ -152,10 +155,15 @@ int ls_workspace_size(const ls_problem_t *P, const ls_sketch_opts_t *so,
 /* Algorithm 1 step 1 on [A b]: Y = Omega [A b], s x (n+1), binary64,
  * column major with leading dimension ldy >= s (device).  Column n is
  * Omega b, which Algorithm 2's sketch-and-solve start needs.  With u_s =
- * LS_BF16 the entries of S are rounded to bf16 from binary32 Box-Muller
- * values, A and b are represented as `terms` bf16 parts, products run on
- * MFMA with binary32 accumulation over chunks of rows of A and the chunks
- * are summed in binary64.  With u_s = LS_FP64 everything is binary64. */
+ * LS_BF16, LS_FP16 or LS_FP8E4M3 (OCP e4m3, largest value 448, saturating)
+ * the entries of S are rounded to the format from binary32 Box-Muller
+ * values; the columns of [A b] are optionally scaled by 2^e_j (e_j the
+ * largest integer with max_i |[A b]_ij| 2^e_j <= the format's largest value,
+ * Section 3.2) and represented as `terms` rounded parts (nearest, ties to
+ * even); products run on MFMA with binary32 accumulation over chunks of rows
+ * of A, the chunks are summed in binary64 and the scaling is undone, so Y is
+ * the sketch of [A b] itself.  A may be stored in binary32 or binary64.
+ * With u_s = LS_FP64 everything is binary64. */
 int ls_sketch(const ls_problem_t *P, const ls_sketch_opts_t *so, ls_prec_t u_s,
               double *Y, int64_t ldy, void *ws, size_t ws_bytes, void *stream);
 
@@ -194,9 +202,30 @@ int ls_solve(const ls_problem_t *P, const ls_sketch_opts_t *so, const ls_precs_t
              const ls_iter_opts_t *io, double *x, double *r, ls_stats_t *stats,
              void *ws, size_t ws_bytes, void *stream);
 
+/* A batch of independent problems (the same method for each; Section 5's
+ * experiments are sets of such problems): P, so, x, r and stats are host
+ * arrays of nprob entries (x[i], r[i] device pointers as in ls_solve), pr and
+ * io apply to all problems (io may be NULL for the defaults; per-call
+ * profiling is off).  The problems are sorted by size and distributed over
+ * nworkers (1..16, 0 = 8) host threads, each with its own internal stream
+ * (default priority), progress slot and slice of the workspace, so that
+ * several problems occupy the device at once.  Work on `stream` before the
+ * call precedes the batch and work queued on it afterwards follows it.  Each
+ * problem's result is bitwise the one ls_solve gives on its own.  Returns the
+ * first error of any problem, else LS_NOT_CONVERGED if any problem did not
+ * converge, else LS_OK; stats[i].status holds each problem's status. */
+int ls_workspace_size_batched(int nprob, const ls_problem_t *P, const ls_sketch_opts_t *so,
+                              const ls_precs_t *pr, const ls_iter_opts_t *io, int nworkers,
+                              size_t *bytes);
+int ls_solve_batched(int nprob, const ls_problem_t *P, const ls_sketch_opts_t *so,
+                     const ls_precs_t *pr, const ls_iter_opts_t *io, double *const *x,
+                     double *const *r, ls_stats_t *stats, int nworkers, void *ws,
+                     size_t ws_bytes, void *stream);
+
 /* The sketch operator itself, for checks and small problems: S[k, i] for
  * k < s, i < m as defined under ls_sketch_opts_t, rounded as the sketch in
- * format fmt (LS_FP64 or LS_BF16) uses it, unscaled (Omega = S / sqrt(s)).
+ * format fmt (LS_FP64, LS_BF16, LS_FP16 or LS_FP8E4M3) uses it, unscaled
+ * (Omega = S / sqrt(s)).
  * S: device, binary64, s x m column major, lds >= s.  Does not synchronise. */
 int ls_omega(uint64_t seed, uint32_t prob_id, int64_t s, int64_t m, ls_prec_t fmt,
              double *S, int64_t lds, void *stream);

@@ -18,6 +18,7 @@ from .api import (  # noqa: F401
     ls_qr_r,
     ls_sketch,
     ls_solve,
+    ls_solve_batched,
     precs,
     problem,
     sketch_opts,

@@ -26,7 +26,7 @@ class Precs(ctypes.Structure):
 
 class SketchOpts(ctypes.Structure):
     _fields_ = [("s", ctypes.c_int64), ("seed", ctypes.c_uint64), ("prob_id", ctypes.c_uint32),
-                ("terms", ctypes.c_int32)]
+                ("terms", ctypes.c_int32), ("col_scale", ctypes.c_int32)]
 
 
 class IterOpts(ctypes.Structure):
@@ -76,6 +76,11 @@ SIGNATURES = {
     "ls_omega": (ctypes.c_int, [ctypes.c_uint64, u32, i64, i64, ctypes.c_int, vp, i64, vp]),
     "ls_philox": (ctypes.c_int, [u32, u32, u32, u32, u32, u32, i64, vp, vp]),
     "ls_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "ls_workspace_size_batched": (ctypes.c_int, [ctypes.c_int, P(Problem), P(SketchOpts), P(Precs), P(IterOpts),
+                                                 ctypes.c_int, P(ctypes.c_size_t)]),
+    "ls_solve_batched": (ctypes.c_int, [ctypes.c_int, P(Problem), P(SketchOpts), P(Precs), P(IterOpts),
+                                        P(ctypes.c_void_p), P(ctypes.c_void_p), P(Stats), ctypes.c_int, vp,
+                                        ctypes.c_size_t, vp]),
 }
 
 _lib = None

@@ -49,8 +49,8 @@ def precs(u_s="bf16", u_qr="f32", u="f32", u_r="f64", u_A=None, u_L=None, u_R=No
                    u_A=B.PREC[u_A], u_L=B.PREC[u_L or u_A], u_R=B.PREC[u_R or u_A])
 
 
-def sketch_opts(s=0, seed=0, prob_id=0, terms=1) -> B.SketchOpts:
-    return B.SketchOpts(s=s, seed=seed, prob_id=prob_id, terms=terms)
+def sketch_opts(s=0, seed=0, prob_id=0, terms=1, col_scale=0) -> B.SketchOpts:
+    return B.SketchOpts(s=s, seed=seed, prob_id=prob_id, terms=terms, col_scale=col_scale)
 
 
 def iter_opts(n, u="f32", **kw) -> B.IterOpts:
@@ -80,10 +80,12 @@ def workspace_size(P, so, pr, io) -> int:
     return n.value
 
 
-def ls_sketch(At, b, s, seed=0, u_s="bf16", terms=1, prob_id=0, ws=None):
-    """Y = Omega [A b] (s x (n+1), float64; returned as a (n+1, s) tensor = column-major Y)."""
+def ls_sketch(At, b, s, seed=0, u_s="bf16", terms=1, prob_id=0, col_scale=0, ws=None):
+    """Y = Omega [A b] (s x (n+1), float64; returned as a (n+1, s) tensor = column-major Y).
+
+    u_s: "f64", "bf16", "f16" or "e4m3"; col_scale 0 = automatic (on for f16 and e4m3)."""
     P = problem(At, b)
-    so = sketch_opts(s=s, seed=seed, prob_id=prob_id, terms=terms)
+    so = sketch_opts(s=s, seed=seed, prob_id=prob_id, terms=terms, col_scale=col_scale)
     pr = precs(u_s=u_s, u_qr="f64", u="f64", u_r="f64")
     if ws is None:
         ws = workspace(workspace_size(P, so, pr, iter_opts(P.n, "f64")), At.device)
@@ -94,7 +96,7 @@ def ls_sketch(At, b, s, seed=0, u_s="bf16", terms=1, prob_id=0, ws=None):
 
 
 def ls_qr_r(Yt: torch.Tensor, u_qr="f32", ws=None):
-    """R factor (ncols x ncols, diag > 0) of Y given as Yt (ncols, s) float64; Yt is overwritten.
+    """R factor (ncols x ncols, diag > 0) of Y given as Yt (ncols, s) float64 (left unchanged).
 
     Returns Rt (ncols, ncols) = the column-major R, i.e. R = Rt.T.
     """
@@ -145,10 +147,10 @@ def ls_lsir_gmres(At, b, Rt, x, r, pr=None, r_given=False, ws=None, **opts):
 class Solver:
     """Reusable ls_solve call: holds the options and one workspace for a problem shape."""
 
-    def __init__(self, At, b, s=0, seed=0, prob_id=0, terms=1, pr=None, **opts):
+    def __init__(self, At, b, s=0, seed=0, prob_id=0, terms=1, pr=None, col_scale=0, **opts):
         self.P = problem(At, b)
         self.At, self.b = At, b
-        self.so = sketch_opts(s=s, seed=seed, prob_id=prob_id, terms=terms)
+        self.so = sketch_opts(s=s, seed=seed, prob_id=prob_id, terms=terms, col_scale=col_scale)
         self.pr = pr or precs()
         self.io = iter_opts(self.P.n, "f64" if self.pr.u == B.FP64 else "f32", **opts)
         self.ws = workspace(workspace_size(self.P, self.so, self.pr, self.io), At.device)
@@ -165,11 +167,39 @@ class Solver:
         return rc
 
 
-def ls_solve(At, b, s=0, seed=0, terms=1, pr=None, **opts):
+def ls_solve(At, b, s=0, seed=0, terms=1, pr=None, col_scale=0, prob_id=0, **opts):
     """The whole method.  Returns (x, r, status, stats dict)."""
-    S = Solver(At, b, s=s, seed=seed, terms=terms, pr=pr, **opts)
+    S = Solver(At, b, s=s, seed=seed, prob_id=prob_id, terms=terms, pr=pr, col_scale=col_scale, **opts)
     rc = S()
     return S.x, S.r, rc, S.stats.as_dict()
+
+
+def ls_solve_batched(problems, s=0, seeds=None, terms=1, pr=None, col_scale=0, nworkers=0, **opts):
+    """The whole method for a list of (At, b) problems on one device.
+
+    Returns (xs, rs, status, list of stats dicts); s = 0 uses 4 n per problem.
+    """
+    nprob = len(problems)
+    Ps = (B.Problem * nprob)(*[problem(At, b) for At, b in problems])
+    seeds = seeds if seeds is not None else [0] * nprob
+    sos = (B.SketchOpts * nprob)(*[sketch_opts(s=s, seed=seeds[i], prob_id=i, terms=terms, col_scale=col_scale)
+                                   for i in range(nprob)])
+    pr = pr or precs()
+    io = iter_opts(max(p.n for p in Ps), "f64" if pr.u == B.FP64 else "f32", **opts)
+    nbytes = ctypes.c_size_t(0)
+    _check(B.load().ls_workspace_size_batched(nprob, Ps, sos, ctypes.byref(pr), ctypes.byref(io), nworkers,
+                                              ctypes.byref(nbytes)), "ls_workspace_size_batched")
+    dev = problems[0][0].device
+    ws = workspace(nbytes.value, dev)
+    xs = [torch.empty(Ps[i].n, dtype=torch.float64, device=dev) for i in range(nprob)]
+    rs = [torch.empty(Ps[i].m, dtype=torch.float64, device=dev) for i in range(nprob)]
+    xp = (ctypes.c_void_p * nprob)(*[t.data_ptr() for t in xs])
+    rp = (ctypes.c_void_p * nprob)(*[t.data_ptr() for t in rs])
+    stats = (B.Stats * nprob)()
+    rc = B.load().ls_solve_batched(nprob, Ps, sos, ctypes.byref(pr), ctypes.byref(io), xp, rp, stats, nworkers,
+                                   ws.data_ptr(), ws.numel(), _stream())
+    _check(rc, "ls_solve_batched")
+    return xs, rs, rc, [stats[i].as_dict() for i in range(nprob)]
 
 
 def ls_omega(seed, s, m, fmt="bf16", prob_id=0, device="cuda"):

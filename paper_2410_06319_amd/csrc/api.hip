@@ -1,6 +1,11 @@
 // C ABI of libls: argument checking, workspace carving and the stage drivers.
+#include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <thread>
+#include <vector>
 
 #include "common.h"
 #include "kernels.h"
@@ -28,9 +33,8 @@ int check_sketch(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_
   const int64_t s = sketch_rows(P, so);
   if (s < P->n + 1) return LS_E_ARG;
   if (s > 8192) return LS_E_UNSUPPORTED;
-  if (u_s == LS_BF16) {
+  if (u_s == LS_BF16 || u_s == LS_FP16 || u_s == LS_FP8E4M3) {
     if (so->terms < 1 || so->terms > 3) return LS_E_ARG;
-    if (P->store != LS_FP32) return LS_E_UNSUPPORTED;
   } else if (u_s == LS_FP64) {
     if (so->terms > 1) return LS_E_ARG;
   } else {
@@ -152,6 +156,52 @@ struct Timer {
 
 }  // namespace
 
+namespace {
+// ------------------------------------------------------------------ batches
+// Internal streams for the workers of a batch, created once per device at
+// the default priority.
+constexpr int kMaxWorkers = 16;
+struct WorkerStreams {
+  std::mutex mu;
+  hipStream_t st[kMaxWorkers] = {};
+  int made = 0;
+};
+WorkerStreams& worker_streams(int dev) {
+  static WorkerStreams pools[64];
+  return pools[(dev >= 0 && dev < 64) ? dev : 0];
+}
+int worker_stream(int dev, int k, hipStream_t* out) {
+  WorkerStreams& w = worker_streams(dev);
+  std::lock_guard<std::mutex> g(w.mu);
+  while (w.made <= k) {
+    LS_HIP_TRY(hipStreamCreateWithFlags(&w.st[w.made], hipStreamNonBlocking));
+    ++w.made;
+  }
+  *out = w.st[k];
+  return LS_OK;
+}
+
+int clamp_workers(int nworkers, int nprob) {
+  int k = (nworkers > 0) ? nworkers : 8;
+  if (k > kMaxWorkers) k = kMaxWorkers;
+  if (k > nprob) k = nprob;
+  return k < 1 ? 1 : k;
+}
+
+// Largest single-problem workspace of the batch.
+int batch_slice_bytes(int nprob, const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t* pr,
+                      const ls_iter_opts_t* io, size_t* out) {
+  size_t mx = 0;
+  for (int i = 0; i < nprob; ++i) {
+    size_t b = 0;
+    LS_TRY(ls_workspace_size(&P[i], &so[i], pr, io, &b));
+    mx = std::max(mx, b);
+  }
+  *out = ls_align256(mx);
+  return LS_OK;
+}
+}  // namespace
+
 extern "C" {
 
 void ls_default_iter_opts(int64_t n, ls_prec_t u, ls_iter_opts_t* o) {
@@ -198,7 +248,7 @@ int ls_workspace_size(const ls_problem_t* P, const ls_sketch_opts_t* so, const l
                  + ls_align256(8 * (size_t)(P->m + n))           // saved x0 for the fallback
                  + b_bytes(P, pr->u)                             // B = A R^-1 for LSQR
                  + (second_b(pr, &io) ? b_bytes(P, LS_FP64) : 0); // binary64 B for FGMRES
-  size_t scratch = sp.operand_bytes + sp.partial_bytes;
+  size_t scratch = sp.operand_bytes + sp.partial_bytes + sp.exp_bytes;
   const size_t q = qr_workspace(s, n + 1, pr->u_qr);
   if (q > scratch) scratch = q;
   const size_t it = iter_bytes(P, pr, &io);
@@ -214,7 +264,7 @@ int ls_sketch(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s, 
   const int64_t s = sketch_rows(P, so);
   if (!Y || ldy < s) return LS_E_ARG;
   const SketchPlan sp = sketch_plan(P->m, P->n, s, u_s, so->terms);
-  if (!ws || ws_bytes < sp.operand_bytes + sp.partial_bytes) return LS_E_WORKSPACE;
+  if (!ws || ws_bytes < sp.operand_bytes + sp.partial_bytes + sp.exp_bytes) return LS_E_WORKSPACE;
   prof_reset(false);
   return sketch_run(P, so, u_s, sp, s, Y, ldy, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
 }
@@ -394,7 +444,7 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
 int ls_omega(uint64_t seed, uint32_t prob_id, int64_t s, int64_t m, ls_prec_t fmt, double* S, int64_t lds,
              void* stream) {
   if (!S || s < 1 || m < 1 || lds < s || s > 65535) return LS_E_ARG;
-  if (!prec_is(fmt, LS_FP64, LS_BF16)) return LS_E_UNSUPPORTED;
+  if (!(fmt == LS_FP64 || fmt == LS_BF16 || fmt == LS_FP16 || fmt == LS_FP8E4M3)) return LS_E_UNSUPPORTED;
   return omega_run(seed, prob_id, s, m, fmt, S, lds, static_cast<hipStream_t>(stream));
 }
 
@@ -403,6 +453,97 @@ int ls_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, u
   if (!out || count < 0) return LS_E_ARG;
   if (count == 0) return LS_OK;
   return philox_run(c0, c1, c2, c3, k0, k1, count, out, static_cast<hipStream_t>(stream));
+}
+
+int ls_workspace_size_batched(int nprob, const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t* pr,
+                              const ls_iter_opts_t* io, int nworkers, size_t* bytes) {
+  if (nprob < 1 || !P || !so || !pr || !bytes) return LS_E_ARG;
+  size_t slice = 0;
+  LS_TRY(batch_slice_bytes(nprob, P, so, pr, io, &slice));
+  *bytes = slice * (size_t)clamp_workers(nworkers, nprob);
+  return LS_OK;
+}
+
+int ls_solve_batched(int nprob, const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t* pr,
+                     const ls_iter_opts_t* io_in, double* const* x, double* const* r, ls_stats_t* stats,
+                     int nworkers, void* ws, size_t ws_bytes, void* stream) {
+  if (nprob < 1 || !P || !so || !pr || !x || !r || !ws) return LS_E_ARG;
+  for (int i = 0; i < nprob; ++i) {
+    LS_TRY(check_problem(&P[i]));
+    LS_TRY(check_sketch(&P[i], &so[i], pr->u_s));
+    if (!x[i] || !r[i]) return LS_E_ARG;
+  }
+  LS_TRY(check_precs(pr));
+  ls_iter_opts_t io;
+  if (io_in) {
+    io = *io_in;
+  } else {
+    std::memset(&io, 0, sizeof(io));
+  }
+  io.profile = 0;
+  const int K = clamp_workers(nworkers, nprob);
+  size_t slice = 0;
+  LS_TRY(batch_slice_bytes(nprob, P, so, pr, io_in ? &io : nullptr, &slice));
+  if (ws_bytes < slice * (size_t)K) return LS_E_WORKSPACE;
+  int dev = 0;
+  LS_HIP_TRY(hipGetDevice(&dev));
+  hipStream_t caller = static_cast<hipStream_t>(stream);
+  hipStream_t wst[kMaxWorkers];
+  for (int k = 0; k < K; ++k) LS_TRY(worker_stream(dev, k, &wst[k]));
+
+  // work lists: largest problems first, each to the worker with the least work so far
+  std::vector<int> order(nprob);
+  for (int i = 0; i < nprob; ++i) order[i] = i;
+  auto work = [&](int i) { return (double)P[i].m * (double)P[i].n * (double)(P[i].n + 8); };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+  std::vector<std::vector<int>> lists(K);
+  std::vector<double> load(K, 0.0);
+  for (int i : order) {
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    lists[k].push_back(i);
+    load[k] += work(i);
+  }
+
+  // the workers start after the caller's earlier work and the caller's stream
+  // continues after all of them
+  hipEvent_t start;
+  LS_HIP_TRY(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+  LS_HIP_TRY(hipEventRecord(start, caller));
+  std::vector<int> status(nprob, LS_OK);
+  std::vector<ls_stats_t> local(stats ? 0 : nprob);
+  std::atomic<int> hip_err{0};
+  std::vector<std::thread> th;
+  for (int k = 0; k < K; ++k) {
+    th.emplace_back([&, k]() {
+      if (hipSetDevice(dev) != hipSuccess || hipStreamWaitEvent(wst[k], start, 0) != hipSuccess) {
+        hip_err = 1;
+        for (int i : lists[k]) status[i] = LS_E_HIP;
+        return;
+      }
+      char* slice_ws = static_cast<char*>(ws) + slice * (size_t)k;
+      for (int i : lists[k]) {
+        ls_stats_t* S = stats ? &stats[i] : &local[i];
+        status[i] = ls_solve(&P[i], &so[i], pr, io_in ? &io : nullptr, x[i], r[i], S, slice_ws, slice, wst[k]);
+      }
+    });
+  }
+  for (auto& t : th) t.join();
+  std::vector<hipEvent_t> done(K);
+  int rc_ev = LS_OK;
+  for (int k = 0; k < K; ++k) {
+    if (hipEventCreateWithFlags(&done[k], hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(done[k], wst[k]) != hipSuccess || hipStreamWaitEvent(caller, done[k], 0) != hipSuccess)
+      rc_ev = LS_E_HIP;
+  }
+  for (int k = 0; k < K; ++k) (void)hipEventDestroy(done[k]);
+  (void)hipEventDestroy(start);
+  if (hip_err || rc_ev != LS_OK) return LS_E_HIP;
+  int rc = LS_OK;
+  for (int i = 0; i < nprob; ++i) {
+    if (status[i] < 0) return status[i];
+    if (status[i] != LS_OK) rc = status[i];
+  }
+  return rc;
 }
 
 }  // extern "C"

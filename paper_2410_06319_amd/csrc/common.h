@@ -87,6 +87,59 @@ __device__ __forceinline__ float ls_bf16_bits_to_f32(uint16_t h) {
   return __uint_as_float(((uint32_t)h) << 16);
 }
 
+// ---------------------------------------------------------------- narrow formats
+// Nearest value of a format with t mantissa bits after the point and minimum
+// normal exponent emin (ties to even), computed exactly: the quantum at x's
+// exponent (clamped to emin, so subnormals are kept) is a power of two, so
+// x / quantum is exact and rint rounds it; beyond fmax the result saturates
+// (e4m3) or becomes infinite.
+struct LsFmt {
+  int t, emin;
+  double fmax;
+  bool saturate;
+};
+__host__ __device__ constexpr LsFmt ls_fmt_bf16() { return {7, -126, 0x1.fep127, false}; }
+__host__ __device__ constexpr LsFmt ls_fmt_f16() { return {10, -14, 65504.0, false}; }
+__host__ __device__ constexpr LsFmt ls_fmt_e4m3() { return {3, -6, 448.0, true}; }
+
+__device__ __forceinline__ double ls_round_fmt(double x, LsFmt f) {
+  if (x == 0.0 || !isfinite(x)) return x;
+  int e;
+  (void)frexp(fabs(x), &e);   // |x| = g 2^e, g in [0.5, 1): leading bit 2^(e-1)
+  int ex = e - 1;
+  if (ex < f.emin) ex = f.emin;
+  const double q = ldexp(1.0, ex - f.t);
+  double r = rint(x / q) * q;
+  if (fabs(r) > f.fmax) r = f.saturate ? copysign(f.fmax, r) : copysign((double)INFINITY, r);
+  return r;
+}
+__device__ __forceinline__ float ls_round_fmt_f(float x, LsFmt f) {
+  if (x == 0.0f || !isfinite(x)) return x;
+  int e;
+  (void)frexpf(fabsf(x), &e);
+  int ex = e - 1;
+  if (ex < f.emin) ex = f.emin;
+  const float q = ldexpf(1.0f, ex - f.t);
+  float r = rintf(x / q) * q;
+  if (fabsf(r) > (float)f.fmax) r = f.saturate ? copysignf((float)f.fmax, r) : copysignf(INFINITY, r);
+  return r;
+}
+// OCP e4m3 bits of a value already representable in e4m3 (|v| <= 448).
+__device__ __forceinline__ uint8_t ls_e4m3_bits(double v) {
+  const uint8_t sgn = (v < 0.0 || (v == 0.0 && signbit(v))) ? 0x80 : 0x00;
+  const double a = fabs(v);
+  if (a == 0.0) return sgn;
+  int e;
+  const double g = frexp(a, &e);        // a = g 2^e, leading bit 2^(e-1)
+  if (e - 1 < -6) return (uint8_t)(sgn | (uint8_t)(a * 512.0));   // subnormal: a = m 2^-9
+  const int mant = (int)((2.0 * g - 1.0) * 8.0);
+  return (uint8_t)(sgn | (uint8_t)((e - 1 + 7) << 3) | (uint8_t)mant);
+}
+// IEEE binary16 bits of a value already representable in binary16.
+__device__ __forceinline__ uint16_t ls_f16_bits(double v) {
+  return __builtin_bit_cast(uint16_t, (_Float16)(float)v);
+}
+
 // ---------------------------------------------------------------- reductions
 template <typename T>
 __device__ __forceinline__ T ls_wave_sum(T v) {

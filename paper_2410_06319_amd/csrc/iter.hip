@@ -1002,7 +1002,7 @@ __global__ __launch_bounds__(1024) void k_fg_col(int64_t m, int64_t n, const TB*
       const int64_t cc = (int64_t)blockIdx.x * 16 + q;
       if (cc < n) s += ((c == j) ? vjx[q] : F.V[m + cc + (int64_t)c * F.ldv]) * wx[q];
     }
-    hxpart[(int64_t)c * gridDim.x + blockIdx.x] = s;
+    hxpart[(int64_t)c * ncb + blockIdx.x] = s;
   }
 }
 
@@ -1175,15 +1175,16 @@ __global__ __launch_bounds__(kUtThreads) void k_fg_dx(const double* __restrict__
 }
 
 // ------------------------------------------------------------------ host helpers
+// Device properties are read once (thread-safe static initialisation); the
+// library assumes the devices of one process are alike.
 size_t device_lds_limit() {
-  static size_t cached = 0;
-  if (cached == 0) {
+  static const size_t cached = [] {
+    size_t v = 0;
     int dev = 0;
     hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-      cached = prop.sharedMemPerBlock;
-    if (cached == 0) cached = 64 * 1024;
-  }
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) v = prop.sharedMemPerBlock;
+    return v ? v : (size_t)64 * 1024;
+  }();
   return cached;
 }
 
@@ -1205,14 +1206,13 @@ int64_t pan_count(int64_t m, size_t elt) { return ls_cdiv(m, (int64_t)(16 / elt)
 
 // Resident waves per SIMD targeted by the panel passes (LS_PASS_WAVES, 1..8).
 int pan_occ() {
-  static int occ = 0;
-  if (occ == 0) {
-    occ = 2;
+  static const int occ = [] {
     if (const char* e = getenv("LS_PASS_WAVES")) {
       const int v = atoi(e);
-      if (v >= 1 && v <= 8) occ = v;
+      if (v >= 1 && v <= 8) return v;
     }
-  }
+    return 2;
+  }();
   return occ;
 }
 
@@ -1231,14 +1231,13 @@ int pan_grid(int64_t npan, int ncu) {
 int device_lds_bytes() { return (int)device_lds_limit(); }
 
 int device_cu_count() {
-  static int cached = 0;
-  if (cached == 0) {
+  static const int cached = [] {
+    int v = 0;
     int dev = 0;
     hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-      cached = prop.multiProcessorCount;
-    if (cached <= 0) cached = 256;
-  }
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) v = prop.multiProcessorCount;
+    return v > 0 ? v : 256;
+  }();
   return cached;
 }
 

@@ -16,15 +16,19 @@ struct SketchPlan {
   int nb;                 // binary64 path: 16-column MFMA blocks per wave
   int kstep;              // rows of A per MFMA step
   int terms;
-  int64_t bn;             // bf16 path: columns per block
-  int64_t ns, nn;         // bf16 path: row tiles of S (128 rows), column tiles
-  int64_t nkb;            // bf16 path: K-blocks of 32 rows in the packed operand
-  int64_t kb_per_split;   // bf16 path: K-blocks per split
+  int64_t bn;             // narrow formats: columns per block
+  int64_t ns, nn;         // narrow formats: row tiles of S (128 rows), column tiles
+  int64_t nkb;            // narrow formats: K-blocks of 32 rows in the packed operand
+  int64_t kb_per_split;   // narrow formats: K-blocks per split
+  int ebytes;             // bytes per operand element
+  size_t exp_bytes;       // column exponents (narrow formats)
   size_t operand_bytes;   // packed [A b]
-  size_t partial_bytes;   // per-split partial sketches
+  size_t partial_bytes;   // per-split partial sketches (followed by the exponents)
 };
 
 SketchPlan sketch_plan(int64_t m, int64_t n, int64_t s, ls_prec_t u_s, int terms);
+// Whether the sketch scales the columns of [A b] by powers of two (Section 3.2).
+bool sketch_colscale(ls_prec_t u_s, int32_t col_scale);
 int sketch_run(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s, const SketchPlan& p,
                int64_t s, double* Y, int64_t ldy, char* ws, hipStream_t st);
 int omega_run(uint64_t seed, uint32_t prob, int64_t s, int64_t m, ls_prec_t fmt, double* S, int64_t lds,
@@ -73,7 +77,7 @@ int device_lds_bytes();   // LDS available to one block
 
 namespace ls {
 // Optional per-kernel timing with HIP events (enabled per call through
-// ls_iter_opts_t.profile).  Not thread-safe: one profiled call at a time.
+// ls_iter_opts_t.profile).  The record is per host thread.
 enum ProfClass { kProfSketch = 0, kProfLsqrPass = 1, kProfFgPass = 2, kProfResidPass = 3, kProfCgs = 4 };
 void prof_reset(bool on);
 void prof_begin(int cls, hipStream_t st);

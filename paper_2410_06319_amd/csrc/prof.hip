@@ -1,5 +1,6 @@
 // Opt-in per-kernel timing: an event pair around every launch of the
-// profiled kernel classes, summed after the call has synchronised.
+// profiled kernel classes, summed after the call has synchronised.  The
+// record is per host thread.
 #include <vector>
 
 #include "common.h"
@@ -12,9 +13,10 @@ struct Pair {
   int cls;
   double work;
 };
-bool g_on = false;
-std::vector<Pair> g_pool;
-size_t g_used = 0;
+// per host thread: concurrent calls on different threads keep separate records
+thread_local bool g_on = false;
+thread_local std::vector<Pair> g_pool;
+thread_local size_t g_used = 0;
 }  // namespace
 
 void prof_reset(bool on) {

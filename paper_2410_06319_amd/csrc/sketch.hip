@@ -20,35 +20,110 @@
 #include "kernels.h"
 
 typedef __bf16 ls_bf16x8 __attribute__((__vector_size__(8 * sizeof(__bf16))));
+typedef _Float16 ls_f16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t ls_u32x2 __attribute__((ext_vector_type(2)));
 typedef float ls_floatx4 __attribute__((ext_vector_type(4)));
 typedef double ls_doublex4 __attribute__((ext_vector_type(4)));
 typedef uint32_t ls_u32x4 __attribute__((ext_vector_type(4)));
 
-// ------------------------------------------------------------------ packing
-// K-panel layout of the bf16 operand: for term t and K-block kb (rows
+// ------------------------------------------------------------------ narrow-format operand
+// Column exponents (Section 3.2 column scaling, power-of-two constant):
+// e_j = the largest integer with max_i |[A b]_ij| 2^e_j <= the format's
+// largest finite value (0 for a zero column).  One block per column.
+template <typename TA>
+__global__ __launch_bounds__(256) void k_colexp(const TA* __restrict__ A, int64_t lda, const TA* __restrict__ b,
+                                                int64_t m, int64_t n, double fmaxv, int32_t* __restrict__ e) {
+  __shared__ double red[4];
+  const int64_t j = blockIdx.x;
+  const TA* col = (j < n) ? A + j * lda : b;
+  double mx = 0.0;
+  for (int64_t i = threadIdx.x; i < m; i += 256) mx = fmax(mx, fabs((double)col[i]));
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    int32_t ej = 0;
+    if (mx > 0.0) {
+      int E, G;
+      const double f = frexp(mx, &E);
+      const double F = frexp(fmaxv, &G);
+      ej = (f <= F) ? G - E : G - E - 1;
+    }
+    e[j] = ej;
+  }
+}
+
+// Formats of the narrow sketch: element bits, S rounding, MFMA.  An operand
+// fragment is the 8 consecutive K elements one lane supplies to a
+// 16x16x32 MFMA (16 bytes for 16-bit formats, 8 for e4m3).
+template <int FMT>
+struct SkFmt;
+template <>
+struct SkFmt<LS_BF16> {
+  using E = uint16_t;
+  using frag = ls_u32x4;
+  static constexpr LsFmt fmt() { return ls_fmt_bf16(); }
+  static __device__ __forceinline__ E from_f32(float z) { return ls_f32_to_bf16_bits(z); }
+  static __device__ __forceinline__ E from_exact(double v) { return ls_f32_to_bf16_bits((float)v); }
+  static __device__ __forceinline__ ls_floatx4 mma(frag a, frag b, ls_floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(ls_bf16x8, a), __builtin_bit_cast(ls_bf16x8, b),
+                                                   c, 0, 0, 0);
+  }
+};
+template <>
+struct SkFmt<LS_FP16> {
+  using E = uint16_t;
+  using frag = ls_u32x4;
+  static constexpr LsFmt fmt() { return ls_fmt_f16(); }
+  static __device__ __forceinline__ E from_f32(float z) { return __builtin_bit_cast(uint16_t, (_Float16)z); }
+  static __device__ __forceinline__ E from_exact(double v) { return ls_f16_bits(v); }
+  static __device__ __forceinline__ ls_floatx4 mma(frag a, frag b, ls_floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(ls_f16x8, a), __builtin_bit_cast(ls_f16x8, b), c,
+                                                  0, 0, 0);
+  }
+};
+template <>
+struct SkFmt<LS_FP8E4M3> {
+  using E = uint8_t;
+  using frag = ls_u32x2;
+  static constexpr LsFmt fmt() { return ls_fmt_e4m3(); }
+  static __device__ __forceinline__ E from_f32(float z) { return ls_e4m3_bits((double)ls_round_fmt_f(z, fmt())); }
+  static __device__ __forceinline__ E from_exact(double v) { return ls_e4m3_bits(v); }
+  static __device__ __forceinline__ ls_floatx4 mma(frag a, frag b, ls_floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(__builtin_bit_cast(long, a), __builtin_bit_cast(long, b), c, 0,
+                                                      0, 0);
+  }
+};
+
+// K-panel layout of the narrow operand: for term t and K-block kb (rows
 // 32 kb .. 32 kb + 31 of [A b]) the n_pad columns follow each other with
-// their 32 values contiguous: element (i, j) of term t sits at
+// their 32 elements contiguous: element (i, j) of term t sits at
 // ((t nkb + i / 32) n_pad + j) 32 + i % 32, nkb = m_pad / 32.  Zero outside
-// i < m, j <= n.  The parts satisfy x = T_0 + T_1 + ... + rest, each T_t the
-// bf16 rounding of what is left (exact differences in binary32).
-__global__ __launch_bounds__(256) void k_pack_bf16(const float* __restrict__ A, int64_t lda,
-                                                   const float* __restrict__ b, int64_t m, int64_t n,
-                                                   int terms, uint16_t* __restrict__ Tt,
-                                                   int64_t m_pad, int64_t n_pad) {
+// i < m, j <= n.  With column exponents e the column is first scaled by 2^e_j
+// (exact).  The parts satisfy x = T_0 + T_1 + ... + rest, each T_t the
+// format's rounding of what is left (differences exact in binary64).
+template <typename TA, int FMT>
+__global__ __launch_bounds__(256) void k_pack_lp(const TA* __restrict__ A, int64_t lda, const TA* __restrict__ b,
+                                                 int64_t m, int64_t n, int terms, const int32_t* __restrict__ e,
+                                                 typename SkFmt<FMT>::E* __restrict__ Tt, int64_t m_pad,
+                                                 int64_t n_pad) {
+  using F = SkFmt<FMT>;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t j = blockIdx.y;
   if (i >= m_pad || j >= n_pad) return;
-  float x = 0.0f;
+  double x = 0.0;
   if (i < m) {
-    if (j < n) x = A[i + j * lda];
-    else if (j == n) x = b[i];
+    if (j < n) x = (double)A[i + j * lda];
+    else if (j == n) x = (double)b[i];
+    if (e && j <= n) x = ldexp(x, e[j]);
   }
   const int64_t nkb = m_pad / 32;
   const int64_t pos = ((i >> 5) * n_pad + j) * 32 + (i & 31);
   for (int t = 0; t < terms; ++t) {
-    const uint16_t h = ls_f32_to_bf16_bits(x);
-    Tt[t * nkb * n_pad * 32 + pos] = h;
-    x = x - ls_bf16_bits_to_f32(h);   // exact (Sterbenz)
+    const double r = ls_round_fmt(x, F::fmt());
+    Tt[t * nkb * n_pad * 32 + pos] = F::from_exact(r);
+    x = x - r;
   }
 }
 
@@ -67,30 +142,38 @@ __global__ __launch_bounds__(256) void k_pack_f64(const TA* __restrict__ A, int6
   M[j * m_pad + i] = x;
 }
 
-// ------------------------------------------------------------------ bf16 MFMA sketch
-// v_mfma_f32_16x16x32_bf16 operands: lane l supplies row (l % 16) of S and
-// column (l % 16) of the packed operand, at the 8 consecutive K indices
-// 8 (l / 16) .. +7 of the step (one 16-byte quarter); the product sums over
+// ------------------------------------------------------------------ narrow MFMA sketch
+// v_mfma_f32_16x16x32_{bf16,f16,fp8_fp8} operands: lane l supplies row (l % 16)
+// of S and column (l % 16) of the packed operand, at the 8 consecutive K
+// indices 8 (l / 16) .. +7 of the step (one fragment); the product sums over
 // the same K set on both sides.  Result: lane l holds D[4 (l/16) + r][l % 16].
+// (On gfx950 the fp8 product reads OCP e4m3, the format the oracle rounds to.)
 constexpr int kSkThreads = 512;
 constexpr int kSkRows = 128;   // rows of S per block
 
-// 16-byte slot of quarter q of LDS row r (rows of 32 bf16 = 4 quarters).
-__device__ __forceinline__ int sk_slot(int r, int q) { return r * 4 + (q ^ ((r >> 2) & 3)); }
+// Fragment slot of quarter q of LDS row r (rows of 32 elements = 4
+// fragments); the XOR with bits of r makes the 16 lanes of an operand read hit
+// distinct banks (16-byte fragments: bits 2..3; 8-byte fragments: bits 3..4).
+template <int FB>
+__device__ __forceinline__ int sk_slot(int r, int q) {
+  return r * 4 + (q ^ ((r >> ((FB == 16) ? 2 : 3)) & 3));
+}
 
-template <int BN, int TERMS>
-__global__ __launch_bounds__(kSkThreads) void k_sketch_bf16(const uint16_t* __restrict__ Tt, int64_t nkb,
-                                                            int64_t n_pad, int64_t kb_per_split, int ns,
-                                                            int nn, uint32_t key0, uint32_t key1,
-                                                            uint32_t prob, float* __restrict__ Yp,
-                                                            int64_t s_pad) {
+template <int FMT, int BN, int TERMS>
+__global__ __launch_bounds__(kSkThreads) void k_sketch_lp(const typename SkFmt<FMT>::E* __restrict__ Tt, int64_t nkb,
+                                                          int64_t n_pad, int64_t kb_per_split, int ns, int nn,
+                                                          uint32_t key0, uint32_t key1, uint32_t prob,
+                                                          float* __restrict__ Yp, int64_t s_pad) {
+  using F = SkFmt<FMT>;
+  using frag = typename F::frag;
+  constexpr int FB = sizeof(frag);
   constexpr int CT = BN / 64;                  // 16-column tiles per wave
   // column tiles whose operand fragments are held in registers at once
   constexpr int HALF = (TERMS >= 3 && CT >= 4) ? CT / 4 : (CT >= 2) ? CT / 2 : 1;
-  constexpr int BQ = TERMS * BN * 4;           // 16-byte quarters of the operand tile
+  constexpr int BQ = TERMS * BN * 4;           // fragments of the operand tile
   constexpr int BPT = (BQ + kSkThreads - 1) / kSkThreads;
-  __shared__ ls_u32x4 As[kSkRows * 4];
-  __shared__ ls_u32x4 Bs[TERMS * BN * 4];
+  __shared__ frag As[kSkRows * 4];
+  __shared__ frag Bs[TERMS * BN * 4];
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int wave = t >> 6;
@@ -111,7 +194,7 @@ __global__ __launch_bounds__(kSkThreads) void k_sketch_bf16(const uint16_t* __re
   const int grow = t & (kSkRows - 1);
   const int gq = t >> 7;
   const uint32_t srow = (uint32_t)(row0 + grow);
-  auto gen = [&](int64_t kb) -> ls_u32x4 {
+  auto gen = [&](int64_t kb) -> frag {
     const uint32_t q = (uint32_t)((kb * 32 + 8 * gq) >> 2);
     uint32_t a0 = q, a1 = srow, a2 = prob, a3 = 0u;
     uint32_t c0 = q + 1u, c1 = srow, c2 = prob, c3 = 0u;
@@ -122,15 +205,23 @@ __global__ __launch_bounds__(kSkThreads) void k_sketch_bf16(const uint16_t* __re
     ls_box_muller_f32(a2, a3, zz[2], zz[3]);
     ls_box_muller_f32(c0, c1, zz[4], zz[5]);
     ls_box_muller_f32(c2, c3, zz[6], zz[7]);
-    ls_u32x4 w;
+    frag w;
+    if constexpr (sizeof(typename F::E) == 2) {
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
-      w[p] = (uint32_t)ls_f32_to_bf16_bits(zz[2 * p]) | ((uint32_t)ls_f32_to_bf16_bits(zz[2 * p + 1]) << 16);
+      for (int p = 0; p < 4; ++p)
+        w[p] = (uint32_t)F::from_f32(zz[2 * p]) | ((uint32_t)F::from_f32(zz[2 * p + 1]) << 16);
+    } else {
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+        w[p] = (uint32_t)F::from_f32(zz[4 * p]) | ((uint32_t)F::from_f32(zz[4 * p + 1]) << 8) |
+               ((uint32_t)F::from_f32(zz[4 * p + 2]) << 16) | ((uint32_t)F::from_f32(zz[4 * p + 3]) << 24);
+    }
     return w;
   };
-  // operand tile: quarter p = t + 512 u is (term, column, quarter) = (p / (4 BN), (p / 4) % BN, p % 4)
-  const int64_t term_stride = nkb * n_pad * 32;
-  auto loadb = [&](int64_t kb, ls_u32x4 (&reg)[BPT]) {
+  // operand tile: fragment p = t + 512 u is (term, column, quarter) = (p / (4 BN), (p / 4) % BN, p % 4)
+  const frag* Tf = reinterpret_cast<const frag*>(Tt);
+  const int64_t term_stride = nkb * n_pad * 4;   // fragments
+  auto loadb = [&](int64_t kb, frag (&reg)[BPT]) {
 #pragma unroll
     for (int u = 0; u < BPT; ++u) {
       const int p = t + kSkThreads * u;
@@ -138,18 +229,18 @@ __global__ __launch_bounds__(kSkThreads) void k_sketch_bf16(const uint16_t* __re
         const int term = p / (4 * BN);
         const int c = (p >> 2) % BN;
         const int q = p & 3;
-        reg[u] = *reinterpret_cast<const ls_u32x4*>(Tt + term * term_stride + (kb * n_pad + col0 + c) * 32 + 8 * q);
+        reg[u] = Tf[term * term_stride + (kb * n_pad + col0 + c) * 4 + q];
       }
     }
   };
-  auto storeb = [&](const ls_u32x4 (&reg)[BPT]) {
+  auto storeb = [&](const frag (&reg)[BPT]) {
 #pragma unroll
     for (int u = 0; u < BPT; ++u) {
       const int p = t + kSkThreads * u;
       if (p < BQ) {
         const int term = p / (4 * BN);
         const int c = (p >> 2) % BN;
-        Bs[term * BN * 4 + sk_slot(c, p & 3)] = reg[u];
+        Bs[term * BN * 4 + sk_slot<FB>(c, p & 3)] = reg[u];
       }
     }
   };
@@ -160,8 +251,8 @@ __global__ __launch_bounds__(kSkThreads) void k_sketch_bf16(const uint16_t* __re
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = ls_floatx4{0.f, 0.f, 0.f, 0.f};
 
-  ls_u32x4 sreg = ls_u32x4{0u, 0u, 0u, 0u};
-  ls_u32x4 breg[BPT];
+  frag sreg{};
+  frag breg[BPT];
   if (kb0 < kb1) {
     sreg = gen(kb0);
     loadb(kb0, breg);
@@ -169,7 +260,7 @@ __global__ __launch_bounds__(kSkThreads) void k_sketch_bf16(const uint16_t* __re
   const int fq = lane >> 4;   // operand quarter of this lane
   for (int64_t kb = kb0; kb < kb1; ++kb) {
     __syncthreads();   // the previous step's operands have been read
-    As[sk_slot(grow, gq)] = sreg;
+    As[sk_slot<FB>(grow, gq)] = sreg;
     storeb(breg);
     __syncthreads();
     if (kb + 1 < kb1) {   // next step's operand loads in flight and its S drawn during the products
@@ -178,22 +269,21 @@ __global__ __launch_bounds__(kSkThreads) void k_sketch_bf16(const uint16_t* __re
     }
 #pragma unroll
     for (int h = 0; h < CT; h += HALF) {
-      ls_bf16x8 bf[HALF][TERMS];
+      frag bf[HALF][TERMS];
 #pragma unroll
       for (int ct = 0; ct < HALF; ++ct) {
         const int c = wc * (BN / 4) + (h + ct) * 16 + (lane & 15);
 #pragma unroll
-        for (int tm = 0; tm < TERMS; ++tm) bf[ct][tm] = __builtin_bit_cast(ls_bf16x8, Bs[tm * BN * 4 + sk_slot(c, fq)]);
+        for (int tm = 0; tm < TERMS; ++tm) bf[ct][tm] = Bs[tm * BN * 4 + sk_slot<FB>(c, fq)];
       }
 #pragma unroll
       for (int rt = 0; rt < 4; ++rt) {
         const int r = wr * 64 + rt * 16 + (lane & 15);
-        const ls_bf16x8 af = __builtin_bit_cast(ls_bf16x8, As[sk_slot(r, fq)]);
+        const frag af = As[sk_slot<FB>(r, fq)];
 #pragma unroll
         for (int ct = 0; ct < HALF; ++ct)
 #pragma unroll
-          for (int tm = 0; tm < TERMS; ++tm)
-            acc[rt][h + ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf[ct][tm], acc[rt][h + ct], 0, 0, 0);
+          for (int tm = 0; tm < TERMS; ++tm) acc[rt][h + ct] = F::mma(af, bf[ct][tm], acc[rt][h + ct]);
       }
     }
   }
@@ -260,19 +350,22 @@ __global__ __launch_bounds__(256) void k_sketch_f64(const double* __restrict__ M
 }
 
 // ------------------------------------------------------------------ chunk combine
-// Y[k + j ldy] = scale * sum_z Yp[z][k + j s_pad], summed in binary64 in
+// Y[k + j ldy] = scale 2^-e_j sum_z Yp[z][k + j s_pad], summed in binary64 in
 // chunk order (deterministic).
 template <typename TP>
 __global__ __launch_bounds__(256) void k_sketch_combine(const TP* __restrict__ Yp, int64_t s_pad,
                                                         int64_t n_pad, int nsplit, int64_t s,
                                                         int64_t ncols, double scale,
+                                                        const int32_t* __restrict__ e,
                                                         double* __restrict__ Y, int64_t ldy) {
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t j = blockIdx.y;
   if (k >= s || j >= ncols) return;
   double acc = 0.0;
   for (int z = 0; z < nsplit; ++z) acc += (double)Yp[(int64_t)z * s_pad * n_pad + k + j * s_pad];
-  Y[k + j * ldy] = acc * scale;
+  acc *= scale;
+  if (e) acc = ldexp(acc, -e[j]);   // undo the column scaling (exact)
+  Y[k + j * ldy] = acc;
 }
 
 // ------------------------------------------------------------------ Omega itself
@@ -293,7 +386,11 @@ __global__ __launch_bounds__(256) void k_omega(uint32_t key0, uint32_t key1, uin
     float zf[4];
     ls_box_muller_f32(c0, c1, zf[0], zf[1]);
     ls_box_muller_f32(c2, c3, zf[2], zf[3]);
-    for (int t = 0; t < 4; ++t) z[t] = (double)ls_bf16_bits_to_f32(ls_f32_to_bf16_bits(zf[t]));
+    for (int t = 0; t < 4; ++t) {
+      if (fmt == LS_FP16) z[t] = (double)(_Float16)zf[t];
+      else if (fmt == LS_FP8E4M3) z[t] = (double)ls_round_fmt_f(zf[t], ls_fmt_e4m3());
+      else z[t] = (double)ls_bf16_bits_to_f32(ls_f32_to_bf16_bits(zf[t]));
+    }
   }
   for (int t = 0; t < 4; ++t) {
     const int64_t i = 4 * q + t;
@@ -317,11 +414,15 @@ __global__ __launch_bounds__(256) void k_philox(uint32_t c0, uint32_t c1, uint32
 // ------------------------------------------------------------------ host side
 namespace ls {
 
+static bool sk_narrow(ls_prec_t u) { return u == LS_BF16 || u == LS_FP16 || u == LS_FP8E4M3; }
+
 SketchPlan sketch_plan(int64_t m, int64_t n, int64_t s, ls_prec_t u_s, int terms) {
   SketchPlan p{};
   p.ncols = n + 1;
-  p.terms = (u_s == LS_BF16) ? terms : 1;
-  if (u_s == LS_BF16) {
+  p.terms = sk_narrow(u_s) ? terms : 1;
+  p.exp_bytes = ls_align256(4 * (size_t)p.ncols);
+  if (sk_narrow(u_s)) {
+    p.ebytes = (u_s == LS_FP8E4M3) ? 1 : 2;
     p.bn = (p.ncols <= 128) ? 128 : (p.ncols <= 256) ? 256 : 512;
     p.nn = ls_cdiv(p.ncols, p.bn);
     p.n_pad = p.nn * p.bn;
@@ -340,10 +441,11 @@ SketchPlan sketch_plan(int64_t m, int64_t n, int64_t s, ls_prec_t u_s, int terms
     p.nkb = p.kb_per_split * nsplit;
     p.m_pad = p.nkb * 32;
     p.kchunk = p.kb_per_split * 32;
-    p.operand_bytes = ls_align256((size_t)p.terms * p.m_pad * p.n_pad * 2);
+    p.operand_bytes = ls_align256((size_t)p.terms * p.m_pad * p.n_pad * p.ebytes);
     p.partial_bytes = ls_align256((size_t)p.nsplit * p.s_pad * p.n_pad * 4);
     return p;
   }
+  p.ebytes = 8;
   p.s_pad = ls_cdiv(s, 64) * 64;
   p.nb = 8;
   p.kstep = 16;
@@ -364,59 +466,91 @@ SketchPlan sketch_plan(int64_t m, int64_t n, int64_t s, ls_prec_t u_s, int terms
   return p;
 }
 
+namespace {
+template <int FMT, typename TA>
+int sketch_narrow(const ls_problem_t* P, const ls_sketch_opts_t* so, const SketchPlan& p, int64_t s, double* Y,
+                  int64_t ldy, char* ws, bool colscale, hipStream_t st) {
+  using F = SkFmt<FMT>;
+  using E = typename F::E;
+  const uint32_t key0 = (uint32_t)(so->seed & 0xffffffffu);
+  const uint32_t key1 = (uint32_t)(so->seed >> 32);
+  E* Tt = reinterpret_cast<E*>(ws);
+  float* Yp = reinterpret_cast<float*>(ws + p.operand_bytes);
+  int32_t* e = colscale ? reinterpret_cast<int32_t*>(ws + p.operand_bytes + p.partial_bytes) : nullptr;
+  const size_t lds = (size_t)(kSkRows * 4 + p.terms * p.bn * 4) * sizeof(typename F::frag);
+  if (lds > (size_t)device_lds_bytes()) return LS_E_UNSUPPORTED;
+  const TA* A = static_cast<const TA*>(P->A);
+  const TA* b = static_cast<const TA*>(P->b);
+  if (e)
+    hipLaunchKernelGGL((k_colexp<TA>), dim3((unsigned)p.ncols), dim3(256), 0, st, A, P->lda, b, P->m, P->n,
+                       F::fmt().fmax, e);
+  hipLaunchKernelGGL((k_pack_lp<TA, FMT>), dim3((unsigned)ls_cdiv(p.m_pad, 256), (unsigned)p.n_pad), dim3(256), 0, st,
+                     A, P->lda, b, P->m, P->n, p.terms, e, Tt, p.m_pad, p.n_pad);
+  const dim3 gb((unsigned)(p.ns * p.nn * p.nsplit));
+  prof_begin(kProfSketch, st);
+#define LS_SK(BN_, T_)                                                                                             \
+  hipLaunchKernelGGL((k_sketch_lp<FMT, BN_, T_>), gb, dim3(kSkThreads), 0, st, Tt, p.nkb, p.n_pad, p.kb_per_split, \
+                     (int)p.ns, (int)p.nn, key0, key1, so->prob_id, Yp, p.s_pad)
+  if (p.bn == 128) {
+    if (p.terms == 1) LS_SK(128, 1); else if (p.terms == 2) LS_SK(128, 2); else LS_SK(128, 3);
+  } else if (p.bn == 256) {
+    if (p.terms == 1) LS_SK(256, 1); else if (p.terms == 2) LS_SK(256, 2); else LS_SK(256, 3);
+  } else {
+    if (p.terms == 1) LS_SK(512, 1); else if (p.terms == 2) LS_SK(512, 2); else LS_SK(512, 3);
+  }
+#undef LS_SK
+  prof_end(kProfSketch, st, 2.0 * (double)s * (double)P->m * (double)(P->n + 1));
+  hipLaunchKernelGGL(k_sketch_combine<float>, dim3((unsigned)ls_cdiv(s, 256), (unsigned)p.ncols), dim3(256), 0, st, Yp,
+                     p.s_pad, p.n_pad, (int)p.nsplit, s, p.ncols, 1.0 / sqrt((double)s), (const int32_t*)e, Y, ldy);
+  LS_HIP_TRY(hipGetLastError());
+  return LS_OK;
+}
+
+template <int FMT>
+int sketch_narrow_store(const ls_problem_t* P, const ls_sketch_opts_t* so, const SketchPlan& p, int64_t s, double* Y,
+                        int64_t ldy, char* ws, bool colscale, hipStream_t st) {
+  if (P->store == LS_FP32) return sketch_narrow<FMT, float>(P, so, p, s, Y, ldy, ws, colscale, st);
+  if (P->store == LS_FP64) return sketch_narrow<FMT, double>(P, so, p, s, Y, ldy, ws, colscale, st);
+  return LS_E_UNSUPPORTED;
+}
+}  // namespace
+
+bool sketch_colscale(ls_prec_t u_s, int32_t col_scale) {
+  if (col_scale < 0) return false;
+  if (col_scale > 0) return sk_narrow(u_s);
+  return u_s == LS_FP16 || u_s == LS_FP8E4M3;
+}
+
 int sketch_run(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s, const SketchPlan& p,
                int64_t s, double* Y, int64_t ldy, char* ws, hipStream_t st) {
+  if (p.terms < 1 || p.terms > 3) return LS_E_ARG;
+  const bool cs = sketch_colscale(u_s, so->col_scale);
+  if (u_s == LS_BF16) return sketch_narrow_store<LS_BF16>(P, so, p, s, Y, ldy, ws, cs, st);
+  if (u_s == LS_FP16) return sketch_narrow_store<LS_FP16>(P, so, p, s, Y, ldy, ws, cs, st);
+  if (u_s == LS_FP8E4M3) return sketch_narrow_store<LS_FP8E4M3>(P, so, p, s, Y, ldy, ws, cs, st);
+  if (u_s != LS_FP64) return LS_E_UNSUPPORTED;
   const uint32_t key0 = (uint32_t)(so->seed & 0xffffffffu);
   const uint32_t key1 = (uint32_t)(so->seed >> 32);
   char* operand = ws;
   char* partial = ws + p.operand_bytes;
   const dim3 gpack((unsigned)ls_cdiv(p.m_pad, 256), (unsigned)p.n_pad);
-  const dim3 gsk((unsigned)(p.s_pad / 64), (unsigned)(p.n_pad / (16 * p.nb ? 16 * p.nb : 1)), (unsigned)p.nsplit);
+  const dim3 gsk((unsigned)(p.s_pad / 64), (unsigned)(p.n_pad / (16 * p.nb)), (unsigned)p.nsplit);
   const dim3 gcomb((unsigned)ls_cdiv(s, 256), (unsigned)p.ncols);
   const double scale = 1.0 / sqrt((double)s);
-  if (u_s == LS_BF16) {
-    if (P->store != LS_FP32) return LS_E_UNSUPPORTED;
-    uint16_t* Tt = reinterpret_cast<uint16_t*>(operand);
-    hipLaunchKernelGGL(k_pack_bf16, gpack, dim3(256), 0, st, (const float*)P->A, P->lda,
-                       (const float*)P->b, P->m, P->n, p.terms, Tt, p.m_pad, p.n_pad);
-    float* Yp = reinterpret_cast<float*>(partial);
-    const size_t lds = (size_t)(kSkRows * 4 + p.terms * p.bn * 4) * 16;
-    if (lds > (size_t)device_lds_bytes()) return LS_E_UNSUPPORTED;
-    const dim3 gb((unsigned)(p.ns * p.nn * p.nsplit));
-    prof_begin(kProfSketch, st);
-#define LS_SK(BN_, T_)                                                                                       \
-  hipLaunchKernelGGL((k_sketch_bf16<BN_, T_>), gb, dim3(kSkThreads), 0, st, Tt, p.nkb, p.n_pad, p.kb_per_split, \
-                     (int)p.ns, (int)p.nn, key0, key1, so->prob_id, Yp, p.s_pad)
-    if (p.terms < 1 || p.terms > 3) return LS_E_ARG;
-    if (p.bn == 128) {
-      if (p.terms == 1) LS_SK(128, 1); else if (p.terms == 2) LS_SK(128, 2); else LS_SK(128, 3);
-    } else if (p.bn == 256) {
-      if (p.terms == 1) LS_SK(256, 1); else if (p.terms == 2) LS_SK(256, 2); else LS_SK(256, 3);
-    } else {
-      if (p.terms == 1) LS_SK(512, 1); else if (p.terms == 2) LS_SK(512, 2); else LS_SK(512, 3);
-    }
-#undef LS_SK
-    prof_end(kProfSketch, st, 2.0 * (double)s * (double)P->m * (double)(P->n + 1));
-    hipLaunchKernelGGL(k_sketch_combine<float>, gcomb, dim3(256), 0, st, Yp, p.s_pad, p.n_pad,
-                       (int)p.nsplit, s, p.ncols, scale, Y, ldy);
-  } else if (u_s == LS_FP64) {
-    double* M = reinterpret_cast<double*>(operand);
-    if (P->store == LS_FP64)
-      hipLaunchKernelGGL(k_pack_f64<double>, gpack, dim3(256), 0, st, (const double*)P->A, P->lda,
-                         (const double*)P->b, P->m, P->n, M, p.m_pad, p.n_pad);
-    else
-      hipLaunchKernelGGL(k_pack_f64<float>, gpack, dim3(256), 0, st, (const float*)P->A, P->lda,
-                         (const float*)P->b, P->m, P->n, M, p.m_pad, p.n_pad);
-    double* Yp = reinterpret_cast<double*>(partial);
-    prof_begin(kProfSketch, st);
-    hipLaunchKernelGGL((k_sketch_f64<8>), gsk, dim3(256), 0, st, M, p.m_pad, p.n_pad, p.kchunk, key0,
-                       key1, so->prob_id, Yp, p.s_pad);
-    prof_end(kProfSketch, st, 2.0 * (double)s * (double)P->m * (double)(P->n + 1));
-    hipLaunchKernelGGL(k_sketch_combine<double>, gcomb, dim3(256), 0, st, Yp, p.s_pad, p.n_pad,
-                       (int)p.nsplit, s, p.ncols, scale, Y, ldy);
-  } else {
-    return LS_E_UNSUPPORTED;
-  }
+  double* M = reinterpret_cast<double*>(operand);
+  if (P->store == LS_FP64)
+    hipLaunchKernelGGL(k_pack_f64<double>, gpack, dim3(256), 0, st, (const double*)P->A, P->lda,
+                       (const double*)P->b, P->m, P->n, M, p.m_pad, p.n_pad);
+  else
+    hipLaunchKernelGGL(k_pack_f64<float>, gpack, dim3(256), 0, st, (const float*)P->A, P->lda,
+                       (const float*)P->b, P->m, P->n, M, p.m_pad, p.n_pad);
+  double* Yp = reinterpret_cast<double*>(partial);
+  prof_begin(kProfSketch, st);
+  hipLaunchKernelGGL((k_sketch_f64<8>), gsk, dim3(256), 0, st, M, p.m_pad, p.n_pad, p.kchunk, key0,
+                     key1, so->prob_id, Yp, p.s_pad);
+  prof_end(kProfSketch, st, 2.0 * (double)s * (double)P->m * (double)(P->n + 1));
+  hipLaunchKernelGGL(k_sketch_combine<double>, gcomb, dim3(256), 0, st, Yp, p.s_pad, p.n_pad,
+                     (int)p.nsplit, s, p.ncols, scale, (const int32_t*)nullptr, Y, ldy);
   LS_HIP_TRY(hipGetLastError());
   return LS_OK;
 }

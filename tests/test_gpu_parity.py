@@ -81,6 +81,21 @@ def test_omega_bf16_matches_oracle(L):
         assert np.all(np.abs(S[diff] - ref[diff]) <= ulp * 1.0000001)
 
 
+@pytest.mark.parametrize("fmt,bits", [("f16", 10), ("e4m3", 3)])
+def test_omega_narrow_matches_oracle(L, fmt, bits):
+    seed, s, m = 78, 64, 4096
+    S = host(L.ls_omega(seed, s, m, fmt=fmt)).T
+    ref = osketch.quantised_gaussian_block(seed, 0, 0, s, 0, m, fmt)
+    # as for bf16: rare entries one ulp apart (binary32 Box-Muller values next
+    # to a rounding boundary of the format)
+    diff = S != ref
+    sync_print(f"{fmt} Omega entries differing by one ulp:", int(diff.sum()), "of", diff.size)
+    assert diff.mean() < 2e-3
+    if diff.any():
+        ulp = np.ldexp(1.0, np.floor(np.log2(np.abs(ref[diff]))).astype(int) - bits)
+        assert np.all(np.abs(S[diff] - ref[diff]) <= ulp * 1.0000001)
+
+
 # ------------------------------------------------------------------ sketch
 def _sketch_gpu(L, P, s, seed, u_s, terms):
     At = dev(P.At)
@@ -133,6 +148,41 @@ def test_sketch_bf16_split_reaches_binary32_accuracy(L):
     sync_print("bf16 sketch error vs exact operands, terms 1/2:", errs)
     assert errs[0] < 8 * 2.0 ** -8 and errs[1] < 8 * 2.0 ** -16
     assert np.linalg.norm(exact_q - exact) / np.linalg.norm(exact) < 2.0 ** -6
+
+
+# narrow formats with the Section 3.2 column scaling (automatic for f16 and
+# e4m3): binary32 or binary64 storage, several terms, ragged m
+@pytest.mark.parametrize("fmt", ["f16", "e4m3"])
+@pytest.mark.parametrize("m,n,s,store,terms", [(5003, 37, 100, "f32", 1), (5003, 37, 100, "f32", 2),
+                                               (3001, 13, 77, "f64", 3), (20000, 300, 1200, "f32", 1),
+                                               (20000, 300, 1200, "f32", 3)])
+def test_sketch_narrow_colscaled_matches_oracle(L, fmt, m, n, s, store, terms):
+    P = make_problem(m, n, 1e3, seed=12, store=store)
+    Y = host(L.ls_sketch(dev(P.At), dev(P.b), s, seed=99, u_s=fmt, terms=terms)).T
+    ref, e = osketch.sketch(P.At, P.b, s, 99, fmt=fmt, terms=terms, colscale=True)
+    Mq, _ = osketch.scaled_operand(P.At, P.b, fmt, terms, True)
+    Sq = np.abs(osketch.quantised_gaussian_block(99, 0, 0, s, 0, m, fmt))
+    bound = (Sq @ np.abs(Mq)) / math.sqrt(s) * np.ldexp(1.0, -e.astype(np.int64))[None, :]
+    # binary32 MFMA accumulation over a row chunk plus rare one-ulp entries of S
+    # (binary32 Box-Muller values within a few ulp of a rounding boundary)
+    err = np.abs(Y - ref) / bound
+    sync_print(f"{fmt} sketch terms={terms} store={store}: max err/bound {err.max():.3e}, "
+               f"median {np.median(err):.3e}, exponents {e.min()}..{e.max()}")
+    assert np.median(err) < 1e-6
+    assert err.max() < 2e-3
+
+
+def test_sketch_e4m3_needs_column_scaling(L):
+    # entries of A are ~ 1/sqrt(m) ~ 1e-2: without scaling most fall into
+    # e4m3's subnormal range (2^-9 .. 2^-6) and lose their digits
+    P = make_problem(6000, 24, 1e2, seed=21, store="f32")
+    exact, _ = osketch.sketch(P.At, P.b, 96, 3, fmt="f64")
+    errs = []
+    for cs in (1, -1):
+        Y = host(L.ls_sketch(dev(P.At), dev(P.b), 96, seed=3, u_s="e4m3", terms=2, col_scale=cs)).T
+        errs.append(np.linalg.norm(Y - exact) / np.linalg.norm(exact))
+    sync_print("e4m3 x2 sketch error vs exact, scaled / unscaled:", errs)
+    assert errs[0] < 0.1 and errs[1] > 3 * errs[0]
 
 
 # ------------------------------------------------------------------ QR
@@ -224,6 +274,26 @@ def test_lsir_reaches_target_from_oracle_start(L, store, u, u_r, target, m, n):
 
 
 # ------------------------------------------------------------------ whole method
+@pytest.mark.parametrize("u_s,terms,u,u_r", [("bf16", 2, "f32", "f64"), ("f16", 2, "f32", "f64"),
+                                             ("f64", 1, "f64", "f64x2")])
+def test_solve_ignores_prior_workspace_contents(L, u_s, terms, u, u_r):
+    # every buffer a step reads is written first: the same solve on a zeroed
+    # workspace and on one filled with large or NaN byte patterns agrees bitwise
+    P = make_problem(6003, 60, 1e4, seed=2410064192, store="f32")
+    pr = L.precs(u_s=u_s, u_qr="f32" if u == "f32" else "f64", u=u, u_r=u_r)
+    S = L.Solver(dev(P.At), dev(P.b), s=240, seed=5, terms=terms, pr=pr,
+                 lsir_tol=6e-6 if u == "f32" else 1e-15, lsqr_tol=1e-6 if u == "f32" else 1e-14)
+    out = []
+    for fill in (0x00, 0x7A, 0xFF, 0x00):
+        S.ws.fill_(fill)
+        rc = S(check=False)
+        out.append((rc, host(S.x), host(S.r), S.stats.as_dict()["fgmres_its_total"]))
+    sync_print(f"workspace fills {u_s}/{u}: status {[o[0] for o in out]} fgmres {[o[3] for o in out]}")
+    for rc, x, r, _ in out:
+        assert rc == 0
+        assert np.array_equal(x, out[0][1]) and np.array_equal(r, out[0][2])
+
+
 def test_solve_fp64_workload_reaches_1e13(L):
     P = make_problem(2000, 50, 1e2, seed=2410063190, store="f64")
     xr, rr, _ = refsolve.ref_solve(P.At, P.b)
@@ -243,6 +313,42 @@ def test_solve_mixed_bf16_reaches_6e6(L):
     ex, er = refsolve.forward_errors(host(x), host(r), xr, rr)
     sync_print("mixed solve:", st, ex, er)
     assert rc == 0 and ex <= 6e-6 and er <= 6e-6
+
+
+@pytest.mark.parametrize("fmt,terms,kappa", [("f16", 2, 1e4), ("e4m3", 3, 1e3)])
+def test_solve_narrow_sketch_reaches_6e6(L, fmt, terms, kappa):
+    P = make_problem(20000, 100, kappa, seed=2410064191, store="f32")
+    xr, rr, _ = refsolve.ref_solve(P.At, P.b)
+    pr = L.precs(u_s=fmt, u_qr="f32", u="f32", u_r="f64")
+    x, r, rc, st = L.ls_solve(dev(P.At), dev(P.b), s=400, seed=8, terms=terms, pr=pr, lsir_tol=6e-6)
+    ex, er = refsolve.forward_errors(host(x), host(r), xr, rr)
+    sync_print(f"{fmt} x{terms} solve:", st["lsqr_its"], st["lsir_its"], st["fgmres_its_total"], ex, er)
+    assert rc == 0 and ex <= 6e-6 and er <= 6e-6
+
+
+def test_solve_batched_equals_single_solves(L):
+    # uneven problems (sizes, conditioning, seeds) over several workers: each
+    # result is bitwise the single-problem one and reaches the target
+    shapes = [(12000, 60, 1e4), (3001, 17, 1e2), (20000, 120, 1e3), (5000, 33, 1e5), (8003, 90, 1e2),
+              (2500, 48, 1e3), (15000, 24, 1e4), (4096, 64, 1e1), (9000, 100, 1e3), (6000, 75, 1e2)]
+    probs = [make_problem(m, n, k, seed=2410063190 + 3000 + i, store="f32") for i, (m, n, k) in enumerate(shapes)]
+    seeds = [2410063190 + 3000 + i for i in range(len(probs))]
+    pr = L.precs(u_s="bf16", u_qr="f32", u="f32", u_r="f64")
+    dev_probs = [(dev(P.At), dev(P.b)) for P in probs]
+    xs, rs, rc, stats = L.ls_solve_batched(dev_probs, seeds=seeds, terms=2, pr=pr, nworkers=4, lsir_tol=6e-6)
+    assert rc == 0
+    for i, (P, (At, b)) in enumerate(zip(probs, dev_probs)):
+        # problem i of a batch draws Omega with prob_id = i
+        x1, r1, rc1, st1 = L.ls_solve(At, b, s=0, seed=seeds[i], terms=2, pr=pr, prob_id=i, lsir_tol=6e-6,
+                                      lsqr_maxit=2 * max(p.n for p in probs))
+        assert rc1 == 0 and stats[i]["status"] == 0
+        assert torch.equal(xs[i], x1) and torch.equal(rs[i], r1), f"problem {i} differs from its single solve"
+        for k in ("lsqr_its", "lsir_its", "fgmres_its_total"):
+            assert stats[i][k] == st1[k], (i, k)
+        xr, rr, _ = refsolve.ref_solve(P.At, P.b)
+        ex, er = refsolve.forward_errors(host(xs[i]), host(rs[i]), xr, rr)
+        assert ex <= 6e-6 and er <= 6e-6, (i, ex, er)
+    sync_print("batched lsqr its:", [st["lsqr_its"] for st in stats], "fgmres:", [st["fgmres_its_total"] for st in stats])
 
 
 def test_solve_rejects_bad_arguments(L):
