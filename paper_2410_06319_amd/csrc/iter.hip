@@ -1244,9 +1244,11 @@ int device_cu_count() {
 namespace {
 // ------------------------------------------------------------------ progress slots
 // One page of pinned, device-mapped, coherent host memory per device, split
-// into slots handed out round-robin to calls.  Kernels store into a slot with
-// system-scope stores; the host polls it.  Null when such memory is not
-// available (the drivers then synchronise to read the state).
+// into slots.  A driver call owns one slot from its start to its end (calls on
+// other host threads, e.g. the workers of a batched solve, get other slots).
+// Kernels store into the slot with system-scope stores; the host polls it.
+// Without such memory, or with every slot taken, the drivers synchronise to
+// read the state instead.
 constexpr int kProgressSlots = 64;
 constexpr int kMaxDevices = 64;
 struct ProgressPool {
@@ -1254,7 +1256,7 @@ struct ProgressPool {
   bool tried = false;
   Progress* host = nullptr;
   Progress* dev = nullptr;
-  std::atomic<unsigned> next{0};
+  uint64_t used = 0;   // bit k: slot k is owned by a call
 };
 
 ProgressPool& progress_pool(int dev) {
@@ -1262,13 +1264,11 @@ ProgressPool& progress_pool(int dev) {
   return pools[(dev >= 0 && dev < kMaxDevices) ? dev : 0];
 }
 
-void progress_acquire(Progress** host, Progress** devp) {
-  *host = nullptr;
-  *devp = nullptr;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return;
-  ProgressPool& p = progress_pool(dev);
-  {
+class ProgressSlot {
+ public:
+  explicit ProgressSlot(hipStream_t st) : st_(st) {
+    if (hipGetDevice(&dev_) != hipSuccess || dev_ < 0 || dev_ >= kMaxDevices) return;
+    ProgressPool& p = progress_pool(dev_);
     std::lock_guard<std::mutex> g(p.mu);
     if (!p.tried) {
       p.tried = true;
@@ -1287,12 +1287,36 @@ void progress_acquire(Progress** host, Progress** devp) {
         (void)hipGetLastError();   // clear the failed allocation's error
       }
     }
+    if (!p.host) return;
+    for (int k = 0; k < kProgressSlots; ++k) {
+      if (!(p.used >> k & 1u)) {
+        p.used |= uint64_t{1} << k;
+        slot_ = k;
+        host = p.host + k;
+        dev = p.dev + k;
+        return;
+      }
+    }
   }
-  if (!p.host) return;
-  const unsigned k = p.next.fetch_add(1) % kProgressSlots;
-  *host = p.host + k;
-  *devp = p.dev + k;
-}
+  // The slot goes back to the pool once no queued kernel of this call can
+  // still store into it; if the stream cannot be drained it stays taken.
+  ~ProgressSlot() {
+    if (slot_ < 0) return;
+    if (hipStreamSynchronize(st_) != hipSuccess) return;
+    ProgressPool& p = progress_pool(dev_);
+    std::lock_guard<std::mutex> g(p.mu);
+    p.used &= ~(uint64_t{1} << slot_);
+  }
+  ProgressSlot(const ProgressSlot&) = delete;
+  ProgressSlot& operator=(const ProgressSlot&) = delete;
+  Progress* host = nullptr;
+  Progress* dev = nullptr;
+
+ private:
+  hipStream_t st_;
+  int dev_ = 0;
+  int slot_ = -1;
+};
 
 void progress_set(int32_t* f, int32_t v) { __atomic_store_n(f, v, __ATOMIC_RELEASE); }
 
@@ -1438,8 +1462,8 @@ int lsqr_typed(const ls_problem_t* P, const double* R, int64_t ldr, const double
   };
   // init: u_1 = b - B z0, beta_1, v_1 = B^T u_1 / beta_1; C_1 -> rec[1]
   pass(1, 1, w.nvpart[0]);
-  Progress *prog = nullptr, *dprog = nullptr;
-  progress_acquire(&prog, &dprog);
+  ProgressSlot slot(st);
+  Progress *prog = slot.host, *dprog = slot.dev;
   if (prog) {
     progress_set(&prog->lsqr_it, -1);
     progress_set(&prog->lsqr_done, 0);
@@ -1613,8 +1637,8 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
   if (!r_given)
     hipLaunchKernelGGL((k_resid_u<TA, TU>), dim3((unsigned)d.Gr), dim3(kThreads), 0, st, A, P->lda, m, n, vec_a, b, x,
                        r);
-  Progress *prog = nullptr, *dprog = nullptr;
-  progress_acquire(&prog, &dprog);
+  ProgressSlot slot(st);
+  Progress *prog = slot.host, *dprog = slot.dev;
   auto fg_pass = [&](int j, int Gw, int final_step, int grid) {
 #define LS_FG_PAN(QQ)                                                                                              \
   fg_pan_launch<TB, QQ>(grid, st, Bm, d.npan, m, n, F, j, d.kmax, w.w2part, Gw, tol, final_step, tpart, w.hpart, \
