@@ -31,7 +31,12 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kMaxKrylov = 96;     // Arnoldi columns per FGMRES cycle (kmax + 1)
-constexpr int kMaxPanQ = 16;       // 16-byte loads per lane for one panel of B (n <= 1024)
+constexpr int kMaxPanQ = 32;       // 16-byte loads per lane for one panel of B (n <= 2048)
+// The panel passes load the next panel while using the current one, except at
+// the widest panels (n > 1024), where one panel is already 32 loads per lane
+// in flight and a second set would not fit the register file.
+template <int Q>
+constexpr bool kPanPrefetch = Q < 32;
 
 typedef float ls_float4v __attribute__((ext_vector_type(4)));
 typedef double ls_double4v __attribute__((ext_vector_type(4)));
@@ -271,9 +276,9 @@ __global__ __launch_bounds__(kThreads) void k_lsqr_pan(const T* __restrict__ Bp,
   };
   if (p0 < p1) load(p0, cur, uo);
   for (int64_t p = p0; p < p1; ++p) {
-    vec_t nxt[Q];
+    vec_t nxt[kPanPrefetch<Q> ? Q : 1];
     vec_t un_o;
-    if (p + 1 < p1) load(p + 1, nxt, un_o);
+    if (kPanPrefetch<Q> && p + 1 < p1) load(p + 1, nxt, un_o);
     const int64_t i0 = p * PR;
     T s[PR];
 #pragma unroll
@@ -307,9 +312,13 @@ __global__ __launch_bounds__(kThreads) void k_lsqr_pan(const T* __restrict__ Bp,
 #pragma unroll
       for (int k = 0; k < PR; ++k) creg[q] += cur[q][k] * un[k];
     if (p + 1 < p1) {
+      if constexpr (kPanPrefetch<Q>) {
 #pragma unroll
-      for (int q = 0; q < Q; ++q) cur[q] = nxt[q];
-      uo = un_o;
+        for (int q = 0; q < Q; ++q) cur[q] = nxt[q];
+        uo = un_o;
+      } else {
+        load(p + 1, cur, uo);
+      }
     }
   }
   // column partials of the block's four waves, summed in wave order
@@ -875,9 +884,9 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
   };
   if (p0 < p1) load(p0, cur, vro, vt);
   for (int64_t p = p0; p < p1; ++p) {
-    vec_t nxt[Q];
+    vec_t nxt[kPanPrefetch<Q> ? Q : 1];
     double vrn[PR], vtn[TM];
-    if (p + 1 < p1) load(p + 1, nxt, vrn, vtn);
+    if (kPanPrefetch<Q> && p + 1 < p1) load(p + 1, nxt, vrn, vtn);
     const int64_t i0 = p * PR;
     double vr[PR];
     TB vrt[PR], s[PR];
@@ -923,12 +932,16 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
       hacc[t] += ((c == j) ? vk : vt[t]) * ((sl < nt) ? wk : 0.0);
     }
     if (p + 1 < p1) {
+      if constexpr (kPanPrefetch<Q>) {
 #pragma unroll
-      for (int q = 0; q < Q; ++q) cur[q] = nxt[q];
+        for (int q = 0; q < Q; ++q) cur[q] = nxt[q];
 #pragma unroll
-      for (int k = 0; k < PR; ++k) vro[k] = vrn[k];
+        for (int k = 0; k < PR; ++k) vro[k] = vrn[k];
 #pragma unroll
-      for (int t = 0; t < TM; ++t) vt[t] = vtn[t];
+        for (int t = 0; t < TM; ++t) vt[t] = vtn[t];
+      } else {
+        load(p + 1, cur, vro, vt);
+      }
     }
   }
   // dot slots: sum the PR lanes of each Krylov column
@@ -1216,10 +1229,12 @@ int pan_occ() {
   return occ;
 }
 
-// Blocks of four waves for a pass over npan panels: at most pan_occ() waves
-// per SIMD, every wave given the same number of panels (k or k - 1).
-int pan_grid(int64_t npan, int ncu) {
-  const int64_t nwmax = (int64_t)pan_occ() * 4 * ncu;
+// Blocks of four waves for a pass over npan panels of n columns: at most
+// pan_occ() waves per SIMD (one from n > 512 on, where a wave's registers
+// take the whole file), every wave given the same number of panels (k or k - 1).
+int pan_grid(int64_t npan, int64_t n, int ncu) {
+  const int occ = (pan_q(n) >= 16) ? 1 : pan_occ();
+  const int64_t nwmax = (int64_t)occ * 4 * ncu;
   const int64_t k = ls_cdiv(npan, nwmax);
   const int64_t nw = ls_cdiv(npan, k);
   const int64_t g = ls_cdiv(nw, 4);
@@ -1416,7 +1431,7 @@ int lsqr_typed(const ls_problem_t* P, const double* R, int64_t ldr, const double
   if (n > 64 * kMaxPanQ) return LS_E_UNSUPPORTED;
   const int ncu = device_cu_count();
   const int64_t npan = pan_count(m, sizeof(T));
-  const int G = pan_grid(npan, ncu);
+  const int G = pan_grid(npan, n, ncu);
   const int Gv = (int)ls_cdiv(n, 4);
   LsqrWs w = lsqr_carve(ws, P, sizeof(T), G, Gv);
   if (w.bytes > ws_bytes) return LS_E_WORKSPACE;
@@ -1454,7 +1469,8 @@ int lsqr_typed(const ls_problem_t* P, const double* R, int64_t ldr, const double
       case 2: LS_LSQR_PAN(2);
       case 4: LS_LSQR_PAN(4);
       case 8: LS_LSQR_PAN(8);
-      default: LS_LSQR_PAN(16);
+      case 16: LS_LSQR_PAN(16);
+      default: LS_LSQR_PAN(32);
     }
 #undef LS_LSQR_PAN
     // B once, u read and written, v read, t written
@@ -1514,7 +1530,7 @@ int lsqr_typed(const ls_problem_t* P, const double* R, int64_t ldr, const double
 
 size_t lsqr_workspace(const ls_problem_t* P, ls_prec_t u, int ncu) {
   const size_t elt = (u == LS_FP32) ? 4 : 8;
-  return lsqr_carve(nullptr, P, elt, pan_grid(pan_count(P->m, elt), ncu), (int)ls_cdiv(P->n, 4)).bytes;
+  return lsqr_carve(nullptr, P, elt, pan_grid(pan_count(P->m, elt), P->n, ncu), (int)ls_cdiv(P->n, 4)).bytes;
 }
 
 int lsqr_device(const ls_problem_t* P, const double* R, int64_t ldr, const double* W, const void* Bm, ls_prec_t u,
@@ -1568,7 +1584,7 @@ LsirDims lsir_dims(const ls_problem_t* P, size_t tb_elt, size_t ta_elt, int fgmr
   d.kmax = fgmres_maxit;
 
   d.npan = pan_count(P->m, tb_elt);
-  d.G = pan_grid(d.npan, ncu);
+  d.G = pan_grid(d.npan, P->n, ncu);
   d.Gr = (int)ls_cdiv(P->m, kResRows);
   d.Gc = (int)ls_cdiv(P->n, 16);
   d.Gd = (int)ls_cdiv(P->m + P->n, kThreads);
@@ -1649,7 +1665,8 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
       case 2: LS_FG_PAN(2);
       case 4: LS_FG_PAN(4);
       case 8: LS_FG_PAN(8);
-      default: LS_FG_PAN(16);
+      case 16: LS_FG_PAN(16);
+      default: LS_FG_PAN(32);
     }
 #undef LS_FG_PAN
   };

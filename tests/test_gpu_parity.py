@@ -155,7 +155,7 @@ def test_sketch_bf16_split_reaches_binary32_accuracy(L):
 @pytest.mark.parametrize("fmt", ["f16", "e4m3"])
 @pytest.mark.parametrize("m,n,s,store,terms", [(5003, 37, 100, "f32", 1), (5003, 37, 100, "f32", 2),
                                                (3001, 13, 77, "f64", 3), (20000, 300, 1200, "f32", 1),
-                                               (20000, 300, 1200, "f32", 3)])
+                                               (20000, 300, 1200, "f32", 3), (6000, 2000, 2100, "f64", 3)])
 def test_sketch_narrow_colscaled_matches_oracle(L, fmt, m, n, s, store, terms):
     P = make_problem(m, n, 1e3, seed=12, store=store)
     Y = host(L.ls_sketch(dev(P.At), dev(P.b), s, seed=99, u_s=fmt, terms=terms)).T
@@ -204,6 +204,22 @@ def test_qr_r_matches_oracle(L, u_qr, s, ncols, kappa):
     assert np.linalg.norm(Gam, 2) <= 10 * math.sqrt(ncols) * u * kappa
 
 
+def test_qr_r_wide_matches_oracle(L):
+    # 2001 columns (binary64 QR of the sketch of an n = 2000 problem)
+    s, ncols = 4100, 2001
+    P = make_problem(s, ncols, 1e3, seed=31, store="f64")
+    Y = np.ascontiguousarray(P.A())
+    R = host(L.ls_qr_r(dev(np.ascontiguousarray(Y.T)), u_qr="f64")).T
+    Rref = oqr.householder_r(Y)
+    assert np.all(np.diag(R) > 0) and np.all(np.tril(R, -1) == 0)
+    u = 2.0 ** -53
+    # the bounds of test_qr_r_matches_oracle
+    assert np.linalg.norm(R.T @ R - Y.T @ Y) <= 20 * ncols * u * np.linalg.norm(Y, 2) ** 2
+    Gam = np.linalg.solve(Rref.T, R.T).T - np.eye(ncols)
+    sync_print("wide QR ||R_hat R^-1 - I||:", np.linalg.norm(Gam, 2))
+    assert np.linalg.norm(Gam, 2) <= 10 * math.sqrt(ncols) * u * 1e3
+
+
 def test_qr_r_rank_deficient_is_reported(L):
     Y = np.random.default_rng(3).standard_normal((100, 8))
     Y[:, 5] = 0.0
@@ -238,6 +254,48 @@ def test_lsqr_iterates_match_oracle(L, store, u, m, n):
         tol = 1e-11 if u == "f64" else 2e-4
         assert np.linalg.norm(got - xr) <= tol * np.linalg.norm(xr)
         assert abs(st["lsqr_normr"] - info["normr"]) <= tol * 10 * info["normr"]
+
+
+def _lapack_R(P, s, seed):
+    # the preconditioner input of the wide-panel tests: R of the oracle sketch
+    # from LAPACK (rows scaled to diag > 0); both sides receive the same R
+    Y, _ = osketch.sketch(P.At, P.b, s, seed)
+    Raug = np.linalg.qr(Y, mode="r")
+    Raug = Raug * np.where(np.diag(Raug) < 0, -1.0, 1.0)[:, None]
+    return Raug[:P.n, :P.n], np.linalg.solve(Raug[:P.n, :P.n], Raug[:P.n, P.n])
+
+
+# panels of 1025..2048 columns (32 loads per lane, no prefetch of the next panel)
+@pytest.mark.parametrize("m,n", [(3001, 1500), (4100, 2048)])
+@pytest.mark.parametrize("store,u", [("f32", "f32"), ("f64", "f64")])
+def test_lsqr_wide_panels_match_oracle(L, store, u, m, n):
+    P = make_problem(m, n, 1e2, seed=19, store=store)
+    R, xs = _lapack_R(P, 2 * n, 3)
+    for k in (1, 5):
+        x = dev(xs.copy())
+        rc, st = L.ls_lsqr_precond(dev(P.At), dev(P.b), dev(np.ascontiguousarray(R.T)), x, u=u,
+                                   lsqr_tol=1e-300, lsqr_maxit=k)
+        xr, info = olsqr.lsqr_precond(P.At, P.b, R, xs, tol=0.0, maxit=k)
+        got = host(x)
+        assert st["lsqr_its"] == k
+        tol = 1e-11 if u == "f64" else 2e-4
+        assert np.linalg.norm(got - xr) <= tol * np.linalg.norm(xr)
+        assert abs(st["lsqr_normr"] - info["normr"]) <= tol * 10 * info["normr"]
+
+
+@pytest.mark.parametrize("m,n", [(5003, 1100), (6000, 2000)])
+def test_lsir_wide_panels_reach_target(L, m, n):
+    P = make_problem(m, n, 1e4, seed=21, store="f32")
+    R, xs = _lapack_R(P, 2 * n, 7)
+    x0, _ = olsqr.lsqr_precond(P.At, P.b, R, xs, tol=1e-6, maxit=200)
+    xr, rr, _ = refsolve.ref_solve(P.At, P.b)
+    x = dev(x0.copy())
+    r = torch.empty(P.m, dtype=torch.float64, device="cuda")
+    pr = L.precs(u_s="f64", u_qr="f64", u="f32", u_r="f64")
+    rc, st = L.ls_lsir_gmres(dev(P.At), dev(P.b), dev(np.ascontiguousarray(R.T)), x, r, pr=pr, lsir_tol=1.5e-6)
+    ex, er = refsolve.forward_errors(host(x), host(r), xr, rr)
+    sync_print(f"wide LSIR n={n}: its {st['lsir_its']} fgmres {st['fgmres_its_total']} err x {ex:.2e} r {er:.2e}")
+    assert rc == 0 and ex <= 6e-6 and er <= 6e-6
 
 
 def test_lsqr_converges_like_oracle(L):
