@@ -16,6 +16,7 @@
 //
 // Scalars live in device memory; kernels of one iteration are enqueued back
 // to back and the host reads a convergence flag every few iterations.
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -779,68 +780,78 @@ struct FgPtrs {
 // the Givens rotations to column j-1 and tests convergence.  Then, per panel
 // of B (one wave per contiguous panel range, next panel in flight):
 // v_r = V_r[:, j] / h (written back normalised), w_r = v_r + B v_x ->
-// V_r[:, j+1], the lanes' column partials of t = B^T v_r, and partial
-// h1_r[c] = V_r[:, c] . w_r for c <= j (lane l: panel row l % PR, Krylov
-// columns l / PR + (64 / PR) t).
+// V_r[:, j+1], and the lanes' column partials of t = B^T v_r.
 template <typename TB, int Q>
 __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, int64_t npan, int64_t m, int64_t n,
                                                      FgPtrs F, int j, int kmax, const double* __restrict__ w2part,
                                                      int Gw, double tol, int final_step, TB* __restrict__ tpart,
-                                                     double* __restrict__ hpart, Progress* prog) {
+                                                     Progress* prog) {
   if (F.st->done) return;
   using vec_t = typename PanVec<TB>::type;
   constexpr int PR = PanVec<TB>::PR;
-  constexpr int TM = (kMaxKrylov * PR + 63) / 64;
   __shared__ TB cred[64 * Q];
-  __shared__ double hred[kMaxKrylov];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const double h = sqrt(wave_sum_array(w2part, Gw, lane));
   const int64_t ldh = kmax + 1;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    FgState S = *F.st;
-    *F.hj = h;
-    if (j == 0) {
-      S.beta = h;
-      F.g[0] = h;
-      S.relres = 1.0;
-      S.k = 0;
-      if (h == 0.0 || !isfinite(h)) {
-        S.done = 1;
-        S.breakdown = (h == 0.0) ? 0 : 2;
-      }
-    } else {
-      const int c = j - 1;
-      double* Hc = F.H + c * ldh;
-      Hc[j] = h;
-      for (int i = 0; i < c; ++i) {
-        const double a = Hc[i], bb = Hc[i + 1];
-        Hc[i] = F.cs[i] * a + F.sn[i] * bb;
-        Hc[i + 1] = -F.sn[i] * a + F.cs[i] * bb;
-      }
-      const double d = hypot(Hc[c], Hc[c + 1]);
-      const double cc = (d > 0.0) ? Hc[c] / d : 1.0;
-      const double ss = (d > 0.0) ? Hc[c + 1] / d : 0.0;
-      F.cs[c] = cc;
-      F.sn[c] = ss;
-      Hc[c] = d;
-      Hc[c + 1] = 0.0;
-      F.g[c + 1] = -ss * F.g[c];
-      F.g[c] = cc * F.g[c];
-      S.relres = fabs(F.g[c + 1]) / S.beta;
-      S.k = j;
-      if (!isfinite(S.relres)) {
-        S.done = 1;
-        S.breakdown = 2;
-      } else if (S.relres <= tol || h == 0.0 || final_step || j >= kmax) {
-        S.done = 1;
-        if (h == 0.0) S.breakdown = 1;
+  if (blockIdx.x == 0) {
+    // Column j - 1 of H, cs and sn are staged in LDS by the block; thread 0
+    // then applies the earlier rotations with the running entry in a register.
+    __shared__ double hcs[kMaxKrylov + 1], css[kMaxKrylov], sns[kMaxKrylov];
+    const int c = j - 1;
+    double* Hc = F.H + (int64_t)(j > 0 ? c : 0) * ldh;
+    for (int t = threadIdx.x; t < j; t += kThreads) {
+      hcs[t] = Hc[t];
+      if (t < c) {
+        css[t] = F.cs[t];
+        sns[t] = F.sn[t];
       }
     }
-    *F.st = S;
-    if (prog && !final_step) {
-      progress_put(&prog->fg_done, S.done ? 1 : 0);
-      progress_put(&prog->fg_j, j);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      FgState S = *F.st;
+      *F.hj = h;
+      if (j == 0) {
+        S.beta = h;
+        F.g[0] = h;
+        S.relres = 1.0;
+        S.k = 0;
+        if (h == 0.0 || !isfinite(h)) {
+          S.done = 1;
+          S.breakdown = (h == 0.0) ? 0 : 2;
+        }
+      } else {
+        double x = hcs[0];
+#pragma unroll 4
+        for (int i = 0; i < c; ++i) {
+          const double y = hcs[i + 1];
+          Hc[i] = css[i] * x + sns[i] * y;
+          x = -sns[i] * x + css[i] * y;
+        }
+        const double d = hypot(x, h);
+        const double cc = (d > 0.0) ? x / d : 1.0;
+        const double ss = (d > 0.0) ? h / d : 0.0;
+        F.cs[c] = cc;
+        F.sn[c] = ss;
+        Hc[c] = d;
+        Hc[c + 1] = 0.0;
+        F.g[c + 1] = -ss * F.g[c];
+        F.g[c] = cc * F.g[c];
+        S.relres = fabs(F.g[c + 1]) / S.beta;
+        S.k = j;
+        if (!isfinite(S.relres)) {
+          S.done = 1;
+          S.breakdown = 2;
+        } else if (S.relres <= tol || h == 0.0 || final_step || j >= kmax) {
+          S.done = 1;
+          if (h == 0.0) S.breakdown = 1;
+        }
+      }
+      *F.st = S;
+      if (prog && !final_step) {
+        progress_put(&prog->fg_done, S.done ? 1 : 0);
+        progress_put(&prog->fg_j, j);
+      }
     }
   }
   if (h == 0.0 || !isfinite(h) || final_step || j >= kmax) return;
@@ -854,17 +865,12 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
     vl[q] = (c < n) ? (TB)(vj[m + c] * inv) : TB(0);
     creg[q] = 0;
   }
-  const int nt = (j + 1) * PR;         // (row, Krylov column) slots of one panel
-  const int kr = lane & (PR - 1);      // this lane's panel row in the dot slots
-  double hacc[TM];
-#pragma unroll
-  for (int t = 0; t < TM; ++t) hacc[t] = 0.0;
   const int64_t nw = (int64_t)gridDim.x * 4;
   int64_t p0, p1;
   row_range(npan, (int)nw, blockIdx.x * 4 + wave, p0, p1);
   vec_t cur[Q];
-  double vro[PR], vt[TM];
-  auto load = [&](int64_t p, vec_t* dst, double* vr_, double* vt_) {
+  double vro[PR];
+  auto load = [&](int64_t p, vec_t* dst, double* vr_) {
     const TB* base = Bp + p * (PR * n);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -874,19 +880,12 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
     const int64_t i0 = p * PR;
 #pragma unroll
     for (int k = 0; k < PR; ++k) vr_[k] = (i0 + k < m) ? vj[i0 + k] : 0.0;
-    const int64_t i = i0 + kr;
-#pragma unroll
-    for (int t = 0; t < TM; ++t) {
-      const int sl = lane + 64 * t;
-      const int c = sl / PR;
-      vt_[t] = (sl < nt && c < j && i < m) ? F.V[i + (int64_t)c * F.ldv] : 0.0;
-    }
   };
-  if (p0 < p1) load(p0, cur, vro, vt);
+  if (p0 < p1) load(p0, cur, vro);
   for (int64_t p = p0; p < p1; ++p) {
     vec_t nxt[kPanPrefetch<Q> ? Q : 1];
-    double vrn[PR], vtn[TM];
-    if (kPanPrefetch<Q> && p + 1 < p1) load(p + 1, nxt, vrn, vtn);
+    double vrn[PR];
+    if (kPanPrefetch<Q> && p + 1 < p1) load(p + 1, nxt, vrn);
     const int64_t i0 = p * PR;
     double vr[PR];
     TB vrt[PR], s[PR];
@@ -918,72 +917,58 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
     for (int q = 0; q < Q; ++q)
 #pragma unroll
       for (int k = 0; k < PR; ++k) creg[q] += cur[q][k] * vrt[k];
-    double wk = wr[0], vk = vr[0];
-#pragma unroll
-    for (int k = 1; k < PR; ++k)
-      if (kr == k) {
-        wk = wr[k];
-        vk = vr[k];
-      }
-#pragma unroll
-    for (int t = 0; t < TM; ++t) {
-      const int sl = lane + 64 * t;
-      const int c = sl / PR;
-      hacc[t] += ((c == j) ? vk : vt[t]) * ((sl < nt) ? wk : 0.0);
-    }
     if (p + 1 < p1) {
       if constexpr (kPanPrefetch<Q>) {
 #pragma unroll
         for (int q = 0; q < Q; ++q) cur[q] = nxt[q];
 #pragma unroll
         for (int k = 0; k < PR; ++k) vro[k] = vrn[k];
-#pragma unroll
-        for (int t = 0; t < TM; ++t) vt[t] = vtn[t];
       } else {
-        load(p + 1, cur, vro, vt);
+        load(p + 1, cur, vro);
       }
     }
   }
-  // dot slots: sum the PR lanes of each Krylov column
-#pragma unroll
-  for (int t = 0; t < TM; ++t)
-#pragma unroll
-    for (int off = 1; off < PR; off <<= 1) hacc[t] += __shfl_xor(hacc[t], off, 64);
   for (int wv = 0; wv < 4; ++wv) {
     if (wave == wv) {
 #pragma unroll
       for (int q = 0; q < Q; ++q) cred[lane + 64 * q] = (wv ? cred[lane + 64 * q] : TB(0)) + creg[q];
-      if (kr == 0) {
-#pragma unroll
-        for (int t = 0; t < TM; ++t) {
-          const int sl = lane + 64 * t;
-          if (sl < nt) hred[sl / PR] = (wv ? hred[sl / PR] : 0.0) + hacc[t];
-        }
-      }
     }
     __syncthreads();
   }
   for (int64_t c = threadIdx.x; c < n; c += kThreads) tpart[c * gridDim.x + blockIdx.x] = cred[c];
-  for (int c = threadIdx.x; c <= j; c += kThreads) hpart[(int64_t)c * gridDim.x + blockIdx.x] = hred[c];
 }
 
 // Blocks < ncb (16 columns each, one wave per column): w_x = B^T v_r from the
 // column partials -> V[m:, j+1], normalise V[m:, j], partial h1_x[c] over the
-// block's columns.  Remaining blocks: h1_r[c] = sum of the pass partials.
+// block's columns.  Blocks ncb .. ncb + nrb - 1 (a range of rows < m each,
+// one wave per Krylov column): partial h1_r[c] = V_r[rows, c] . w_r[rows]
+// for c <= j (V_r[:, j] was normalised by the pass).  Partials of block b
+// go to hxpart[c (ncb + nrb) + b].
 template <typename TB>
-__global__ __launch_bounds__(1024) void k_fg_col(int64_t m, int64_t n, const TB* __restrict__ tpart, int G,
-                                                 const double* __restrict__ hpart, FgPtrs F, int j, int ncb,
-                                                 double* __restrict__ hxpart, double* __restrict__ h1r) {
+__global__ __launch_bounds__(1024) void k_fg_col(int64_t m, int64_t n, const TB* __restrict__ tpart, int G, FgPtrs F,
+                                                 int j, int ncb, int nrb, double* __restrict__ hxpart) {
   if (F.st->done) return;
   __shared__ double wx[16];
   __shared__ double vjx[16];
   const int lane = threadIdx.x & 63;
   const int wvi = threadIdx.x >> 6;
+  const int64_t Gx = ncb + nrb;
   if ((int)blockIdx.x >= ncb) {
-    const int c = blockIdx.x - ncb;
-    if (c > j || wvi != 0) return;
-    const double s = wave_sum_array(hpart + (int64_t)c * G, G, lane);
-    if (lane == 0) h1r[c] = s;
+    int64_t r0, r1;
+    row_range(m, nrb, (int)blockIdx.x - ncb, r0, r1);
+    const double* w = F.V + (int64_t)(j + 1) * F.ldv;
+    for (int c = wvi; c <= j; c += 16) {
+      const double* vc = F.V + (int64_t)c * F.ldv;
+      double a0 = 0.0, a1 = 0.0;
+      int64_t i = r0 + lane;
+      for (; i + 64 < r1; i += 128) {
+        a0 += vc[i] * w[i];
+        a1 += vc[i + 64] * w[i + 64];
+      }
+      if (i < r1) a0 += vc[i] * w[i];
+      const double t = ls_wave_sum(a0 + a1);
+      if (lane == 0) hxpart[(int64_t)c * Gx + blockIdx.x] = t;
+    }
     return;
   }
   const int64_t col = (int64_t)blockIdx.x * 16 + wvi;
@@ -1015,7 +1000,7 @@ __global__ __launch_bounds__(1024) void k_fg_col(int64_t m, int64_t n, const TB*
       const int64_t cc = (int64_t)blockIdx.x * 16 + q;
       if (cc < n) s += ((c == j) ? vjx[q] : F.V[m + cc + (int64_t)c * F.ldv]) * wx[q];
     }
-    hxpart[(int64_t)c * ncb + blockIdx.x] = s;
+    hxpart[(int64_t)c * Gx + blockIdx.x] = s;
   }
 }
 
@@ -1036,11 +1021,11 @@ __device__ __forceinline__ double vrow_dot(const double* __restrict__ V, int64_t
 }
 
 // First Gram-Schmidt sweep over rows [256 b, 256 b + 256) of w = V[:, j+1]:
-// h1[c] = h1r[c] + sum of x-part partials; w <- w - V[:, 0:j+1] h1; partial
+// h1[c] = sum of the Gx partials of k_fg_col; w <- w - V[:, 0:j+1] h1; partial
 // h2[c] = V[:, c] . w.  Block 0 records h1 in column j of H.
 __global__ __launch_bounds__(kThreads) void k_cgs1(FgPtrs F, int64_t m, int64_t n, int j, int kmax,
-                                                   const double* __restrict__ h1r, const double* __restrict__ hx,
-                                                   int Gx, double* __restrict__ h2part) {
+                                                   const double* __restrict__ hx, int Gx,
+                                                   double* __restrict__ h2part) {
   if (F.st->done) return;
   __shared__ double hs[96];
   __shared__ double wsh[kThreads];
@@ -1048,7 +1033,7 @@ __global__ __launch_bounds__(kThreads) void k_cgs1(FgPtrs F, int64_t m, int64_t 
   const int wave = threadIdx.x >> 6;
   for (int c = wave; c <= j; c += 4) {
     const double s = wave_sum_array(hx + (int64_t)c * Gx, Gx, lane);
-    if (lane == 0) hs[c] = h1r[c] + s;
+    if (lane == 0) hs[c] = s;
   }
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x <= j) F.H[(int64_t)j * (kmax + 1) + threadIdx.x] = hs[threadIdx.x];
@@ -1552,9 +1537,7 @@ struct LsirWs {
   double* g;
   double* hj;
   char* tpart;        // n x G (TB), column-major partials
-  double* hpart;      // (kmax+1) x G
-  double* h1r;        // kmax + 1
-  double* hxpart;     // (kmax+1) x Gc
+  double* hxpart;     // (kmax+1) x (Gc + Gk)
   double* h2part;     // (kmax+1) x Gd
   double* h2;         // kmax + 1
   double* w2part;     // max(Gr + Gh, Gd)
@@ -1567,16 +1550,16 @@ struct LsirWs {
 };
 
 struct LsirDims {
-  int kmax, G, Gr, Gc, Gd, Gh, Gn;
+  int kmax, G, Gr, Gc, Gk, Gd, Gh, Gn;
   int64_t npan;   // panels of B
 };
 
 template <typename TB, int Q>
 void fg_pan_launch(int G, hipStream_t st, const TB* Bm, int64_t npan, int64_t m, int64_t n, const FgPtrs& F, int j,
-                   int kmax, const double* w2part, int Gw, double tol, int final_step, TB* tpart, double* hpart,
+                   int kmax, const double* w2part, int Gw, double tol, int final_step, TB* tpart,
                    Progress* prog) {
   hipLaunchKernelGGL((k_fg_pan<TB, Q>), dim3(G), dim3(kThreads), 0, st, Bm, npan, m, n, F, j, kmax, w2part, Gw, tol,
-                     final_step, tpart, hpart, prog);
+                     final_step, tpart, prog);
 }
 
 LsirDims lsir_dims(const ls_problem_t* P, size_t tb_elt, size_t ta_elt, int fgmres_maxit, int ncu) {
@@ -1587,6 +1570,7 @@ LsirDims lsir_dims(const ls_problem_t* P, size_t tb_elt, size_t ta_elt, int fgmr
   d.G = pan_grid(d.npan, P->n, ncu);
   d.Gr = (int)ls_cdiv(P->m, kResRows);
   d.Gc = (int)ls_cdiv(P->n, 16);
+  d.Gk = (int)std::min<int64_t>(128, ls_cdiv(P->m, 512));   // row blocks of the r-part Arnoldi dots
   d.Gd = (int)ls_cdiv(P->m + P->n, kThreads);
   d.Gh = (int)ls_cdiv(P->n, 4);
   d.Gn = (int)ls_cdiv(P->n, 32);
@@ -1612,9 +1596,7 @@ LsirWs lsir_carve(char* ws, const ls_problem_t* P, const LsirDims& d, size_t tb_
   w.g = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1)));
   w.hj = reinterpret_cast<double*>(take(8));
   w.tpart = take(tb_elt * (size_t)d.G * n);
-  w.hpart = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1) * d.G));
-  w.h1r = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1)));
-  w.hxpart = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1) * d.Gc));
+  w.hxpart = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1) * (d.Gc + d.Gk)));
   w.h2part = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1) * d.Gd));
   w.h2 = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1)));
   const int w2n = (d.Gr + d.Gh > d.Gd) ? d.Gr + d.Gh : d.Gd;
@@ -1657,7 +1639,7 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
   Progress *prog = slot.host, *dprog = slot.dev;
   auto fg_pass = [&](int j, int Gw, int final_step, int grid) {
 #define LS_FG_PAN(QQ)                                                                                              \
-  fg_pan_launch<TB, QQ>(grid, st, Bm, d.npan, m, n, F, j, d.kmax, w.w2part, Gw, tol, final_step, tpart, w.hpart, \
+  fg_pan_launch<TB, QQ>(grid, st, Bm, d.npan, m, n, F, j, d.kmax, w.w2part, Gw, tol, final_step, tpart,         \
                         dprog);                                                                                    \
   break
     switch (q) {
@@ -1696,14 +1678,13 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
       const int Gw = (j == 0) ? d.Gr + d.Gh : d.Gd;
       prof_begin(kProfFgPass, st);
       fg_pass(j, Gw, 0, d.G);
-      // B once, v_j read and written, w written, v_x read, t written, V_r(:, 0:j) for the fused dots
-      prof_end(kProfFgPass, st,
-               (double)m * n * sizeof(TB) + 24.0 * m + 8.0 * n + (double)n * sizeof(TB) + 8.0 * (j + 1) * m);
-      hipLaunchKernelGGL(k_fg_col<TB>, dim3((unsigned)(ncb + j + 1)), dim3(1024), 0, st, m, n, tpart, d.G, w.hpart, F,
-                         j, ncb, w.hxpart, w.h1r);
+      // B once, v_j read and written, w written, v_x read, t written
+      prof_end(kProfFgPass, st, (double)m * n * sizeof(TB) + 24.0 * m + 8.0 * n + (double)n * sizeof(TB));
+      hipLaunchKernelGGL(k_fg_col<TB>, dim3((unsigned)(ncb + d.Gk)), dim3(1024), 0, st, m, n, tpart, d.G, F, j, ncb,
+                         d.Gk, w.hxpart);
       prof_begin(kProfCgs, st);
-      hipLaunchKernelGGL(k_cgs1, dim3((unsigned)d.Gd), dim3(kThreads), 0, st, F, m, n, j, d.kmax, w.h1r, w.hxpart, d.Gc,
-                         w.h2part);
+      hipLaunchKernelGGL(k_cgs1, dim3((unsigned)d.Gd), dim3(kThreads), 0, st, F, m, n, j, d.kmax, w.hxpart,
+                         d.Gc + d.Gk, w.h2part);
       hipLaunchKernelGGL(k_cgs_reduce, dim3((unsigned)(j + 1)), dim3(64), 0, st, F, j, d.kmax, w.h2part, d.Gd, w.h2);
       hipLaunchKernelGGL(k_cgs2, dim3((unsigned)d.Gd), dim3(kThreads), 0, st, F, m, n, j, w.h2, w.w2part);
       // V(:, 0:j) read three times (first sweep twice, second once), w read and written twice
