@@ -354,7 +354,7 @@ __device__ __forceinline__ int qr_drow(int lane, int r) {
 // chunks computes V W2 (wave w: two 16-row tiles) and subtracts it from C.
 constexpr int kUpdRows = 256;
 
-template <typename T, int NB>
+template <typename T, int NB, int HC>
 __device__ __forceinline__ void qr_update16(T* __restrict__ Y, int64_t ldy, int64_t s, int64_t j0, int nb0,
                                             const T* __restrict__ Tm, int64_t c0, int cw) {
   using acc_t = typename std::conditional<sizeof(T) == 4, ls_qr_f4, ls_qr_d4>::type;
@@ -406,19 +406,41 @@ __device__ __forceinline__ void qr_update16(T* __restrict__ Y, int64_t ldy, int6
     }
   };
 
-  vec_t reg[PT];
   acc_t acc = acc_t{0, 0, 0, 0};
-  if (nch > 0) load(j0, reg);
-  for (int64_t ch = 0; ch < nch; ++ch) {
-    const int64_t r0 = j0 + ch * kUpdRows;
-    __syncthreads();
-    stage(r0, reg);
-    __syncthreads();
-    if (ch + 1 < nch) load(r0 + kUpdRows, reg);
+  auto w_chunk = [&]() {
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
       const int k = 32 * wave + 4 * kk + (lane >> 4);
       acc = qr_mfma(Vs[k][cl], Cs[k][cl], acc);
+    }
+  };
+  // HC > 0: all nch <= HC chunks are loaded at once and kept in registers for
+  // both sweeps; otherwise one chunk is loaded ahead of the one in use.
+  constexpr int HR = HC > 0 ? HC : 1;
+  vec_t held[HR][PT];
+  vec_t reg[PT];
+  if constexpr (HC > 0) {
+#pragma unroll
+    for (int ch = 0; ch < HC; ++ch)
+      if (ch < nch) load(j0 + ch * kUpdRows, held[ch]);
+#pragma unroll
+    for (int ch = 0; ch < HC; ++ch) {
+      if (ch < nch) {
+        __syncthreads();
+        stage(j0 + ch * kUpdRows, held[ch]);
+        __syncthreads();
+        w_chunk();
+      }
+    }
+  } else {
+    if (nch > 0) load(j0, reg);
+    for (int64_t ch = 0; ch < nch; ++ch) {
+      const int64_t r0 = j0 + ch * kUpdRows;
+      __syncthreads();
+      stage(r0, reg);
+      __syncthreads();
+      if (ch + 1 < nch) load(r0 + kUpdRows, reg);
+      w_chunk();
     }
   }
 #pragma unroll
@@ -439,13 +461,7 @@ __device__ __forceinline__ void qr_update16(T* __restrict__ Y, int64_t ldy, int6
       for (int q = 0; q <= a; ++q) w2 += Tm[q + a * NB] * Ws[q][c];
     W2s[a][c] = w2;
   }
-  if (nch > 0) load(j0, reg);
-  for (int64_t ch = 0; ch < nch; ++ch) {
-    const int64_t r0 = j0 + ch * kUpdRows;
-    __syncthreads();
-    stage(r0, reg);
-    __syncthreads();
-    if (ch + 1 < nch) load(r0 + kUpdRows, reg);
+  auto c_chunk = [&](int64_t r0) {
 #pragma unroll
     for (int tt = 0; tt < 2; ++tt) {
       const int it = 16 * (2 * wave + tt);
@@ -473,6 +489,27 @@ __device__ __forceinline__ void qr_update16(T* __restrict__ Y, int64_t ldy, int6
         *reinterpret_cast<vec_t*>(Y + i + (c0 + (k - 16)) * ldy) = v;
       }
     }
+  };
+  if constexpr (HC > 0) {
+#pragma unroll
+    for (int ch = 0; ch < HC; ++ch) {
+      if (ch < nch) {
+        __syncthreads();
+        stage(j0 + ch * kUpdRows, held[ch]);
+        __syncthreads();
+        c_chunk(j0 + ch * kUpdRows);
+      }
+    }
+  } else {
+    if (nch > 0) load(j0, reg);
+    for (int64_t ch = 0; ch < nch; ++ch) {
+      const int64_t r0 = j0 + ch * kUpdRows;
+      __syncthreads();
+      stage(r0, reg);
+      __syncthreads();
+      if (ch + 1 < nch) load(r0 + kUpdRows, reg);
+      c_chunk(r0);
+    }
   }
 }
 
@@ -481,19 +518,25 @@ __device__ __forceinline__ void qr_update16(T* __restrict__ Y, int64_t ldy, int6
 // next panel (columns j1 .. j1 + nb1 - 1) and factors that panel (T into
 // Tnext); blocks b >= 1 apply it to the 16 columns jt + 16 (b - 1) .. of the
 // trailing matrix, which the next panel's reflectors reach in the next step.
+// Chunks of the trailing update held in registers: the row capacity of the
+// panel (RPT x kPanelThreads rows) in 256-row chunks, while that stays within
+// 32 vectors per thread; 0 (streamed chunks) beyond.
+template <typename T, int RPT>
+constexpr int kQrHeld = (sizeof(T) == 4) ? (RPT <= 8 ? RPT : 0) : (RPT <= 4 ? RPT : 0);
+
 template <typename T, int RPT, int NB>
 __global__ __launch_bounds__(kQrThreads) void k_qr_step(T* __restrict__ Y, int64_t ldy, int64_t s, int64_t ncols,
                                                          int64_t j0, int nb0, const T* __restrict__ Tprev,
                                                          int64_t j1, int nb1, T* __restrict__ tau,
                                                          T* __restrict__ Tnext, int64_t jt) {
   if (blockIdx.x == 0) {
-    qr_update16<T, NB>(Y, ldy, s, j0, nb0, Tprev, j1, nb1);
+    qr_update16<T, NB, kQrHeld<T, RPT>>(Y, ldy, s, j0, nb0, Tprev, j1, nb1);
     __syncthreads();   // the next panel's updated columns are read back below
     qr_panel_body<T, RPT, NB>(Y, ldy, s, j1, nb1, tau, Tnext);
   } else {
     const int64_t c0 = jt + 16 * (int64_t)(blockIdx.x - 1);
     const int cw = (int)((ncols - c0 < 16) ? ncols - c0 : 16);
-    qr_update16<T, NB>(Y, ldy, s, j0, nb0, Tprev, c0, cw);
+    qr_update16<T, NB, kQrHeld<T, RPT>>(Y, ldy, s, j0, nb0, Tprev, c0, cw);
   }
 }
 
