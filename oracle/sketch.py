@@ -77,3 +77,71 @@ def sketch_rows(At, b, s, seed, rows, prob=0, fmt="f64", terms=1, colscale=False
     out *= 1.0 / np.sqrt(s)
     out *= np.ldexp(1.0, -e.astype(np.int64))[None, :]
     return out
+
+
+# ------------------------------------------------------------------ sparse sign embedding
+SPARSE_MAX_WORDS = 256   # Philox words a column may use before the draw is declared failed
+
+
+def sparse_sign_pattern(seed: int, prob: int, m: int, s: int, zeta: int):
+    """Nonzeros of the sparse sign embedding of Section 2.
+
+    Column i of Omega (the column that multiplies row i of [A b]) has zeta
+    nonzeros at distinct rows chosen uniformly at random, each +1 or -1 with
+    probability 1/2, scaled by 1/sqrt(zeta) (this build's reading of the
+    printed scale; it makes E[Omega^T Omega] = I as the embedding definition of
+    Section 2 requires).  The random choices are read from the words of the
+    Philox4x32-10 blocks with counter (i, t, prob, 1), t = 0, 1, ..., key
+    (seed mod 2^32, seed / 2^32), in order: word w proposes row
+    floor(w s / 2^32), negative when w is odd; a proposal equal to an earlier
+    row of the same column is skipped.
+
+    Returns (H, S): (m, zeta) int64 rows and (m, zeta) float64 signs, in
+    the order drawn.
+    """
+    if not (2 <= zeta <= s):
+        raise ValueError("need 2 <= zeta <= s")
+    k0, k1 = seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF
+    rows = np.arange(m, dtype=np.uint64)
+    H = np.full((m, zeta), -1, dtype=np.int64)
+    S = np.zeros((m, zeta))
+    count = np.zeros(m, dtype=np.int64)
+    t = 0
+    while np.any(count < zeta):
+        if 4 * t >= SPARSE_MAX_WORDS:
+            raise RuntimeError("sparse sign draw did not finish")
+        words = philox.philox4x32_10(rows, np.uint64(t), np.uint64(prob), np.uint64(1), k0, k1)
+        for w in words:
+            w64 = w.astype(np.uint64)
+            h = ((w64 * np.uint64(s)) >> np.uint64(32)).astype(np.int64)
+            sign = np.where((w64 & np.uint64(1)) == 1, -1.0, 1.0)
+            dup = np.any(H == h[:, None], axis=1)
+            take = (count < zeta) & ~dup
+            idx = np.nonzero(take)[0]
+            H[idx, count[idx]] = h[idx]
+            S[idx, count[idx]] = sign[idx]
+            count[idx] += 1
+        t += 1
+    return H, S
+
+
+def sparse_sketch(At: np.ndarray, b: np.ndarray, s: int, seed: int, zeta: int, prob: int = 0,
+                  chunk: int = 2048):
+    """Y = Omega [A b] for the sparse sign embedding (Section 2), binary64.
+
+    Every row i of [A b] is added, with its signs, into the zeta rows of Y
+    that column i of Omega selects, rows i in increasing order; Y is then
+    multiplied by 1/sqrt(zeta).
+    """
+    m, n = At.shape[1], At.shape[0]
+    H, S = sparse_sign_pattern(seed, prob, m, s, zeta)
+    Y = np.zeros((s, n + 1))
+    for i0 in range(0, m, chunk):
+        i1 = min(m, i0 + chunk)
+        M = np.empty((i1 - i0, n + 1))
+        M[:, :n] = At[:, i0:i1].T
+        M[:, n] = b[i0:i1]
+        contrib = S[i0:i1, :, None] * M[:, None, :]          # (rows, zeta, n+1), exact
+        np.add.at(Y, H[i0:i1].ravel(), contrib.reshape(-1, n + 1))
+    Y *= 1.0 / np.sqrt(float(zeta))
+    return Y
