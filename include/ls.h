@@ -93,6 +93,14 @@ typedef struct {
   int32_t col_scale; /* Section 3.2 column scaling by powers of two: 0 = on for
                         LS_FP16 and LS_FP8E4M3 (whose range is narrow), off
                         otherwise; 1 = on; -1 = off */
+  int32_t zeta;      /* 0: the Gaussian embedding above.  2..32 with 4 zeta <= s:
+                        the sparse sign embedding of Section 2 instead, column i
+                        of Omega holding zeta entries +-1/sqrt(zeta) at distinct
+                        rows; rows and signs from the Philox4x32-10 words with
+                        counter (i, t, prob_id, 1), t = 0, 1, ...: word w
+                        proposes row floor(w s / 2^32), negative when w is odd,
+                        repeats of a row skipped.  Needs u_s = LS_FP64 and
+                        terms = 1: [A b] is gathered as stored, in binary64 */
 } ls_sketch_opts_t;
 
 /* Iteration control (Section 5): LSQR at most 2n iterations, tolerance 1e-6
@@ -134,12 +142,13 @@ typedef struct {
   double ms_sketch, ms_qr, ms_lsqr, ms_lsir;
   /* With profile != 0: summed device time and launch count of the main
    * kernels, by class: 0 sketch MFMA, 1 LSQR pass over A, 2 FGMRES pass
-   * over A, 3 refinement residual pass over A, 4 Gram-Schmidt sweeps. */
-  double kernel_ms[5];
-  int32_t kernel_launches[5];
+   * over A, 3 refinement residual pass over A, 4 Gram-Schmidt sweeps,
+   * 5 sparse sign sketch gather. */
+  double kernel_ms[6];
+  int32_t kernel_launches[6];
   /* Algorithmic work of those launches: flops for class 0, bytes that the
-   * operation must move to or from HBM for classes 1-4. */
-  double kernel_work[5];
+   * operation must move to or from HBM for classes 1-5. */
+  double kernel_work[6];
 } ls_stats_t;
 
 /* Fill the defaults described above for a problem with n columns and

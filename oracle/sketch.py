@@ -145,3 +145,22 @@ def sparse_sketch(At: np.ndarray, b: np.ndarray, s: int, seed: int, zeta: int, p
         np.add.at(Y, H[i0:i1].ravel(), contrib.reshape(-1, n + 1))
     Y *= 1.0 / np.sqrt(float(zeta))
     return Y
+
+
+def sparse_sketch_rows(At: np.ndarray, b: np.ndarray, s: int, seed: int, zeta: int, rows, prob: int = 0):
+    """Selected rows of the sparse sign sketch, with the additions of
+    ``sparse_sketch`` in the same order (its sources in increasing row i)."""
+    m, n = At.shape[1], At.shape[0]
+    H, S = sparse_sign_pattern(seed, prob, m, s, zeta)
+    out = np.zeros((len(rows), n + 1))
+    for t, r in enumerate(rows):
+        src, k = np.nonzero(H == r)          # row-major order: increasing i
+        acc = np.zeros(n + 1)
+        for i, kk in zip(src, k):
+            row = np.empty(n + 1)
+            row[:n] = At[:, i]
+            row[n] = b[i]
+            acc += S[i, kk] * row
+        out[t] = acc
+    out *= 1.0 / np.sqrt(float(zeta))
+    return out

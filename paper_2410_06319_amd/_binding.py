@@ -26,7 +26,7 @@ class Precs(ctypes.Structure):
 
 class SketchOpts(ctypes.Structure):
     _fields_ = [("s", ctypes.c_int64), ("seed", ctypes.c_uint64), ("prob_id", ctypes.c_uint32),
-                ("terms", ctypes.c_int32), ("col_scale", ctypes.c_int32)]
+                ("terms", ctypes.c_int32), ("col_scale", ctypes.c_int32), ("zeta", ctypes.c_int32)]
 
 
 class IterOpts(ctypes.Structure):
@@ -43,10 +43,10 @@ class Stats(ctypes.Structure):
                 ("lsqr_normB", ctypes.c_double), ("lsir_dx_rel", ctypes.c_double),
                 ("lsir_dr_rel", ctypes.c_double), ("ms_sketch", ctypes.c_double),
                 ("ms_qr", ctypes.c_double), ("ms_lsqr", ctypes.c_double), ("ms_lsir", ctypes.c_double),
-                ("kernel_ms", ctypes.c_double * 5), ("kernel_launches", ctypes.c_int32 * 5),
-                ("kernel_work", ctypes.c_double * 5)]
+                ("kernel_ms", ctypes.c_double * 6), ("kernel_launches", ctypes.c_int32 * 6),
+                ("kernel_work", ctypes.c_double * 6)]
 
-    KERNEL_CLASSES = ("sketch_mfma", "lsqr_pass", "fgmres_pass", "lsir_resid_pass", "cgs_sweep")
+    KERNEL_CLASSES = ("sketch_mfma", "lsqr_pass", "fgmres_pass", "lsir_resid_pass", "cgs_sweep", "sparse_sketch")
 
     def as_dict(self):
         arrays = ("kernel_ms", "kernel_launches", "kernel_work")

@@ -49,8 +49,8 @@ def precs(u_s="bf16", u_qr="f32", u="f32", u_r="f64", u_A=None, u_L=None, u_R=No
                    u_A=B.PREC[u_A], u_L=B.PREC[u_L or u_A], u_R=B.PREC[u_R or u_A])
 
 
-def sketch_opts(s=0, seed=0, prob_id=0, terms=1, col_scale=0) -> B.SketchOpts:
-    return B.SketchOpts(s=s, seed=seed, prob_id=prob_id, terms=terms, col_scale=col_scale)
+def sketch_opts(s=0, seed=0, prob_id=0, terms=1, col_scale=0, zeta=0) -> B.SketchOpts:
+    return B.SketchOpts(s=s, seed=seed, prob_id=prob_id, terms=terms, col_scale=col_scale, zeta=zeta)
 
 
 def iter_opts(n, u="f32", **kw) -> B.IterOpts:
@@ -80,12 +80,12 @@ def workspace_size(P, so, pr, io) -> int:
     return n.value
 
 
-def ls_sketch(At, b, s, seed=0, u_s="bf16", terms=1, prob_id=0, col_scale=0, ws=None):
+def ls_sketch(At, b, s, seed=0, u_s="bf16", terms=1, prob_id=0, col_scale=0, zeta=0, ws=None):
     """Y = Omega [A b] (s x (n+1), float64; returned as a (n+1, s) tensor = column-major Y).
 
     u_s: "f64", "bf16", "f16" or "e4m3"; col_scale 0 = automatic (on for f16 and e4m3)."""
     P = problem(At, b)
-    so = sketch_opts(s=s, seed=seed, prob_id=prob_id, terms=terms, col_scale=col_scale)
+    so = sketch_opts(s=s, seed=seed, prob_id=prob_id, terms=terms, col_scale=col_scale, zeta=zeta)
     pr = precs(u_s=u_s, u_qr="f64", u="f64", u_r="f64")
     if ws is None:
         ws = workspace(workspace_size(P, so, pr, iter_opts(P.n, "f64")), At.device)
@@ -147,10 +147,10 @@ def ls_lsir_gmres(At, b, Rt, x, r, pr=None, r_given=False, ws=None, **opts):
 class Solver:
     """Reusable ls_solve call: holds the options and one workspace for a problem shape."""
 
-    def __init__(self, At, b, s=0, seed=0, prob_id=0, terms=1, pr=None, col_scale=0, **opts):
+    def __init__(self, At, b, s=0, seed=0, prob_id=0, terms=1, pr=None, col_scale=0, zeta=0, **opts):
         self.P = problem(At, b)
         self.At, self.b = At, b
-        self.so = sketch_opts(s=s, seed=seed, prob_id=prob_id, terms=terms, col_scale=col_scale)
+        self.so = sketch_opts(s=s, seed=seed, prob_id=prob_id, terms=terms, col_scale=col_scale, zeta=zeta)
         self.pr = pr or precs()
         self.io = iter_opts(self.P.n, "f64" if self.pr.u == B.FP64 else "f32", **opts)
         self.ws = workspace(workspace_size(self.P, self.so, self.pr, self.io), At.device)
@@ -167,9 +167,9 @@ class Solver:
         return rc
 
 
-def ls_solve(At, b, s=0, seed=0, terms=1, pr=None, col_scale=0, prob_id=0, **opts):
-    """The whole method.  Returns (x, r, status, stats dict)."""
-    S = Solver(At, b, s=s, seed=seed, prob_id=prob_id, terms=terms, pr=pr, col_scale=col_scale, **opts)
+def ls_solve(At, b, s=0, seed=0, terms=1, pr=None, col_scale=0, prob_id=0, zeta=0, **opts):
+    """The whole method.  Returns (x, r, status, stats dict); zeta > 0 selects the sparse sign embedding."""
+    S = Solver(At, b, s=s, seed=seed, prob_id=prob_id, terms=terms, pr=pr, col_scale=col_scale, zeta=zeta, **opts)
     rc = S()
     return S.x, S.r, rc, S.stats.as_dict()
 

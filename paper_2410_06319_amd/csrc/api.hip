@@ -33,6 +33,10 @@ int check_sketch(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_
   const int64_t s = sketch_rows(P, so);
   if (s < P->n + 1) return LS_E_ARG;
   if (s > 8192) return LS_E_UNSUPPORTED;
+  if (so->zeta != 0) {   // sparse sign embedding: binary64 gather of the stored data
+    if (u_s != LS_FP64 || so->terms > 1) return LS_E_ARG;
+    return sparse_check(P->m, so->zeta, s);
+  }
   if (u_s == LS_BF16 || u_s == LS_FP16 || u_s == LS_FP8E4M3) {
     if (so->terms < 1 || so->terms > 3) return LS_E_ARG;
   } else if (u_s == LS_FP64) {
@@ -241,7 +245,7 @@ int ls_workspace_size(const ls_problem_t* P, const ls_sketch_opts_t* so, const l
   LS_TRY(check_sketch(P, so, pr->u_s));
   const ls_iter_opts_t io = fill_opts(io_in, P->n, pr->u);
   const int64_t n = P->n, s = sketch_rows(P, so);
-  const SketchPlan sp = sketch_plan(P->m, n, s, pr->u_s, so->terms);
+  const SketchPlan sp = sketch_plan(P, so, s, pr->u_s);
   size_t fixed = ls_align256(8 * (size_t)s * (n + 1))          // Y
                  + ls_align256(8 * (size_t)(n + 1) * (n + 1))    // R_aug
                  + inv_carve(nullptr, n).bytes                   // R^-1
@@ -263,7 +267,7 @@ int ls_sketch(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s, 
   LS_TRY(check_sketch(P, so, u_s));
   const int64_t s = sketch_rows(P, so);
   if (!Y || ldy < s) return LS_E_ARG;
-  const SketchPlan sp = sketch_plan(P->m, P->n, s, u_s, so->terms);
+  const SketchPlan sp = sketch_plan(P, so, s, u_s);
   if (!ws || ws_bytes < sp.operand_bytes + sp.partial_bytes + sp.exp_bytes) return LS_E_WORKSPACE;
   prof_reset(false);
   return sketch_run(P, so, u_s, sp, s, Y, ldy, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
@@ -383,7 +387,7 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
   Timer tm;
   tm.mark(0, st);
   // Algorithm 1 step 1
-  const SketchPlan sp = sketch_plan(m, n, s, pr->u_s, so->terms);
+  const SketchPlan sp = sketch_plan(P, so, s, pr->u_s);
   LS_TRY(sketch_run(P, so, pr->u_s, sp, s, Y, s, scratch, st));
   tm.mark(1, st);
   // Algorithm 1 step 2, then x^s = R^-1 (Q^T Omega b)

@@ -24,9 +24,15 @@ struct SketchPlan {
   size_t exp_bytes;       // column exponents (narrow formats)
   size_t operand_bytes;   // packed [A b]
   size_t partial_bytes;   // per-split partial sketches (followed by the exponents)
+  int zeta;               // sparse sign embedding: nonzeros per column of Omega (0: Gaussian)
 };
 
-SketchPlan sketch_plan(int64_t m, int64_t n, int64_t s, ls_prec_t u_s, int terms);
+SketchPlan sketch_plan(const ls_problem_t* P, const ls_sketch_opts_t* so, int64_t s, ls_prec_t u_s);
+// Sparse sign embedding (Section 2): argument check, workspace, run.
+int sparse_check(int64_t m, int zeta, int64_t s);
+size_t sparse_workspace(int64_t m, int64_t n, int zeta, int64_t s, size_t ta_bytes);
+int sparse_run(const ls_problem_t* P, const ls_sketch_opts_t* so, int64_t s, double* Y, int64_t ldy, char* ws,
+               hipStream_t st);
 // Whether the sketch scales the columns of [A b] by powers of two (Section 3.2).
 bool sketch_colscale(ls_prec_t u_s, int32_t col_scale);
 int sketch_run(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s, const SketchPlan& p,
@@ -78,7 +84,8 @@ int device_lds_bytes();   // LDS available to one block
 namespace ls {
 // Optional per-kernel timing with HIP events (enabled per call through
 // ls_iter_opts_t.profile).  The record is per host thread.
-enum ProfClass { kProfSketch = 0, kProfLsqrPass = 1, kProfFgPass = 2, kProfResidPass = 3, kProfCgs = 4 };
+enum ProfClass { kProfSketch = 0, kProfLsqrPass = 1, kProfFgPass = 2, kProfResidPass = 3, kProfCgs = 4, kProfSparse = 5 };
+constexpr int kProfClasses = 6;
 void prof_reset(bool on);
 void prof_begin(int cls, hipStream_t st);
 void prof_end(int cls, hipStream_t st, double work);   // work: algorithmic flops or bytes

@@ -47,7 +47,7 @@ void prof_end(int cls, hipStream_t st, double work) {
 
 void prof_collect(ls_stats_t* stats) {
   if (!stats) return;
-  for (int c = 0; c < 5; ++c) {
+  for (int c = 0; c < kProfClasses; ++c) {
     stats->kernel_ms[c] = 0.0;
     stats->kernel_launches[c] = 0;
     stats->kernel_work[c] = 0.0;

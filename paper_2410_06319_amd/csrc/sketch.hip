@@ -416,9 +416,17 @@ namespace ls {
 
 static bool sk_narrow(ls_prec_t u) { return u == LS_BF16 || u == LS_FP16 || u == LS_FP8E4M3; }
 
-SketchPlan sketch_plan(int64_t m, int64_t n, int64_t s, ls_prec_t u_s, int terms) {
+SketchPlan sketch_plan(const ls_problem_t* P, const ls_sketch_opts_t* so, int64_t s, ls_prec_t u_s) {
+  const int64_t m = P->m, n = P->n;
+  const int terms = so->terms;
   SketchPlan p{};
   p.ncols = n + 1;
+  if (so->zeta > 0) {   // sparse sign embedding: its workspace in place of the operand
+    p.zeta = so->zeta;
+    p.terms = 1;
+    p.operand_bytes = ls_align256(sparse_workspace(m, n, so->zeta, s, (P->store == LS_FP64) ? 8 : 4));
+    return p;
+  }
   p.terms = sk_narrow(u_s) ? terms : 1;
   p.exp_bytes = ls_align256(4 * (size_t)p.ncols);
   if (sk_narrow(u_s)) {
@@ -523,6 +531,7 @@ bool sketch_colscale(ls_prec_t u_s, int32_t col_scale) {
 
 int sketch_run(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s, const SketchPlan& p,
                int64_t s, double* Y, int64_t ldy, char* ws, hipStream_t st) {
+  if (p.zeta > 0) return sparse_run(P, so, s, Y, ldy, ws, st);
   if (p.terms < 1 || p.terms > 3) return LS_E_ARG;
   const bool cs = sketch_colscale(u_s, so->col_scale);
   if (u_s == LS_BF16) return sketch_narrow_store<LS_BF16>(P, so, p, s, Y, ldy, ws, cs, st);

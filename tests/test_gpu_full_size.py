@@ -117,6 +117,33 @@ def test_full_size_e4m3_workload(L):
     _run_workload(L, "fp8_m1M_n1000", 3, rows=[0, 2048, 3999], cols=[0, 1, 511, 512, 998, 999])
 
 
+def test_full_size_sparse_sign_sketch(L):
+    # the m=1e5 n=500 s=2000 problem sketched with the sparse sign embedding
+    # (zeta = 8): sampled rows of Y equal the oracle's bit for bit, and the
+    # solve reaches the target with it
+    wl = WORKLOADS["bf16_m100k_n500"]
+    seed = data_seed(wl["index"])
+    P = make_problem(wl["m"], wl["n"], wl["kappa"], seed, store=wl["store"])
+    At, b = torch.from_numpy(P.At).cuda(), torch.from_numpy(P.b).cuda()
+    Y = host(L.ls_sketch(At, b, wl["s"], seed=seed, u_s="f64", zeta=8)).T
+    rows = [0, 1, 999, 1999]
+    ref = osketch.sparse_sketch_rows(P.At, P.b, wl["s"], seed, 8, rows)
+    assert np.array_equal(Y[rows], ref)
+    pr = L.precs(u_s="f64", u_qr="f32", u="f32", u_r="f64")
+    S = L.Solver(At, b, s=wl["s"], seed=seed, pr=pr, zeta=8, lsir_tol=TARGET, lsqr_tol=1e-6)
+    rc = S(check=False)
+    st = S.stats.as_dict()
+    x, r = host(S.x), host(S.r)
+    say(f"sparse sign: status {rc}, lsqr {st['lsqr_its']}, lsir {st['lsir_its']}, fgmres {st['fgmres_its_total']}, "
+        f"sketch {st['ms_sketch']:.3f} ms")
+    del S, At, b
+    torch.cuda.empty_cache()
+    xr, rr, _ = refsolve.ref_solve(P.At, P.b, maxit=2)
+    ex, er = refsolve.forward_errors(x, r, xr, rr)
+    say(f"sparse sign: forward error x {ex:.3e} r {er:.3e}")
+    assert rc == 0 and ex <= TARGET and er <= TARGET
+
+
 def test_full_size_batch_of_256(L):
     # 256 problems, m in [5000, 200000], n in [32, 256], s = 4n, kappa in
     # [1e1, 1e5]: solved in one call; every problem converges, sampled ones are

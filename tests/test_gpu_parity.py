@@ -331,6 +331,47 @@ def test_lsir_reaches_target_from_oracle_start(L, store, u, u_r, target, m, n):
     assert ex <= target and er <= target
 
 
+# ------------------------------------------------------------------ sparse sign embedding
+# Same pattern (Philox words, rejection of repeated rows) and the same
+# binary64 additions in the same order (sources of a row of Y in increasing
+# i): the GPU sketch equals the oracle's bit for bit.  Shapes: ragged m, both
+# storage precisions, n + 1 above 1024 (two column sweeps of the gather).
+@pytest.mark.parametrize("m,n,s,zeta,store", [(5003, 37, 160, 4, "f32"), (3001, 13, 100, 8, "f64"),
+                                              (20000, 300, 1200, 8, "f32"), (4100, 1500, 1600, 2, "f32"),
+                                              (2000, 50, 200, 32, "f64")])
+def test_sparse_sketch_matches_oracle_bitwise(L, m, n, s, zeta, store):
+    P = make_problem(m, n, 1e3, seed=23, store=store)
+    Y = host(L.ls_sketch(dev(P.At), dev(P.b), s, seed=77, u_s="f64", zeta=zeta, prob_id=3)).T
+    ref = osketch.sparse_sketch(P.At, P.b, s, 77, zeta, prob=3)
+    nd = int(np.count_nonzero(Y != ref))
+    sync_print(f"sparse sketch m={m} n={n} s={s} zeta={zeta}: entries differing {nd}")
+    assert nd == 0
+
+
+def test_sparse_sketch_rejects_bad_arguments(L):
+    P = make_problem(1000, 20, 10.0, seed=1, store="f32")
+    At, b = dev(P.At), dev(P.b)
+    for kw in (dict(zeta=1), dict(zeta=33), dict(zeta=30)):          # zeta range, 4 zeta <= s
+        with pytest.raises(L.LsError):
+            L.ls_sketch(At, b, 100, seed=1, u_s="f64", **kw)
+    with pytest.raises(L.LsError):
+        L.ls_sketch(At, b, 100, seed=1, u_s="bf16", zeta=4)           # binary64 only
+
+
+@pytest.mark.parametrize("store,u,u_r,target,m,n,s,kappa", [("f32", "f32", "f64", 6e-6, 20000, 100, 400, 1e4),
+                                                            ("f64", "f64", "f64x2", 1e-13, 2000, 50, 200, 1e2)])
+def test_solve_with_sparse_sketch_reaches_target(L, store, u, u_r, target, m, n, s, kappa):
+    P = make_problem(m, n, kappa, seed=2410064193, store=store)
+    xr, rr, _ = refsolve.ref_solve(P.At, P.b)
+    pr = L.precs(u_s="f64", u_qr="f32" if u == "f32" else "f64", u=u, u_r=u_r)
+    x, r, rc, st = L.ls_solve(dev(P.At), dev(P.b), s=s, seed=9, pr=pr, zeta=8,
+                              lsir_tol=target if u == "f32" else 1e-15, lsqr_tol=1e-6 if u == "f32" else 1e-14)
+    ex, er = refsolve.forward_errors(host(x), host(r), xr, rr)
+    sync_print(f"sparse-sketch solve {store}/{u}: lsqr {st['lsqr_its']} lsir {st['lsir_its']} "
+               f"fgmres {st['fgmres_its_total']} err x {ex:.2e} r {er:.2e}")
+    assert rc == 0 and ex <= target and er <= target
+
+
 # ------------------------------------------------------------------ whole method
 @pytest.mark.parametrize("u_s,terms,u,u_r", [("bf16", 2, "f32", "f64"), ("f16", 2, "f32", "f64"),
                                              ("f64", 1, "f64", "f64x2")])

@@ -78,3 +78,10 @@ def test_sparse_sketch_preconditions_like_the_gaussian(zeta):
         Y = osk.sparse_sketch(P.At, P.b, 400, seed + 100, zeta)
         R = oqr.householder_r(Y)[:100, :100]
         assert osolve.preconditioned_norms(P.At, R)[2] < 4.0
+
+
+def test_sketch_rows_equal_full_sketch_rows():
+    P = make_problem(3000, 11, 1e2, seed=8, store="f32")
+    Y = osk.sparse_sketch(P.At, P.b, 60, 4, 4, prob=1)
+    rows = [0, 17, 59]
+    assert np.array_equal(osk.sparse_sketch_rows(P.At, P.b, 60, 4, 4, rows, prob=1), Y[rows])
