@@ -4,7 +4,7 @@ One step = one whole solve (bf16 sketch of [A b] on MFMA, Householder R,
 preconditioned LSQR, FGMRES refinement) of a synthetic problem already
 resident in HBM.  Prints ONE JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline] [--no-fp64]
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline] [--no-fp64] [--no-sparse]
 """
 
 import argparse
@@ -36,6 +36,7 @@ def parse():
     ap.add_argument("--terms", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-sparse", action="store_true", help="skip the sparse sign embedding solve")
     ap.add_argument("--counter-pass", action="store_true",
                     help="for a rocprofv3 --pmc run: a 256 MiB device copy (calibration), then one solve")
     return ap.parse_args()
@@ -209,6 +210,33 @@ def main():
                             "stage_ms": {k: round(s64[k], 3) for k in ("ms_sketch", "ms_qr", "ms_lsqr", "ms_lsir")}}
         out["speedup_vs_fp64"] = (t64 / (dt / args.steps)) if ok else None
         del S64
+    if not args.no_sparse and mixed:
+        # the same problem with the sparse sign embedding (Section 2, zeta = 8)
+        # in place of the Gaussian sketch: binary64 gather, same QR/LSQR/FGMRES
+        prs = L.precs(u_s="f64", u_qr=wl["u_qr"], u=wl["u"], u_r=u_r)
+        Ss = L.Solver(At, b, s=s, seed=seed, pr=prs, zeta=8, lsir_tol=lsir_tol, lsqr_tol=lsqr_tol)
+        Ss()
+        torch.cuda.synchronize()
+        log("[bench] sparse sign embedding, 5 solves")
+        t2 = time.perf_counter()
+        for _ in range(5):
+            Ss()
+        torch.cuda.synchronize()
+        ts = (time.perf_counter() - t2) / 5
+        es = refsolve.forward_errors(Ss.x.cpu().numpy(), Ss.r.cpu().numpy(), xr, rr)
+        ss = Ss.stats.as_dict()
+        Sq = L.Solver(At, b, s=s, seed=seed, pr=prs, zeta=8, lsir_tol=lsir_tol, lsqr_tol=lsqr_tol, profile=1,
+                      check_every=1)
+        Sq()
+        qs = Sq.stats.as_dict()
+        g_ms, g_n, g_w = (qs[k]["sparse_sketch"] for k in ("kernel_ms", "kernel_launches", "kernel_work"))
+        out["sparse_sign"] = {
+            "zeta": 8, "ms": 1e3 * ts, "solves_per_s": 1.0 / ts, "fwd_err_x": es[0], "fwd_err_r": es[1],
+            "stage_ms": {k: round(ss[k], 4) for k in ("ms_sketch", "ms_qr", "ms_lsqr", "ms_lsir")},
+            "gather": {"avg_us": 1e3 * g_ms / max(g_n, 1), "achieved": g_w / max(g_ms * 1e-3, 1e-30) / 1e9,
+                       "unit": "GB/s", "bytes_per_launch": g_w / max(g_n, 1)},
+        }
+        del Ss, Sq
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline (bounded sample)")
         out["cpu_baseline"] = cpu_baseline(wl, P, seed, terms)
