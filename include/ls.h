@@ -125,6 +125,11 @@ typedef struct {
                             per device (one page); without it the host synchronises
                             every check_every iterations */
   int32_t profile;       /* nonzero: time the main kernels with HIP events (see ls_stats_t) */
+  int32_t inner_adapt;   /* 0: every refinement step runs FGMRES to fgmres_tol (Section 5).
+                            1: from the second step on, to
+                            min(1e-2, max(fgmres_tol, 0.1 lsir_tol / rho)), rho the larger
+                            relative correction of x and r in the previous step: a step
+                            whose correction is far below lsir_tol needs it only roughly */
 } ls_iter_opts_t;
 
 /* Results and timings of one call. */

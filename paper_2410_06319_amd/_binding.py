@@ -33,7 +33,8 @@ class IterOpts(ctypes.Structure):
     _fields_ = [("lsqr_tol", ctypes.c_double), ("lsqr_maxit", ctypes.c_int32),
                 ("fgmres_tol", ctypes.c_double), ("fgmres_maxit", ctypes.c_int32),
                 ("lsir_maxit", ctypes.c_int32), ("lsir_tol", ctypes.c_double),
-                ("fallback", ctypes.c_int32), ("check_every", ctypes.c_int32), ("profile", ctypes.c_int32)]
+                ("fallback", ctypes.c_int32), ("check_every", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("inner_adapt", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

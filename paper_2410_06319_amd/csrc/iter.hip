@@ -1628,7 +1628,7 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
   const int q = pan_q(n);
   TB* tpart = reinterpret_cast<TB*>(w.tpart);
   const int check = io->check_every > 0 ? io->check_every : 8;
-  const double tol = io->fgmres_tol;
+  double tol = io->fgmres_tol;   // FGMRES tolerance of the current step
   const double lsir_tol = io->lsir_tol;
   const int ncb = (int)d.Gc;
 
@@ -1656,6 +1656,11 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
   double dx_rel = 0.0, dr_rel = 0.0;
   std::vector<double> up(2 * (size_t)(d.Gd + d.Gn));
   for (its = 1; its <= io->lsir_maxit; ++its) {
+    if (io->inner_adapt && its > 1) {
+      const double rho = std::max(dx_rel, dr_rel);
+      tol = (rho > 0.0) ? 0.1 * lsir_tol / rho : 1e-2;
+      tol = std::min(1e-2, std::max(io->fgmres_tol, tol));
+    }
     // lines 5-6: f, g, h in u_r
     prof_begin(kProfResidPass, st);
     hipLaunchKernelGGL((k_lsir_resid<TA, DD>), dim3((unsigned)d.Gr), dim3(kThreads), 0, st, A, P->lda, m, n, vec_a, b,

@@ -393,6 +393,24 @@ def test_solve_ignores_prior_workspace_contents(L, u_s, terms, u, u_r):
         assert np.array_equal(x, out[0][1]) and np.array_equal(r, out[0][2])
 
 
+@pytest.mark.parametrize("fmt,terms,kappa", [("bf16", 2, 1e4), ("e4m3", 3, 1e3)])
+def test_adaptive_inner_tolerance_reaches_target_with_fewer_iterations(L, fmt, terms, kappa):
+    P = make_problem(20000, 100, kappa, seed=2410064194, store="f32")
+    xr, rr, _ = refsolve.ref_solve(P.At, P.b)
+    pr = L.precs(u_s=fmt, u_qr="f32", u="f32", u_r="f64")
+    res = {}
+    for adapt in (0, 1):
+        x, r, rc, st = L.ls_solve(dev(P.At), dev(P.b), s=400, seed=7, terms=terms, pr=pr, lsir_tol=6e-6,
+                                  inner_adapt=adapt)
+        ex, er = refsolve.forward_errors(host(x), host(r), xr, rr)
+        res[adapt] = (rc, st["lsir_its"], st["fgmres_its_total"], ex, er)
+        sync_print(f"{fmt} inner_adapt={adapt}: lsir {st['lsir_its']} fgmres {st['fgmres_its_total']} "
+                   f"err x {ex:.2e} r {er:.2e}")
+    for rc, _, _, ex, er in res.values():
+        assert rc == 0 and ex <= 6e-6 and er <= 6e-6
+    assert res[1][2] < res[0][2]
+
+
 def test_solve_fp64_workload_reaches_1e13(L):
     P = make_problem(2000, 50, 1e2, seed=2410063190, store="f64")
     xr, rr, _ = refsolve.ref_solve(P.At, P.b)
