@@ -25,7 +25,7 @@ typedef double ls_qr_d2 __attribute__((ext_vector_type(2)));
 namespace {
 
 constexpr int kQrThreads = 512;      // block size of the QR kernels
-constexpr int kPanelThreads = 256;   // threads that hold the panel (the other waves only join barriers)
+constexpr int kPanelThreads = 512;   // threads that hold the panel (all of the block)
 
 // Sum each of v[0..NB) over the 64 lanes of a wave with a transposed
 // butterfly: after it, the returned value is the full sum of index `idx`.
@@ -519,10 +519,12 @@ __device__ __forceinline__ void qr_update16(T* __restrict__ Y, int64_t ldy, int6
 // Tnext); blocks b >= 1 apply it to the 16 columns jt + 16 (b - 1) .. of the
 // trailing matrix, which the next panel's reflectors reach in the next step.
 // Chunks of the trailing update held in registers: the row capacity of the
-// panel (RPT x kPanelThreads rows) in 256-row chunks, while that stays within
-// 32 vectors per thread; 0 (streamed chunks) beyond.
+// panel (RPT x kPanelThreads rows) in 256-row chunks, while the held vectors
+// stay within 128 VGPRs per thread; 0 (streamed chunks) beyond.
 template <typename T, int RPT>
-constexpr int kQrHeld = (sizeof(T) == 4) ? (RPT <= 8 ? RPT : 0) : (RPT <= 4 ? RPT : 0);
+constexpr int kQrChunks = RPT * kPanelThreads / kUpdRows;
+template <typename T, int RPT>
+constexpr int kQrHeld = (kQrChunks<T, RPT> * (32 * kUpdRows / kQrThreads) * 4 <= 128) ? kQrChunks<T, RPT> : 0;
 
 template <typename T, int RPT, int NB>
 __global__ __launch_bounds__(kQrThreads) void k_qr_step(T* __restrict__ Y, int64_t ldy, int64_t s, int64_t ncols,
@@ -617,14 +619,13 @@ int qr_dispatch(T* Y, int64_t ldy, int64_t s, int64_t ncols, char* ws, hipStream
   // Panel width chosen so that RPT x NB panel values stay in registers of the
   // kPanelThreads panel threads (512-thread blocks allow 256 VGPRs per lane).
   const int64_t rpt = ls_cdiv(s, kPanelThreads);
+  // (RPT = 8 would spill at this width of the panel: such s use RPT = 16.)
   if constexpr (sizeof(T) == 4) {
     if (rpt <= 4) return qr_blocked<T, 4, 16>(Y, ldy, s, ncols, ws, st);
-    if (rpt <= 8) return qr_blocked<T, 8, 16>(Y, ldy, s, ncols, ws, st);
     if (rpt <= 16) return qr_blocked<T, 16, 8>(Y, ldy, s, ncols, ws, st);
     if (rpt <= 32) return qr_blocked<T, 32, 4>(Y, ldy, s, ncols, ws, st);
   } else {
     if (rpt <= 4) return qr_blocked<T, 4, 8>(Y, ldy, s, ncols, ws, st);
-    if (rpt <= 8) return qr_blocked<T, 8, 8>(Y, ldy, s, ncols, ws, st);
     if (rpt <= 16) return qr_blocked<T, 16, 4>(Y, ldy, s, ncols, ws, st);
     if (rpt <= 32) return qr_blocked<T, 32, 2>(Y, ldy, s, ncols, ws, st);
   }
