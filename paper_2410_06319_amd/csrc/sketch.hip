@@ -12,7 +12,9 @@
 // bf16 path: a block of 8 waves owns 128 rows of S and BN columns of [A b].
 // Every K-step of 32 rows, the block generates its 128 x 32 tile of S once
 // (each Gaussian is drawn once per column tile) and stages the TERMS x BN x 32
-// operand tile, both in LDS; wave (wr, wc) multiplies rows 64 wr .. +64 by
+// operand tile, both in LDS.  With BN = 512 each wave multiplies all 128 rows
+// by 64 columns (eight S fragments and the wave's operand fragments read from
+// LDS per step); with narrower BN, wave (wr, wc) takes rows 64 wr .. +64 and
 // columns wc BN/4 .. +BN/4.  LDS rows of 32 bf16 (four 16-byte quarters) are
 // stored with the quarter index XORed with bits 2..3 of the row, so that the
 // 16 lanes of each MFMA operand read hit distinct banks.
@@ -54,6 +56,39 @@ __global__ __launch_bounds__(256) void k_colexp(const TA* __restrict__ A, int64_
   }
 }
 
+// Binary32 Gaussians rounded to nearest even in the sketch format by the
+// hardware conversions, packed in K order (the first value in the lowest bits).
+typedef __bf16 ls_bf16x2v __attribute__((ext_vector_type(2)));
+typedef float ls_f32x2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t sk_pack2_bf16(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((ls_f32x2v){a, b}, ls_bf16x2v));
+}
+__device__ __forceinline__ uint32_t sk_pack2_f16(float a, float b) {
+  return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)a) |
+         ((uint32_t)__builtin_bit_cast(uint16_t, (_Float16)b) << 16);
+}
+__device__ __forceinline__ uint32_t sk_pack4_e4m3(float a, float b, float c, float d) {
+  int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+  w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
+  return (uint32_t)w;
+}
+// Values of packed elements (exact in binary64).
+__device__ __forceinline__ double sk_bf16_at(uint32_t w, int i) {
+  return (double)__uint_as_float(((w >> (16 * i)) & 0xffffu) << 16);
+}
+__device__ __forceinline__ double sk_f16_at(uint32_t w, int i) {
+  return (double)__builtin_bit_cast(_Float16, (uint16_t)((w >> (16 * i)) & 0xffffu));
+}
+__device__ __forceinline__ double sk_e4m3_at(uint32_t w, int i) {
+  const uint32_t b = (w >> (8 * i)) & 0xffu;
+  const uint32_t e = (b >> 3) & 15u, mnt = b & 7u;
+  double v;
+  if (e == 15u && mnt == 7u) v = __builtin_nan("");
+  else if (e == 0u) v = ldexp((double)mnt, -9);
+  else v = ldexp((double)(8u + mnt), (int)e - 10);
+  return (b & 0x80u) ? -v : v;
+}
+
 // Formats of the narrow sketch: element bits, S rounding, MFMA.  An operand
 // fragment is the 8 consecutive K elements one lane supplies to a
 // 16x16x32 MFMA (16 bytes for 16-bit formats, 8 for e4m3).
@@ -64,7 +99,10 @@ struct SkFmt<LS_BF16> {
   using E = uint16_t;
   using frag = ls_u32x4;
   static constexpr LsFmt fmt() { return ls_fmt_bf16(); }
-  static __device__ __forceinline__ E from_f32(float z) { return ls_f32_to_bf16_bits(z); }
+  static __device__ __forceinline__ frag pack8(const float (&z)[8]) {
+    return frag{sk_pack2_bf16(z[0], z[1]), sk_pack2_bf16(z[2], z[3]), sk_pack2_bf16(z[4], z[5]),
+                sk_pack2_bf16(z[6], z[7])};
+  }
   static __device__ __forceinline__ E from_exact(double v) { return ls_f32_to_bf16_bits((float)v); }
   static __device__ __forceinline__ ls_floatx4 mma(frag a, frag b, ls_floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(ls_bf16x8, a), __builtin_bit_cast(ls_bf16x8, b),
@@ -76,7 +114,9 @@ struct SkFmt<LS_FP16> {
   using E = uint16_t;
   using frag = ls_u32x4;
   static constexpr LsFmt fmt() { return ls_fmt_f16(); }
-  static __device__ __forceinline__ E from_f32(float z) { return __builtin_bit_cast(uint16_t, (_Float16)z); }
+  static __device__ __forceinline__ frag pack8(const float (&z)[8]) {
+    return frag{sk_pack2_f16(z[0], z[1]), sk_pack2_f16(z[2], z[3]), sk_pack2_f16(z[4], z[5]), sk_pack2_f16(z[6], z[7])};
+  }
   static __device__ __forceinline__ E from_exact(double v) { return ls_f16_bits(v); }
   static __device__ __forceinline__ ls_floatx4 mma(frag a, frag b, ls_floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(ls_f16x8, a), __builtin_bit_cast(ls_f16x8, b), c,
@@ -88,7 +128,9 @@ struct SkFmt<LS_FP8E4M3> {
   using E = uint8_t;
   using frag = ls_u32x2;
   static constexpr LsFmt fmt() { return ls_fmt_e4m3(); }
-  static __device__ __forceinline__ E from_f32(float z) { return ls_e4m3_bits((double)ls_round_fmt_f(z, fmt())); }
+  static __device__ __forceinline__ frag pack8(const float (&z)[8]) {
+    return frag{sk_pack4_e4m3(z[0], z[1], z[2], z[3]), sk_pack4_e4m3(z[4], z[5], z[6], z[7])};
+  }
   static __device__ __forceinline__ E from_exact(double v) { return ls_e4m3_bits(v); }
   static __device__ __forceinline__ ls_floatx4 mma(frag a, frag b, ls_floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(__builtin_bit_cast(long, a), __builtin_bit_cast(long, b), c, 0,
@@ -167,9 +209,14 @@ __global__ __launch_bounds__(kSkThreads) void k_sketch_lp(const typename SkFmt<F
   using F = SkFmt<FMT>;
   using frag = typename F::frag;
   constexpr int FB = sizeof(frag);
-  constexpr int CT = BN / 64;                  // 16-column tiles per wave
+  // wave layout: WRG groups of rows x (8 / WRG) groups of columns; with 512
+  // columns every wave takes all 128 rows (fewer operand reads from LDS per
+  // product), otherwise two row groups of 64
+  constexpr int WRG = (BN >= 512) ? 1 : 2;
+  constexpr int RT = 8 / WRG;                  // 16-row tiles per wave
+  constexpr int CT = BN / (16 * (8 / WRG));    // 16-column tiles per wave
   // column tiles whose operand fragments are held in registers at once
-  constexpr int HALF = (TERMS >= 3 && CT >= 4) ? CT / 4 : (CT >= 2) ? CT / 2 : 1;
+  constexpr int HALF = (CT * TERMS <= 8) ? CT : (TERMS >= 3 && CT >= 4) ? CT / 4 : (CT >= 2) ? CT / 2 : 1;
   constexpr int BQ = TERMS * BN * 4;           // fragments of the operand tile
   constexpr int BPT = (BQ + kSkThreads - 1) / kSkThreads;
   __shared__ frag As[kSkRows * 4];
@@ -177,7 +224,7 @@ __global__ __launch_bounds__(kSkThreads) void k_sketch_lp(const typename SkFmt<F
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int wave = t >> 6;
-  const int wr = wave & 1, wc = wave >> 1;
+  const int wr = wave % WRG, wc = wave / WRG;
   // blocks of one (K-split, column tile) group run on one XCD (block b -> XCD b % 8)
   const int b = blockIdx.x;
   const int rest = b >> 3;
@@ -205,18 +252,7 @@ __global__ __launch_bounds__(kSkThreads) void k_sketch_lp(const typename SkFmt<F
     ls_box_muller_f32(a2, a3, zz[2], zz[3]);
     ls_box_muller_f32(c0, c1, zz[4], zz[5]);
     ls_box_muller_f32(c2, c3, zz[6], zz[7]);
-    frag w;
-    if constexpr (sizeof(typename F::E) == 2) {
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-        w[p] = (uint32_t)F::from_f32(zz[2 * p]) | ((uint32_t)F::from_f32(zz[2 * p + 1]) << 16);
-    } else {
-#pragma unroll
-      for (int p = 0; p < 2; ++p)
-        w[p] = (uint32_t)F::from_f32(zz[4 * p]) | ((uint32_t)F::from_f32(zz[4 * p + 1]) << 8) |
-               ((uint32_t)F::from_f32(zz[4 * p + 2]) << 16) | ((uint32_t)F::from_f32(zz[4 * p + 3]) << 24);
-    }
-    return w;
+    return F::pack8(zz);
   };
   // operand tile: fragment p = t + 512 u is (term, column, quarter) = (p / (4 BN), (p / 4) % BN, p % 4)
   const frag* Tf = reinterpret_cast<const frag*>(Tt);
@@ -245,9 +281,9 @@ __global__ __launch_bounds__(kSkThreads) void k_sketch_lp(const typename SkFmt<F
     }
   };
 
-  ls_floatx4 acc[4][CT];
+  ls_floatx4 acc[RT][CT];
 #pragma unroll
-  for (int rt = 0; rt < 4; ++rt)
+  for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = ls_floatx4{0.f, 0.f, 0.f, 0.f};
 
@@ -272,13 +308,13 @@ __global__ __launch_bounds__(kSkThreads) void k_sketch_lp(const typename SkFmt<F
       frag bf[HALF][TERMS];
 #pragma unroll
       for (int ct = 0; ct < HALF; ++ct) {
-        const int c = wc * (BN / 4) + (h + ct) * 16 + (lane & 15);
+        const int c = wc * (16 * CT) + (h + ct) * 16 + (lane & 15);
 #pragma unroll
         for (int tm = 0; tm < TERMS; ++tm) bf[ct][tm] = Bs[tm * BN * 4 + sk_slot<FB>(c, fq)];
       }
 #pragma unroll
-      for (int rt = 0; rt < 4; ++rt) {
-        const int r = wr * 64 + rt * 16 + (lane & 15);
+      for (int rt = 0; rt < RT; ++rt) {
+        const int r = wr * (16 * RT) + rt * 16 + (lane & 15);
         const frag af = As[sk_slot<FB>(r, fq)];
 #pragma unroll
         for (int ct = 0; ct < HALF; ++ct)
@@ -289,11 +325,11 @@ __global__ __launch_bounds__(kSkThreads) void k_sketch_lp(const typename SkFmt<F
   }
   float* out = Yp + (int64_t)z * s_pad * n_pad;
 #pragma unroll
-  for (int rt = 0; rt < 4; ++rt) {
-    const int64_t r = row0 + wr * 64 + rt * 16 + 4 * (lane >> 4);
+  for (int rt = 0; rt < RT; ++rt) {
+    const int64_t r = row0 + wr * (16 * RT) + rt * 16 + 4 * (lane >> 4);
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      const int64_t c = col0 + wc * (BN / 4) + ct * 16 + (lane & 15);
+      const int64_t c = col0 + wc * (16 * CT) + ct * 16 + (lane & 15);
       *reinterpret_cast<ls_floatx4*>(out + r + c * s_pad) = acc[rt][ct];
     }
   }
@@ -386,10 +422,16 @@ __global__ __launch_bounds__(256) void k_omega(uint32_t key0, uint32_t key1, uin
     float zf[4];
     ls_box_muller_f32(c0, c1, zf[0], zf[1]);
     ls_box_muller_f32(c2, c3, zf[2], zf[3]);
-    for (int t = 0; t < 4; ++t) {
-      if (fmt == LS_FP16) z[t] = (double)(_Float16)zf[t];
-      else if (fmt == LS_FP8E4M3) z[t] = (double)ls_round_fmt_f(zf[t], ls_fmt_e4m3());
-      else z[t] = (double)ls_bf16_bits_to_f32(ls_f32_to_bf16_bits(zf[t]));
+    // the conversions the sketch kernel uses
+    if (fmt == LS_FP8E4M3) {
+      const uint32_t w = sk_pack4_e4m3(zf[0], zf[1], zf[2], zf[3]);
+      for (int t = 0; t < 4; ++t) z[t] = sk_e4m3_at(w, t);
+    } else if (fmt == LS_FP16) {
+      const uint32_t w0 = sk_pack2_f16(zf[0], zf[1]), w1 = sk_pack2_f16(zf[2], zf[3]);
+      z[0] = sk_f16_at(w0, 0), z[1] = sk_f16_at(w0, 1), z[2] = sk_f16_at(w1, 0), z[3] = sk_f16_at(w1, 1);
+    } else {
+      const uint32_t w0 = sk_pack2_bf16(zf[0], zf[1]), w1 = sk_pack2_bf16(zf[2], zf[3]);
+      z[0] = sk_bf16_at(w0, 0), z[1] = sk_bf16_at(w0, 1), z[2] = sk_bf16_at(w1, 0), z[3] = sk_bf16_at(w1, 1);
     }
   }
   for (int t = 0; t < 4; ++t) {
