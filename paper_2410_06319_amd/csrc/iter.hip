@@ -979,7 +979,16 @@ __global__ __launch_bounds__(1024) void k_fg_col(int64_t m, int64_t n, const TB*
   if (col < n) {
     const TB* tp = tpart + col * G;
     TB acc = 0;
-    for (int g = lane; g < G; g += 64) acc += tp[g];
+    for (int g0 = 0; g0 < G; g0 += 512) {   // eight loads per lane in flight
+      TB v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int g = g0 + 64 * q + lane;
+        v[q] = (g < G) ? tp[g] : TB(0);
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc += v[q];
+    }
     acc = ls_wave_sum(acc);
     val = (double)acc;
     vn = vj[m + col] * inv;
@@ -1004,105 +1013,139 @@ __global__ __launch_bounds__(1024) void k_fg_col(int64_t m, int64_t n, const TB*
   }
 }
 
-// sum_{c <= j} V[i + c ldv] h[c] with eight independent loads in flight.
+// sum_{c <= j} V[i + c ldv] h[c] with NL independent loads in flight.
+template <int NL = 8>
 __device__ __forceinline__ double vrow_dot(const double* __restrict__ V, int64_t ldv, int64_t i, int j,
                                            const double* __restrict__ h) {
   double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int c = 0;
-  for (; c + 8 <= j + 1; c += 8) {
-    double v[8];
+  for (; c + NL <= j + 1; c += NL) {
+    double v[NL];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = V[i + (int64_t)(c + q) * ldv];
+    for (int q = 0; q < NL; ++q) v[q] = V[i + (int64_t)(c + q) * ldv];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) a[q] += v[q] * h[c + q];
+    for (int q = 0; q < NL; ++q) a[q & 7] += v[q] * h[c + q];
   }
   for (; c <= j; ++c) a[0] += V[i + (int64_t)c * ldv] * h[c];
   return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
-// First Gram-Schmidt sweep over rows [256 b, 256 b + 256) of w = V[:, j+1]:
-// h1[c] = sum of the Gx partials of k_fg_col; w <- w - V[:, 0:j+1] h1; partial
-// h2[c] = V[:, c] . w.  Block 0 records h1 in column j of H.
-__global__ __launch_bounds__(kThreads) void k_cgs1(FgPtrs F, int64_t m, int64_t n, int j, int kmax,
-                                                   const double* __restrict__ hx, int Gx,
-                                                   double* __restrict__ h2part) {
-  if (F.st->done) return;
-  __shared__ double hs[96];
-  __shared__ double wsh[kThreads];
+// Threads per block of the Gram-Schmidt sweeps (one row of V per thread):
+// 512 balances the partials each second-sweep block sums (one per block and
+// column) against the compute units the sweeps reach.
+constexpr int kSweepThreads = 512;
+
+// s[c] = sum_{g < G} part[c G + g] for c <= j (< kMaxKrylov): wave w sums the
+// columns w + kSweepWaves k, four at a time, with the loads of the four
+// columns (four per lane each) issued before the first addition.
+template <int kSweepWaves>
+__device__ __forceinline__ void sweep_sum_columns(const double* __restrict__ part, int G, int j,
+                                                  double* __restrict__ s) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  for (int c = wave; c <= j; c += 4) {
-    const double s = wave_sum_array(hx + (int64_t)c * Gx, Gx, lane);
-    if (lane == 0) hs[c] = s;
+  for (int c0 = wave; c0 <= j; c0 += 4 * kSweepWaves) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int g0 = 0; g0 < G; g0 += 256) {
+      double v[4][4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int c = c0 + kSweepWaves * k;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int g = g0 + 64 * q + lane;
+          v[k][q] = (c <= j && g < G) ? part[(int64_t)c * G + g] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[k] += (v[k][0] + v[k][1]) + (v[k][2] + v[k][3]);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int c = c0 + kSweepWaves * k;
+      const double t = ls_wave_sum(acc[k]);
+      if (lane == 0 && c <= j) s[c] = t;
+    }
   }
+}
+
+// First Gram-Schmidt sweep over rows [1024 b, 1024 b + 1024) of w = V[:, j+1]:
+// h1[c] = sum of the Gx partials of k_fg_col; w <- w - V[:, 0:j+1] h1; partial
+// h2[c] = V[:, c] . w over the block's rows.  Block 0 records h1 in column j of H.
+__global__ __launch_bounds__(kSweepThreads) void k_cgs1(FgPtrs F, int64_t m, int64_t n, int j, int kmax,
+                                                        const double* __restrict__ hx, int Gx,
+                                                        double* __restrict__ h2part) {
+  if (F.st->done) return;
+  constexpr int kSweepWaves = kSweepThreads / 64;
+  __shared__ double hs[kMaxKrylov];
+  __shared__ double wsh[kSweepThreads];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  sweep_sum_columns<kSweepWaves>(hx, Gx, j, hs);
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x <= j) F.H[(int64_t)j * (kmax + 1) + threadIdx.x] = hs[threadIdx.x];
   const int64_t rows = m + n;
   double* w = F.V + (int64_t)(j + 1) * F.ldv;
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * kSweepThreads;
+  const int64_t i = base + threadIdx.x;
   double wi = 0.0;
   if (i < rows) {
-    wi = w[i] - vrow_dot(F.V, F.ldv, i, j, hs);
+    wi = w[i] - vrow_dot<16>(F.V, F.ldv, i, j, hs);
     w[i] = wi;
   }
   wsh[threadIdx.x] = wi;
   __syncthreads();
-  // partial dots: wave per Krylov column, four columns' loads issued together
-  const int64_t base = (int64_t)blockIdx.x * kThreads;
-  for (int c0 = wave; c0 <= j; c0 += 16) {
-    double prod[4] = {0.0, 0.0, 0.0, 0.0};
+  // partial dots: wave per Krylov column, the loads of kCols columns (one row
+  // per wave of the block for each lane) issued together
+  constexpr int kCols = 32 / kSweepWaves;
+  for (int c0 = wave; c0 <= j; c0 += kCols * kSweepWaves) {
+    double prod[kCols];
 #pragma unroll
-    for (int cc = 0; cc < 4; ++cc) {
-      const int c = c0 + 4 * cc;
+    for (int cc = 0; cc < kCols; ++cc) {
+      const int c = c0 + kSweepWaves * cc;
+      prod[cc] = 0.0;
       if (c <= j) {
         const double* vc = F.V + (int64_t)c * F.ldv + base;
+        double v[kSweepWaves];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < kSweepWaves; ++q) {
           const int li = q * 64 + lane;
-          if (base + li < rows) prod[cc] += vc[li] * wsh[li];
+          v[q] = (base + li < rows) ? vc[li] : 0.0;
         }
+#pragma unroll
+        for (int q = 0; q < kSweepWaves; ++q) prod[cc] += v[q] * wsh[q * 64 + lane];
       }
     }
 #pragma unroll
-    for (int cc = 0; cc < 4; ++cc) {
-      const int c = c0 + 4 * cc;
+    for (int cc = 0; cc < kCols; ++cc) {
+      const int c = c0 + kSweepWaves * cc;
       const double t = ls_wave_sum(prod[cc]);
       if (c <= j && lane == 0) h2part[(int64_t)c * gridDim.x + blockIdx.x] = t;
     }
   }
 }
 
-// h2[c] = sum of the sweep partials (one wave per c); H(c, j) += h2[c].
-__global__ __launch_bounds__(64) void k_cgs_reduce(FgPtrs F, int j, int kmax, const double* __restrict__ h2part, int G2,
-                                                   double* __restrict__ h2) {
+// Second sweep: h2[c] = sum of the first sweep's partials (every block),
+// H(c, j) += h2[c] (block 0); w <- w - V[:, 0:j+1] h2; partial ||w||^2.
+__global__ __launch_bounds__(kSweepThreads) void k_cgs2(FgPtrs F, int64_t m, int64_t n, int j, int kmax,
+                                                        const double* __restrict__ h2part,
+                                                        double* __restrict__ w2part) {
   if (F.st->done) return;
-  const int c = blockIdx.x;
-  if (c > j) return;
-  const double s = wave_sum_array(h2part + (int64_t)c * G2, G2, threadIdx.x);
-  if (threadIdx.x == 0) {
-    h2[c] = s;
-    F.H[(int64_t)j * (kmax + 1) + c] += s;
-  }
-}
-
-// Second sweep: w <- w - V[:, 0:j+1] h2; partial ||w||^2.
-__global__ __launch_bounds__(kThreads) void k_cgs2(FgPtrs F, int64_t m, int64_t n, int j,
-                                                   const double* __restrict__ h2, double* __restrict__ w2part) {
-  if (F.st->done) return;
-  __shared__ double hs[96];
-  __shared__ double dsh[4];
-  for (int c = threadIdx.x; c <= j; c += kThreads) hs[c] = h2[c];
+  constexpr int kSweepWaves = kSweepThreads / 64;
+  __shared__ double hs[kMaxKrylov];
+  __shared__ double dsh[kSweepWaves];
+  sweep_sum_columns<kSweepWaves>(h2part, (int)gridDim.x, j, hs);
   __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x <= j) F.H[(int64_t)j * (kmax + 1) + threadIdx.x] += hs[threadIdx.x];
   const int64_t rows = m + n;
   double* w = F.V + (int64_t)(j + 1) * F.ldv;
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * kSweepThreads + threadIdx.x;
   double nrm = 0.0;
   if (i < rows) {
-    const double wi = w[i] - vrow_dot(F.V, F.ldv, i, j, hs);
+    const double wi = w[i] - vrow_dot<16>(F.V, F.ldv, i, j, hs);
     w[i] = wi;
     nrm = wi * wi;
   }
-  nrm = block_sum256(nrm, dsh);
+  nrm = ls_block_sum<double, kSweepThreads>(nrm, dsh);
   if (threadIdx.x == 0) w2part[blockIdx.x] = nrm;
 }
 
@@ -1538,9 +1581,8 @@ struct LsirWs {
   double* hj;
   char* tpart;        // n x G (TB), column-major partials
   double* hxpart;     // (kmax+1) x (Gc + Gk)
-  double* h2part;     // (kmax+1) x Gd
-  double* h2;         // kmax + 1
-  double* w2part;     // max(Gr + Gh, Gd)
+  double* h2part;     // (kmax+1) x Gs
+  double* w2part;     // max(Gr + Gh, Gs)
   double* rt_hi;      // n x Gr
   double* rt_lo;      // n x Gr
   double* gvec;       // n
@@ -1550,7 +1592,7 @@ struct LsirWs {
 };
 
 struct LsirDims {
-  int kmax, G, Gr, Gc, Gk, Gd, Gh, Gn;
+  int kmax, G, Gr, Gc, Gk, Gd, Gs, Gh, Gn;
   int64_t npan;   // panels of B
 };
 
@@ -1572,6 +1614,7 @@ LsirDims lsir_dims(const ls_problem_t* P, size_t tb_elt, size_t ta_elt, int fgmr
   d.Gc = (int)ls_cdiv(P->n, 16);
   d.Gk = (int)std::min<int64_t>(128, ls_cdiv(P->m, 512));   // row blocks of the r-part Arnoldi dots
   d.Gd = (int)ls_cdiv(P->m + P->n, kThreads);
+  d.Gs = (int)ls_cdiv(P->m + P->n, kSweepThreads);
   d.Gh = (int)ls_cdiv(P->n, 4);
   d.Gn = (int)ls_cdiv(P->n, 32);
   return d;
@@ -1597,9 +1640,8 @@ LsirWs lsir_carve(char* ws, const ls_problem_t* P, const LsirDims& d, size_t tb_
   w.hj = reinterpret_cast<double*>(take(8));
   w.tpart = take(tb_elt * (size_t)d.G * n);
   w.hxpart = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1) * (d.Gc + d.Gk)));
-  w.h2part = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1) * d.Gd));
-  w.h2 = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1)));
-  const int w2n = (d.Gr + d.Gh > d.Gd) ? d.Gr + d.Gh : d.Gd;
+  w.h2part = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1) * d.Gs));
+  const int w2n = (d.Gr + d.Gh > d.Gs) ? d.Gr + d.Gh : d.Gs;
   w.w2part = reinterpret_cast<double*>(take(8 * (size_t)w2n));
   w.rt_hi = reinterpret_cast<double*>(take(8 * (size_t)d.Gr * n));
   w.rt_lo = reinterpret_cast<double*>(take(8 * (size_t)d.Gr * n));
@@ -1680,7 +1722,7 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
       progress_set(&prog->fg_done, 0);
     }
     for (; j < d.kmax; ++j) {
-      const int Gw = (j == 0) ? d.Gr + d.Gh : d.Gd;
+      const int Gw = (j == 0) ? d.Gr + d.Gh : d.Gs;
       prof_begin(kProfFgPass, st);
       fg_pass(j, Gw, 0, d.G);
       // B once, v_j read and written, w written, v_x read, t written
@@ -1688,10 +1730,10 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
       hipLaunchKernelGGL(k_fg_col<TB>, dim3((unsigned)(ncb + d.Gk)), dim3(1024), 0, st, m, n, tpart, d.G, F, j, ncb,
                          d.Gk, w.hxpart);
       prof_begin(kProfCgs, st);
-      hipLaunchKernelGGL(k_cgs1, dim3((unsigned)d.Gd), dim3(kThreads), 0, st, F, m, n, j, d.kmax, w.hxpart,
+      hipLaunchKernelGGL(k_cgs1, dim3((unsigned)d.Gs), dim3(kSweepThreads), 0, st, F, m, n, j, d.kmax, w.hxpart,
                          d.Gc + d.Gk, w.h2part);
-      hipLaunchKernelGGL(k_cgs_reduce, dim3((unsigned)(j + 1)), dim3(64), 0, st, F, j, d.kmax, w.h2part, d.Gd, w.h2);
-      hipLaunchKernelGGL(k_cgs2, dim3((unsigned)d.Gd), dim3(kThreads), 0, st, F, m, n, j, w.h2, w.w2part);
+      hipLaunchKernelGGL(k_cgs2, dim3((unsigned)d.Gs), dim3(kSweepThreads), 0, st, F, m, n, j, d.kmax, w.h2part,
+                         w.w2part);
       // V(:, 0:j) read three times (first sweep twice, second once), w read and written twice
       prof_end(kProfCgs, st, 3.0 * 8.0 * (j + 1) * (double)(m + n) + 4.0 * 8.0 * (double)(m + n));
       // at most `check` iterations in flight; stop queueing once converged
@@ -1709,7 +1751,7 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
       }
     }
     // final Givens step for the last column (no-op when already done)
-    fg_pass(j < d.kmax ? j + 1 : d.kmax, d.Gd, 1, 1);
+    fg_pass(j < d.kmax ? j + 1 : d.kmax, d.Gs, 1, 1);
     hipLaunchKernelGGL(k_fg_update<TU>, dim3((unsigned)d.Gd), dim3(kThreads), 0, st, F, m, n, d.kmax, r, w.dz, w.upart);
     hipLaunchKernelGGL(k_fg_dx<TU>, dim3((unsigned)d.Gn), dim3(kUtThreads), 0, st, W, n, w.dz, x,
                        w.upart + 2 * (size_t)d.Gd);
