@@ -108,8 +108,8 @@ __device__ __forceinline__ double ls_round_fmt(double x, LsFmt f) {
   (void)frexp(fabs(x), &e);   // |x| = g 2^e, g in [0.5, 1): leading bit 2^(e-1)
   int ex = e - 1;
   if (ex < f.emin) ex = f.emin;
-  const double q = ldexp(1.0, ex - f.t);
-  double r = rint(x / q) * q;
+  // the spacing 2^(ex - t) is a power of two: scaling by it is exact
+  double r = ldexp(rint(ldexp(x, f.t - ex)), ex - f.t);
   if (fabs(r) > f.fmax) r = f.saturate ? copysign(f.fmax, r) : copysign((double)INFINITY, r);
   return r;
 }
@@ -119,8 +119,7 @@ __device__ __forceinline__ float ls_round_fmt_f(float x, LsFmt f) {
   (void)frexpf(fabsf(x), &e);
   int ex = e - 1;
   if (ex < f.emin) ex = f.emin;
-  const float q = ldexpf(1.0f, ex - f.t);
-  float r = rintf(x / q) * q;
+  float r = ldexpf(rintf(ldexpf(x, f.t - ex)), ex - f.t);
   if (fabsf(r) > (float)f.fmax) r = f.saturate ? copysignf((float)f.fmax, r) : copysignf(INFINITY, r);
   return r;
 }

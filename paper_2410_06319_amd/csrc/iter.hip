@@ -93,9 +93,10 @@ __device__ __forceinline__ void row_range(int64_t nrb, int G, int bx, int64_t& b
 }
 
 // ================================================================== B = A W
-// MFMA 16x16x4 (binary32 or binary64).  Block tile 64 x 64, K step 16; wave w
-// owns rows 32 (w & 1) .. +32 and columns 32 (w >> 1) .. +32 (2 x 2 MFMA tiles).
-// W is upper triangular: column tile [j0, j0+64) needs K < j0 + 64 only.
+// MFMA 16x16x4 (binary32 or binary64).  Block tile 64 x 64, K step 32 with the
+// next step's tiles loaded into registers while the current one is multiplied;
+// wave w owns rows 32 (w & 1) .. +32 and columns 32 (w >> 1) .. +32 (2 x 2 MFMA
+// tiles).  W is upper triangular: column tile [j0, j0+64) needs K < j0 + 64 only.
 __device__ __forceinline__ ls_float4v mfma4(float a, float b, ls_float4v c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
@@ -113,8 +114,10 @@ template <typename TA, typename T>
 __global__ __launch_bounds__(kThreads) void k_form_b(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n,
                                                      const T* __restrict__ W, T* __restrict__ B) {
   using acc_t = typename std::conditional<sizeof(T) == 4, ls_float4v, ls_double4v>::type;
-  __shared__ T As[16][64 + 1];   // As[k][i]
-  __shared__ T Ws[16][64 + 1];   // Ws[k][j]
+  constexpr int KS = 32;                   // K step
+  constexpr int LPT = KS * 64 / kThreads;  // tile elements per thread (A and W each)
+  __shared__ T As[KS][64 + 1];   // As[k][i]
+  __shared__ T Ws[KS][64 + 1];   // Ws[k][j]
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int64_t i0 = (int64_t)blockIdx.x * 64;
@@ -126,19 +129,34 @@ __global__ __launch_bounds__(kThreads) void k_form_b(const TA* __restrict__ A, i
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
-  for (int64_t k0 = 0; k0 < kend; k0 += 16) {
-    __syncthreads();
-    for (int idx = t; idx < 16 * 64; idx += kThreads) {
-      const int kk = idx / 64, ii = idx % 64;       // A tile: column kk, row ii (coalesced over ii)
+  // element u of this thread: A tile column kk = idx / 64, row ii = idx % 64
+  // (coalesced over ii); W tile column jj = idx / KS, row k2 = idx % KS
+  T ra[LPT], rw[LPT];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < LPT; ++u) {
+      const int idx = t + kThreads * u;
+      const int kk = idx / 64, ii = idx % 64;
       const int64_t gi = i0 + ii, gk = k0 + kk;
-      As[kk][ii] = (gi < m && gk < n) ? (T)A[gi + gk * lda] : T(0);
-      const int jj = idx / 16, k2 = idx % 16;       // W tile: column jj, row k2 (coalesced over k2)
+      ra[u] = (gi < m && gk < n) ? (T)A[gi + gk * lda] : T(0);
+      const int jj = idx / KS, k2 = idx % KS;
       const int64_t gj = j0 + jj, gk2 = k0 + k2;
-      Ws[k2][jj] = (gj < n && gk2 < n) ? W[gk2 + gj * n] : T(0);
+      rw[u] = (gj < n && gk2 < n) ? W[gk2 + gj * n] : T(0);
+    }
+  };
+  load(0);
+  for (int64_t k0 = 0; k0 < kend; k0 += KS) {
+    __syncthreads();   // the previous step's tiles have been read
+#pragma unroll
+    for (int u = 0; u < LPT; ++u) {
+      const int idx = t + kThreads * u;
+      As[idx / 64][idx % 64] = ra[u];
+      Ws[idx % KS][idx / KS] = rw[u];
     }
     __syncthreads();
+    if (k0 + KS < kend) load(k0 + KS);   // in flight during the products
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
+    for (int ks = 0; ks < KS / 4; ++ks) {
       const int kk = ks * 4 + (lane >> 4);
 #pragma unroll
       for (int a = 0; a < 2; ++a) {

@@ -26,6 +26,7 @@ typedef _Float16 ls_f16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t ls_u32x2 __attribute__((ext_vector_type(2)));
 typedef float ls_floatx4 __attribute__((ext_vector_type(4)));
 typedef double ls_doublex4 __attribute__((ext_vector_type(4)));
+typedef double ls_double2v __attribute__((ext_vector_type(2)));
 typedef uint32_t ls_u32x4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ narrow-format operand
@@ -145,27 +146,77 @@ struct SkFmt<LS_FP8E4M3> {
 // i < m, j <= n.  With column exponents e the column is first scaled by 2^e_j
 // (exact).  The parts satisfy x = T_0 + T_1 + ... + rest, each T_t the
 // format's rounding of what is left (differences exact in binary64).
+// One thread per 8 consecutive rows of one column (one operand fragment):
+// every part of the fragment leaves with one vector store.
+template <int EB>
+struct SkPackVec;
+template <>
+struct SkPackVec<2> {
+  using type = uint4;
+};
+template <>
+struct SkPackVec<1> {
+  using type = uint2;
+};
 template <typename TA, int FMT>
 __global__ __launch_bounds__(256) void k_pack_lp(const TA* __restrict__ A, int64_t lda, const TA* __restrict__ b,
                                                  int64_t m, int64_t n, int terms, const int32_t* __restrict__ e,
                                                  typename SkFmt<FMT>::E* __restrict__ Tt, int64_t m_pad,
                                                  int64_t n_pad) {
   using F = SkFmt<FMT>;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  using E = typename F::E;
+  using V = typename SkPackVec<sizeof(E)>::type;
+  const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 8;
   const int64_t j = blockIdx.y;
-  if (i >= m_pad || j >= n_pad) return;
-  double x = 0.0;
-  if (i < m) {
-    if (j < n) x = (double)A[i + j * lda];
-    else if (j == n) x = (double)b[i];
-    if (e && j <= n) x = ldexp(x, e[j]);
+  if (i0 >= m_pad || j >= n_pad) return;
+  const TA* col = (j < n) ? A + j * lda : b;
+  TA xa[8];
+  if (j <= n && i0 + 8 <= m && ((uintptr_t)(col + i0) & 15) == 0) {   // 16-byte loads
+    constexpr int VW = 16 / sizeof(TA);
+    using LV = typename std::conditional<sizeof(TA) == 4, ls_floatx4, ls_double2v>::type;
+#pragma unroll
+    for (int q = 0; q < 8; q += VW) {
+      const LV v = *reinterpret_cast<const LV*>(col + i0 + q);
+#pragma unroll
+      for (int e2 = 0; e2 < VW; ++e2) xa[q + e2] = v[e2];
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) xa[r] = (i0 + r < m && j <= n) ? col[i0 + r] : TA(0);
   }
   const int64_t nkb = m_pad / 32;
-  const int64_t pos = ((i >> 5) * n_pad + j) * 32 + (i & 31);
+  const int64_t pos = ((i0 >> 5) * n_pad + j) * 32 + (i0 & 31);
+  if constexpr (FMT == LS_BF16 && sizeof(TA) == 4) {
+    if (!e) {
+      // binary32 data: each part is the hardware's round-to-nearest-even of what
+      // is left, and what is left stays exact in binary32
+#pragma unroll 1
+      for (int t = 0; t < terms; ++t) {
+        ls_u32x4 w;
+#pragma unroll
+        for (int p2 = 0; p2 < 4; ++p2) {
+          w[p2] = sk_pack2_bf16(xa[2 * p2], xa[2 * p2 + 1]);
+          xa[2 * p2] -= __uint_as_float(w[p2] << 16);
+          xa[2 * p2 + 1] -= __uint_as_float(w[p2] & 0xffff0000u);
+        }
+        *reinterpret_cast<ls_u32x4*>(Tt + t * nkb * n_pad * 32 + pos) = w;
+      }
+      return;
+    }
+  }
+  const int ej = (e && j <= n) ? e[j] : 0;
+  double x[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) x[r] = ldexp((double)xa[r], ej);
   for (int t = 0; t < terms; ++t) {
-    const double r = ls_round_fmt(x, F::fmt());
-    Tt[t * nkb * n_pad * 32 + pos] = F::from_exact(r);
-    x = x - r;
+    E v[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const double q = ls_round_fmt(x[r], F::fmt());
+      v[r] = F::from_exact(q);
+      x[r] -= q;
+    }
+    *reinterpret_cast<V*>(Tt + t * nkb * n_pad * 32 + pos) = __builtin_bit_cast(V, v);
   }
 }
 
@@ -534,7 +585,7 @@ int sketch_narrow(const ls_problem_t* P, const ls_sketch_opts_t* so, const Sketc
   if (e)
     hipLaunchKernelGGL((k_colexp<TA>), dim3((unsigned)p.ncols), dim3(256), 0, st, A, P->lda, b, P->m, P->n,
                        F::fmt().fmax, e);
-  hipLaunchKernelGGL((k_pack_lp<TA, FMT>), dim3((unsigned)ls_cdiv(p.m_pad, 256), (unsigned)p.n_pad), dim3(256), 0, st,
+  hipLaunchKernelGGL((k_pack_lp<TA, FMT>), dim3((unsigned)ls_cdiv(p.m_pad, 2048), (unsigned)p.n_pad), dim3(256), 0, st,
                      A, P->lda, b, P->m, P->n, p.terms, e, Tt, p.m_pad, p.n_pad);
   const dim3 gb((unsigned)(p.ns * p.nn * p.nsplit));
   prof_begin(kProfSketch, st);
