@@ -79,10 +79,20 @@ __device__ __forceinline__ T block_sum256(T v, T* sh) {
   return ls_block_sum<T, kThreads>(v, sh);
 }
 
-// Sum of part[0..G) by one wave (all lanes get the result).
+// Sum of part[0..G) by one wave (all lanes get the result); each lane adds
+// its elements lane, lane + 64, ... in order, eight loads in flight.
 __device__ __forceinline__ double wave_sum_array(const double* __restrict__ part, int G, int lane) {
   double s = 0.0;
-  for (int g = lane; g < G; g += 64) s += part[g];
+  for (int g0 = 0; g0 < G; g0 += 512) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int g = g0 + 64 * q + lane;
+      v[q] = (g < G) ? part[g] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s += v[q];
+  }
   return ls_wave_sum(s);
 }
 

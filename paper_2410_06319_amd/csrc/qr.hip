@@ -566,24 +566,65 @@ __global__ __launch_bounds__(256) void k_qr_finish(const T* __restrict__ Y, int6
   if (i == j && i < check_cols && (d == 0.0 || !isfinite(d))) *flag = 1;
 }
 
-// W = R^-1, one block per column j: back substitution R w = e_j in binary64.
+// W = R^-1, one block per column j: back substitution R w = e_j in binary64,
+// rows taken in chunks of 64 from the diagonal up.  Wave 0 solves a chunk's
+// triangle with one row per lane (the chunk's rows of R in registers, each
+// solved entry broadcast from its lane through a scalar register, the
+// diagonal applied as a precomputed reciprocal); then every thread subtracts
+// the chunk's contribution from the rows above it.
+__device__ __forceinline__ double trinv_bcast(double v, int lane) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 __global__ __launch_bounds__(256) void k_trinv(const double* __restrict__ R, int64_t ldr, int64_t n,
                                                double* __restrict__ W, int64_t ldw, int* __restrict__ flag) {
   extern __shared__ double bsh[];
   const int64_t j = blockIdx.x;
   const int t = threadIdx.x;
+  const int lane = t & 63;
   for (int64_t i = t; i <= j; i += 256) bsh[i] = (i == j) ? 1.0 : 0.0;
   for (int64_t i = j + 1 + t; i < n; i += 256) W[i + j * ldw] = 0.0;
-  for (int64_t k = j; k >= 0; --k) {
+  for (int64_t c0 = (j / 64) * 64; c0 >= 0; c0 -= 64) {
+    const int cn = (int)((j + 1 - c0 < 64) ? j + 1 - c0 : 64);   // rows c0 .. c0 + cn - 1
     __syncthreads();
-    const double rkk = R[k + k * ldr];
-    const double wk = bsh[k] / rkk;
-    if (t == 0) {
-      W[k + j * ldw] = wk;
-      if (!isfinite(wk)) *flag = 1;
+    if (t < 64) {
+      const int64_t i = c0 + lane;
+      const bool act = lane < cn;
+      double rrow[64];
+#pragma unroll
+      for (int kk = 0; kk < 64; ++kk) rrow[kk] = (act && kk < cn && kk >= lane) ? R[i + (c0 + kk) * ldr] : 0.0;
+      double bi = act ? bsh[i] : 0.0;
+      const double rinv = act ? 1.0 / R[i + i * ldr] : 0.0;
+#pragma unroll
+      for (int kk = 63; kk >= 0; --kk) {
+        if (kk < cn) {
+          const double wk = trinv_bcast(bi * rinv, kk);
+          if (lane == kk) bi = wk;
+          else if (lane < kk) bi -= rrow[kk] * wk;
+        }
+      }
+      if (act) {
+        bsh[i] = bi;
+        W[i + j * ldw] = bi;
+        if (!isfinite(bi)) *flag = 1;
+      }
     }
-    const double* rc = R + k * ldr;
-    for (int64_t i = t; i < k; i += 256) bsh[i] -= rc[i] * wk;
+    __syncthreads();
+    // rows above the chunk: b_i -= sum_kk R(i, c0 + kk) w(c0 + kk)
+    for (int64_t i = t; i < c0; i += 256) {
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int kb = 0; kb < cn; kb += 16) {
+        double v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = (kb + q < cn) ? R[i + (c0 + kb + q) * ldr] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q & 3] += v[q] * ((kb + q < cn) ? bsh[c0 + kb + q] : 0.0);
+      }
+      bsh[i] -= (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    }
   }
 }
 
