@@ -101,6 +101,14 @@ typedef struct {
                         proposes row floor(w s / 2^32), negative when w is odd,
                         repeats of a row skipped.  Needs u_s = LS_FP64 and
                         terms = 1: [A b] is gathered as stored, in binary64 */
+  int32_t max_terms; /* ls_solve (and the batch) only.  0: `terms` parts, fixed.
+                        terms < max_terms <= 3 (LS_BF16, LS_FP16, LS_FP8E4M3):
+                        Section 4's convergence condition asks for
+                        kappa(A) u_s < 1.  Once R is formed, kappa_est (see
+                        ls_stats_t) stands for kappa(A), and while kappa_est
+                        u^terms > 1 (u the format's unit roundoff: 2^-8, 2^-11,
+                        2^-4) and terms < max_terms, the sketch, R and R^-1 are
+                        formed again with one more part (ls_sketch_terms_for) */
 } ls_sketch_opts_t;
 
 /* Iteration control (Section 5): LSQR at most 2n iterations, tolerance 1e-6
@@ -154,6 +162,11 @@ typedef struct {
   /* Algorithmic work of those launches: flops for class 0, bytes that the
    * operation must move to or from HBM for classes 1-5. */
   double kernel_work[6];
+  int32_t sketch_terms;   /* parts of [A b] the sketch used (ls_solve) */
+  double kappa_est;       /* ||R||_F ||R^-1||_F / sqrt(n) of the preconditioner
+                             (ls_solve): kappa_2(R) / sqrt(n) <= kappa_est <=
+                             sqrt(n) kappa_2(R), and kappa_2(R) is kappa(A) up to
+                             the embedding's distortion (Section 2) */
 } ls_stats_t;
 
 /* Fill the defaults described above for a problem with n columns and
@@ -249,6 +262,14 @@ int ls_omega(uint64_t seed, uint32_t prob_id, int64_t s, int64_t m, ls_prec_t fm
  * Does not synchronise. */
 int ls_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
               int64_t count, uint32_t *out, void *stream);
+
+/* The number of parts ls_solve sketches with next, given the estimate
+ * kappa_est of kappa(A) from an R formed with `terms` parts: terms + 1 when
+ * u_s is LS_BF16, LS_FP16 or LS_FP8E4M3, terms < max_terms and
+ * kappa_est u^terms > 1 (u = 2^-8, 2^-11, 2^-4: Section 4's condition
+ * kappa(A) u_s < 1 with u_s = u^terms, the accuracy of a terms-part
+ * representation); otherwise terms.  Host only. */
+int ls_sketch_terms_for(double kappa_est, ls_prec_t u_s, int32_t terms, int32_t max_terms);
 
 /* Static text for a status code. */
 const char *ls_strerror(int status);

@@ -49,8 +49,9 @@ def precs(u_s="bf16", u_qr="f32", u="f32", u_r="f64", u_A=None, u_L=None, u_R=No
                    u_A=B.PREC[u_A], u_L=B.PREC[u_L or u_A], u_R=B.PREC[u_R or u_A])
 
 
-def sketch_opts(s=0, seed=0, prob_id=0, terms=1, col_scale=0, zeta=0) -> B.SketchOpts:
-    return B.SketchOpts(s=s, seed=seed, prob_id=prob_id, terms=terms, col_scale=col_scale, zeta=zeta)
+def sketch_opts(s=0, seed=0, prob_id=0, terms=1, col_scale=0, zeta=0, max_terms=0) -> B.SketchOpts:
+    return B.SketchOpts(s=s, seed=seed, prob_id=prob_id, terms=terms, col_scale=col_scale, zeta=zeta,
+                        max_terms=max_terms)
 
 
 def iter_opts(n, u="f32", **kw) -> B.IterOpts:
@@ -147,10 +148,11 @@ def ls_lsir_gmres(At, b, Rt, x, r, pr=None, r_given=False, ws=None, **opts):
 class Solver:
     """Reusable ls_solve call: holds the options and one workspace for a problem shape."""
 
-    def __init__(self, At, b, s=0, seed=0, prob_id=0, terms=1, pr=None, col_scale=0, zeta=0, **opts):
+    def __init__(self, At, b, s=0, seed=0, prob_id=0, terms=1, pr=None, col_scale=0, zeta=0, max_terms=0, **opts):
         self.P = problem(At, b)
         self.At, self.b = At, b
-        self.so = sketch_opts(s=s, seed=seed, prob_id=prob_id, terms=terms, col_scale=col_scale, zeta=zeta)
+        self.so = sketch_opts(s=s, seed=seed, prob_id=prob_id, terms=terms, col_scale=col_scale, zeta=zeta,
+                              max_terms=max_terms)
         self.pr = pr or precs()
         self.io = iter_opts(self.P.n, "f64" if self.pr.u == B.FP64 else "f32", **opts)
         self.ws = workspace(workspace_size(self.P, self.so, self.pr, self.io), At.device)
@@ -167,14 +169,16 @@ class Solver:
         return rc
 
 
-def ls_solve(At, b, s=0, seed=0, terms=1, pr=None, col_scale=0, prob_id=0, zeta=0, **opts):
-    """The whole method.  Returns (x, r, status, stats dict); zeta > 0 selects the sparse sign embedding."""
-    S = Solver(At, b, s=s, seed=seed, prob_id=prob_id, terms=terms, pr=pr, col_scale=col_scale, zeta=zeta, **opts)
+def ls_solve(At, b, s=0, seed=0, terms=1, pr=None, col_scale=0, prob_id=0, zeta=0, max_terms=0, **opts):
+    """The whole method.  Returns (x, r, status, stats dict); zeta > 0 selects the sparse sign embedding;
+    max_terms > terms lets the solve add sketch parts while kappa_est u_s^terms > 1."""
+    S = Solver(At, b, s=s, seed=seed, prob_id=prob_id, terms=terms, pr=pr, col_scale=col_scale, zeta=zeta,
+               max_terms=max_terms, **opts)
     rc = S()
     return S.x, S.r, rc, S.stats.as_dict()
 
 
-def ls_solve_batched(problems, s=0, seeds=None, terms=1, pr=None, col_scale=0, nworkers=0, **opts):
+def ls_solve_batched(problems, s=0, seeds=None, terms=1, pr=None, col_scale=0, nworkers=0, max_terms=0, **opts):
     """The whole method for a list of (At, b) problems on one device.
 
     Returns (xs, rs, status, list of stats dicts); s = 0 uses 4 n per problem.
@@ -182,7 +186,8 @@ def ls_solve_batched(problems, s=0, seeds=None, terms=1, pr=None, col_scale=0, n
     nprob = len(problems)
     Ps = (B.Problem * nprob)(*[problem(At, b) for At, b in problems])
     seeds = seeds if seeds is not None else [0] * nprob
-    sos = (B.SketchOpts * nprob)(*[sketch_opts(s=s, seed=seeds[i], prob_id=i, terms=terms, col_scale=col_scale)
+    sos = (B.SketchOpts * nprob)(*[sketch_opts(s=s, seed=seeds[i], prob_id=i, terms=terms, col_scale=col_scale,
+                                               max_terms=max_terms)
                                    for i in range(nprob)])
     pr = pr or precs()
     io = iter_opts(max(p.n for p in Ps), "f64" if pr.u == B.FP64 else "f32", **opts)
@@ -200,6 +205,11 @@ def ls_solve_batched(problems, s=0, seeds=None, terms=1, pr=None, col_scale=0, n
                                    ws.data_ptr(), ws.numel(), _stream())
     _check(rc, "ls_solve_batched")
     return xs, rs, rc, [stats[i].as_dict() for i in range(nprob)]
+
+
+def sketch_terms_for(kappa_est, u_s="bf16", terms=1, max_terms=3):
+    """Parts the solve sketches with next after an R formed with ``terms`` parts (host only)."""
+    return B.load().ls_sketch_terms_for(float(kappa_est), B.PREC[u_s], int(terms), int(max_terms))
 
 
 def ls_omega(seed, s, m, fmt="bf16", prob_id=0, device="cuda"):

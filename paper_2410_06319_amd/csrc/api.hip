@@ -34,13 +34,14 @@ int check_sketch(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_
   if (s < P->n + 1) return LS_E_ARG;
   if (s > 8192) return LS_E_UNSUPPORTED;
   if (so->zeta != 0) {   // sparse sign embedding: binary64 gather of the stored data
-    if (u_s != LS_FP64 || so->terms > 1) return LS_E_ARG;
+    if (u_s != LS_FP64 || so->terms > 1 || so->max_terms > 1) return LS_E_ARG;
     return sparse_check(P->m, so->zeta, s);
   }
   if (u_s == LS_BF16 || u_s == LS_FP16 || u_s == LS_FP8E4M3) {
     if (so->terms < 1 || so->terms > 3) return LS_E_ARG;
+    if (so->max_terms != 0 && (so->max_terms < so->terms || so->max_terms > 3)) return LS_E_ARG;
   } else if (u_s == LS_FP64) {
-    if (so->terms > 1) return LS_E_ARG;
+    if (so->terms > 1 || so->max_terms > 1) return LS_E_ARG;
   } else {
     return LS_E_UNSUPPORTED;
   }
@@ -89,6 +90,7 @@ struct Inv {
   double* W;
   float* W32;
   int* flag;
+  double* fro;   // 2n: squared column norms of R^-1 and R
   size_t bytes;
 };
 
@@ -103,6 +105,7 @@ Inv inv_carve(char* ws, int64_t n) {
   v.W = reinterpret_cast<double*>(take(8 * (size_t)n * n));
   v.W32 = reinterpret_cast<float*>(take(4 * (size_t)n * n));
   v.flag = reinterpret_cast<int*>(take(256));
+  v.fro = reinterpret_cast<double*>(take(16 * (size_t)n));
   v.bytes = off;
   return v;
 }
@@ -237,6 +240,17 @@ const char* ls_strerror(int s) {
   }
 }
 
+int ls_sketch_terms_for(double kappa_est, ls_prec_t u_s, int32_t terms, int32_t max_terms) {
+  double u;
+  if (u_s == LS_BF16) u = 0x1p-8;
+  else if (u_s == LS_FP16) u = 0x1p-11;
+  else if (u_s == LS_FP8E4M3) u = 0x1p-4;
+  else return terms;
+  if (terms < 1 || terms >= max_terms) return terms;
+  const double us = std::pow(u, (double)terms);   // a terms-part representation
+  return (kappa_est * us > 1.0 || !std::isfinite(kappa_est)) ? terms + 1 : terms;
+}
+
 int ls_workspace_size(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t* pr,
                       const ls_iter_opts_t* io_in, size_t* bytes) {
   if (!bytes) return LS_E_ARG;
@@ -245,7 +259,9 @@ int ls_workspace_size(const ls_problem_t* P, const ls_sketch_opts_t* so, const l
   LS_TRY(check_sketch(P, so, pr->u_s));
   const ls_iter_opts_t io = fill_opts(io_in, P->n, pr->u);
   const int64_t n = P->n, s = sketch_rows(P, so);
-  const SketchPlan sp = sketch_plan(P, so, s, pr->u_s);
+  ls_sketch_opts_t so_max = *so;   // the sketch with the most parts it may use
+  if (so->max_terms > so->terms) so_max.terms = so->max_terms;
+  const SketchPlan sp = sketch_plan(P, &so_max, s, pr->u_s);
   size_t fixed = ls_align256(8 * (size_t)s * (n + 1))          // Y
                  + ls_align256(8 * (size_t)(n + 1) * (n + 1))    // R_aug
                  + inv_carve(nullptr, n).bytes                   // R^-1
@@ -385,23 +401,42 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
 
   prof_reset(io.profile != 0);
   Timer tm;
-  tm.mark(0, st);
-  // Algorithm 1 step 1
-  const SketchPlan sp = sketch_plan(P, so, s, pr->u_s);
-  LS_TRY(sketch_run(P, so, pr->u_s, sp, s, Y, s, scratch, st));
-  tm.mark(1, st);
-  // Algorithm 1 step 2, then x^s = R^-1 (Q^T Omega b)
-  LS_HIP_TRY(hipMemsetAsync(inv.flag, 0, sizeof(int), st));
-  LS_TRY(qr_run(s, n + 1, pr->u_qr, Y, s, Raug, n + 1, scratch, scratch_bytes, inv.flag, n, st));
-  LS_TRY(trinv_run(Raug, n + 1, n, inv.W, n, inv.W32, inv.flag, st));
-  hipLaunchKernelGGL(k_trmv_f64, dim3((unsigned)ls_cdiv(n, 32)), dim3(kUtThreads), 0, st, inv.W, n, Raug + n * (n + 1), x);
-  int flag = 0;
-  LS_HIP_TRY(hipMemcpyAsync(&flag, inv.flag, sizeof(int), hipMemcpyDeviceToHost, st));
-  LS_HIP_TRY(hipStreamSynchronize(st));
-  tm.mark(2, st);
-  if (flag) {
-    S->status = LS_E_SINGULAR;
-    return LS_E_SINGULAR;
+  ls_sketch_opts_t so_t = *so;   // the parts of the current sketch
+  std::vector<double> fro(2 * (size_t)n);
+  double ms_sk = 0.0, ms_qr = 0.0;
+  for (;;) {
+    tm.mark(0, st);
+    // Algorithm 1 step 1
+    const SketchPlan sp = sketch_plan(P, &so_t, s, pr->u_s);
+    LS_TRY(sketch_run(P, &so_t, pr->u_s, sp, s, Y, s, scratch, st));
+    tm.mark(1, st);
+    // Algorithm 1 step 2, then x^s = R^-1 (Q^T Omega b)
+    LS_HIP_TRY(hipMemsetAsync(inv.flag, 0, sizeof(int), st));
+    LS_TRY(qr_run(s, n + 1, pr->u_qr, Y, s, Raug, n + 1, scratch, scratch_bytes, inv.flag, n, st));
+    LS_TRY(trinv_run(Raug, n + 1, n, inv.W, n, inv.W32, inv.flag, st, inv.fro));
+    hipLaunchKernelGGL(k_trmv_f64, dim3((unsigned)ls_cdiv(n, 32)), dim3(kUtThreads), 0, st, inv.W, n,
+                       Raug + n * (n + 1), x);
+    int flag = 0;
+    LS_HIP_TRY(hipMemcpyAsync(&flag, inv.flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    LS_HIP_TRY(hipMemcpyAsync(fro.data(), inv.fro, 16 * (size_t)n, hipMemcpyDeviceToHost, st));
+    tm.mark(2, st);
+    LS_HIP_TRY(hipStreamSynchronize(st));
+    if (flag) {
+      S->status = LS_E_SINGULAR;
+      return LS_E_SINGULAR;
+    }
+    double w2 = 0.0, r2 = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+      w2 += fro[2 * (size_t)j];
+      r2 += fro[2 * (size_t)j + 1];
+    }
+    S->kappa_est = std::sqrt(w2) * std::sqrt(r2) / std::sqrt((double)n);
+    S->sketch_terms = so_t.terms;
+    ms_sk += tm.ms(0, 1);
+    ms_qr += tm.ms(1, 2);
+    const int next = ls_sketch_terms_for(S->kappa_est, pr->u_s, so_t.terms, so->max_terms);
+    if (next == so_t.terms) break;
+    so_t.terms = next;   // Section 4: kappa(A) u_s < 1 not met with this many parts
   }
   // the preconditioned operator B = A R^-1, then Algorithm 2 line 1
   LS_TRY(form_b(P, inv.W, inv.W32, pr->u, B1, st));
@@ -435,8 +470,8 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
   }
   tm.mark(4, st);
   LS_HIP_TRY(hipStreamSynchronize(st));
-  S->ms_sketch = tm.ms(0, 1);
-  S->ms_qr = tm.ms(1, 2);
+  S->ms_sketch = ms_sk;
+  S->ms_qr = ms_qr;
   S->ms_lsqr = tm.ms(2, 3);
   S->ms_lsir = tm.ms(3, 4);
   if (io.profile) prof_collect(S);

@@ -48,8 +48,9 @@ size_t qr_workspace(int64_t s, int64_t ncols, ls_prec_t u_qr);
 int qr_run(int64_t s, int64_t ncols, ls_prec_t u_qr, double* Y, int64_t ldy, double* R, int64_t ldr,
            char* ws, size_t ws_bytes, int* d_flag, int64_t check_cols, hipStream_t st);
 // W = R^-1 (n x n upper, binary64, ldw) and, if W32 != NULL, its binary32 copy (ld n).
+// With fro != NULL: fro[2j] = ||W[:, j]||^2, fro[2j+1] = ||R[:, j]||^2 (2n doubles).
 int trinv_run(const double* R, int64_t ldr, int64_t n, double* W, int64_t ldw, float* W32, int* d_flag,
-              hipStream_t st);
+              hipStream_t st, double* fro = nullptr);
 
 // ------------------------------------------------------------------ iterations
 struct FgState {

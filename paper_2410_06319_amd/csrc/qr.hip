@@ -571,7 +571,8 @@ __global__ __launch_bounds__(256) void k_qr_finish(const T* __restrict__ Y, int6
 // triangle with one row per lane (the chunk's rows of R in registers, each
 // solved entry broadcast from its lane through a scalar register, the
 // diagonal applied as a precomputed reciprocal); then every thread subtracts
-// the chunk's contribution from the rows above it.
+// the chunk's contribution from the rows above it.  With fro != nullptr the
+// block also stores fro[2j] = ||W[:, j]||^2 and fro[2j+1] = ||R[0:j+1, j]||^2.
 __device__ __forceinline__ double trinv_bcast(double v, int lane) {
   const uint64_t u = __builtin_bit_cast(uint64_t, v);
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
@@ -580,11 +581,14 @@ __device__ __forceinline__ double trinv_bcast(double v, int lane) {
 }
 
 __global__ __launch_bounds__(256) void k_trinv(const double* __restrict__ R, int64_t ldr, int64_t n,
-                                               double* __restrict__ W, int64_t ldw, int* __restrict__ flag) {
+                                               double* __restrict__ W, int64_t ldw, int* __restrict__ flag,
+                                               double* __restrict__ fro) {
   extern __shared__ double bsh[];
+  __shared__ double red[4];
   const int64_t j = blockIdx.x;
   const int t = threadIdx.x;
   const int lane = t & 63;
+  double wsq = 0.0;   // wave 0: squares of the solved entries of its lanes
   for (int64_t i = t; i <= j; i += 256) bsh[i] = (i == j) ? 1.0 : 0.0;
   for (int64_t i = j + 1 + t; i < n; i += 256) W[i + j * ldw] = 0.0;
   for (int64_t c0 = (j / 64) * 64; c0 >= 0; c0 -= 64) {
@@ -609,6 +613,7 @@ __global__ __launch_bounds__(256) void k_trinv(const double* __restrict__ R, int
       if (act) {
         bsh[i] = bi;
         W[i + j * ldw] = bi;
+        wsq += bi * bi;
         if (!isfinite(bi)) *flag = 1;
       }
     }
@@ -624,6 +629,19 @@ __global__ __launch_bounds__(256) void k_trinv(const double* __restrict__ R, int
         for (int q = 0; q < 16; ++q) acc[q & 3] += v[q] * ((kb + q < cn) ? bsh[c0 + kb + q] : 0.0);
       }
       bsh[i] -= (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    }
+  }
+  if (fro) {
+    double rsq = 0.0;
+    for (int64_t i = t; i <= j; i += 256) {
+      const double v = R[i + j * ldr];
+      rsq += v * v;
+    }
+    const double rs = ls_block_sum<double, 256>(rsq, red);
+    const double ws = ls_wave_sum(wsq);   // nonzero in wave 0 only
+    if (t == 0) {
+      fro[2 * j] = ws;
+      fro[2 * j + 1] = rs;
     }
   }
 }
@@ -716,9 +734,9 @@ int qr_run(int64_t s, int64_t ncols, ls_prec_t u_qr, double* Y, int64_t ldy, dou
 }
 
 int trinv_run(const double* R, int64_t ldr, int64_t n, double* W, int64_t ldw, float* W32, int* d_flag,
-              hipStream_t st) {
+              hipStream_t st, double* fro) {
   hipLaunchKernelGGL(k_trinv, dim3((unsigned)n), dim3(256), (size_t)n * sizeof(double), st, R, ldr, n, W, ldw,
-                     d_flag);
+                     d_flag, fro);
   if (W32)
     hipLaunchKernelGGL(k_to_f32, dim3((unsigned)ls_cdiv(n, 256), (unsigned)n), dim3(256), 0, st, W, ldw, n, W32);
   LS_HIP_TRY(hipGetLastError());

@@ -53,3 +53,30 @@ def test_default_options_follow_section_5():
     lib.ls_default_iter_opts(100, _binding.FP64, ctypes.byref(o))
     assert (o.lsqr_tol, o.fgmres_tol) == (1e-12, 1e-12)
     assert o.lsir_tol == pytest.approx(4 * 2.0 ** -53)
+
+
+def test_struct_layouts_match_the_binding(tmp_path):
+    # the header is plain C: gcc reports each field's offset and each struct's
+    # size, which the ctypes mirrors in the binding must reproduce
+    import ctypes
+    from paper_2410_06319_amd import _binding as B
+    structs = {"ls_problem_t": B.Problem, "ls_precs_t": B.Precs, "ls_sketch_opts_t": B.SketchOpts,
+               "ls_iter_opts_t": B.IterOpts, "ls_stats_t": B.Stats}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "ls.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        s, f, v = line.split()
+        got[(s, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

@@ -443,6 +443,38 @@ def test_solve_narrow_sketch_reaches_6e6(L, fmt, terms, kappa):
     assert rc == 0 and ex <= 6e-6 and er <= 6e-6
 
 
+@pytest.mark.parametrize("kappa,want_terms", [(1e1, 1), (1e4, 2)])
+def test_solve_adds_sketch_parts_while_kappa_u_s_exceeds_one(L, kappa, want_terms):
+    # bf16 from one part with max_terms = 3: kappa(A) = 1e4 gives kappa_est u_s
+    # near 40 with one part and 0.15 with two, so the solve settles on two parts
+    # (kappa = 10: one part suffices).  The reported estimate is the oracle's
+    # estimate of the R the GPU forms from the sketch with that many parts, and
+    # the oracle's rule on the GPU's one-part R asks for the same parts.
+    from oracle import solve as osolve
+    P = make_problem(20000, 100, kappa, seed=2410064192, store="f32")
+    At, b = dev(P.At), dev(P.b)
+    pr = L.precs(u_s="bf16", u_qr="f32", u="f32", u_r="f64")
+    x, r, rc, st = L.ls_solve(At, b, s=400, seed=9, terms=1, max_terms=3, pr=pr, lsir_tol=6e-6)
+    sync_print(f"kappa {kappa:g}: parts {st['sketch_terms']}, kappa_est {st['kappa_est']:.4g}, "
+               f"lsqr {st['lsqr_its']}, fgmres {st['fgmres_its_total']}")
+    assert rc == 0 and st["sketch_terms"] == want_terms
+    ests = []
+    for t in range(1, want_terms + 1):
+        Y = L.ls_sketch(At, b, 400, seed=9, u_s="bf16", terms=t)
+        R = host(L.ls_qr_r(Y, u_qr="f32")).T[:100, :100]
+        ests.append(osolve.kappa_est(R))
+    # the same R (deterministic sketch and QR); R^-1 by two routes: binary64
+    # rounding amplified by kappa(R) <= 1e4 at most
+    assert st["kappa_est"] == pytest.approx(ests[-1], rel=1e-9)
+    t = 1
+    while osolve.terms_for(ests[t - 1], "bf16", t, 3) != t:
+        t += 1
+    assert t == want_terms
+    xr, rr, _ = refsolve.ref_solve(P.At, P.b)
+    ex, er = refsolve.forward_errors(host(x), host(r), xr, rr)
+    assert ex <= 6e-6 and er <= 6e-6
+
+
 def test_solve_batched_equals_single_solves(L):
     # uneven problems (sizes, conditioning, seeds) over several workers: each
     # result is bitwise the single-problem one and reaches the target
@@ -477,3 +509,7 @@ def test_solve_rejects_bad_arguments(L):
     with pytest.raises(L.LsError) as e:
         L.ls_solve(At, b, s=40, seed=1, terms=4, pr=L.precs())         # terms out of range
     assert e.value.code == -1
+    for terms, max_terms in ((2, 1), (1, 4)):                         # max_terms below terms or above 3
+        with pytest.raises(L.LsError) as e:
+            L.ls_solve(At, b, s=40, seed=1, terms=terms, max_terms=max_terms, pr=L.precs())
+        assert e.value.code == -1
