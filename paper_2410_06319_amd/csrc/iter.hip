@@ -1473,11 +1473,11 @@ LsqrWs lsqr_carve(char* ws, const ls_problem_t* P, size_t elt, int G, int Gv) {
 }
 
 template <typename T, int Q>
-void lsqr_pan_launch(int G, hipStream_t st, const T* Bm, int64_t npan, int64_t m, int64_t n, const T* v,
+void lsqr_pan_launch(int G, hipStream_t st, ProfEv ev, const T* Bm, int64_t npan, int64_t m, int64_t n, const T* v,
                      const double* nvp, int Gv, T* u, const LsqrState* S, int par, int init, T* tpart,
                      double* nupart, double* nbpart) {
-  hipLaunchKernelGGL((k_lsqr_pan<T, Q>), dim3(G), dim3(kThreads), 0, st, Bm, npan, m, n, v, nvp, Gv, u, S, par, init,
-                     tpart, nupart, nbpart);
+  hipExtLaunchKernelGGL((k_lsqr_pan<T, Q>), dim3(G), dim3(kThreads), 0, st, ev.a, ev.b, 0, Bm, npan, m, n, v, nvp,
+                        Gv, u, S, par, init, tpart, nupart, nbpart);
 }
 
 template <typename T>
@@ -1516,9 +1516,9 @@ int lsqr_typed(const ls_problem_t* P, const double* R, int64_t ldr, const double
     hipLaunchKernelGGL((k_cast<T, double>), dim3((unsigned)ls_cdiv(m, kThreads)), dim3(kThreads), 0, st,
                        (const double*)P->b, u, m, T(1));
   auto pass = [&](int par, int init, const double* nvp) {
-    prof_begin(kProfLsqrPass, st);
-#define LS_LSQR_PAN(QQ)                                                                                        \
-  lsqr_pan_launch<T, QQ>(G, st, Bm, npan, m, n, v, nvp, Gv, u, w.st, par, init, tpart, w.nupart, w.nbpart); \
+    const ProfEv ev = prof_events(kProfLsqrPass);
+#define LS_LSQR_PAN(QQ)                                                                                            \
+  lsqr_pan_launch<T, QQ>(G, st, ev, Bm, npan, m, n, v, nvp, Gv, u, w.st, par, init, tpart, w.nupart, w.nbpart); \
   break
     switch (q) {
       case 1: LS_LSQR_PAN(1);
@@ -1530,9 +1530,10 @@ int lsqr_typed(const ls_problem_t* P, const double* R, int64_t ldr, const double
     }
 #undef LS_LSQR_PAN
     // B once, u read and written, v read, t written
-    prof_end(kProfLsqrPass, st, (double)m * n * sizeof(T) + 2.0 * m * sizeof(T) + 2.0 * n * sizeof(T));
+    prof_commit(kProfLsqrPass, (double)m * n * sizeof(T) + 2.0 * m * sizeof(T) + 2.0 * n * sizeof(T));
   };
   // init: u_1 = b - B z0, beta_1, v_1 = B^T u_1 / beta_1; C_1 -> rec[1]
+  const size_t pmark = prof_mark();
   pass(1, 1, w.nvpart[0]);
   ProgressSlot slot(st);
   Progress *prog = slot.host, *dprog = slot.dev;
@@ -1573,6 +1574,9 @@ int lsqr_typed(const ls_problem_t* P, const double* R, int64_t ldr, const double
   LS_HIP_TRY(hipStreamSynchronize(st));
   LS_HIP_TRY(hipGetLastError());
   rec = S.rec[fpar];
+  // full passes: the first one, then iterations 1 .. its + 1 (the column
+  // kernel of the last of them finds the stop)
+  prof_keep(kProfLsqrPass, pmark, rec.its + 2);
   if (stats) {
     stats->lsqr_its = rec.its;
     stats->lsqr_normr = rec.normr;
@@ -1625,11 +1629,11 @@ struct LsirDims {
 };
 
 template <typename TB, int Q>
-void fg_pan_launch(int G, hipStream_t st, const TB* Bm, int64_t npan, int64_t m, int64_t n, const FgPtrs& F, int j,
-                   int kmax, const double* w2part, int Gw, double tol, int final_step, TB* tpart,
-                   Progress* prog) {
-  hipLaunchKernelGGL((k_fg_pan<TB, Q>), dim3(G), dim3(kThreads), 0, st, Bm, npan, m, n, F, j, kmax, w2part, Gw, tol,
-                     final_step, tpart, prog);
+void fg_pan_launch(int G, hipStream_t st, ProfEv ev, const TB* Bm, int64_t npan, int64_t m, int64_t n,
+                   const FgPtrs& F, int j, int kmax, const double* w2part, int Gw, double tol, int final_step,
+                   TB* tpart, Progress* prog) {
+  hipExtLaunchKernelGGL((k_fg_pan<TB, Q>), dim3(G), dim3(kThreads), 0, st, ev.a, ev.b, 0, Bm, npan, m, n, F, j, kmax,
+                        w2part, Gw, tol, final_step, tpart, prog);
 }
 
 LsirDims lsir_dims(const ls_problem_t* P, size_t tb_elt, size_t ta_elt, int fgmres_maxit, int ncu) {
@@ -1707,9 +1711,9 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
                        r);
   ProgressSlot slot(st);
   Progress *prog = slot.host, *dprog = slot.dev;
-  auto fg_pass = [&](int j, int Gw, int final_step, int grid) {
+  auto fg_pass = [&](int j, int Gw, int final_step, int grid, ProfEv ev) {
 #define LS_FG_PAN(QQ)                                                                                              \
-  fg_pan_launch<TB, QQ>(grid, st, Bm, d.npan, m, n, F, j, d.kmax, w.w2part, Gw, tol, final_step, tpart,         \
+  fg_pan_launch<TB, QQ>(grid, st, ev, Bm, d.npan, m, n, F, j, d.kmax, w.w2part, Gw, tol, final_step, tpart,     \
                         dprog);                                                                                    \
   break
     switch (q) {
@@ -1732,17 +1736,18 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
       tol = std::min(1e-2, std::max(io->fgmres_tol, tol));
     }
     // lines 5-6: f, g, h in u_r
-    prof_begin(kProfResidPass, st);
-    hipLaunchKernelGGL((k_lsir_resid<TA, DD>), dim3((unsigned)d.Gr), dim3(kThreads), 0, st, A, P->lda, m, n, vec_a, b,
-                       r, x, w.V, w.rt_hi, w.rt_lo, w.w2part);
+    const ProfEv ev = prof_events(kProfResidPass);
+    hipExtLaunchKernelGGL((k_lsir_resid<TA, DD>), dim3((unsigned)d.Gr), dim3(kThreads), 0, st, ev.a, ev.b, 0, A,
+                          P->lda, m, n, vec_a, b, r, x, w.V, w.rt_hi, w.rt_lo, w.w2part);
     // A and b once, r read, f written, x read, g written
-    prof_end(kProfResidPass, st, (double)m * n * sizeof(TA) + (double)m * sizeof(TA) + 16.0 * m + 16.0 * n);
+    prof_commit(kProfResidPass, (double)m * n * sizeof(TA) + (double)m * sizeof(TA) + 16.0 * m + 16.0 * n);
     hipLaunchKernelGGL(k_lsir_g<DD>, dim3((unsigned)ls_cdiv(n, 4)), dim3(kThreads), 0, st, w.rt_hi, w.rt_lo, d.Gr, n,
                        w.gvec);
     hipLaunchKernelGGL(k_lsir_h<DD>, dim3((unsigned)d.Gh), dim3(kThreads), 0, st, W, n, m, w.gvec, w.V,
                        w.w2part + d.Gr);
     hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(kThreads), 0, st, reinterpret_cast<char*>(w.st), sizeof(FgState));
     // line 7: FGMRES on [I B; B^T 0]
+    const size_t pmark = prof_mark();
     int j = 0;
     FgState S{};
     if (prog) {   // the previous cycle has been synchronised: no kernel writes the slot now
@@ -1751,10 +1756,9 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
     }
     for (; j < d.kmax; ++j) {
       const int Gw = (j == 0) ? d.Gr + d.Gh : d.Gs;
-      prof_begin(kProfFgPass, st);
-      fg_pass(j, Gw, 0, d.G);
+      fg_pass(j, Gw, 0, d.G, prof_events(kProfFgPass));
       // B once, v_j read and written, w written, v_x read, t written
-      prof_end(kProfFgPass, st, (double)m * n * sizeof(TB) + 24.0 * m + 8.0 * n + (double)n * sizeof(TB));
+      prof_commit(kProfFgPass, (double)m * n * sizeof(TB) + 24.0 * m + 8.0 * n + (double)n * sizeof(TB));
       hipLaunchKernelGGL(k_fg_col<TB>, dim3((unsigned)(ncb + d.Gk)), dim3(1024), 0, st, m, n, tpart, d.G, F, j, ncb,
                          d.Gk, w.hxpart);
       prof_begin(kProfCgs, st);
@@ -1779,7 +1783,7 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
       }
     }
     // final Givens step for the last column (no-op when already done)
-    fg_pass(j < d.kmax ? j + 1 : d.kmax, d.Gs, 1, 1);
+    fg_pass(j < d.kmax ? j + 1 : d.kmax, d.Gs, 1, 1, ProfEv{});
     hipLaunchKernelGGL(k_fg_update<TU>, dim3((unsigned)d.Gd), dim3(kThreads), 0, st, F, m, n, d.kmax, r, w.dz, w.upart);
     hipLaunchKernelGGL(k_fg_dx<TU>, dim3((unsigned)d.Gn), dim3(kUtThreads), 0, st, W, n, w.dz, x,
                        w.upart + 2 * (size_t)d.Gd);
@@ -1788,6 +1792,9 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
     LS_HIP_TRY(hipStreamSynchronize(st));
     LS_HIP_TRY(hipGetLastError());
     if (S.breakdown == 2) return LS_E_NONFINITE;
+    // passes and sweeps of columns 0 .. k-1; later ones were queued past convergence
+    prof_keep(kProfFgPass, pmark, S.k);
+    prof_keep(kProfCgs, pmark, S.k);
     total_fg += S.k;
     double nr[2] = {0, 0}, nx[2] = {0, 0};
     for (int g = 0; g < d.Gd; ++g) {

@@ -1,6 +1,8 @@
 // Internal interfaces between the host drivers and the kernel files of libls.
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "common.h"
 
 namespace ls {
@@ -90,5 +92,17 @@ constexpr int kProfClasses = 6;
 void prof_reset(bool on);
 void prof_begin(int cls, hipStream_t st);
 void prof_end(int cls, hipStream_t st, double work);   // work: algorithmic flops or bytes
+// Single-kernel classes: the event pair that the class's next launch carries
+// (hipExtLaunchKernelGGL stamps it with the kernel's own start and end; both
+// null when profiling is off), then prof_commit files that launch.
+struct ProfEv {
+  hipEvent_t a = nullptr, b = nullptr;
+};
+ProfEv prof_events(int cls);
+void prof_commit(int cls, double work);
+// Launches queued beyond convergence return at once: after a loop, keep only
+// the first `keep` records of class cls filed since position `from`.
+size_t prof_mark();
+void prof_keep(int cls, size_t from, int keep);
 void prof_collect(ls_stats_t* stats);   // after the stream has been synchronised
 }  // namespace ls

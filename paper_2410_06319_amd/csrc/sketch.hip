@@ -588,10 +588,10 @@ int sketch_narrow(const ls_problem_t* P, const ls_sketch_opts_t* so, const Sketc
   hipLaunchKernelGGL((k_pack_lp<TA, FMT>), dim3((unsigned)ls_cdiv(p.m_pad, 2048), (unsigned)p.n_pad), dim3(256), 0, st,
                      A, P->lda, b, P->m, P->n, p.terms, e, Tt, p.m_pad, p.n_pad);
   const dim3 gb((unsigned)(p.ns * p.nn * p.nsplit));
-  prof_begin(kProfSketch, st);
+  const ProfEv ev = prof_events(kProfSketch);
 #define LS_SK(BN_, T_)                                                                                             \
-  hipLaunchKernelGGL((k_sketch_lp<FMT, BN_, T_>), gb, dim3(kSkThreads), 0, st, Tt, p.nkb, p.n_pad, p.kb_per_split, \
-                     (int)p.ns, (int)p.nn, key0, key1, so->prob_id, Yp, p.s_pad)
+  hipExtLaunchKernelGGL((k_sketch_lp<FMT, BN_, T_>), gb, dim3(kSkThreads), 0, st, ev.a, ev.b, 0, Tt, p.nkb,       \
+                        p.n_pad, p.kb_per_split, (int)p.ns, (int)p.nn, key0, key1, so->prob_id, Yp, p.s_pad)
   if (p.bn == 128) {
     if (p.terms == 1) LS_SK(128, 1); else if (p.terms == 2) LS_SK(128, 2); else LS_SK(128, 3);
   } else if (p.bn == 256) {
@@ -600,7 +600,7 @@ int sketch_narrow(const ls_problem_t* P, const ls_sketch_opts_t* so, const Sketc
     if (p.terms == 1) LS_SK(512, 1); else if (p.terms == 2) LS_SK(512, 2); else LS_SK(512, 3);
   }
 #undef LS_SK
-  prof_end(kProfSketch, st, 2.0 * (double)s * (double)P->m * (double)(P->n + 1));
+  prof_commit(kProfSketch, 2.0 * (double)s * (double)P->m * (double)(P->n + 1));
   hipLaunchKernelGGL(k_sketch_combine<float>, dim3((unsigned)ls_cdiv(s, 256), (unsigned)p.ncols), dim3(256), 0, st, Yp,
                      p.s_pad, p.n_pad, (int)p.nsplit, s, p.ncols, 1.0 / sqrt((double)s), (const int32_t*)e, Y, ldy);
   LS_HIP_TRY(hipGetLastError());
@@ -647,10 +647,10 @@ int sketch_run(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s,
     hipLaunchKernelGGL(k_pack_f64<float>, gpack, dim3(256), 0, st, (const float*)P->A, P->lda,
                        (const float*)P->b, P->m, P->n, M, p.m_pad, p.n_pad);
   double* Yp = reinterpret_cast<double*>(partial);
-  prof_begin(kProfSketch, st);
-  hipLaunchKernelGGL((k_sketch_f64<8>), gsk, dim3(256), 0, st, M, p.m_pad, p.n_pad, p.kchunk, key0,
-                     key1, so->prob_id, Yp, p.s_pad);
-  prof_end(kProfSketch, st, 2.0 * (double)s * (double)P->m * (double)(P->n + 1));
+  const ProfEv ev = prof_events(kProfSketch);
+  hipExtLaunchKernelGGL((k_sketch_f64<8>), gsk, dim3(256), 0, st, ev.a, ev.b, 0, M, p.m_pad, p.n_pad, p.kchunk,
+                        key0, key1, so->prob_id, Yp, p.s_pad);
+  prof_commit(kProfSketch, 2.0 * (double)s * (double)P->m * (double)(P->n + 1));
   hipLaunchKernelGGL(k_sketch_combine<double>, gcomb, dim3(256), 0, st, Yp, p.s_pad, p.n_pad,
                      (int)p.nsplit, s, p.ncols, scale, (const int32_t*)nullptr, Y, ldy);
   LS_HIP_TRY(hipGetLastError());

@@ -221,11 +221,11 @@ int sparse_typed(const ls_problem_t* P, const ls_sketch_opts_t* so, int64_t s, d
   hipLaunchKernelGGL((k_ss_transpose<TA>), gt, dim3(256), 0, st, static_cast<const TA*>(P->A), P->lda,
                      static_cast<const TA*>(P->b), m, n, reinterpret_cast<TA*>(c.T));
   const double scale = 1.0 / std::sqrt((double)zeta);
-  prof_begin(kProfSparse, st);
-  hipLaunchKernelGGL((k_ss_gather<TA>), dim3((unsigned)s), dim3(kGatherThreads), 0, st,
-                     reinterpret_cast<const TA*>(c.T), n1, c.start, c.vals_out, scale, Y, ldy);
+  const ProfEv ev = prof_events(kProfSparse);
+  hipExtLaunchKernelGGL((k_ss_gather<TA>), dim3((unsigned)s), dim3(kGatherThreads), 0, st, ev.a, ev.b, 0,
+                        reinterpret_cast<const TA*>(c.T), n1, c.start, c.vals_out, scale, Y, ldy);
   // [A b] once (as the transposed copy) and Y written
-  prof_end(kProfSparse, st, (double)m * n1 * sizeof(TA) + 8.0 * (double)s * n1);
+  prof_commit(kProfSparse, (double)m * n1 * sizeof(TA) + 8.0 * (double)s * n1);
   LS_HIP_TRY(hipGetLastError());
   int fail = 0;
   LS_HIP_TRY(hipMemcpyAsync(&fail, c.fail, sizeof(int), hipMemcpyDeviceToHost, st));

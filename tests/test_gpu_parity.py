@@ -475,6 +475,24 @@ def test_solve_adds_sketch_parts_while_kappa_u_s_exceeds_one(L, kappa, want_term
     assert ex <= 6e-6 and er <= 6e-6
 
 
+def test_profile_files_one_record_per_launch_before_convergence(L):
+    # profile = 1 with the default queue depth: the launches queued past
+    # convergence are not filed, so the counts follow the iteration counts
+    P = make_problem(20000, 100, 1e4, seed=2410064193, store="f32")
+    pr = L.precs(u_s="bf16", u_qr="f32", u="f32", u_r="f64")
+    x, r, rc, st = L.ls_solve(dev(P.At), dev(P.b), s=400, seed=7, terms=2, pr=pr, lsir_tol=6e-6, profile=1)
+    n_l, ms = st["kernel_launches"], st["kernel_ms"]
+    sync_print("profile:", n_l, {k: round(v, 3) for k, v in ms.items()})
+    assert rc == 0
+    assert n_l["sketch_mfma"] == 1
+    assert n_l["lsqr_pass"] == st["lsqr_its"] + 2          # the first pass, then iterations 1 .. its + 1
+    assert n_l["fgmres_pass"] == st["fgmres_its_total"]
+    assert n_l["cgs_sweep"] == st["fgmres_its_total"]
+    assert n_l["lsir_resid_pass"] == st["lsir_its"]
+    for k in ("sketch_mfma", "lsqr_pass", "fgmres_pass", "lsir_resid_pass", "cgs_sweep"):
+        assert ms[k] > 0
+
+
 def test_solve_batched_equals_single_solves(L):
     # uneven problems (sizes, conditioning, seeds) over several workers: each
     # result is bitwise the single-problem one and reaches the target
