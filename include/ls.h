@@ -109,6 +109,11 @@ typedef struct {
                         u^terms > 1 (u the format's unit roundoff: 2^-8, 2^-11,
                         2^-4) and terms < max_terms, the sketch, R and R^-1 are
                         formed again with one more part (ls_sketch_terms_for) */
+  int32_t plan;      /* launch shape of the sketch kernels: 0 = the library's
+                        choice (a table tuned on the device by the package's
+                        autotune module, for the shape, format and parts), k >= 1 =
+                        candidate k of ls_sketch_plan_info.  Changes the
+                        grouping of the binary32 partial sums, not the method */
 } ls_sketch_opts_t;
 
 /* Iteration control (Section 5): LSQR at most 2n iterations, tolerance 1e-6
@@ -163,6 +168,7 @@ typedef struct {
    * operation must move to or from HBM for classes 1-5. */
   double kernel_work[6];
   int32_t sketch_terms;   /* parts of [A b] the sketch used (ls_solve) */
+  int32_t sketch_plan;    /* launch shape the sketch took (ls_solve; see ls_sketch_plan_info) */
   double kappa_est;       /* ||R||_F ||R^-1||_F / sqrt(n) of the preconditioner
                              (ls_solve): kappa_2(R) / sqrt(n) <= kappa_est <=
                              sqrt(n) kappa_2(R), and kappa_2(R) is kappa(A) up to
@@ -270,6 +276,13 @@ int ls_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, u
  * kappa(A) u_s < 1 with u_s = u^terms, the accuracy of a terms-part
  * representation); otherwise terms.  Host only. */
 int ls_sketch_terms_for(double kappa_est, ls_prec_t u_s, int32_t terms, int32_t max_terms);
+
+/* Launch shape candidate `plan` (1-based) of the sketch in format u_s:
+ * columns of [A b] per block (0: the narrowest of 128, 256 and 512 that holds
+ * n + 1; binary64 blocks hold 128) and the blocks the K-splits aim at, in
+ * quarters of the device's compute units.  Returns LS_E_ARG past the last
+ * candidate (the count is the first plan that fails).  Host only. */
+int ls_sketch_plan_info(ls_prec_t u_s, int32_t plan, int32_t *tile_cols, int32_t *quarter_cus);
 
 /* Static text for a status code. */
 const char *ls_strerror(int status);

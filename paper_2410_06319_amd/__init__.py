@@ -22,6 +22,7 @@ from .api import (  # noqa: F401
     precs,
     problem,
     sketch_opts,
+    sketch_plan_info,
     sketch_terms_for,
     workspace,
     workspace_size,

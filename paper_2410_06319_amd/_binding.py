@@ -27,7 +27,7 @@ class Precs(ctypes.Structure):
 class SketchOpts(ctypes.Structure):
     _fields_ = [("s", ctypes.c_int64), ("seed", ctypes.c_uint64), ("prob_id", ctypes.c_uint32),
                 ("terms", ctypes.c_int32), ("col_scale", ctypes.c_int32), ("zeta", ctypes.c_int32),
-                ("max_terms", ctypes.c_int32)]
+                ("max_terms", ctypes.c_int32), ("plan", ctypes.c_int32)]
 
 
 class IterOpts(ctypes.Structure):
@@ -47,7 +47,7 @@ class Stats(ctypes.Structure):
                 ("ms_qr", ctypes.c_double), ("ms_lsqr", ctypes.c_double), ("ms_lsir", ctypes.c_double),
                 ("kernel_ms", ctypes.c_double * 6), ("kernel_launches", ctypes.c_int32 * 6),
                 ("kernel_work", ctypes.c_double * 6), ("sketch_terms", ctypes.c_int32),
-                ("kappa_est", ctypes.c_double)]
+                ("sketch_plan", ctypes.c_int32), ("kappa_est", ctypes.c_double)]
 
     KERNEL_CLASSES = ("sketch_mfma", "lsqr_pass", "fgmres_pass", "lsir_resid_pass", "cgs_sweep", "sparse_sketch")
 
@@ -80,6 +80,7 @@ SIGNATURES = {
     "ls_philox": (ctypes.c_int, [u32, u32, u32, u32, u32, u32, i64, vp, vp]),
     "ls_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "ls_sketch_terms_for": (ctypes.c_int, [ctypes.c_double, ctypes.c_int, ctypes.c_int32, ctypes.c_int32]),
+    "ls_sketch_plan_info": (ctypes.c_int, [ctypes.c_int, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32)]),
     "ls_workspace_size_batched": (ctypes.c_int, [ctypes.c_int, P(Problem), P(SketchOpts), P(Precs), P(IterOpts),
                                                  ctypes.c_int, P(ctypes.c_size_t)]),
     "ls_solve_batched": (ctypes.c_int, [ctypes.c_int, P(Problem), P(SketchOpts), P(Precs), P(IterOpts),

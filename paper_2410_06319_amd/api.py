@@ -49,9 +49,9 @@ def precs(u_s="bf16", u_qr="f32", u="f32", u_r="f64", u_A=None, u_L=None, u_R=No
                    u_A=B.PREC[u_A], u_L=B.PREC[u_L or u_A], u_R=B.PREC[u_R or u_A])
 
 
-def sketch_opts(s=0, seed=0, prob_id=0, terms=1, col_scale=0, zeta=0, max_terms=0) -> B.SketchOpts:
+def sketch_opts(s=0, seed=0, prob_id=0, terms=1, col_scale=0, zeta=0, max_terms=0, plan=0) -> B.SketchOpts:
     return B.SketchOpts(s=s, seed=seed, prob_id=prob_id, terms=terms, col_scale=col_scale, zeta=zeta,
-                        max_terms=max_terms)
+                        max_terms=max_terms, plan=plan)
 
 
 def iter_opts(n, u="f32", **kw) -> B.IterOpts:
@@ -81,12 +81,12 @@ def workspace_size(P, so, pr, io) -> int:
     return n.value
 
 
-def ls_sketch(At, b, s, seed=0, u_s="bf16", terms=1, prob_id=0, col_scale=0, zeta=0, ws=None):
+def ls_sketch(At, b, s, seed=0, u_s="bf16", terms=1, prob_id=0, col_scale=0, zeta=0, ws=None, plan=0):
     """Y = Omega [A b] (s x (n+1), float64; returned as a (n+1, s) tensor = column-major Y).
 
     u_s: "f64", "bf16", "f16" or "e4m3"; col_scale 0 = automatic (on for f16 and e4m3)."""
     P = problem(At, b)
-    so = sketch_opts(s=s, seed=seed, prob_id=prob_id, terms=terms, col_scale=col_scale, zeta=zeta)
+    so = sketch_opts(s=s, seed=seed, prob_id=prob_id, terms=terms, col_scale=col_scale, zeta=zeta, plan=plan)
     pr = precs(u_s=u_s, u_qr="f64", u="f64", u_r="f64")
     if ws is None:
         ws = workspace(workspace_size(P, so, pr, iter_opts(P.n, "f64")), At.device)
@@ -205,6 +205,14 @@ def ls_solve_batched(problems, s=0, seeds=None, terms=1, pr=None, col_scale=0, n
                                    ws.data_ptr(), ws.numel(), _stream())
     _check(rc, "ls_solve_batched")
     return xs, rs, rc, [stats[i].as_dict() for i in range(nprob)]
+
+
+def sketch_plan_info(u_s, plan):
+    """(columns per block, target blocks in quarters of the compute units) of
+    launch shape ``plan`` of the sketch in ``u_s``, or None past the last one."""
+    tc, qc = ctypes.c_int32(0), ctypes.c_int32(0)
+    rc = B.load().ls_sketch_plan_info(B.PREC[u_s], int(plan), ctypes.byref(tc), ctypes.byref(qc))
+    return (tc.value, qc.value) if rc == 0 else None
 
 
 def sketch_terms_for(kappa_est, u_s="bf16", terms=1, max_terms=3):

@@ -37,6 +37,7 @@ int check_sketch(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_
     if (u_s != LS_FP64 || so->terms > 1 || so->max_terms > 1) return LS_E_ARG;
     return sparse_check(P->m, so->zeta, s);
   }
+  if (so->plan < 0 || (so->zeta == 0 && so->plan > sketch_plan_count(u_s))) return LS_E_ARG;
   if (u_s == LS_BF16 || u_s == LS_FP16 || u_s == LS_FP8E4M3) {
     if (so->terms < 1 || so->terms > 3) return LS_E_ARG;
     if (so->max_terms != 0 && (so->max_terms < so->terms || so->max_terms > 3)) return LS_E_ARG;
@@ -240,6 +241,15 @@ const char* ls_strerror(int s) {
   }
 }
 
+int ls_sketch_plan_info(ls_prec_t u_s, int32_t plan, int32_t* tile_cols, int32_t* quarter_cus) {
+  if (!tile_cols || !quarter_cus) return LS_E_ARG;
+  int bn = 0, q = 0;
+  LS_TRY(sketch_plan_shape(u_s, plan, &bn, &q));
+  *tile_cols = (u_s == LS_FP64) ? 128 : bn;
+  *quarter_cus = q;
+  return LS_OK;
+}
+
 int ls_sketch_terms_for(double kappa_est, ls_prec_t u_s, int32_t terms, int32_t max_terms) {
   double u;
   if (u_s == LS_BF16) u = 0x1p-8;
@@ -259,16 +269,22 @@ int ls_workspace_size(const ls_problem_t* P, const ls_sketch_opts_t* so, const l
   LS_TRY(check_sketch(P, so, pr->u_s));
   const ls_iter_opts_t io = fill_opts(io_in, P->n, pr->u);
   const int64_t n = P->n, s = sketch_rows(P, so);
-  ls_sketch_opts_t so_max = *so;   // the sketch with the most parts it may use
-  if (so->max_terms > so->terms) so_max.terms = so->max_terms;
-  const SketchPlan sp = sketch_plan(P, &so_max, s, pr->u_s);
+  // the sketch with the most room over the parts the solve may use (each
+  // count of parts may take its own tuned launch shape)
+  size_t sk_bytes = 0;
+  for (int t = so->terms; t <= std::max(so->terms, so->max_terms); ++t) {
+    ls_sketch_opts_t so_t = *so;
+    so_t.terms = t;
+    const SketchPlan sp = sketch_plan(P, &so_t, s, pr->u_s);
+    sk_bytes = std::max(sk_bytes, sp.operand_bytes + sp.partial_bytes + sp.exp_bytes);
+  }
   size_t fixed = ls_align256(8 * (size_t)s * (n + 1))          // Y
                  + ls_align256(8 * (size_t)(n + 1) * (n + 1))    // R_aug
                  + inv_carve(nullptr, n).bytes                   // R^-1
                  + ls_align256(8 * (size_t)(P->m + n))           // saved x0 for the fallback
                  + b_bytes(P, pr->u)                             // B = A R^-1 for LSQR
                  + (second_b(pr, &io) ? b_bytes(P, LS_FP64) : 0); // binary64 B for FGMRES
-  size_t scratch = sp.operand_bytes + sp.partial_bytes + sp.exp_bytes;
+  size_t scratch = sk_bytes;
   const size_t q = qr_workspace(s, n + 1, pr->u_qr);
   if (q > scratch) scratch = q;
   const size_t it = iter_bytes(P, pr, &io);
@@ -432,6 +448,7 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
     }
     S->kappa_est = std::sqrt(w2) * std::sqrt(r2) / std::sqrt((double)n);
     S->sketch_terms = so_t.terms;
+    S->sketch_plan = sp.plan;
     ms_sk += tm.ms(0, 1);
     ms_qr += tm.ms(1, 2);
     const int next = ls_sketch_terms_for(S->kappa_est, pr->u_s, so_t.terms, so->max_terms);

@@ -27,9 +27,12 @@ struct SketchPlan {
   size_t operand_bytes;   // packed [A b]
   size_t partial_bytes;   // per-split partial sketches (followed by the exponents)
   int zeta;               // sparse sign embedding: nonzeros per column of Omega (0: Gaussian)
+  int plan;               // launch shape taken (1-based; see sketch_plan_shape)
 };
 
 SketchPlan sketch_plan(const ls_problem_t* P, const ls_sketch_opts_t* so, int64_t s, ls_prec_t u_s);
+int sketch_plan_count(ls_prec_t u_s);
+int sketch_plan_shape(ls_prec_t u_s, int plan, int* bn, int* quarter_cus);
 // Sparse sign embedding (Section 2): argument check, workspace, run.
 int sparse_check(int64_t m, int zeta, int64_t s);
 size_t sparse_workspace(int64_t m, int64_t n, int zeta, int64_t s, size_t ta_bytes);

@@ -509,6 +509,56 @@ namespace ls {
 
 static bool sk_narrow(ls_prec_t u) { return u == LS_BF16 || u == LS_FP16 || u == LS_FP8E4M3; }
 
+// Launch shapes the planner can take (plan = index + 1).  Narrow formats:
+// columns per block (0: the narrowest of 128 / 256 / 512 that holds n + 1)
+// and the blocks the K-splits aim at, in 1/4 of the compute units.  Binary64:
+// the blocks the K-splits aim at, in 1/4 of the compute units.  The first
+// entry is the untuned rule; the tuned table picks per shape.
+struct SkCand {
+  int bn;
+  int quarter_cus;
+};
+constexpr SkCand kNarrowCands[] = {{0, 4}, {0, 2}, {0, 1}, {0, 8}, {128, 4}, {256, 4}, {512, 4}};
+constexpr SkCand kF64Cands[] = {{0, 8}, {0, 4}, {0, 16}, {0, 2}};
+constexpr int kNarrowCandCount = (int)(sizeof(kNarrowCands) / sizeof(kNarrowCands[0]));
+constexpr int kF64CandCount = (int)(sizeof(kF64Cands) / sizeof(kF64Cands[0]));
+
+// Tuned choices: for each (format, parts) the first entry with n + 1 <=
+// ncols_max and m <= m_max gives the plan (written by the package's
+// autotune module from timings on the device).
+struct SkTuned {
+  int fmt, terms;
+  int64_t ncols_max, m_max;
+  int plan;
+};
+static const SkTuned kSkTuned[] = {
+#include "sketch_tuned.inc"
+    {-1, 0, 0, 0, 0}};
+
+int sketch_plan_count(ls_prec_t u_s) {
+  if (sk_narrow(u_s)) return kNarrowCandCount;
+  if (u_s == LS_FP64) return kF64CandCount;
+  return 0;
+}
+
+int sketch_plan_shape(ls_prec_t u_s, int plan, int* bn, int* quarter_cus) {
+  if (plan < 1 || plan > sketch_plan_count(u_s)) return LS_E_ARG;
+  const SkCand c = sk_narrow(u_s) ? kNarrowCands[plan - 1] : kF64Cands[plan - 1];
+  *bn = c.bn;
+  *quarter_cus = c.quarter_cus;
+  return LS_OK;
+}
+
+static int sketch_tuned_plan(ls_prec_t u_s, int terms, int64_t ncols, int64_t m) {
+  for (const SkTuned& t : kSkTuned) {
+    if (t.fmt < 0) break;
+    if (t.fmt == (int)u_s && t.terms == terms && ncols <= t.ncols_max && m <= t.m_max) {
+      return (t.plan >= 1 && t.plan <= sketch_plan_count(u_s)) ? t.plan : 1;
+    }
+  }
+  return 1;
+}
+
 SketchPlan sketch_plan(const ls_problem_t* P, const ls_sketch_opts_t* so, int64_t s, ls_prec_t u_s) {
   const int64_t m = P->m, n = P->n;
   const int terms = so->terms;
@@ -522,18 +572,24 @@ SketchPlan sketch_plan(const ls_problem_t* P, const ls_sketch_opts_t* so, int64_
   }
   p.terms = sk_narrow(u_s) ? terms : 1;
   p.exp_bytes = ls_align256(4 * (size_t)p.ncols);
+  int plan = (so->plan > 0) ? so->plan : sketch_tuned_plan(u_s, p.terms, p.ncols, m);
+  if (plan > sketch_plan_count(u_s)) plan = 1;
+  p.plan = plan;
+  const int64_t target = (int64_t)device_cu_count() *
+                         (sk_narrow(u_s) ? kNarrowCands[plan - 1].quarter_cus : kF64Cands[plan - 1].quarter_cus) / 4;
   if (sk_narrow(u_s)) {
     p.ebytes = (u_s == LS_FP8E4M3) ? 1 : 2;
-    p.bn = (p.ncols <= 128) ? 128 : (p.ncols <= 256) ? 256 : 512;
+    const int bn = kNarrowCands[plan - 1].bn;
+    p.bn = bn ? bn : (p.ncols <= 128) ? 128 : (p.ncols <= 256) ? 256 : 512;
     p.nn = ls_cdiv(p.ncols, p.bn);
     p.n_pad = p.nn * p.bn;
     p.ns = ls_cdiv(s, kSkRows);
     p.s_pad = p.ns * kSkRows;
     p.kstep = 32;
-    // about one block per compute unit; (column tiles x K-splits) a multiple
-    // of 8 so that each XCD receives whole groups
+    // about `target` blocks; (column tiles x K-splits) a multiple of 8 so
+    // that each XCD receives whole groups
     const int64_t kbn = ls_cdiv(m, 32);
-    int64_t nsplit = ls_cdiv(device_cu_count(), p.ns * p.nn);
+    int64_t nsplit = ls_cdiv(target, p.ns * p.nn);
     if (nsplit > kbn) nsplit = kbn;
     if (nsplit < 1) nsplit = 1;
     while ((p.nn * nsplit) % 8) ++nsplit;
@@ -551,9 +607,9 @@ SketchPlan sketch_plan(const ls_problem_t* P, const ls_sketch_opts_t* so, int64_
   p.nb = 8;
   p.kstep = 16;
   p.n_pad = ls_cdiv(p.ncols, 16 * p.nb) * 16 * p.nb;
-  // Split K so that the grid holds roughly 2 blocks per compute unit.
+  // split K so that the grid holds about `target` blocks
   const int64_t tiles = (p.s_pad / 64) * (p.n_pad / (16 * p.nb));
-  int64_t nsplit = ls_cdiv(512, tiles);
+  int64_t nsplit = ls_cdiv(target, tiles);
   const int64_t ksteps = ls_cdiv(m, p.kstep);
   if (nsplit > ksteps) nsplit = ksteps;
   if (nsplit < 1) nsplit = 1;

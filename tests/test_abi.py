@@ -80,3 +80,34 @@ def test_struct_layouts_match_the_binding(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_sketch_plan_candidates_and_tuned_table():
+    # the launch-shape candidates the library offers, and the tuned table it
+    # compiles in: every entry names a known format, parts and candidate, and
+    # within a (format, parts) group the cells grow in both sizes
+    import paper_2410_06319_amd as L
+    from paper_2410_06319_amd import _binding as B
+    L.load()
+    counts = {}
+    for fmt in ("bf16", "f16", "e4m3", "f64"):
+        k = 1
+        while L.sketch_plan_info(fmt, k) is not None:
+            tc, qc = L.sketch_plan_info(fmt, k)
+            assert tc in (0, 128, 256, 512) and qc >= 1
+            k += 1
+        counts[B.PREC[fmt]] = k - 1
+        assert k - 1 >= 4 and L.sketch_plan_info(fmt, 0) is None
+    assert L.sketch_plan_info("bf16", 1) == (0, 4)          # plan 1: the untuned rule
+    path = os.path.join(ROOT, "paper_2410_06319_amd", "csrc", "sketch_tuned.inc")
+    rows = []
+    for line in open(path):
+        line = line.split("//")[0].strip()
+        if line:
+            vals = [int(v) for v in re.findall(r"-?\d+", line)]
+            assert len(vals) == 5, line
+            rows.append(vals)
+    for fmt, terms, ncols_max, m_max, plan in rows:
+        assert fmt in counts and 1 <= plan <= counts[fmt]
+        assert (terms == 1) if fmt == B.FP64 else (1 <= terms <= 3)
+        assert ncols_max > 0 and m_max > 0

@@ -172,6 +172,38 @@ def test_sketch_narrow_colscaled_matches_oracle(L, fmt, m, n, s, store, terms):
     assert err.max() < 2e-3
 
 
+# every launch shape the planner can take (and the autotuned table's choice)
+# computes the same sketch: only the grouping of the binary32 partial sums moves
+@pytest.mark.parametrize("fmt,terms,store", [("bf16", 2, "f32"), ("e4m3", 3, "f32"), ("f64", 1, "f64")])
+def test_sketch_every_launch_shape_matches_oracle(L, fmt, terms, store):
+    m, n, s = 7003, 150, 600
+    P = make_problem(m, n, 1e3, seed=14, store=store)
+    At, b = dev(P.At), dev(P.b)
+    cs = fmt == "e4m3"
+    ref, e = osketch.sketch(P.At, P.b, s, 77, fmt=fmt, terms=terms, colscale=cs)
+    if fmt == "f64":
+        M = np.abs(np.column_stack([P.A(), P.b]))
+        Sa = np.abs(ophilox.gaussian_block(77, 0, 0, s, 0, m))
+        bound = (Sa @ M) / math.sqrt(s)
+        tol_max, tol_med = 4 * 2.0 ** -53 * math.sqrt(m), 4 * 2.0 ** -53 * math.sqrt(m)
+    else:
+        Mq, _ = osketch.scaled_operand(P.At, P.b, fmt, terms, cs)
+        Sq = np.abs(osketch.quantised_gaussian_block(77, 0, 0, s, 0, m, fmt))
+        bound = (Sq @ np.abs(Mq)) / math.sqrt(s) * np.ldexp(1.0, -e.astype(np.int64))[None, :]
+        tol_max, tol_med = 2e-3, 1e-6          # as in the single-shape sketch tests
+    outs = {}
+    k = 1
+    while L.sketch_plan_info(fmt, k) is not None:
+        Y = host(L.ls_sketch(At, b, s, seed=77, u_s=fmt, terms=terms, plan=k)).T
+        err = np.abs(Y - ref) / bound
+        sync_print(f"{fmt} x{terms} plan {k} {L.sketch_plan_info(fmt, k)}: max err/bound {err.max():.3e}")
+        assert err.max() < tol_max and np.median(err) < tol_med, k
+        outs[k] = Y
+        k += 1
+    Y0 = host(L.ls_sketch(At, b, s, seed=77, u_s=fmt, terms=terms)).T
+    assert any(np.array_equal(Y0, Y) for Y in outs.values())   # the table names one of them
+
+
 def test_sketch_e4m3_needs_column_scaling(L):
     # entries of A are ~ 1/sqrt(m) ~ 1e-2: without scaling most fall into
     # e4m3's subnormal range (2^-9 .. 2^-6) and lose their digits
@@ -530,4 +562,8 @@ def test_solve_rejects_bad_arguments(L):
     for terms, max_terms in ((2, 1), (1, 4)):                         # max_terms below terms or above 3
         with pytest.raises(L.LsError) as e:
             L.ls_solve(At, b, s=40, seed=1, terms=terms, max_terms=max_terms, pr=L.precs())
+        assert e.value.code == -1
+    for plan in (-1, 99):                                             # no such launch shape
+        with pytest.raises(L.LsError) as e:
+            L.ls_sketch(At, b, 40, seed=1, u_s="bf16", terms=1, plan=plan)
         assert e.value.code == -1
