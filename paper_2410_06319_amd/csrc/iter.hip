@@ -531,6 +531,8 @@ __global__ __launch_bounds__(kUtThreads) void k_lsqr_finish(const double* __rest
 // columns of the w-th quarter of [0, n), sixteen at a time (sixteen loads in
 // flight).  Row sums are added over the four waves in LDS at the end.
 constexpr int kResRows = 256;
+constexpr int kResWaves = 8;                  // column groups of a residual block
+constexpr int kResThreads = 64 * kResWaves;
 
 template <typename TA>
 __device__ __forceinline__ void load_rows4(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t i0, int64_t j,
@@ -624,15 +626,15 @@ __device__ __forceinline__ RAcc<DD> racc_multi_sum16(RAcc<DD> (&v)[16], int lane
 
 // r = b - A x in precision T (Algorithm 2 line 2).
 template <typename TA, typename T>
-__global__ __launch_bounds__(kThreads) void k_resid_u(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n,
-                                                      int vec_ok, const TA* __restrict__ b,
-                                                      const double* __restrict__ x, double* __restrict__ r) {
-  __shared__ T rs[4][kResRows];
+__global__ __launch_bounds__(kResThreads) void k_resid_u(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                                                         int vec_ok, const TA* __restrict__ b,
+                                                         const double* __restrict__ x, double* __restrict__ r) {
+  __shared__ T rs[kResWaves][kResRows];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t i0 = (int64_t)blockIdx.x * kResRows + 4 * lane;
   const bool vec = vec_ok && i0 + 4 <= m;
-  const int64_t jq = ls_cdiv(n, 4);
+  const int64_t jq = ls_cdiv(n, kResWaves);
   const int64_t j0 = wave * jq, j1 = (j0 + jq < n) ? j0 + jq : n;
   T acc[4] = {0, 0, 0, 0};
   for (int64_t jb = j0; jb < j1; jb += 16) {
@@ -651,10 +653,13 @@ __global__ __launch_bounds__(kThreads) void k_resid_u(const TA* __restrict__ A, 
 #pragma unroll
   for (int k = 0; k < 4; ++k) rs[wave][4 * lane + k] = acc[k];
   __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * kResRows + threadIdx.x;
-  if (i < m) {
-    const int t = threadIdx.x;
-    r[i] = (double)((T)b[i] - ((rs[0][t] + rs[1][t]) + (rs[2][t] + rs[3][t])));
+  const int t = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * kResRows + t;
+  if (t < kResRows && i < m) {
+    T q = rs[0][t];
+#pragma unroll
+    for (int w = 1; w < kResWaves; ++w) q += rs[w][t];
+    r[i] = (double)((T)b[i] - q);
   }
 }
 
@@ -662,19 +667,19 @@ __global__ __launch_bounds__(kThreads) void k_resid_u(const TA* __restrict__ A, 
 // per-block column partials (tpart[c G + block], hi and lo parts), binary64
 // or double-double; A and b are used exactly as stored.
 template <typename TA, bool DD>
-__global__ __launch_bounds__(kThreads) void k_lsir_resid(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n,
-                                                         int vec_ok, const TA* __restrict__ b,
-                                                         const double* __restrict__ r, const double* __restrict__ x,
-                                                         double* __restrict__ V, double* __restrict__ tpart_hi,
-                                                         double* __restrict__ tpart_lo, double* __restrict__ fpart) {
-  __shared__ double rsh[4][kResRows], rsl[4][kResRows];
-  __shared__ double dsh[4];
+__global__ __launch_bounds__(kResThreads) __attribute__((amdgpu_waves_per_eu(DD ? 2 : 4))) void k_lsir_resid(const TA* __restrict__ A, int64_t lda, int64_t m,
+                                                            int64_t n, int vec_ok, const TA* __restrict__ b,
+                                                            const double* __restrict__ r, const double* __restrict__ x,
+                                                            double* __restrict__ V, double* __restrict__ tpart_hi,
+                                                            double* __restrict__ tpart_lo, double* __restrict__ fpart) {
+  __shared__ double rsh[kResWaves][kResRows], rsl[kResWaves][kResRows];
+  __shared__ double dsh[kResWaves];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int G = gridDim.x;
   const int64_t i0 = (int64_t)blockIdx.x * kResRows + 4 * lane;
   const bool vec = vec_ok && i0 + 4 <= m;
-  const int64_t jq = ls_cdiv(n, 4);
+  const int64_t jq = ls_cdiv(n, kResWaves);
   const int64_t j0 = wave * jq, j1 = (j0 + jq < n) ? j0 + jq : n;
   double rv[4];
 #pragma unroll
@@ -713,12 +718,12 @@ __global__ __launch_bounds__(kThreads) void k_lsir_resid(const TA* __restrict__ 
   const int t = threadIdx.x;
   const int64_t i = (int64_t)blockIdx.x * kResRows + t;
   double fn = 0.0;
-  if (i < m) {
+  if (t < kResRows && i < m) {
     RAcc<DD> q;
     q.hi = rsh[0][t];
     q.lo = rsl[0][t];
 #pragma unroll
-    for (int w = 1; w < 4; ++w) {
+    for (int w = 1; w < kResWaves; ++w) {
       RAcc<DD> o;
       o.hi = rsh[w][t];
       o.lo = rsl[w][t];
@@ -736,7 +741,7 @@ __global__ __launch_bounds__(kThreads) void k_lsir_resid(const TA* __restrict__ 
     V[i] = f;
     fn = f * f;
   }
-  fn = block_sum256(fn, dsh);
+  fn = ls_block_sum<double, kResThreads>(fn, dsh);
   if (threadIdx.x == 0) fpart[blockIdx.x] = fn;
 }
 
@@ -1707,7 +1712,7 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
   const int ncb = (int)d.Gc;
 
   if (!r_given)
-    hipLaunchKernelGGL((k_resid_u<TA, TU>), dim3((unsigned)d.Gr), dim3(kThreads), 0, st, A, P->lda, m, n, vec_a, b, x,
+    hipLaunchKernelGGL((k_resid_u<TA, TU>), dim3((unsigned)d.Gr), dim3(kResThreads), 0, st, A, P->lda, m, n, vec_a, b, x,
                        r);
   ProgressSlot slot(st);
   Progress *prog = slot.host, *dprog = slot.dev;
@@ -1737,7 +1742,7 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
     }
     // lines 5-6: f, g, h in u_r
     const ProfEv ev = prof_events(kProfResidPass);
-    hipExtLaunchKernelGGL((k_lsir_resid<TA, DD>), dim3((unsigned)d.Gr), dim3(kThreads), 0, st, ev.a, ev.b, 0, A,
+    hipExtLaunchKernelGGL((k_lsir_resid<TA, DD>), dim3((unsigned)d.Gr), dim3(kResThreads), 0, st, ev.a, ev.b, 0, A,
                           P->lda, m, n, vec_a, b, r, x, w.V, w.rt_hi, w.rt_lo, w.w2part);
     // A and b once, r read, f written, x read, g written
     prof_commit(kProfResidPass, (double)m * n * sizeof(TA) + (double)m * sizeof(TA) + 16.0 * m + 16.0 * n);
