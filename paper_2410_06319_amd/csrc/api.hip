@@ -419,6 +419,8 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
   Timer tm;
   ls_sketch_opts_t so_t = *so;   // the parts of the current sketch
   std::vector<double> fro(2 * (size_t)n);
+  std::vector<char> rb((size_t)(reinterpret_cast<char*>(inv.fro) - reinterpret_cast<char*>(inv.flag)) +
+                       16 * (size_t)n);
   double ms_sk = 0.0, ms_qr = 0.0;
   for (;;) {
     tm.mark(0, st);
@@ -432,11 +434,14 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
     LS_TRY(trinv_run(Raug, n + 1, n, inv.W, n, inv.W32, inv.flag, st, inv.fro));
     hipLaunchKernelGGL(k_trmv_f64, dim3((unsigned)ls_cdiv(n, 32)), dim3(kUtThreads), 0, st, inv.W, n,
                        Raug + n * (n + 1), x);
-    int flag = 0;
-    LS_HIP_TRY(hipMemcpyAsync(&flag, inv.flag, sizeof(int), hipMemcpyDeviceToHost, st));
-    LS_HIP_TRY(hipMemcpyAsync(fro.data(), inv.fro, 16 * (size_t)n, hipMemcpyDeviceToHost, st));
+    // the flag and the norms in one copy (they are adjacent in the workspace)
+    const size_t fro_off = (size_t)(reinterpret_cast<char*>(inv.fro) - reinterpret_cast<char*>(inv.flag));
+    LS_HIP_TRY(hipMemcpyAsync(rb.data(), inv.flag, rb.size(), hipMemcpyDeviceToHost, st));
     tm.mark(2, st);
     LS_HIP_TRY(hipStreamSynchronize(st));
+    int flag = 0;
+    std::memcpy(&flag, rb.data(), sizeof(int));
+    std::memcpy(fro.data(), rb.data() + fro_off, 16 * (size_t)n);
     if (flag) {
       S->status = LS_E_SINGULAR;
       return LS_E_SINGULAR;

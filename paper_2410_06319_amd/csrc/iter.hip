@@ -1669,6 +1669,8 @@ LsirWs lsir_carve(char* ws, const ls_problem_t* P, const LsirDims& d, size_t tb_
   const int kmax = d.kmax;
   w.ldv = m + n;
   w.st = reinterpret_cast<FgState*>(take(sizeof(FgState)));
+  // right after the state: the host reads both back with one copy per step
+  w.upart = reinterpret_cast<double*>(take(8 * 2 * (size_t)(d.Gd + d.Gn)));
   w.V = reinterpret_cast<double*>(take(8 * (size_t)w.ldv * (kmax + 1)));
   w.H = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1) * kmax));
   w.cs = reinterpret_cast<double*>(take(8 * (size_t)kmax));
@@ -1684,7 +1686,6 @@ LsirWs lsir_carve(char* ws, const ls_problem_t* P, const LsirDims& d, size_t tb_
   w.rt_lo = reinterpret_cast<double*>(take(8 * (size_t)d.Gr * n));
   w.gvec = reinterpret_cast<double*>(take(8 * (size_t)n));
   w.dz = reinterpret_cast<double*>(take(8 * (size_t)n));
-  w.upart = reinterpret_cast<double*>(take(8 * 2 * (size_t)(d.Gd + d.Gn)));
   w.bytes = off;
   return w;
 }
@@ -1734,6 +1735,8 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
   int total_fg = 0, its = 0, status = LS_NOT_CONVERGED;
   double dx_rel = 0.0, dr_rel = 0.0;
   std::vector<double> up(2 * (size_t)(d.Gd + d.Gn));
+  std::vector<char> rb((size_t)(reinterpret_cast<char*>(w.upart) - reinterpret_cast<char*>(w.st)) +
+                       8 * 2 * (size_t)(d.Gd + d.Gn));
   for (its = 1; its <= io->lsir_maxit; ++its) {
     if (io->inner_adapt && its > 1) {
       const double rho = std::max(dx_rel, dr_rel);
@@ -1792,10 +1795,14 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
     hipLaunchKernelGGL(k_fg_update<TU>, dim3((unsigned)d.Gd), dim3(kThreads), 0, st, F, m, n, d.kmax, r, w.dz, w.upart);
     hipLaunchKernelGGL(k_fg_dx<TU>, dim3((unsigned)d.Gn), dim3(kUtThreads), 0, st, W, n, w.dz, x,
                        w.upart + 2 * (size_t)d.Gd);
-    LS_HIP_TRY(hipMemcpyAsync(&S, w.st, sizeof(FgState), hipMemcpyDeviceToHost, st));
-    LS_HIP_TRY(hipMemcpyAsync(up.data(), w.upart, 8 * 2 * (size_t)(d.Gd + d.Gn), hipMemcpyDeviceToHost, st));
+    // the state and the norm partials in one copy (each copy to pageable
+    // memory costs a round trip of the host)
+    const size_t up_off = (size_t)(reinterpret_cast<char*>(w.upart) - reinterpret_cast<char*>(w.st));
+    LS_HIP_TRY(hipMemcpyAsync(rb.data(), w.st, rb.size(), hipMemcpyDeviceToHost, st));
     LS_HIP_TRY(hipStreamSynchronize(st));
     LS_HIP_TRY(hipGetLastError());
+    std::memcpy(&S, rb.data(), sizeof(FgState));
+    std::memcpy(up.data(), rb.data() + up_off, 8 * 2 * (size_t)(d.Gd + d.Gn));
     if (S.breakdown == 2) return LS_E_NONFINITE;
     // passes and sweeps of columns 0 .. k-1; later ones were queued past convergence
     prof_keep(kProfFgPass, pmark, S.k);

@@ -525,6 +525,27 @@ def test_profile_files_one_record_per_launch_before_convergence(L):
         assert ms[k] > 0
 
 
+# degenerate shapes: one column, s = n + 1 (no embedding margin), m = n + 1,
+# very few columns with a long ragged m; the oracle converges on each
+@pytest.mark.parametrize("m,n,s,kappa", [(200, 1, 4, 1.0), (2000, 20, 21, 10.0), (41, 40, 41, 10.0),
+                                         (5000, 3, 12, 1e3)])
+def test_solve_degenerate_shapes(L, m, n, s, kappa):
+    P = make_problem(m, n, kappa, seed=77, store="f32")
+    xr, rr, _ = refsolve.ref_solve(P.At, P.b)
+    pr = L.precs(u_s="bf16", u_qr="f32", u="f32", u_r="f64")
+    x, r, rc, st = L.ls_solve(dev(P.At), dev(P.b), s=s, seed=5, terms=2, pr=pr, lsir_tol=6e-6)
+    ex, er = refsolve.forward_errors(host(x), host(r), xr, rr)
+    sync_print(f"m={m} n={n} s={s}: lsqr {st['lsqr_its']} lsir {st['lsir_its']} fgmres {st['fgmres_its_total']} "
+               f"x {ex:.2e} r {er:.2e}")
+    assert rc == 0 and ex <= 6e-6 and er <= 6e-6
+    P64 = make_problem(m, n, kappa, seed=77, store="f64")
+    xr, rr, _ = refsolve.ref_solve(P64.At, P64.b)
+    pr = L.precs(u_s="f64", u_qr="f64", u="f64", u_r="f64x2")
+    x, r, rc, st = L.ls_solve(dev(P64.At), dev(P64.b), s=s, seed=5, pr=pr, lsir_tol=1e-15)
+    ex, er = refsolve.forward_errors(host(x), host(r), xr, rr)
+    assert rc == 0 and ex <= 1e-13 and er <= 1e-13
+
+
 def test_solve_batched_equals_single_solves(L):
     # uneven problems (sizes, conditioning, seeds) over several workers: each
     # result is bitwise the single-problem one and reaches the target
