@@ -18,6 +18,7 @@
 // to back and the host reads a convergence flag every few iterations.
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -1400,10 +1401,15 @@ void progress_set(int32_t* f, int32_t v) { __atomic_store_n(f, v, __ATOMIC_RELEA
 // the target was reached, -1 when the stream went idle with neither (the slot
 // is not being updated).
 int progress_wait(int32_t* val, int32_t* done, int target, hipStream_t st) {
+  // The stream is queried only after 2 ms without progress (an iteration
+  // takes tens of microseconds): a query can place a marker in the stream,
+  // which the device then processes between two kernels.
+  const auto t0 = std::chrono::steady_clock::now();
   for (unsigned spin = 0;; ++spin) {
     if (__atomic_load_n(done, __ATOMIC_ACQUIRE)) return 1;
     if (__atomic_load_n(val, __ATOMIC_ACQUIRE) >= target) return 0;
-    if ((spin & 255u) == 255u && hipStreamQuery(st) == hipSuccess) {
+    if ((spin & 255u) == 255u && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2) &&
+        hipStreamQuery(st) == hipSuccess) {
       if (__atomic_load_n(done, __ATOMIC_ACQUIRE)) return 1;
       return (__atomic_load_n(val, __ATOMIC_ACQUIRE) >= target) ? 0 : -1;
     }
