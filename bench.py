@@ -91,8 +91,8 @@ def cpu_baseline(wl, P, seed, terms):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 (multi-GPU sharding is "
-                                   "described in DESIGN.md, not implemented)"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 (sharding the problem "
+                                   "over several GPUs is not implemented)"}))
         sys.exit(2)
     import numpy as np
     import torch
@@ -102,7 +102,7 @@ def main():
 
     wl = dict(WORKLOADS[args.workload])
     if "m" not in wl:
-        raise SystemExit("batched workload is not a bench line in this build")
+        raise SystemExit("the batched workload has no bench line (tests/test_gpu_full_size.py covers it)")
     seed = data_seed(wl["index"])
     m, n, s, kappa = wl["m"], wl["n"], wl["s"], wl["kappa"]
     terms = args.terms if wl["u_s"] == "bf16" else 1

@@ -54,7 +54,7 @@ enum {
   LS_E_HIP = -3,          /* a HIP runtime call failed */
   LS_E_SINGULAR = -4,     /* zero or non-finite diagonal in R: A is rank deficient in u_s */
   LS_E_NONFINITE = -5,    /* NaN or Inf met in an iterate */
-  LS_E_UNSUPPORTED = -6   /* combination not implemented in this build */
+  LS_E_UNSUPPORTED = -6   /* combination the library does not implement */
 };
 
 /* One least-squares problem (Section 1).  A: device, m x n column major,
@@ -69,10 +69,10 @@ typedef struct {
 } ls_problem_t;
 
 /* Precisions of Algorithms 1 and 2 (Sections 3 and 4):
- *  u_s  sketch (Algorithm 1 step 1): LS_FP64 or LS_BF16
- *  u_qr QR of the sketch (Algorithm 1 step 2): LS_FP32 or LS_FP64
+ *  u_s  sketch (Algorithm 1): LS_FP64, LS_BF16, LS_FP16 or LS_FP8E4M3
+ *  u_qr QR of the sketch (Algorithm 1): LS_FP32 or LS_FP64
  *  u    working precision of LSQR, FGMRES and the stored x, r: LS_FP32 or LS_FP64
- *  u_r  refinement residual and R^-T g (Algorithm 2 lines 5-6): LS_FP64 or LS_FP64X2
+ *  u_r  refinement residuals and R^-T g (Algorithm 2): LS_FP64 or LS_FP64X2
  *  u_A, u_L, u_R  products with Atilde, M_L^-1, M_R^-1 inside FGMRES: LS_FP32 or LS_FP64,
  *       not coarser than u.  The Arnoldi process itself runs in binary64. */
 typedef struct {
@@ -185,7 +185,7 @@ void ls_default_iter_opts(int64_t n, ls_prec_t u, ls_iter_opts_t *opts);
 int ls_workspace_size(const ls_problem_t *P, const ls_sketch_opts_t *so,
                       const ls_precs_t *pr, const ls_iter_opts_t *io, size_t *bytes);
 
-/* Algorithm 1 step 1 on [A b]: Y = Omega [A b], s x (n+1), binary64,
+/* Algorithm 1's sketch, of [A b]: Y = Omega [A b], s x (n+1), binary64,
  * column major with leading dimension ldy >= s (device).  Column n is
  * Omega b, which Algorithm 2's sketch-and-solve start needs.  With u_s =
  * LS_BF16, LS_FP16 or LS_FP8E4M3 (OCP e4m3, largest value 448, saturating)
@@ -200,7 +200,7 @@ int ls_workspace_size(const ls_problem_t *P, const ls_sketch_opts_t *so,
 int ls_sketch(const ls_problem_t *P, const ls_sketch_opts_t *so, ls_prec_t u_s,
               double *Y, int64_t ldy, void *ws, size_t ws_bytes, void *stream);
 
-/* Algorithm 1 step 2: economic Householder QR of Y (s x ncols, binary64,
+/* Algorithm 1's QR: economic Householder QR of Y (s x ncols, binary64,
  * device, left unchanged: the factorisation runs on a copy in the workspace)
  * in precision u_qr, returning only R: ncols x ncols
  * upper triangular with positive diagonal, binary64, leading dimension
@@ -210,7 +210,7 @@ int ls_sketch(const ls_problem_t *P, const ls_sketch_opts_t *so, ls_prec_t u_s,
 int ls_qr_r(int64_t s, int64_t ncols, ls_prec_t u_qr, double *Y, int64_t ldy,
             double *R, int64_t ldr, void *ws, size_t ws_bytes, void *stream);
 
-/* Algorithm 2 line 1: LSQR on A R^-1 (right preconditioning, Paige and
+/* Algorithm 2's LSQR solve: LSQR on A R^-1 (right preconditioning, Paige and
  * Saunders' recurrences) in precision u, started from x (device, length n,
  * binary64 in and out; typically x^s = R^-1 Q^T Omega b).  R: device, n x n
  * upper triangular, binary64, leading dimension ldr.  Stops when
@@ -220,11 +220,11 @@ int ls_lsqr_precond(const ls_problem_t *P, const double *R, int64_t ldr, ls_prec
                     double *x, const ls_iter_opts_t *io, ls_stats_t *stats,
                     void *ws, size_t ws_bytes, void *stream);
 
-/* Algorithm 2 lines 2-10: refinement on the augmented system with
+/* Algorithm 2's refinement loop on the augmented system with
  * split-preconditioned FGMRES (M_L^-1 = diag(I, R^-T), M_R^-1 = diag(I, R^-1)).
  * x: device, length n, binary64, in and out.  r: device, length m, binary64,
  * out (and in when r_given != 0; otherwise r = b - A x is formed first,
- * Algorithm 2 line 2).  stats may be NULL. */
+ * as Algorithm 2 starts the refinement).  stats may be NULL. */
 int ls_lsir_gmres(const ls_problem_t *P, const double *R, int64_t ldr, const ls_precs_t *pr,
                   double *x, double *r, int r_given, const ls_iter_opts_t *io,
                   ls_stats_t *stats, void *ws, size_t ws_bytes, void *stream);

@@ -14,12 +14,12 @@ What is here (plain numpy, float64 unless a step says otherwise):
 * ``formats`` -- round-to-nearest-even into bf16 / fp16 / OCP e4m3, the
   power-of-two column scaling of Section 3.2, and the split of A into a sum
   of narrow-format terms.
-* ``sketch``  -- Algorithm 1 step 1: Y = Omega [A b].
-* ``qr``      -- Algorithm 1 step 2: economic Householder QR, R factor only;
+* ``sketch``  -- Algorithm 1, the sketch: Y = Omega [A b].
+* ``qr``      -- Algorithm 1, the QR: economic Householder QR, R factor only;
   back substitution with R and R^T.
-* ``lsqr``    -- Algorithm 2 line 1: LSQR right-preconditioned with R,
+* ``lsqr``    -- Algorithm 2, the LSQR solve: right-preconditioned with R,
   started at the sketch-and-solve solution (Paige and Saunders, 1982).
-* ``lsir``    -- Algorithm 2 lines 2-10: augmented-system refinement with
+* ``lsir``    -- Algorithm 2, the refinement loop: augmented-system refinement with
   split-preconditioned flexible GMRES.
 * ``refsolve`` -- the exact solution of the stored data (extended-precision
   residual refinement on the augmented system), the target of every

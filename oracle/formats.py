@@ -4,7 +4,7 @@ Section 3 lets the sketch run in a precision u_s and says that A is "stored
 in precision u_s" (Algorithm 1, input).  Section 3.2 describes a one-sided
 column scaling for narrow-range formats: divide every column by its largest
 magnitude and multiply by a positive constant, then use R S^-1 as the
-preconditioner.  This build takes the constant as a power of two, so that the
+preconditioner.  The constant is taken as a power of two, so that the
 scaling is exact.
 
 Rounding is round-to-nearest, ties to even, computed on the exact binary64

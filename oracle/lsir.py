@@ -1,15 +1,15 @@
-"""Algorithm 2, lines 2-10: augmented-system refinement with split-preconditioned
+"""Algorithm 2, the refinement loop: augmented-system refinement with split-preconditioned
 flexible GMRES (oracle, test use only).
 
 Augmented system (Section 1):  [I A; A^T 0] [r; x] = [b; 0].
 Split preconditioner (Section 1):  M_L^-1 = diag(I, R^-T),  M_R^-1 = diag(I, R^-1).
 
 One refinement step i (Algorithm 2):
-    line 5:  f = b - r - A x,   g = -A^T r                      (precision u_r)
-    line 6:  h = R^-T g                                         (u_r)
-    line 7:  FGMRES on M_L^-1 Atilde M_R^-1 y = [f; h]; the correction is
+    residuals:        f = b - r - A x,   g = -A^T r             (precision u_r)
+    preconditioned:   h = R^-T g                                (u_r)
+    correction:       FGMRES on M_L^-1 Atilde M_R^-1 y = [f; h]; the correction is
              [dr; dx] = Z_k y_k with Z_k = M_R^-1 V_k, so dx = R^-1 dz
-    line 8:  [r; x] += [dr; dx]                                  (u)
+    update:           [r; x] += [dr; dx]                        (u)
 
 FGMRES: one cycle, zero initial guess, modified Gram-Schmidt Arnoldi, Givens
 rotations; it stops when the preconditioned relative residual estimate
@@ -100,7 +100,7 @@ def lsir(At: np.ndarray, b: np.ndarray, R: np.ndarray, x0: np.ndarray, r0=None,
     Rw = np.asarray(R, dtype=wide)
     b = np.asarray(b, dtype=np.float64)
     x = np.array(x0, dtype=np.float64, copy=True)
-    r = b - A @ x if r0 is None else np.array(r0, dtype=np.float64, copy=True)   # line 2
+    r = b - A @ x if r0 is None else np.array(r0, dtype=np.float64, copy=True)   # the starting residual
     info = dict(its=0, fgmres_its=[], converged=False, relres=[])
 
     def errs():
@@ -113,14 +113,14 @@ def lsir(At: np.ndarray, b: np.ndarray, R: np.ndarray, x0: np.ndarray, r0=None,
         return x, r, info
     for i in range(maxit):
         xw, rw = x.astype(wide), r.astype(wide)
-        f = (bw - rw - Aw @ xw)                             # line 5
+        f = (bw - rw - Aw @ xw)                             # residuals in u_r
         g = -(Aw.T @ rw)
-        h = solve_upper_t(Rw, g).astype(np.float64)         # line 6
+        h = solve_upper_t(Rw, g).astype(np.float64)         # h = R^-T g in u_r
         f = f.astype(np.float64)
-        dr, dx, k, rr = fgmres_split(A, R, f, h, fgmres_tol, fgmres_maxit)   # line 7
+        dr, dx, k, rr = fgmres_split(A, R, f, h, fgmres_tol, fgmres_maxit)   # the FGMRES correction
         info["fgmres_its"].append(k)
         info["relres"].append(rr)
-        r = r + dr                                          # line 8
+        r = r + dr                                          # the update
         x = x + dx
         info["its"] = i + 1
         if x_ref is not None:

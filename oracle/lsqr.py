@@ -1,4 +1,4 @@
-"""Algorithm 2, line 1: LSQR right-preconditioned with R (oracle, test use only).
+"""Algorithm 2, the LSQR solve: LSQR right-preconditioned with R (oracle, test use only).
 
 LSQR is Paige and Saunders' Golub-Kahan bidiagonalisation method (ACM TOMS
 8(1), 1982).  It is applied to B = A R^-1 (right preconditioning) in
@@ -7,7 +7,7 @@ residual form: starting from the sketch-and-solve point x^s,
     min_y || r_s - B y ||,   r_s = b - A x^s,   x = x^s + R^-1 y.
 
 Stopping (Section 5: "at most 2n iterations or until the tolerance reaches
-1e-6 / 1e-12"; this build reads the tolerance as the two Paige-Saunders
+1e-6 / 1e-12"; the tolerance is read as the two Paige-Saunders
 tests with atol = btol = tol):
 
     ||r_k|| <= tol ||b||        or        ||B^T r_k|| / (||B||_F,est ||r_k||) <= tol

@@ -9,7 +9,7 @@ permutes; the key is advanced by the two Weyl constants between rounds.
 
 Gaussian entries of Omega (Section 2: entries N(0, 1/s); Section 5:
 Omega = (4n)^(-1/2) G with G standard normal).  The paper leaves the random
-number generator open; this build fixes it as follows.
+number generator open; it is fixed here as follows.
 
 * Entry S[k, i] (row k < s of the sketch, column i < m, i.e. row i of A) of
   problem ``prob`` comes from the Philox block with counter

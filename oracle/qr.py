@@ -1,4 +1,4 @@
-"""Algorithm 1, step 2: economic Householder QR, R factor only (oracle, test use only).
+"""Algorithm 1, the QR of the sketch: economic Householder QR, R factor only (oracle, test use only).
 
 Householder QR as in Golub and Van Loan (the analysis of Section 3.1 uses
 its standard backward error result): for column j the reflector

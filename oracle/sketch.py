@@ -1,7 +1,7 @@
-"""Algorithm 1, step 1: the sketch Y = Omega [A b] (oracle, test use only).
+"""Algorithm 1, the sketch: Y = Omega [A b] (oracle, test use only).
 
 Definition (Section 2 and Algorithm 1; the sketch of [A b] rather than of A
-alone is this build's reading of how Q^T Omega b in Algorithm 2's
+alone is the reading taken here of how Q^T Omega b in Algorithm 2's
 sketch-and-solve start is obtained without forming Q):
 
     M   = [A b] * diag(2^e)                 (Section 3.2 column scaling; e = 0 for
@@ -88,7 +88,7 @@ def sparse_sign_pattern(seed: int, prob: int, m: int, s: int, zeta: int):
 
     Column i of Omega (the column that multiplies row i of [A b]) has zeta
     nonzeros at distinct rows chosen uniformly at random, each +1 or -1 with
-    probability 1/2, scaled by 1/sqrt(zeta) (this build's reading of the
+    probability 1/2, scaled by 1/sqrt(zeta) (the reading taken here of the
     printed scale; it makes E[Omega^T Omega] = I as the embedding definition of
     Section 2 requires).  The random choices are read from the words of the
     Philox4x32-10 blocks with counter (i, t, prob, 1), t = 0, 1, ..., key

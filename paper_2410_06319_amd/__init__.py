@@ -1,10 +1,10 @@
 """Sketch-preconditioned mixed-precision least squares on one MI355X (gfx950).
 
 The method (Carson and Dauzickaite): sketch [A b] with a Gaussian embedding
-(Algorithm 1 step 1), take the R factor of a Householder QR of the sketch
-(step 2), run LSQR right-preconditioned with R from the sketch-and-solve
-point (Algorithm 2 line 1) and refine x and r on the augmented system with
-split-preconditioned FGMRES (lines 2-10).  All of it runs in libls.so
+(Algorithm 1), take the R factor of a Householder QR of the sketch, run
+LSQR right-preconditioned with R from the sketch-and-solve point
+(Algorithm 2) and refine x and r on the augmented system with
+split-preconditioned FGMRES (Algorithm 2's refinement loop).  All of it runs in libls.so
 (hand-written HIP); this package is its Python binding.
 """
 

@@ -128,7 +128,7 @@ def ls_lsqr_precond(At, b, Rt, x, u="f32", ws=None, **opts):
 
 
 def ls_lsir_gmres(At, b, Rt, x, r, pr=None, r_given=False, ws=None, **opts):
-    """Refinement (Algorithm 2 lines 2-10); x (n,) and r (m,) float64, updated in place."""
+    """Refinement (Algorithm 2's refinement loop); x (n,) and r (m,) float64, updated in place."""
     P = problem(At, b)
     pr = pr or precs()
     io = iter_opts(P.n, "f64" if pr.u == B.FP64 else "f32", **opts)

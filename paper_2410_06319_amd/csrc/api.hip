@@ -236,7 +236,7 @@ const char* ls_strerror(int s) {
     case LS_E_HIP: return "HIP runtime error";
     case LS_E_SINGULAR: return "R has a zero or non-finite diagonal entry (rank-deficient sketch)";
     case LS_E_NONFINITE: return "non-finite value in an iterate";
-    case LS_E_UNSUPPORTED: return "combination not supported by this build";
+    case LS_E_UNSUPPORTED: return "combination not supported by the library";
     default: return "unknown status";
   }
 }
@@ -424,11 +424,11 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
   double ms_sk = 0.0, ms_qr = 0.0;
   for (;;) {
     tm.mark(0, st);
-    // Algorithm 1 step 1
+    // Algorithm 1: the sketch
     const SketchPlan sp = sketch_plan(P, &so_t, s, pr->u_s);
     LS_TRY(sketch_run(P, &so_t, pr->u_s, sp, s, Y, s, scratch, st));
     tm.mark(1, st);
-    // Algorithm 1 step 2, then x^s = R^-1 (Q^T Omega b)
+    // Algorithm 1: the QR, then x^s = R^-1 (Q^T Omega b)
     LS_HIP_TRY(hipMemsetAsync(inv.flag, 0, sizeof(int), st));
     LS_TRY(qr_run(s, n + 1, pr->u_qr, Y, s, Raug, n + 1, scratch, scratch_bytes, inv.flag, n, st));
     LS_TRY(trinv_run(Raug, n + 1, n, inv.W, n, inv.W32, inv.flag, st, inv.fro));
@@ -460,7 +460,7 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
     if (next == so_t.terms) break;
     so_t.terms = next;   // Section 4: kappa(A) u_s < 1 not met with this many parts
   }
-  // the preconditioned operator B = A R^-1, then Algorithm 2 line 1
+  // the preconditioned operator B = A R^-1, then Algorithm 2's LSQR solve
   LS_TRY(form_b(P, inv.W, inv.W32, pr->u, B1, st));
   int rc = lsqr_device(P, Raug, n + 1, inv.W, B1, pr->u, x, &io, S, scratch, scratch_bytes, st);
   tm.mark(3, st);
@@ -468,7 +468,7 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
     S->status = rc;
     return rc;
   }
-  // Algorithm 2 lines 2-10
+  // Algorithm 2's refinement loop
   if (io.fallback) {
     LS_HIP_TRY(hipMemcpyAsync(saved, x, 8 * (size_t)n, hipMemcpyDeviceToDevice, st));
   }

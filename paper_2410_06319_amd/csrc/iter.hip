@@ -1,11 +1,11 @@
-// Algorithm 2 on gfx950: LSQR right-preconditioned with R (line 1) and
-// augmented-system refinement with split-preconditioned FGMRES (lines 2-10).
+// Algorithm 2 on gfx950: LSQR right-preconditioned with R and the
+// augmented-system refinement loop with split-preconditioned FGMRES.
 //
 // The preconditioned operator B = A R^-1 is formed once per call (an MFMA
 // GEMM with the explicit upper-triangular W = R^-1).  LSQR then works on
 // min ||b - B z|| with x = W z, and FGMRES on the split-preconditioned
 // augmented matrix, which is exactly [I B; B^T 0]; R^-1 is applied only to
-// the final corrections.  The refinement residuals (lines 5-6) use A itself.
+// the final corrections.  The refinement residuals use A itself.
 //
 // Every iteration reads B once: a block of RB rows (all n columns) is
 // prefetched into registers while the previous block, staged in LDS, is used
@@ -625,7 +625,7 @@ __device__ __forceinline__ RAcc<DD> racc_multi_sum16(RAcc<DD> (&v)[16], int lane
   return s;
 }
 
-// r = b - A x in precision T (Algorithm 2 line 2).
+// r = b - A x in precision T (the refinement's starting residual).
 template <typename TA, typename T>
 __global__ __launch_bounds__(kResThreads) void k_resid_u(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n,
                                                          int vec_ok, const TA* __restrict__ b,
@@ -664,7 +664,7 @@ __global__ __launch_bounds__(kResThreads) void k_resid_u(const TA* __restrict__ 
   }
 }
 
-// Line 5 in u_r: f = b - r - A x (rows, written to V[:, 0]) and g = A^T r as
+// Refinement residuals in u_r: f = b - r - A x (rows, written to V[:, 0]) and g = A^T r as
 // per-block column partials (tpart[c G + block], hi and lo parts), binary64
 // or double-double; A and b are used exactly as stored.
 template <typename TA, bool DD>
@@ -767,7 +767,7 @@ __global__ __launch_bounds__(kThreads) void k_lsir_g(const double* __restrict__ 
   if (lane == 0) g[col] = -(acc.hi + acc.lo);
 }
 
-// h = W^T g (line 6) into V[m:, 0]; partial ||h||^2.  One wave per column.
+// h = W^T g (the preconditioned residual) into V[m:, 0]; partial ||h||^2.  One wave per column.
 template <bool DD>
 __global__ __launch_bounds__(kThreads) void k_lsir_h(const double* __restrict__ W, int64_t n, int64_t m,
                                                      const double* __restrict__ g, double* __restrict__ V,
@@ -1749,7 +1749,7 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
       tol = (rho > 0.0) ? 0.1 * lsir_tol / rho : 1e-2;
       tol = std::min(1e-2, std::max(io->fgmres_tol, tol));
     }
-    // lines 5-6: f, g, h in u_r
+    // residuals f, g and h = R^-T g in u_r
     const ProfEv ev = prof_events(kProfResidPass);
     hipExtLaunchKernelGGL((k_lsir_resid<TA, DD>), dim3((unsigned)d.Gr), dim3(kResThreads), 0, st, ev.a, ev.b, 0, A,
                           P->lda, m, n, vec_a, b, r, x, w.V, w.rt_hi, w.rt_lo, w.w2part);
@@ -1760,7 +1760,7 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
     hipLaunchKernelGGL(k_lsir_h<DD>, dim3((unsigned)d.Gh), dim3(kThreads), 0, st, W, n, m, w.gvec, w.V,
                        w.w2part + d.Gr);
     hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(kThreads), 0, st, reinterpret_cast<char*>(w.st), sizeof(FgState));
-    // line 7: FGMRES on [I B; B^T 0]
+    // the correction: FGMRES on [I B; B^T 0]
     const size_t pmark = prof_mark();
     int j = 0;
     FgState S{};

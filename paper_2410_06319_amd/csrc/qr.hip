@@ -1,4 +1,4 @@
-// Algorithm 1 step 2: economic Householder QR of the sketch, R factor only,
+// Algorithm 1, the QR: economic Householder QR of the sketch, R factor only,
 // plus the explicit inverse R^-1 used to apply the preconditioner.
 //
 // Blocked right-looking Householder QR (compact WY, LAPACK's forward

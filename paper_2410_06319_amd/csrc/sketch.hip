@@ -1,4 +1,4 @@
-// Algorithm 1 step 1: the Gaussian sketch Y = Omega [A b] on gfx950.
+// Algorithm 1, the sketch: the Gaussian sketch Y = Omega [A b] on gfx950.
 //
 // Omega = S / sqrt(s) is never stored: S entries are regenerated from
 // Philox4x32-10 (counter (i/4, k, prob, 0), key = seed) where they are
