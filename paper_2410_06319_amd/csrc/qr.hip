@@ -165,6 +165,17 @@ struct QrVec<double> {
   static constexpr int W = 2;
 };
 
+// Value of lane `src` (a constant after unrolling) on every lane of the wave.
+__device__ __forceinline__ float qr_bcast(float v, int src) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
+}
+__device__ __forceinline__ double qr_bcast(double v, int src) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), src);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ float qr_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double qr_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float qr_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -228,18 +239,23 @@ __device__ __forceinline__ void qr_panel_body(T* __restrict__ Y, int64_t ldy, in
       }
       __syncthreads();
       if (act) {
-        // every thread adds the wave partials itself (same order everywhere)
-        T dots[NB];
+        // lane q (mod NB) of each wave adds the wave partials of index q, in
+        // wave order, and reads entry q of row c; the values then reach every
+        // lane by cross-lane reads (one LDS read per lane instead of all of
+        // the partials on every thread)
+        const int lq = lane % NB;
+        T mine = red[par][0][lq];
 #pragma unroll
-        for (int q = 0; q < NB; q += VW) {
-          vec_t acc = *reinterpret_cast<const vec_t*>(&red[par][0][q]);
+        for (int w = 1; w < PW; ++w) mine += red[par][w][lq];
+        const T rmine = rowc[par][lq];
+        T dots[NB], rc[NB];
 #pragma unroll
-          for (int w = 1; w < PW; ++w) acc += *reinterpret_cast<const vec_t*>(&red[par][w][q]);
-#pragma unroll
-          for (int e = 0; e < VW; ++e) dots[q + e] = acc[e];
+        for (int q = 0; q < NB; ++q) {
+          dots[q] = qr_bcast(mine, q);
+          rc[q] = qr_bcast(rmine, q);
         }
         const T ss = dots[c];
-        const T x0 = rowc[par][c];
+        const T x0 = rc[c];
         T beta, tauc, scal;
         if (ss == T(0)) {
           tauc = 0;
@@ -252,12 +268,7 @@ __device__ __forceinline__ void qr_panel_body(T* __restrict__ Y, int64_t ldy, in
           scal = qr_rcp(x0 - beta);
         }
         // inner products with the earlier reflectors, for T after the loop
-        if (tid < c) {
-          T dt = red[par][0][tid];
-#pragma unroll
-          for (int w = 1; w < PW; ++w) dt += red[par][w][tid];
-          Gs[c][tid] = rowc[par][tid] + scal * dt;
-        }
+        if (tid < c) Gs[c][tid] = rmine + scal * mine;
         if (tid == 0) {
           tau[j0 + c] = tauc;
           taus[c] = tauc;
@@ -265,7 +276,7 @@ __device__ __forceinline__ void qr_panel_body(T* __restrict__ Y, int64_t ldy, in
         // v_c in place of x, then H_c applied to the later panel columns
         T coef[NB];
 #pragma unroll
-        for (int bq = c + 1; bq < NB; ++bq) coef[bq] = tauc * (rowc[par][bq] + scal * dots[bq]);
+        for (int bq = c + 1; bq < NB; ++bq) coef[bq] = tauc * (rc[bq] + scal * dots[bq]);
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
           const int li = RPT * tid + r;
@@ -524,7 +535,9 @@ __device__ __forceinline__ void qr_update16(T* __restrict__ Y, int64_t ldy, int6
 template <typename T, int RPT>
 constexpr int kQrChunks = RPT * kPanelThreads / kUpdRows;
 template <typename T, int RPT>
-constexpr int kQrHeld = (kQrChunks<T, RPT> * (32 * kUpdRows / kQrThreads) * 4 <= 128) ? kQrChunks<T, RPT> : 0;
+constexpr int kQrHeld =
+    (kQrChunks<T, RPT> * (32 * kUpdRows / kQrThreads) * (int)sizeof(T) / 4 <= 128) ? kQrChunks<T, RPT> : 0;
+static_assert(kQrHeld<float, 4> == 8, "binary32 with s <= 2048 holds its update chunks");
 
 template <typename T, int RPT, int NB>
 __global__ __launch_bounds__(kQrThreads) void k_qr_step(T* __restrict__ Y, int64_t ldy, int64_t s, int64_t ncols,

@@ -219,7 +219,10 @@ def test_sketch_e4m3_needs_column_scaling(L):
 
 # ------------------------------------------------------------------ QR
 @pytest.mark.parametrize("u_qr", ["f64", "f32"])
-@pytest.mark.parametrize("s,ncols,kappa", [(200, 51, 1e2), (2000, 501, 1e2), (1111, 97, 1e4)])
+# s = 2048 is the largest binary32 sketch whose update chunks stay in
+# registers (8 chunks of 256 rows), s = 2049 the smallest that streams them
+@pytest.mark.parametrize("s,ncols,kappa", [(200, 51, 1e2), (2000, 501, 1e2), (1111, 97, 1e4), (2048, 130, 1e3),
+                                          (2049, 33, 1e3)])
 def test_qr_r_matches_oracle(L, u_qr, s, ncols, kappa):
     P = make_problem(s, ncols, kappa, seed=14, store="f64")
     Y = P.A()                                       # s x ncols with known conditioning
