@@ -357,101 +357,64 @@ __device__ __forceinline__ int qr_drow(int lane, int r) {
 // Apply the nb0 reflectors of the panel starting at j0 (V unit lower
 // trapezoidal below row j0, T upper triangular, Tm[a + c NB] = T(a, c)) to the
 // cw <= 16 columns c0.. of Y: C <- C - V (T^T (V^T C)).  One block of
-// kQrThreads threads.  Rows j0 .. s - 1 are taken in chunks of kUpdRows: the
-// chunk's 16 columns of V and of C are read with 16-byte loads (the next
-// chunk's in flight during the products) and staged in LDS.  W = V^T C on
-// MFMA 16x16x4 (wave w sums rows 32 w .. 32 w + 31 of each chunk; the wave
-// partials are added in wave order); W2 = T^T W; then a second sweep over the
-// chunks computes V W2 (wave w: two 16-row tiles) and subtracts it from C.
-constexpr int kUpdRows = 256;
-
-template <typename T, int NB, int HC>
+// kQrThreads threads; both products on MFMA 16x16x4 straight from registers.
+//   W = V^T C: lane l (column l % 16, row group l / 16) loads VW consecutive
+//   rows of its column of V and of C as one vector; product step e pairs row
+//   e of every lane's vector, so the K index of the MFMA runs over the same
+//   rows for both operands.  Wave w takes the row groups w, w + 8, ... (8 in
+//   flight); the wave partials are added in wave order through LDS.
+//   W2 = T^T W.
+//   C <- C - V W2 by 16-row tiles (wave w: tiles w, w + 8, ...): lane l reads
+//   V(row l % 16, columns 4q + l / 16) for the A operand, and the rows of C
+//   that the MFMA result places in lane l (4 consecutive rows for binary32).
+// Rows from s up to ldy are zero in the working copy and stay zero.
+template <typename T, int NB>
 __device__ __forceinline__ void qr_update16(T* __restrict__ Y, int64_t ldy, int64_t s, int64_t j0, int nb0,
                                             const T* __restrict__ Tm, int64_t c0, int cw) {
   using acc_t = typename std::conditional<sizeof(T) == 4, ls_qr_f4, ls_qr_d4>::type;
   using vec_t = typename QrVec<T>::type;
   constexpr int VW = QrVec<T>::W;
-  constexpr int QV = kUpdRows / VW;             // vectors per column segment
-  constexpr int PT = 32 * QV / kQrThreads;      // vectors per thread per chunk (16 V + 16 C columns)
-  static_assert(PT * kQrThreads == 32 * QV, "chunk vectors must divide among the threads");
-  __shared__ T Vs[kUpdRows][17];
-  __shared__ T Cs[kUpdRows][17];
-  __shared__ T part[kQrThreads / 64][16][17];
+  constexpr int NW = kQrThreads / 64;
+  constexpr int GR = 4 * VW;   // rows of one row group (4 lane groups x VW)
+  constexpr int UG = 8;        // row groups in flight per wave
+  constexpr int UT = 4;        // 16-row tiles in flight per wave
+  __shared__ T part[NW][16][17];
   __shared__ T Ws[16][17];
   __shared__ T W2s[16][17];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int cl = lane & 15;
-  const int64_t nch = ls_cdiv(s - j0, kUpdRows);
+  const int kq = lane >> 4;
+  const bool vok = cl < nb0;
+  const bool cok = cl < cw;
+  const int64_t vcol = j0 + cl;                       // this lane's column of V (if vok)
+  const T* __restrict__ Vc = Y + (vok ? vcol : j0) * ldy;
+  T* __restrict__ Cc = Y + (c0 + (cok ? cl : 0)) * ldy;
+  const int64_t rows = s - j0;
 
-  // vector u of this thread: p = tid + kQrThreads u, column k = p / QV (k < 16:
-  // V column k, else C column k - 16), rows VW (p % QV) .. of the chunk
-  auto load = [&](int64_t r0, vec_t (&reg)[PT]) {
+  // W = V^T C
+  const int64_t ng = ls_cdiv(rows, GR);
+  acc_t acc = acc_t{0, 0, 0, 0};
+  for (int64_t g0 = wave; g0 < ng; g0 += (int64_t)NW * UG) {
+    vec_t va[UG], ca[UG];
 #pragma unroll
-    for (int u = 0; u < PT; ++u) {
-      const int p = tid + kQrThreads * u;
-      const int k = p / QV;
-      const int64_t i = r0 + VW * (p % QV);
-      const bool isv = k < 16;
-      const int64_t col = isv ? j0 + k : c0 + (k - 16);
-      const bool ok = (isv ? k < nb0 : (k - 16) < cw) && i < ldy;
-      reg[u] = ok ? *reinterpret_cast<const vec_t*>(Y + i + col * ldy) : vec_t{};
+    for (int u = 0; u < UG; ++u) {
+      const int64_t g = g0 + (int64_t)NW * u;
+      const int64_t rs = j0 + GR * g + VW * kq;
+      const bool in = g < ng && rs < ldy;
+      va[u] = (in && vok) ? *reinterpret_cast<const vec_t*>(Vc + rs) : vec_t{};
+      ca[u] = (in && cok) ? *reinterpret_cast<const vec_t*>(Cc + rs) : vec_t{};
     }
-  };
-  auto stage = [&](int64_t r0, const vec_t (&reg)[PT]) {
 #pragma unroll
-    for (int u = 0; u < PT; ++u) {
-      const int p = tid + kQrThreads * u;
-      const int k = p / QV;
-      const int rl = VW * (p % QV);
+    for (int u = 0; u < UG; ++u) {
+      const int64_t rs = j0 + GR * (g0 + (int64_t)NW * u) + VW * kq;
 #pragma unroll
       for (int e = 0; e < VW; ++e) {
-        if (k < 16) {
-          const int64_t i = r0 + rl + e, d = j0 + k;
-          Vs[rl + e][k] = (k < nb0) ? ((i > d) ? reg[u][e] : ((i == d) ? T(1) : T(0))) : T(0);
-        } else {
-          Cs[rl + e][k - 16] = reg[u][e];
-        }
+        const int64_t i = rs + e;
+        const T v = !vok ? T(0) : ((i > vcol) ? va[u][e] : ((i == vcol) ? T(1) : T(0)));
+        acc = qr_mfma(v, ca[u][e], acc);
       }
-    }
-  };
-
-  acc_t acc = acc_t{0, 0, 0, 0};
-  auto w_chunk = [&]() {
-#pragma unroll
-    for (int kk = 0; kk < 8; ++kk) {
-      const int k = 32 * wave + 4 * kk + (lane >> 4);
-      acc = qr_mfma(Vs[k][cl], Cs[k][cl], acc);
-    }
-  };
-  // HC > 0: all nch <= HC chunks are loaded at once and kept in registers for
-  // both sweeps; otherwise one chunk is loaded ahead of the one in use.
-  constexpr int HR = HC > 0 ? HC : 1;
-  vec_t held[HR][PT];
-  vec_t reg[PT];
-  if constexpr (HC > 0) {
-#pragma unroll
-    for (int ch = 0; ch < HC; ++ch)
-      if (ch < nch) load(j0 + ch * kUpdRows, held[ch]);
-#pragma unroll
-    for (int ch = 0; ch < HC; ++ch) {
-      if (ch < nch) {
-        __syncthreads();
-        stage(j0 + ch * kUpdRows, held[ch]);
-        __syncthreads();
-        w_chunk();
-      }
-    }
-  } else {
-    if (nch > 0) load(j0, reg);
-    for (int64_t ch = 0; ch < nch; ++ch) {
-      const int64_t r0 = j0 + ch * kUpdRows;
-      __syncthreads();
-      stage(r0, reg);
-      __syncthreads();
-      if (ch + 1 < nch) load(r0 + kUpdRows, reg);
-      w_chunk();
     }
   }
 #pragma unroll
@@ -461,7 +424,7 @@ __device__ __forceinline__ void qr_update16(T* __restrict__ Y, int64_t ldy, int6
     const int a = tid >> 4, c = tid & 15;
     T w = 0;
 #pragma unroll
-    for (int q = 0; q < kQrThreads / 64; ++q) w += part[q][a][c];
+    for (int q = 0; q < NW; ++q) w += part[q][a][c];
     Ws[a][c] = w;
   }
   __syncthreads();
@@ -472,54 +435,66 @@ __device__ __forceinline__ void qr_update16(T* __restrict__ Y, int64_t ldy, int6
       for (int q = 0; q <= a; ++q) w2 += Tm[q + a * NB] * Ws[q][c];
     W2s[a][c] = w2;
   }
-  auto c_chunk = [&](int64_t r0) {
+  __syncthreads();
+
+  // C <- C - V W2
+  T wb[4];
 #pragma unroll
-    for (int tt = 0; tt < 2; ++tt) {
-      const int it = 16 * (2 * wave + tt);
+  for (int q = 0; q < 4; ++q) wb[q] = W2s[4 * q + kq][cl];
+  const int64_t nt = ls_cdiv(rows, 16);
+  for (int64_t t0 = wave; t0 < nt; t0 += (int64_t)NW * UT) {
+    T av[UT][4], cv[UT][4];
+#pragma unroll
+    for (int u = 0; u < UT; ++u) {
+      const int64_t r0 = j0 + 16 * (t0 + (int64_t)NW * u);
+      const bool tin = t0 + (int64_t)NW * u < nt;
+      const int64_t i = r0 + cl;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = 4 * q + kq;
+        const int64_t d = j0 + k;
+        T v = 0;
+        if (tin && k < nb0 && i < ldy) v = (i > d) ? Y[i + d * ldy] : ((i == d) ? T(1) : T(0));
+        av[u][q] = v;
+      }
+      if constexpr (sizeof(T) == 4) {
+        const int64_t rc = r0 + 4 * kq;
+        vec_t c4 = vec_t{};
+        if (tin && cok && rc < ldy) c4 = *reinterpret_cast<const vec_t*>(Cc + rc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cv[u][r] = c4[r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t ir = r0 + qr_drow<T>(lane, r);
+          cv[u][r] = (tin && cok && ir < ldy) ? Cc[ir] : T(0);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UT; ++u) {
+      const int64_t r0 = j0 + 16 * (t0 + (int64_t)NW * u);
+      const bool tin = t0 + (int64_t)NW * u < nt;
       acc_t d = acc_t{0, 0, 0, 0};
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int a = 4 * kk + (lane >> 4);
-        d = qr_mfma(Vs[it + cl][a], W2s[a][cl], d);
+      for (int q = 0; q < 4; ++q) d = qr_mfma(av[u][q], wb[q], d);
+      if (tin && cok) {
+        if constexpr (sizeof(T) == 4) {
+          const int64_t rc = r0 + 4 * kq;
+          if (rc < ldy) {
+            vec_t c4;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) c4[r] = cv[u][r] - d[r];
+            *reinterpret_cast<vec_t*>(Cc + rc) = c4;
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t ir = r0 + qr_drow<T>(lane, r);
+            if (ir < ldy) Cc[ir] = cv[u][r] - d[r];
+          }
+        }
       }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) Cs[it + qr_drow<T>(lane, r)][cl] -= d[r];
-    }
-    __syncthreads();
-    // the chunk of C back to Y (the C vectors of this thread)
-#pragma unroll
-    for (int u = 0; u < PT; ++u) {
-      const int p = tid + kQrThreads * u;
-      const int k = p / QV;
-      const int rl = VW * (p % QV);
-      const int64_t i = r0 + rl;
-      if (k >= 16 && (k - 16) < cw && i < ldy) {
-        vec_t v;
-#pragma unroll
-        for (int e = 0; e < VW; ++e) v[e] = Cs[rl + e][k - 16];
-        *reinterpret_cast<vec_t*>(Y + i + (c0 + (k - 16)) * ldy) = v;
-      }
-    }
-  };
-  if constexpr (HC > 0) {
-#pragma unroll
-    for (int ch = 0; ch < HC; ++ch) {
-      if (ch < nch) {
-        __syncthreads();
-        stage(j0 + ch * kUpdRows, held[ch]);
-        __syncthreads();
-        c_chunk(j0 + ch * kUpdRows);
-      }
-    }
-  } else {
-    if (nch > 0) load(j0, reg);
-    for (int64_t ch = 0; ch < nch; ++ch) {
-      const int64_t r0 = j0 + ch * kUpdRows;
-      __syncthreads();
-      stage(r0, reg);
-      __syncthreads();
-      if (ch + 1 < nch) load(r0 + kUpdRows, reg);
-      c_chunk(r0);
     }
   }
 }
@@ -529,15 +504,6 @@ __device__ __forceinline__ void qr_update16(T* __restrict__ Y, int64_t ldy, int6
 // next panel (columns j1 .. j1 + nb1 - 1) and factors that panel (T into
 // Tnext); blocks b >= 1 apply it to the 16 columns jt + 16 (b - 1) .. of the
 // trailing matrix, which the next panel's reflectors reach in the next step.
-// Chunks of the trailing update held in registers: the row capacity of the
-// panel (RPT x kPanelThreads rows) in 256-row chunks, while the held vectors
-// stay within 128 VGPRs per thread; 0 (streamed chunks) beyond.
-template <typename T, int RPT>
-constexpr int kQrChunks = RPT * kPanelThreads / kUpdRows;
-template <typename T, int RPT>
-constexpr int kQrHeld =
-    (kQrChunks<T, RPT> * (32 * kUpdRows / kQrThreads) * (int)sizeof(T) / 4 <= 128) ? kQrChunks<T, RPT> : 0;
-static_assert(kQrHeld<float, 4> == 8, "binary32 with s <= 2048 holds its update chunks");
 
 template <typename T, int RPT, int NB>
 __global__ __launch_bounds__(kQrThreads) void k_qr_step(T* __restrict__ Y, int64_t ldy, int64_t s, int64_t ncols,
@@ -545,13 +511,13 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_step(T* __restrict__ Y, int64
                                                          int64_t j1, int nb1, T* __restrict__ tau,
                                                          T* __restrict__ Tnext, int64_t jt) {
   if (blockIdx.x == 0) {
-    qr_update16<T, NB, kQrHeld<T, RPT>>(Y, ldy, s, j0, nb0, Tprev, j1, nb1);
+    qr_update16<T, NB>(Y, ldy, s, j0, nb0, Tprev, j1, nb1);
     __syncthreads();   // the next panel's updated columns are read back below
     qr_panel_body<T, RPT, NB>(Y, ldy, s, j1, nb1, tau, Tnext);
   } else {
     const int64_t c0 = jt + 16 * (int64_t)(blockIdx.x - 1);
     const int cw = (int)((ncols - c0 < 16) ? ncols - c0 : 16);
-    qr_update16<T, NB, kQrHeld<T, RPT>>(Y, ldy, s, j0, nb0, Tprev, c0, cw);
+    qr_update16<T, NB>(Y, ldy, s, j0, nb0, Tprev, c0, cw);
   }
 }
 
