@@ -664,6 +664,7 @@ int qr_dispatch(T* Y, int64_t ldy, int64_t s, int64_t ncols, char* ws, hipStream
     if (rpt <= 32) return qr_blocked<T, 32, 4>(Y, ldy, s, ncols, ws, st);
   } else {
     if (rpt <= 4) return qr_blocked<T, 4, 8>(Y, ldy, s, ncols, ws, st);
+    if (rpt <= 8) return qr_blocked<T, 8, 8>(Y, ldy, s, ncols, ws, st);
     if (rpt <= 16) return qr_blocked<T, 16, 4>(Y, ldy, s, ncols, ws, st);
     if (rpt <= 32) return qr_blocked<T, 32, 2>(Y, ldy, s, ncols, ws, st);
   }

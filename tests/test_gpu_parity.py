@@ -219,10 +219,11 @@ def test_sketch_e4m3_needs_column_scaling(L):
 
 # ------------------------------------------------------------------ QR
 @pytest.mark.parametrize("u_qr", ["f64", "f32"])
-# s = 2048 is the largest binary32 sketch whose update chunks stay in
-# registers (8 chunks of 256 rows), s = 2049 the smallest that streams them
+# panel shapes (rows per thread x columns): s = 2048 is the largest with 4
+# rows per thread, s = 2049 the smallest with more; s = 3000 takes the
+# 8-row, 8-column binary64 panel
 @pytest.mark.parametrize("s,ncols,kappa", [(200, 51, 1e2), (2000, 501, 1e2), (1111, 97, 1e4), (2048, 130, 1e3),
-                                          (2049, 33, 1e3)])
+                                          (2049, 33, 1e3), (3000, 77, 1e3)])
 def test_qr_r_matches_oracle(L, u_qr, s, ncols, kappa):
     P = make_problem(s, ncols, kappa, seed=14, store="f64")
     Y = P.A()                                       # s x ncols with known conditioning
