@@ -991,16 +991,22 @@ __global__ __launch_bounds__(1024) void k_fg_col(int64_t m, int64_t n, const TB*
     int64_t r0, r1;
     row_range(m, nrb, (int)blockIdx.x - ncb, r0, r1);
     const double* w = F.V + (int64_t)(j + 1) * F.ldv;
+    constexpr int kRB = 16;   // rows per lane with their loads in flight together
     for (int c = wvi; c <= j; c += 16) {
       const double* vc = F.V + (int64_t)c * F.ldv;
-      double a0 = 0.0, a1 = 0.0;
-      int64_t i = r0 + lane;
-      for (; i + 64 < r1; i += 128) {
-        a0 += vc[i] * w[i];
-        a1 += vc[i + 64] * w[i + 64];
+      double a[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int64_t i0 = r0 + lane; i0 < r1; i0 += 64 * kRB) {
+        double x[kRB], y[kRB];
+#pragma unroll
+        for (int q = 0; q < kRB; ++q) {
+          const int64_t i = i0 + 64 * q;
+          x[q] = (i < r1) ? vc[i] : 0.0;
+          y[q] = (i < r1) ? w[i] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kRB; ++q) a[q & 3] += x[q] * y[q];
       }
-      if (i < r1) a0 += vc[i] * w[i];
-      const double t = ls_wave_sum(a0 + a1);
+      const double t = ls_wave_sum((a[0] + a[1]) + (a[2] + a[3]));
       if (lane == 0) hxpart[(int64_t)c * Gx + blockIdx.x] = t;
     }
     return;
@@ -1047,20 +1053,20 @@ __global__ __launch_bounds__(1024) void k_fg_col(int64_t m, int64_t n, const TB*
   }
 }
 
-// sum_{c <= j} V[i + c ldv] h[c] with NL independent loads in flight.
+// sum_{c <= j} V[i + c ldv] h[c] with NL independent loads in flight: the
+// columns in groups of NL, the last group guarded (its loads issued together
+// like the others; columns beyond j add zero).
 template <int NL = 8>
 __device__ __forceinline__ double vrow_dot(const double* __restrict__ V, int64_t ldv, int64_t i, int j,
                                            const double* __restrict__ h) {
   double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int c = 0;
-  for (; c + NL <= j + 1; c += NL) {
+  for (int c = 0; c <= j; c += NL) {
     double v[NL];
 #pragma unroll
-    for (int q = 0; q < NL; ++q) v[q] = V[i + (int64_t)(c + q) * ldv];
+    for (int q = 0; q < NL; ++q) v[q] = (c + q <= j) ? V[i + (int64_t)(c + q) * ldv] : 0.0;
 #pragma unroll
-    for (int q = 0; q < NL; ++q) a[q & 7] += v[q] * h[c + q];
+    for (int q = 0; q < NL; ++q) a[q & 7] += v[q] * ((c + q <= j) ? h[c + q] : 0.0);
   }
-  for (; c <= j; ++c) a[0] += V[i + (int64_t)c * ldv] * h[c];
   return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
