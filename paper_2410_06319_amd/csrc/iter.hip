@@ -1198,15 +1198,40 @@ __global__ __launch_bounds__(kThreads) void k_fg_update(FgPtrs F, int64_t m, int
                                                         double* __restrict__ part) {
   __shared__ double y[128];
   __shared__ double dsh[8];
+  __shared__ double Hs[kMaxKrylov * (kMaxKrylov + 1) / 2];   // upper triangle, column c at c (c + 1) / 2
   const int k = F.st->k;
   const int64_t ldh = kmax + 1;
   for (int i = threadIdx.x; i < k; i += kThreads) y[i] = F.g[i];
+  // stage H(0:k, 0:k)'s upper triangle in LDS (eight loads per thread in
+  // flight), so that the substitution below waits on no global load
+  const int kk = k * k;
+  for (int b0 = 0; b0 < kk; b0 += 8 * kThreads) {
+    double hv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = b0 + (int)threadIdx.x + kThreads * u;
+      hv[u] = 0.0;
+      if (idx < kk) {
+        const int c = idx / k, t = idx - c * k;
+        if (t <= c) hv[u] = F.H[t + (int64_t)c * ldh];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = b0 + (int)threadIdx.x + kThreads * u;
+      if (idx < kk) {
+        const int c = idx / k, t = idx - c * k;
+        if (t <= c) Hs[c * (c + 1) / 2 + t] = hv[u];
+      }
+    }
+  }
   for (int i = k - 1; i >= 0; --i) {
     __syncthreads();
-    const double yi = y[i] / F.H[i + (int64_t)i * ldh];
+    const double* hc = Hs + i * (i + 1) / 2;
+    const double yi = y[i] / hc[i];
     __syncthreads();
     if (threadIdx.x == 0) y[i] = yi;
-    for (int t = threadIdx.x; t < i; t += kThreads) y[t] -= F.H[t + (int64_t)i * ldh] * yi;
+    for (int t = threadIdx.x; t < i; t += kThreads) y[t] -= hc[t] * yi;
   }
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
