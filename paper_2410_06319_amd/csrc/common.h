@@ -163,28 +163,32 @@ __device__ __forceinline__ T ls_block_sum(T v, T* sh /* NT/64 entries */) {
 
 // Upper-triangular matrix-vector product out = U f, rows of one block of
 // kUtThreads threads: thread (r = t % 32, g = t / 32) sums the columns
-// j = row + g + 32 k with four independent loads in flight, then the 32
-// column-group sums of each row are added in a fixed order.  The row value is
-// returned in the threads with g == 0 (zero elsewhere).  Launch with
-// ceil(n / 32) blocks of kUtThreads threads; red holds 32 x 33 doubles.
+// j = row + g + 32 k, sixteen of them (and their f) loaded together per
+// round, then the 32 column-group sums of each row are added in a fixed
+// order.  The row value is returned in the threads with g == 0 (zero
+// elsewhere).  Launch with ceil(n / 32) blocks of kUtThreads threads; red
+// holds 32 x 33 doubles.
 constexpr int kUtThreads = 1024;
 template <typename TU, typename F>
 __device__ __forceinline__ double ls_utmv_row(const TU* __restrict__ U, int64_t ldu, int64_t n, F f,
                                               double* red) {
   const int r = threadIdx.x & 31, g = threadIdx.x >> 5;
   const int64_t row = (int64_t)blockIdx.x * 32 + r;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
   if (row < n) {
-    int64_t j = row + g;
-    for (; j + 96 < n; j += 128) {
-      a0 += (double)U[row + j * ldu] * f(j);
-      a1 += (double)U[row + (j + 32) * ldu] * f(j + 32);
-      a2 += (double)U[row + (j + 64) * ldu] * f(j + 64);
-      a3 += (double)U[row + (j + 96) * ldu] * f(j + 96);
+    for (int64_t j0 = row + g; j0 < n; j0 += 32 * 16) {
+      double u[16], x[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int64_t j = j0 + 32 * q;
+        u[q] = (j < n) ? (double)U[row + j * ldu] : 0.0;
+        x[q] = (j < n) ? f(j) : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) a[q & 3] += u[q] * x[q];
     }
-    for (; j < n; j += 32) a0 += (double)U[row + j * ldu] * f(j);
   }
-  red[g * 33 + r] = (a0 + a1) + (a2 + a3);
+  red[g * 33 + r] = (a[0] + a[1]) + (a[2] + a[3]);
   __syncthreads();
   double s = 0.0;
   if (g == 0)
