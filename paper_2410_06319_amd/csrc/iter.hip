@@ -97,6 +97,30 @@ __device__ __forceinline__ double wave_sum_array(const double* __restrict__ part
   return ls_wave_sum(s);
 }
 
+// wave_sum_array of two arrays at once (their loads issued together); each
+// sum is added in the same order as by wave_sum_array alone.
+__device__ __forceinline__ void wave_sum_array2(const double* __restrict__ pa, int Ga,
+                                                const double* __restrict__ pb, int Gb, int lane, double& sa,
+                                                double& sb) {
+  double s0 = 0.0, s1 = 0.0;
+  const int Gm = (Ga > Gb) ? Ga : Gb;
+  for (int g0 = 0; g0 < Gm; g0 += 512) {
+    double va[8], vb[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int g = g0 + 64 * q + lane;
+      va[q] = (g < Ga) ? pa[g] : 0.0;
+      vb[q] = (g < Gb) ? pb[g] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s0 += va[q];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s1 += vb[q];
+  }
+  sa = ls_wave_sum(s0);
+  sb = ls_wave_sum(s1);
+}
+
 // Range of row blocks owned by block `bx` of G.
 __device__ __forceinline__ void row_range(int64_t nrb, int G, int bx, int64_t& b0, int64_t& b1) {
   b0 = (nrb * bx) / G;
@@ -396,7 +420,14 @@ __global__ __launch_bounds__(kThreads) void k_lsqr_col(int64_t n, const T* __res
   }
   const int lane = threadIdx.x & 63;
   const int64_t col = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const double beta = sqrt(wave_sum_array(nupart, G, lane));          // beta_{i+1}
+  double beta, alpha2 = 0.0;
+  if (init) {
+    beta = sqrt(wave_sum_array(nupart, G, lane));                     // beta_{i+1}
+  } else {
+    double beta2;
+    wave_sum_array2(nupart, G, nvpart_in, Gv, lane, beta2, alpha2);
+    beta = sqrt(beta2);
+  }
   LsqrRec N = R;
   double alpha = 0.0, xw = 0.0, yw = 0.0, vcoef = 0.0;
   bool done = false;
@@ -413,7 +444,7 @@ __global__ __launch_bounds__(kThreads) void k_lsqr_col(int64_t n, const T* __res
     done = N.stop != 0;
     N.done = done ? 1 : 0;
   } else {
-    alpha = sqrt(wave_sum_array(nvpart_in, Gv, lane));                // alpha_i
+    alpha = sqrt(alpha2);                                             // alpha_i
     const double rhobar = -R.c * alpha;
     const double theta = R.s * alpha;
     // stopping tests of iteration i-1 (they need alpha_i)
@@ -461,7 +492,16 @@ __global__ __launch_bounds__(kThreads) void k_lsqr_col(int64_t n, const T* __res
   if (!done && col < n) {
     const T* tp = tpart + col * G;
     T acc = 0;
-    for (int g = lane; g < G; g += 64) acc += tp[g];
+    for (int g0 = 0; g0 < G; g0 += 512) {   // eight loads per lane in flight
+      T pv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int g = g0 + 64 * q + lane;
+        pv[q] = (g < G) ? tp[g] : T(0);
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc += pv[q];
+    }
     acc = ls_wave_sum(acc);
     if (lane == 0) {
       const T t = (beta > 0.0) ? (T)(acc / (T)beta) : T(0);
