@@ -866,6 +866,27 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
   __shared__ TB cred[64 * Q];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
+  double* vj = F.V + (int64_t)j * F.ldv;
+  double* w = F.V + (int64_t)(j + 1) * F.ldv;
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  int64_t p0, p1;
+  row_range(npan, (int)nw, blockIdx.x * 4 + wave, p0, p1);
+  vec_t cur[Q];
+  double vro[PR];
+  auto load = [&](int64_t p, vec_t* dst, double* vr_) {
+    const TB* base = Bp + p * (PR * n);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t c = lane + 64 * q;
+      dst[q] = (c < n) ? *reinterpret_cast<const vec_t*>(base + c * PR) : vec_t{};
+    }
+    const int64_t i0 = p * PR;
+#pragma unroll
+    for (int k = 0; k < PR; ++k) vr_[k] = (i0 + k < m) ? vj[i0 + k] : 0.0;
+  };
+  // the first panel of B and its rows of v_j do not depend on ||w||: their
+  // loads go out before the norm's partials are summed
+  if (p0 < p1) load(p0, cur, vro);
   const double h = sqrt(wave_sum_array(w2part, Gw, lane));
   const int64_t ldh = kmax + 1;
   if (blockIdx.x == 0) {
@@ -930,8 +951,6 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
   }
   if (h == 0.0 || !isfinite(h) || final_step || j >= kmax) return;
   const double inv = 1.0 / h;
-  double* vj = F.V + (int64_t)j * F.ldv;
-  double* w = F.V + (int64_t)(j + 1) * F.ldv;
   TB vl[Q], creg[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -939,23 +958,6 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
     vl[q] = (c < n) ? (TB)(vj[m + c] * inv) : TB(0);
     creg[q] = 0;
   }
-  const int64_t nw = (int64_t)gridDim.x * 4;
-  int64_t p0, p1;
-  row_range(npan, (int)nw, blockIdx.x * 4 + wave, p0, p1);
-  vec_t cur[Q];
-  double vro[PR];
-  auto load = [&](int64_t p, vec_t* dst, double* vr_) {
-    const TB* base = Bp + p * (PR * n);
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int64_t c = lane + 64 * q;
-      dst[q] = (c < n) ? *reinterpret_cast<const vec_t*>(base + c * PR) : vec_t{};
-    }
-    const int64_t i0 = p * PR;
-#pragma unroll
-    for (int k = 0; k < PR; ++k) vr_[k] = (i0 + k < m) ? vj[i0 + k] : 0.0;
-  };
-  if (p0 < p1) load(p0, cur, vro);
   for (int64_t p = p0; p < p1; ++p) {
     vec_t nxt[kPanPrefetch<Q> ? Q : 1];
     double vrn[PR];
