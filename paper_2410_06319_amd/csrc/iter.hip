@@ -294,19 +294,6 @@ __global__ __launch_bounds__(kThreads) void k_lsqr_pan(const T* __restrict__ Bp,
   __shared__ double dsh[8];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  T scale = 1, coef = -1;
-  if (!init) {
-    const double alpha = sqrt(wave_sum_array(nvpart, Gv, lane));
-    scale = (T)(1.0 / alpha);
-    coef = (T)(alpha / st->rec[par].beta);
-  }
-  T vl[Q], creg[Q];
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int64_t c = lane + 64 * q;
-    vl[q] = (c < n) ? v[c] * scale : T(0);
-    creg[q] = 0;
-  }
   const int64_t nw = (int64_t)gridDim.x * 4;
   int64_t p0, p1;
   row_range(npan, (int)nw, blockIdx.x * 4 + wave, p0, p1);
@@ -328,7 +315,22 @@ __global__ __launch_bounds__(kThreads) void k_lsqr_pan(const T* __restrict__ Bp,
       for (int k = 0; k < PR; ++k) uu[k] = (i0 + k < m) ? u[i0 + k] : T(0);
     }
   };
+  // the first panel of B and its rows of u do not depend on alpha: their
+  // loads go out before alpha's partials are summed
   if (p0 < p1) load(p0, cur, uo);
+  T scale = 1, coef = -1;
+  if (!init) {
+    const double alpha = sqrt(wave_sum_array(nvpart, Gv, lane));
+    scale = (T)(1.0 / alpha);
+    coef = (T)(alpha / st->rec[par].beta);
+  }
+  T vl[Q], creg[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t c = lane + 64 * q;
+    vl[q] = (c < n) ? v[c] * scale : T(0);
+    creg[q] = 0;
+  }
   for (int64_t p = p0; p < p1; ++p) {
     vec_t nxt[kPanPrefetch<Q> ? Q : 1];
     vec_t un_o;
