@@ -577,6 +577,31 @@ constexpr int kResRows = 256;
 constexpr int kResWaves = 8;                  // column groups of a residual block
 constexpr int kResThreads = 64 * kResWaves;
 
+// Rows i0 .. i0 + 3 of column j of A in its storage type, zero where ok is
+// false or past m.
+template <typename TA>
+__device__ __forceinline__ void load_rows4_st(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t i0,
+                                              int64_t j, bool vec, bool ok, TA (&a)[4]) {
+  const TA* p = A + i0 + j * lda;
+  if (ok && vec) {
+    if constexpr (sizeof(TA) == 4) {
+      const ls_float4v v = *reinterpret_cast<const ls_float4v*>(p);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) a[k] = v[k];
+    } else {
+      const ls_double2v v0 = *reinterpret_cast<const ls_double2v*>(p);
+      const ls_double2v v1 = *reinterpret_cast<const ls_double2v*>(p + 2);
+      a[0] = v0[0];
+      a[1] = v0[1];
+      a[2] = v1[0];
+      a[3] = v1[1];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a[k] = (ok && i0 + k < m) ? p[k] : TA(0);
+  }
+}
+
 template <typename TA>
 __device__ __forceinline__ void load_rows4(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t i0, int64_t j,
                                            bool vec, double (&a)[4]) {
@@ -710,7 +735,7 @@ __global__ __launch_bounds__(kResThreads) void k_resid_u(const TA* __restrict__ 
 // per-block column partials (tpart[c G + block], hi and lo parts), binary64
 // or double-double; A and b are used exactly as stored.
 template <typename TA, bool DD>
-__global__ __launch_bounds__(kResThreads) __attribute__((amdgpu_waves_per_eu(DD ? 2 : 4))) void k_lsir_resid(const TA* __restrict__ A, int64_t lda, int64_t m,
+__global__ __launch_bounds__(kResThreads) __attribute__((amdgpu_waves_per_eu(DD ? 2 : 3))) void k_lsir_resid(const TA* __restrict__ A, int64_t lda, int64_t m,
                                                             int64_t n, int vec_ok, const TA* __restrict__ b,
                                                             const double* __restrict__ r, const double* __restrict__ x,
                                                             double* __restrict__ V, double* __restrict__ tpart_hi,
@@ -728,19 +753,30 @@ __global__ __launch_bounds__(kResThreads) __attribute__((amdgpu_waves_per_eu(DD 
 #pragma unroll
   for (int k = 0; k < 4; ++k) rv[k] = (i0 + k < m) ? r[i0 + k] : 0.0;
   RAcc<DD> racc[4];
+  constexpr int NQ = (sizeof(TA) == 4 || DD) ? 8 : 4;   // columns whose loads are in flight together
   for (int64_t jb = j0; jb < j1; jb += 16) {
     RAcc<DD> cp[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int64_t j = jb + q;
-      if (j < j1 && i0 < m) {
-        double a[4];
-        load_rows4(A, lda, m, i0, j, vec, a);
-        const double xj = x[j];
+    for (int h = 0; h < 16; h += NQ) {
+      // NQ columns' loads first, then the products (same order of addition)
+      TA av[NQ][4];
+      double xv[NQ];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          racc[k].fma(a[k], xj);
-          cp[q].fma(a[k], rv[k]);
+      for (int q = 0; q < NQ; ++q) {
+        const int64_t j = jb + h + q;
+        const bool ok = j < j1 && i0 < m;
+        load_rows4_st(A, lda, m, i0, j, vec, ok, av[q]);
+        xv[q] = (j < j1) ? x[j] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        if (jb + h + q < j1 && i0 < m) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const double a = (double)av[q][k];
+            racc[k].fma(a, xv[q]);
+            cp[h + q].fma(a, rv[k]);
+          }
         }
       }
     }
