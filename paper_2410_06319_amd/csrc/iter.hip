@@ -705,16 +705,23 @@ __global__ __launch_bounds__(kResThreads) void k_resid_u(const TA* __restrict__ 
   const int64_t jq = ls_cdiv(n, kResWaves);
   const int64_t j0 = wave * jq, j1 = (j0 + jq < n) ? j0 + jq : n;
   T acc[4] = {0, 0, 0, 0};
-  for (int64_t jb = j0; jb < j1; jb += 16) {
+  constexpr int NQ = 8;   // columns whose loads are in flight together
+  for (int64_t jb = j0; jb < j1; jb += NQ) {
+    TA av[NQ][4];
+    double xv[NQ];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const int64_t j = jb + q;
-      if (j < j1 && i0 < m) {
-        double a[4];
-        load_rows4(A, lda, m, i0, j, vec, a);
-        const T xj = (T)x[j];
+      const bool ok = j < j1 && i0 < m;
+      load_rows4_st(A, lda, m, i0, j, vec, ok, av[q]);
+      xv[q] = (j < j1) ? x[j] : 0.0;
+    }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) acc[k] += (T)a[k] * xj;
+    for (int q = 0; q < NQ; ++q) {
+      if (jb + q < j1 && i0 < m) {
+        const T xj = (T)xv[q];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] += (T)(double)av[q][k] * xj;
       }
     }
   }
