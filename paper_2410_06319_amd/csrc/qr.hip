@@ -3,11 +3,12 @@
 //
 // Blocked right-looking Householder QR (compact WY, LAPACK's forward
 // column-wise convention H = I - V T V^T):
-//   * a panel of NB columns is factored by one 1024-thread block that keeps
-//     the panel in registers (RPT rows per thread) and builds T on the fly,
-//     with one block-wide reduction per column;
-//   * trailing columns are updated as C <- C - V (T^T (V^T C)) on MFMA, 16
-//     columns per block;
+//   * a panel of NB columns is factored by one 512-thread block that keeps
+//     the panel in registers (RPT rows per thread), with one block-wide
+//     reduction per column, and forms T from the stored inner products after
+//     the column loop;
+//   * trailing columns are updated as C <- C - V (T^T (V^T C)) on MFMA
+//     straight from registers, 16 columns per block;
 //   * one launch per panel with look-ahead: while block 0 updates and
 //     factors the next panel, the other blocks update the rest.
 // Reflectors follow the usual choice beta = -sign(x_1) ||x||; at the end
