@@ -47,11 +47,18 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2410_06319_amd", "csrc", f) for f in
 
 
 def kernel_source_hash():
+    """Hash of the code of the FGMRES pass's sources, with comments and blank
+    lines removed (a comment edit does not change the kernels)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+        h.update(code.encode())
     return h.hexdigest()[:16]
 
 

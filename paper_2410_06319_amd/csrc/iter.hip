@@ -1195,7 +1195,7 @@ __device__ __forceinline__ void sweep_sum_columns(const double* __restrict__ par
   }
 }
 
-// First Gram-Schmidt sweep over rows [1024 b, 1024 b + 1024) of w = V[:, j+1]:
+// First Gram-Schmidt sweep over rows [512 b, 512 b + 512) of w = V[:, j+1]:
 // h1[c] = sum of the Gx partials of k_fg_col; w <- w - V[:, 0:j+1] h1; partial
 // h2[c] = V[:, c] . w over the block's rows.  Block 0 records h1 in column j of H.
 __global__ __launch_bounds__(kSweepThreads) void k_cgs1(FgPtrs F, int64_t m, int64_t n, int j, int kmax,
