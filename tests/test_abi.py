@@ -111,3 +111,30 @@ def test_sketch_plan_candidates_and_tuned_table():
         assert fmt in counts and 1 <= plan <= counts[fmt]
         assert (terms == 1) if fmt == B.FP64 else (1 <= terms <= 3)
         assert ncols_max > 0 and m_max > 0
+
+
+def test_traffic_figure_follows_the_code_not_its_comments(tmp_path, monkeypatch):
+    # bench.py reports the recorded HBM traffic only while the hash of the
+    # pass's sources matches: comment and blank-line edits keep the hash, a
+    # code edit changes it and the recorded figure is then dropped
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    a = tmp_path / "a.hip"
+    a.write_text("int f() {\n  return 1;  // one\n}\n")
+    b = tmp_path / "b.hip"
+    b.write_text("// header\nint f() {\n\n  return 1;\n}  /* tail\n   comment */\n")
+    c = tmp_path / "c.hip"
+    c.write_text("int f() {\n  return 2;\n}\n")
+    hashes = []
+    for f in (a, b, c):
+        monkeypatch.setattr(bench, "KERNEL_SOURCES", [str(f)])
+        hashes.append(bench.kernel_source_hash())
+    assert hashes[0] == hashes[1] and hashes[0] != hashes[2]
+    rec = tmp_path / "traffic.md"
+    rec.write_text(f"    traffic_bytes_per_launch=2.0e+08 source_sha256_16={hashes[0]}\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(rec))
+    monkeypatch.setattr(bench, "KERNEL_SOURCES", [str(b)])
+    assert bench.recorded_traffic() == 2.0e8
+    monkeypatch.setattr(bench, "KERNEL_SOURCES", [str(c)])
+    assert bench.recorded_traffic() is None
