@@ -18,8 +18,9 @@
  *  - `stream` is a hipStream_t (passed as void*); NULL is the default stream.
  *    All work is enqueued on it.  Entry points that iterate synchronise the
  *    stream at their convergence checks and before returning, so their
- *    outputs and statistics are valid on return.  ls_sketch, ls_qr_r and
- *    ls_omega do not synchronise.
+ *    outputs and statistics are valid on return.  ls_qr_r also
+ *    synchronises the stream before returning (it reads back the flag that reports a zero or non-finite diagonal entry of R);
+ *    ls_sketch, ls_omega and ls_philox do not synchronise.
  *  - Errors are returned as negative status codes; nothing aborts or throws
  *    across the ABI.  ls_strerror(code) gives a message.
  *  - Calls that share a workspace must not overlap in time.
@@ -52,8 +53,11 @@ enum {
   LS_E_ARG = -1,          /* bad size, pointer, leading dimension or precision choice */
   LS_E_WORKSPACE = -2,    /* workspace smaller than ls_workspace_size reports */
   LS_E_HIP = -3,          /* a HIP runtime call failed */
-  LS_E_SINGULAR = -4,     /* zero or non-finite diagonal in R: A is rank deficient in u_s */
-  LS_E_NONFINITE = -5,    /* NaN or Inf met in an iterate */
+  LS_E_SINGULAR = -4,     /* zero diagonal entry in R (or R^-1 overflows): A is rank
+                             deficient in u_s */
+  LS_E_NONFINITE = -5,    /* NaN or Inf met: in the sketch of [A b] (a non-finite
+                             diagonal entry of R, e.g. from NaN or Inf in A) or in
+                             an iterate (e.g. from NaN or Inf in b) */
   LS_E_UNSUPPORTED = -6   /* combination the library does not implement */
 };
 
@@ -209,6 +213,11 @@ int ls_sketch(const ls_problem_t *P, const ls_sketch_opts_t *so, ls_prec_t u_s,
  * Q^T Omega b (Algorithm 2, sketch-and-solve start). */
 int ls_qr_r(int64_t s, int64_t ncols, ls_prec_t u_qr, double *Y, int64_t ldy,
             double *R, int64_t ldr, void *ws, size_t ws_bytes, void *stream);
+
+/* Bytes of workspace ls_qr_r needs for an s x ncols sketch in u_qr (the
+ * working copy of Y in u_qr, the Householder scalars, two T factors and the
+ * flag word).  Returns LS_OK, LS_E_ARG (bad sizes) or LS_E_UNSUPPORTED. */
+int ls_qr_workspace_size(int64_t s, int64_t ncols, ls_prec_t u_qr, size_t *bytes);
 
 /* Algorithm 2's LSQR solve: LSQR on A R^-1 (right preconditioning, Paige and
  * Saunders' recurrences) in precision u, started from x (device, length n,

@@ -21,6 +21,7 @@ from .api import (  # noqa: F401
     ls_solve_batched,
     precs,
     problem,
+    qr_workspace_size,
     sketch_opts,
     sketch_plan_info,
     sketch_terms_for,

@@ -81,6 +81,12 @@ def workspace_size(P, so, pr, io) -> int:
     return n.value
 
 
+def qr_workspace_size(s, ncols, u_qr="f32") -> int:
+    n = ctypes.c_size_t(0)
+    _check(B.load().ls_qr_workspace_size(int(s), int(ncols), B.PREC[u_qr], ctypes.byref(n)), "ls_qr_workspace_size")
+    return n.value
+
+
 def ls_sketch(At, b, s, seed=0, u_s="bf16", terms=1, prob_id=0, col_scale=0, zeta=0, ws=None, plan=0):
     """Y = Omega [A b] (s x (n+1), float64; returned as a (n+1, s) tensor = column-major Y).
 
@@ -106,7 +112,7 @@ def ls_qr_r(Yt: torch.Tensor, u_qr="f32", ws=None):
     if Yt.dtype != torch.float64 or Yt.stride(1) != 1:
         raise ValueError("Yt must be float64 with unit stride along s")
     if ws is None:
-        ws = workspace(8 * (s * ncols * 2 + 64 * ncols) + (1 << 20), Yt.device)
+        ws = workspace(qr_workspace_size(s, ncols, u_qr), Yt.device)
     Rt = torch.empty((ncols, ncols), dtype=torch.float64, device=Yt.device)
     _check(B.load().ls_qr_r(s, ncols, B.PREC[u_qr], Yt.data_ptr(), Yt.stride(0), Rt.data_ptr(), ncols,
                             ws.data_ptr(), ws.numel(), _stream()), "ls_qr_r")

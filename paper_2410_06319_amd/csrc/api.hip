@@ -78,6 +78,18 @@ int check_precs(const ls_precs_t* pr) {
   return LS_OK;
 }
 
+}  // namespace
+
+// Status of the flag word the QR and R^-1 kernels set (bit 1: a non-finite
+// diagonal entry of R, bit 0: a zero one, or an overflow in R^-1).
+int ls::qr_flag_status(int flag) {
+  if (flag & 2) return LS_E_NONFINITE;
+  if (flag & 1) return LS_E_SINGULAR;
+  return LS_OK;
+}
+
+namespace {
+
 // x = W c with W upper triangular n x n (ld n): x^s = R^-1 (Q^T Omega b).
 __global__ __launch_bounds__(kUtThreads) void k_trmv_f64(const double* __restrict__ W, int64_t n,
                                                          const double* __restrict__ c, double* __restrict__ x) {
@@ -138,7 +150,7 @@ int make_inverse(const double* R, int64_t ldr, int64_t n, const Inv& v, hipStrea
   int flag = 0;
   LS_HIP_TRY(hipMemcpyAsync(&flag, v.flag, sizeof(int), hipMemcpyDeviceToHost, st));
   LS_HIP_TRY(hipStreamSynchronize(st));
-  return flag ? LS_E_SINGULAR : LS_OK;
+  return qr_flag_status(flag);
 }
 
 struct Timer {
@@ -319,7 +331,14 @@ int ls_qr_r(int64_t s, int64_t ncols, ls_prec_t u_qr, double* Y, int64_t ldy, do
   int h = 0;
   LS_HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
   LS_HIP_TRY(hipStreamSynchronize(st));
-  return h ? LS_E_SINGULAR : LS_OK;
+  return qr_flag_status(h);
+}
+
+int ls_qr_workspace_size(int64_t s, int64_t ncols, ls_prec_t u_qr, size_t* bytes) {
+  if (!bytes || ncols < 1 || s < ncols) return LS_E_ARG;
+  if (!prec_is(u_qr, LS_FP32, LS_FP64)) return LS_E_UNSUPPORTED;
+  *bytes = qr_workspace(s, ncols, u_qr) + 256;
+  return LS_OK;
 }
 
 int ls_lsqr_precond(const ls_problem_t* P, const double* R, int64_t ldr, ls_prec_t u, double* x,
@@ -443,8 +462,8 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
     std::memcpy(&flag, rb.data(), sizeof(int));
     std::memcpy(fro.data(), rb.data() + fro_off, 16 * (size_t)n);
     if (flag) {
-      S->status = LS_E_SINGULAR;
-      return LS_E_SINGULAR;
+      S->status = qr_flag_status(flag);
+      return S->status;
     }
     double w2 = 0.0, r2 = 0.0;
     for (int64_t j = 0; j < n; ++j) {

@@ -52,6 +52,8 @@ size_t qr_workspace(int64_t s, int64_t ncols, ls_prec_t u_qr);
 // check_cols: leading diagonal entries of R tested for zero / non-finite values.
 int qr_run(int64_t s, int64_t ncols, ls_prec_t u_qr, double* Y, int64_t ldy, double* R, int64_t ldr,
            char* ws, size_t ws_bytes, int* d_flag, int64_t check_cols, hipStream_t st);
+// LS_OK, LS_E_SINGULAR or LS_E_NONFINITE from the flag word of qr_run / trinv_run.
+int qr_flag_status(int flag);
 // W = R^-1 (n x n upper, binary64, ldw) and, if W32 != NULL, its binary32 copy (ld n).
 // With fro != NULL: fro[2j] = ||W[:, j]||^2, fro[2j+1] = ||R[:, j]||^2 (2n doubles).
 int trinv_run(const double* R, int64_t ldr, int64_t n, double* W, int64_t ldw, float* W32, int* d_flag,

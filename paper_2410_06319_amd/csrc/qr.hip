@@ -543,7 +543,14 @@ __global__ __launch_bounds__(256) void k_qr_finish(const T* __restrict__ Y, int6
   const double d = (double)Y[i + i * ldy];
   const double sg = (d < 0.0) ? -1.0 : 1.0;
   R[i + j * ldr] = (i <= j) ? sg * (double)Y[i + j * ldy] : 0.0;
-  if (i == j && i < check_cols && (d == 0.0 || !isfinite(d))) *flag = 1;
+  // bit 0: a zero diagonal entry (rank deficient), bit 1: a non-finite one
+  // (NaN or Inf reached the sketch)
+  if (i == j && i < check_cols) {
+    if (!isfinite(d))
+      atomicOr(flag, 2);
+    else if (d == 0.0)
+      atomicOr(flag, 1);
+  }
 }
 
 // W = R^-1, one block per column j: back substitution R w = e_j in binary64,
@@ -594,7 +601,7 @@ __global__ __launch_bounds__(256) void k_trinv(const double* __restrict__ R, int
         bsh[i] = bi;
         W[i + j * ldw] = bi;
         wsq += bi * bi;
-        if (!isfinite(bi)) *flag = 1;
+        if (!isfinite(bi)) atomicOr(flag, 1);
       }
     }
     __syncthreads();
