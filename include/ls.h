@@ -18,8 +18,9 @@
  *  - `stream` is a hipStream_t (passed as void*); NULL is the default stream.
  *    All work is enqueued on it.  Entry points that iterate synchronise the
  *    stream at their convergence checks and before returning, so their
- *    outputs and statistics are valid on return.  ls_qr_r also
- *    synchronises the stream before returning (it reads back the flag that reports a zero or non-finite diagonal entry of R);
+ *    outputs and statistics are valid on return.  ls_qr_r and
+ *    ls_qr_r_noalloc also synchronise the stream before returning (they read
+ *    back the flag that reports a zero or non-finite diagonal entry of R);
  *    ls_sketch, ls_omega and ls_philox do not synchronise.
  *  - Errors are returned as negative status codes; nothing aborts or throws
  *    across the ABI.  ls_strerror(code) gives a message.
@@ -218,6 +219,22 @@ int ls_qr_r(int64_t s, int64_t ncols, ls_prec_t u_qr, double *Y, int64_t ldy,
  * working copy of Y in u_qr, the Householder scalars, two T factors and the
  * flag word).  Returns LS_OK, LS_E_ARG (bad sizes) or LS_E_UNSUPPORTED. */
 int ls_qr_workspace_size(int64_t s, int64_t ncols, ls_prec_t u_qr, size_t *bytes);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): ls_qr_r with the
+ * same arguments and results, but no workspace argument.  Its scratch (the
+ * working copy of Y, the Householder scalars and T factors, the flag word) is
+ * a static device array of LS_NOALLOC_SCRATCH_BYTES that each GPU the library
+ * runs on holds until the process ends; the call allocates nothing.  Shapes
+ * whose scratch exceeds it (256 + the QR's workspace: about
+ * s * ncols * (4 or 8) bytes) return LS_E_WORKSPACE without touching the
+ * device.  All calls on one GPU share that GPU's array, and its contents are
+ * the last call's: calls that overlap in time on one GPU (other streams or
+ * host threads) race and must be serialised by the caller.  Synchronises the
+ * stream before returning. */
+#define LS_NOALLOC_SCRATCH_BYTES (64u << 20)
+int ls_qr_r_noalloc(int64_t s, int64_t ncols, ls_prec_t u_qr, double *Y, int64_t ldy,
+                    double *R, int64_t ldr, void *stream);
 
 /* Algorithm 2's LSQR solve: LSQR on A R^-1 (right preconditioning, Paige and
  * Saunders' recurrences) in precision u, started from x (device, length n,

@@ -71,6 +71,7 @@ SIGNATURES = {
     "ls_sketch": (ctypes.c_int, [P(Problem), P(SketchOpts), ctypes.c_int, vp, i64, vp, ctypes.c_size_t, vp]),
     "ls_qr_r": (ctypes.c_int, [i64, i64, ctypes.c_int, vp, i64, vp, i64, vp, ctypes.c_size_t, vp]),
     "ls_qr_workspace_size": (ctypes.c_int, [i64, i64, ctypes.c_int, P(ctypes.c_size_t)]),
+    "ls_qr_r_noalloc": (ctypes.c_int, [i64, i64, ctypes.c_int, vp, i64, vp, i64, vp]),
     "ls_lsqr_precond": (ctypes.c_int, [P(Problem), vp, i64, ctypes.c_int, vp, P(IterOpts), P(Stats), vp,
                                        ctypes.c_size_t, vp]),
     "ls_lsir_gmres": (ctypes.c_int, [P(Problem), vp, i64, P(Precs), vp, vp, ctypes.c_int, P(IterOpts), P(Stats),

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libls.so")
-SOURCES = ["api.hip", "sketch.hip", "sparse.hip", "qr.hip", "iter.hip", "prof.hip"]
+SOURCES = ["api.hip", "sketch.hip", "sparse.hip", "qr.hip", "iter.hip", "prof.hip", "noalloc.hip"]
 ARCH = os.environ.get("LS_OFFLOAD_ARCH", "gfx950")
 
 
