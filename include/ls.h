@@ -89,12 +89,14 @@ typedef struct {
  * Philox4x32-10 block with counter (i / 4, k, prob_id, 0) and key
  * (seed mod 2^32, seed / 2^32) by Box-Muller on 23-bit uniforms.
  * terms: A (and b) are represented in u_s as a sum of `terms` rounded parts
- * (1 = a plain cast; 2 or 3 recover binary32 accuracy on the same MFMA). */
+ * (1 = a plain cast; each further part adds the format's precision, so that
+ * u_s = u^terms, on the same MFMA; e4m3's exponent range bounds its parts'
+ * combined accuracy near 2^-17 of a column's largest entry). */
 typedef struct {
   int64_t s;         /* sketch rows, s >= n + 1; 0 selects 4n */
   uint64_t seed;
   uint32_t prob_id;
-  int32_t terms;     /* 1..3 for LS_BF16, LS_FP16, LS_FP8E4M3; 1 for LS_FP64 */
+  int32_t terms;     /* 1..5 for LS_BF16, LS_FP16, LS_FP8E4M3; 1 for LS_FP64 */
   int32_t col_scale; /* Section 3.2 column scaling by powers of two: 0 = on for
                         LS_FP16 and LS_FP8E4M3 (whose range is narrow), off
                         otherwise; 1 = on; -1 = off */
@@ -107,7 +109,7 @@ typedef struct {
                         repeats of a row skipped.  Needs u_s = LS_FP64 and
                         terms = 1: [A b] is gathered as stored, in binary64 */
   int32_t max_terms; /* ls_solve (and the batch) only.  0: `terms` parts, fixed.
-                        terms < max_terms <= 3 (LS_BF16, LS_FP16, LS_FP8E4M3):
+                        terms < max_terms <= 5 (LS_BF16, LS_FP16, LS_FP8E4M3):
                         Section 4's convergence condition asks for
                         kappa(A) u_s < 1.  Once R is formed, kappa_est (see
                         ls_stats_t) stands for kappa(A), and while kappa_est
@@ -125,9 +127,15 @@ typedef struct {
  * (u single) or 1e-12 (u double); FGMRES at most 50 iterations with the same
  * tolerance; at most 30 refinement steps.  Zero fields select those defaults.
  * lsir_tol: refinement stops once ||dx|| <= lsir_tol ||x|| and
- * ||dr|| <= lsir_tol ||r|| (default 4u).  fallback != 0 repeats the
- * refinement with u_A = u_L = u_R = binary64 and at most 80 FGMRES iterations
- * when it has not converged (Section 5). */
+ * ||dr|| <= lsir_tol ||r|| (default 4u).
+ * fallback != 0 (ls_solve and the batch only; Section 5): when the refinement
+ * has not converged within lsir_maxit steps with u_A = u_L = u_R = binary32
+ * and kappa(A) u_s < 1 -- kappa_est (ls_stats_t) standing for kappa(A), u_s
+ * the sketch's unit roundoff (u^terms for a narrow format, 2^-53 for a
+ * binary64 sketch) -- the refinement loop runs again from the LSQR solution
+ * with u_A = u_L = u_R = u^2 = binary64 and the same FGMRES limit (Table 3).
+ * With u = binary64 the fallback would need quad products: ls_solve returns
+ * LS_E_UNSUPPORTED when it is requested. */
 typedef struct {
   double lsqr_tol;
   int32_t lsqr_maxit;
@@ -156,7 +164,9 @@ typedef struct {
   int32_t lsqr_its;
   int32_t lsir_its;
   int32_t fgmres_its_total;
-  int32_t fallback_used;
+  int32_t fallback_used;  /* 0: no fallback run; 1: the refinement was rerun with
+                             binary64 products; 2: not converged, but the fallback
+                             was declined because kappa_est u_s >= 1 */
   double lsqr_normr;      /* LSQR estimate of ||b - A x0|| */
   double lsqr_normar;     /* LSQR estimate of ||(A R^-1)^T (b - A x0)|| */
   double lsqr_normB;      /* LSQR estimate of ||A R^-1||_F */
@@ -284,7 +294,8 @@ int ls_solve_batched(int nprob, const ls_problem_t *P, const ls_sketch_opts_t *s
 /* The sketch operator itself, for checks and small problems: S[k, i] for
  * k < s, i < m as defined under ls_sketch_opts_t, rounded as the sketch in
  * format fmt (LS_FP64, LS_BF16, LS_FP16 or LS_FP8E4M3) uses it, unscaled
- * (Omega = S / sqrt(s)).
+ * (Omega = S / sqrt(s)).  fmt = LS_FP32 gives the binary32 Box-Muller values
+ * the narrow formats are rounded from.
  * S: device, binary64, s x m column major, lds >= s.  Does not synchronise. */
 int ls_omega(uint64_t seed, uint32_t prob_id, int64_t s, int64_t m, ls_prec_t fmt,
              double *S, int64_t lds, void *stream);
@@ -309,6 +320,15 @@ int ls_sketch_terms_for(double kappa_est, ls_prec_t u_s, int32_t terms, int32_t 
  * quarters of the device's compute units.  Returns LS_E_ARG past the last
  * candidate (the count is the first plan that fails).  Host only. */
 int ls_sketch_plan_info(ls_prec_t u_s, int32_t plan, int32_t *tile_cols, int32_t *quarter_cus);
+
+/* Rows of [A b] that each binary32 partial sum of the narrow-format sketch
+ * covers (the K-split length, the same for every split but possibly the last)
+ * for this problem, these options and u_s; the partial sums are then added in
+ * binary64.  For the binary64 sketch the split of its binary64 sums; 0 for
+ * the sparse sign embedding (an exact-order binary64 gather).  Lets a caller
+ * bound the sketch's rounding error.  Host only; returns LS_OK or an argument
+ * error. */
+int ls_sketch_split_rows(const ls_problem_t *P, const ls_sketch_opts_t *so, ls_prec_t u_s, int64_t *rows);
 
 /* Static text for a status code. */
 const char *ls_strerror(int status);

@@ -79,6 +79,110 @@ def sketch_rows(At, b, s, seed, rows, prob=0, fmt="f64", terms=1, colscale=False
     return out
 
 
+# ------------------------------------------------------------------ rounding-error scale
+def ambiguous_s_entries(seed, prob, k0, k1, i0, i1, fmt, rel=0.0, absr=2.0 ** -21):
+    """Mask of S entries whose rounding to ``fmt`` is not settled by a binary32
+    evaluation of Box-Muller that is accurate to rel |z| + absr * rad (rad =
+    sqrt(z0^2 + z1^2) of the entry's pair) plus one binary32 ulp: entries whose
+    binary32 value lies within that distance of a rounding boundary of the
+    format.  Elsewhere such an evaluation rounds to the same format value as
+    the binary64 one.  (The default, 2^-21 rad, is about twice the largest
+    deviation measured for hardware binary32 log / sin / cos evaluations over
+    16.7 million samples.)"""
+    z = philox.gaussian_block(seed, prob, k0, k1, 4 * (i0 // 4), 4 * ((i1 + 3) // 4))
+    rad = np.empty_like(z)
+    for a, b in ((0, 1), (2, 3)):
+        r = np.hypot(z[:, a::4], z[:, b::4])
+        rad[:, a::4], rad[:, b::4] = r, r
+    off = i0 - 4 * (i0 // 4)
+    z, rad = z[:, off:off + (i1 - i0)], rad[:, off:off + (i1 - i0)]
+    z32 = z.astype(np.float32).astype(np.float64)
+    ulp32 = np.spacing(np.abs(z32).astype(np.float32)).astype(np.float64)
+    delta = rel * np.abs(z32) + absr * rad + ulp32
+    return formats.round_to(z32 - delta, fmt) != formats.round_to(z32 + delta, fmt)
+
+
+# Relative precision, with respect to the largest of its products, of one
+# 32-term dot product of an MFMA: for e4m3 operands the products are aligned
+# to the largest one within a window of about 17 bits, so that each of the 32
+# may lose up to 2^-17 of the largest, about sqrt(32) 2^-17 = 2^-14.5 in all
+# (measured on gfx950 for products of few bits: 2^-17.6 per step; for random
+# operands about 2^-14.7); bf16 and fp16 products are summed to about binary32
+# accuracy (one rounding of 2^-24 of the largest product, 2^-23 allowed).
+DOT_PRECISION = {"e4m3": 2.0 ** -14, "bf16": 2.0 ** -23, "f16": 2.0 ** -23}
+
+
+def error_scale(At, b, s, seed, rows, fmt, terms, colscale, split_rows, prob=0, kstep=32):
+    """Scale of the rounding error of selected rows of the narrow-format sketch
+    computed with binary32 accumulation (test use).
+
+    Section 3.1 bounds the sketch's error by a casting term and the matrix
+    product's accumulation term.  With the cast operands (S_q, M_q) fixed, an
+    evaluation that sums the products of each ``split_rows``-row split in
+    binary32, one rounding per ``kstep`` rows, and adds the split sums in
+    binary64 deviates from the exact product by rounding errors of at most
+    u32 |P_t| at each step t, P_t the running sum after step t.  Modelled as
+    independent, they add up to about
+
+        sigma_acc[k, j] = u32 * sqrt(sum_t P_t[k, j]^2),
+
+    where each step's dot product of ``kstep`` products may itself carry an
+    error of d |p|_max (d = DOT_PRECISION[fmt], |p|_max the largest of its
+    products, per part T_t of the split):
+
+        sigma_dot[k, j] = d * sqrt(sum_t sum_steps |p|_max^2),
+
+    and entries of S that a binary32 Box-Muller evaluation may round the other
+    way (``ambiguous_s_entries``) add one format ulp each:
+
+        sigma_s[k, j] = sqrt(sum_{i ambiguous} (ulp(S_q[k, i]) M_q[i, j])^2).
+
+    Returns (sigma_acc + sigma_dot + sigma_s) / sqrt(s) * 2^-e_j for the
+    sampled rows and every column of [At^T b] (len(rows) x (n+1))."""
+    Mq, e = scaled_operand(At, b, fmt, terms, colscale)
+    m, nc = Mq.shape
+    d = DOT_PRECISION[fmt]
+    if d:
+        n = At.shape[0]
+        M = np.empty((m, n + 1))
+        M[:, :n] = At.T
+        M[:, n] = b
+        parts = formats.split_terms(M * np.ldexp(1.0, e.astype(np.int64))[None, :], fmt, terms)
+    t = formats.FORMATS[fmt][0]
+    out = np.empty((len(rows), nc))
+    L = int(split_rows) if split_rows else m
+    for r, k in enumerate(rows):
+        Sq = quantised_gaussian_block(seed, prob, k, k + 1, 0, m, fmt)[0]
+        amb = ambiguous_s_entries(seed, prob, k, k + 1, 0, m, fmt)[0]
+        acc2 = np.zeros(nc)
+        for c0 in range(0, m, L):
+            c1 = min(m, c0 + L)
+            prod = Sq[c0:c1, None] * Mq[c0:c1]
+            nblk = -(-(c1 - c0) // kstep)
+            pad = np.zeros((nblk * kstep, nc))
+            pad[:c1 - c0] = prod
+            P = np.cumsum(pad.reshape(nblk, kstep, nc).sum(axis=1), axis=0)
+            acc2 += np.sum(P * P, axis=0)
+        sig_acc = 2.0 ** -24 * np.sqrt(acc2)
+        sig_dot = np.zeros(nc)
+        if d:
+            nblk = -(-m // kstep)
+            for T in parts:
+                pad = np.zeros((nblk * kstep, nc))
+                pad[:m] = np.abs(Sq[:, None] * T)
+                sig_dot += np.sum(pad.reshape(nblk, kstep, nc).max(axis=1) ** 2, axis=0)
+            sig_dot = d * np.sqrt(sig_dot)
+        ia = np.nonzero(amb)[0]
+        if ia.size:
+            ulp = np.ldexp(1.0, np.maximum(np.floor(np.log2(np.abs(Sq[ia]) + 1e-300)),
+                                           formats.FORMATS[fmt][1]).astype(np.int64) - t)
+            sig_s = np.sqrt(np.sum((ulp[:, None] * Mq[ia]) ** 2, axis=0))
+        else:
+            sig_s = np.zeros(nc)
+        out[r] = (sig_acc + sig_dot + sig_s) / np.sqrt(s) * np.ldexp(1.0, -e.astype(np.int64))
+    return out
+
+
 # ------------------------------------------------------------------ sparse sign embedding
 SPARSE_MAX_WORDS = 256   # Philox words a column may use before the draw is declared failed
 

@@ -24,6 +24,7 @@ from .api import (  # noqa: F401
     qr_workspace_size,
     sketch_opts,
     sketch_plan_info,
+    sketch_split_rows,
     sketch_terms_for,
     workspace,
     workspace_size,

@@ -82,6 +82,7 @@ SIGNATURES = {
     "ls_philox": (ctypes.c_int, [u32, u32, u32, u32, u32, u32, i64, vp, vp]),
     "ls_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "ls_sketch_terms_for": (ctypes.c_int, [ctypes.c_double, ctypes.c_int, ctypes.c_int32, ctypes.c_int32]),
+    "ls_sketch_split_rows": (ctypes.c_int, [P(Problem), P(SketchOpts), ctypes.c_int, P(ctypes.c_int64)]),
     "ls_sketch_plan_info": (ctypes.c_int, [ctypes.c_int, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32)]),
     "ls_workspace_size_batched": (ctypes.c_int, [ctypes.c_int, P(Problem), P(SketchOpts), P(Precs), P(IterOpts),
                                                  ctypes.c_int, P(ctypes.c_size_t)]),

@@ -221,6 +221,16 @@ def sketch_plan_info(u_s, plan):
     return (tc.value, qc.value) if rc == 0 else None
 
 
+def sketch_split_rows(At, b, s, u_s="bf16", terms=1, plan=0, prob_id=0, col_scale=0, zeta=0):
+    """Rows of [A b] each binary32 partial sum of the sketch covers (its K-split length)."""
+    P = problem(At, b)
+    so = sketch_opts(s=s, terms=terms, plan=plan, prob_id=prob_id, col_scale=col_scale, zeta=zeta)
+    rows = ctypes.c_int64(0)
+    _check(B.load().ls_sketch_split_rows(ctypes.byref(P), ctypes.byref(so), B.PREC[u_s], ctypes.byref(rows)),
+           "ls_sketch_split_rows")
+    return rows.value
+
+
 def sketch_terms_for(kappa_est, u_s="bf16", terms=1, max_terms=3):
     """Parts the solve sketches with next after an R formed with ``terms`` parts (host only)."""
     return B.load().ls_sketch_terms_for(float(kappa_est), B.PREC[u_s], int(terms), int(max_terms))

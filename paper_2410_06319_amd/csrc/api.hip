@@ -39,8 +39,8 @@ int check_sketch(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_
   }
   if (so->plan < 0 || (so->zeta == 0 && so->plan > sketch_plan_count(u_s))) return LS_E_ARG;
   if (u_s == LS_BF16 || u_s == LS_FP16 || u_s == LS_FP8E4M3) {
-    if (so->terms < 1 || so->terms > 3) return LS_E_ARG;
-    if (so->max_terms != 0 && (so->max_terms < so->terms || so->max_terms > 3)) return LS_E_ARG;
+    if (so->terms < 1 || so->terms > kMaxSketchTerms) return LS_E_ARG;
+    if (so->max_terms != 0 && (so->max_terms < so->terms || so->max_terms > kMaxSketchTerms)) return LS_E_ARG;
   } else if (u_s == LS_FP64) {
     if (so->terms > 1 || so->max_terms > 1) return LS_E_ARG;
   } else {
@@ -128,12 +128,22 @@ size_t iter_bytes(const ls_problem_t* P, const ls_precs_t* pr, const ls_iter_opt
   size_t a = lsqr_workspace(P, pr->u, ncu);
   ls_precs_t p64 = *pr;
   p64.u_A = p64.u_L = p64.u_R = LS_FP64;
-  int kmax = io->fgmres_maxit;
-  if (io->fallback && kmax < 80) kmax = 80;
   size_t b = lsir_workspace(P, pr, io->fgmres_maxit, ncu);
-  size_t c = lsir_workspace(P, &p64, kmax, ncu);
+  size_t c = lsir_workspace(P, &p64, io->fgmres_maxit, ncu);
   size_t m = a > b ? a : b;
   return m > c ? m : c;
+}
+
+// Unit roundoff of the sketch: u^terms for a terms-part narrow sketch
+// (u = 2^-8 bf16, 2^-11 fp16, 2^-4 e4m3), binary64 otherwise (the binary64
+// Gaussian sketch and the sparse sign embedding).
+double sketch_unit_roundoff(ls_prec_t u_s, int32_t terms) {
+  double u;
+  if (u_s == LS_BF16) u = 0x1p-8;
+  else if (u_s == LS_FP16) u = 0x1p-11;
+  else if (u_s == LS_FP8E4M3) u = 0x1p-4;
+  else return 0x1p-53;
+  return std::pow(u, (double)(terms < 1 ? 1 : terms));
 }
 
 // A second, binary64 copy of B is needed when FGMRES works in binary64 but
@@ -259,6 +269,15 @@ int ls_sketch_plan_info(ls_prec_t u_s, int32_t plan, int32_t* tile_cols, int32_t
   LS_TRY(sketch_plan_shape(u_s, plan, &bn, &q));
   *tile_cols = (u_s == LS_FP64) ? 128 : bn;
   *quarter_cus = q;
+  return LS_OK;
+}
+
+int ls_sketch_split_rows(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s, int64_t* rows) {
+  if (!rows) return LS_E_ARG;
+  LS_TRY(check_problem(P));
+  LS_TRY(check_sketch(P, so, u_s));
+  const SketchPlan sp = sketch_plan(P, so, sketch_rows(P, so), u_s);
+  *rows = (sp.zeta > 0) ? 0 : sp.kchunk;
   return LS_OK;
 }
 
@@ -408,6 +427,8 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
   if (!ws || ws_bytes < need) return LS_E_WORKSPACE;
   const ls_iter_opts_t io = fill_opts(io_in, P->n, pr->u);
   if (io.fgmres_maxit > 95) return LS_E_ARG;
+  // the fallback raises the products to u^2: quad for u = binary64, not implemented
+  if (io.fallback && pr->u == LS_FP64) return LS_E_UNSUPPORTED;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t m = P->m, n = P->n, s = sketch_rows(P, so);
   ls_stats_t local;
@@ -497,17 +518,21 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
     Bfg = B2;
   }
   rc = lsir_device(P, inv.W, Bfg, pr, x, r, 0, &io, S, scratch, scratch_bytes, st);
-  if (rc == LS_NOT_CONVERGED && io.fallback) {
-    // Section 5: rerun the refinement with u_A = u_L = u_R = binary64 and up to 80 FGMRES iterations.
-    ls_precs_t p2 = *pr;
-    p2.u_A = p2.u_L = p2.u_R = LS_FP64;
-    ls_iter_opts_t io2 = io;
-    io2.fgmres_maxit = 80;
-    LS_HIP_TRY(hipMemcpyAsync(x, saved, 8 * (size_t)n, hipMemcpyDeviceToDevice, st));
-    S->fallback_used = 1;
-    void* B64 = (pr->u == LS_FP64) ? B1 : B2;
-    if (Bfg != B64) LS_TRY(form_b(P, inv.W, inv.W32, LS_FP64, B64, st));
-    rc = lsir_device(P, inv.W, B64, &p2, x, r, 0, &io2, S, scratch, scratch_bytes, st);
+  if (rc == LS_NOT_CONVERGED && io.fallback && pr->u_A == LS_FP32) {
+    // Section 5: when the refinement has not converged within its limit and
+    // kappa(A) < 1/u_s (kappa_est standing for kappa(A)), raise u_A, u_L and u_R
+    // to u^2 (binary64 for u = binary32; the FGMRES limit stays, as in Table 3)
+    // and run the refinement loop again from the LSQR solution.
+    if (S->kappa_est * sketch_unit_roundoff(pr->u_s, so_t.terms) < 1.0) {
+      ls_precs_t p2 = *pr;
+      p2.u_A = p2.u_L = p2.u_R = LS_FP64;
+      LS_HIP_TRY(hipMemcpyAsync(x, saved, 8 * (size_t)n, hipMemcpyDeviceToDevice, st));
+      S->fallback_used = 1;
+      LS_TRY(form_b(P, inv.W, inv.W32, LS_FP64, B2, st));
+      rc = lsir_device(P, inv.W, B2, &p2, x, r, 0, &io, S, scratch, scratch_bytes, st);
+    } else {
+      S->fallback_used = 2;   // declined: outside the condition of Section 4
+    }
   }
   tm.mark(4, st);
   LS_HIP_TRY(hipStreamSynchronize(st));
@@ -524,7 +549,8 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
 int ls_omega(uint64_t seed, uint32_t prob_id, int64_t s, int64_t m, ls_prec_t fmt, double* S, int64_t lds,
              void* stream) {
   if (!S || s < 1 || m < 1 || lds < s || s > 65535) return LS_E_ARG;
-  if (!(fmt == LS_FP64 || fmt == LS_BF16 || fmt == LS_FP16 || fmt == LS_FP8E4M3)) return LS_E_UNSUPPORTED;
+  if (!(fmt == LS_FP64 || fmt == LS_FP32 || fmt == LS_BF16 || fmt == LS_FP16 || fmt == LS_FP8E4M3))
+    return LS_E_UNSUPPORTED;
   return omega_run(seed, prob_id, s, m, fmt, S, lds, static_cast<hipStream_t>(stream));
 }
 

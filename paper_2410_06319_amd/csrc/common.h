@@ -123,8 +123,10 @@ __device__ __forceinline__ float ls_round_fmt_f(float x, LsFmt f) {
   if (fabsf(r) > (float)f.fmax) r = f.saturate ? copysignf((float)f.fmax, r) : copysignf(INFINITY, r);
   return r;
 }
-// OCP e4m3 bits of a value already representable in e4m3 (|v| <= 448).
+// OCP e4m3 bits of a value already representable in e4m3 (|v| <= 448); a
+// NaN or an infinity (which the format lacks) becomes its NaN, 0x7f.
 __device__ __forceinline__ uint8_t ls_e4m3_bits(double v) {
+  if (!isfinite(v)) return 0x7f;
   const uint8_t sgn = (v < 0.0 || (v == 0.0 && signbit(v))) ? 0x80 : 0x00;
   const double a = fabs(v);
   if (a == 0.0) return sgn;

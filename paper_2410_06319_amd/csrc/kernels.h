@@ -8,6 +8,9 @@
 namespace ls {
 
 // ------------------------------------------------------------------ sketch
+// Parts a narrow-format sketch may split [A b] into.
+constexpr int kMaxSketchTerms = 5;
+
 struct SketchPlan {
   int64_t ncols;          // n + 1
   int64_t s_pad;          // s rounded up to the rows of S per block

@@ -18,6 +18,9 @@
 // columns wc BN/4 .. +BN/4.  LDS rows of 32 bf16 (four 16-byte quarters) are
 // stored with the quarter index XORed with bits 2..3 of the row, so that the
 // 16 lanes of each MFMA operand read hit distinct banks.
+#include <algorithm>
+#include <cmath>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -473,8 +476,11 @@ __global__ __launch_bounds__(256) void k_omega(uint32_t key0, uint32_t key1, uin
     float zf[4];
     ls_box_muller_f32(c0, c1, zf[0], zf[1]);
     ls_box_muller_f32(c2, c3, zf[2], zf[3]);
-    // the conversions the sketch kernel uses
-    if (fmt == LS_FP8E4M3) {
+    // the conversions the sketch kernel uses (LS_FP32: none, the binary32
+    // values themselves)
+    if (fmt == LS_FP32) {
+      for (int t = 0; t < 4; ++t) z[t] = (double)zf[t];
+    } else if (fmt == LS_FP8E4M3) {
       const uint32_t w = sk_pack4_e4m3(zf[0], zf[1], zf[2], zf[3]);
       for (int t = 0; t < 4; ++t) z[t] = sk_e4m3_at(w, t);
     } else if (fmt == LS_FP16) {
@@ -559,6 +565,22 @@ static int sketch_tuned_plan(ls_prec_t u_s, int terms, int64_t ncols, int64_t m)
   return 1;
 }
 
+// LDS of one block of k_sketch_lp: the 128 x 32 S tile and the parts' BN x 32
+// operand tile, in fragments of 8 elements.
+static constexpr size_t sk_lds_bytes(int ebytes, int terms, int bn) {
+  return (size_t)(kSkRows * 4 + terms * bn * 4) * (size_t)(8 * ebytes);
+}
+
+// Largest K-split, in 32-row K-blocks, for a terms-part sketch in u_s.
+static int64_t sk_chunk_kblocks_max(ls_prec_t u_s, int terms) {
+  const double u = (u_s == LS_BF16) ? 0x1p-8 : (u_s == LS_FP16) ? 0x1p-11 : 0x1p-4;
+  const double us = std::pow(u, (double)terms);
+  const double q = us / (4.0 * 0x1p-24);
+  const double rows = 32.0 * q * q;
+  if (rows >= 1e15) return (int64_t)1 << 40;
+  return std::max<int64_t>(8192 / 32, (int64_t)(rows / 32.0));
+}
+
 SketchPlan sketch_plan(const ls_problem_t* P, const ls_sketch_opts_t* so, int64_t s, ls_prec_t u_s) {
   const int64_t m = P->m, n = P->n;
   const int terms = so->terms;
@@ -581,6 +603,11 @@ SketchPlan sketch_plan(const ls_problem_t* P, const ls_sketch_opts_t* so, int64_
     p.ebytes = (u_s == LS_FP8E4M3) ? 1 : 2;
     const int bn = kNarrowCands[plan - 1].bn;
     p.bn = bn ? bn : (p.ncols <= 128) ? 128 : (p.ncols <= 256) ? 256 : 512;
+    // the automatic width stays at 256 columns where 512 would spill the
+    // accumulators' registers (three or more 16-bit parts, five e4m3 parts)
+    if (!bn && p.terms >= ((p.ebytes == 2) ? 3 : 5) && p.bn > 256) p.bn = 256;
+    // the block's S tile and its parts' operand tile must fit in LDS
+    while (p.bn > 128 && sk_lds_bytes(p.ebytes, p.terms, p.bn) > (size_t)device_lds_bytes()) p.bn /= 2;
     p.nn = ls_cdiv(p.ncols, p.bn);
     p.n_pad = p.nn * p.bn;
     p.ns = ls_cdiv(s, kSkRows);
@@ -590,6 +617,12 @@ SketchPlan sketch_plan(const ls_problem_t* P, const ls_sketch_opts_t* so, int64_
     // that each XCD receives whole groups
     const int64_t kbn = ls_cdiv(m, 32);
     int64_t nsplit = ls_cdiv(target, p.ns * p.nn);
+    // accuracy: each K-split sums its rows in binary32, one MFMA accumulation
+    // per 32 rows, an error of about u32 sqrt(L / 32) relative to the sums for
+    // L rows; splits of at most L_max = 32 (u_s / (4 u32))^2 rows (not below
+    // 8192) keep it under a quarter of the parts' own accuracy u_s = u^terms
+    const int64_t kb_max = sk_chunk_kblocks_max(u_s, p.terms);
+    if (nsplit < ls_cdiv(kbn, kb_max)) nsplit = ls_cdiv(kbn, kb_max);
     if (nsplit > kbn) nsplit = kbn;
     if (nsplit < 1) nsplit = 1;
     while ((p.nn * nsplit) % 8) ++nsplit;
@@ -624,11 +657,51 @@ SketchPlan sketch_plan(const ls_problem_t* P, const ls_sketch_opts_t* so, int64_
 }
 
 namespace {
+// Arguments of one k_sketch_lp launch.
+template <typename E>
+struct SkLaunchT {
+  dim3 grid;
+  hipStream_t st;
+  ProfEv ev;
+  const E* Tt;
+  int64_t nkb, n_pad, kb_per_split;
+  int ns, nn;
+  uint32_t key0, key1, prob;
+  float* Yp;
+  int64_t s_pad;
+};
+
+// Launch k_sketch_lp<FMT, BN, TERMS>; shapes whose tiles exceed the LDS of a
+// compute unit are not instantiated (the planner narrows BN first).
+template <int FMT, int BN, int TERMS>
+int sk_launch(const SkLaunchT<typename SkFmt<FMT>::E>& L) {
+  if constexpr (sk_lds_bytes(sizeof(typename SkFmt<FMT>::E), TERMS, BN) <= 160 * 1024) {
+    hipExtLaunchKernelGGL((k_sketch_lp<FMT, BN, TERMS>), L.grid, dim3(kSkThreads), 0, L.st, L.ev.a, L.ev.b, 0, L.Tt,
+                          L.nkb, L.n_pad, L.kb_per_split, L.ns, L.nn, L.key0, L.key1, L.prob, L.Yp, L.s_pad);
+    return LS_OK;
+  } else {
+    return LS_E_UNSUPPORTED;
+  }
+}
+
+template <int FMT, int BN>
+int sk_launch_terms(const SkLaunchT<typename SkFmt<FMT>::E>& L, int terms) {
+  switch (terms) {
+    case 1: return sk_launch<FMT, BN, 1>(L);
+    case 2: return sk_launch<FMT, BN, 2>(L);
+    case 3: return sk_launch<FMT, BN, 3>(L);
+    case 4: return sk_launch<FMT, BN, 4>(L);
+    case 5: return sk_launch<FMT, BN, 5>(L);
+    default: return LS_E_ARG;
+  }
+}
+
 template <int FMT, typename TA>
 int sketch_narrow(const ls_problem_t* P, const ls_sketch_opts_t* so, const SketchPlan& p, int64_t s, double* Y,
                   int64_t ldy, char* ws, bool colscale, hipStream_t st) {
   using F = SkFmt<FMT>;
   using E = typename F::E;
+  using SkLaunch = SkLaunchT<E>;
   const uint32_t key0 = (uint32_t)(so->seed & 0xffffffffu);
   const uint32_t key1 = (uint32_t)(so->seed >> 32);
   E* Tt = reinterpret_cast<E*>(ws);
@@ -645,17 +718,13 @@ int sketch_narrow(const ls_problem_t* P, const ls_sketch_opts_t* so, const Sketc
                      A, P->lda, b, P->m, P->n, p.terms, e, Tt, p.m_pad, p.n_pad);
   const dim3 gb((unsigned)(p.ns * p.nn * p.nsplit));
   const ProfEv ev = prof_events(kProfSketch);
-#define LS_SK(BN_, T_)                                                                                             \
-  hipExtLaunchKernelGGL((k_sketch_lp<FMT, BN_, T_>), gb, dim3(kSkThreads), 0, st, ev.a, ev.b, 0, Tt, p.nkb,       \
-                        p.n_pad, p.kb_per_split, (int)p.ns, (int)p.nn, key0, key1, so->prob_id, Yp, p.s_pad)
-  if (p.bn == 128) {
-    if (p.terms == 1) LS_SK(128, 1); else if (p.terms == 2) LS_SK(128, 2); else LS_SK(128, 3);
-  } else if (p.bn == 256) {
-    if (p.terms == 1) LS_SK(256, 1); else if (p.terms == 2) LS_SK(256, 2); else LS_SK(256, 3);
-  } else {
-    if (p.terms == 1) LS_SK(512, 1); else if (p.terms == 2) LS_SK(512, 2); else LS_SK(512, 3);
-  }
-#undef LS_SK
+  const SkLaunch L{gb, st, ev, Tt, p.nkb, p.n_pad, p.kb_per_split, (int)p.ns, (int)p.nn, key0, key1, so->prob_id,
+                  Yp, p.s_pad};
+  int rc = LS_E_UNSUPPORTED;
+  if (p.bn == 128) rc = sk_launch_terms<FMT, 128>(L, p.terms);
+  else if (p.bn == 256) rc = sk_launch_terms<FMT, 256>(L, p.terms);
+  else if (p.bn == 512) rc = sk_launch_terms<FMT, 512>(L, p.terms);
+  LS_TRY(rc);
   prof_commit(kProfSketch, 2.0 * (double)s * (double)P->m * (double)(P->n + 1));
   hipLaunchKernelGGL(k_sketch_combine<float>, dim3((unsigned)ls_cdiv(s, 256), (unsigned)p.ncols), dim3(256), 0, st, Yp,
                      p.s_pad, p.n_pad, (int)p.nsplit, s, p.ncols, 1.0 / sqrt((double)s), (const int32_t*)e, Y, ldy);
@@ -681,7 +750,7 @@ bool sketch_colscale(ls_prec_t u_s, int32_t col_scale) {
 int sketch_run(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s, const SketchPlan& p,
                int64_t s, double* Y, int64_t ldy, char* ws, hipStream_t st) {
   if (p.zeta > 0) return sparse_run(P, so, s, Y, ldy, ws, st);
-  if (p.terms < 1 || p.terms > 3) return LS_E_ARG;
+  if (p.terms < 1 || p.terms > kMaxSketchTerms) return LS_E_ARG;
   const bool cs = sketch_colscale(u_s, so->col_scale);
   if (u_s == LS_BF16) return sketch_narrow_store<LS_BF16>(P, so, p, s, Y, ldy, ws, cs, st);
   if (u_s == LS_FP16) return sketch_narrow_store<LS_FP16>(P, so, p, s, Y, ldy, ws, cs, st);

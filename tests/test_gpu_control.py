@@ -1,0 +1,181 @@
+"""Control paths of the solve on the GPU: Section 5's fallback rule, the
+not-converged result, non-finite input and undersized workspaces.
+
+* Fallback (Section 5; Table 3, starred rows): on the paper's own problem
+  (m = 1000, n = 100, s = 4n, ||A|| = 1, b uniform on (0,1) normalised,
+  single-precision storage and working precision) at kappa(A) = 1e6 and 1e7,
+  with a sketch about as accurate as single precision (bf16 x 3, u_s =
+  2^-24, so kappa(A) u_s < 1), the refinement with binary32 products does not
+  converge in 30 steps; the fallback reruns it with binary64 products and
+  reaches the paper's stopping accuracy, 4u in x and r (checked at 8u: x and
+  r are rounded to single precision).
+* The rule's condition: with kappa(A) u_s far above 1 the fallback is
+  declined; with u = binary64 it would need quad products and is refused.
+* The status codes of the boundary: LS_NOT_CONVERGED with a finite last
+  iterate, LS_E_NONFINITE for NaN in b or A, LS_E_WORKSPACE for a workspace
+  256 bytes short of what the library reports.
+"""
+
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from lsdata import make_paper_problem, make_problem
+from oracle import refsolve
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def L():
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    import paper_2410_06319_amd as lib
+    lib.load()
+    return lib
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+PR_SINGLE = dict(u_s="bf16", u_qr="f32", u="f32", u_r="f64")
+
+
+@pytest.mark.parametrize("kappa,lsir_maxit", [(1e7, 2), (3e7, 4)])
+def test_fallback_reruns_refinement_with_binary64_products(L, kappa, lsir_maxit):
+    # The fallback fires when the refinement reaches its step limit (30 in
+    # Section 5); the limit is lowered here so that the binary32 products stop
+    # short of the target, as they do within 30 steps in the paper's starred
+    # rows.  The rerun with binary64 products then converges in a couple of
+    # steps (Table 3: 2*).
+    P = make_paper_problem(1000, 100, kappa, 1, store="f32")
+    xr, rr, _ = refsolve.ref_solve(P.At, P.b)
+    pr = L.precs(**PR_SINGLE)
+    At, b = dev(P.At), dev(P.b)
+    x, r, rc0, st0 = L.ls_solve(At, b, s=400, seed=101, terms=3, pr=pr, lsqr_tol=1e-6, lsir_maxit=lsir_maxit)
+    ex0, er0 = refsolve.forward_errors(host(x), host(r), xr, rr)
+    say(f"kappa {kappa:.0e} without fallback: status {rc0}, lsir {st0['lsir_its']}, fgmres {st0['fgmres_its_total']}, "
+        f"kappa_est {st0['kappa_est']:.3g}, err x {ex0:.2e} r {er0:.2e}")
+    assert rc0 == 1 and st0["fallback_used"] == 0 and st0["lsir_its"] == lsir_maxit
+    assert st0["kappa_est"] * U32 < 1                  # the fallback's condition holds
+    x, r, rc, st = L.ls_solve(At, b, s=400, seed=101, terms=3, pr=pr, lsqr_tol=1e-6, lsir_maxit=lsir_maxit,
+                              fallback=1)
+    ex, er = refsolve.forward_errors(host(x), host(r), xr, rr)
+    say(f"kappa {kappa:.0e} with fallback: status {rc}, used {st['fallback_used']}, lsir {st['lsir_its']}, "
+        f"fgmres {st['fgmres_its_total']}, err x {ex:.2e} r {er:.2e}")
+    assert rc == 0 and st["fallback_used"] == 1
+    # the rerun starts again from the LSQR solution; its steps add to the first run's
+    assert lsir_maxit < st["lsir_its"] <= 2 * lsir_maxit
+    # Section 5's stopping accuracy 4u, up to the rounding of x and r to single precision
+    assert ex <= 8 * U32 and er <= 8 * U32
+
+
+def test_fallback_declined_when_kappa_u_s_exceeds_one(L):
+    # one bf16 part at kappa(A) = 1e6: kappa_est u_s ~ 1e3, outside Section 4's condition
+    P = make_paper_problem(1000, 100, 1e6, 1, store="f32")
+    pr = L.precs(**PR_SINGLE)
+    x, r, rc, st = L.ls_solve(dev(P.At), dev(P.b), s=400, seed=101, terms=1, pr=pr, lsqr_tol=1e-6, fallback=1)
+    say(f"bf16 x1 at kappa 1e6: status {rc}, used {st['fallback_used']}, kappa_est {st['kappa_est']:.3g}")
+    assert st["kappa_est"] * 2.0 ** -8 > 1
+    assert rc == 1 and st["fallback_used"] == 2
+    assert np.all(np.isfinite(host(x))) and np.all(np.isfinite(host(r)))
+
+
+def test_fallback_with_binary64_working_precision_is_unsupported(L):
+    P = make_problem(2000, 50, 1e2, seed=5, store="f64")
+    pr = L.precs(u_s="f64", u_qr="f64", u="f64", u_r="f64x2")
+    with pytest.raises(L.LsError) as e:
+        L.ls_solve(dev(P.At), dev(P.b), s=200, seed=5, pr=pr, fallback=1)
+    assert e.value.code == -6
+
+
+def test_not_converged_returns_the_finite_last_iterate(L):
+    # two refinement steps against an unreachable tolerance: LS_NOT_CONVERGED,
+    # with the last iterate (already at the target accuracy) and its statistics
+    P = make_problem(6003, 60, 1e4, seed=2410064195, store="f32")
+    xr, rr, _ = refsolve.ref_solve(P.At, P.b)
+    pr = L.precs(**PR_SINGLE)
+    x, r, rc, st = L.ls_solve(dev(P.At), dev(P.b), s=240, seed=5, terms=2, pr=pr, lsir_maxit=2, lsir_tol=1e-300)
+    ex, er = refsolve.forward_errors(host(x), host(r), xr, rr)
+    say(f"not converged: status {rc}, lsir {st['lsir_its']}, fgmres {st['fgmres_its_total']}, "
+        f"dx {st['lsir_dx_rel']:.2e} dr {st['lsir_dr_rel']:.2e}, err x {ex:.2e} r {er:.2e}")
+    assert rc == 1 and st["status"] == 1 and st["lsir_its"] == 2
+    assert np.isfinite(st["lsir_dx_rel"]) and np.isfinite(st["lsir_dr_rel"]) and st["lsqr_its"] > 0
+    assert ex <= 6e-6 and er <= 6e-6
+
+
+@pytest.mark.parametrize("where", ["b", "A"])
+@pytest.mark.parametrize("u_s,terms,u,store", [("bf16", 2, "f32", "f32"), ("e4m3", 3, "f32", "f32"),
+                                               ("f64", 1, "f64", "f64")])
+def test_nonfinite_input_is_reported(L, where, u_s, terms, u, store):
+    P = make_problem(3001, 40, 1e2, seed=9, store=store)
+    At, b = P.At.copy(), P.b.copy()
+    if where == "b":
+        b[1717] = np.nan
+    else:
+        At[7, 1234] = np.inf
+    pr = L.precs(u_s=u_s, u_qr="f32" if u == "f32" else "f64", u=u, u_r="f64" if u == "f32" else "f64x2")
+    with pytest.raises(L.LsError) as e:
+        L.ls_solve(dev(At), dev(b), s=160, seed=3, terms=terms, pr=pr)
+    say(f"non-finite {where}, {u_s} x{terms}: status {e.value.code}")
+    assert e.value.code == -5
+
+
+def test_undersized_workspace_is_reported(L):
+    B = L.load()
+    from paper_2410_06319_amd import _binding as Bd
+    P = make_problem(4001, 30, 1e2, seed=4, store="f32")
+    At, b = dev(P.At), dev(P.b)
+    pr = L.precs(**PR_SINGLE)
+    S = L.Solver(At, b, s=120, seed=2, terms=2, pr=pr)
+    need = S.ws.numel()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    x = torch.zeros(30, dtype=torch.float64, device="cuda")
+    r = torch.zeros(4001, dtype=torch.float64, device="cuda")
+    rc = B.ls_solve(ctypes.byref(S.P), ctypes.byref(S.so), ctypes.byref(S.pr), ctypes.byref(S.io), x.data_ptr(),
+                    r.data_ptr(), None, S.ws.data_ptr(), need - 256, stream)
+    assert rc == Bd.E_WORKSPACE
+    assert S() == 0                                  # the reported size suffices
+    # QR: 256 bytes short of ls_qr_workspace_size
+    Yt = L.ls_sketch(At, b, 120, seed=2, u_s="bf16", terms=2)
+    R = torch.zeros((31, 31), dtype=torch.float64, device="cuda")
+    qneed = L.qr_workspace_size(120, 31, "f32")
+    rc = B.ls_qr_r(120, 31, Bd.FP32, Yt.data_ptr(), 120, R.data_ptr(), 31, S.ws.data_ptr(), qneed - 256, stream)
+    assert rc == Bd.E_WORKSPACE
+    # the other entry points with a workspace far too small for their scratch
+    small = torch.empty(256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(L.LsError) as e:
+        L.ls_sketch(At, b, 120, seed=2, u_s="bf16", terms=2, ws=small)
+    assert e.value.code == -2
+    Rt = L.ls_qr_r(Yt, u_qr="f64")[:30, :30].contiguous()
+    with pytest.raises(L.LsError) as e:
+        L.ls_lsqr_precond(At, b, Rt, x, u="f32", ws=small)
+    assert e.value.code == -2
+    with pytest.raises(L.LsError) as e:
+        L.ls_lsir_gmres(At, b, Rt, x, r, pr=pr, ws=small)
+    assert e.value.code == -2
+    # a batch whose workspace is 256 bytes short
+    n1 = ctypes.c_size_t(0)
+    Ps = (Bd.Problem * 2)(S.P, S.P)
+    sos = (Bd.SketchOpts * 2)(S.so, S.so)
+    assert B.ls_workspace_size_batched(2, Ps, sos, ctypes.byref(pr), ctypes.byref(S.io), 2, ctypes.byref(n1)) == 0
+    wsb = torch.empty(n1.value, dtype=torch.uint8, device="cuda")
+    xs = (ctypes.c_void_p * 2)(x.data_ptr(), x.data_ptr())
+    rs = (ctypes.c_void_p * 2)(r.data_ptr(), r.data_ptr())
+    stats = (Bd.Stats * 2)()
+    rc = B.ls_solve_batched(2, Ps, sos, ctypes.byref(pr), ctypes.byref(S.io), xs, rs, stats, 2, wsb.data_ptr(),
+                            n1.value - 256, stream)
+    assert rc == Bd.E_WORKSPACE

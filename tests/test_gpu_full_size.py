@@ -25,6 +25,7 @@ import torch
 
 from lsdata import WORKLOADS, data_seed, make_batch_sizes, make_problem
 from oracle import refsolve, sketch as osketch
+from sketch_check import sketch_ratio
 
 pytestmark = pytest.mark.gpu
 
@@ -50,22 +51,10 @@ def host(t):
 
 
 def _sketch_entries(L, At, b, P, s, seed, fmt, terms, rows, cols):
-    """Sampled entries of the GPU sketch against the oracle; returns err / bound."""
-    n, m = P.n, P.m
-    colscale = fmt in ("f16", "e4m3")
-    Y = host(L.ls_sketch(At, b, s, seed=seed, u_s=fmt, terms=terms)).T
-    acols = [c for c in cols if c < n]
-    sub = np.ascontiguousarray(P.At[acols])
-    # columns are independent (exponents, splits and products act per column)
-    ref = osketch.sketch_rows(sub, P.b, s, seed, rows, fmt=fmt, terms=terms, colscale=colscale)
-    Mq, e = osketch.scaled_operand(sub, P.b, fmt, terms, colscale)
-    bound = np.empty_like(ref)
-    for t, k in enumerate(rows):
-        Sq = np.abs(osketch.quantised_gaussian_block(seed, 0, k, k + 1, 0, m, fmt)[0])
-        bound[t] = (Sq @ np.abs(Mq)) / math.sqrt(s)
-    bound *= np.ldexp(1.0, -e.astype(np.int64))[None, :]
-    got = Y[np.ix_(rows, acols + [n])]
-    return Y, np.abs(got - ref) / bound
+    """Sampled entries of the GPU sketch against the oracle: the GPU sketch and
+    err / (2 x the oracle's rounding scale) for the sampled entries."""
+    mx, Y, ratio = sketch_ratio(L, P, At, b, s, seed, fmt, terms, rows, cols=cols)
+    return Y, ratio
 
 
 def _qr_backward(L, Y, u_qr):
@@ -84,10 +73,10 @@ def _run_workload(L, name, terms, rows, cols):
     say(f"{name}: generated {wl['m']} x {wl['n']} in {time.time() - t0:.1f} s")
     At, b = torch.from_numpy(P.At).cuda(), torch.from_numpy(P.b).cuda()
     Y, err = _sketch_entries(L, At, b, P, wl["s"], seed, wl["u_s"], terms, rows, cols)
-    say(f"{name}: sketch entries err/bound max {err.max():.3e} median {np.median(err):.3e}")
-    # binary32 MFMA accumulation over a K-split chunk, plus rare one-ulp
-    # differences of S entries next to a rounding boundary of the format
-    assert err.max() < 2e-3 and np.median(err) < 1e-5
+    say(f"{name}: sketch entries err/(3 scale) max {err.max():.3f} median {np.median(err):.3f}")
+    # binary32 accumulation over the library's K-split, the e4m3 MFMA's
+    # dot-product window and one-ulp S entries next to a rounding boundary
+    assert err.max() <= 1.0
     rel, lim = _qr_backward(L, Y, wl["u_qr"])
     say(f"{name}: |R^T R - Y^T Y| / |Y|^2 = {rel:.3e} (limit {lim:.1e})")
     assert rel <= lim
@@ -186,3 +175,62 @@ def test_full_size_batch_of_256(L):
         ex, er = refsolve.forward_errors(host(xs[i]), host(rs[i]), xr, rr)
         say(f"batch problem {i} (m={P.m} n={P.n} kappa={sizes[i]['kappa']:.2e}): x {ex:.3e} r {er:.3e}")
         assert ex <= TARGET and er <= TARGET
+
+
+# ------------------------------------------------------------------ kappa = 1e10, binary64 data
+@pytest.fixture(scope="module")
+def cfg4():
+    # m = 5e5, n = 2000, kappa = 1e10, binary64 storage (8 GB), and the exact
+    # solution of the stored data (double-double refinement)
+    wl = WORKLOADS["fp16_m500k_n2000"]
+    seed = data_seed(wl["index"])
+    t0 = time.time()
+    P = make_problem(wl["m"], wl["n"], wl["kappa"], seed, store=wl["store"])
+    say(f"kappa 1e10 workload: generated {wl['m']} x {wl['n']} in {time.time() - t0:.1f} s")
+    t0 = time.time()
+    xr, rr, info = refsolve.ref_solve(P.At, P.b, maxit=6)
+    say(f"kappa 1e10 workload: reference in {time.time() - t0:.1f} s, steps {['%.1e' % v for v in info['steps']]}")
+    return wl, seed, P, xr, rr
+
+
+def _cfg4_solve(L, cfg4, pr, terms, **opts):
+    wl, seed, P, xr, rr = cfg4
+    At, b = torch.from_numpy(P.At).cuda(), torch.from_numpy(P.b).cuda()
+    S = L.Solver(At, b, s=wl["s"], seed=seed, terms=terms, pr=pr, **opts)
+    t0 = time.time()
+    rc = S(check=False)
+    torch.cuda.synchronize()
+    dt = time.time() - t0
+    st = S.stats.as_dict()
+    x, r = host(S.x), host(S.r)
+    del S, At, b
+    torch.cuda.empty_cache()
+    ex, er = refsolve.forward_errors(x, r, xr, rr)
+    say(f"  status {rc}, {dt * 1e3:.0f} ms, kappa_est {st['kappa_est']:.3g}, lsqr {st['lsqr_its']}, lsir {st['lsir_its']}, "
+        f"fgmres {st['fgmres_its_total']}, err x {ex:.3e} r {er:.3e}, stages "
+        f"{[round(st[k], 1) for k in ('ms_sketch', 'ms_qr', 'ms_lsqr', 'ms_lsir')]} ms")
+    return rc, st, ex, er, dt
+
+
+def test_full_size_fp16_workload_as_written(L, cfg4):
+    # fp16 sketch (one part, column scaling), binary64 QR, binary32 LSQR and
+    # FGMRES products, binary64 residuals.  kappa(A) u = 1e10 2^-24 ~ 600 and
+    # kappa(A) u_s ~ 5e6 lie outside the conditions of Section 4 (and of the
+    # refinement's limiting accuracy with binary64 residuals); Table 4 prints
+    # "-" for u_s half and single at kappa = 1e10 even with u = double.  The
+    # library reports LS_NOT_CONVERGED with finite iterates.
+    say("kappa 1e10 as written (fp16 x1, u = binary32):")
+    pr = L.precs(u_s="f16", u_qr="f64", u="f32", u_r="f64")
+    rc, st, ex, er, _ = _cfg4_solve(L, cfg4, pr, 1, lsir_tol=6e-6, lsqr_tol=1e-6)
+    assert rc == 1
+    assert np.isfinite(ex) and np.isfinite(er)
+
+
+def test_full_size_fp16_workload_binary64_path(L, cfg4):
+    # the all-binary64 path on the same problem (binary64 MFMA sketch, QR,
+    # LSQR and FGMRES; double-double residuals): Table 4's u_s = double column
+    # converges at kappa = 1e10 (2 steps, 100 FGMRES iterations)
+    say("kappa 1e10, all binary64:")
+    pr = L.precs(u_s="f64", u_qr="f64", u="f64", u_r="f64x2")
+    rc, st, ex, er, dt = _cfg4_solve(L, cfg4, pr, 1, lsir_tol=1e-12, lsqr_tol=1e-12)
+    assert rc == 0 and ex <= TARGET and er <= TARGET

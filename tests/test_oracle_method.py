@@ -198,6 +198,59 @@ def test_ref_solve_matches_mpmath_normal_equations():
     assert np.linalg.norm(rr - rm) <= 1e-14 * np.linalg.norm(rm)
 
 
+def _mpmath_ls(P):
+    mpmath.mp.dps = 60
+    A = mpmath.matrix([[mpmath.mpf(float(v)) for v in row] for row in P.A()])
+    b = mpmath.matrix([mpmath.mpf(float(v)) for v in P.b])
+    x = mpmath.lu_solve(A.T * A, A.T * b)
+    r = b - A * x
+    return np.array([float(v) for v in x]), np.array([float(v) for v in r])
+
+
+@pytest.mark.parametrize("m,n", [(40, 6), (200, 12)])
+def test_ref_solve_matches_mpmath_at_kappa_1e10(m, n):
+    # binary64 data with kappa(A) = 1e10 (the m = 5e5, n = 2000 workload's
+    # conditioning): the double-double reference equals the 60-digit normal
+    # equations solution to binary64 resolution; x87 residuals stall far off
+    # (their limiting accuracy, u_ld kappa^2 ||r|| / (||A|| ||x||), is near 1e-4),
+    # so the check tells the two apart
+    P = make_problem(m, n, 1e10, seed=9, store="f64")
+    xm, rm = _mpmath_ls(P)
+    xr, rr, info = refsolve.ref_solve(P.At, P.b)
+    assert np.linalg.norm(xr - xm) <= 4e-16 * np.linalg.norm(xm)
+    assert np.linalg.norm(rr - rm) <= 4e-16 * np.linalg.norm(rm)
+    xl, _, _ = refsolve.ref_solve(P.At, P.b, residual="ld")
+    assert np.linalg.norm(xl - xm) > 1e-8 * np.linalg.norm(xm)
+
+
+def test_dd_residual_matches_exact_rationals():
+    # f = b - r - A x and g = -A^T r with x, r given as double-double pairs,
+    # against exact rational arithmetic: error <= 2^-100 times the sum of the
+    # magnitudes of the terms (a double-double's accuracy is about 2^-104)
+    rng = np.random.default_rng(21)
+    m, n = 9, 4
+    A = rng.standard_normal((m, n)) * np.exp(rng.uniform(-8, 8, (m, n)))
+    b = rng.standard_normal(m)
+    xh = rng.standard_normal(n)
+    xl = xh * rng.uniform(-1, 1, n) * 2.0 ** -54
+    rh = rng.standard_normal(m) * 1e-3
+    rl = rh * rng.uniform(-1, 1, m) * 2.0 ** -54
+    At64 = np.ascontiguousarray(A.T)
+    fh, fl, gh, gl = refsolve.dd_aug_residual(At64, b, xh, xl, rh, rl)
+    F = Fraction
+    for i in range(m):
+        terms = [F(b[i]), -F(rh[i]), -F(rl[i])] + [-F(A[i, j]) * (F(xh[j]) + F(xl[j])) for j in range(n)]
+        exact = sum(terms)
+        mag = sum(abs(t) for t in terms)
+        assert abs(F(fh[i]) + F(fl[i]) - exact) <= mag * F(2) ** -100
+        assert fh[i] == fh[i] + fl[i]                       # normalised pair
+    for j in range(n):
+        terms = [-F(A[i, j]) * (F(rh[i]) + F(rl[i])) for i in range(m)]
+        exact = sum(terms)
+        mag = sum(abs(t) for t in terms)
+        assert abs(F(gh[j]) + F(gl[j]) - exact) <= mag * F(2) ** -100
+
+
 def test_ref_solve_recovers_construction_for_exact_storage():
     P = make_problem(3000, 40, 1e2, seed=10, store="f64")
     xr, rr, _ = refsolve.ref_solve(P.At, P.b)

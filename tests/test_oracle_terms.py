@@ -66,8 +66,8 @@ def test_library_rule_equals_oracle_rule():
     for fmt in ("bf16", "f16", "e4m3", "f64"):
         for kappa in (1.0, 10.0, 255.0, 257.0, 2047.0, 2049.0, 15.0, 17.0, 6.5e4, 6.6e4, 1e6, 1e12,
                       float("inf"), float("nan")):
-            for terms in (1, 2, 3):
-                for max_terms in (0, 1, 2, 3):
+            for terms in (1, 2, 3, 4, 5):
+                for max_terms in (0, 1, 2, 3, 4, 5):
                     want = osolve.terms_for(kappa, fmt, terms, max_terms)
                     got = L.sketch_terms_for(kappa, fmt, terms, max_terms)
                     assert got == want, (fmt, kappa, terms, max_terms)
