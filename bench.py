@@ -179,7 +179,7 @@ def run_workload(L, name, terms, steps, warmup, want_fp64, want_sparse, want_ada
     b = torch.from_numpy(P.b).cuda()
     mixed = wl["u"] == "f32"
     u_r = wl["u_r"] if mixed else "f64x2"
-    pr = L.precs(u_s=wl["u_s"], u_qr=wl["u_qr"], u=wl["u"], u_r=u_r)
+    pr = L.precs(u_s=wl["u_s"], u_qr=wl["u_qr"], u=wl["u"], u_r=u_r, u_A=wl.get("u_A"))
     lsir_tol = TARGET_ERR if mixed else 1e-15
     lsqr_tol = 1e-6 if mixed else 1e-14
     S = L.Solver(At, b, s=s, seed=seed, terms=terms, pr=pr, lsir_tol=lsir_tol, lsqr_tol=lsqr_tol)
@@ -211,7 +211,8 @@ def run_workload(L, name, terms, steps, warmup, want_fp64, want_sparse, want_ada
         "value": (steps / dt) if ok else 0.0, "ms_per_step": ms, "fwd_err_x": ex, "fwd_err_r": er,
         "meets_target": ok,
         "config": {"workload": name, "m": m, "n": n, "s": s, "kappa": kappa, "store": wl["store"],
-                   "u_s": wl["u_s"], "terms": terms, "u_qr": wl["u_qr"], "u": wl["u"], "u_r": u_r},
+                   "u_s": wl["u_s"], "terms": terms, "u_qr": wl["u_qr"], "u": wl["u"], "u_r": u_r,
+                   "u_A": wl.get("u_A", wl["u"])},
         "sketch_tflops": sketch_tflops,
         "sketch_mfma_frac": (sketch_tflops / MFMA_PEAK_TFLOPS[wl["u_s"]]) if sketch_tflops else None,
         "sketch_mfma_issued_frac": (terms * sketch_tflops / MFMA_PEAK_TFLOPS[wl["u_s"]]) if sketch_tflops else None,
@@ -308,7 +309,7 @@ def main():
         for _ in range(3):
             ya.copy_(xa)
         torch.cuda.synchronize()
-        pr = L.precs(u_s=wl["u_s"], u_qr=wl["u_qr"], u=wl["u"], u_r=wl["u_r"])
+        pr = L.precs(u_s=wl["u_s"], u_qr=wl["u_qr"], u=wl["u"], u_r=wl["u_r"], u_A=wl.get("u_A"))
         Sc = L.Solver(At, b, s=wl["s"], seed=seed, terms=terms, pr=pr, lsir_tol=TARGET_ERR, lsqr_tol=1e-6,
                       check_every=1)
         Sc()

@@ -40,7 +40,7 @@ WORKLOADS = {
     "bf16_m100k_n500": dict(index=1, m=100_000, n=500, s=2000, kappa=1e4, store="f32",
                             u_s="bf16", u_qr="f32", u="f32", u_r="f64"),
     "fp8_m1M_n1000": dict(index=2, m=1_000_000, n=1000, s=4000, kappa=1e6, store="f32",
-                          u_s="e4m3", u_qr="f64", u="f32", u_r="f64"),
+                          u_s="e4m3", u_qr="f64", u="f32", u_r="f64", u_A="f64"),
     "batched_256": dict(index=3, nprob=256, m_range=(5000, 200_000), n_range=(32, 256),
                         log10_kappa_range=(1.0, 5.0), store="f32",
                         u_s="bf16", u_qr="f32", u="f32", u_r="f64"),

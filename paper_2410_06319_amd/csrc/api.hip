@@ -146,11 +146,17 @@ double sketch_unit_roundoff(ls_prec_t u_s, int32_t terms) {
   return std::pow(u, (double)(terms < 1 ? 1 : terms));
 }
 
-// A second, binary64 copy of B is needed when FGMRES works in binary64 but
-// LSQR in binary32 (u_A = FP64 with u = FP32, or the binary64 fallback).
+// A second FGMRES operand besides LSQR's B is needed when FGMRES takes
+// binary64 products while LSQR works in binary32 (u_A = FP64 with u = FP32,
+// or the binary64 fallback): A's panel copy for the A-path.
 bool second_b(const ls_precs_t* pr, const ls_iter_opts_t* io) {
   if (pr->u != LS_FP32) return false;
   return pr->u_A == LS_FP64 || io->fallback != 0;
+}
+ls_precs_t with_binary64_products(const ls_precs_t* pr) {
+  ls_precs_t p = *pr;
+  p.u_A = p.u_L = p.u_R = LS_FP64;
+  return p;
 }
 
 // Make R^-1 available: W (binary64) and its binary32 copy.
@@ -300,6 +306,7 @@ int ls_workspace_size(const ls_problem_t* P, const ls_sketch_opts_t* so, const l
   LS_TRY(check_sketch(P, so, pr->u_s));
   const ls_iter_opts_t io = fill_opts(io_in, P->n, pr->u);
   const int64_t n = P->n, s = sketch_rows(P, so);
+  const ls_precs_t p64 = with_binary64_products(pr);
   // the sketch with the most room over the parts the solve may use (each
   // count of parts may take its own tuned launch shape)
   size_t sk_bytes = 0;
@@ -314,7 +321,7 @@ int ls_workspace_size(const ls_problem_t* P, const ls_sketch_opts_t* so, const l
                  + inv_carve(nullptr, n).bytes                   // R^-1
                  + ls_align256(8 * (size_t)(P->m + n))           // saved x0 for the fallback
                  + b_bytes(P, pr->u)                             // B = A R^-1 for LSQR
-                 + (second_b(pr, &io) ? b_bytes(P, LS_FP64) : 0); // binary64 B for FGMRES
+                 + (second_b(pr, &io) ? fg_operand_bytes(P, &p64) : 0);   // A's panels for binary64 FGMRES
   size_t scratch = sk_bytes;
   const size_t q = qr_workspace(s, n + 1, pr->u_qr);
   if (q > scratch) scratch = q;
@@ -398,12 +405,12 @@ int ls_lsir_gmres(const ls_problem_t* P, const double* R, int64_t ldr, const ls_
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
   const Inv inv = inv_carve(base, P->n);
-  const size_t bb = b_bytes(P, pr->u_A);
+  const size_t bb = fg_operand_bytes(P, pr);
   const size_t need = inv.bytes + bb + lsir_workspace(P, pr, io.fgmres_maxit, device_cu_count());
   if (!ws || ws_bytes < need) return LS_E_WORKSPACE;
   LS_TRY(make_inverse(R, ldr, P->n, inv, st));
   void* Bm = base + inv.bytes;
-  LS_TRY(form_b(P, inv.W, inv.W32, pr->u_A, Bm, st));
+  LS_TRY(form_fg_operand(P, inv.W, inv.W32, pr, Bm, st));
   if (stats) std::memset(stats, 0, sizeof(*stats));
   prof_reset(io.profile != 0);
   const int rc = lsir_device(P, inv.W, Bm, pr, x, r, r_given, &io, stats, base + inv.bytes + bb,
@@ -447,10 +454,11 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
   off += ls_align256(8 * (size_t)(m + n));
   void* B1 = base + off;                       // B in the working precision u
   off += b_bytes(P, pr->u);
-  void* B2 = nullptr;                          // binary64 B for FGMRES when needed
+  const ls_precs_t p64 = with_binary64_products(pr);
+  void* B2 = nullptr;                          // A's panels for binary64 FGMRES when needed
   if (second_b(pr, &io)) {
     B2 = base + off;
-    off += b_bytes(P, LS_FP64);
+    off += fg_operand_bytes(P, &p64);
   }
   char* scratch = base + off;
   const size_t scratch_bytes = ws_bytes - off;
@@ -513,9 +521,11 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
     LS_HIP_TRY(hipMemcpyAsync(saved, x, 8 * (size_t)n, hipMemcpyDeviceToDevice, st));
   }
   void* Bfg = B1;
-  if (pr->u_A != pr->u) {
-    LS_TRY(form_b(P, inv.W, inv.W32, pr->u_A, B2, st));
+  bool have_b2 = false;
+  if (pr->u_A != pr->u) {   // u = binary32, u_A = binary64: the A-path
+    LS_TRY(form_fg_operand(P, inv.W, inv.W32, pr, B2, st));
     Bfg = B2;
+    have_b2 = true;
   }
   rc = lsir_device(P, inv.W, Bfg, pr, x, r, 0, &io, S, scratch, scratch_bytes, st);
   if (rc == LS_NOT_CONVERGED && io.fallback && pr->u_A == LS_FP32) {
@@ -524,12 +534,10 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
     // to u^2 (binary64 for u = binary32; the FGMRES limit stays, as in Table 3)
     // and run the refinement loop again from the LSQR solution.
     if (S->kappa_est * sketch_unit_roundoff(pr->u_s, so_t.terms) < 1.0) {
-      ls_precs_t p2 = *pr;
-      p2.u_A = p2.u_L = p2.u_R = LS_FP64;
       LS_HIP_TRY(hipMemcpyAsync(x, saved, 8 * (size_t)n, hipMemcpyDeviceToDevice, st));
       S->fallback_used = 1;
-      LS_TRY(form_b(P, inv.W, inv.W32, LS_FP64, B2, st));
-      rc = lsir_device(P, inv.W, B2, &p2, x, r, 0, &io, S, scratch, scratch_bytes, st);
+      if (!have_b2) LS_TRY(form_fg_operand(P, inv.W, inv.W32, &p64, B2, st));
+      rc = lsir_device(P, inv.W, B2, &p64, x, r, 0, &io, S, scratch, scratch_bytes, st);
     } else {
       S->fallback_used = 2;   // declined: outside the condition of Section 4
     }

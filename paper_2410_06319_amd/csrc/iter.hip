@@ -897,18 +897,22 @@ struct FgPtrs {
 
 // Column j: h = ||w|| from partials (j = 0: beta = ||s||); block 0 applies
 // the Givens rotations to column j-1 and tests convergence.  Then, per panel
-// of B (one wave per contiguous panel range, next panel in flight):
-// v_r = V_r[:, j] / h (written back normalised), w_r = v_r + B v_x ->
-// V_r[:, j+1], and the lanes' column partials of t = B^T v_r.
-template <typename TB, int Q>
+// of P (one wave per contiguous panel range, next panel in flight):
+// v_r = V_r[:, j] / h (written back normalised), w_r = v_r + P y ->
+// V_r[:, j+1], and the lanes' column partials of t = P^T v_r, with products
+// and sums in TC.  B-path: P = B = A W in its precision TB, y = v_x = V_x[:, j] / h
+// (xin null), TC = TB.  A-path: P = A in its storage precision (panel copy),
+// y = W v_x = xin / h with xin = W V_x[:, j], TC = binary64: the products with
+// the preconditioned operator in binary64 over the stored data.
+template <typename TB, typename TC, int Q>
 __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, int64_t npan, int64_t m, int64_t n,
                                                      FgPtrs F, int j, int kmax, const double* __restrict__ w2part,
-                                                     int Gw, double tol, int final_step, TB* __restrict__ tpart,
-                                                     Progress* prog) {
+                                                     int Gw, double tol, int final_step, TC* __restrict__ tpart,
+                                                     const double* __restrict__ xin, Progress* prog) {
   if (F.st->done) return;
   using vec_t = typename PanVec<TB>::type;
   constexpr int PR = PanVec<TB>::PR;
-  __shared__ TB cred[64 * Q];
+  __shared__ TC cred[64 * Q];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   double* vj = F.V + (int64_t)j * F.ldv;
@@ -996,11 +1000,12 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
   }
   if (h == 0.0 || !isfinite(h) || final_step || j >= kmax) return;
   const double inv = 1.0 / h;
-  TB vl[Q], creg[Q];
+  TC vl[Q], creg[Q];
+  const double* xs = xin ? xin : vj + m;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int64_t c = lane + 64 * q;
-    vl[q] = (c < n) ? (TB)(vj[m + c] * inv) : TB(0);
+    vl[q] = (c < n) ? (TC)(xs[c] * inv) : TC(0);
     creg[q] = 0;
   }
   for (int64_t p = p0; p < p1; ++p) {
@@ -1009,21 +1014,21 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
     if (kPanPrefetch<Q> && p + 1 < p1) load(p + 1, nxt, vrn);
     const int64_t i0 = p * PR;
     double vr[PR];
-    TB vrt[PR], s[PR];
+    TC vrt[PR], s[PR];
 #pragma unroll
     for (int k = 0; k < PR; ++k) {
       vr[k] = vro[k] * inv;
-      vrt[k] = (TB)vr[k];
+      vrt[k] = (TC)vr[k];
       s[k] = 0;
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
-      for (int k = 0; k < PR; ++k) s[k] += cur[q][k] * vl[q];
+      for (int k = 0; k < PR; ++k) s[k] += (TC)cur[q][k] * vl[q];
     double wr[PR];
 #pragma unroll
     for (int k = 0; k < PR; ++k) {
-      const TB sk = wave_allsum(s[k]);
+      const TC sk = wave_allsum(s[k]);
       wr[k] = (i0 + k < m) ? (double)(vrt[k] + sk) : 0.0;
     }
     if (lane == 0) {
@@ -1037,7 +1042,7 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
-      for (int k = 0; k < PR; ++k) creg[q] += cur[q][k] * vrt[k];
+      for (int k = 0; k < PR; ++k) creg[q] += (TC)cur[q][k] * vrt[k];
     if (p + 1 < p1) {
       if constexpr (kPanPrefetch<Q>) {
 #pragma unroll
@@ -1052,22 +1057,24 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
   for (int wv = 0; wv < 4; ++wv) {
     if (wave == wv) {
 #pragma unroll
-      for (int q = 0; q < Q; ++q) cred[lane + 64 * q] = (wv ? cred[lane + 64 * q] : TB(0)) + creg[q];
+      for (int q = 0; q < Q; ++q) cred[lane + 64 * q] = (wv ? cred[lane + 64 * q] : TC(0)) + creg[q];
     }
     __syncthreads();
   }
   for (int64_t c = threadIdx.x; c < n; c += kThreads) tpart[c * gridDim.x + blockIdx.x] = cred[c];
 }
 
-// Blocks < ncb (16 columns each, one wave per column): w_x = B^T v_r from the
-// column partials -> V[m:, j+1], normalise V[m:, j], partial h1_x[c] over the
-// block's columns.  Blocks ncb .. ncb + nrb - 1 (a range of rows < m each,
-// one wave per Krylov column): partial h1_r[c] = V_r[rows, c] . w_r[rows]
-// for c <= j (V_r[:, j] was normalised by the pass).  Partials of block b
-// go to hxpart[c (ncb + nrb) + b].
+// Blocks < ncb (16 columns each, one wave per column): t = P^T v_r from the
+// column partials, normalise V[m:, j]; B-path (tout null): w_x = t ->
+// V[m:, j+1] and partial h1_x[c] over the block's columns; A-path: t -> tout
+// (k_fg_wt forms w_x = W^T t and those partials).  Blocks ncb .. ncb + nrb - 1
+// (a range of rows < m each, one wave per Krylov column): partial
+// h1_r[c] = V_r[rows, c] . w_r[rows] for c <= j (V_r[:, j] was normalised by
+// the pass).  Partials of block b go to hxpart[c (ncb + nrb) + b].
 template <typename TB>
 __global__ __launch_bounds__(1024) void k_fg_col(int64_t m, int64_t n, const TB* __restrict__ tpart, int G, FgPtrs F,
-                                                 int j, int ncb, int nrb, double* __restrict__ hxpart) {
+                                                 int j, int ncb, int nrb, double* __restrict__ hxpart,
+                                                 double* __restrict__ tout) {
   if (F.st->done) return;
   __shared__ double wx[16];
   __shared__ double vjx[16];
@@ -1121,6 +1128,13 @@ __global__ __launch_bounds__(1024) void k_fg_col(int64_t m, int64_t n, const TB*
     vn = vj[m + col] * inv;
   }
   __syncthreads();   // every wave has read V[m:, j] before it is overwritten
+  if (tout) {
+    if (col < n && lane == 0) {
+      tout[col] = val;
+      vj[m + col] = vn;
+    }
+    return;
+  }
   if (col < n && lane == 0) {
     w[m + col] = val;
     vj[m + col] = vn;
@@ -1137,6 +1151,99 @@ __global__ __launch_bounds__(1024) void k_fg_col(int64_t m, int64_t n, const TB*
       if (cc < n) s += ((c == j) ? vjx[q] : F.V[m + cc + (int64_t)c * F.ldv]) * wx[q];
     }
     hxpart[(int64_t)c * Gx + blockIdx.x] = s;
+  }
+}
+
+// A-path, before the pass of column j: xin = W V[m:, j] (the x part of v_j
+// before its normalisation, which the pass applies).
+__global__ __launch_bounds__(kUtThreads) void k_fg_zx(const double* __restrict__ W, int64_t n, FgPtrs F, int64_t m,
+                                                      int j, double* __restrict__ xin) {
+  if (F.st->done) return;
+  __shared__ double red[32 * 33];
+  const double* vx = F.V + (int64_t)j * F.ldv + m;
+  const double z = ls_utmv_row(W, n, n, [&](int64_t c) { return vx[c]; }, red);
+  const int64_t row = (int64_t)blockIdx.x * 32 + threadIdx.x;
+  if (threadIdx.x < 32 && row < n) xin[row] = z;
+}
+
+// A-path, after the pass: w_x = W^T t -> V[m:, j+1] (one wave per column,
+// 16 columns per block, column c of W being row c of W^T), then the partials
+// h1_x[c] = V_x[block's columns, c] . w_x for c <= j (V_x[:, j] normalised by
+// k_fg_col), stored as k_fg_col stores them on the B-path.
+__global__ __launch_bounds__(1024) void k_fg_wt(const double* __restrict__ W, int64_t m, int64_t n,
+                                                const double* __restrict__ t, FgPtrs F, int j, int ncb, int nrb,
+                                                double* __restrict__ hxpart) {
+  if (F.st->done) return;
+  __shared__ double wx[16];
+  const int lane = threadIdx.x & 63;
+  const int wvi = threadIdx.x >> 6;
+  const int64_t col = (int64_t)blockIdx.x * 16 + wvi;
+  double val = 0.0;
+  if (col < n) {
+    const double* wc = W + col * n;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i0 = lane; i0 <= col; i0 += 64 * 8) {   // eight loads per lane in flight
+      double wv[8], tv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int64_t i = i0 + 64 * q;
+        wv[q] = (i <= col) ? wc[i] : 0.0;
+        tv[q] = (i <= col) ? t[i] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[q & 3] += wv[q] * tv[q];
+    }
+    val = ls_wave_sum((a[0] + a[1]) + (a[2] + a[3]));
+    if (lane == 0) F.V[m + col + (int64_t)(j + 1) * F.ldv] = val;
+  }
+  if (lane == 0) wx[wvi] = (col < n) ? val : 0.0;
+  __syncthreads();
+  const int64_t Gx = ncb + nrb;
+  for (int c = threadIdx.x; c <= j; c += 1024) {
+    double s = 0.0;
+    for (int q = 0; q < 16; ++q) {
+      const int64_t cc = (int64_t)blockIdx.x * 16 + q;
+      if (cc < n) s += F.V[m + cc + (int64_t)c * F.ldv] * wx[q];
+    }
+    hxpart[(int64_t)c * Gx + blockIdx.x] = s;
+  }
+}
+
+// A copied into the panel layout of B, in its storage precision (the A-path's
+// operand): a block moves 64 rows x 64 columns through LDS, reading each
+// column's rows with coalesced 16-byte loads and writing each panel's 64
+// columns as one contiguous 1 KB run.  Rows of the last panel past m are zero.
+template <typename TA>
+__global__ __launch_bounds__(kThreads) void k_a_panels(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                                                       int vec_ok, TA* __restrict__ Ap) {
+  using vec_t = typename PanVec<TA>::type;
+  constexpr int PR = PanVec<TA>::PR;
+  constexpr int NP = 64 / PR;   // panels in the tile
+  __shared__ vec_t tile[64][NP + 1];
+  const int t = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  const int64_t c0 = (int64_t)blockIdx.y * 64;
+  const int64_t npan = ls_cdiv(m, PR);
+  for (int u = t; u < 64 * NP; u += kThreads) {
+    const int c = u / NP, pq = u % NP;
+    const int64_t gc = c0 + c, gi = i0 + (int64_t)pq * PR;
+    vec_t v{};
+    if (gc < n && gi < m) {
+      const TA* src = A + gi + gc * lda;
+      if (vec_ok && gi + PR <= m) {
+        v = *reinterpret_cast<const vec_t*>(src);
+      } else {
+#pragma unroll
+        for (int k = 0; k < PR; ++k) v[k] = (gi + k < m) ? src[k] : TA(0);
+      }
+    }
+    tile[c][pq] = v;
+  }
+  __syncthreads();
+  for (int u = t; u < 64 * NP; u += kThreads) {
+    const int pq = u / 64, c = u % 64;
+    const int64_t gp = i0 / PR + pq, gc = c0 + c;
+    if (gp < npan && gc < n) *reinterpret_cast<vec_t*>(Ap + gp * PR * n + gc * PR) = tile[c][pq];
   }
 }
 
@@ -1749,6 +1856,8 @@ struct LsirWs {
   double* gvec;       // n
   double* dz;         // n
   double* upart;      // 2 x (Gd + Gn)
+  double* xin;        // n: W V_x[:, j] (A-path)
+  double* tbuf;       // n: A^T v_r (A-path)
   size_t bytes;
 };
 
@@ -1757,12 +1866,12 @@ struct LsirDims {
   int64_t npan;   // panels of B
 };
 
-template <typename TB, int Q>
+template <typename TB, typename TC, int Q>
 void fg_pan_launch(int G, hipStream_t st, ProfEv ev, const TB* Bm, int64_t npan, int64_t m, int64_t n,
                    const FgPtrs& F, int j, int kmax, const double* w2part, int Gw, double tol, int final_step,
-                   TB* tpart, Progress* prog) {
-  hipExtLaunchKernelGGL((k_fg_pan<TB, Q>), dim3(G), dim3(kThreads), 0, st, ev.a, ev.b, 0, Bm, npan, m, n, F, j, kmax,
-                        w2part, Gw, tol, final_step, tpart, prog);
+                   TC* tpart, const double* xin, Progress* prog) {
+  hipExtLaunchKernelGGL((k_fg_pan<TB, TC, Q>), dim3(G), dim3(kThreads), 0, st, ev.a, ev.b, 0, Bm, npan, m, n, F, j,
+                        kmax, w2part, Gw, tol, final_step, tpart, xin, prog);
 }
 
 LsirDims lsir_dims(const ls_problem_t* P, size_t tb_elt, size_t ta_elt, int fgmres_maxit, int ncu) {
@@ -1810,27 +1919,32 @@ LsirWs lsir_carve(char* ws, const ls_problem_t* P, const LsirDims& d, size_t tb_
   w.rt_lo = reinterpret_cast<double*>(take(8 * (size_t)d.Gr * n));
   w.gvec = reinterpret_cast<double*>(take(8 * (size_t)n));
   w.dz = reinterpret_cast<double*>(take(8 * (size_t)n));
+  w.xin = reinterpret_cast<double*>(take(8 * (size_t)n));
+  w.tbuf = reinterpret_cast<double*>(take(8 * (size_t)n));
   w.bytes = off;
   return w;
 }
 
-template <typename TA, typename TB, typename TU, bool DD>
+// TB: element type of the panels the FGMRES pass streams; TC: its arithmetic
+// (TB on the B-path, binary64 on the A-path, AP, where the panels are A's).
+template <typename TA, typename TB, typename TU, bool DD, bool AP>
 int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, double* r, int r_given,
                const ls_iter_opts_t* io, ls_stats_t* stats, char* ws, size_t ws_bytes, hipStream_t st,
                int fg_maxit) {
+  using TC = typename std::conditional<AP, double, TB>::type;
   const int64_t m = P->m, n = P->n;
   const int ncu = device_cu_count();
   const LsirDims d = lsir_dims(P, sizeof(TB), sizeof(TA), fg_maxit, ncu);
   if (d.kmax > kMaxKrylov - 1) return LS_E_ARG;
   if (n > 64 * kMaxPanQ) return LS_E_UNSUPPORTED;
-  LsirWs w = lsir_carve(ws, P, d, sizeof(TB));
+  LsirWs w = lsir_carve(ws, P, d, sizeof(TC));
   if (w.bytes > ws_bytes) return LS_E_WORKSPACE;
   FgPtrs F{w.V, w.ldv, w.H, w.cs, w.sn, w.g, w.hj, w.st};
   const TA* A = static_cast<const TA*>(P->A);
   const TA* b = static_cast<const TA*>(P->b);
   const int vec_a = vec_aligned(A, P->lda, sizeof(TA)) ? 1 : 0;
   const int q = pan_q(n);
-  TB* tpart = reinterpret_cast<TB*>(w.tpart);
+  TC* tpart = reinterpret_cast<TC*>(w.tpart);
   const int check = io->check_every > 0 ? io->check_every : 8;
   double tol = io->fgmres_tol;   // FGMRES tolerance of the current step
   const double lsir_tol = io->lsir_tol;
@@ -1843,8 +1957,8 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
   Progress *prog = slot.host, *dprog = slot.dev;
   auto fg_pass = [&](int j, int Gw, int final_step, int grid, ProfEv ev) {
 #define LS_FG_PAN(QQ)                                                                                              \
-  fg_pan_launch<TB, QQ>(grid, st, ev, Bm, d.npan, m, n, F, j, d.kmax, w.w2part, Gw, tol, final_step, tpart,     \
-                        dprog);                                                                                    \
+  fg_pan_launch<TB, TC, QQ>(grid, st, ev, Bm, d.npan, m, n, F, j, d.kmax, w.w2part, Gw, tol, final_step, tpart, \
+                            AP ? w.xin : nullptr, dprog);                                                          \
   break
     switch (q) {
       case 1: LS_FG_PAN(1);
@@ -1888,11 +2002,16 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
     }
     for (; j < d.kmax; ++j) {
       const int Gw = (j == 0) ? d.Gr + d.Gh : d.Gs;
+      if (AP)   // the x part of v_j times W, before the pass
+        hipLaunchKernelGGL(k_fg_zx, dim3((unsigned)ls_cdiv(n, 32)), dim3(kUtThreads), 0, st, W, n, F, m, j, w.xin);
       fg_pass(j, Gw, 0, d.G, prof_events(kProfFgPass));
-      // B once, v_j read and written, w written, v_x read, t written
-      prof_commit(kProfFgPass, (double)m * n * sizeof(TB) + 24.0 * m + 8.0 * n + (double)n * sizeof(TB));
-      hipLaunchKernelGGL(k_fg_col<TB>, dim3((unsigned)(ncb + d.Gk)), dim3(1024), 0, st, m, n, tpart, d.G, F, j, ncb,
-                         d.Gk, w.hxpart);
+      // the panels once, v_j read and written, w written, v_x (or W v_x) read, t written
+      prof_commit(kProfFgPass, (double)m * n * sizeof(TB) + 24.0 * m + 8.0 * n + (double)n * sizeof(TC));
+      hipLaunchKernelGGL(k_fg_col<TC>, dim3((unsigned)(ncb + d.Gk)), dim3(1024), 0, st, m, n, tpart, d.G, F, j, ncb,
+                         d.Gk, w.hxpart, AP ? w.tbuf : nullptr);
+      if (AP)   // w_x = W^T t and the x-part Arnoldi partials
+        hipLaunchKernelGGL(k_fg_wt, dim3((unsigned)ncb), dim3(1024), 0, st, W, m, n, w.tbuf, F, j, ncb, d.Gk,
+                           w.hxpart);
       prof_begin(kProfCgs, st);
       hipLaunchKernelGGL(k_cgs1, dim3((unsigned)d.Gs), dim3(kSweepThreads), 0, st, F, m, n, j, d.kmax, w.hxpart,
                          d.Gc + d.Gk, w.h2part);
@@ -1960,11 +2079,35 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
 }
 }  // namespace
 
+bool fg_apath(const ls_precs_t* pr) { return pr->u == LS_FP32 && pr->u_A == LS_FP64; }
+
+size_t fg_operand_bytes(const ls_problem_t* P, const ls_precs_t* pr) {
+  return fg_apath(pr) ? b_bytes(P, P->store) : b_bytes(P, pr->u_A);
+}
+
+int form_fg_operand(const ls_problem_t* P, const double* W, const float* W32, const ls_precs_t* pr, void* out,
+                    hipStream_t st) {
+  if (!fg_apath(pr)) return form_b(P, W, W32, pr->u_A, out, st);
+  const dim3 g((unsigned)ls_cdiv(P->m, 64), (unsigned)ls_cdiv(P->n, 64));
+  if (P->store == LS_FP32)
+    hipLaunchKernelGGL(k_a_panels<float>, g, dim3(kThreads), 0, st, (const float*)P->A, P->lda, P->m, P->n,
+                       vec_aligned(P->A, P->lda, 4) ? 1 : 0, (float*)out);
+  else
+    hipLaunchKernelGGL(k_a_panels<double>, g, dim3(kThreads), 0, st, (const double*)P->A, P->lda, P->m, P->n,
+                       vec_aligned(P->A, P->lda, 8) ? 1 : 0, (double*)out);
+  LS_HIP_TRY(hipGetLastError());
+  return LS_OK;
+}
+
 size_t lsir_workspace(const ls_problem_t* P, const ls_precs_t* pr, int fgmres_maxit, int ncu) {
-  const size_t tb = (pr->u_A == LS_FP64) ? 8 : 4;
+  // panels streamed by the pass (A's on the A-path, B's otherwise) and the
+  // element of its column partials (binary64 on the A-path)
+  const bool ap = fg_apath(pr);
   const size_t ta = (P->store == LS_FP64) ? 8 : 4;
+  const size_t tb = ap ? ta : ((pr->u_A == LS_FP64) ? 8 : 4);
+  const size_t tc = ap ? 8 : tb;
   const LsirDims d = lsir_dims(P, tb, ta, fgmres_maxit, ncu);
-  return lsir_carve(nullptr, P, d, tb).bytes;
+  return lsir_carve(nullptr, P, d, tc).bytes;
 }
 
 int lsir_device(const ls_problem_t* P, const double* W, const void* Bm, const ls_precs_t* pr, double* x, double* r,
@@ -1978,30 +2121,30 @@ int lsir_device(const ls_problem_t* P, const double* W, const void* Bm, const ls
   if (!u32 && pr->u != LS_FP64) return LS_E_UNSUPPORTED;
   if (!u32 && tb == LS_FP32) return LS_E_ARG;   // products not coarser than u
   const int kmax = io->fgmres_maxit;
-#define LS_LSIR_CALL(TA, TB_, TU, DD_) \
-  return lsir_typed<TA, TB_, TU, DD_>(P, W, (const TB_*)Bm, x, r, r_given, io, stats, ws, ws_bytes, st, kmax)
+#define LS_LSIR_CALL(TA, TB_, TU, DD_, AP_) \
+  return lsir_typed<TA, TB_, TU, DD_, AP_>(P, W, (const TB_*)Bm, x, r, r_given, io, stats, ws, ws_bytes, st, kmax)
+  if (fg_apath(pr)) {   // binary32 working precision, binary64 products over A's panels
+    if (P->store == LS_FP32) {
+      if (dd) LS_LSIR_CALL(float, float, float, true, true);
+      LS_LSIR_CALL(float, float, float, false, true);
+    }
+    if (dd) LS_LSIR_CALL(double, double, float, true, true);
+    LS_LSIR_CALL(double, double, float, false, true);
+  }
   if (P->store == LS_FP32) {
     if (tb == LS_FP32) {
-      if (dd) LS_LSIR_CALL(float, float, float, true);
-      LS_LSIR_CALL(float, float, float, false);
+      if (dd) LS_LSIR_CALL(float, float, float, true, false);
+      LS_LSIR_CALL(float, float, float, false, false);
     }
-    if (u32) {
-      if (dd) LS_LSIR_CALL(float, double, float, true);
-      LS_LSIR_CALL(float, double, float, false);
-    }
-    if (dd) LS_LSIR_CALL(float, double, double, true);
-    LS_LSIR_CALL(float, double, double, false);
+    if (dd) LS_LSIR_CALL(float, double, double, true, false);
+    LS_LSIR_CALL(float, double, double, false, false);
   } else {
     if (tb == LS_FP32) {
-      if (dd) LS_LSIR_CALL(double, float, float, true);
-      LS_LSIR_CALL(double, float, float, false);
+      if (dd) LS_LSIR_CALL(double, float, float, true, false);
+      LS_LSIR_CALL(double, float, float, false, false);
     }
-    if (u32) {
-      if (dd) LS_LSIR_CALL(double, double, float, true);
-      LS_LSIR_CALL(double, double, float, false);
-    }
-    if (dd) LS_LSIR_CALL(double, double, double, true);
-    LS_LSIR_CALL(double, double, double, false);
+    if (dd) LS_LSIR_CALL(double, double, double, true, false);
+    LS_LSIR_CALL(double, double, double, false, false);
   }
 #undef LS_LSIR_CALL
 }

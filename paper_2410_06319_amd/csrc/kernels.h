@@ -81,7 +81,16 @@ int lsqr_device(const ls_problem_t* P, const double* R, int64_t ldr, const doubl
                 double* x, const ls_iter_opts_t* io, ls_stats_t* stats, char* ws, size_t ws_bytes, hipStream_t st);
 size_t lsqr_workspace(const ls_problem_t* P, ls_prec_t u, int ncu);
 
-// Refinement with FGMRES on [I B; B^T 0]; B in precision u_A.
+// The operand of the refinement's FGMRES pass.  B-path: B = A W in u_A.
+// A-path (u = binary32 with u_A = binary64): A itself in its storage
+// precision, in B's panel layout, with the products in binary64 and W = R^-1
+// applied on either side (no binary64 copy of B).
+bool fg_apath(const ls_precs_t* pr);
+size_t fg_operand_bytes(const ls_problem_t* P, const ls_precs_t* pr);
+int form_fg_operand(const ls_problem_t* P, const double* W, const float* W32, const ls_precs_t* pr, void* out,
+                    hipStream_t st);
+
+// Refinement with FGMRES on [I B; B^T 0]; Bm from form_fg_operand.
 int lsir_device(const ls_problem_t* P, const double* W, const void* Bm, const ls_precs_t* pr, double* x, double* r,
                 int r_given, const ls_iter_opts_t* io, ls_stats_t* stats, char* ws, size_t ws_bytes,
                 hipStream_t st);

@@ -80,7 +80,7 @@ def _run_workload(L, name, terms, rows, cols):
     rel, lim = _qr_backward(L, Y, wl["u_qr"])
     say(f"{name}: |R^T R - Y^T Y| / |Y|^2 = {rel:.3e} (limit {lim:.1e})")
     assert rel <= lim
-    pr = L.precs(u_s=wl["u_s"], u_qr=wl["u_qr"], u=wl["u"], u_r=wl["u_r"])
+    pr = L.precs(u_s=wl["u_s"], u_qr=wl["u_qr"], u=wl["u"], u_r=wl["u_r"], u_A=wl.get("u_A"))
     S = L.Solver(At, b, s=wl["s"], seed=seed, terms=terms, pr=pr, lsir_tol=TARGET, lsqr_tol=1e-6)
     rc = S(check=False)
     st = S.stats.as_dict()

@@ -637,3 +637,51 @@ def test_solve_rejects_bad_arguments(L):
         with pytest.raises(L.LsError) as e:
             L.ls_sketch(At, b, 40, seed=1, u_s="bf16", terms=1, plan=plan)
         assert e.value.code == -1
+
+
+# ------------------------------------------------------------------ binary64 products over A (A-path)
+# With u = binary32 and u_A = u_L = u_R = binary64 the FGMRES pass streams a
+# panel copy of A (as stored) and applies W = R^-1 on either side, with
+# binary64 products: one refinement step of k FGMRES iterations then matches
+# the oracle's binary64 step up to the rounding of x and r to binary32.
+# Shapes: 4-row panels with a ragged last one, and n from one to sixteen
+# 64-column loads per lane (n = 1100: the widest panels, no prefetch).
+@pytest.mark.parametrize("m,n", [(3001, 40), (5003, 300), (4001, 700), (6002, 1100)])
+@pytest.mark.parametrize("store", ["f32", "f64"])
+def test_refinement_step_with_binary64_products_matches_oracle(L, m, n, store):
+    P = make_problem(m, n, 1e4, seed=25, store=store)
+    R, xs = _lapack_R(P, 2 * n, 5)
+    x0, _ = olsqr.lsqr_precond(P.At, P.b, R, xs, tol=1e-6, maxit=60)
+    A = P.A()
+    r0 = P.b.astype(np.float64) - A @ x0
+    k = 12
+    ox, orr, _ = olsir.lsir(P.At, P.b, R, x0, r0=r0, tol=0.0, maxit=1, fgmres_tol=1e-300, fgmres_maxit=k)
+    x, r = dev(x0.copy()), dev(r0.copy())
+    pr = L.precs(u_s="f64", u_qr="f64", u="f32", u_r="f64", u_A="f64")
+    rc, st = L.ls_lsir_gmres(dev(P.At), dev(P.b), dev(np.ascontiguousarray(R.T)), x, r, pr=pr, r_given=True,
+                             lsir_maxit=1, lsir_tol=1e-300, fgmres_tol=1e-300, fgmres_maxit=k)
+    gx, gr = host(x), host(r)
+    assert st["fgmres_its_total"] == k
+    # x and r leave the step rounded to binary32 (the working precision)
+    ex = np.abs(gx - ox) / (2 * U32 * np.abs(ox) + 1e-9 * np.abs(ox).max())
+    er = np.abs(gr - orr) / (2 * U32 * np.abs(orr) + 1e-9 * np.abs(orr).max())
+    sync_print(f"A-path step m={m} n={n} {store}: max dev/bound x {ex.max():.3f} r {er.max():.3f}")
+    assert ex.max() <= 1.0 and er.max() <= 1.0
+
+
+@pytest.mark.parametrize("m,n,kappa", [(20000, 100, 1e4), (6003, 700, 1e5), (5003, 1100, 1e4)])
+def test_solve_with_binary64_products_reaches_target(L, m, n, kappa):
+    P = make_problem(m, n, kappa, seed=2410064196, store="f32")
+    xr, rr, _ = refsolve.ref_solve(P.At, P.b)
+    res = {}
+    for uA in ("f32", "f64"):
+        pr = L.precs(u_s="bf16", u_qr="f32", u="f32", u_r="f64", u_A=uA)
+        x, r, rc, st = L.ls_solve(dev(P.At), dev(P.b), s=max(4 * n, n + 1), seed=3, terms=3, pr=pr, lsir_tol=6e-6)
+        ex, er = refsolve.forward_errors(host(x), host(r), xr, rr)
+        res[uA] = (rc, st["lsir_its"], st["fgmres_its_total"], ex, er)
+        sync_print(f"m={m} n={n} kappa={kappa:.0e} u_A={uA}: status {rc}, lsir {st['lsir_its']}, "
+                   f"fgmres {st['fgmres_its_total']}, err x {ex:.2e} r {er:.2e}")
+    for rc, _, _, ex, er in res.values():
+        assert rc == 0 and ex <= 6e-6 and er <= 6e-6
+    # binary64 products need no more refinement steps than binary32 ones
+    assert res["f64"][1] <= res["f32"][1]
