@@ -318,7 +318,7 @@ def main():
                           "source_sha256_16": kernel_source_hash()}), flush=True)
         return
     res, P, seed = run_workload(L, name, terms, args.steps, args.warmup, not args.no_fp64, not args.no_sparse,
-                                True)
+                                name == SECONDARY)
     mixed = wl["u"] == "f32"
     out = {
         "metric": METRIC, "value": res.pop("value"), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -329,7 +329,7 @@ def main():
     out.update(res)
     if not args.no_secondary and name != SECONDARY:
         # the m = 1e5, n = 500 bf16 workload, reported beside the headline
-        sec, _, _ = run_workload(L, SECONDARY, DEFAULT_TERMS[SECONDARY], 20, 3, not args.no_fp64, False, False)
+        sec, _, _ = run_workload(L, SECONDARY, DEFAULT_TERMS[SECONDARY], 20, 3, not args.no_fp64, False, True)
         out["secondary"] = sec
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline (bounded sample)")
