@@ -121,6 +121,12 @@ typedef struct {
                         autotune module, for the shape, format and parts), k >= 1 =
                         candidate k of ls_sketch_plan_info.  Changes the
                         grouping of the binary32 partial sums, not the method */
+  int32_t *col_exp;  /* optional output (device, n + 1 entries; NULL: not wanted):
+                        the exponents e_j of the Section 3.2 column scaling the
+                        sketch applied (0 where it scaled nothing).  Y itself is
+                        always the sketch of the unscaled [A b], so R needs no
+                        correction; the exponents say how far each column of
+                        [A b] was shifted into the format's range */
 } ls_sketch_opts_t;
 
 /* Iteration control (Section 5): LSQR at most 2n iterations, tolerance 1e-6
@@ -156,6 +162,13 @@ typedef struct {
                             min(1e-2, max(fgmres_tol, 0.1 lsir_tol / rho)), rho the larger
                             relative correction of x and r in the previous step: a step
                             whose correction is far below lsir_tol needs it only roughly */
+  /* x_ref, r_ref: optional (both or neither): device, binary64, the solution x*
+   * (length n) and residual r* = b - A x* (length m).  Given, the refinement
+   * stops as in Section 5, once the forward errors ||x* - x|| / ||x*|| and
+   * ||r* - r|| / ||r*|| are both at most lsir_tol, and ls_stats_t reports them
+   * (err_x, err_r). */
+  const double *x_ref;
+  const double *r_ref;
 } ls_iter_opts_t;
 
 /* Results and timings of one call. */
@@ -188,6 +201,8 @@ typedef struct {
                              (ls_solve): kappa_2(R) / sqrt(n) <= kappa_est <=
                              sqrt(n) kappa_2(R), and kappa_2(R) is kappa(A) up to
                              the embedding's distortion (Section 2) */
+  double err_x, err_r;    /* with x_ref and r_ref: the forward errors after the last
+                             refinement step; -1 otherwise */
 } ls_stats_t;
 
 /* Fill the defaults described above for a problem with n columns and

@@ -27,7 +27,7 @@ class Precs(ctypes.Structure):
 class SketchOpts(ctypes.Structure):
     _fields_ = [("s", ctypes.c_int64), ("seed", ctypes.c_uint64), ("prob_id", ctypes.c_uint32),
                 ("terms", ctypes.c_int32), ("col_scale", ctypes.c_int32), ("zeta", ctypes.c_int32),
-                ("max_terms", ctypes.c_int32), ("plan", ctypes.c_int32)]
+                ("max_terms", ctypes.c_int32), ("plan", ctypes.c_int32), ("col_exp", ctypes.c_void_p)]
 
 
 class IterOpts(ctypes.Structure):
@@ -35,7 +35,7 @@ class IterOpts(ctypes.Structure):
                 ("fgmres_tol", ctypes.c_double), ("fgmres_maxit", ctypes.c_int32),
                 ("lsir_maxit", ctypes.c_int32), ("lsir_tol", ctypes.c_double),
                 ("fallback", ctypes.c_int32), ("check_every", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("inner_adapt", ctypes.c_int32)]
+                ("inner_adapt", ctypes.c_int32), ("x_ref", ctypes.c_void_p), ("r_ref", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -47,7 +47,8 @@ class Stats(ctypes.Structure):
                 ("ms_qr", ctypes.c_double), ("ms_lsqr", ctypes.c_double), ("ms_lsir", ctypes.c_double),
                 ("kernel_ms", ctypes.c_double * 6), ("kernel_launches", ctypes.c_int32 * 6),
                 ("kernel_work", ctypes.c_double * 6), ("sketch_terms", ctypes.c_int32),
-                ("sketch_plan", ctypes.c_int32), ("kappa_est", ctypes.c_double)]
+                ("sketch_plan", ctypes.c_int32), ("kappa_est", ctypes.c_double), ("err_x", ctypes.c_double),
+                ("err_r", ctypes.c_double)]
 
     KERNEL_CLASSES = ("sketch_mfma", "lsqr_pass", "fgmres_pass", "lsir_resid_pass", "cgs_sweep", "sparse_sketch")
 

@@ -49,9 +49,9 @@ def precs(u_s="bf16", u_qr="f32", u="f32", u_r="f64", u_A=None, u_L=None, u_R=No
                    u_A=B.PREC[u_A], u_L=B.PREC[u_L or u_A], u_R=B.PREC[u_R or u_A])
 
 
-def sketch_opts(s=0, seed=0, prob_id=0, terms=1, col_scale=0, zeta=0, max_terms=0, plan=0) -> B.SketchOpts:
+def sketch_opts(s=0, seed=0, prob_id=0, terms=1, col_scale=0, zeta=0, max_terms=0, plan=0, col_exp=None) -> B.SketchOpts:
     return B.SketchOpts(s=s, seed=seed, prob_id=prob_id, terms=terms, col_scale=col_scale, zeta=zeta,
-                        max_terms=max_terms, plan=plan)
+                        max_terms=max_terms, plan=plan, col_exp=col_exp)
 
 
 def iter_opts(n, u="f32", **kw) -> B.IterOpts:
@@ -87,12 +87,15 @@ def qr_workspace_size(s, ncols, u_qr="f32") -> int:
     return n.value
 
 
-def ls_sketch(At, b, s, seed=0, u_s="bf16", terms=1, prob_id=0, col_scale=0, zeta=0, ws=None, plan=0):
+def ls_sketch(At, b, s, seed=0, u_s="bf16", terms=1, prob_id=0, col_scale=0, zeta=0, ws=None, plan=0,
+              col_exp=None):
     """Y = Omega [A b] (s x (n+1), float64; returned as a (n+1, s) tensor = column-major Y).
 
-    u_s: "f64", "bf16", "f16" or "e4m3"; col_scale 0 = automatic (on for f16 and e4m3)."""
+    u_s: "f64", "bf16", "f16" or "e4m3"; col_scale 0 = automatic (on for f16 and e4m3);
+    col_exp: optional int32 device tensor of n+1 entries receiving the column exponents."""
     P = problem(At, b)
-    so = sketch_opts(s=s, seed=seed, prob_id=prob_id, terms=terms, col_scale=col_scale, zeta=zeta, plan=plan)
+    so = sketch_opts(s=s, seed=seed, prob_id=prob_id, terms=terms, col_scale=col_scale, zeta=zeta, plan=plan,
+                     col_exp=None if col_exp is None else col_exp.data_ptr())
     pr = precs(u_s=u_s, u_qr="f64", u="f64", u_r="f64")
     if ws is None:
         ws = workspace(workspace_size(P, so, pr, iter_opts(P.n, "f64")), At.device)
@@ -197,6 +200,9 @@ def ls_solve_batched(problems, s=0, seeds=None, terms=1, pr=None, col_scale=0, n
                                    for i in range(nprob)])
     pr = pr or precs()
     io = iter_opts(max(p.n for p in Ps), "f64" if pr.u == B.FP64 else "f32", **opts)
+    # the LSQR limit 2n is per problem (Section 5): zero lets the library take each problem's own
+    if "lsqr_maxit" not in opts:
+        io.lsqr_maxit = 0
     nbytes = ctypes.c_size_t(0)
     _check(B.load().ls_workspace_size_batched(nprob, Ps, sos, ctypes.byref(pr), ctypes.byref(io), nworkers,
                                               ctypes.byref(nbytes)), "ls_workspace_size_batched")

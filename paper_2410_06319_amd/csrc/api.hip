@@ -382,7 +382,10 @@ int ls_lsqr_precond(const ls_problem_t* P, const double* R, int64_t ldr, ls_prec
   LS_TRY(make_inverse(R, ldr, P->n, inv, st));
   void* Bm = base + inv.bytes;
   LS_TRY(form_b(P, inv.W, inv.W32, u, Bm, st));
-  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->err_x = stats->err_r = -1.0;
+  }
   prof_reset(io.profile != 0);
   const int rc = lsqr_device(P, R, ldr, inv.W, Bm, u, x, &io, stats, base + inv.bytes + bb,
                              ws_bytes - inv.bytes - bb, st);
@@ -411,7 +414,10 @@ int ls_lsir_gmres(const ls_problem_t* P, const double* R, int64_t ldr, const ls_
   LS_TRY(make_inverse(R, ldr, P->n, inv, st));
   void* Bm = base + inv.bytes;
   LS_TRY(form_fg_operand(P, inv.W, inv.W32, pr, Bm, st));
-  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->err_x = stats->err_r = -1.0;
+  }
   prof_reset(io.profile != 0);
   const int rc = lsir_device(P, inv.W, Bm, pr, x, r, r_given, &io, stats, base + inv.bytes + bb,
                              ws_bytes - inv.bytes - bb, st);
@@ -441,6 +447,7 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
   ls_stats_t local;
   ls_stats_t* S = stats ? stats : &local;
   std::memset(S, 0, sizeof(*S));
+  S->err_x = S->err_r = -1.0;
 
   char* base = static_cast<char*>(ws);
   size_t off = 0;

@@ -922,6 +922,8 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
   row_range(npan, (int)nw, blockIdx.x * 4 + wave, p0, p1);
   vec_t cur[Q];
   double vro[PR];
+  // v_j's rows of a panel: 16-byte loads where the column is aligned to them
+  const bool vvec = (((uintptr_t)vj | (uintptr_t)w) & 15) == 0;
   auto load = [&](int64_t p, vec_t* dst, double* vr_) {
     const TB* base = Bp + p * (PR * n);
 #pragma unroll
@@ -930,8 +932,17 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
       dst[q] = (c < n) ? *reinterpret_cast<const vec_t*>(base + c * PR) : vec_t{};
     }
     const int64_t i0 = p * PR;
+    if (vvec && i0 + PR <= m) {
 #pragma unroll
-    for (int k = 0; k < PR; ++k) vr_[k] = (i0 + k < m) ? vj[i0 + k] : 0.0;
+      for (int k = 0; k < PR; k += 2) {
+        const ls_double2v t2 = *reinterpret_cast<const ls_double2v*>(vj + i0 + k);
+        vr_[k] = t2[0];
+        vr_[k + 1] = t2[1];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < PR; ++k) vr_[k] = (i0 + k < m) ? vj[i0 + k] : 0.0;
+    }
   };
   // the first panel of B and its rows of v_j do not depend on ||w||: their
   // loads go out before the norm's partials are summed
@@ -1031,13 +1042,15 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
       const TC sk = wave_allsum(s[k]);
       wr[k] = (i0 + k < m) ? (double)(vrt[k] + sk) : 0.0;
     }
-    if (lane == 0) {
+    // every lane holds the panel's rows of v_j and w: lanes 0 .. PR-1 store
+    // v_j's, lanes PR .. 2 PR-1 w's (one store instruction)
+    if (lane < 2 * PR) {
+      const int k = lane % PR;
+      double val = 0.0;
 #pragma unroll
-      for (int k = 0; k < PR; ++k)
-        if (i0 + k < m) {
-          vj[i0 + k] = vr[k];
-          w[i0 + k] = wr[k];
-        }
+      for (int k2 = 0; k2 < PR; ++k2)
+        if (k2 == k) val = (lane < PR) ? vr[k2] : wr[k2];
+      if (i0 + k < m) ((lane < PR) ? vj : w)[i0 + k] = val;
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q)
@@ -1384,14 +1397,15 @@ __global__ __launch_bounds__(kSweepThreads) void k_cgs2(FgPtrs F, int64_t m, int
 }
 
 // Correction of one refinement step: y = H(0:k,0:k)^-1 g(0:k) (every block);
-// rows < m: dr = V_r y, r += dr (working precision TU), partial norms;
+// rows < m: dr = V_r y, r += dr (working precision TU), partial norms of dr
+// and r (and, with r_ref, of r - r_ref and r_ref), four per block;
 // rows >= m: dz = V_x y -> dz buffer.
 template <typename TU>
 __global__ __launch_bounds__(kThreads) void k_fg_update(FgPtrs F, int64_t m, int64_t n, int kmax,
                                                         double* __restrict__ r, double* __restrict__ dz,
-                                                        double* __restrict__ part) {
+                                                        double* __restrict__ part, const double* __restrict__ r_ref) {
   __shared__ double y[128];
-  __shared__ double dsh[8];
+  __shared__ double dsh[16];
   __shared__ double Hs[kMaxKrylov * (kMaxKrylov + 1) / 2];   // upper triangle, column c at c (c + 1) / 2
   const int k = F.st->k;
   const int64_t ldh = kmax + 1;
@@ -1429,7 +1443,7 @@ __global__ __launch_bounds__(kThreads) void k_fg_update(FgPtrs F, int64_t m, int
   }
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  double a0 = 0.0, a1 = 0.0;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   if (i < m + n) {
     const double d = (k > 0) ? vrow_dot(F.V, F.ldv, i, k - 1, y) : 0.0;
     if (i < m) {
@@ -1437,39 +1451,60 @@ __global__ __launch_bounds__(kThreads) void k_fg_update(FgPtrs F, int64_t m, int
       r[i] = rn;
       a0 = d * d;
       a1 = rn * rn;
+      if (r_ref) {
+        const double rr = r_ref[i];
+        a2 = (rn - rr) * (rn - rr);
+        a3 = rr * rr;
+      }
     } else {
       dz[i - m] = d;
     }
   }
   a0 = block_sum256(a0, dsh);
   a1 = block_sum256(a1, dsh + 4);
+  a2 = block_sum256(a2, dsh + 8);
+  a3 = block_sum256(a3, dsh + 12);
   if (threadIdx.x == 0) {
-    part[2 * (int64_t)blockIdx.x] = a0;
-    part[2 * (int64_t)blockIdx.x + 1] = a1;
+    double* p = part + 4 * (int64_t)blockIdx.x;
+    p[0] = a0;
+    p[1] = a1;
+    p[2] = a2;
+    p[3] = a3;
   }
 }
 
-// dx = W dz (R^-1 on the x part of the correction), x += dx (TU); partial norms.
+// dx = W dz (R^-1 on the x part of the correction), x += dx (TU); partial
+// norms of dx and x (and, with x_ref, of x - x_ref and x_ref), four per block.
 template <typename TU>
 __global__ __launch_bounds__(kUtThreads) void k_fg_dx(const double* __restrict__ W, int64_t n,
                                                       const double* __restrict__ dz, double* __restrict__ x,
-                                                      double* __restrict__ part) {
+                                                      double* __restrict__ part, const double* __restrict__ x_ref) {
   __shared__ double red[32 * 33];
   const double d = ls_utmv_row(W, n, n, [&](int64_t j) { return dz[j]; }, red);
   const int64_t row = (int64_t)blockIdx.x * 32 + threadIdx.x;
-  double a0 = 0.0, a1 = 0.0;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   if (threadIdx.x < 32 && row < n) {
     const double xn = (double)((TU)x[row] + (TU)d);
     x[row] = xn;
     a0 = d * d;
     a1 = xn * xn;
+    if (x_ref) {
+      const double xr = x_ref[row];
+      a2 = (xn - xr) * (xn - xr);
+      a3 = xr * xr;
+    }
   }
   if (threadIdx.x < 64) {   // rows of the block live in the first wave
     a0 = ls_wave_sum(a0);
     a1 = ls_wave_sum(a1);
+    a2 = ls_wave_sum(a2);
+    a3 = ls_wave_sum(a3);
     if (threadIdx.x == 0) {
-      part[2 * (int64_t)blockIdx.x] = a0;
-      part[2 * (int64_t)blockIdx.x + 1] = a1;
+      double* p = part + 4 * (int64_t)blockIdx.x;
+      p[0] = a0;
+      p[1] = a1;
+      p[2] = a2;
+      p[3] = a3;
     }
   }
 }
@@ -1855,7 +1890,7 @@ struct LsirWs {
   double* rt_lo;      // n x Gr
   double* gvec;       // n
   double* dz;         // n
-  double* upart;      // 2 x (Gd + Gn)
+  double* upart;      // 4 x (Gd + Gn)
   double* xin;        // n: W V_x[:, j] (A-path)
   double* tbuf;       // n: A^T v_r (A-path)
   size_t bytes;
@@ -1903,7 +1938,7 @@ LsirWs lsir_carve(char* ws, const ls_problem_t* P, const LsirDims& d, size_t tb_
   w.ldv = m + n;
   w.st = reinterpret_cast<FgState*>(take(sizeof(FgState)));
   // right after the state: the host reads both back with one copy per step
-  w.upart = reinterpret_cast<double*>(take(8 * 2 * (size_t)(d.Gd + d.Gn)));
+  w.upart = reinterpret_cast<double*>(take(8 * 4 * (size_t)(d.Gd + d.Gn)));
   w.V = reinterpret_cast<double*>(take(8 * (size_t)w.ldv * (kmax + 1)));
   w.H = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1) * kmax));
   w.cs = reinterpret_cast<double*>(take(8 * (size_t)kmax));
@@ -1972,9 +2007,11 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
   };
   int total_fg = 0, its = 0, status = LS_NOT_CONVERGED;
   double dx_rel = 0.0, dr_rel = 0.0;
-  std::vector<double> up(2 * (size_t)(d.Gd + d.Gn));
+  std::vector<double> up(4 * (size_t)(d.Gd + d.Gn));
   std::vector<char> rb((size_t)(reinterpret_cast<char*>(w.upart) - reinterpret_cast<char*>(w.st)) +
-                       8 * 2 * (size_t)(d.Gd + d.Gn));
+                       8 * 4 * (size_t)(d.Gd + d.Gn));
+  const bool with_ref = io->x_ref && io->r_ref;
+  double err_x = -1.0, err_r = -1.0;
   for (its = 1; its <= io->lsir_maxit; ++its) {
     if (io->inner_adapt && its > 1) {
       const double rho = std::max(dx_rel, dr_rel);
@@ -2035,9 +2072,10 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
     }
     // final Givens step for the last column (no-op when already done)
     fg_pass(j < d.kmax ? j + 1 : d.kmax, d.Gs, 1, 1, ProfEv{});
-    hipLaunchKernelGGL(k_fg_update<TU>, dim3((unsigned)d.Gd), dim3(kThreads), 0, st, F, m, n, d.kmax, r, w.dz, w.upart);
+    hipLaunchKernelGGL(k_fg_update<TU>, dim3((unsigned)d.Gd), dim3(kThreads), 0, st, F, m, n, d.kmax, r, w.dz, w.upart,
+                       with_ref ? io->r_ref : nullptr);
     hipLaunchKernelGGL(k_fg_dx<TU>, dim3((unsigned)d.Gn), dim3(kUtThreads), 0, st, W, n, w.dz, x,
-                       w.upart + 2 * (size_t)d.Gd);
+                       w.upart + 4 * (size_t)d.Gd, with_ref ? io->x_ref : nullptr);
     // the state and the norm partials in one copy (each copy to pageable
     // memory costs a round trip of the host)
     const size_t up_off = (size_t)(reinterpret_cast<char*>(w.upart) - reinterpret_cast<char*>(w.st));
@@ -2045,25 +2083,29 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
     LS_HIP_TRY(hipStreamSynchronize(st));
     LS_HIP_TRY(hipGetLastError());
     std::memcpy(&S, rb.data(), sizeof(FgState));
-    std::memcpy(up.data(), rb.data() + up_off, 8 * 2 * (size_t)(d.Gd + d.Gn));
+    std::memcpy(up.data(), rb.data() + up_off, 8 * 4 * (size_t)(d.Gd + d.Gn));
     if (S.breakdown == 2) return LS_E_NONFINITE;
     // passes and sweeps of columns 0 .. k-1; later ones were queued past convergence
     prof_keep(kProfFgPass, pmark, S.k);
     prof_keep(kProfCgs, pmark, S.k);
     total_fg += S.k;
-    double nr[2] = {0, 0}, nx[2] = {0, 0};
-    for (int g = 0; g < d.Gd; ++g) {
-      nr[0] += up[2 * (size_t)g];
-      nr[1] += up[2 * (size_t)g + 1];
-    }
-    for (int g = 0; g < d.Gn; ++g) {
-      nx[0] += up[2 * (size_t)(d.Gd + g)];
-      nx[1] += up[2 * (size_t)(d.Gd + g) + 1];
-    }
+    double nr[4] = {0, 0, 0, 0}, nx[4] = {0, 0, 0, 0};
+    for (int g = 0; g < d.Gd; ++g)
+      for (int q = 0; q < 4; ++q) nr[q] += up[4 * (size_t)g + q];
+    for (int g = 0; g < d.Gn; ++g)
+      for (int q = 0; q < 4; ++q) nx[q] += up[4 * (size_t)(d.Gd + g) + q];
     dr_rel = sqrt(nr[0]) / (nr[1] > 0 ? sqrt(nr[1]) : 1.0);
     dx_rel = sqrt(nx[0]) / (nx[1] > 0 ? sqrt(nx[1]) : 1.0);
     if (!std::isfinite(dr_rel) || !std::isfinite(dx_rel)) return LS_E_NONFINITE;
-    if (dx_rel <= lsir_tol && dr_rel <= lsir_tol) {
+    if (with_ref) {
+      // Section 5's test: forward errors of x and r against the given solution
+      err_r = sqrt(nr[2]) / (nr[3] > 0 ? sqrt(nr[3]) : 1.0);
+      err_x = sqrt(nx[2]) / (nx[3] > 0 ? sqrt(nx[3]) : 1.0);
+      if (err_x <= lsir_tol && err_r <= lsir_tol) {
+        status = LS_OK;
+        break;
+      }
+    } else if (dx_rel <= lsir_tol && dr_rel <= lsir_tol) {
       status = LS_OK;
       break;
     }
@@ -2074,6 +2116,8 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
     stats->fgmres_its_total += total_fg;
     stats->lsir_dx_rel = dx_rel;
     stats->lsir_dr_rel = dr_rel;
+    stats->err_x = err_x;
+    stats->err_r = err_r;
   }
   return status;
 }

@@ -729,6 +729,12 @@ int sketch_narrow(const ls_problem_t* P, const ls_sketch_opts_t* so, const Sketc
   hipLaunchKernelGGL(k_sketch_combine<float>, dim3((unsigned)ls_cdiv(s, 256), (unsigned)p.ncols), dim3(256), 0, st, Yp,
                      p.s_pad, p.n_pad, (int)p.nsplit, s, p.ncols, 1.0 / sqrt((double)s), (const int32_t*)e, Y, ldy);
   LS_HIP_TRY(hipGetLastError());
+  if (so->col_exp) {
+    if (e)
+      LS_HIP_TRY(hipMemcpyAsync(so->col_exp, e, 4 * (size_t)p.ncols, hipMemcpyDeviceToDevice, st));
+    else
+      LS_HIP_TRY(hipMemsetAsync(so->col_exp, 0, 4 * (size_t)p.ncols, st));
+  }
   return LS_OK;
 }
 
@@ -749,7 +755,10 @@ bool sketch_colscale(ls_prec_t u_s, int32_t col_scale) {
 
 int sketch_run(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s, const SketchPlan& p,
                int64_t s, double* Y, int64_t ldy, char* ws, hipStream_t st) {
-  if (p.zeta > 0) return sparse_run(P, so, s, Y, ldy, ws, st);
+  if (p.zeta > 0) {
+    if (so->col_exp) LS_HIP_TRY(hipMemsetAsync(so->col_exp, 0, 4 * (size_t)(P->n + 1), st));
+    return sparse_run(P, so, s, Y, ldy, ws, st);
+  }
   if (p.terms < 1 || p.terms > kMaxSketchTerms) return LS_E_ARG;
   const bool cs = sketch_colscale(u_s, so->col_scale);
   if (u_s == LS_BF16) return sketch_narrow_store<LS_BF16>(P, so, p, s, Y, ldy, ws, cs, st);
@@ -779,6 +788,7 @@ int sketch_run(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s,
   hipLaunchKernelGGL(k_sketch_combine<double>, gcomb, dim3(256), 0, st, Yp, p.s_pad, p.n_pad,
                      (int)p.nsplit, s, p.ncols, scale, (const int32_t*)nullptr, Y, ldy);
   LS_HIP_TRY(hipGetLastError());
+  if (so->col_exp) LS_HIP_TRY(hipMemsetAsync(so->col_exp, 0, 4 * (size_t)p.ncols, st));
   return LS_OK;
 }
 

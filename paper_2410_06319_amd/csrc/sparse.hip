@@ -9,14 +9,16 @@
 //      t = 0, 1, ...: word w proposes row floor(w s / 2^32), negative when w
 //      is odd; a proposal equal to an earlier row of the column is skipped;
 //      (destination row, 2 i + sign bit) pairs are written in (i, draw) order;
-//   2. a stable radix sort of the pairs by destination row, so that each row
-//      of Y lists its sources in increasing i;
+//   2. a stable counting sort of the pairs by destination row, so that each
+//      row of Y lists its sources in increasing i: per tile of kTileRows
+//      source rows an LDS histogram of destinations, a scan over (tile,
+//      destination) giving every tile its first slot per destination, then
+//      one wave per tile places its pairs in source order (a pair's rank
+//      among equal destinations of its round of 64 rows by comparison in LDS);
 //   3. [A b] is copied to row-major order (one pass), so that a source row is
 //      one contiguous read;
 //   4. one block per row of Y adds its source rows, with their signs, in that
 //      order in binary64, then multiplies by 1/sqrt(zeta).
-#include <hipcub/hipcub.hpp>
-
 #include "common.h"
 #include "kernels.h"
 
@@ -67,6 +69,132 @@ __global__ __launch_bounds__(kDrawThreads) void k_ss_draw(int64_t m, int64_t s, 
   }
 }
 
+// ------------------------------------------------------------------ counting sort
+constexpr int kTileRows = 256;     // source rows per tile of the counting sort
+constexpr int kScanGroup = 32;     // tiles per group of the offset scan
+constexpr int kSortBuckets = 8192; // destinations (rows of Y) the LDS histogram holds
+
+// cnt[t s + r] = pairs of tile t with destination r (tile-major, so that the
+// writes are coalesced).  Integer LDS atomics: the counts do not depend on
+// their order.
+__global__ __launch_bounds__(256) void k_ss_count(int64_t m, int64_t s, int zeta, const uint32_t* __restrict__ keys,
+                                                  uint32_t* __restrict__ cnt) {
+  __shared__ uint32_t h[kSortBuckets];
+  const int64_t t = blockIdx.x;
+  for (int64_t r = threadIdx.x; r < s; r += 256) h[r] = 0u;
+  __syncthreads();
+  const int64_t i = t * kTileRows + threadIdx.x;
+  if (i < m)
+    for (int k = 0; k < zeta; ++k) {
+      const uint32_t d = keys[i * zeta + k];
+      if (d < (uint32_t)s) atomicAdd(&h[d], 1u);
+    }
+  __syncthreads();
+  for (int64_t r = threadIdx.x; r < s; r += 256) cnt[t * s + r] = h[r];
+}
+
+// Exclusive prefix over the tiles of each group (in place) and the group
+// totals gsum[g s + r]; thread per destination, the group's tiles in order.
+__global__ __launch_bounds__(256) void k_ss_scan_tiles(int64_t s, int64_t ntile, uint32_t* __restrict__ cnt,
+                                                       uint32_t* __restrict__ gsum) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t g = blockIdx.y;
+  if (r >= s) return;
+  uint32_t acc = 0u;
+  const int64_t t1 = (g + 1) * kScanGroup < ntile ? (g + 1) * kScanGroup : ntile;
+  for (int64_t t = g * kScanGroup; t < t1; ++t) {
+    const uint32_t c = cnt[t * s + r];
+    cnt[t * s + r] = acc;
+    acc += c;
+  }
+  gsum[g * s + r] = acc;
+}
+
+// Exclusive prefix over the groups of each destination (in place) and the
+// destination totals; then (one block) the exclusive scan of the totals gives
+// start[r], the first slot of destination r (start[s] = all pairs).
+__global__ __launch_bounds__(256) void k_ss_scan_groups(int64_t s, int64_t ngroup, uint32_t* __restrict__ gsum,
+                                                        uint32_t* __restrict__ total) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= s) return;
+  uint32_t acc = 0u;
+  for (int64_t g = 0; g < ngroup; ++g) {
+    const uint32_t c = gsum[g * s + r];
+    gsum[g * s + r] = acc;
+    acc += c;
+  }
+  total[r] = acc;
+}
+
+__global__ __launch_bounds__(1024) void k_ss_scan_starts(int64_t s, const uint32_t* __restrict__ total,
+                                                         int64_t* __restrict__ start) {
+  __shared__ int64_t part[1024];
+  // each thread a contiguous run of destinations, then a scan of the run sums
+  const int64_t per = ls_cdiv(s, 1024);
+  const int64_t r0 = (int64_t)threadIdx.x * per;
+  int64_t sum = 0;
+  for (int64_t r = r0; r < r0 + per && r < s; ++r) sum += total[r];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int64_t v = (threadIdx.x >= (unsigned)off) ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int64_t acc = (threadIdx.x > 0) ? part[threadIdx.x - 1] : 0;
+  for (int64_t r = r0; r < r0 + per && r < s; ++r) {
+    start[r] = acc;
+    acc += total[r];
+  }
+  if (threadIdx.x == 1023) start[s] = part[1023];
+}
+
+// One wave per tile: its pairs go to start[r] + (group offset) + (tile
+// offset) + (rank among the tile's earlier pairs with destination r), in
+// source order.  Rounds of 64 source rows (lane = row); a pair's rank within
+// its round counts the pairs of lower lanes with the same destination (the
+// pairs of one row have distinct destinations), read from LDS.
+__global__ __launch_bounds__(64) void k_ss_scatter(int64_t m, int64_t s, int zeta, const uint32_t* __restrict__ keys,
+                                                   const uint32_t* __restrict__ vals,
+                                                   const uint32_t* __restrict__ cnt,
+                                                   const uint32_t* __restrict__ gsum,
+                                                   const int64_t* __restrict__ start,
+                                                   uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+  __shared__ uint32_t base[kSortBuckets];
+  __shared__ uint32_t rk[64 * kZetaMax];
+  const int lane = threadIdx.x;
+  const int64_t t = blockIdx.x;
+  const int64_t g = t / kScanGroup;
+  for (int64_t r = lane; r < s; r += 64) base[r] = (uint32_t)start[r] + gsum[g * s + r] + cnt[t * s + r];
+  __syncthreads();
+  for (int rd = 0; rd < kTileRows / 64; ++rd) {
+    const int64_t i = t * kTileRows + rd * 64 + lane;
+    const bool live = i < m;
+    uint32_t mk[kZetaMax], mv[kZetaMax];
+    for (int k = 0; k < zeta; ++k) {
+      mk[k] = live ? keys[i * zeta + k] : 0xffffffffu;
+      mv[k] = live ? vals[i * zeta + k] : 0u;
+      rk[lane * zeta + k] = mk[k];
+    }
+    __syncthreads();
+    for (int k = 0; k < zeta; ++k) {
+      const uint32_t d = mk[k];
+      if (!live || d >= (uint32_t)s) continue;   // failed draws point past the last row
+      uint32_t rank = 0;
+      for (int l = 0; l < lane; ++l)
+        for (int k2 = 0; k2 < zeta; ++k2) rank += (rk[l * zeta + k2] == d) ? 1u : 0u;
+      const uint32_t pos = base[d] + rank;
+      keys_out[pos] = d;
+      vals_out[pos] = mv[k];
+    }
+    __syncthreads();
+    for (int k = 0; k < zeta; ++k)
+      if (live && mk[k] < (uint32_t)s) atomicAdd(&base[mk[k]], 1u);
+    __syncthreads();
+  }
+}
+
 // T (m x (n+1), row-major) = [A b]; 32 x 32 tiles through LDS.
 template <typename TA>
 __global__ __launch_bounds__(256) void k_ss_transpose(const TA* __restrict__ A, int64_t lda, const TA* __restrict__ b,
@@ -87,24 +215,6 @@ __global__ __launch_bounds__(256) void k_ss_transpose(const TA* __restrict__ A, 
     const int64_t i = i0 + ty + 8 * k, j = j0 + tx;
     if (i < m && j <= n) T[i * (n + 1) + j] = tile[tx][ty + 8 * k];
   }
-}
-
-// First index e in [0, N) with key[e] >= r (keys sorted).
-__device__ int64_t lower_bound_u32(const uint32_t* __restrict__ key, int64_t N, uint32_t r) {
-  int64_t lo = 0, hi = N;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (key[mid] < r) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
-
-// start[r] = first sorted entry with destination >= r, r = 0 .. s.
-__global__ __launch_bounds__(256) void k_ss_starts(const uint32_t* __restrict__ keys, int64_t N, int64_t s,
-                                                   int64_t* __restrict__ start) {
-  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (r <= s) start[r] = lower_bound_u32(keys, N, (uint32_t)r);
 }
 
 // Row r of Y (one block): sum over its sources e (increasing i) of
@@ -165,21 +275,15 @@ struct SparseCarve {
   uint32_t *keys_in, *vals_in, *keys_out, *vals_out;
   int* fail;
   int64_t* start;
-  void* tmp;
-  size_t tmp_bytes;
+  uint32_t *cnt, *gsum, *total;
   char* T;
   size_t bytes;
 };
 
-int sort_bits(int64_t s) {
-  int b = 1;
-  while (((int64_t)1 << b) < s) ++b;
-  return b;
-}
-
 SparseCarve sparse_carve(char* ws, int64_t m, int64_t n, int zeta, int64_t s, size_t ta_bytes) {
   SparseCarve c{};
   const int64_t N = m * zeta;
+  const int64_t ntile = ls_cdiv(m, kTileRows), ngroup = ls_cdiv(ntile, kScanGroup);
   size_t off = 0;
   auto take = [&](size_t b) {
     char* q = ws ? ws + off : nullptr;
@@ -192,11 +296,9 @@ SparseCarve sparse_carve(char* ws, int64_t m, int64_t n, int zeta, int64_t s, si
   c.vals_out = reinterpret_cast<uint32_t*>(take(4 * (size_t)N));
   c.fail = reinterpret_cast<int*>(take(sizeof(int)));
   c.start = reinterpret_cast<int64_t*>(take(8 * (size_t)(s + 1)));
-  size_t tb = 0;
-  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (const uint32_t*)nullptr, (uint32_t*)nullptr,
-                                           (const uint32_t*)nullptr, (uint32_t*)nullptr, (int)N, 0, sort_bits(s + 1));
-  c.tmp_bytes = tb;
-  c.tmp = take(tb);
+  c.cnt = reinterpret_cast<uint32_t*>(take(4 * (size_t)ntile * s));
+  c.gsum = reinterpret_cast<uint32_t*>(take(4 * (size_t)ngroup * s));
+  c.total = reinterpret_cast<uint32_t*>(take(4 * (size_t)s));
   c.T = take(ta_bytes * (size_t)m * (size_t)(n + 1));
   c.bytes = off;
   return c;
@@ -213,10 +315,15 @@ int sparse_typed(const ls_problem_t* P, const ls_sketch_opts_t* so, int64_t s, d
   LS_HIP_TRY(hipMemsetAsync(c.fail, 0, sizeof(int), st));
   hipLaunchKernelGGL(k_ss_draw, dim3((unsigned)ls_cdiv(m, kDrawThreads)), dim3(kDrawThreads), 0, st, m, s, zeta, key0,
                      key1, so->prob_id, c.keys_in, c.vals_in, c.fail);
-  size_t tb = c.tmp_bytes;
-  LS_HIP_TRY(hipcub::DeviceRadixSort::SortPairs(c.tmp, tb, c.keys_in, c.keys_out, c.vals_in, c.vals_out, (int)N, 0,
-                                                sort_bits(s + 1), st));
-  hipLaunchKernelGGL(k_ss_starts, dim3((unsigned)ls_cdiv(s + 1, 256)), dim3(256), 0, st, c.keys_out, N, s, c.start);
+  const int64_t ntile = ls_cdiv(m, kTileRows), ngroup = ls_cdiv(ntile, kScanGroup);
+  hipLaunchKernelGGL(k_ss_count, dim3((unsigned)ntile), dim3(256), 0, st, m, s, zeta, c.keys_in, c.cnt);
+  hipLaunchKernelGGL(k_ss_scan_tiles, dim3((unsigned)ls_cdiv(s, 256), (unsigned)ngroup), dim3(256), 0, st, s, ntile,
+                     c.cnt, c.gsum);
+  hipLaunchKernelGGL(k_ss_scan_groups, dim3((unsigned)ls_cdiv(s, 256)), dim3(256), 0, st, s, ngroup, c.gsum,
+                     c.total);
+  hipLaunchKernelGGL(k_ss_scan_starts, dim3(1), dim3(1024), 0, st, s, c.total, c.start);
+  hipLaunchKernelGGL(k_ss_scatter, dim3((unsigned)ntile), dim3(64), 0, st, m, s, zeta, c.keys_in, c.vals_in, c.cnt,
+                     c.gsum, c.start, c.keys_out, c.vals_out);
   const dim3 gt((unsigned)ls_cdiv(m, 32), (unsigned)ls_cdiv(n1, 32));
   hipLaunchKernelGGL((k_ss_transpose<TA>), gt, dim3(256), 0, st, static_cast<const TA*>(P->A), P->lda,
                      static_cast<const TA*>(P->b), m, n, reinterpret_cast<TA*>(c.T));
@@ -240,6 +347,7 @@ size_t sparse_workspace(int64_t m, int64_t n, int zeta, int64_t s, size_t ta_byt
 
 int sparse_check(int64_t m, int zeta, int64_t s) {
   if (zeta < 2 || zeta > kZetaMax || 4 * (int64_t)zeta > s) return LS_E_ARG;
+  if (s > kSortBuckets) return LS_E_UNSUPPORTED;
   if (m * (int64_t)zeta >= ((int64_t)1 << 31) || m >= ((int64_t)1 << 31)) return LS_E_UNSUPPORTED;
   return LS_OK;
 }

@@ -245,6 +245,18 @@ def test_sketch_every_launch_shape_matches_oracle(L, fmt, terms, store):
     assert any(np.array_equal(Y0, Y) for Y in outs.values())   # the table names one of them
 
 
+@pytest.mark.parametrize("fmt,store", [("e4m3", "f32"), ("f16", "f64"), ("bf16", "f32")])
+def test_sketch_reports_column_exponents(L, fmt, store):
+    # the Section 3.2 exponents the sketch applied, against the oracle's (0 for
+    # bf16, which is not scaled by default)
+    P = make_problem(3001, 21, 1e3, seed=24, store=store)
+    e = torch.full((22,), -999, dtype=torch.int32, device="cuda")
+    L.ls_sketch(dev(P.At), dev(P.b), 96, seed=3, u_s=fmt, terms=2, col_exp=e)
+    M = np.column_stack([P.A(), P.b.astype(np.float64)])
+    want = formats.column_exponents(M, fmt) if fmt != "bf16" else np.zeros(22, dtype=np.int32)
+    assert np.array_equal(host(e), want)
+
+
 def test_sketch_e4m3_needs_column_scaling(L):
     # entries of A are ~ 1/sqrt(m) ~ 1e-2: without scaling most fall into
     # e4m3's subnormal range (2^-9 .. 2^-6) and lose their digits
@@ -608,8 +620,7 @@ def test_solve_batched_equals_single_solves(L):
     assert rc == 0
     for i, (P, (At, b)) in enumerate(zip(probs, dev_probs)):
         # problem i of a batch draws Omega with prob_id = i
-        x1, r1, rc1, st1 = L.ls_solve(At, b, s=0, seed=seeds[i], terms=2, pr=pr, prob_id=i, lsir_tol=6e-6,
-                                      lsqr_maxit=2 * max(p.n for p in probs))
+        x1, r1, rc1, st1 = L.ls_solve(At, b, s=0, seed=seeds[i], terms=2, pr=pr, prob_id=i, lsir_tol=6e-6)
         assert rc1 == 0 and stats[i]["status"] == 0
         assert torch.equal(xs[i], x1) and torch.equal(rs[i], r1), f"problem {i} differs from its single solve"
         for k in ("lsqr_its", "lsir_its", "fgmres_its_total"):
@@ -618,6 +629,18 @@ def test_solve_batched_equals_single_solves(L):
         ex, er = refsolve.forward_errors(host(xs[i]), host(rs[i]), xr, rr)
         assert ex <= 6e-6 and er <= 6e-6, (i, ex, er)
     sync_print("batched lsqr its:", [st["lsqr_its"] for st in stats], "fgmres:", [st["fgmres_its_total"] for st in stats])
+
+
+def test_batched_lsqr_limit_is_per_problem(L):
+    # Section 5's LSQR limit is 2n for each problem: with an unreachable
+    # tolerance every problem of a batch stops at its own 2n
+    shapes = [(4000, 12), (3001, 40), (5000, 25)]
+    probs = [make_problem(m, n, 1e2, seed=2410063190 + 4000 + i, store="f32") for i, (m, n) in enumerate(shapes)]
+    pr = L.precs(u_s="bf16", u_qr="f32", u="f32", u_r="f64")
+    dev_probs = [(dev(P.At), dev(P.b)) for P in probs]
+    xs, rs, rc, stats = L.ls_solve_batched(dev_probs, seeds=[5, 6, 7], terms=2, pr=pr, lsqr_tol=1e-300,
+                                           lsir_maxit=1, nworkers=2)
+    assert [st["lsqr_its"] for st in stats] == [2 * n for _, n in shapes]
 
 
 def test_solve_rejects_bad_arguments(L):
