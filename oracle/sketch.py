@@ -7,7 +7,7 @@ sketch-and-solve start is obtained without forming Q):
     M   = [A b] * diag(2^e)                 (Section 3.2 column scaling; e = 0 for
                                              bf16, f32 and f64)
     M_q = T_1 + ... + T_terms,  T_t = fl_us(M - T_1 - ... - T_{t-1})
-                                            (A "stored in precision u_s";
+                                            (A held in the sketch's precision;
                                              terms > 1 is a multi-term split)
     S_q = fl_us(fl_32(S))                   (entries of S: ``philox.gaussian_block``;
                                              the f64 sketch uses S unrounded)

@@ -1020,9 +1020,15 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
     creg[q] = 0;
   }
   for (int64_t p = p0; p < p1; ++p) {
-    vec_t nxt[kPanPrefetch<Q> ? Q : 1];
+    // binary64 products of binary32 entries: converting a whole panel at once
+    // would take the registers of a second panel, so the next panel is loaded
+    // after the current one is used (faster than prefetching, measured at one
+    // wave per SIMD)
+    constexpr bool kConv = sizeof(TC) > sizeof(TB);
+    constexpr bool PF = kPanPrefetch<Q> && !kConv;
+    vec_t nxt[PF ? Q : 1];
     double vrn[PR];
-    if (kPanPrefetch<Q> && p + 1 < p1) load(p + 1, nxt, vrn);
+    if (PF && p + 1 < p1) load(p + 1, nxt, vrn);
     const int64_t i0 = p * PR;
     double vr[PR];
     TC vrt[PR], s[PR];
@@ -1032,10 +1038,25 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
       vrt[k] = (TC)vr[k];
       s[k] = 0;
     }
+    if constexpr (kConv) {
+      // both products of an entry while its binary64 conversion is live; the
+      // scheduling barrier keeps the compiler from converting every entry first
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
+      for (int q = 0; q < Q; ++q) {
 #pragma unroll
-      for (int k = 0; k < PR; ++k) s[k] += (TC)cur[q][k] * vl[q];
+        for (int k = 0; k < PR; ++k) {
+          const TC a = (TC)cur[q][k];
+          s[k] += a * vl[q];
+          creg[q] += a * vrt[k];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int k = 0; k < PR; ++k) s[k] += (TC)cur[q][k] * vl[q];
+    }
     double wr[PR];
 #pragma unroll
     for (int k = 0; k < PR; ++k) {
@@ -1052,12 +1073,14 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
         if (k2 == k) val = (lane < PR) ? vr[k2] : wr[k2];
       if (i0 + k < m) ((lane < PR) ? vj : w)[i0 + k] = val;
     }
+    if constexpr (!kConv) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
+      for (int q = 0; q < Q; ++q)
 #pragma unroll
-      for (int k = 0; k < PR; ++k) creg[q] += (TC)cur[q][k] * vrt[k];
+        for (int k = 0; k < PR; ++k) creg[q] += (TC)cur[q][k] * vrt[k];
+    }
     if (p + 1 < p1) {
-      if constexpr (kPanPrefetch<Q>) {
+      if constexpr (PF) {
 #pragma unroll
         for (int q = 0; q < Q; ++q) cur[q] = nxt[q];
 #pragma unroll

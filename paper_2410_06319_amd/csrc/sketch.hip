@@ -3,11 +3,11 @@
 // Omega = S / sqrt(s) is never stored: S entries are regenerated from
 // Philox4x32-10 (counter (i/4, k, prob, 0), key = seed) where they are
 // multiplied.  [A b] is first packed into a zero-padded operand of the sketch
-// format ("A stored in precision u_s", Algorithm 1's input); for bf16 it may
-// be split into several bf16 terms whose sum reproduces the binary32 data more
-// closely.  Products run on MFMA with binary32 (bf16 path) or binary64 (f64
-// path) accumulation over a chunk of rows of A; the chunk partial sums are
-// added in binary64.
+// format (Algorithm 1 takes A in the sketch's precision); it may be split into
+// up to five parts of that format whose sum reproduces the data more closely.
+// Products run on MFMA with binary32 (narrow formats) or binary64 (f64 path)
+// accumulation over a chunk of rows of A; the chunk partial sums are added in
+// binary64.
 //
 // bf16 path: a block of 8 waves owns 128 rows of S and BN columns of [A b].
 // Every K-step of 32 rows, the block generates its 128 x 32 tile of S once
