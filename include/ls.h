@@ -169,6 +169,16 @@ typedef struct {
    * (err_x, err_r). */
   const double *x_ref;
   const double *r_ref;
+  /* lsqr_operand: how LSQR applies the preconditioned operator A R^-1 (the
+   * method is the same; the rounding differs).  1: B = A R^-1 is formed once in
+   * u (an MFMA product) and each iteration streams B.  2: each iteration
+   * streams A itself (stored in u) and applies R^-1 as the products W v and
+   * W^T (A^T u), W = R^-1, in binary64 rounded to u, so that B is never formed
+   * (m n^2 flops and one m x n operand saved); for ls_solve this needs the
+   * refinement's A-path (u = binary32, u_A = binary64, A stored in binary32),
+   * whose operand LSQR then shares.  0 (default): 2 for ls_solve when it
+   * qualifies, 1 otherwise.  Unsupported combinations: LS_E_UNSUPPORTED. */
+  int32_t lsqr_operand;
 } ls_iter_opts_t;
 
 /* Results and timings of one call. */
@@ -271,6 +281,10 @@ int ls_lsqr_precond(const ls_problem_t *P, const double *R, int64_t ldr, ls_prec
                     double *x, const ls_iter_opts_t *io, ls_stats_t *stats,
                     void *ws, size_t ws_bytes, void *stream);
 
+/* Workspace (bytes, device memory the caller owns) that ls_lsqr_precond needs
+ * for P, u and io (NULL: defaults).  Host only. */
+int ls_lsqr_workspace_size(const ls_problem_t *P, ls_prec_t u, const ls_iter_opts_t *io, size_t *bytes);
+
 /* Algorithm 2's refinement loop on the augmented system with
  * split-preconditioned FGMRES (M_L^-1 = diag(I, R^-T), M_R^-1 = diag(I, R^-1)).
  * x: device, length n, binary64, in and out.  r: device, length m, binary64,
@@ -279,6 +293,11 @@ int ls_lsqr_precond(const ls_problem_t *P, const double *R, int64_t ldr, ls_prec
 int ls_lsir_gmres(const ls_problem_t *P, const double *R, int64_t ldr, const ls_precs_t *pr,
                   double *x, double *r, int r_given, const ls_iter_opts_t *io,
                   ls_stats_t *stats, void *ws, size_t ws_bytes, void *stream);
+
+/* Workspace (bytes) that ls_lsir_gmres needs for P, pr and io (NULL: defaults).
+ * Host only. */
+int ls_lsir_workspace_size(const ls_problem_t *P, const ls_precs_t *pr, const ls_iter_opts_t *io,
+                           size_t *bytes);
 
 /* The whole method: sketch, R, x^s, LSQR, refinement.  x (n) and r (m):
  * device, binary64, out.  stats may be NULL. */

@@ -35,7 +35,8 @@ class IterOpts(ctypes.Structure):
                 ("fgmres_tol", ctypes.c_double), ("fgmres_maxit", ctypes.c_int32),
                 ("lsir_maxit", ctypes.c_int32), ("lsir_tol", ctypes.c_double),
                 ("fallback", ctypes.c_int32), ("check_every", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("inner_adapt", ctypes.c_int32), ("x_ref", ctypes.c_void_p), ("r_ref", ctypes.c_void_p)]
+                ("inner_adapt", ctypes.c_int32), ("x_ref", ctypes.c_void_p), ("r_ref", ctypes.c_void_p),
+                ("lsqr_operand", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -72,6 +73,8 @@ SIGNATURES = {
     "ls_sketch": (ctypes.c_int, [P(Problem), P(SketchOpts), ctypes.c_int, vp, i64, vp, ctypes.c_size_t, vp]),
     "ls_qr_r": (ctypes.c_int, [i64, i64, ctypes.c_int, vp, i64, vp, i64, vp, ctypes.c_size_t, vp]),
     "ls_qr_workspace_size": (ctypes.c_int, [i64, i64, ctypes.c_int, P(ctypes.c_size_t)]),
+    "ls_lsqr_workspace_size": (ctypes.c_int, [P(Problem), ctypes.c_int, P(IterOpts), P(ctypes.c_size_t)]),
+    "ls_lsir_workspace_size": (ctypes.c_int, [P(Problem), P(Precs), P(IterOpts), P(ctypes.c_size_t)]),
     "ls_qr_r_noalloc": (ctypes.c_int, [i64, i64, ctypes.c_int, vp, i64, vp, i64, vp]),
     "ls_lsqr_precond": (ctypes.c_int, [P(Problem), vp, i64, ctypes.c_int, vp, P(IterOpts), P(Stats), vp,
                                        ctypes.c_size_t, vp]),

@@ -128,8 +128,10 @@ def ls_lsqr_precond(At, b, Rt, x, u="f32", ws=None, **opts):
     io = iter_opts(P.n, u, **opts)
     st = B.Stats()
     if ws is None:
-        so = sketch_opts(s=max(4 * P.n, P.n + 1), terms=1)
-        ws = workspace(workspace_size(P, so, precs(u_s="f64", u_qr="f64", u=u), io), At.device)
+        nbytes = ctypes.c_size_t(0)
+        _check(B.load().ls_lsqr_workspace_size(ctypes.byref(P), B.PREC[u], ctypes.byref(io), ctypes.byref(nbytes)),
+               "ls_lsqr_workspace_size")
+        ws = workspace(nbytes.value, At.device)
     rc = B.load().ls_lsqr_precond(ctypes.byref(P), Rt.data_ptr(), Rt.stride(0), B.PREC[u], x.data_ptr(),
                                   ctypes.byref(io), ctypes.byref(st), ws.data_ptr(), ws.numel(), _stream())
     _check(rc, "ls_lsqr_precond")
@@ -143,10 +145,10 @@ def ls_lsir_gmres(At, b, Rt, x, r, pr=None, r_given=False, ws=None, **opts):
     io = iter_opts(P.n, "f64" if pr.u == B.FP64 else "f32", **opts)
     st = B.Stats()
     if ws is None:
-        so = sketch_opts(s=max(4 * P.n, P.n + 1), terms=1)
-        pr_ws = B.Precs(**{k: getattr(pr, k) for k, _ in B.Precs._fields_})
-        pr_ws.u_s = B.FP64
-        ws = workspace(workspace_size(P, so, pr_ws, io), At.device)
+        nbytes = ctypes.c_size_t(0)
+        _check(B.load().ls_lsir_workspace_size(ctypes.byref(P), ctypes.byref(pr), ctypes.byref(io),
+                                               ctypes.byref(nbytes)), "ls_lsir_workspace_size")
+        ws = workspace(nbytes.value, At.device)
     rc = B.load().ls_lsir_gmres(ctypes.byref(P), Rt.data_ptr(), Rt.stride(0), ctypes.byref(pr), x.data_ptr(),
                                 r.data_ptr(), int(r_given), ctypes.byref(io), ctypes.byref(st), ws.data_ptr(),
                                 ws.numel(), _stream())

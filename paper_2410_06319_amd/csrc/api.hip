@@ -159,6 +159,20 @@ ls_precs_t with_binary64_products(const ls_precs_t* pr) {
   return p;
 }
 
+// ls_solve's LSQR operand (ls_iter_opts_t.lsqr_operand): over A's panels (the
+// refinement's A-path operand, shared) or over B = A R^-1.
+int solve_lsqr_on_a(const ls_problem_t* P, const ls_precs_t* pr, const ls_iter_opts_t* io, bool* on_a) {
+  switch (io->lsqr_operand) {
+    case 0: *on_a = lsqr_on_a(P, pr); return LS_OK;
+    case 1: *on_a = false; return LS_OK;
+    case 2:
+      if (!lsqr_on_a(P, pr)) return LS_E_UNSUPPORTED;
+      *on_a = true;
+      return LS_OK;
+    default: return LS_E_ARG;
+  }
+}
+
 // Make R^-1 available: W (binary64) and its binary32 copy.
 int make_inverse(const double* R, int64_t ldr, int64_t n, const Inv& v, hipStream_t st) {
   LS_HIP_TRY(hipMemsetAsync(v.flag, 0, sizeof(int), st));
@@ -307,6 +321,8 @@ int ls_workspace_size(const ls_problem_t* P, const ls_sketch_opts_t* so, const l
   const ls_iter_opts_t io = fill_opts(io_in, P->n, pr->u);
   const int64_t n = P->n, s = sketch_rows(P, so);
   const ls_precs_t p64 = with_binary64_products(pr);
+  bool on_a = false;
+  LS_TRY(solve_lsqr_on_a(P, pr, &io, &on_a));
   // the sketch with the most room over the parts the solve may use (each
   // count of parts may take its own tuned launch shape)
   size_t sk_bytes = 0;
@@ -320,7 +336,7 @@ int ls_workspace_size(const ls_problem_t* P, const ls_sketch_opts_t* so, const l
                  + ls_align256(8 * (size_t)(n + 1) * (n + 1))    // R_aug
                  + inv_carve(nullptr, n).bytes                   // R^-1
                  + ls_align256(8 * (size_t)(P->m + n))           // saved x0 for the fallback
-                 + b_bytes(P, pr->u)                             // B = A R^-1 for LSQR
+                 + (on_a ? 0 : b_bytes(P, pr->u))                // B = A R^-1 for LSQR
                  + (second_b(pr, &io) ? fg_operand_bytes(P, &p64) : 0);   // A's panels for binary64 FGMRES
   size_t scratch = sk_bytes;
   const size_t q = qr_workspace(s, n + 1, pr->u_qr);
@@ -367,27 +383,44 @@ int ls_qr_workspace_size(int64_t s, int64_t ncols, ls_prec_t u_qr, size_t* bytes
   return LS_OK;
 }
 
+int ls_lsqr_workspace_size(const ls_problem_t* P, ls_prec_t u, const ls_iter_opts_t* io_in, size_t* bytes) {
+  if (!bytes) return LS_E_ARG;
+  LS_TRY(check_problem(P));
+  if (!prec_is(u, LS_FP32, LS_FP64)) return LS_E_UNSUPPORTED;
+  const ls_iter_opts_t io = fill_opts(io_in, P->n, u);
+  if (io.lsqr_operand < 0 || io.lsqr_operand > 2) return LS_E_ARG;
+  if (io.lsqr_operand == 2 && P->store != u) return LS_E_UNSUPPORTED;   // A's panels need A stored in u
+  // R^-1, then B or A's panels (the same size when A is stored in u), then LSQR's vectors
+  *bytes = inv_carve(nullptr, P->n).bytes + b_bytes(P, u) + lsqr_workspace(P, u, device_cu_count());
+  return LS_OK;
+}
+
 int ls_lsqr_precond(const ls_problem_t* P, const double* R, int64_t ldr, ls_prec_t u, double* x,
                     const ls_iter_opts_t* io_in, ls_stats_t* stats, void* ws, size_t ws_bytes, void* stream) {
   LS_TRY(check_problem(P));
   if (!R || !x || ldr < P->n) return LS_E_ARG;
-  if (!prec_is(u, LS_FP32, LS_FP64)) return LS_E_UNSUPPORTED;
+  size_t need = 0;
+  LS_TRY(ls_lsqr_workspace_size(P, u, io_in, &need));
+  if (!ws || ws_bytes < need) return LS_E_WORKSPACE;
   const ls_iter_opts_t io = fill_opts(io_in, P->n, u);
+  const bool on_a = (io.lsqr_operand == 2);
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
   const Inv inv = inv_carve(base, P->n);
   const size_t bb = b_bytes(P, u);
-  const size_t need = inv.bytes + bb + lsqr_workspace(P, u, device_cu_count());
-  if (!ws || ws_bytes < need) return LS_E_WORKSPACE;
   LS_TRY(make_inverse(R, ldr, P->n, inv, st));
   void* Bm = base + inv.bytes;
-  LS_TRY(form_b(P, inv.W, inv.W32, u, Bm, st));
+  if (on_a) {
+    LS_TRY(form_a_panels(P, Bm, st));
+  } else {
+    LS_TRY(form_b(P, inv.W, inv.W32, u, Bm, st));
+  }
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
     stats->err_x = stats->err_r = -1.0;
   }
   prof_reset(io.profile != 0);
-  const int rc = lsqr_device(P, R, ldr, inv.W, Bm, u, x, &io, stats, base + inv.bytes + bb,
+  const int rc = lsqr_device(P, R, ldr, inv.W, Bm, on_a ? 1 : 0, u, x, &io, stats, base + inv.bytes + bb,
                              ws_bytes - inv.bytes - bb, st);
   if (stats) {
     stats->status = rc;
@@ -397,20 +430,32 @@ int ls_lsqr_precond(const ls_problem_t* P, const double* R, int64_t ldr, ls_prec
   return rc;
 }
 
+int ls_lsir_workspace_size(const ls_problem_t* P, const ls_precs_t* pr, const ls_iter_opts_t* io_in,
+                           size_t* bytes) {
+  if (!bytes) return LS_E_ARG;
+  LS_TRY(check_problem(P));
+  LS_TRY(check_precs(pr));
+  const ls_iter_opts_t io = fill_opts(io_in, P->n, pr->u);
+  if (io.fgmres_maxit > 95) return LS_E_ARG;
+  // R^-1, the FGMRES operand, then the refinement's vectors
+  *bytes = inv_carve(nullptr, P->n).bytes + fg_operand_bytes(P, pr) +
+           lsir_workspace(P, pr, io.fgmres_maxit, device_cu_count());
+  return LS_OK;
+}
+
 int ls_lsir_gmres(const ls_problem_t* P, const double* R, int64_t ldr, const ls_precs_t* pr, double* x, double* r,
                   int r_given, const ls_iter_opts_t* io_in, ls_stats_t* stats, void* ws, size_t ws_bytes,
                   void* stream) {
   LS_TRY(check_problem(P));
-  LS_TRY(check_precs(pr));
   if (!R || !x || !r || ldr < P->n) return LS_E_ARG;
+  size_t need = 0;
+  LS_TRY(ls_lsir_workspace_size(P, pr, io_in, &need));
+  if (!ws || ws_bytes < need) return LS_E_WORKSPACE;
   const ls_iter_opts_t io = fill_opts(io_in, P->n, pr->u);
-  if (io.fgmres_maxit > 95) return LS_E_ARG;
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
   const Inv inv = inv_carve(base, P->n);
   const size_t bb = fg_operand_bytes(P, pr);
-  const size_t need = inv.bytes + bb + lsir_workspace(P, pr, io.fgmres_maxit, device_cu_count());
-  if (!ws || ws_bytes < need) return LS_E_WORKSPACE;
   LS_TRY(make_inverse(R, ldr, P->n, inv, st));
   void* Bm = base + inv.bytes;
   LS_TRY(form_fg_operand(P, inv.W, inv.W32, pr, Bm, st));
@@ -459,8 +504,10 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
   off += inv.bytes;
   double* saved = reinterpret_cast<double*>(base + off);
   off += ls_align256(8 * (size_t)(m + n));
-  void* B1 = base + off;                       // B in the working precision u
-  off += b_bytes(P, pr->u);
+  bool on_a = false;
+  LS_TRY(solve_lsqr_on_a(P, pr, &io, &on_a));
+  void* B1 = base + off;                       // B in the working precision u (unless LSQR runs over A)
+  off += on_a ? 0 : b_bytes(P, pr->u);
   const ls_precs_t p64 = with_binary64_products(pr);
   void* B2 = nullptr;                          // A's panels for binary64 FGMRES when needed
   if (second_b(pr, &io)) {
@@ -515,9 +562,16 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
     if (next == so_t.terms) break;
     so_t.terms = next;   // Section 4: kappa(A) u_s < 1 not met with this many parts
   }
-  // the preconditioned operator B = A R^-1, then Algorithm 2's LSQR solve
-  LS_TRY(form_b(P, inv.W, inv.W32, pr->u, B1, st));
-  int rc = lsqr_device(P, Raug, n + 1, inv.W, B1, pr->u, x, &io, S, scratch, scratch_bytes, st);
+  // Algorithm 2's LSQR solve on the preconditioned operator A R^-1: over
+  // B = A R^-1 formed once, or over A's panels (the refinement's operand)
+  // with R^-1 applied around each pass
+  if (on_a) {
+    LS_TRY(form_fg_operand(P, inv.W, inv.W32, pr, B2, st));
+  } else {
+    LS_TRY(form_b(P, inv.W, inv.W32, pr->u, B1, st));
+  }
+  int rc = lsqr_device(P, Raug, n + 1, inv.W, on_a ? B2 : B1, on_a ? 1 : 0, pr->u, x, &io, S, scratch,
+                       scratch_bytes, st);
   tm.mark(3, st);
   if (rc < 0) {
     S->status = rc;
@@ -530,7 +584,7 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
   void* Bfg = B1;
   bool have_b2 = false;
   if (pr->u_A != pr->u) {   // u = binary32, u_A = binary64: the A-path
-    LS_TRY(form_fg_operand(P, inv.W, inv.W32, pr, B2, st));
+    if (!on_a) LS_TRY(form_fg_operand(P, inv.W, inv.W32, pr, B2, st));
     Bfg = B2;
     have_b2 = true;
   }

@@ -399,8 +399,9 @@ __global__ __launch_bounds__(kThreads) void k_lsqr_pan(const T* __restrict__ Bp,
 
 // Column kernel, one wave per column (4 per block).  Reads rec[par] (C_i),
 // block 0 writes rec[par ^ 1] (C_{i+1}).  Init: v_1 = B^T u_1 / beta_1.
+// tpart: Gt partials per column of B^T u; nupart, nbpart: the pass's G partials.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_lsqr_col(int64_t n, const T* __restrict__ tpart, int G,
+__global__ __launch_bounds__(kThreads) void k_lsqr_col(int64_t n, const T* __restrict__ tpart, int Gt, int G,
                                                        const double* __restrict__ nupart,
                                                        const double* __restrict__ nbpart,
                                                        const double* __restrict__ nvpart_in, int Gv,
@@ -492,14 +493,14 @@ __global__ __launch_bounds__(kThreads) void k_lsqr_col(int64_t n, const T* __res
   }
   double contrib = 0.0;
   if (!done && col < n) {
-    const T* tp = tpart + col * G;
+    const T* tp = tpart + col * Gt;
     T acc = 0;
-    for (int g0 = 0; g0 < G; g0 += 512) {   // eight loads per lane in flight
+    for (int g0 = 0; g0 < Gt; g0 += 512) {   // eight loads per lane in flight
       T pv[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int g = g0 + 64 * q + lane;
-        pv[q] = (g < G) ? tp[g] : T(0);
+        pv[q] = (g < Gt) ? tp[g] : T(0);
       }
 #pragma unroll
       for (int q = 0; q < 8; ++q) acc += pv[q];
@@ -537,6 +538,75 @@ __global__ __launch_bounds__(kThreads) void k_lsqr_col(int64_t n, const T* __res
       progress_put(&prog->lsqr_it, it);
     }
   }
+}
+
+// LSQR over A's panels with W = R^-1 applied on either side of the pass
+// (B = A W is then never formed): before the pass, vz = W v (binary64
+// products, rounded to the working precision); after it, the column partials
+// of A^T u are summed (k_lsqr_colsum) and t = W^T (A^T u) is formed
+// (k_lsqr_wt), which the column kernel reads as a single partial per column.
+template <typename T>
+__global__ __launch_bounds__(kUtThreads) void k_lsqr_zx(const double* __restrict__ W, int64_t n,
+                                                        const T* __restrict__ v, const LsqrState* __restrict__ st,
+                                                        int par, int init, T* __restrict__ vz) {
+  if (!init && st->rec[par].done) return;
+  __shared__ double red[32 * 33];
+  const double z = ls_utmv_row(W, n, n, [&](int64_t c) { return (double)v[c]; }, red);
+  const int64_t row = (int64_t)blockIdx.x * 32 + threadIdx.x;
+  if (threadIdx.x < 32 && row < n) vz[row] = (T)z;
+}
+
+// a[c] = sum over the pass's G blocks of the column partials (one wave per
+// column, eight loads per lane in flight), in binary64.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_lsqr_colsum(int64_t n, const T* __restrict__ tpart, int G,
+                                                          const LsqrState* __restrict__ st, int par, int init,
+                                                          double* __restrict__ a) {
+  if (!init && st->rec[par].done) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t col = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (col >= n) return;
+  const T* tp = tpart + col * G;
+  double acc = 0.0;
+  for (int g0 = 0; g0 < G; g0 += 512) {
+    T pv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int g = g0 + 64 * q + lane;
+      pv[q] = (g < G) ? tp[g] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc += (double)pv[q];
+  }
+  acc = ls_wave_sum(acc);
+  if (lane == 0) a[col] = acc;
+}
+
+// t = W^T a (column c of W is row c of W^T; one wave per column, 16 per
+// block), rounded to the working precision.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_lsqr_wt(const double* __restrict__ W, int64_t n,
+                                                  const double* __restrict__ a, const LsqrState* __restrict__ st,
+                                                  int par, int init, T* __restrict__ t) {
+  if (!init && st->rec[par].done) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t col = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 6);
+  if (col >= n) return;
+  const double* wc = W + col * n;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t i0 = lane; i0 <= col; i0 += 64 * 8) {   // eight loads per lane in flight
+    double wv[8], av[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t i = i0 + 64 * q;
+      wv[q] = (i <= col) ? wc[i] : 0.0;
+      av[q] = (i <= col) ? a[i] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q & 3] += wv[q] * av[q];
+  }
+  const double val = ls_wave_sum((acc[0] + acc[1]) + (acc[2] + acc[3]));
+  if (lane == 0) t[col] = (T)val;
 }
 
 // Final: stopping data of the last iteration (needs alpha_{k+1}) and x = W (z0 + y).
@@ -1740,6 +1810,9 @@ struct LsqrWs {
   double* nupart;
   double* nbpart;
   double* nvpart[2];
+  char* vz;       // W v (LSQR over A's panels)
+  char* tw;       // W^T A^T u
+  double* asum;   // A^T u
   size_t bytes;
 };
 
@@ -1762,6 +1835,9 @@ LsqrWs lsqr_carve(char* ws, const ls_problem_t* P, size_t elt, int G, int Gv) {
   w.nbpart = reinterpret_cast<double*>(take(8 * (size_t)G));
   w.nvpart[0] = reinterpret_cast<double*>(take(8 * (size_t)Gv));
   w.nvpart[1] = reinterpret_cast<double*>(take(8 * (size_t)Gv));
+  w.vz = take(elt * P->n);
+  w.tw = take(elt * P->n);
+  w.asum = reinterpret_cast<double*>(take(8 * (size_t)P->n));
   w.bytes = off;
   return w;
 }
@@ -1775,8 +1851,8 @@ void lsqr_pan_launch(int G, hipStream_t st, ProfEv ev, const T* Bm, int64_t npan
 }
 
 template <typename T>
-int lsqr_typed(const ls_problem_t* P, const double* R, int64_t ldr, const double* W, const T* Bm, double* x,
-               const ls_iter_opts_t* io, ls_stats_t* stats, char* ws, size_t ws_bytes, hipStream_t st) {
+int lsqr_typed(const ls_problem_t* P, const double* R, int64_t ldr, const double* W, const T* Bm, int apply_w,
+               double* x, const ls_iter_opts_t* io, ls_stats_t* stats, char* ws, size_t ws_bytes, hipStream_t st) {
   const int64_t m = P->m, n = P->n;
   if (n > 64 * kMaxPanQ) return LS_E_UNSUPPORTED;
   const int ncu = device_cu_count();
@@ -1789,6 +1865,8 @@ int lsqr_typed(const ls_problem_t* P, const double* R, int64_t ldr, const double
   T* u = reinterpret_cast<T*>(w.u);
   T* wv = reinterpret_cast<T*>(w.w);
   T* tpart = reinterpret_cast<T*>(w.tpart);
+  T* vz = reinterpret_cast<T*>(w.vz);
+  T* tw = reinterpret_cast<T*>(w.tw);
   const int q = pan_q(n);
   const int maxit = io->lsqr_maxit;
   const double tol = io->lsqr_tol;
@@ -1809,10 +1887,14 @@ int lsqr_typed(const ls_problem_t* P, const double* R, int64_t ldr, const double
   else
     hipLaunchKernelGGL((k_cast<T, double>), dim3((unsigned)ls_cdiv(m, kThreads)), dim3(kThreads), 0, st,
                        (const double*)P->b, u, m, T(1));
+  // Bm is B = A W, or with apply_w A's panels, W applied before and after the pass
+  const T* vin = apply_w ? vz : v;
   auto pass = [&](int par, int init, const double* nvp) {
+    if (apply_w)
+      hipLaunchKernelGGL(k_lsqr_zx<T>, gut, dim3(kUtThreads), 0, st, W, n, v, w.st, par, init, vz);
     const ProfEv ev = prof_events(kProfLsqrPass);
-#define LS_LSQR_PAN(QQ)                                                                                            \
-  lsqr_pan_launch<T, QQ>(G, st, ev, Bm, npan, m, n, v, nvp, Gv, u, w.st, par, init, tpart, w.nupart, w.nbpart); \
+#define LS_LSQR_PAN(QQ)                                                                                              \
+  lsqr_pan_launch<T, QQ>(G, st, ev, Bm, npan, m, n, vin, nvp, Gv, u, w.st, par, init, tpart, w.nupart, w.nbpart); \
   break
     switch (q) {
       case 1: LS_LSQR_PAN(1);
@@ -1825,7 +1907,15 @@ int lsqr_typed(const ls_problem_t* P, const double* R, int64_t ldr, const double
 #undef LS_LSQR_PAN
     // B once, u read and written, v read, t written
     prof_commit(kProfLsqrPass, (double)m * n * sizeof(T) + 2.0 * m * sizeof(T) + 2.0 * n * sizeof(T));
+    if (apply_w) {
+      hipLaunchKernelGGL(k_lsqr_colsum<T>, gcol, dim3(kThreads), 0, st, n, tpart, G, w.st, par, init, w.asum);
+      hipLaunchKernelGGL(k_lsqr_wt<T>, dim3((unsigned)ls_cdiv(n, 16)), dim3(1024), 0, st, W, n, w.asum, w.st, par,
+                         init, tw);
+    }
   };
+  // the column kernel's partials of B^T u: the pass's, or W^T A^T u as one per column
+  const T* tcol = apply_w ? tw : tpart;
+  const int Gcol = apply_w ? 1 : G;
   // init: u_1 = b - B z0, beta_1, v_1 = B^T u_1 / beta_1; C_1 -> rec[1]
   const size_t pmark = prof_mark();
   pass(1, 1, w.nvpart[0]);
@@ -1835,16 +1925,16 @@ int lsqr_typed(const ls_problem_t* P, const double* R, int64_t ldr, const double
     progress_set(&prog->lsqr_it, -1);
     progress_set(&prog->lsqr_done, 0);
   }
-  hipLaunchKernelGGL(k_lsqr_col<T>, gcol, dim3(kThreads), 0, st, n, tpart, G, w.nupart, w.nbpart, w.nvpart[1], Gv,
-                     w.nvpart[0], w.st, 0, 1, 0, tol, v, wv, w.y, dprog);
+  hipLaunchKernelGGL(k_lsqr_col<T>, gcol, dim3(kThreads), 0, st, n, tcol, Gcol, G, w.nupart, w.nbpart,
+                     w.nvpart[1], Gv, w.nvpart[0], w.st, 0, 1, 0, tol, v, wv, w.y, dprog);
   int it = 1, cur = 0;   // nvpart[cur] holds ||v_it||^2 partials
   int last = 0;          // last column kernel launched
   LsqrRec rec{};
   for (; it <= maxit; ++it) {
     const int par = it & 1;
     pass(par, 0, w.nvpart[cur]);
-    hipLaunchKernelGGL(k_lsqr_col<T>, gcol, dim3(kThreads), 0, st, n, tpart, G, w.nupart, w.nbpart, w.nvpart[cur], Gv,
-                       w.nvpart[cur ^ 1], w.st, par, 0, it, tol, v, wv, w.y, dprog);
+    hipLaunchKernelGGL(k_lsqr_col<T>, gcol, dim3(kThreads), 0, st, n, tcol, Gcol, G, w.nupart, w.nbpart,
+                       w.nvpart[cur], Gv, w.nvpart[cur ^ 1], w.st, par, 0, it, tol, v, wv, w.y, dprog);
     cur ^= 1;
     last = it;
     // at most `check` iterations in flight; stop queueing once converged
@@ -1887,10 +1977,13 @@ size_t lsqr_workspace(const ls_problem_t* P, ls_prec_t u, int ncu) {
   return lsqr_carve(nullptr, P, elt, pan_grid(pan_count(P->m, elt), P->n, ncu), (int)ls_cdiv(P->n, 4)).bytes;
 }
 
-int lsqr_device(const ls_problem_t* P, const double* R, int64_t ldr, const double* W, const void* Bm, ls_prec_t u,
-                double* x, const ls_iter_opts_t* io, ls_stats_t* stats, char* ws, size_t ws_bytes, hipStream_t st) {
-  if (u == LS_FP32) return lsqr_typed<float>(P, R, ldr, W, (const float*)Bm, x, io, stats, ws, ws_bytes, st);
-  if (u == LS_FP64) return lsqr_typed<double>(P, R, ldr, W, (const double*)Bm, x, io, stats, ws, ws_bytes, st);
+int lsqr_device(const ls_problem_t* P, const double* R, int64_t ldr, const double* W, const void* Bm, int apply_w,
+                ls_prec_t u, double* x, const ls_iter_opts_t* io, ls_stats_t* stats, char* ws, size_t ws_bytes,
+                hipStream_t st) {
+  if (u == LS_FP32)
+    return lsqr_typed<float>(P, R, ldr, W, (const float*)Bm, apply_w, x, io, stats, ws, ws_bytes, st);
+  if (u == LS_FP64)
+    return lsqr_typed<double>(P, R, ldr, W, (const double*)Bm, apply_w, x, io, stats, ws, ws_bytes, st);
   return LS_E_UNSUPPORTED;
 }
 
@@ -2148,6 +2241,8 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
 
 bool fg_apath(const ls_precs_t* pr) { return pr->u == LS_FP32 && pr->u_A == LS_FP64; }
 
+bool lsqr_on_a(const ls_problem_t* P, const ls_precs_t* pr) { return fg_apath(pr) && P->store == LS_FP32; }
+
 size_t fg_operand_bytes(const ls_problem_t* P, const ls_precs_t* pr) {
   return fg_apath(pr) ? b_bytes(P, P->store) : b_bytes(P, pr->u_A);
 }
@@ -2155,6 +2250,10 @@ size_t fg_operand_bytes(const ls_problem_t* P, const ls_precs_t* pr) {
 int form_fg_operand(const ls_problem_t* P, const double* W, const float* W32, const ls_precs_t* pr, void* out,
                     hipStream_t st) {
   if (!fg_apath(pr)) return form_b(P, W, W32, pr->u_A, out, st);
+  return form_a_panels(P, out, st);
+}
+
+int form_a_panels(const ls_problem_t* P, void* out, hipStream_t st) {
   const dim3 g((unsigned)ls_cdiv(P->m, 64), (unsigned)ls_cdiv(P->n, 64));
   if (P->store == LS_FP32)
     hipLaunchKernelGGL(k_a_panels<float>, g, dim3(kThreads), 0, st, (const float*)P->A, P->lda, P->m, P->n,

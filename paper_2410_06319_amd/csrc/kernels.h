@@ -77,8 +77,14 @@ int form_b(const ls_problem_t* P, const double* W, const float* W32, ls_prec_t t
 size_t b_bytes(const ls_problem_t* P, ls_prec_t tb);
 
 // LSQR on B = A R^-1 from x (in/out): R (ldr) maps x0 to z0 = R x0, W maps z back.
-int lsqr_device(const ls_problem_t* P, const double* R, int64_t ldr, const double* W, const void* Bm, ls_prec_t u,
-                double* x, const ls_iter_opts_t* io, ls_stats_t* stats, char* ws, size_t ws_bytes, hipStream_t st);
+// Bm is B in the panel layout, or with apply_w A's panels in precision u
+// (form_fg_operand's A-path copy), W then being applied around each pass.
+int lsqr_device(const ls_problem_t* P, const double* R, int64_t ldr, const double* W, const void* Bm, int apply_w,
+                ls_prec_t u, double* x, const ls_iter_opts_t* io, ls_stats_t* stats, char* ws, size_t ws_bytes,
+                hipStream_t st);
+// ls_solve runs LSQR over A's panels (no B) when the refinement uses them and
+// A is stored in the working precision.
+bool lsqr_on_a(const ls_problem_t* P, const ls_precs_t* pr);
 size_t lsqr_workspace(const ls_problem_t* P, ls_prec_t u, int ncu);
 
 // The operand of the refinement's FGMRES pass.  B-path: B = A W in u_A.
@@ -89,6 +95,8 @@ bool fg_apath(const ls_precs_t* pr);
 size_t fg_operand_bytes(const ls_problem_t* P, const ls_precs_t* pr);
 int form_fg_operand(const ls_problem_t* P, const double* W, const float* W32, const ls_precs_t* pr, void* out,
                     hipStream_t st);
+// A in its storage precision, in B's panel layout (b_bytes(P, P->store) bytes).
+int form_a_panels(const ls_problem_t* P, void* out, hipStream_t st);
 
 // Refinement with FGMRES on [I B; B^T 0]; Bm from form_fg_operand.
 int lsir_device(const ls_problem_t* P, const double* W, const void* Bm, const ls_precs_t* pr, double* x, double* r,

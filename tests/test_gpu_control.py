@@ -167,6 +167,20 @@ def test_undersized_workspace_is_reported(L):
     with pytest.raises(L.LsError) as e:
         L.ls_lsir_gmres(At, b, Rt, x, r, pr=pr, ws=small)
     assert e.value.code == -2
+    # LSQR and the refinement: 256 bytes short of their workspace queries
+    for operand in (1, 2):
+        io = L.iter_opts(30, "f32", lsqr_operand=operand)
+        lneed = ctypes.c_size_t(0)
+        assert B.ls_lsqr_workspace_size(ctypes.byref(S.P), Bd.FP32, ctypes.byref(io), ctypes.byref(lneed)) == 0
+        rc = B.ls_lsqr_precond(ctypes.byref(S.P), Rt.data_ptr(), 30, Bd.FP32, x.data_ptr(), ctypes.byref(io), None,
+                               S.ws.data_ptr(), lneed.value - 256, stream)
+        assert rc == Bd.E_WORKSPACE
+    io = L.iter_opts(30, "f32")
+    gneed = ctypes.c_size_t(0)
+    assert B.ls_lsir_workspace_size(ctypes.byref(S.P), ctypes.byref(pr), ctypes.byref(io), ctypes.byref(gneed)) == 0
+    rc = B.ls_lsir_gmres(ctypes.byref(S.P), Rt.data_ptr(), 30, ctypes.byref(pr), x.data_ptr(), r.data_ptr(), 0,
+                         ctypes.byref(io), None, S.ws.data_ptr(), gneed.value - 256, stream)
+    assert rc == Bd.E_WORKSPACE
     # a batch whose workspace is 256 bytes short
     n1 = ctypes.c_size_t(0)
     Ps = (Bd.Problem * 2)(S.P, S.P)

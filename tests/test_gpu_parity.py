@@ -326,15 +326,18 @@ def _oracle_R(P, s, seed):
 
 # shapes: 4-row binary32 / 2-row binary64 panels with and without a ragged last
 # panel, and n covering one to sixteen 64-column loads per lane
+# operand 1: B = A R^-1 formed once; operand 2: A's panels with W = R^-1
+# applied around each pass (A stored in u)
 @pytest.mark.parametrize("m,n", [(3000, 40), (3001, 40), (5003, 500), (1802, 700)])
-@pytest.mark.parametrize("store,u", [("f64", "f64"), ("f32", "f32"), ("f32", "f64")])
-def test_lsqr_iterates_match_oracle(L, store, u, m, n):
+@pytest.mark.parametrize("store,u,operand", [("f64", "f64", 1), ("f64", "f64", 2), ("f32", "f32", 1),
+                                             ("f32", "f32", 2), ("f32", "f64", 1)])
+def test_lsqr_iterates_match_oracle(L, store, u, operand, m, n):
     P = make_problem(m, n, 1e3, seed=15, store=store)
     R, xs = _oracle_R(P, max(160, 2 * n), 3)
     for k in (1, 5, 17):
         x = dev(xs.copy())
         rc, st = L.ls_lsqr_precond(dev(P.At), dev(P.b), dev(np.ascontiguousarray(R.T)), x, u=u,
-                                   lsqr_tol=1e-300, lsqr_maxit=k)
+                                   lsqr_tol=1e-300, lsqr_maxit=k, lsqr_operand=operand)
         xr, info = olsqr.lsqr_precond(P.At, P.b, R, xs, tol=0.0, maxit=k)
         got = host(x)
         assert st["lsqr_its"] == k
@@ -358,14 +361,14 @@ def _lapack_R(P, s, seed):
 
 # panels of 1025..2048 columns (32 loads per lane, no prefetch of the next panel)
 @pytest.mark.parametrize("m,n", [(3001, 1500), (4100, 2048)])
-@pytest.mark.parametrize("store,u", [("f32", "f32"), ("f64", "f64")])
-def test_lsqr_wide_panels_match_oracle(L, store, u, m, n):
+@pytest.mark.parametrize("store,u,operand", [("f32", "f32", 1), ("f32", "f32", 2), ("f64", "f64", 1)])
+def test_lsqr_wide_panels_match_oracle(L, store, u, operand, m, n):
     P = make_problem(m, n, 1e2, seed=19, store=store)
     R, xs = _lapack_R(P, 2 * n, 3)
     for k in (1, 5):
         x = dev(xs.copy())
         rc, st = L.ls_lsqr_precond(dev(P.At), dev(P.b), dev(np.ascontiguousarray(R.T)), x, u=u,
-                                   lsqr_tol=1e-300, lsqr_maxit=k)
+                                   lsqr_tol=1e-300, lsqr_maxit=k, lsqr_operand=operand)
         xr, info = olsqr.lsqr_precond(P.At, P.b, R, xs, tol=0.0, maxit=k)
         got = host(x)
         assert st["lsqr_its"] == k
@@ -389,6 +392,44 @@ def test_lsir_wide_panels_reach_target(L, m, n):
     ex, er = refsolve.forward_errors(host(x), host(r), xr, rr)
     sync_print(f"wide LSIR n={n}: its {st['lsir_its']} fgmres {st['fgmres_its_total']} err x {ex:.2e} r {er:.2e}")
     assert rc == 0 and ex <= 6e-6 and er <= 6e-6
+
+
+def test_lsqr_operand_choices_are_checked(L):
+    P = make_problem(3000, 40, 1e3, seed=15, store="f64")
+    R, xs = _oracle_R(P, 160, 3)
+    Rt = dev(np.ascontiguousarray(R.T))
+    with pytest.raises(L.LsError) as e:   # A's panels need A stored in u
+        L.ls_lsqr_precond(dev(P.At), dev(P.b), Rt, dev(xs.copy()), u="f32", lsqr_operand=2)
+    assert e.value.code == -6   # LS_E_UNSUPPORTED
+    with pytest.raises(L.LsError) as e:
+        L.ls_lsqr_precond(dev(P.At), dev(P.b), Rt, dev(xs.copy()), u="f64", lsqr_operand=3)
+    assert e.value.code == -1   # LS_E_ARG
+    Q = make_problem(3000, 40, 1e3, seed=15, store="f32")
+    pr = L.precs(u_s="bf16", u_qr="f32", u="f32", u_r="f64")   # u_A = u: no A-path to share
+    with pytest.raises(L.LsError) as e:
+        L.ls_solve(dev(Q.At), dev(Q.b), s=160, seed=3, pr=pr, lsqr_operand=2)
+    assert e.value.code == -6   # LS_E_UNSUPPORTED
+
+
+# ls_solve on the A-path: LSQR over A's panels (the default there) and over
+# B = A R^-1 reach the same accuracy with about as many iterations
+@pytest.mark.parametrize("m,n,kappa", [(20000, 100, 1e4), (6003, 700, 1e5)])
+def test_solve_lsqr_operands_agree(L, m, n, kappa):
+    P = make_problem(m, n, kappa, seed=2410064197, store="f32")
+    xr, rr, _ = refsolve.ref_solve(P.At, P.b)
+    pr = L.precs(u_s="bf16", u_qr="f32", u="f32", u_r="f64", u_A="f64")
+    res = {}
+    for op in (1, 2):
+        x, r, rc, st = L.ls_solve(dev(P.At), dev(P.b), s=max(4 * n, n + 1), seed=3, terms=3, pr=pr, lsir_tol=6e-6,
+                                  lsqr_operand=op)
+        ex, er = refsolve.forward_errors(host(x), host(r), xr, rr)
+        res[op] = (rc, st["lsqr_its"], st["lsqr_normr"], ex, er)
+        sync_print(f"m={m} n={n} LSQR operand {op}: status {rc} lsqr {st['lsqr_its']} normr {st['lsqr_normr']:.6e} "
+                   f"err x {ex:.2e} r {er:.2e}")
+    for rc, _, _, ex, er in res.values():
+        assert rc == 0 and ex <= 6e-6 and er <= 6e-6
+    assert abs(res[1][1] - res[2][1]) <= 2
+    assert abs(res[1][2] - res[2][2]) <= 1e-3 * res[1][2]
 
 
 def test_lsqr_converges_like_oracle(L):
