@@ -1374,6 +1374,11 @@ __device__ __forceinline__ double vrow_dot(const double* __restrict__ V, int64_t
 // 512 balances the partials each second-sweep block sums (one per block and
 // column) against the compute units the sweeps reach.
 constexpr int kSweepThreads = 512;
+// Above this many row blocks the sweeps' partials are summed by a separate
+// launch (k_colsum_parts) instead of by every block: each block reading all
+// (j + 1) x Gs partials costs Gs^2 (j + 1) reads in all (about 0.8 GB of cache
+// traffic per iteration at a million rows).
+constexpr int kSweepSumAbove = 512;
 
 // s[c] = sum_{g < G} part[c G + g] for c <= j (< kMaxKrylov): wave w sums the
 // columns w + kSweepWaves k, four at a time, with the loads of the four
@@ -1406,6 +1411,31 @@ __device__ __forceinline__ void sweep_sum_columns(const double* __restrict__ par
       if (lane == 0 && c <= j) s[c] = t;
     }
   }
+}
+
+// out[c] = sum of the G partials part[c G + g], one block per column c <= j.
+// Used between the sweeps when there are so many row blocks that every block
+// summing all partials itself would read far more than the sweep (the sum
+// over g is then taken once, in a fixed order).
+__global__ __launch_bounds__(kThreads) void k_colsum_parts(const FgState* __restrict__ st,
+                                                           const double* __restrict__ part, int G,
+                                                           double* __restrict__ out) {
+  if (st->done) return;
+  __shared__ double dsh[4];
+  const double* pc = part + (int64_t)blockIdx.x * G;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int g0 = threadIdx.x; g0 < G; g0 += 4 * kThreads) {
+    double v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int g = g0 + q * kThreads;
+      v[q] = (g < G) ? pc[g] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[q] += v[q];
+  }
+  const double t = block_sum256((a[0] + a[1]) + (a[2] + a[3]), dsh);
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
 }
 
 // First Gram-Schmidt sweep over rows [512 b, 512 b + 512) of w = V[:, j+1]:
@@ -1464,16 +1494,17 @@ __global__ __launch_bounds__(kSweepThreads) void k_cgs1(FgPtrs F, int64_t m, int
   }
 }
 
-// Second sweep: h2[c] = sum of the first sweep's partials (every block),
+// Second sweep: h2[c] = sum of the first sweep's G2 partials (every block;
+// G2 = 1 when k_colsum_parts has summed them),
 // H(c, j) += h2[c] (block 0); w <- w - V[:, 0:j+1] h2; partial ||w||^2.
 __global__ __launch_bounds__(kSweepThreads) void k_cgs2(FgPtrs F, int64_t m, int64_t n, int j, int kmax,
-                                                        const double* __restrict__ h2part,
+                                                        const double* __restrict__ h2part, int G2,
                                                         double* __restrict__ w2part) {
   if (F.st->done) return;
   constexpr int kSweepWaves = kSweepThreads / 64;
   __shared__ double hs[kMaxKrylov];
   __shared__ double dsh[kSweepWaves];
-  sweep_sum_columns<kSweepWaves>(h2part, (int)gridDim.x, j, hs);
+  sweep_sum_columns<kSweepWaves>(h2part, G2, j, hs);
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x <= j) F.H[(int64_t)j * (kmax + 1) + threadIdx.x] += hs[threadIdx.x];
   const int64_t rows = m + n;
@@ -2009,6 +2040,8 @@ struct LsirWs {
   double* upart;      // 4 x (Gd + Gn)
   double* xin;        // n: W V_x[:, j] (A-path)
   double* tbuf;       // n: A^T v_r (A-path)
+  double* h1sum;      // kmax + 1: summed partials of h1 (many row blocks)
+  double* h2sum;      // kmax + 1: summed partials of h2
   size_t bytes;
 };
 
@@ -2033,9 +2066,11 @@ LsirDims lsir_dims(const ls_problem_t* P, size_t tb_elt, size_t ta_elt, int fgmr
   d.G = pan_grid(d.npan, P->n, ncu);
   d.Gr = (int)ls_cdiv(P->m, kResRows);
   d.Gc = (int)ls_cdiv(P->n, 16);
-  d.Gk = (int)std::min<int64_t>(128, ls_cdiv(P->m, 512));   // row blocks of the r-part Arnoldi dots
-  d.Gd = (int)ls_cdiv(P->m + P->n, kThreads);
+  // row blocks of the r-part Arnoldi dots: one per compute unit when the
+  // sweeps' partials are summed separately, otherwise at most 128
   d.Gs = (int)ls_cdiv(P->m + P->n, kSweepThreads);
+  d.Gk = (int)std::min<int64_t>((d.Gs > kSweepSumAbove) ? ncu : 128, ls_cdiv(P->m, 512));
+  d.Gd = (int)ls_cdiv(P->m + P->n, kThreads);
   d.Gh = (int)ls_cdiv(P->n, 4);
   d.Gn = (int)ls_cdiv(P->n, 32);
   return d;
@@ -2072,6 +2107,8 @@ LsirWs lsir_carve(char* ws, const ls_problem_t* P, const LsirDims& d, size_t tb_
   w.dz = reinterpret_cast<double*>(take(8 * (size_t)n));
   w.xin = reinterpret_cast<double*>(take(8 * (size_t)n));
   w.tbuf = reinterpret_cast<double*>(take(8 * (size_t)n));
+  w.h1sum = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1)));
+  w.h2sum = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1)));
   w.bytes = off;
   return w;
 }
@@ -2166,10 +2203,21 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
         hipLaunchKernelGGL(k_fg_wt, dim3((unsigned)ncb), dim3(1024), 0, st, W, m, n, w.tbuf, F, j, ncb, d.Gk,
                            w.hxpart);
       prof_begin(kProfCgs, st);
-      hipLaunchKernelGGL(k_cgs1, dim3((unsigned)d.Gs), dim3(kSweepThreads), 0, st, F, m, n, j, d.kmax, w.hxpart,
-                         d.Gc + d.Gk, w.h2part);
-      hipLaunchKernelGGL(k_cgs2, dim3((unsigned)d.Gs), dim3(kSweepThreads), 0, st, F, m, n, j, d.kmax, w.h2part,
-                         w.w2part);
+      if (d.Gs > kSweepSumAbove) {   // the partials summed once, then read by every block
+        hipLaunchKernelGGL(k_colsum_parts, dim3((unsigned)(j + 1)), dim3(kThreads), 0, st, w.st, w.hxpart,
+                           d.Gc + d.Gk, w.h1sum);
+        hipLaunchKernelGGL(k_cgs1, dim3((unsigned)d.Gs), dim3(kSweepThreads), 0, st, F, m, n, j, d.kmax, w.h1sum, 1,
+                           w.h2part);
+        hipLaunchKernelGGL(k_colsum_parts, dim3((unsigned)(j + 1)), dim3(kThreads), 0, st, w.st, w.h2part, d.Gs,
+                           w.h2sum);
+        hipLaunchKernelGGL(k_cgs2, dim3((unsigned)d.Gs), dim3(kSweepThreads), 0, st, F, m, n, j, d.kmax, w.h2sum, 1,
+                           w.w2part);
+      } else {
+        hipLaunchKernelGGL(k_cgs1, dim3((unsigned)d.Gs), dim3(kSweepThreads), 0, st, F, m, n, j, d.kmax, w.hxpart,
+                           d.Gc + d.Gk, w.h2part);
+        hipLaunchKernelGGL(k_cgs2, dim3((unsigned)d.Gs), dim3(kSweepThreads), 0, st, F, m, n, j, d.kmax, w.h2part,
+                           d.Gs, w.w2part);
+      }
       // V(:, 0:j) read three times (first sweep twice, second once), w read and written twice
       prof_end(kProfCgs, st, 3.0 * 8.0 * (j + 1) * (double)(m + n) + 4.0 * 8.0 * (double)(m + n));
       // at most `check` iterations in flight; stop queueing once converged
