@@ -965,9 +965,11 @@ struct FgPtrs {
   FgState* st;
 };
 
-// Column j: h = ||w|| from partials (j = 0: beta = ||s||); block 0 applies
-// the Givens rotations to column j-1 and tests convergence.  Then, per panel
-// of P (one wave per contiguous panel range, next panel in flight):
+// Column j: h = ||u_j|| from partials (j = 0: beta = ||s||, and block 0
+// starts the cycle's state); h is stored for the kernels after the pass, and
+// a zero or non-finite h ends the pass (the Gram-Schmidt stage then closes the
+// cycle).  Then, per panel of P (one wave per contiguous panel range, next
+// panel in flight):
 // v_r = V_r[:, j] / h (written back normalised), w_r = v_r + P y ->
 // V_r[:, j+1], and the lanes' column partials of t = P^T v_r, with products
 // and sums in TC.  B-path: P = B = A W in its precision TB, y = v_x = V_x[:, j] / h
@@ -976,9 +978,8 @@ struct FgPtrs {
 // the preconditioned operator in binary64 over the stored data.
 template <typename TB, typename TC, int Q>
 __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, int64_t npan, int64_t m, int64_t n,
-                                                     FgPtrs F, int j, int kmax, const double* __restrict__ w2part,
-                                                     int Gw, double tol, int final_step, TC* __restrict__ tpart,
-                                                     const double* __restrict__ xin, Progress* prog) {
+                                                     FgPtrs F, int j, const double* __restrict__ w2part, int Gw,
+                                                     TC* __restrict__ tpart, const double* __restrict__ xin) {
   if (F.st->done) return;
   using vec_t = typename PanVec<TB>::type;
   constexpr int PR = PanVec<TB>::PR;
@@ -1018,68 +1019,22 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
   // loads go out before the norm's partials are summed
   if (p0 < p1) load(p0, cur, vro);
   const double h = sqrt(wave_sum_array(w2part, Gw, lane));
-  const int64_t ldh = kmax + 1;
-  if (blockIdx.x == 0) {
-    // Column j - 1 of H, cs and sn are staged in LDS by the block; thread 0
-    // then applies the earlier rotations with the running entry in a register.
-    __shared__ double hcs[kMaxKrylov + 1], css[kMaxKrylov], sns[kMaxKrylov];
-    const int c = j - 1;
-    double* Hc = F.H + (int64_t)(j > 0 ? c : 0) * ldh;
-    for (int t = threadIdx.x; t < j; t += kThreads) {
-      hcs[t] = Hc[t];
-      if (t < c) {
-        css[t] = F.cs[t];
-        sns[t] = F.sn[t];
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *F.hj = h;
+    if (j == 0) {
       FgState S = *F.st;
-      *F.hj = h;
-      if (j == 0) {
-        S.beta = h;
-        F.g[0] = h;
-        S.relres = 1.0;
-        S.k = 0;
-        if (h == 0.0 || !isfinite(h)) {
-          S.done = 1;
-          S.breakdown = (h == 0.0) ? 0 : 2;
-        }
-      } else {
-        double x = hcs[0];
-#pragma unroll 4
-        for (int i = 0; i < c; ++i) {
-          const double y = hcs[i + 1];
-          Hc[i] = css[i] * x + sns[i] * y;
-          x = -sns[i] * x + css[i] * y;
-        }
-        const double d = hypot(x, h);
-        const double cc = (d > 0.0) ? x / d : 1.0;
-        const double ss = (d > 0.0) ? h / d : 0.0;
-        F.cs[c] = cc;
-        F.sn[c] = ss;
-        Hc[c] = d;
-        Hc[c + 1] = 0.0;
-        F.g[c + 1] = -ss * F.g[c];
-        F.g[c] = cc * F.g[c];
-        S.relres = fabs(F.g[c + 1]) / S.beta;
-        S.k = j;
-        if (!isfinite(S.relres)) {
-          S.done = 1;
-          S.breakdown = 2;
-        } else if (S.relres <= tol || h == 0.0 || final_step || j >= kmax) {
-          S.done = 1;
-          if (h == 0.0) S.breakdown = 1;
-        }
+      S.beta = h;
+      F.g[0] = h;
+      S.relres = 1.0;
+      S.k = 0;
+      if (h == 0.0 || !isfinite(h)) {
+        S.done = 1;
+        S.breakdown = (h == 0.0) ? 0 : 2;
       }
       *F.st = S;
-      if (prog && !final_step) {
-        progress_put(&prog->fg_done, S.done ? 1 : 0);
-        progress_put(&prog->fg_j, j);
-      }
     }
   }
-  if (h == 0.0 || !isfinite(h) || final_step || j >= kmax) return;
+  if (h == 0.0 || !isfinite(h)) return;
   const double inv = 1.0 / h;
   TC vl[Q], creg[Q];
   const double* xs = xin ? xin : vj + m;
@@ -1170,93 +1125,38 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
   for (int64_t c = threadIdx.x; c < n; c += kThreads) tpart[c * gridDim.x + blockIdx.x] = cred[c];
 }
 
-// Blocks < ncb (16 columns each, one wave per column): t = P^T v_r from the
-// column partials, normalise V[m:, j]; B-path (tout null): w_x = t ->
-// V[m:, j+1] and partial h1_x[c] over the block's columns; A-path: t -> tout
-// (k_fg_wt forms w_x = W^T t and those partials).  Blocks ncb .. ncb + nrb - 1
-// (a range of rows < m each, one wave per Krylov column): partial
-// h1_r[c] = V_r[rows, c] . w_r[rows] for c <= j (V_r[:, j] was normalised by
-// the pass).  Partials of block b go to hxpart[c (ncb + nrb) + b].
+// One wave per column (16 per block): t = P^T v_r from the pass's column
+// partials; V_x[:, j] normalised by the pass's h; B-path (tout null): w_x = t
+// -> V[m:, j+1]; A-path: t -> tout (k_fg_wt forms w_x = W^T t).
 template <typename TB>
 __global__ __launch_bounds__(1024) void k_fg_col(int64_t m, int64_t n, const TB* __restrict__ tpart, int G, FgPtrs F,
-                                                 int j, int ncb, int nrb, double* __restrict__ hxpart,
-                                                 double* __restrict__ tout) {
+                                                 int j, double* __restrict__ tout) {
   if (F.st->done) return;
-  __shared__ double wx[16];
-  __shared__ double vjx[16];
+  const double h = *F.hj;
+  if (h == 0.0 || !isfinite(h)) return;   // the Gram-Schmidt stage closes the cycle
   const int lane = threadIdx.x & 63;
   const int wvi = threadIdx.x >> 6;
-  const int64_t Gx = ncb + nrb;
-  if ((int)blockIdx.x >= ncb) {
-    int64_t r0, r1;
-    row_range(m, nrb, (int)blockIdx.x - ncb, r0, r1);
-    const double* w = F.V + (int64_t)(j + 1) * F.ldv;
-    constexpr int kRB = 16;   // rows per lane with their loads in flight together
-    for (int c = wvi; c <= j; c += 16) {
-      const double* vc = F.V + (int64_t)c * F.ldv;
-      double a[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int64_t i0 = r0 + lane; i0 < r1; i0 += 64 * kRB) {
-        double x[kRB], y[kRB];
-#pragma unroll
-        for (int q = 0; q < kRB; ++q) {
-          const int64_t i = i0 + 64 * q;
-          x[q] = (i < r1) ? vc[i] : 0.0;
-          y[q] = (i < r1) ? w[i] : 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < kRB; ++q) a[q & 3] += x[q] * y[q];
-      }
-      const double t = ls_wave_sum((a[0] + a[1]) + (a[2] + a[3]));
-      if (lane == 0) hxpart[(int64_t)c * Gx + blockIdx.x] = t;
-    }
-    return;
-  }
   const int64_t col = (int64_t)blockIdx.x * 16 + wvi;
-  const double inv = 1.0 / *F.hj;
-  double* w = F.V + (int64_t)(j + 1) * F.ldv;
-  double* vj = F.V + (int64_t)j * F.ldv;
-  double val = 0.0, vn = 0.0;
-  if (col < n) {
-    const TB* tp = tpart + col * G;
-    TB acc = 0;
-    for (int g0 = 0; g0 < G; g0 += 512) {   // eight loads per lane in flight
-      TB v[8];
+  if (col >= n) return;
+  const double inv = 1.0 / h;
+  const TB* tp = tpart + col * G;
+  TB acc = 0;
+  for (int g0 = 0; g0 < G; g0 += 512) {   // eight loads per lane in flight
+    TB v[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int g = g0 + 64 * q + lane;
-        v[q] = (g < G) ? tp[g] : TB(0);
-      }
+    for (int q = 0; q < 8; ++q) {
+      const int g = g0 + 64 * q + lane;
+      v[q] = (g < G) ? tp[g] : TB(0);
+    }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) acc += v[q];
-    }
-    acc = ls_wave_sum(acc);
-    val = (double)acc;
-    vn = vj[m + col] * inv;
+    for (int q = 0; q < 8; ++q) acc += v[q];
   }
-  __syncthreads();   // every wave has read V[m:, j] before it is overwritten
-  if (tout) {
-    if (col < n && lane == 0) {
-      tout[col] = val;
-      vj[m + col] = vn;
-    }
-    return;
-  }
-  if (col < n && lane == 0) {
-    w[m + col] = val;
-    vj[m + col] = vn;
-  }
+  acc = ls_wave_sum(acc);
   if (lane == 0) {
-    wx[wvi] = val;
-    vjx[wvi] = vn;
-  }
-  __syncthreads();
-  for (int c = threadIdx.x; c <= j; c += 1024) {
-    double s = 0.0;
-    for (int q = 0; q < 16; ++q) {
-      const int64_t cc = (int64_t)blockIdx.x * 16 + q;
-      if (cc < n) s += ((c == j) ? vjx[q] : F.V[m + cc + (int64_t)c * F.ldv]) * wx[q];
-    }
-    hxpart[(int64_t)c * Gx + blockIdx.x] = s;
+    double* vj = F.V + (int64_t)j * F.ldv;
+    vj[m + col] *= inv;
+    if (tout) tout[col] = (double)acc;
+    else F.V[m + col + (int64_t)(j + 1) * F.ldv] = (double)acc;
   }
 }
 
@@ -1273,46 +1173,31 @@ __global__ __launch_bounds__(kUtThreads) void k_fg_zx(const double* __restrict__
 }
 
 // A-path, after the pass: w_x = W^T t -> V[m:, j+1] (one wave per column,
-// 16 columns per block, column c of W being row c of W^T), then the partials
-// h1_x[c] = V_x[block's columns, c] . w_x for c <= j (V_x[:, j] normalised by
-// k_fg_col), stored as k_fg_col stores them on the B-path.
+// 16 columns per block, column c of W being row c of W^T).
 __global__ __launch_bounds__(1024) void k_fg_wt(const double* __restrict__ W, int64_t m, int64_t n,
-                                                const double* __restrict__ t, FgPtrs F, int j, int ncb, int nrb,
-                                                double* __restrict__ hxpart) {
+                                                const double* __restrict__ t, FgPtrs F, int j) {
   if (F.st->done) return;
-  __shared__ double wx[16];
+  const double h = *F.hj;
+  if (h == 0.0 || !isfinite(h)) return;
   const int lane = threadIdx.x & 63;
   const int wvi = threadIdx.x >> 6;
   const int64_t col = (int64_t)blockIdx.x * 16 + wvi;
-  double val = 0.0;
-  if (col < n) {
-    const double* wc = W + col * n;
-    double a[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t i0 = lane; i0 <= col; i0 += 64 * 8) {   // eight loads per lane in flight
-      double wv[8], tv[8];
+  if (col >= n) return;
+  const double* wc = W + col * n;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t i0 = lane; i0 <= col; i0 += 64 * 8) {   // eight loads per lane in flight
+    double wv[8], tv[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int64_t i = i0 + 64 * q;
-        wv[q] = (i <= col) ? wc[i] : 0.0;
-        tv[q] = (i <= col) ? t[i] : 0.0;
-      }
+    for (int q = 0; q < 8; ++q) {
+      const int64_t i = i0 + 64 * q;
+      wv[q] = (i <= col) ? wc[i] : 0.0;
+      tv[q] = (i <= col) ? t[i] : 0.0;
+    }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) a[q & 3] += wv[q] * tv[q];
-    }
-    val = ls_wave_sum((a[0] + a[1]) + (a[2] + a[3]));
-    if (lane == 0) F.V[m + col + (int64_t)(j + 1) * F.ldv] = val;
+    for (int q = 0; q < 8; ++q) a[q & 3] += wv[q] * tv[q];
   }
-  if (lane == 0) wx[wvi] = (col < n) ? val : 0.0;
-  __syncthreads();
-  const int64_t Gx = ncb + nrb;
-  for (int c = threadIdx.x; c <= j; c += 1024) {
-    double s = 0.0;
-    for (int q = 0; q < 16; ++q) {
-      const int64_t cc = (int64_t)blockIdx.x * 16 + q;
-      if (cc < n) s += F.V[m + cc + (int64_t)c * F.ldv] * wx[q];
-    }
-    hxpart[(int64_t)c * Gx + blockIdx.x] = s;
-  }
+  const double val = ls_wave_sum((a[0] + a[1]) + (a[2] + a[3]));
+  if (lane == 0) F.V[m + col + (int64_t)(j + 1) * F.ldv] = val;
 }
 
 // A copied into the panel layout of B, in its storage precision (the A-path's
@@ -1370,53 +1255,38 @@ __device__ __forceinline__ double vrow_dot(const double* __restrict__ V, int64_t
   return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
-// Threads per block of the Gram-Schmidt sweeps (one row of V per thread):
-// 512 balances the partials each second-sweep block sums (one per block and
-// column) against the compute units the sweeps reach.
-constexpr int kSweepThreads = 512;
-// Above this many row blocks the sweeps' partials are summed by a separate
-// launch (k_colsum_parts) instead of by every block: each block reading all
-// (j + 1) x Gs partials costs Gs^2 (j + 1) reads in all (about 0.8 GB of cache
-// traffic per iteration at a million rows).
+// Arnoldi orthogonalisation: classical Gram-Schmidt with the second pass
+// (reorthogonalisation) of each vector delayed to the next iteration, so that
+// one sweep over V computes every inner product an iteration needs and one
+// more sweep applies every update (V is read twice per iteration).
+//
+// Entering iteration j, V[:, 0:j] are final (orthonormal) and V[:, j] holds
+// u_j, the previous iteration's vector after one Gram-Schmidt pass; the pass
+// normalises it to q_j = u_j / beta_j and writes w = M q_j to V[:, j+1] (M the
+// split-preconditioned augmented operator).  Then:
+//   sweep 1 (k_dcgs_dots): s = V_{<j}^T q_j, b = V_{<j}^T w, q_j . w, q_j . q_j;
+//   one block (k_dcgs_small): the second pass of q_j, v_j = (q_j - V s) / nu
+//     with nu^2 = q_j . q_j - |s|^2, makes column j-1 of the Hessenberg matrix
+//     final (H[<j, j-1] += beta_j s, H[j, j-1] = beta_j nu; the Givens
+//     rotations and the convergence test are applied to it); M v_j follows
+//     from w and the Arnoldi relation of the earlier columns,
+//     M v_j = (w - V_{<=j} t) / nu with t = H[0:j+1, 0:j] s, whose first-pass
+//     coefficients h'_j = V_{<=j}^T M v_j come from s, b and t alone; u_{j+1} =
+//     M v_j - V_{<=j} h'_j = w / nu - V_{<j} d - (gamma / nu) q_j;
+//   sweep 2 (k_dcgs_update): writes v_j and u_{j+1} and the partials of
+//     |u_{j+1}|^2.
+// H keeps the rotated columns (the triangular factor of the least-squares
+// problem), Hraw the unrotated ones (t needs them).  A cycle that reaches its
+// iteration limit closes with a sweep and a stage of the same kind for its
+// last column (closing = 1: no w).
+constexpr int kSweepThreads = 512;   // rows of V per block of the sweeps (one per thread)
+constexpr int kSweepWaves = kSweepThreads / 64;
+// Above this many row blocks the sweep's partials are summed by a launch of
+// their own (k_colsum_parts, once) rather than by the one-block stage.
 constexpr int kSweepSumAbove = 512;
+constexpr int kMaxDots = 2 * kMaxKrylov + 2;   // quantities of sweep 1
 
-// s[c] = sum_{g < G} part[c G + g] for c <= j (< kMaxKrylov): wave w sums the
-// columns w + kSweepWaves k, four at a time, with the loads of the four
-// columns (four per lane each) issued before the first addition.
-template <int kSweepWaves>
-__device__ __forceinline__ void sweep_sum_columns(const double* __restrict__ part, int G, int j,
-                                                  double* __restrict__ s) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  for (int c0 = wave; c0 <= j; c0 += 4 * kSweepWaves) {
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int g0 = 0; g0 < G; g0 += 256) {
-      double v[4][4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int c = c0 + kSweepWaves * k;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int g = g0 + 64 * q + lane;
-          v[k][q] = (c <= j && g < G) ? part[(int64_t)c * G + g] : 0.0;
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) acc[k] += (v[k][0] + v[k][1]) + (v[k][2] + v[k][3]);
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int c = c0 + kSweepWaves * k;
-      const double t = ls_wave_sum(acc[k]);
-      if (lane == 0 && c <= j) s[c] = t;
-    }
-  }
-}
-
-// out[c] = sum of the G partials part[c G + g], one block per column c <= j.
-// Used between the sweeps when there are so many row blocks that every block
-// summing all partials itself would read far more than the sweep (the sum
-// over g is then taken once, in a fixed order).
+// out[e] = sum of the G partials part[e G + g], one block per quantity e.
 __global__ __launch_bounds__(kThreads) void k_colsum_parts(const FgState* __restrict__ st,
                                                            const double* __restrict__ part, int G,
                                                            double* __restrict__ out) {
@@ -1438,83 +1308,247 @@ __global__ __launch_bounds__(kThreads) void k_colsum_parts(const FgState* __rest
   if (threadIdx.x == 0) out[blockIdx.x] = t;
 }
 
-// First Gram-Schmidt sweep over rows [512 b, 512 b + 512) of w = V[:, j+1]:
-// h1[c] = sum of the Gx partials of k_fg_col; w <- w - V[:, 0:j+1] h1; partial
-// h2[c] = V[:, c] . w over the block's rows.  Block 0 records h1 in column j of H.
-__global__ __launch_bounds__(kSweepThreads) void k_cgs1(FgPtrs F, int64_t m, int64_t n, int j, int kmax,
-                                                        const double* __restrict__ hx, int Gx,
-                                                        double* __restrict__ h2part) {
+// Sweep 1 over rows [512 b, 512 b + 512): partials part[e G + b] of
+// e = c < j: V[:, c] . q;  e = j + c (c < j): V[:, c] . w;  e = 2j: q . w;
+// e = 2j + 1: q . q;  q = V[:, j], w = V[:, j+1] (closing: no w, q = u_j).
+__global__ __launch_bounds__(kSweepThreads) void k_dcgs_dots(FgPtrs F, int64_t rows, int j, int closing,
+                                                             double* __restrict__ part) {
   if (F.st->done) return;
-  constexpr int kSweepWaves = kSweepThreads / 64;
-  __shared__ double hs[kMaxKrylov];
-  __shared__ double wsh[kSweepThreads];
+  if (!closing) {
+    const double h = *F.hj;
+    if (h == 0.0 || !isfinite(h)) return;   // the stage closes the cycle without the partials
+  }
+  __shared__ double qs[kSweepThreads];
+  __shared__ double ws[kSweepThreads];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  sweep_sum_columns<kSweepWaves>(hx, Gx, j, hs);
-  __syncthreads();
-  if (blockIdx.x == 0 && threadIdx.x <= j) F.H[(int64_t)j * (kmax + 1) + threadIdx.x] = hs[threadIdx.x];
-  const int64_t rows = m + n;
-  double* w = F.V + (int64_t)(j + 1) * F.ldv;
+  const int G = gridDim.x;
   const int64_t base = (int64_t)blockIdx.x * kSweepThreads;
   const int64_t i = base + threadIdx.x;
-  double wi = 0.0;
-  if (i < rows) {
-    wi = w[i] - vrow_dot<16>(F.V, F.ldv, i, j, hs);
-    w[i] = wi;
-  }
-  wsh[threadIdx.x] = wi;
+  const double* q = F.V + (int64_t)j * F.ldv;
+  qs[threadIdx.x] = (i < rows) ? q[i] : 0.0;
+  ws[threadIdx.x] = (!closing && i < rows) ? q[F.ldv + i] : 0.0;
   __syncthreads();
-  // partial dots: wave per Krylov column, the loads of kCols columns (one row
-  // per wave of the block for each lane) issued together
-  constexpr int kCols = 32 / kSweepWaves;
-  for (int c0 = wave; c0 <= j; c0 += kCols * kSweepWaves) {
-    double prod[kCols];
+  // wave per Krylov column, the loads of kCols columns (kSweepWaves rows per
+  // lane each) issued together
+  constexpr int kCols = 4;
+  for (int c0 = wave; c0 < j; c0 += kCols * kSweepWaves) {
+    double as[kCols], ab[kCols];
 #pragma unroll
     for (int cc = 0; cc < kCols; ++cc) {
       const int c = c0 + kSweepWaves * cc;
-      prod[cc] = 0.0;
-      if (c <= j) {
+      as[cc] = 0.0;
+      ab[cc] = 0.0;
+      if (c < j) {
         const double* vc = F.V + (int64_t)c * F.ldv + base;
         double v[kSweepWaves];
 #pragma unroll
-        for (int q = 0; q < kSweepWaves; ++q) {
-          const int li = q * 64 + lane;
-          v[q] = (base + li < rows) ? vc[li] : 0.0;
+        for (int u = 0; u < kSweepWaves; ++u) {
+          const int li = u * 64 + lane;
+          v[u] = (base + li < rows) ? vc[li] : 0.0;
         }
 #pragma unroll
-        for (int q = 0; q < kSweepWaves; ++q) prod[cc] += v[q] * wsh[q * 64 + lane];
+        for (int u = 0; u < kSweepWaves; ++u) {
+          as[cc] += v[u] * qs[u * 64 + lane];
+          ab[cc] += v[u] * ws[u * 64 + lane];
+        }
       }
     }
 #pragma unroll
     for (int cc = 0; cc < kCols; ++cc) {
       const int c = c0 + kSweepWaves * cc;
-      const double t = ls_wave_sum(prod[cc]);
-      if (c <= j && lane == 0) h2part[(int64_t)c * gridDim.x + blockIdx.x] = t;
+      const double t1 = ls_wave_sum(as[cc]);
+      const double t2 = ls_wave_sum(ab[cc]);
+      if (c < j && lane == 0) {
+        part[(int64_t)c * G + blockIdx.x] = t1;
+        if (!closing) part[(int64_t)(j + c) * G + blockIdx.x] = t2;
+      }
     }
+  }
+  if (wave == kSweepWaves - 1 || wave == kSweepWaves - 2) {
+    const bool qq = (wave == kSweepWaves - 1);
+    double a = 0.0;
+#pragma unroll
+    for (int u = 0; u < kSweepWaves; ++u) {
+      const int li = u * 64 + lane;
+      a += qs[li] * (qq ? qs[li] : ws[li]);
+    }
+    a = ls_wave_sum(a);
+    if (lane == 0 && (qq || !closing)) part[(int64_t)(2 * j + (qq ? 1 : 0)) * G + blockIdx.x] = a;
   }
 }
 
-// Second sweep: h2[c] = sum of the first sweep's G2 partials (every block;
-// G2 = 1 when k_colsum_parts has summed them),
-// H(c, j) += h2[c] (block 0); w <- w - V[:, 0:j+1] h2; partial ||w||^2.
-__global__ __launch_bounds__(kSweepThreads) void k_cgs2(FgPtrs F, int64_t m, int64_t n, int j, int kmax,
-                                                        const double* __restrict__ h2part, int G2,
-                                                        double* __restrict__ w2part) {
+// The stage of iteration j, one block: sums the sweep's partials (Gp per
+// quantity; 1 when k_colsum_parts has summed them), completes column j-1 of
+// the Hessenberg matrix and its Givens rotation (the convergence test), and
+// unless the cycle ends, forms column j's first-pass coefficients (Hraw and H
+// column j) and the coefficients of sweep 2: coef = [s (j), d (j), 1/nu,
+// gamma/nu].
+__global__ __launch_bounds__(kThreads) void k_dcgs_small(FgPtrs F, double* __restrict__ Hraw, int kmax, int j,
+                                                         int closing, const double* __restrict__ part, int Gp,
+                                                         double tol, double* __restrict__ coef, Progress* prog) {
   if (F.st->done) return;
-  constexpr int kSweepWaves = kSweepThreads / 64;
-  __shared__ double hs[kMaxKrylov];
-  __shared__ double dsh[kSweepWaves];
-  sweep_sum_columns<kSweepWaves>(h2part, G2, j, hs);
+  __shared__ double e[kMaxDots];
+  __shared__ double sv[kMaxKrylov + 1];
+  __shared__ double tv[kMaxKrylov + 1];
+  __shared__ double hp[kMaxKrylov + 1];
+  __shared__ double col[kMaxKrylov + 1];
+  __shared__ double sc[4];   // beta_j, nu, done flag, s . b
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t ldh = kmax + 1;
+  const double hj = closing ? 0.0 : *F.hj;
+  const bool skip = !closing && (hj == 0.0 || !isfinite(hj));   // no sweep ran: nothing to read
+  const int ne = 2 * j + 2;
+  if (!skip) {
+    for (int q = wave; q < ne; q += kThreads / 64) {
+      if (closing && q >= j && q < 2 * j + 1) continue;   // the closing sweep has no w
+      const double* pq = part + (int64_t)q * Gp;
+      double a = 0.0;
+      for (int g = lane; g < Gp; g += 64) a += pq[g];
+      a = ls_wave_sum(a);
+      if (lane == 0) e[q] = a;
+    }
+  }
   __syncthreads();
-  if (blockIdx.x == 0 && threadIdx.x <= j) F.H[(int64_t)j * (kmax + 1) + threadIdx.x] += hs[threadIdx.x];
-  const int64_t rows = m + n;
-  double* w = F.V + (int64_t)(j + 1) * F.ldv;
+  if (threadIdx.x == 0) {
+    FgState S = *F.st;
+    double beta = hj, nu = 1.0;
+    if (closing) {
+      beta = sqrt(e[2 * j + 1]);
+    }
+    if (j == 0) {
+      nu = 1.0;   // v_0 is final
+    } else if (skip || !isfinite(beta) || beta == 0.0) {
+      nu = 0.0;
+    } else {
+      const double inv = closing ? 1.0 / beta : 1.0;
+      double ss = 0.0;
+      for (int c = 0; c < j; ++c) {
+        sv[c] = e[c] * inv;
+        ss += sv[c] * sv[c];
+      }
+      const double sig = closing ? 1.0 : e[2 * j + 1];
+      const double nu2 = sig - ss;
+      nu = (nu2 > 0.0) ? sqrt(nu2) : 0.0;
+    }
+    int done = 0;
+    if (j > 0) {
+      // column j - 1 becomes final: H[<j, j-1] += beta s, H[j, j-1] = beta nu
+      double* hr = Hraw + (int64_t)(j - 1) * ldh;
+      const bool ok = isfinite(beta) && beta > 0.0 && nu > 0.0;
+      if (ok)
+        for (int c = 0; c < j; ++c) hr[c] += beta * sv[c];
+      const double sub = ok ? beta * nu : 0.0;
+      hr[j] = sub;
+      // Givens rotations of the earlier columns, then a new one for this column
+      double* Hc = F.H + (int64_t)(j - 1) * ldh;
+      double x = hr[0];
+      for (int i = 0; i < j - 1; ++i) {
+        const double y = hr[i + 1];
+        Hc[i] = F.cs[i] * x + F.sn[i] * y;
+        x = -F.sn[i] * x + F.cs[i] * y;
+      }
+      const double dd = hypot(x, sub);
+      const double cc = (dd > 0.0) ? x / dd : 1.0;
+      const double sn = (dd > 0.0) ? sub / dd : 0.0;
+      F.cs[j - 1] = cc;
+      F.sn[j - 1] = sn;
+      Hc[j - 1] = dd;
+      Hc[j] = 0.0;
+      F.g[j] = -sn * F.g[j - 1];
+      F.g[j - 1] = cc * F.g[j - 1];
+      S.relres = fabs(F.g[j]) / S.beta;
+      S.k = j;
+      if (!isfinite(S.relres) || !isfinite(beta)) {
+        done = 1;
+        S.breakdown = 2;
+      } else if (S.relres <= tol || sub == 0.0 || closing || j >= kmax) {
+        done = 1;
+        if (sub == 0.0) S.breakdown = 1;
+      }
+      if (done) S.done = 1;
+      *F.st = S;
+      if (prog) {
+        progress_put(&prog->fg_done, done);
+        progress_put(&prog->fg_j, j);
+      }
+    }
+    sc[0] = beta;
+    sc[1] = nu;
+    sc[2] = (double)done;
+  }
+  __syncthreads();
+  if (sc[2] != 0.0 || closing) return;
+  const double nu = sc[1];
+  // t = Hraw[0:j+1, 0:j] s (the earlier columns, column k holding rows <= k + 1)
+  for (int c = threadIdx.x; c <= j; c += kThreads) {
+    double a = 0.0;
+    for (int k = (c > 0 ? c - 1 : 0); k < j; ++k) a += Hraw[c + (int64_t)k * ldh] * sv[k];
+    tv[c] = a;
+  }
+  if (threadIdx.x == 0) {
+    double sb = 0.0;
+    for (int c = 0; c < j; ++c) sb += sv[c] * e[j + c];
+    sc[3] = sb;
+  }
+  __syncthreads();
+  const double inu = 1.0 / nu;
+  for (int c = threadIdx.x; c <= j; c += kThreads) {
+    const double h = (c < j) ? (e[j + c] - tv[c]) * inu : ((e[2 * j] - sc[3]) * inu - tv[j]) * inu;
+    hp[c] = h;
+    Hraw[c + (int64_t)j * ldh] = h;
+    col[c] = tv[c] * inu + h;   // c < j: the coefficient of V[:, c]; c = j: gamma
+  }
+  __syncthreads();
+  const double gq = col[j] * inu;   // gamma / nu
+  for (int c = threadIdx.x; c < j; c += kThreads) {
+    coef[c] = sv[c];
+    coef[j + c] = col[c] - gq * sv[c];
+  }
+  if (threadIdx.x == 0) {
+    coef[2 * j] = inu;
+    coef[2 * j + 1] = gq;
+  }
+}
+
+// Sweep 2: rows i of v_j = (q - V_{<j} s) / nu -> V[:, j] and u_{j+1} =
+// w / nu - V_{<j} d - (gamma / nu) q -> V[:, j+1]; partial |u_{j+1}|^2.
+__global__ __launch_bounds__(kSweepThreads) void k_dcgs_update(FgPtrs F, int64_t rows, int j,
+                                                               const double* __restrict__ coef,
+                                                               double* __restrict__ w2part) {
+  if (F.st->done) return;
+  __shared__ double cs_[2 * kMaxKrylov + 2];
+  __shared__ double dsh[kSweepWaves];
+  for (int t = threadIdx.x; t < 2 * j + 2; t += kSweepThreads) cs_[t] = coef[t];
+  __syncthreads();
+  const double* sv = cs_;
+  const double* dv = cs_ + j;
+  const double inu = cs_[2 * j], gq = cs_[2 * j + 1];
   const int64_t i = (int64_t)blockIdx.x * kSweepThreads + threadIdx.x;
   double nrm = 0.0;
   if (i < rows) {
-    const double wi = w[i] - vrow_dot<16>(F.V, F.ldv, i, j, hs);
-    w[i] = wi;
-    nrm = wi * wi;
+    double as[8] = {0, 0, 0, 0, 0, 0, 0, 0}, ad[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    constexpr int NL = 16;   // loads of V in flight per thread
+    for (int c = 0; c < j; c += NL) {
+      double v[NL];
+#pragma unroll
+      for (int q = 0; q < NL; ++q) v[q] = (c + q < j) ? F.V[i + (int64_t)(c + q) * F.ldv] : 0.0;
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        const bool in = (c + q < j);
+        as[q & 7] += v[q] * (in ? sv[c + q] : 0.0);
+        ad[q & 7] += v[q] * (in ? dv[c + q] : 0.0);
+      }
+    }
+    const double vs = ((as[0] + as[1]) + (as[2] + as[3])) + ((as[4] + as[5]) + (as[6] + as[7]));
+    const double vd = ((ad[0] + ad[1]) + (ad[2] + ad[3])) + ((ad[4] + ad[5]) + (ad[6] + ad[7]));
+    double* q = F.V + (int64_t)j * F.ldv;
+    const double qi = q[i], wi = q[F.ldv + i];
+    const double u = wi * inu - vd - gq * qi;
+    q[i] = (qi - vs) * inu;
+    q[F.ldv + i] = u;
+    nrm = u * u;
   }
   nrm = ls_block_sum<double, kSweepThreads>(nrm, dsh);
   if (threadIdx.x == 0) w2part[blockIdx.x] = nrm;
@@ -2030,8 +2064,10 @@ struct LsirWs {
   double* g;
   double* hj;
   char* tpart;        // n x G (TB), column-major partials
-  double* hxpart;     // (kmax+1) x (Gc + Gk)
-  double* h2part;     // (kmax+1) x Gs
+  double* Hraw;       // (kmax + 1) x kmax: the Hessenberg columns before rotation
+  double* dots;       // (2 kmax + 2) x Gs: sweep 1's partials
+  double* dsum;       // 2 kmax + 2: their sums (many row blocks)
+  double* coef;       // 2 kmax + 2: sweep 2's coefficients
   double* w2part;     // max(Gr + Gh, Gs)
   double* rt_hi;      // n x Gr
   double* rt_lo;      // n x Gr
@@ -2040,22 +2076,19 @@ struct LsirWs {
   double* upart;      // 4 x (Gd + Gn)
   double* xin;        // n: W V_x[:, j] (A-path)
   double* tbuf;       // n: A^T v_r (A-path)
-  double* h1sum;      // kmax + 1: summed partials of h1 (many row blocks)
-  double* h2sum;      // kmax + 1: summed partials of h2
   size_t bytes;
 };
 
 struct LsirDims {
-  int kmax, G, Gr, Gc, Gk, Gd, Gs, Gh, Gn;
+  int kmax, G, Gr, Gc, Gd, Gs, Gh, Gn;
   int64_t npan;   // panels of B
 };
 
 template <typename TB, typename TC, int Q>
 void fg_pan_launch(int G, hipStream_t st, ProfEv ev, const TB* Bm, int64_t npan, int64_t m, int64_t n,
-                   const FgPtrs& F, int j, int kmax, const double* w2part, int Gw, double tol, int final_step,
-                   TC* tpart, const double* xin, Progress* prog) {
+                   const FgPtrs& F, int j, const double* w2part, int Gw, TC* tpart, const double* xin) {
   hipExtLaunchKernelGGL((k_fg_pan<TB, TC, Q>), dim3(G), dim3(kThreads), 0, st, ev.a, ev.b, 0, Bm, npan, m, n, F, j,
-                        kmax, w2part, Gw, tol, final_step, tpart, xin, prog);
+                        w2part, Gw, tpart, xin);
 }
 
 LsirDims lsir_dims(const ls_problem_t* P, size_t tb_elt, size_t ta_elt, int fgmres_maxit, int ncu) {
@@ -2066,10 +2099,7 @@ LsirDims lsir_dims(const ls_problem_t* P, size_t tb_elt, size_t ta_elt, int fgmr
   d.G = pan_grid(d.npan, P->n, ncu);
   d.Gr = (int)ls_cdiv(P->m, kResRows);
   d.Gc = (int)ls_cdiv(P->n, 16);
-  // row blocks of the r-part Arnoldi dots: one per compute unit when the
-  // sweeps' partials are summed separately, otherwise at most 128
   d.Gs = (int)ls_cdiv(P->m + P->n, kSweepThreads);
-  d.Gk = (int)std::min<int64_t>((d.Gs > kSweepSumAbove) ? ncu : 128, ls_cdiv(P->m, 512));
   d.Gd = (int)ls_cdiv(P->m + P->n, kThreads);
   d.Gh = (int)ls_cdiv(P->n, 4);
   d.Gn = (int)ls_cdiv(P->n, 32);
@@ -2097,8 +2127,10 @@ LsirWs lsir_carve(char* ws, const ls_problem_t* P, const LsirDims& d, size_t tb_
   w.g = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1)));
   w.hj = reinterpret_cast<double*>(take(8));
   w.tpart = take(tb_elt * (size_t)d.G * n);
-  w.hxpart = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1) * (d.Gc + d.Gk)));
-  w.h2part = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1) * d.Gs));
+  w.Hraw = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1) * kmax));
+  w.dots = reinterpret_cast<double*>(take(8 * (size_t)(2 * kmax + 2) * d.Gs));
+  w.dsum = reinterpret_cast<double*>(take(8 * (size_t)(2 * kmax + 2)));
+  w.coef = reinterpret_cast<double*>(take(8 * (size_t)(2 * kmax + 2)));
   const int w2n = (d.Gr + d.Gh > d.Gs) ? d.Gr + d.Gh : d.Gs;
   w.w2part = reinterpret_cast<double*>(take(8 * (size_t)w2n));
   w.rt_hi = reinterpret_cast<double*>(take(8 * (size_t)d.Gr * n));
@@ -2107,8 +2139,6 @@ LsirWs lsir_carve(char* ws, const ls_problem_t* P, const LsirDims& d, size_t tb_
   w.dz = reinterpret_cast<double*>(take(8 * (size_t)n));
   w.xin = reinterpret_cast<double*>(take(8 * (size_t)n));
   w.tbuf = reinterpret_cast<double*>(take(8 * (size_t)n));
-  w.h1sum = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1)));
-  w.h2sum = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1)));
   w.bytes = off;
   return w;
 }
@@ -2143,10 +2173,9 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
                        r);
   ProgressSlot slot(st);
   Progress *prog = slot.host, *dprog = slot.dev;
-  auto fg_pass = [&](int j, int Gw, int final_step, int grid, ProfEv ev) {
-#define LS_FG_PAN(QQ)                                                                                              \
-  fg_pan_launch<TB, TC, QQ>(grid, st, ev, Bm, d.npan, m, n, F, j, d.kmax, w.w2part, Gw, tol, final_step, tpart, \
-                            AP ? w.xin : nullptr, dprog);                                                          \
+  auto fg_pass = [&](int j, int Gw, ProfEv ev) {
+#define LS_FG_PAN(QQ)                                                                                           \
+  fg_pan_launch<TB, TC, QQ>(d.G, st, ev, Bm, d.npan, m, n, F, j, w.w2part, Gw, tpart, AP ? w.xin : nullptr); \
   break
     switch (q) {
       case 1: LS_FG_PAN(1);
@@ -2157,6 +2186,25 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
       default: LS_FG_PAN(32);
     }
 #undef LS_FG_PAN
+  };
+  // sweep 1, the one-block stage and sweep 2 of iteration j (closing: the
+  // last column's second pass only)
+  auto gram_schmidt = [&](int j, int closing) {
+    const int64_t rows = m + n;
+    hipLaunchKernelGGL(k_dcgs_dots, dim3((unsigned)d.Gs), dim3(kSweepThreads), 0, st, F, rows, j, closing, w.dots);
+    const double* parts = w.dots;
+    int Gp = d.Gs;
+    if (d.Gs > kSweepSumAbove) {   // summed once rather than by the stage's waves
+      hipLaunchKernelGGL(k_colsum_parts, dim3((unsigned)(2 * j + 2)), dim3(kThreads), 0, st, w.st, w.dots, d.Gs,
+                         w.dsum);
+      parts = w.dsum;
+      Gp = 1;
+    }
+    hipLaunchKernelGGL(k_dcgs_small, dim3(1), dim3(kThreads), 0, st, F, w.Hraw, d.kmax, j, closing, parts, Gp, tol,
+                       w.coef, dprog);
+    if (!closing)
+      hipLaunchKernelGGL(k_dcgs_update, dim3((unsigned)d.Gs), dim3(kSweepThreads), 0, st, F, rows, j, w.coef,
+                         w.w2part);
   };
   int total_fg = 0, its = 0, status = LS_NOT_CONVERGED;
   double dx_rel = 0.0, dr_rel = 0.0;
@@ -2194,32 +2242,17 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
       const int Gw = (j == 0) ? d.Gr + d.Gh : d.Gs;
       if (AP)   // the x part of v_j times W, before the pass
         hipLaunchKernelGGL(k_fg_zx, dim3((unsigned)ls_cdiv(n, 32)), dim3(kUtThreads), 0, st, W, n, F, m, j, w.xin);
-      fg_pass(j, Gw, 0, d.G, prof_events(kProfFgPass));
+      fg_pass(j, Gw, prof_events(kProfFgPass));
       // the panels once, v_j read and written, w written, v_x (or W v_x) read, t written
       prof_commit(kProfFgPass, (double)m * n * sizeof(TB) + 24.0 * m + 8.0 * n + (double)n * sizeof(TC));
-      hipLaunchKernelGGL(k_fg_col<TC>, dim3((unsigned)(ncb + d.Gk)), dim3(1024), 0, st, m, n, tpart, d.G, F, j, ncb,
-                         d.Gk, w.hxpart, AP ? w.tbuf : nullptr);
-      if (AP)   // w_x = W^T t and the x-part Arnoldi partials
-        hipLaunchKernelGGL(k_fg_wt, dim3((unsigned)ncb), dim3(1024), 0, st, W, m, n, w.tbuf, F, j, ncb, d.Gk,
-                           w.hxpart);
+      hipLaunchKernelGGL(k_fg_col<TC>, dim3((unsigned)ncb), dim3(1024), 0, st, m, n, tpart, d.G, F, j,
+                         AP ? w.tbuf : nullptr);
+      if (AP)   // w_x = W^T t
+        hipLaunchKernelGGL(k_fg_wt, dim3((unsigned)ncb), dim3(1024), 0, st, W, m, n, w.tbuf, F, j);
       prof_begin(kProfCgs, st);
-      if (d.Gs > kSweepSumAbove) {   // the partials summed once, then read by every block
-        hipLaunchKernelGGL(k_colsum_parts, dim3((unsigned)(j + 1)), dim3(kThreads), 0, st, w.st, w.hxpart,
-                           d.Gc + d.Gk, w.h1sum);
-        hipLaunchKernelGGL(k_cgs1, dim3((unsigned)d.Gs), dim3(kSweepThreads), 0, st, F, m, n, j, d.kmax, w.h1sum, 1,
-                           w.h2part);
-        hipLaunchKernelGGL(k_colsum_parts, dim3((unsigned)(j + 1)), dim3(kThreads), 0, st, w.st, w.h2part, d.Gs,
-                           w.h2sum);
-        hipLaunchKernelGGL(k_cgs2, dim3((unsigned)d.Gs), dim3(kSweepThreads), 0, st, F, m, n, j, d.kmax, w.h2sum, 1,
-                           w.w2part);
-      } else {
-        hipLaunchKernelGGL(k_cgs1, dim3((unsigned)d.Gs), dim3(kSweepThreads), 0, st, F, m, n, j, d.kmax, w.hxpart,
-                           d.Gc + d.Gk, w.h2part);
-        hipLaunchKernelGGL(k_cgs2, dim3((unsigned)d.Gs), dim3(kSweepThreads), 0, st, F, m, n, j, d.kmax, w.h2part,
-                           d.Gs, w.w2part);
-      }
-      // V(:, 0:j) read three times (first sweep twice, second once), w read and written twice
-      prof_end(kProfCgs, st, 3.0 * 8.0 * (j + 1) * (double)(m + n) + 4.0 * 8.0 * (double)(m + n));
+      gram_schmidt(j, 0);
+      // V(:, 0:j) read twice, q_j and w read twice, v_j and u_{j+1} written
+      prof_end(kProfCgs, st, 2.0 * 8.0 * (j + 2) * (double)(m + n) + 2.0 * 8.0 * (double)(m + n));
       // at most `check` iterations in flight; stop queueing once converged
       if (prog) {
         const int rc = progress_wait(&prog->fg_j, &prog->fg_done, j - check + 1, st);
@@ -2234,8 +2267,9 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
         if (S.done) break;
       }
     }
-    // final Givens step for the last column (no-op when already done)
-    fg_pass(j < d.kmax ? j + 1 : d.kmax, d.Gs, 1, 1, ProfEv{});
+    // a cycle at its iteration limit: the second pass of its last vector
+    // makes the last column final (no-op when already done)
+    gram_schmidt(d.kmax, 1);
     hipLaunchKernelGGL(k_fg_update<TU>, dim3((unsigned)d.Gd), dim3(kThreads), 0, st, F, m, n, d.kmax, r, w.dz, w.upart,
                        with_ref ? io->r_ref : nullptr);
     hipLaunchKernelGGL(k_fg_dx<TU>, dim3((unsigned)d.Gn), dim3(kUtThreads), 0, st, W, n, w.dz, x,
@@ -2249,9 +2283,10 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
     std::memcpy(&S, rb.data(), sizeof(FgState));
     std::memcpy(up.data(), rb.data() + up_off, 8 * 4 * (size_t)(d.Gd + d.Gn));
     if (S.breakdown == 2) return LS_E_NONFINITE;
-    // passes and sweeps of columns 0 .. k-1; later ones were queued past convergence
-    prof_keep(kProfFgPass, pmark, S.k);
-    prof_keep(kProfCgs, pmark, S.k);
+    // passes and sweeps of iterations 0 .. k (iteration k's stage found the
+    // convergence of column k-1); later ones were queued past convergence
+    prof_keep(kProfFgPass, pmark, S.k + 1);
+    prof_keep(kProfCgs, pmark, S.k + 1);
     total_fg += S.k;
     double nr[4] = {0, 0, 0, 0}, nx[4] = {0, 0, 0, 0};
     for (int g = 0; g < d.Gd; ++g)

@@ -620,8 +620,10 @@ def test_profile_files_one_record_per_launch_before_convergence(L):
     assert rc == 0
     assert n_l["sketch_mfma"] == 1
     assert n_l["lsqr_pass"] == st["lsqr_its"] + 2          # the first pass, then iterations 1 .. its + 1
-    assert n_l["fgmres_pass"] == st["fgmres_its_total"]
-    assert n_l["cgs_sweep"] == st["fgmres_its_total"]
+    # a converged cycle of k columns makes k + 1 passes: the stage after the
+    # last one finds the convergence of column k - 1
+    assert n_l["fgmres_pass"] == st["fgmres_its_total"] + st["lsir_its"]
+    assert n_l["cgs_sweep"] == st["fgmres_its_total"] + st["lsir_its"]
     assert n_l["lsir_resid_pass"] == st["lsir_its"]
     for k in ("sketch_mfma", "lsqr_pass", "fgmres_pass", "lsir_resid_pass", "cgs_sweep"):
         assert ms[k] > 0
