@@ -1265,7 +1265,7 @@ __device__ __forceinline__ double vrow_dot(const double* __restrict__ V, int64_t
 // normalises it to q_j = u_j / beta_j and writes w = M q_j to V[:, j+1] (M the
 // split-preconditioned augmented operator).  Then:
 //   sweep 1 (k_dcgs_dots): s = V_{<j}^T q_j, b = V_{<j}^T w, q_j . w, q_j . q_j;
-//   one block (k_dcgs_small): the second pass of q_j, v_j = (q_j - V s) / nu
+//   the stage (every block of sweep 2): the second pass of q_j, v_j = (q_j - V s) / nu
 //     with nu^2 = q_j . q_j - |s|^2, makes column j-1 of the Hessenberg matrix
 //     final (H[<j, j-1] += beta_j s, H[j, j-1] = beta_j nu; the Givens
 //     rotations and the convergence test are applied to it); M v_j follows
@@ -1276,9 +1276,9 @@ __device__ __forceinline__ double vrow_dot(const double* __restrict__ V, int64_t
 //   sweep 2 (k_dcgs_update): writes v_j and u_{j+1} and the partials of
 //     |u_{j+1}|^2.
 // H keeps the rotated columns (the triangular factor of the least-squares
-// problem), Hraw the unrotated ones (t needs them).  A cycle that reaches its
-// iteration limit closes with a sweep and a stage of the same kind for its
-// last column (closing = 1: no w).
+// problem), Hraw the unrotated final ones (t needs them), pend the pending
+// first-pass column.  A cycle that reaches its iteration limit closes with a
+// sweep and a stage of the same kind for its last column (closing = 1: no w).
 constexpr int kSweepThreads = 512;   // rows of V per block of the sweeps (one per thread)
 constexpr int kSweepWaves = kSweepThreads / 64;
 // Above this many row blocks the sweep's partials are summed by a launch of
@@ -1378,76 +1378,144 @@ __global__ __launch_bounds__(kSweepThreads) void k_dcgs_dots(FgPtrs F, int64_t r
   }
 }
 
-// The stage of iteration j, one block: sums the sweep's partials (Gp per
-// quantity; 1 when k_colsum_parts has summed them), completes column j-1 of
-// the Hessenberg matrix and its Givens rotation (the convergence test), and
-// unless the cycle ends, forms column j's first-pass coefficients (Hraw and H
-// column j) and the coefficients of sweep 2: coef = [s (j), d (j), 1/nu,
-// gamma/nu].
-__global__ __launch_bounds__(kThreads) void k_dcgs_small(FgPtrs F, double* __restrict__ Hraw, int kmax, int j,
-                                                         int closing, const double* __restrict__ part, int Gp,
-                                                         double tol, double* __restrict__ coef, Progress* prog) {
-  if (F.st->done) return;
-  __shared__ double e[kMaxDots];
-  __shared__ double sv[kMaxKrylov + 1];
-  __shared__ double tv[kMaxKrylov + 1];
-  __shared__ double hp[kMaxKrylov + 1];
-  __shared__ double col[kMaxKrylov + 1];
-  __shared__ double sc[4];   // beta_j, nu, done flag, s . b
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+// The stage of iteration j, computed by every block of sweep 2 (each from the
+// same data in the same order, so that all hold the same coefficients):
+// sums the sweep's partials (Gp per quantity; 1 when k_colsum_parts has summed
+// them); stages Hraw's final columns 0 .. j-2 and the pending first-pass
+// column j-1 (pend[(j-1) % 2]); completes column j-1 (H[<j, j-1] += beta s,
+// H[j, j-1] = beta nu) and, unless the cycle closes, forms column j's
+// first-pass coefficients h'_j and sweep 2's coefficients s, d, 1/nu,
+// gamma/nu.  The writer block (block 0) stores the final column j-1 in Hraw,
+// applies the Givens rotations to it (the convergence test) and stores h'_j in
+// pend[j % 2]; no block reads what the writer stores in the same launch.
+constexpr int kTriMax = kMaxKrylov * (kMaxKrylov + 3) / 2;   // columns 0 .. j-1, rows <= k + 1
+struct DcgsLds {
+  double e[kMaxDots];
+  double tri[kTriMax];   // column k at k (k + 3) / 2, rows 0 .. k + 1
+  double sv[kMaxKrylov + 1];
+  double dv[kMaxKrylov + 1];
+  double tv[kMaxKrylov + 1];
+  double css[kMaxKrylov], sns[kMaxKrylov];
+  double sc[8];          // beta, nu, s . b, 1/nu, gamma/nu
+};
+
+// Returns true when sweep 2 should run (a regular iteration whose vector did
+// not break down).
+template <int NT>
+__device__ bool dcgs_stage(const FgPtrs& F, double* __restrict__ Hraw, double* __restrict__ pend, int kmax, int j,
+                           int closing, const double* __restrict__ part, int Gp, double tol, Progress* prog,
+                           bool writer, DcgsLds& L) {
+  constexpr int nwaves = NT / 64;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
   const int64_t ldh = kmax + 1;
   const double hj = closing ? 0.0 : *F.hj;
   const bool skip = !closing && (hj == 0.0 || !isfinite(hj));   // no sweep ran: nothing to read
   const int ne = 2 * j + 2;
+  auto wanted = [&](int q) { return !(closing && q >= j && q < 2 * j + 1); };   // the closing sweep has no w
   if (!skip) {
-    for (int q = wave; q < ne; q += kThreads / 64) {
-      if (closing && q >= j && q < 2 * j + 1) continue;   // the closing sweep has no w
-      const double* pq = part + (int64_t)q * Gp;
-      double a = 0.0;
-      for (int g = lane; g < Gp; g += 64) a += pq[g];
-      a = ls_wave_sum(a);
-      if (lane == 0) e[q] = a;
+    if (Gp == 1) {
+      for (int q = tid; q < ne; q += NT)
+        if (wanted(q)) L.e[q] = part[q];
+    } else {
+      // wave per quantity, four quantities' loads (up to eight per lane each) in flight
+      for (int q0 = wave; q0 < ne; q0 += 4 * nwaves) {
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int g0 = lane; g0 < Gp; g0 += 64 * 8) {
+          double v[4][8];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int q = q0 + nwaves * u;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              const int g = g0 + 64 * k;
+              v[u][k] = (q < ne && wanted(q) && g < Gp) ? part[(int64_t)q * Gp + g] : 0.0;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) a[u] += v[u][k];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int q = q0 + nwaves * u;
+          const double t = ls_wave_sum(a[u]);
+          if (lane == 0 && q < ne) L.e[q] = t;
+        }
+      }
+    }
+  }
+  // final columns 0 .. j-2 from Hraw, pending column j-1 from pend
+  const int ntri = j * (j + 3) / 2;
+  const double* pj = pend + (int64_t)((j - 1) & 1) * ldh;
+  for (int idx = tid; idx < ntri; idx += NT) {
+    int k = (int)((sqrt(8.0 * idx + 9.0) - 3.0) * 0.5);   // column of idx: k (k + 3) / 2 <= idx
+    while (k > 0 && k * (k + 3) / 2 > idx) --k;
+    while ((k + 1) * (k + 4) / 2 <= idx) ++k;
+    const int r = idx - k * (k + 3) / 2;
+    L.tri[idx] = (k == j - 1) ? ((r < j) ? pj[r] : 0.0) : Hraw[r + (int64_t)k * ldh];
+  }
+  if (writer)
+    for (int i = tid; i < j - 1; i += NT) {
+      L.css[i] = F.cs[i];
+      L.sns[i] = F.sn[i];
+    }
+  __syncthreads();
+  // s, beta and nu (wave 0)
+  if (wave == 0) {
+    const double beta = closing ? sqrt(L.e[2 * j + 1]) : hj;
+    double nu = 1.0;   // j = 0: v_0 is final
+    if (j > 0) {
+      if (skip || !isfinite(beta) || beta == 0.0) {
+        nu = 0.0;
+      } else {
+        const double inv = closing ? 1.0 / beta : 1.0;
+        double ss = 0.0;
+        for (int c = lane; c < j; c += 64) {
+          const double v = L.e[c] * inv;
+          L.sv[c] = v;
+          ss += v * v;
+        }
+        ss = ls_wave_sum(ss);
+        const double sig = closing ? 1.0 : L.e[2 * j + 1];
+        const double nu2 = sig - ss;
+        nu = (nu2 > 0.0) ? sqrt(nu2) : 0.0;
+      }
+    }
+    if (lane == 0) {
+      L.sc[0] = beta;
+      L.sc[1] = nu;
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    FgState S = *F.st;
-    double beta = hj, nu = 1.0;
-    if (closing) {
-      beta = sqrt(e[2 * j + 1]);
-    }
-    if (j == 0) {
-      nu = 1.0;   // v_0 is final
-    } else if (skip || !isfinite(beta) || beta == 0.0) {
-      nu = 0.0;
-    } else {
-      const double inv = closing ? 1.0 / beta : 1.0;
-      double ss = 0.0;
-      for (int c = 0; c < j; ++c) {
-        sv[c] = e[c] * inv;
-        ss += sv[c] * sv[c];
+  const double beta = L.sc[0], nu = L.sc[1];
+  const bool ok = (j == 0) || (isfinite(beta) && beta > 0.0 && nu > 0.0);
+  if (j > 0) {
+    // column j - 1 becomes final
+    double* tc = L.tri + (j - 1) * (j + 2) / 2;
+    for (int c = tid; c <= j; c += NT) {
+      double v = tc[c];
+      if (c < j) {
+        if (ok) v += beta * L.sv[c];
+      } else {
+        v = ok ? beta * nu : 0.0;
       }
-      const double sig = closing ? 1.0 : e[2 * j + 1];
-      const double nu2 = sig - ss;
-      nu = (nu2 > 0.0) ? sqrt(nu2) : 0.0;
+      tc[c] = v;
+      if (writer) Hraw[c + (int64_t)(j - 1) * ldh] = v;
     }
-    int done = 0;
-    if (j > 0) {
-      // column j - 1 becomes final: H[<j, j-1] += beta s, H[j, j-1] = beta nu
-      double* hr = Hraw + (int64_t)(j - 1) * ldh;
-      const bool ok = isfinite(beta) && beta > 0.0 && nu > 0.0;
-      if (ok)
-        for (int c = 0; c < j; ++c) hr[c] += beta * sv[c];
-      const double sub = ok ? beta * nu : 0.0;
-      hr[j] = sub;
+    __syncthreads();
+    if (writer && tid == 0) {
       // Givens rotations of the earlier columns, then a new one for this column
+      FgState S = *F.st;
+      const double sub = tc[j];
       double* Hc = F.H + (int64_t)(j - 1) * ldh;
-      double x = hr[0];
+      double x = tc[0];
       for (int i = 0; i < j - 1; ++i) {
-        const double y = hr[i + 1];
-        Hc[i] = F.cs[i] * x + F.sn[i] * y;
-        x = -F.sn[i] * x + F.cs[i] * y;
+        const double y = tc[i + 1];
+        Hc[i] = L.css[i] * x + L.sns[i] * y;
+        x = -L.sns[i] * x + L.css[i] * y;
       }
       const double dd = hypot(x, sub);
       const double cc = (dd > 0.0) ? x / dd : 1.0;
@@ -1456,10 +1524,12 @@ __global__ __launch_bounds__(kThreads) void k_dcgs_small(FgPtrs F, double* __res
       F.sn[j - 1] = sn;
       Hc[j - 1] = dd;
       Hc[j] = 0.0;
-      F.g[j] = -sn * F.g[j - 1];
-      F.g[j - 1] = cc * F.g[j - 1];
-      S.relres = fabs(F.g[j]) / S.beta;
+      const double gl = F.g[j - 1];
+      F.g[j] = -sn * gl;
+      F.g[j - 1] = cc * gl;
+      S.relres = fabs(sn * gl) / S.beta;
       S.k = j;
+      int done = 0;
       if (!isfinite(S.relres) || !isfinite(beta)) {
         done = 1;
         S.breakdown = 2;
@@ -1474,57 +1544,54 @@ __global__ __launch_bounds__(kThreads) void k_dcgs_small(FgPtrs F, double* __res
         progress_put(&prog->fg_j, j);
       }
     }
-    sc[0] = beta;
-    sc[1] = nu;
-    sc[2] = (double)done;
   }
-  __syncthreads();
-  if (sc[2] != 0.0 || closing) return;
-  const double nu = sc[1];
-  // t = Hraw[0:j+1, 0:j] s (the earlier columns, column k holding rows <= k + 1)
-  for (int c = threadIdx.x; c <= j; c += kThreads) {
+  if (closing || !ok) return false;
+  // t = Hraw[0:j+1, 0:j] s (column k holding rows <= k + 1)
+  for (int c = tid; c <= j; c += NT) {
     double a = 0.0;
-    for (int k = (c > 0 ? c - 1 : 0); k < j; ++k) a += Hraw[c + (int64_t)k * ldh] * sv[k];
-    tv[c] = a;
+    for (int k = (c > 0 ? c - 1 : 0); k < j; ++k) a += L.tri[k * (k + 3) / 2 + c] * L.sv[k];
+    L.tv[c] = a;
   }
-  if (threadIdx.x == 0) {
+  if (wave == nwaves - 1) {
     double sb = 0.0;
-    for (int c = 0; c < j; ++c) sb += sv[c] * e[j + c];
-    sc[3] = sb;
+    for (int c = lane; c < j; c += 64) sb += L.sv[c] * L.e[j + c];
+    sb = ls_wave_sum(sb);
+    if (lane == 0) L.sc[2] = sb;
   }
   __syncthreads();
   const double inu = 1.0 / nu;
-  for (int c = threadIdx.x; c <= j; c += kThreads) {
-    const double h = (c < j) ? (e[j + c] - tv[c]) * inu : ((e[2 * j] - sc[3]) * inu - tv[j]) * inu;
-    hp[c] = h;
-    Hraw[c + (int64_t)j * ldh] = h;
-    col[c] = tv[c] * inu + h;   // c < j: the coefficient of V[:, c]; c = j: gamma
+  double* pn = pend + (int64_t)(j & 1) * ldh;
+  for (int c = tid; c <= j; c += NT) {
+    const double h = (c < j) ? (L.e[j + c] - L.tv[c]) * inu : ((L.e[2 * j] - L.sc[2]) * inu - L.tv[j]) * inu;
+    if (writer) pn[c] = h;
+    L.tv[c] = L.tv[c] * inu + h;   // c < j: the coefficient of V[:, c]; c = j: gamma
   }
   __syncthreads();
-  const double gq = col[j] * inu;   // gamma / nu
-  for (int c = threadIdx.x; c < j; c += kThreads) {
-    coef[c] = sv[c];
-    coef[j + c] = col[c] - gq * sv[c];
+  const double gq = L.tv[j] * inu;   // gamma / nu
+  for (int c = tid; c < j; c += NT) L.dv[c] = L.tv[c] - gq * L.sv[c];
+  if (tid == 0) {
+    L.sc[3] = inu;
+    L.sc[4] = gq;
   }
-  if (threadIdx.x == 0) {
-    coef[2 * j] = inu;
-    coef[2 * j + 1] = gq;
-  }
+  __syncthreads();
+  return true;
 }
 
-// Sweep 2: rows i of v_j = (q - V_{<j} s) / nu -> V[:, j] and u_{j+1} =
-// w / nu - V_{<j} d - (gamma / nu) q -> V[:, j+1]; partial |u_{j+1}|^2.
-__global__ __launch_bounds__(kSweepThreads) void k_dcgs_update(FgPtrs F, int64_t rows, int j,
-                                                               const double* __restrict__ coef,
-                                                               double* __restrict__ w2part) {
+// A cycle at its iteration limit: the second pass of u_kmax makes column
+// kmax - 1 final (one block).
+__global__ __launch_bounds__(kSweepThreads) void k_dcgs_close(FgPtrs F, double* __restrict__ Hraw,
+                                                              double* __restrict__ pend, int kmax,
+                                                              const double* __restrict__ part, int Gp, double tol) {
   if (F.st->done) return;
-  __shared__ double cs_[2 * kMaxKrylov + 2];
-  __shared__ double dsh[kSweepWaves];
-  for (int t = threadIdx.x; t < 2 * j + 2; t += kSweepThreads) cs_[t] = coef[t];
-  __syncthreads();
-  const double* sv = cs_;
-  const double* dv = cs_ + j;
-  const double inu = cs_[2 * j], gq = cs_[2 * j + 1];
+  __shared__ DcgsLds L;
+  dcgs_stage<kSweepThreads>(F, Hraw, pend, kmax, kmax, 1, part, Gp, tol, nullptr, true, L);
+}
+
+// Sweep 2 over the block's rows: v_j = (q - V_{<j} s) / nu -> V[:, j] and
+// u_{j+1} = w / nu - V_{<j} d - (gamma / nu) q -> V[:, j+1]; partial
+// |u_{j+1}|^2 -> w2part.
+__device__ __forceinline__ void dcgs_rows(const FgPtrs& F, int64_t rows, int j, const double* sv, const double* dv,
+                                          double inu, double gq, double* __restrict__ w2part, double* dsh) {
   const int64_t i = (int64_t)blockIdx.x * kSweepThreads + threadIdx.x;
   double nrm = 0.0;
   if (i < rows) {
@@ -1552,6 +1619,52 @@ __global__ __launch_bounds__(kSweepThreads) void k_dcgs_update(FgPtrs F, int64_t
   }
   nrm = ls_block_sum<double, kSweepThreads>(nrm, dsh);
   if (threadIdx.x == 0) w2part[blockIdx.x] = nrm;
+}
+
+// Sweep 2 with the stage in every block (few row blocks: the stage's reads are
+// cheap and its launch is saved).
+__global__ __launch_bounds__(kSweepThreads) void k_dcgs_update(FgPtrs F, int64_t rows, int j, double* __restrict__ Hraw,
+                                                               double* __restrict__ pend, int kmax,
+                                                               const double* __restrict__ part, int Gp, double tol,
+                                                               Progress* prog, double* __restrict__ w2part) {
+  if (F.st->done) return;
+  __shared__ DcgsLds L;
+  __shared__ double dsh[kSweepWaves];
+  if (!dcgs_stage<kSweepThreads>(F, Hraw, pend, kmax, j, 0, part, Gp, tol, prog, blockIdx.x == 0, L)) return;
+  dcgs_rows(F, rows, j, L.sv, L.dv, L.sc[3], L.sc[4], w2part, dsh);
+}
+
+// Many row blocks: the stage runs once (one block) and stores sweep 2's
+// coefficients coef = [s (j), d (j), 1/nu, gamma/nu, go], go = 0 when sweep 2
+// is not needed; k_dcgs_apply then reads them.
+__global__ __launch_bounds__(kSweepThreads) void k_dcgs_stage(FgPtrs F, int j, double* __restrict__ Hraw,
+                                                              double* __restrict__ pend, int kmax,
+                                                              const double* __restrict__ part, int Gp, double tol,
+                                                              Progress* prog, double* __restrict__ coef) {
+  if (F.st->done) return;
+  __shared__ DcgsLds L;
+  const bool go = dcgs_stage<kSweepThreads>(F, Hraw, pend, kmax, j, 0, part, Gp, tol, prog, true, L);
+  for (int c = threadIdx.x; c < j; c += kSweepThreads) {
+    coef[c] = L.sv[c];
+    coef[j + c] = L.dv[c];
+  }
+  if (threadIdx.x == 0) {
+    coef[2 * j] = L.sc[3];
+    coef[2 * j + 1] = L.sc[4];
+    coef[2 * j + 2] = go ? 1.0 : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(kSweepThreads) void k_dcgs_apply(FgPtrs F, int64_t rows, int j,
+                                                              const double* __restrict__ coef,
+                                                              double* __restrict__ w2part) {
+  if (F.st->done) return;
+  __shared__ double cs_[2 * kMaxKrylov + 3];
+  __shared__ double dsh[kSweepWaves];
+  for (int t = threadIdx.x; t < 2 * j + 3; t += kSweepThreads) cs_[t] = coef[t];
+  __syncthreads();
+  if (cs_[2 * j + 2] == 0.0) return;
+  dcgs_rows(F, rows, j, cs_, cs_ + j, cs_[2 * j], cs_[2 * j + 1], w2part, dsh);
 }
 
 // Correction of one refinement step: y = H(0:k,0:k)^-1 g(0:k) (every block);
@@ -2067,7 +2180,8 @@ struct LsirWs {
   double* Hraw;       // (kmax + 1) x kmax: the Hessenberg columns before rotation
   double* dots;       // (2 kmax + 2) x Gs: sweep 1's partials
   double* dsum;       // 2 kmax + 2: their sums (many row blocks)
-  double* coef;       // 2 kmax + 2: sweep 2's coefficients
+  double* pend;       // 2 x (kmax + 1): the pending first-pass column, by parity of j
+  double* coef;       // 2 kmax + 3: sweep 2's coefficients (many row blocks)
   double* w2part;     // max(Gr + Gh, Gs)
   double* rt_hi;      // n x Gr
   double* rt_lo;      // n x Gr
@@ -2130,7 +2244,8 @@ LsirWs lsir_carve(char* ws, const ls_problem_t* P, const LsirDims& d, size_t tb_
   w.Hraw = reinterpret_cast<double*>(take(8 * (size_t)(kmax + 1) * kmax));
   w.dots = reinterpret_cast<double*>(take(8 * (size_t)(2 * kmax + 2) * d.Gs));
   w.dsum = reinterpret_cast<double*>(take(8 * (size_t)(2 * kmax + 2)));
-  w.coef = reinterpret_cast<double*>(take(8 * (size_t)(2 * kmax + 2)));
+  w.pend = reinterpret_cast<double*>(take(8 * 2 * (size_t)(kmax + 1)));
+  w.coef = reinterpret_cast<double*>(take(8 * (size_t)(2 * kmax + 3)));
   const int w2n = (d.Gr + d.Gh > d.Gs) ? d.Gr + d.Gh : d.Gs;
   w.w2part = reinterpret_cast<double*>(take(8 * (size_t)w2n));
   w.rt_hi = reinterpret_cast<double*>(take(8 * (size_t)d.Gr * n));
@@ -2187,8 +2302,8 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
     }
 #undef LS_FG_PAN
   };
-  // sweep 1, the one-block stage and sweep 2 of iteration j (closing: the
-  // last column's second pass only)
+  // sweep 1, then sweep 2 with the stage (closing: the last column's second
+  // pass only)
   auto gram_schmidt = [&](int j, int closing) {
     const int64_t rows = m + n;
     hipLaunchKernelGGL(k_dcgs_dots, dim3((unsigned)d.Gs), dim3(kSweepThreads), 0, st, F, rows, j, closing, w.dots);
@@ -2200,11 +2315,16 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
       parts = w.dsum;
       Gp = 1;
     }
-    hipLaunchKernelGGL(k_dcgs_small, dim3(1), dim3(kThreads), 0, st, F, w.Hraw, d.kmax, j, closing, parts, Gp, tol,
-                       w.coef, dprog);
-    if (!closing)
-      hipLaunchKernelGGL(k_dcgs_update, dim3((unsigned)d.Gs), dim3(kSweepThreads), 0, st, F, rows, j, w.coef,
-                         w.w2part);
+    if (closing) {
+      hipLaunchKernelGGL(k_dcgs_close, dim3(1), dim3(kSweepThreads), 0, st, F, w.Hraw, w.pend, d.kmax, parts, Gp, tol);
+    } else if (d.Gs > kSweepSumAbove) {   // the stage once, then the sweep
+      hipLaunchKernelGGL(k_dcgs_stage, dim3(1), dim3(kSweepThreads), 0, st, F, j, w.Hraw, w.pend, d.kmax, parts, Gp,
+                         tol, dprog, w.coef);
+      hipLaunchKernelGGL(k_dcgs_apply, dim3((unsigned)d.Gs), dim3(kSweepThreads), 0, st, F, rows, j, w.coef, w.w2part);
+    } else {
+      hipLaunchKernelGGL(k_dcgs_update, dim3((unsigned)d.Gs), dim3(kSweepThreads), 0, st, F, rows, j, w.Hraw, w.pend,
+                         d.kmax, parts, Gp, tol, dprog, w.w2part);
+    }
   };
   int total_fg = 0, its = 0, status = LS_NOT_CONVERGED;
   double dx_rel = 0.0, dr_rel = 0.0;
