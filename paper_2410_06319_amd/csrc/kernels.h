@@ -82,8 +82,8 @@ size_t b_bytes(const ls_problem_t* P, ls_prec_t tb);
 int lsqr_device(const ls_problem_t* P, const double* R, int64_t ldr, const double* W, const void* Bm, int apply_w,
                 ls_prec_t u, double* x, const ls_iter_opts_t* io, ls_stats_t* stats, char* ws, size_t ws_bytes,
                 hipStream_t st);
-// ls_solve runs LSQR over A's panels (no B) when the refinement uses them and
-// A is stored in the working precision.
+// LSQR can run over A's panels (no B) when the refinement uses them and A is
+// stored in the working precision (ls_iter_opts_t.lsqr_operand = 2).
 bool lsqr_on_a(const ls_problem_t* P, const ls_precs_t* pr);
 size_t lsqr_workspace(const ls_problem_t* P, ls_prec_t u, int ncu);
 

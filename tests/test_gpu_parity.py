@@ -411,8 +411,8 @@ def test_lsqr_operand_choices_are_checked(L):
     assert e.value.code == -6   # LS_E_UNSUPPORTED
 
 
-# ls_solve on the A-path: LSQR over A's panels (the default there) and over
-# B = A R^-1 reach the same accuracy with about as many iterations
+# ls_solve on the A-path: LSQR over A's panels (lsqr_operand = 2) and over
+# B = A R^-1 (the default) reach the same accuracy with about as many iterations
 @pytest.mark.parametrize("m,n,kappa", [(20000, 100, 1e4), (6003, 700, 1e5)])
 def test_solve_lsqr_operands_agree(L, m, n, kappa):
     P = make_problem(m, n, kappa, seed=2410064197, store="f32")
