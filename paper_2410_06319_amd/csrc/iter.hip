@@ -27,6 +27,7 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "lanes.h"
 
 namespace ls {
 namespace {
@@ -61,6 +62,17 @@ struct PanVec<double> {
   static constexpr int PR = 2;
   using type = ls_double2v;
 };
+
+// The value of lane src on every lane (through a scalar register).
+__device__ __forceinline__ float lane_value(float v, int src) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
+}
+__device__ __forceinline__ double lane_value(double v, int src) {
+  const long long u = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), src);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
 
 // Butterfly sum over the wave; every lane ends with the same bits (each step
 // adds the same two numbers in every lane of a pair).
@@ -343,10 +355,14 @@ __global__ __launch_bounds__(kThreads) void k_lsqr_pan(const T* __restrict__ Bp,
     for (int q = 0; q < Q; ++q)
 #pragma unroll
       for (int k = 0; k < PR; ++k) s[k] += cur[q][k] * vl[q];
+    // the panel's row sums: a transposed butterfly leaves row idx's on lanes
+    // (64 / PR) idx .., then each row's sum reaches every lane
+    int idx;
+    const T tot = wave_multi_sum<T, PR>(s, lane, idx);
     vec_t un;
 #pragma unroll
     for (int k = 0; k < PR; ++k) {
-      const T sk = wave_allsum(s[k]);
+      const T sk = lane_value(tot, k * (64 / PR));
       un[k] = (i0 + k < m) ? sk - coef * uo[k] : T(0);
     }
     if (lane == 0) {
@@ -1082,21 +1098,23 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
 #pragma unroll
         for (int k = 0; k < PR; ++k) s[k] += (TC)cur[q][k] * vl[q];
     }
-    double wr[PR];
-#pragma unroll
-    for (int k = 0; k < PR; ++k) {
-      const TC sk = wave_allsum(s[k]);
-      wr[k] = (i0 + k < m) ? (double)(vrt[k] + sk) : 0.0;
-    }
-    // every lane holds the panel's rows of v_j and w: lanes 0 .. PR-1 store
-    // v_j's, lanes PR .. 2 PR-1 w's (one store instruction)
-    if (lane < 2 * PR) {
-      const int k = lane % PR;
-      double val = 0.0;
+    // the panel's row sums: a transposed butterfly leaves row idx's on lanes
+    // (64 / PR) idx .. (64 / PR) (idx + 1) - 1; the first of them stores w's
+    // row idx, the second v_j's (one store instruction)
+    int idx;
+    const TC sk = wave_multi_sum<TC, PR>(s, lane, idx);
+    const int sub = lane % (64 / PR);
+    if (sub < 2 && i0 + idx < m) {
+      double vrk = 0.0;
+      TC vrtk = 0;
 #pragma unroll
       for (int k2 = 0; k2 < PR; ++k2)
-        if (k2 == k) val = (lane < PR) ? vr[k2] : wr[k2];
-      if (i0 + k < m) ((lane < PR) ? vj : w)[i0 + k] = val;
+        if (k2 == idx) {
+          vrk = vr[k2];
+          vrtk = vrt[k2];
+        }
+      if (sub == 0) w[i0 + idx] = (double)(vrtk + sk);
+      else vj[i0 + idx] = vrk;
     }
     if constexpr (!kConv) {
 #pragma unroll
