@@ -1,7 +1,7 @@
 """Narrow floating-point formats used by the sketch (oracle, test use only).
 
-Section 3 lets the sketch run in a precision u_s and says that A is "stored
-in precision u_s" (Algorithm 1, input).  Section 3.2 describes a one-sided
+Section 3 lets the sketch run in a precision u_s, A being held in that
+precision (Algorithm 1's input).  Section 3.2 describes a one-sided
 column scaling for narrow-range formats: divide every column by its largest
 magnitude and multiply by a positive constant, then use R S^-1 as the
 preconditioner.  The constant is taken as a power of two, so that the

@@ -34,8 +34,18 @@ def test_quantised_sketch_is_product_of_quantised_operands(fmt, terms):
     s = 9
     colscale = fmt in ("f16", "e4m3")
     Y, e = sketch.sketch(P.At, P.b, s, seed=3, fmt=fmt, terms=terms, colscale=colscale, chunk=64)
-    S = philox.gaussian_block(3, 0, 0, s, 0, 301)
-    Sq = formats.round_to(S.astype(np.float32).astype(np.float64), fmt)
+    # S from its definition: the 16-bit uniform of entry (k, i) from the Philox
+    # block (i // 8, k, 0, 2), through Phi^-1 (mpmath's erfinv), rounded
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 30
+    S = np.empty((s, 301))
+    for k in range(s):
+        for q in range(0, 301, 8):
+            w = philox.philox4x32_10(q // 8, k, 0, 2, 3, 0)
+            for t in range(min(8, 301 - q)):
+                U = (int(w[t // 2]) >> (16 * (t % 2))) & 0xFFFF
+                S[k, q + t] = float(mpmath.sqrt(2) * mpmath.erfinv(mpmath.mpf(2 * U + 1) / 65536 - 1))
+    Sq = formats.round_to(S, fmt)
     M = np.column_stack([P.A(), P.b.astype(np.float64)])
     Ms = M * 2.0 ** e
     Mq = sum(formats.split_terms(Ms, fmt, terms))
@@ -43,8 +53,9 @@ def test_quantised_sketch_is_product_of_quantised_operands(fmt, terms):
     assert np.allclose(Y, ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
     # every scaled, quantised entry is a finite value of the format
     assert np.all(np.isfinite(Mq)) and np.abs(Mq).max() <= formats.FORMATS[fmt][2]
-    # and the quantised sketch approximates the exact one to the format's accuracy
-    Y64, _ = sketch.sketch(P.At, P.b, s, seed=3, fmt="f64")
+    # and the quantised sketch approximates the one with unrounded operands
+    # (the same Gaussian values, [A b] exact) to the format's accuracy
+    Y64 = (S @ M) / math.sqrt(s)
     u = formats.UNIT_ROUNDOFF[fmt]
     rel = np.linalg.norm(Y - Y64) / np.linalg.norm(Y64)
     assert rel < 8 * u

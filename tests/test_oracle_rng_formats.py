@@ -9,6 +9,7 @@ from scipy import stats
 
 from conftest import read_golden
 from oracle import formats, philox
+from oracle import sketch as osketch
 
 
 def test_philox_known_answer_vectors():
@@ -131,3 +132,71 @@ def test_split_terms_error_shrinks_geometrically(fmt):
             assert np.array_equal(formats.round_to(t, fmt), t)
         err = np.max(np.abs(np.sum(T, axis=0) - M) / np.abs(M))
         assert err <= u ** terms * 2.0 + 1e-300
+
+
+# ------------------------------------------------------------------ narrow-format sketch entries
+def test_normal_quantiles16_against_mpmath():
+    # z[U] = Phi^-1((U + 1/2) / 2^16): compared with mpmath's inverse error
+    # function at 40 digits (an independent evaluation), increasing and odd
+    mpmath = pytest.importorskip("mpmath")
+    z = philox.normal_quantiles16()
+    assert z.shape == (65536,)
+    assert np.all(np.diff(z) > 0)
+    assert np.array_equal(z[::-1], -z)
+    mpmath.mp.dps = 40
+    for U in list(range(0, 65536, 611)) + [0, 1, 2, 32767, 32768, 65534, 65535]:
+        p = mpmath.mpf(2 * U + 1) / 131072
+        ref = float(mpmath.sqrt(2) * mpmath.erfinv(2 * p - 1))
+        assert abs(z[U] - ref) <= 1e-15 * max(1.0, abs(ref)), U
+
+
+def test_normal_quantiles16_distribution():
+    z = philox.normal_quantiles16()
+    U = np.arange(65536)
+    # the normal distribution function (ndtr, another routine) maps them back
+    assert np.max(np.abs(stats.norm.cdf(z) - (U + 0.5) / 65536)) < 1e-13
+    assert abs(z.sum()) < 1e-9
+    v = np.mean(z * z)          # the law's tails end near 4.32: slightly under 1
+    assert 0.9999 < v < 1.0
+    assert 4.32 < z[-1] < 4.33
+
+
+def test_uniform16_stream():
+    seed, prob = 2410063190, 3
+    U = philox.uniform16_block(seed, prob, 0, 5, 0, 40)
+    # entry (k, i): half i % 2 of word (i % 8) // 2 of the block (i // 8, k, prob, 2)
+    for k, i in ((0, 0), (0, 1), (0, 7), (2, 13), (4, 39)):
+        w = philox.philox4x32_10(i // 8, k, prob, 2, seed & 0xFFFFFFFF, seed >> 32)
+        assert U[k, i] == (int(w[(i % 8) // 2]) >> (16 * (i % 2))) & 0xFFFF
+    part = philox.uniform16_block(seed, prob, 1, 4, 3, 29)
+    assert np.array_equal(part, U[1:4, 3:29])
+    big = philox.uniform16_block(seed, prob, 0, 64, 0, 4096)
+    counts = np.bincount((big >> 8).ravel(), minlength=256)
+    assert stats.chisquare(counts).pvalue > 1e-4
+    for a, b in ((0, 1), (1, 2), (3, 4), (7, 8)):
+        corr = np.corrcoef(big[:, a::16].ravel(), big[:, b::16].ravel())[0, 1]
+        assert abs(corr) < 5 / math.sqrt(big[:, a::16].size)
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "f16", "e4m3"])
+def test_format_quantiles_round_far_from_ties(fmt):
+    # any evaluation of z within 1e-12 relative rounds to the same format value
+    z = philox.normal_quantiles16()
+    lo = formats.round_to(z * (1 - 1e-12), fmt)
+    hi = formats.round_to(z * (1 + 1e-12), fmt)
+    assert np.array_equal(lo, hi)
+    q = osketch.format_quantiles(fmt)
+    assert np.array_equal(q, formats.round_to(z, fmt))
+    assert np.array_equal(q[::-1], -q)
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "e4m3"])
+def test_narrow_sketch_entries_moments(fmt):
+    # sample moments of S against the exact moments of the 2^16 rounded quantiles
+    q = osketch.format_quantiles(fmt)
+    m2, m4 = np.mean(q ** 2), np.mean(q ** 4)
+    S = osketch.quantised_gaussian_block(11, 0, 0, 64, 0, 4096, fmt).ravel()
+    n = S.size
+    assert abs(S.mean()) < 5 * math.sqrt(m2 / n)
+    assert abs(np.mean(S ** 2) - m2) < 5 * math.sqrt((m4 - m2 ** 2) / n)
+    assert abs(m2 - 1.0) < (2e-2 if fmt == "e4m3" else 2e-3)
