@@ -85,9 +85,13 @@ typedef struct {
 } ls_precs_t;
 
 /* Sketch options (Section 2: Gaussian embedding, s = c n with small c;
- * Section 5 uses s = 4n).  Omega = S / sqrt(s), S[k, i] drawn from the
- * Philox4x32-10 block with counter (i / 4, k, prob_id, 0) and key
- * (seed mod 2^32, seed / 2^32) by Box-Muller on 23-bit uniforms.
+ * Section 5 uses s = 4n).  Omega = S / sqrt(s); key (seed mod 2^32,
+ * seed / 2^32).  u_s = LS_FP64: S[k, i] from the Philox4x32-10 block with
+ * counter (i / 4, k, prob_id, 0) by Box-Muller on 23-bit uniforms.  Narrow
+ * u_s: S[k, i] = the format's rounding (nearest, ties to even) of
+ * Phi^-1((U + 1/2) / 2^16), U the 16-bit uniform in half i % 2 of word
+ * (i % 8) / 2 of the block with counter (i / 8, k, prob_id, 2): a Gaussian
+ * to 16-bit resolution, eight entries per block.
  * terms: A (and b) are represented in u_s as a sum of `terms` rounded parts
  * (1 = a plain cast; each further part adds the format's precision, so that
  * u_s = u^terms, on the same MFMA; e4m3's exponent range bounds its parts'
@@ -232,8 +236,8 @@ int ls_workspace_size(const ls_problem_t *P, const ls_sketch_opts_t *so,
  * column major with leading dimension ldy >= s (device).  Column n is
  * Omega b, which Algorithm 2's sketch-and-solve start needs.  With u_s =
  * LS_BF16, LS_FP16 or LS_FP8E4M3 (OCP e4m3, largest value 448, saturating)
- * the entries of S are rounded to the format from binary32 Box-Muller
- * values; the columns of [A b] are optionally scaled by 2^e_j (e_j the
+ * the entries of S are the format's table values above; the columns of
+ * [A b] are optionally scaled by 2^e_j (e_j the
  * largest integer with max_i |[A b]_ij| 2^e_j <= the format's largest value,
  * Section 3.2) and represented as `terms` rounded parts (nearest, ties to
  * even); products run on MFMA with binary32 accumulation over chunks of rows
@@ -329,10 +333,10 @@ int ls_solve_batched(int nprob, const ls_problem_t *P, const ls_sketch_opts_t *s
                      size_t ws_bytes, void *stream);
 
 /* The sketch operator itself, for checks and small problems: S[k, i] for
- * k < s, i < m as defined under ls_sketch_opts_t, rounded as the sketch in
- * format fmt (LS_FP64, LS_BF16, LS_FP16 or LS_FP8E4M3) uses it, unscaled
- * (Omega = S / sqrt(s)).  fmt = LS_FP32 gives the binary32 Box-Muller values
- * the narrow formats are rounded from.
+ * k < s, i < m as defined under ls_sketch_opts_t, as the sketch in format fmt
+ * (LS_FP64, LS_BF16, LS_FP16 or LS_FP8E4M3) uses it, unscaled
+ * (Omega = S / sqrt(s)).  The first call for a narrow format on a device (here
+ * or in a sketch) fills that device's quantile tables and synchronises.
  * S: device, binary64, s x m column major, lds >= s.  Does not synchronise. */
 int ls_omega(uint64_t seed, uint32_t prob_id, int64_t s, int64_t m, ls_prec_t fmt,
              double *S, int64_t lds, void *stream);

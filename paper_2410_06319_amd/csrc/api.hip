@@ -618,8 +618,7 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
 int ls_omega(uint64_t seed, uint32_t prob_id, int64_t s, int64_t m, ls_prec_t fmt, double* S, int64_t lds,
              void* stream) {
   if (!S || s < 1 || m < 1 || lds < s || s > 65535) return LS_E_ARG;
-  if (!(fmt == LS_FP64 || fmt == LS_FP32 || fmt == LS_BF16 || fmt == LS_FP16 || fmt == LS_FP8E4M3))
-    return LS_E_UNSUPPORTED;
+  if (!(fmt == LS_FP64 || fmt == LS_BF16 || fmt == LS_FP16 || fmt == LS_FP8E4M3)) return LS_E_UNSUPPORTED;
   return omega_run(seed, prob_id, s, m, fmt, S, lds, static_cast<hipStream_t>(stream));
 }
 

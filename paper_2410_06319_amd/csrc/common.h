@@ -46,23 +46,9 @@ __device__ __forceinline__ void ls_philox4x32_10(uint32_t& c0, uint32_t& c1, uin
   }
 }
 
-// Uniform in (0, 1) from the top 23 bits of a word: (2 (w >> 9) + 1) 2^-24,
-// exact in binary32.
-__device__ __forceinline__ float ls_u01f(uint32_t w) {
-  return (float)((w >> 9) * 2u + 1u) * 5.9604644775390625e-8f;
-}
+// Uniform in (0, 1) from the top 23 bits of a word: (2 (w >> 9) + 1) 2^-24.
 __device__ __forceinline__ double ls_u01d(uint32_t w) {
   return (double)((w >> 9) * 2u + 1u) * 5.9604644775390625e-8;
-}
-
-// Box-Muller in binary32 with the hardware transcendental units:
-// v_log_f32 is log2, v_sin/v_cos take the angle in revolutions.
-__device__ __forceinline__ void ls_box_muller_f32(uint32_t w0, uint32_t w1, float& z0, float& z1) {
-  const float u0 = ls_u01f(w0);
-  const float u1 = ls_u01f(w1);
-  const float rad = __builtin_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u0));
-  z0 = rad * __builtin_amdgcn_cosf(u1);
-  z1 = rad * __builtin_amdgcn_sinf(u1);
 }
 
 // Box-Muller in binary64 (library log/sqrt/sincospi).

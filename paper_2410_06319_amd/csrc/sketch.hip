@@ -1,8 +1,12 @@
 // Algorithm 1, the sketch: the Gaussian sketch Y = Omega [A b] on gfx950.
 //
 // Omega = S / sqrt(s) is never stored: S entries are regenerated from
-// Philox4x32-10 (counter (i/4, k, prob, 0), key = seed) where they are
-// multiplied.  [A b] is first packed into a zero-padded operand of the sketch
+// Philox4x32-10 (key = seed) where they are multiplied.  Narrow formats: the
+// entry of S row k and column i is the 16-bit uniform U in half i % 2 of word
+// (i % 8) / 2 of the block with counter (i / 8, k, prob, 2), mapped to the
+// format's rounding of Phi^-1((U + 1/2) / 2^16) by a 2^15-entry table held in
+// LDS (one Philox block serves eight entries).  Binary64: Box-Muller on the
+// words of the block (i / 4, k, prob, 0).  [A b] is first packed into a zero-padded operand of the sketch
 // format (Algorithm 1 takes A in the sketch's precision); it may be split into
 // up to five parts of that format whose sum reproduces the data more closely.
 // Products run on MFMA with binary32 (narrow formats) or binary64 (f64 path)
@@ -20,6 +24,7 @@
 // 16 lanes of each MFMA operand read hit distinct banks.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "common.h"
 #include "kernels.h"
@@ -60,21 +65,12 @@ __global__ __launch_bounds__(256) void k_colexp(const TA* __restrict__ A, int64_
   }
 }
 
-// Binary32 Gaussians rounded to nearest even in the sketch format by the
-// hardware conversions, packed in K order (the first value in the lowest bits).
+// Two binary32 values rounded to nearest even in bf16 by the hardware
+// conversion, packed (the first value in the lowest bits).
 typedef __bf16 ls_bf16x2v __attribute__((ext_vector_type(2)));
 typedef float ls_f32x2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t sk_pack2_bf16(float a, float b) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector((ls_f32x2v){a, b}, ls_bf16x2v));
-}
-__device__ __forceinline__ uint32_t sk_pack2_f16(float a, float b) {
-  return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)a) |
-         ((uint32_t)__builtin_bit_cast(uint16_t, (_Float16)b) << 16);
-}
-__device__ __forceinline__ uint32_t sk_pack4_e4m3(float a, float b, float c, float d) {
-  int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
-  w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
-  return (uint32_t)w;
 }
 // Values of packed elements (exact in binary64).
 __device__ __forceinline__ double sk_bf16_at(uint32_t w, int i) {
@@ -93,9 +89,66 @@ __device__ __forceinline__ double sk_e4m3_at(uint32_t w, int i) {
   return (b & 0x80u) ? -v : v;
 }
 
+// ------------------------------------------------------------------ quantile tables
+// Narrow-format entries of S: for v = 0 .. 2^15 - 1, the format's bits of
+// a_v = -Phi^-1((v + 1/2) / 2^16) > 0 (round to nearest even); U < 2^15 maps
+// to -a_U, U >= 2^15 to a_{2^16 - 1 - U}.  One table per format in device
+// memory, filled once per device by k_icdf_init.
+constexpr int kIcdfHalf = 32768;
+static __device__ __align__(256) uint16_t g_icdf_bf16[kIcdfHalf];
+static __device__ __align__(256) uint16_t g_icdf_f16[kIcdfHalf];
+static __device__ __align__(256) uint8_t g_icdf_e4m3[kIcdfHalf];
+
+// a_v by bisection on 0.5 erfc(a / sqrt 2) = p (its left side decreases in a)
+// to about 1e-7, then Newton steps, which converge quadratically from there.
+__global__ __launch_bounds__(256) void k_icdf_init(uint16_t* __restrict__ tb, uint16_t* __restrict__ th,
+                                                   uint8_t* __restrict__ te) {
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  if (v >= kIcdfHalf) return;
+  const double p = ((double)v + 0.5) * (1.0 / 65536.0);
+  const double r2 = 0.70710678118654752440;   // 1 / sqrt(2)
+  double lo = 0.0, hi = 9.0;
+  for (int it = 0; it < 27; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (0.5 * erfc(mid * r2) > p) lo = mid;
+    else hi = mid;
+  }
+  double a = 0.5 * (lo + hi);
+  for (int it = 0; it < 5; ++it) {
+    const double f = 0.5 * erfc(a * r2) - p;
+    const double dens = 0.39894228040143267794 * exp(-0.5 * a * a);   // the normal density at a
+    a += f / dens;
+  }
+  tb[v] = ls_f32_to_bf16_bits((float)ls_round_fmt(a, ls_fmt_bf16()));
+  th[v] = ls_f16_bits(ls_round_fmt(a, ls_fmt_f16()));
+  te[v] = ls_e4m3_bits(ls_round_fmt(a, ls_fmt_e4m3()));
+}
+
+// Format bits of entry U (16-bit uniform) from the table of magnitudes.
+__device__ __forceinline__ uint32_t sk_icdf16(const uint16_t* tab, uint32_t U) {
+  const uint32_t neg = (U >> 15) ^ 1u;                 // U < 2^15: negative
+  const uint32_t v = (U ^ (0xffffu * (1u - neg))) & 0x7fffu;
+  return (uint32_t)tab[v] | (neg << 15);
+}
+__device__ __forceinline__ uint32_t sk_icdf8(const uint8_t* tab, uint32_t U) {
+  const uint32_t neg = (U >> 15) ^ 1u;
+  const uint32_t v = (U ^ (0xffffu * (1u - neg))) & 0x7fffu;
+  return (uint32_t)tab[v] | (neg << 7);
+}
+
 // Formats of the narrow sketch: element bits, S rounding, MFMA.  An operand
 // fragment is the 8 consecutive K elements one lane supplies to a
 // 16x16x32 MFMA (16 bytes for 16-bit formats, 8 for e4m3).
+// Eight 16-bit entries (K order: low half of word 0 first) from four words.
+__device__ __forceinline__ ls_u32x4 sk_words16(const uint16_t* tab, uint32_t w0, uint32_t w1, uint32_t w2,
+                                               uint32_t w3) {
+  const uint32_t w[4] = {w0, w1, w2, w3};
+  ls_u32x4 f;
+#pragma unroll
+  for (int h = 0; h < 4; ++h) f[h] = sk_icdf16(tab, w[h] & 0xffffu) | (sk_icdf16(tab, w[h] >> 16) << 16);
+  return f;
+}
+
 template <int FMT>
 struct SkFmt;
 template <>
@@ -103,9 +156,8 @@ struct SkFmt<LS_BF16> {
   using E = uint16_t;
   using frag = ls_u32x4;
   static constexpr LsFmt fmt() { return ls_fmt_bf16(); }
-  static __device__ __forceinline__ frag pack8(const float (&z)[8]) {
-    return frag{sk_pack2_bf16(z[0], z[1]), sk_pack2_bf16(z[2], z[3]), sk_pack2_bf16(z[4], z[5]),
-                sk_pack2_bf16(z[6], z[7])};
+  static __device__ __forceinline__ frag from_words(const E* tab, uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3) {
+    return sk_words16(tab, w0, w1, w2, w3);
   }
   static __device__ __forceinline__ E from_exact(double v) { return ls_f32_to_bf16_bits((float)v); }
   static __device__ __forceinline__ ls_floatx4 mma(frag a, frag b, ls_floatx4 c) {
@@ -118,8 +170,8 @@ struct SkFmt<LS_FP16> {
   using E = uint16_t;
   using frag = ls_u32x4;
   static constexpr LsFmt fmt() { return ls_fmt_f16(); }
-  static __device__ __forceinline__ frag pack8(const float (&z)[8]) {
-    return frag{sk_pack2_f16(z[0], z[1]), sk_pack2_f16(z[2], z[3]), sk_pack2_f16(z[4], z[5]), sk_pack2_f16(z[6], z[7])};
+  static __device__ __forceinline__ frag from_words(const E* tab, uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3) {
+    return sk_words16(tab, w0, w1, w2, w3);
   }
   static __device__ __forceinline__ E from_exact(double v) { return ls_f16_bits(v); }
   static __device__ __forceinline__ ls_floatx4 mma(frag a, frag b, ls_floatx4 c) {
@@ -132,8 +184,16 @@ struct SkFmt<LS_FP8E4M3> {
   using E = uint8_t;
   using frag = ls_u32x2;
   static constexpr LsFmt fmt() { return ls_fmt_e4m3(); }
-  static __device__ __forceinline__ frag pack8(const float (&z)[8]) {
-    return frag{sk_pack4_e4m3(z[0], z[1], z[2], z[3]), sk_pack4_e4m3(z[4], z[5], z[6], z[7])};
+  static __device__ __forceinline__ frag from_words(const E* tab, uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3) {
+    const uint32_t w[4] = {w0, w1, w2, w3};
+    frag f;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {   // entries 4h .. 4h+3 from words 2h, 2h+1
+      const uint32_t a = w[2 * h], b = w[2 * h + 1];
+      f[h] = sk_icdf8(tab, a & 0xffffu) | (sk_icdf8(tab, a >> 16) << 8) | (sk_icdf8(tab, b & 0xffffu) << 16) |
+             (sk_icdf8(tab, b >> 16) << 24);
+    }
+    return f;
   }
   static __device__ __forceinline__ E from_exact(double v) { return ls_e4m3_bits(v); }
   static __device__ __forceinline__ ls_floatx4 mma(frag a, frag b, ls_floatx4 c) {
@@ -259,6 +319,7 @@ template <int FMT, int BN, int TERMS>
 __global__ __launch_bounds__(kSkThreads) void k_sketch_lp(const typename SkFmt<FMT>::E* __restrict__ Tt, int64_t nkb,
                                                           int64_t n_pad, int64_t kb_per_split, int ns, int nn,
                                                           uint32_t key0, uint32_t key1, uint32_t prob,
+                                                          const typename SkFmt<FMT>::E* __restrict__ icdf,
                                                           float* __restrict__ Yp, int64_t s_pad) {
   using F = SkFmt<FMT>;
   using frag = typename F::frag;
@@ -275,7 +336,14 @@ __global__ __launch_bounds__(kSkThreads) void k_sketch_lp(const typename SkFmt<F
   constexpr int BPT = (BQ + kSkThreads - 1) / kSkThreads;
   __shared__ frag As[kSkRows * 4];
   __shared__ frag Bs[TERMS * BN * 4];
+  __shared__ __align__(16) typename F::E tab[kIcdfHalf];
   const int t = threadIdx.x;
+  {   // the quantile table, 16-byte pieces
+    const uint4* src = reinterpret_cast<const uint4*>(icdf);
+    uint4* dst = reinterpret_cast<uint4*>(tab);
+    constexpr int nq = (int)(kIcdfHalf * sizeof(typename F::E) / 16);
+    for (int i = t; i < nq; i += kSkThreads) dst[i] = src[i];
+  }
   const int lane = t & 63;
   const int wave = t >> 6;
   const int wr = wave % WRG, wc = wave / WRG;
@@ -291,22 +359,15 @@ __global__ __launch_bounds__(kSkThreads) void k_sketch_lp(const typename SkFmt<F
   const int64_t kb0 = (int64_t)z * kb_per_split;
   const int64_t kb1 = (kb0 + kb_per_split < nkb) ? kb0 + kb_per_split : nkb;
 
-  // S generation: thread t draws row t % 128, quarter t / 128 of the K-step
+  // S generation: thread t draws row t % 128, quarter t / 128 of the K-step:
+  // the eight entries of one Philox block (counter (i / 8, row, prob, 2))
   const int grow = t & (kSkRows - 1);
   const int gq = t >> 7;
   const uint32_t srow = (uint32_t)(row0 + grow);
   auto gen = [&](int64_t kb) -> frag {
-    const uint32_t q = (uint32_t)((kb * 32 + 8 * gq) >> 2);
-    uint32_t a0 = q, a1 = srow, a2 = prob, a3 = 0u;
-    uint32_t c0 = q + 1u, c1 = srow, c2 = prob, c3 = 0u;
+    uint32_t a0 = (uint32_t)(kb * 4 + gq), a1 = srow, a2 = prob, a3 = 2u;
     ls_philox4x32_10(a0, a1, a2, a3, key0, key1);
-    ls_philox4x32_10(c0, c1, c2, c3, key0, key1);
-    float zz[8];
-    ls_box_muller_f32(a0, a1, zz[0], zz[1]);
-    ls_box_muller_f32(a2, a3, zz[2], zz[3]);
-    ls_box_muller_f32(c0, c1, zz[4], zz[5]);
-    ls_box_muller_f32(c2, c3, zz[6], zz[7]);
-    return F::pack8(zz);
+    return F::from_words(tab, a0, a1, a2, a3);
   };
   // operand tile: fragment p = t + 512 u is (term, column, quarter) = (p / (4 BN), (p / 4) % BN, p % 4)
   const frag* Tf = reinterpret_cast<const frag*>(Tt);
@@ -343,6 +404,7 @@ __global__ __launch_bounds__(kSkThreads) void k_sketch_lp(const typename SkFmt<F
 
   frag sreg{};
   frag breg[BPT];
+  __syncthreads();   // the table is in LDS
   if (kb0 < kb1) {
     sreg = gen(kb0);
     loadb(kb0, breg);
@@ -460,39 +522,40 @@ __global__ __launch_bounds__(256) void k_sketch_combine(const TP* __restrict__ Y
 
 // ------------------------------------------------------------------ Omega itself
 // S[k + i lds] for k < s, i < m: one Philox block per thread (4 consecutive i).
+// The sketch's S (unscaled) as binary64 values, S[k + i lds]: Box-Muller
+// values for LS_FP64, the narrow formats' table entries otherwise.
 __global__ __launch_bounds__(256) void k_omega(uint32_t key0, uint32_t key1, uint32_t prob,
-                                               int64_t s, int64_t m, int fmt,
+                                               int64_t s, int64_t m, int fmt, const void* __restrict__ icdf,
                                                double* __restrict__ S, int64_t lds) {
-  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;   // quad index along m
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;   // index of 8 columns along m
   const int64_t k = blockIdx.y;
-  if (4 * q >= m || k >= s) return;
-  uint32_t c0 = (uint32_t)q, c1 = (uint32_t)k, c2 = prob, c3 = 0u;
-  ls_philox4x32_10(c0, c1, c2, c3, key0, key1);
-  double z[4];
+  if (8 * q >= m || k >= s) return;
+  double z[8];
   if (fmt == LS_FP64) {
-    ls_box_muller_f64(c0, c1, z[0], z[1]);
-    ls_box_muller_f64(c2, c3, z[2], z[3]);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      uint32_t c0 = (uint32_t)(2 * q + h), c1 = (uint32_t)k, c2 = prob, c3 = 0u;
+      ls_philox4x32_10(c0, c1, c2, c3, key0, key1);
+      ls_box_muller_f64(c0, c1, z[4 * h], z[4 * h + 1]);
+      ls_box_muller_f64(c2, c3, z[4 * h + 2], z[4 * h + 3]);
+    }
   } else {
-    float zf[4];
-    ls_box_muller_f32(c0, c1, zf[0], zf[1]);
-    ls_box_muller_f32(c2, c3, zf[2], zf[3]);
-    // the conversions the sketch kernel uses (LS_FP32: none, the binary32
-    // values themselves)
-    if (fmt == LS_FP32) {
-      for (int t = 0; t < 4; ++t) z[t] = (double)zf[t];
-    } else if (fmt == LS_FP8E4M3) {
-      const uint32_t w = sk_pack4_e4m3(zf[0], zf[1], zf[2], zf[3]);
-      for (int t = 0; t < 4; ++t) z[t] = sk_e4m3_at(w, t);
-    } else if (fmt == LS_FP16) {
-      const uint32_t w0 = sk_pack2_f16(zf[0], zf[1]), w1 = sk_pack2_f16(zf[2], zf[3]);
-      z[0] = sk_f16_at(w0, 0), z[1] = sk_f16_at(w0, 1), z[2] = sk_f16_at(w1, 0), z[3] = sk_f16_at(w1, 1);
-    } else {
-      const uint32_t w0 = sk_pack2_bf16(zf[0], zf[1]), w1 = sk_pack2_bf16(zf[2], zf[3]);
-      z[0] = sk_bf16_at(w0, 0), z[1] = sk_bf16_at(w0, 1), z[2] = sk_bf16_at(w1, 0), z[3] = sk_bf16_at(w1, 1);
+    uint32_t c0 = (uint32_t)q, c1 = (uint32_t)k, c2 = prob, c3 = 2u;
+    ls_philox4x32_10(c0, c1, c2, c3, key0, key1);
+    const uint32_t w[4] = {c0, c1, c2, c3};
+    for (int t = 0; t < 8; ++t) {
+      const uint32_t U = (w[t / 2] >> (16 * (t % 2))) & 0xffffu;
+      if (fmt == LS_FP8E4M3) {
+        z[t] = sk_e4m3_at(sk_icdf8(static_cast<const uint8_t*>(icdf), U), 0);
+      } else if (fmt == LS_FP16) {
+        z[t] = sk_f16_at(sk_icdf16(static_cast<const uint16_t*>(icdf), U), 0);
+      } else {
+        z[t] = sk_bf16_at(sk_icdf16(static_cast<const uint16_t*>(icdf), U), 0);
+      }
     }
   }
-  for (int t = 0; t < 4; ++t) {
-    const int64_t i = 4 * q + t;
+  for (int t = 0; t < 8; ++t) {
+    const int64_t i = 8 * q + t;
     if (i < m) S[k + i * lds] = z[t];
   }
 }
@@ -512,6 +575,39 @@ __global__ __launch_bounds__(256) void k_philox(uint32_t c0, uint32_t c1, uint32
 
 // ------------------------------------------------------------------ host side
 namespace ls {
+
+// Device address of the quantile table of a narrow format on the current
+// device, filled on first use: the filling kernel runs on a stream of its
+// own, which is synchronised before any sketch can read the table.
+int icdf_table(int fmt, const void** out) {
+  struct Tabs {
+    bool ready = false;
+    void* p[3] = {nullptr, nullptr, nullptr};
+  };
+  static std::mutex mu;
+  static Tabs tabs[64];
+  int dev = 0;
+  LS_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return LS_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(mu);
+  Tabs& t = tabs[dev];
+  if (!t.ready) {
+    LS_HIP_TRY(hipGetSymbolAddress(&t.p[0], HIP_SYMBOL(g_icdf_bf16)));
+    LS_HIP_TRY(hipGetSymbolAddress(&t.p[1], HIP_SYMBOL(g_icdf_f16)));
+    LS_HIP_TRY(hipGetSymbolAddress(&t.p[2], HIP_SYMBOL(g_icdf_e4m3)));
+    hipStream_t st;
+    LS_HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    hipLaunchKernelGGL(k_icdf_init, dim3(kIcdfHalf / 256), dim3(256), 0, st, (uint16_t*)t.p[0], (uint16_t*)t.p[1],
+                       (uint8_t*)t.p[2]);
+    const hipError_t e1 = hipGetLastError();
+    const hipError_t e2 = hipStreamSynchronize(st);
+    const hipError_t e3 = hipStreamDestroy(st);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return LS_E_HIP;
+    t.ready = true;
+  }
+  *out = (fmt == LS_BF16) ? t.p[0] : (fmt == LS_FP16) ? t.p[1] : t.p[2];
+  return LS_OK;
+}
 
 static bool sk_narrow(ls_prec_t u) { return u == LS_BF16 || u == LS_FP16 || u == LS_FP8E4M3; }
 
@@ -566,9 +662,9 @@ static int sketch_tuned_plan(ls_prec_t u_s, int terms, int64_t ncols, int64_t m)
 }
 
 // LDS of one block of k_sketch_lp: the 128 x 32 S tile and the parts' BN x 32
-// operand tile, in fragments of 8 elements.
+// operand tile, in fragments of 8 elements, and the quantile table.
 static constexpr size_t sk_lds_bytes(int ebytes, int terms, int bn) {
-  return (size_t)(kSkRows * 4 + terms * bn * 4) * (size_t)(8 * ebytes);
+  return (size_t)(kSkRows * 4 + terms * bn * 4) * (size_t)(8 * ebytes) + (size_t)kIcdfHalf * ebytes;
 }
 
 // Largest K-split, in 32-row K-blocks, for a terms-part sketch in u_s.
@@ -667,6 +763,7 @@ struct SkLaunchT {
   int64_t nkb, n_pad, kb_per_split;
   int ns, nn;
   uint32_t key0, key1, prob;
+  const E* icdf;
   float* Yp;
   int64_t s_pad;
 };
@@ -677,7 +774,8 @@ template <int FMT, int BN, int TERMS>
 int sk_launch(const SkLaunchT<typename SkFmt<FMT>::E>& L) {
   if constexpr (sk_lds_bytes(sizeof(typename SkFmt<FMT>::E), TERMS, BN) <= 160 * 1024) {
     hipExtLaunchKernelGGL((k_sketch_lp<FMT, BN, TERMS>), L.grid, dim3(kSkThreads), 0, L.st, L.ev.a, L.ev.b, 0, L.Tt,
-                          L.nkb, L.n_pad, L.kb_per_split, L.ns, L.nn, L.key0, L.key1, L.prob, L.Yp, L.s_pad);
+                          L.nkb, L.n_pad, L.kb_per_split, L.ns, L.nn, L.key0, L.key1, L.prob, L.icdf, L.Yp,
+                          L.s_pad);
     return LS_OK;
   } else {
     return LS_E_UNSUPPORTED;
@@ -707,8 +805,9 @@ int sketch_narrow(const ls_problem_t* P, const ls_sketch_opts_t* so, const Sketc
   E* Tt = reinterpret_cast<E*>(ws);
   float* Yp = reinterpret_cast<float*>(ws + p.operand_bytes);
   int32_t* e = colscale ? reinterpret_cast<int32_t*>(ws + p.operand_bytes + p.partial_bytes) : nullptr;
-  const size_t lds = (size_t)(kSkRows * 4 + p.terms * p.bn * 4) * sizeof(typename F::frag);
-  if (lds > (size_t)device_lds_bytes()) return LS_E_UNSUPPORTED;
+  if (sk_lds_bytes(sizeof(E), p.terms, p.bn) > (size_t)device_lds_bytes()) return LS_E_UNSUPPORTED;
+  const E* icdf = nullptr;
+  LS_TRY(icdf_table(FMT, reinterpret_cast<const void**>(&icdf)));
   const TA* A = static_cast<const TA*>(P->A);
   const TA* b = static_cast<const TA*>(P->b);
   if (e)
@@ -719,7 +818,7 @@ int sketch_narrow(const ls_problem_t* P, const ls_sketch_opts_t* so, const Sketc
   const dim3 gb((unsigned)(p.ns * p.nn * p.nsplit));
   const ProfEv ev = prof_events(kProfSketch);
   const SkLaunch L{gb, st, ev, Tt, p.nkb, p.n_pad, p.kb_per_split, (int)p.ns, (int)p.nn, key0, key1, so->prob_id,
-                  Yp, p.s_pad};
+                  icdf, Yp, p.s_pad};
   int rc = LS_E_UNSUPPORTED;
   if (p.bn == 128) rc = sk_launch_terms<FMT, 128>(L, p.terms);
   else if (p.bn == 256) rc = sk_launch_terms<FMT, 256>(L, p.terms);
@@ -794,9 +893,11 @@ int sketch_run(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s,
 
 int omega_run(uint64_t seed, uint32_t prob, int64_t s, int64_t m, ls_prec_t fmt, double* S, int64_t lds,
               hipStream_t st) {
-  const dim3 g((unsigned)ls_cdiv(ls_cdiv(m, 4), 256), (unsigned)s);
+  const void* icdf = nullptr;
+  if (fmt != LS_FP64) LS_TRY(icdf_table((int)fmt, &icdf));
+  const dim3 g((unsigned)ls_cdiv(ls_cdiv(m, 8), 256), (unsigned)s);
   hipLaunchKernelGGL(k_omega, g, dim3(256), 0, st, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32),
-                     prob, s, m, (int)fmt, S, lds);
+                     prob, s, m, (int)fmt, icdf, S, lds);
   LS_HIP_TRY(hipGetLastError());
   return LS_OK;
 }

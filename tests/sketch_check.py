@@ -2,9 +2,9 @@
 
 The tolerance of each sampled entry is TOL_FACTOR times the oracle's rounding
 scale for it (``oracle.sketch.error_scale``): binary32 accumulation over the
-library's K-split (its length from ``ls_sketch_split_rows``), the e4m3 MFMA's
-dot-product window, and one format ulp for each S entry that a binary32
-Box-Muller evaluation may round the other way.  The scale is a root-sum-square
+library's K-split (its length from ``ls_sketch_split_rows``) and the e4m3
+MFMA's dot-product window (S's entries are the same on both sides).  The
+scale is a root-sum-square
 of per-step rounding bounds; a factor of 3 covers the tails of the largest of
 many entries (the largest measured ratio of error to scale is about 2.7).
 """
