@@ -47,8 +47,19 @@ __global__ __launch_bounds__(256) void k_colexp(const TA* __restrict__ A, int64_
   __shared__ double red[4];
   const int64_t j = blockIdx.x;
   const TA* col = (j < n) ? A + j * lda : b;
-  double mx = 0.0;
-  for (int64_t i = threadIdx.x; i < m; i += 256) mx = fmax(mx, fabs((double)col[i]));
+  // the largest magnitude (exact in TA), eight loads per thread in flight
+  TA mt = 0;
+  for (int64_t i0 = threadIdx.x; i0 < m; i0 += 256 * 8) {
+    TA v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t i = i0 + 256 * u;
+      v[u] = (i < m) ? col[i] : TA(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) mt = fmax(mt, fabs(v[u]));
+  }
+  double mx = (double)mt;
   for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
   __syncthreads();
@@ -263,6 +274,45 @@ __global__ __launch_bounds__(256) void k_pack_lp(const TA* __restrict__ A, int64
           xa[2 * p2 + 1] -= __uint_as_float(w[p2] & 0xffff0000u);
         }
         *reinterpret_cast<ls_u32x4*>(Tt + t * nkb * n_pad * 32 + pos) = w;
+      }
+      return;
+    }
+  }
+  if constexpr (sizeof(TA) == 4 && (FMT == LS_FP8E4M3 || FMT == LS_FP16)) {
+    if (e) {
+      // binary32 data scaled by 2^e_j (exact: the scaled column lies within
+      // the format's range): each part is the hardware's round-to-nearest-even
+      // of what is left, and what is left stays exact in binary32
+      const int ej = (j <= n) ? e[j] : 0;
+      float xs[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) xs[r] = ldexpf(xa[r], ej);
+#pragma unroll 1
+      for (int t = 0; t < terms; ++t) {
+        if constexpr (FMT == LS_FP8E4M3) {
+          ls_u32x2 w;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            int wd = __builtin_amdgcn_cvt_pk_fp8_f32(xs[4 * h], xs[4 * h + 1], 0, false);
+            wd = __builtin_amdgcn_cvt_pk_fp8_f32(xs[4 * h + 2], xs[4 * h + 3], wd, true);
+            w[h] = (uint32_t)wd;
+            xs[4 * h] -= __builtin_amdgcn_cvt_f32_fp8(wd, 0);
+            xs[4 * h + 1] -= __builtin_amdgcn_cvt_f32_fp8(wd, 1);
+            xs[4 * h + 2] -= __builtin_amdgcn_cvt_f32_fp8(wd, 2);
+            xs[4 * h + 3] -= __builtin_amdgcn_cvt_f32_fp8(wd, 3);
+          }
+          *reinterpret_cast<ls_u32x2*>(Tt + t * nkb * n_pad * 32 + pos) = w;
+        } else {
+          ls_u32x4 w;
+#pragma unroll
+          for (int p2 = 0; p2 < 4; ++p2) {
+            const _Float16 h0 = (_Float16)xs[2 * p2], h1 = (_Float16)xs[2 * p2 + 1];
+            w[p2] = (uint32_t)__builtin_bit_cast(uint16_t, h0) | ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
+            xs[2 * p2] -= (float)h0;
+            xs[2 * p2 + 1] -= (float)h1;
+          }
+          *reinterpret_cast<ls_u32x4*>(Tt + t * nkb * n_pad * 32 + pos) = w;
+        }
       }
       return;
     }
