@@ -115,7 +115,7 @@ Inv inv_carve(char* ws, int64_t n) {
     off += ls_align256(b);
     return q;
   };
-  v.W = reinterpret_cast<double*>(take(8 * (size_t)n * n));
+  v.W = reinterpret_cast<double*>(take(16 * (size_t)n * n));   // R^-1, then its transpose
   v.W32 = reinterpret_cast<float*>(take(4 * (size_t)n * n));
   v.flag = reinterpret_cast<int*>(take(256));
   v.fro = reinterpret_cast<double*>(take(16 * (size_t)n));

@@ -562,14 +562,28 @@ __global__ __launch_bounds__(kThreads) void k_lsqr_col(int64_t n, const T* __res
 // of A^T u are summed (k_lsqr_colsum) and t = W^T (A^T u) is formed
 // (k_lsqr_wt), which the column kernel reads as a single partial per column.
 template <typename T>
-__global__ __launch_bounds__(kUtThreads) void k_lsqr_zx(const double* __restrict__ W, int64_t n,
-                                                        const T* __restrict__ v, const LsqrState* __restrict__ st,
-                                                        int par, int init, T* __restrict__ vz) {
+__global__ __launch_bounds__(1024) void k_lsqr_zx(const double* __restrict__ W, int64_t n, const T* __restrict__ v,
+                                                  const LsqrState* __restrict__ st, int par, int init,
+                                                  T* __restrict__ vz) {
   if (!init && st->rec[par].done) return;
-  __shared__ double red[32 * 33];
-  const double z = ls_utmv_row(W, n, n, [&](int64_t c) { return (double)v[c]; }, red);
-  const int64_t row = (int64_t)blockIdx.x * 32 + threadIdx.x;
-  if (threadIdx.x < 32 && row < n) vz[row] = (T)z;
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const double* wr = W + n * n + row * n;   // W[row, :] from W^T, which follows W
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t c0 = row + lane; c0 < n; c0 += 64 * 8) {
+    double wv[8], xv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t c = c0 + 64 * q;
+      wv[q] = (c < n) ? wr[c] : 0.0;
+      xv[q] = (c < n) ? (double)v[c] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q & 3] += wv[q] * xv[q];
+  }
+  const double z = ls_wave_sum((a[0] + a[1]) + (a[2] + a[3]));
+  if (lane == 0) vz[row] = (T)z;
 }
 
 // a[c] = sum over the pass's G blocks of the column partials (one wave per
@@ -1179,15 +1193,30 @@ __global__ __launch_bounds__(1024) void k_fg_col(int64_t m, int64_t n, const TB*
 }
 
 // A-path, before the pass of column j: xin = W V[m:, j] (the x part of v_j
-// before its normalisation, which the pass applies).
-__global__ __launch_bounds__(kUtThreads) void k_fg_zx(const double* __restrict__ W, int64_t n, FgPtrs F, int64_t m,
-                                                      int j, double* __restrict__ xin) {
+// before its normalisation, which the pass applies).  W^T follows W in memory:
+// row r of W is column r of W^T, contiguous; one wave per row, 16 per block.
+__global__ __launch_bounds__(1024) void k_fg_zx(const double* __restrict__ W, int64_t n, FgPtrs F, int64_t m, int j,
+                                                double* __restrict__ xin) {
   if (F.st->done) return;
-  __shared__ double red[32 * 33];
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const double* wr = W + n * n + row * n;   // W[row, :] = W^T[:, row]
   const double* vx = F.V + (int64_t)j * F.ldv + m;
-  const double z = ls_utmv_row(W, n, n, [&](int64_t c) { return vx[c]; }, red);
-  const int64_t row = (int64_t)blockIdx.x * 32 + threadIdx.x;
-  if (threadIdx.x < 32 && row < n) xin[row] = z;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t c0 = row + lane; c0 < n; c0 += 64 * 8) {   // eight loads per lane in flight
+    double wv[8], xv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t c = c0 + 64 * q;
+      wv[q] = (c < n) ? wr[c] : 0.0;
+      xv[q] = (c < n) ? vx[c] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q & 3] += wv[q] * xv[q];
+  }
+  const double z = ls_wave_sum((a[0] + a[1]) + (a[2] + a[3]));
+  if (lane == 0) xin[row] = z;
 }
 
 // A-path, after the pass: w_x = W^T t -> V[m:, j+1] (one wave per column,
@@ -2087,7 +2116,8 @@ int lsqr_typed(const ls_problem_t* P, const double* R, int64_t ldr, const double
   const T* vin = apply_w ? vz : v;
   auto pass = [&](int par, int init, const double* nvp) {
     if (apply_w)
-      hipLaunchKernelGGL(k_lsqr_zx<T>, gut, dim3(kUtThreads), 0, st, W, n, v, w.st, par, init, vz);
+      hipLaunchKernelGGL(k_lsqr_zx<T>, dim3((unsigned)ls_cdiv(n, 16)), dim3(1024), 0, st, W, n, v, w.st, par, init,
+                         vz);
     const ProfEv ev = prof_events(kProfLsqrPass);
 #define LS_LSQR_PAN(QQ)                                                                                              \
   lsqr_pan_launch<T, QQ>(G, st, ev, Bm, npan, m, n, vin, nvp, Gv, u, w.st, par, init, tpart, w.nupart, w.nbpart); \
@@ -2379,7 +2409,7 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
     for (; j < d.kmax; ++j) {
       const int Gw = (j == 0) ? d.Gr + d.Gh : d.Gs;
       if (AP)   // the x part of v_j times W, before the pass
-        hipLaunchKernelGGL(k_fg_zx, dim3((unsigned)ls_cdiv(n, 32)), dim3(kUtThreads), 0, st, W, n, F, m, j, w.xin);
+        hipLaunchKernelGGL(k_fg_zx, dim3((unsigned)ls_cdiv(n, 16)), dim3(1024), 0, st, W, n, F, m, j, w.xin);
       fg_pass(j, Gw, prof_events(kProfFgPass));
       // the panels once, v_j read and written, w written, v_x (or W v_x) read, t written
       prof_commit(kProfFgPass, (double)m * n * sizeof(TB) + 24.0 * m + 8.0 * n + (double)n * sizeof(TC));

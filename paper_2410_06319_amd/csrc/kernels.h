@@ -59,6 +59,7 @@ int qr_run(int64_t s, int64_t ncols, ls_prec_t u_qr, double* Y, int64_t ldy, dou
 int qr_flag_status(int flag);
 // W = R^-1 (n x n upper, binary64, ldw) and, if W32 != NULL, its binary32 copy (ld n).
 // With fro != NULL: fro[2j] = ||W[:, j]||^2, fro[2j+1] = ||R[:, j]||^2 (2n doubles).
+// W^T is written right after W (W + ldw n, ld n): W needs 2 ldw n entries.
 int trinv_run(const double* R, int64_t ldr, int64_t n, double* W, int64_t ldw, float* W32, int* d_flag,
               hipStream_t st, double* fro = nullptr);
 
@@ -76,6 +77,8 @@ struct FgState {
 int form_b(const ls_problem_t* P, const double* W, const float* W32, ls_prec_t tb, void* Bout, hipStream_t st);
 size_t b_bytes(const ls_problem_t* P, ls_prec_t tb);
 
+// W below is R^-1 (n x n binary64, ld n) followed by its transpose, as
+// trinv_run writes it.
 // LSQR on B = A R^-1 from x (in/out): R (ldr) maps x0 to z0 = R x0, W maps z back.
 // Bm is B in the panel layout, or with apply_w A's panels in precision u
 // (form_fg_operand's A-path copy), W then being applied around each pass.

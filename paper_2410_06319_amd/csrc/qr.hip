@@ -529,6 +529,23 @@ __global__ __launch_bounds__(256) void k_to_f32(const double* __restrict__ W, in
   if (i < n && j < n) W32[i + j * n] = (float)W[i + j * ldw];
 }
 
+// Wt = W^T (n x n, ld n), 32 x 32 tiles through LDS: coalesced reads and writes.
+__global__ __launch_bounds__(256) void k_transpose_f64(const double* __restrict__ W, int64_t ldw, int64_t n,
+                                                       double* __restrict__ Wt) {
+  __shared__ double tile[32][33];
+  const int64_t i0 = (int64_t)blockIdx.x * 32, j0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 8 rows of threads
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = i0 + tx, j = j0 + r;
+    tile[r][tx] = (i < n && j < n) ? W[i + j * ldw] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t j = j0 + tx, i = i0 + r;
+    if (i < n && j < n) Wt[j + i * n] = tile[tx][r];
+  }
+}
+
 template <typename T, int RPT, int NB>
 int qr_blocked(T* Y, int64_t ldy, int64_t s, int64_t ncols, char* ws, hipStream_t st) {
   T* tau = reinterpret_cast<T*>(ws);
@@ -616,6 +633,9 @@ int trinv_run(const double* R, int64_t ldr, int64_t n, double* W, int64_t ldw, f
                      d_flag, fro);
   if (W32)
     hipLaunchKernelGGL(k_to_f32, dim3((unsigned)ls_cdiv(n, 256), (unsigned)n), dim3(256), 0, st, W, ldw, n, W32);
+  // W^T right after W (ld n): row r of W is then contiguous
+  hipLaunchKernelGGL(k_transpose_f64, dim3((unsigned)ls_cdiv(n, 32), (unsigned)ls_cdiv(n, 32)), dim3(256), 0, st, W,
+                     ldw, n, W + ldw * n);
   LS_HIP_TRY(hipGetLastError());
   return LS_OK;
 }

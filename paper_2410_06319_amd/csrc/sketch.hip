@@ -240,8 +240,11 @@ __global__ __launch_bounds__(256) void k_pack_lp(const TA* __restrict__ A, int64
   using F = SkFmt<FMT>;
   using E = typename F::E;
   using V = typename SkPackVec<sizeof(E)>::type;
-  const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 8;
-  const int64_t j = blockIdx.y;
+  // block (kb, cb): K-block kb (32 rows) of 64 columns; thread t takes rows
+  // 8 (t % 4) .. +7 of column 64 cb + t / 4, so that a wave's stores of one
+  // part are one contiguous run (16 columns x 32 elements)
+  const int64_t i0 = (int64_t)blockIdx.x * 32 + 8 * (threadIdx.x & 3);
+  const int64_t j = (int64_t)blockIdx.y * 64 + (threadIdx.x >> 2);
   if (i0 >= m_pad || j >= n_pad) return;
   const TA* col = (j < n) ? A + j * lda : b;
   TA xa[8];
@@ -863,7 +866,7 @@ int sketch_narrow(const ls_problem_t* P, const ls_sketch_opts_t* so, const Sketc
   if (e)
     hipLaunchKernelGGL((k_colexp<TA>), dim3((unsigned)p.ncols), dim3(256), 0, st, A, P->lda, b, P->m, P->n,
                        F::fmt().fmax, e);
-  hipLaunchKernelGGL((k_pack_lp<TA, FMT>), dim3((unsigned)ls_cdiv(p.m_pad, 2048), (unsigned)p.n_pad), dim3(256), 0, st,
+  hipLaunchKernelGGL((k_pack_lp<TA, FMT>), dim3((unsigned)(p.m_pad / 32), (unsigned)ls_cdiv(p.n_pad, 64)), dim3(256), 0, st,
                      A, P->lda, b, P->m, P->n, p.terms, e, Tt, p.m_pad, p.n_pad);
   const dim3 gb((unsigned)(p.ns * p.nn * p.nsplit));
   const ProfEv ev = prof_events(kProfSketch);
