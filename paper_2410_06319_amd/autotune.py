@@ -11,7 +11,10 @@ A candidate replaces the default (plan 1) only when it is faster by more than
 ``--margin`` (default 5 %), so that timing noise does not move the table;
 candidates that give the same launch for a shape are timed once.
 
-    python -m paper_2410_06319_amd.autotune [--quick] [--out PATH]
+    python -m paper_2410_06319_amd.autotune [--quick] [--out PATH] [--formats e4m3,...]
+
+With ``--formats`` only those formats' shapes are timed; the table's rows for
+the other formats are kept as they are.
 """
 
 import argparse
@@ -111,12 +114,37 @@ def tune(ncols_grid, m_grid, cases, reps, margin, log):
     return entries
 
 
-def write_table(entries, path, device_name):
+def kept_rows(path, formats):
+    """Rows of an existing table whose format is not among `formats` (text lines, in order)."""
+    if not os.path.exists(path):
+        return []
+    codes = {FMT_CODE[f] for f in formats}
+    rows = []
+    with open(path) as fh:
+        for line in fh:
+            line = line.rstrip("\n")
+            if line.startswith("{"):
+                if int(line[1:].split(",")[0]) not in codes:
+                    rows.append(line)
+    return rows
+
+
+def write_table(entries, path, device_name, kept=()):
     lines = [f"// fmt, terms, ncols_max, m_max, plan: written by `python -m paper_2410_06319_amd.autotune`",
              f"// from ls_sketch timings on {device_name} (median of the repetitions; default",
              "// plan 1 unless another is faster by the margin).  Regenerate, then rebuild."]
+    new = {}
     for u_s, terms, nmax, mmax, best, t1, tb in entries:
-        lines.append(f"{{{FMT_CODE[u_s]}, {terms}, {nmax}, {mmax}, {best}}},   // {t1:.3f} -> {tb:.3f} ms")
+        new.setdefault(FMT_CODE[u_s], []).append(
+            f"{{{FMT_CODE[u_s]}, {terms}, {nmax}, {mmax}, {best}}},   // {t1:.3f} -> {tb:.3f} ms")
+    # kept rows and new rows grouped by format, in the order of CASES
+    by_code = {}
+    for line in kept:
+        by_code.setdefault(int(line[1:].split(",")[0]), []).append(line)
+    for code, rows in new.items():
+        by_code[code] = rows
+    for code in dict.fromkeys(FMT_CODE[u] for u, _ in CASES):
+        lines.extend(by_code.get(code, []))
     with open(path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
 
@@ -127,6 +155,7 @@ def main():
     ap.add_argument("--reps", type=int, default=7)
     ap.add_argument("--margin", type=float, default=0.05)
     ap.add_argument("--quick", action="store_true", help="a small grid (checks the tool, not a table to keep)")
+    ap.add_argument("--formats", default="", help="comma-separated formats to retune (default: all)")
     args = ap.parse_args()
     if not torch.cuda.is_available():
         raise SystemExit("the autotuner times kernels: it needs a visible GPU")
@@ -134,10 +163,19 @@ def main():
     ncols, mrows, cases = NCOLS, MROWS, CASES
     if args.quick:
         ncols, mrows, cases = [33, 257], [5000, 30000], [("bf16", 2), ("f64", 1)]
+    formats = [f for f in args.formats.split(",") if f]
+    for f in formats:
+        if f not in FMT_CODE:
+            raise SystemExit(f"unknown format {f!r} (one of {', '.join(FMT_CODE)})")
+    kept = []
+    if formats:
+        cases = [c for c in cases if c[0] in formats]
+        kept = kept_rows(args.out, formats)
     t0 = time.time()
     entries = tune(ncols, mrows, cases, args.reps, args.margin, lambda s: print(s, flush=True))
     arch = getattr(torch.cuda.get_device_properties(0), "gcnArchName", "").split(":")[0]
-    write_table(entries, args.out, f"{torch.cuda.get_device_name(0)} ({arch})" if arch else torch.cuda.get_device_name(0))
+    write_table(entries, args.out, f"{torch.cuda.get_device_name(0)} ({arch})" if arch else torch.cuda.get_device_name(0),
+                kept)
     print(f"[autotune] {len(entries)} shapes in {time.time() - t0:.1f} s -> {args.out}", flush=True)
 
 

@@ -13,7 +13,7 @@
 // accumulation over a chunk of rows of A; the chunk partial sums are added in
 // binary64.
 //
-// bf16 path: a block of 8 waves owns 128 rows of S and BN columns of [A b].
+// bf16 and fp16 path: a block of 8 waves owns 128 rows of S and BN columns of [A b].
 // Every K-step of 32 rows, the block generates its 128 x 32 tile of S once
 // (each Gaussian is drawn once per column tile) and stages the TERMS x BN x 32
 // operand tile, both in LDS.  With BN = 512 each wave multiplies all 128 rows
@@ -22,6 +22,10 @@
 // columns wc BN/4 .. +BN/4.  LDS rows of 32 bf16 (four 16-byte quarters) are
 // stored with the quarter index XORed with bits 2..3 of the row, so that the
 // 16 lanes of each MFMA operand read hit distinct banks.
+//
+// e4m3 path: the same block shape on the 16x16x128 f8f6f4 MFMA with 128-row
+// K-steps (k_sketch_x128), which doubles the product rate of the fp8 form of
+// the 16x16x32 instruction.
 #include <algorithm>
 #include <cmath>
 #include <mutex>
@@ -148,8 +152,9 @@ __device__ __forceinline__ uint32_t sk_icdf8(const uint8_t* tab, uint32_t U) {
 }
 
 // Formats of the narrow sketch: element bits, S rounding, MFMA.  An operand
-// fragment is the 8 consecutive K elements one lane supplies to a
-// 16x16x32 MFMA (16 bytes for 16-bit formats, 8 for e4m3).
+// fragment is 8 consecutive K elements: what one lane supplies to a 16x16x32
+// MFMA in the 16-bit formats (16 bytes); in e4m3 (8 bytes) four of them make
+// a lane's operand of the 16x16x128 f8f6f4 MFMA.
 // Eight 16-bit entries (K order: low half of word 0 first) from four words.
 __device__ __forceinline__ ls_u32x4 sk_words16(const uint16_t* tab, uint32_t w0, uint32_t w1, uint32_t w2,
                                                uint32_t w3) {
@@ -207,10 +212,6 @@ struct SkFmt<LS_FP8E4M3> {
     return f;
   }
   static __device__ __forceinline__ E from_exact(double v) { return ls_e4m3_bits(v); }
-  static __device__ __forceinline__ ls_floatx4 mma(frag a, frag b, ls_floatx4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(__builtin_bit_cast(long, a), __builtin_bit_cast(long, b), c, 0,
-                                                      0, 0);
-  }
 };
 
 // K-panel layout of the narrow operand: for term t and K-block kb (rows
@@ -352,11 +353,10 @@ __global__ __launch_bounds__(256) void k_pack_f64(const TA* __restrict__ A, int6
 }
 
 // ------------------------------------------------------------------ narrow MFMA sketch
-// v_mfma_f32_16x16x32_{bf16,f16,fp8_fp8} operands: lane l supplies row (l % 16)
+// v_mfma_f32_16x16x32_{bf16,f16} operands: lane l supplies row (l % 16)
 // of S and column (l % 16) of the packed operand, at the 8 consecutive K
 // indices 8 (l / 16) .. +7 of the step (one fragment); the product sums over
 // the same K set on both sides.  Result: lane l holds D[4 (l/16) + r][l % 16].
-// (On gfx950 the fp8 product reads OCP e4m3, the format the oracle rounds to.)
 constexpr int kSkThreads = 512;
 constexpr int kSkRows = 128;   // rows of S per block
 
@@ -499,6 +499,165 @@ __global__ __launch_bounds__(kSkThreads) void k_sketch_lp(const typename SkFmt<F
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
       const int64_t c = col0 + wc * (16 * CT) + ct * 16 + (lane & 15);
+      *reinterpret_cast<ls_floatx4*>(out + r + c * s_pad) = acc[rt][ct];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ e4m3 sketch, 16x16x128 MFMA
+// The e4m3 parts on v_mfma_scale_f32_16x16x128_f8f6f4 (unit scales): each
+// instruction takes 32 bytes of K per lane, twice the throughput of the
+// 16x16x32 fp8 form with the same dot-product rounding.  A lane of K-group
+// g = lane / 16 supplies one whole 32-row K-block (block 4 ks + g of the
+// 128-row step ks) of its row of S or column of the operand: the operand's
+// K-panel layout already holds those 32 bytes contiguously, and S's 32
+// entries of the block are four Philox blocks (counters 4 kblock + i).  The
+// same K order on both sides gives the same dot products.  (Format code 0
+// of the f8f6f4 form reads OCP e4m3, the format the oracle rounds to.)
+//
+// LDS: S tile [4 groups][128 rows][32 bytes], operand tile [parts][4 groups]
+// [BN columns][32 bytes], 16-byte halves swapped in rows / columns 8..15 of
+// each 16 (a 16-lane read then covers every bank once), and the quantile
+// table.  Waves: two groups of 64 rows x four groups of BN / 4 columns, S's
+// fragments held over the column tiles.
+constexpr size_t sk_x128_lds_bytes(int terms, int bn) {
+  return (size_t)(kSkRows * 128) + (size_t)terms * bn * 128 + (size_t)kIcdfHalf;
+}
+
+__device__ __forceinline__ int sk_x128_half(int rc, int h) { return h ^ ((rc >> 3) & 1); }
+
+template <int BN, int TERMS>
+__global__ __launch_bounds__(kSkThreads) void k_sketch_x128(const uint8_t* __restrict__ Tt, int64_t nkb,
+                                                            int64_t n_pad, int64_t kb_per_split, int ns, int nn,
+                                                            uint32_t key0, uint32_t key1, uint32_t prob,
+                                                            const uint8_t* __restrict__ icdf,
+                                                            float* __restrict__ Yp, int64_t s_pad) {
+  using F = SkFmt<LS_FP8E4M3>;
+  typedef int v8i __attribute__((ext_vector_type(8)));
+  constexpr int RT = 4;                    // 16-row tiles per wave (64 rows)
+  constexpr int CT = BN / 64;              // 16-column tiles per wave (BN / 4 columns)
+  constexpr int BQ = TERMS * 4 * BN * 2;   // 16-byte pieces of the operand tile
+  constexpr int BPT = (BQ + kSkThreads - 1) / kSkThreads;
+  __shared__ ls_u32x4 As[4 * kSkRows * 2];
+  __shared__ ls_u32x4 Bs[BQ];
+  __shared__ __align__(16) uint8_t tab[kIcdfHalf];
+  const int t = threadIdx.x;
+  {
+    const ls_u32x4* src = reinterpret_cast<const ls_u32x4*>(icdf);
+    ls_u32x4* dst = reinterpret_cast<ls_u32x4*>(tab);
+    for (int i = t; i < kIcdfHalf / 16; i += kSkThreads) dst[i] = src[i];
+  }
+  const int lane = t & 63;
+  const int wave = t >> 6;
+  const int wr = wave & 1, wc = wave >> 1;
+  // blocks of one (K-split, column tile) group run on one XCD (block b -> XCD b % 8)
+  const int b = blockIdx.x;
+  const int rest = b >> 3;
+  const int grp = (rest / ns) * 8 + (b & 7);
+  const int st = rest % ns;
+  const int z = grp / nn;
+  const int ntile = grp % nn;
+  const int64_t row0 = (int64_t)st * kSkRows;
+  const int64_t col0 = (int64_t)ntile * BN;
+  // 128-row steps [ks0, ks1) of this K-split (kb_per_split and nkb are multiples of 4)
+  const int64_t ks0 = (int64_t)z * (kb_per_split / 4);
+  const int64_t ks1 = ks0 + kb_per_split / 4 < nkb / 4 ? ks0 + kb_per_split / 4 : nkb / 4;
+
+  // S: thread t draws row t % 128 of K-block 4 ks + t / 128 (four Philox blocks)
+  const int grow = t & (kSkRows - 1);
+  const int gg = t >> 7;
+  const uint32_t srow = (uint32_t)(row0 + grow);
+  auto gen = [&](int64_t ks, ls_u32x4 (&out)[2]) {
+    ls_u32x2 f[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      uint32_t a0 = (uint32_t)(ks * 16 + gg * 4 + i), a1 = srow, a2 = prob, a3 = 2u;
+      ls_philox4x32_10(a0, a1, a2, a3, key0, key1);
+      f[i] = F::from_words(tab, a0, a1, a2, a3);
+    }
+    out[0] = ls_u32x4{f[0][0], f[0][1], f[1][0], f[1][1]};
+    out[1] = ls_u32x4{f[2][0], f[2][1], f[3][0], f[3][1]};
+  };
+  // operand piece p = t + 512 u: (part, group, column, half) = (p / 8BN, (p / 2BN) % 4, (p / 2) % BN, p % 2)
+  const ls_u32x4* T16 = reinterpret_cast<const ls_u32x4*>(Tt);
+  const int64_t term_stride = nkb * n_pad * 2;   // pieces
+  auto loadb = [&](int64_t ks, ls_u32x4 (&reg)[BPT]) {
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+      const int p = t + kSkThreads * u;
+      if (p < BQ) {
+        const int term = p / (8 * BN);
+        const int g = (p / (2 * BN)) & 3;
+        const int c = (p >> 1) % BN;
+        reg[u] = T16[term * term_stride + ((ks * 4 + g) * n_pad + col0 + c) * 2 + (p & 1)];
+      }
+    }
+  };
+  auto storeb = [&](const ls_u32x4 (&reg)[BPT]) {
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+      const int p = t + kSkThreads * u;
+      if (p < BQ) {
+        const int c = (p >> 1) % BN;
+        Bs[(p & ~(2 * BN - 1)) + c * 2 + sk_x128_half(c, p & 1)] = reg[u];
+      }
+    }
+  };
+  auto frag_at = [&](const ls_u32x4* base, int rc) -> v8i {
+    const ls_u32x4 lo = base[rc * 2 + sk_x128_half(rc, 0)];
+    const ls_u32x4 hi = base[rc * 2 + sk_x128_half(rc, 1)];
+    return v8i{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+  };
+
+  ls_floatx4 acc[RT][CT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = ls_floatx4{0.f, 0.f, 0.f, 0.f};
+
+  ls_u32x4 sreg[2] = {};
+  ls_u32x4 breg[BPT];
+  __syncthreads();   // the table is in LDS
+  if (ks0 < ks1) {
+    gen(ks0, sreg);
+    loadb(ks0, breg);
+  }
+  const int g = lane >> 4;   // K-group of this lane
+  for (int64_t ks = ks0; ks < ks1; ++ks) {
+    __syncthreads();   // the previous step's tiles have been read
+    As[(gg * kSkRows + grow) * 2 + sk_x128_half(grow, 0)] = sreg[0];
+    As[(gg * kSkRows + grow) * 2 + sk_x128_half(grow, 1)] = sreg[1];
+    storeb(breg);
+    __syncthreads();
+    {   // the next step's operand loads in flight and its S drawn during the products
+      const int64_t kn = (ks + 1 < ks1) ? ks + 1 : ks;
+      loadb(kn, breg);
+      gen(kn, sreg);
+    }
+    v8i af[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) af[rt] = frag_at(As + g * kSkRows * 2, wr * 64 + rt * 16 + (lane & 15));
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const int c = wc * (BN / 4) + ct * 16 + (lane & 15);
+      v8i bf[TERMS];
+#pragma unroll
+      for (int tm = 0; tm < TERMS; ++tm) bf[tm] = frag_at(Bs + (tm * 4 + g) * BN * 2, c);
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int tm = 0; tm < TERMS; ++tm)
+          acc[rt][ct] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(af[rt], bf[tm], acc[rt][ct], 0, 0, 0, 127,
+                                                                         0, 127);
+    }
+  }
+  float* out = Yp + (int64_t)z * s_pad * n_pad;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int64_t r = row0 + wr * 64 + rt * 16 + 4 * (lane >> 4);
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const int64_t c = col0 + wc * (BN / 4) + ct * 16 + (lane & 15);
       *reinterpret_cast<ls_floatx4*>(out + r + c * s_pad) = acc[rt][ct];
     }
   }
@@ -753,10 +912,12 @@ SketchPlan sketch_plan(const ls_problem_t* P, const ls_sketch_opts_t* so, int64_
     const int bn = kNarrowCands[plan - 1].bn;
     p.bn = bn ? bn : (p.ncols <= 128) ? 128 : (p.ncols <= 256) ? 256 : 512;
     // the automatic width stays at 256 columns where 512 would spill the
-    // accumulators' registers (three or more 16-bit parts, five e4m3 parts)
-    if (!bn && p.terms >= ((p.ebytes == 2) ? 3 : 5) && p.bn > 256) p.bn = 256;
+    // accumulators' registers (three or more 16-bit parts)
+    if (!bn && p.ebytes == 2 && p.terms >= 3 && p.bn > 256) p.bn = 256;
     // the block's S tile and its parts' operand tile must fit in LDS
-    while (p.bn > 128 && sk_lds_bytes(p.ebytes, p.terms, p.bn) > (size_t)device_lds_bytes()) p.bn /= 2;
+    const bool x128 = (u_s == LS_FP8E4M3);
+    auto lds = [&](int w) { return x128 ? sk_x128_lds_bytes(p.terms, w) : sk_lds_bytes(p.ebytes, p.terms, w); };
+    while (p.bn > 128 && lds(p.bn) > (size_t)device_lds_bytes()) p.bn /= 2;
     p.nn = ls_cdiv(p.ncols, p.bn);
     p.n_pad = p.nn * p.bn;
     p.ns = ls_cdiv(s, kSkRows);
@@ -776,6 +937,7 @@ SketchPlan sketch_plan(const ls_problem_t* P, const ls_sketch_opts_t* so, int64_
     if (nsplit < 1) nsplit = 1;
     while ((p.nn * nsplit) % 8) ++nsplit;
     p.kb_per_split = ls_cdiv(kbn, nsplit);
+    if (x128) p.kb_per_split = ls_cdiv(p.kb_per_split, 4) * 4;   // whole 128-row steps
     p.nsplit = nsplit;
     p.nkb = p.kb_per_split * nsplit;
     p.m_pad = p.nkb * 32;
@@ -835,15 +997,38 @@ int sk_launch(const SkLaunchT<typename SkFmt<FMT>::E>& L) {
   }
 }
 
+// Launch k_sketch_x128<BN, TERMS> (e4m3); shapes beyond the LDS are not instantiated.
+template <int BN, int TERMS>
+int sk_x128_launch(const SkLaunchT<uint8_t>& L) {
+  if constexpr (sk_x128_lds_bytes(TERMS, BN) <= 160 * 1024) {
+    hipExtLaunchKernelGGL((k_sketch_x128<BN, TERMS>), L.grid, dim3(kSkThreads), 0, L.st, L.ev.a, L.ev.b, 0, L.Tt, L.nkb,
+                          L.n_pad, L.kb_per_split, L.ns, L.nn, L.key0, L.key1, L.prob, L.icdf, L.Yp, L.s_pad);
+    return LS_OK;
+  } else {
+    return LS_E_UNSUPPORTED;
+  }
+}
+
 template <int FMT, int BN>
 int sk_launch_terms(const SkLaunchT<typename SkFmt<FMT>::E>& L, int terms) {
-  switch (terms) {
-    case 1: return sk_launch<FMT, BN, 1>(L);
-    case 2: return sk_launch<FMT, BN, 2>(L);
-    case 3: return sk_launch<FMT, BN, 3>(L);
-    case 4: return sk_launch<FMT, BN, 4>(L);
-    case 5: return sk_launch<FMT, BN, 5>(L);
-    default: return LS_E_ARG;
+  if constexpr (FMT == LS_FP8E4M3) {
+    switch (terms) {
+      case 1: return sk_x128_launch<BN, 1>(L);
+      case 2: return sk_x128_launch<BN, 2>(L);
+      case 3: return sk_x128_launch<BN, 3>(L);
+      case 4: return sk_x128_launch<BN, 4>(L);
+      case 5: return sk_x128_launch<BN, 5>(L);
+      default: return LS_E_ARG;
+    }
+  } else {
+    switch (terms) {
+      case 1: return sk_launch<FMT, BN, 1>(L);
+      case 2: return sk_launch<FMT, BN, 2>(L);
+      case 3: return sk_launch<FMT, BN, 3>(L);
+      case 4: return sk_launch<FMT, BN, 4>(L);
+      case 5: return sk_launch<FMT, BN, 5>(L);
+      default: return LS_E_ARG;
+    }
   }
 }
 
@@ -858,7 +1043,8 @@ int sketch_narrow(const ls_problem_t* P, const ls_sketch_opts_t* so, const Sketc
   E* Tt = reinterpret_cast<E*>(ws);
   float* Yp = reinterpret_cast<float*>(ws + p.operand_bytes);
   int32_t* e = colscale ? reinterpret_cast<int32_t*>(ws + p.operand_bytes + p.partial_bytes) : nullptr;
-  if (sk_lds_bytes(sizeof(E), p.terms, p.bn) > (size_t)device_lds_bytes()) return LS_E_UNSUPPORTED;
+  const size_t lds = (FMT == LS_FP8E4M3) ? sk_x128_lds_bytes(p.terms, (int)p.bn) : sk_lds_bytes(sizeof(E), p.terms, p.bn);
+  if (lds > (size_t)device_lds_bytes()) return LS_E_UNSUPPORTED;
   const E* icdf = nullptr;
   LS_TRY(icdf_table(FMT, reinterpret_cast<const void**>(&icdf)));
   const TA* A = static_cast<const TA*>(P->A);
