@@ -151,17 +151,27 @@ __device__ __forceinline__ uint32_t sk_icdf8(const uint8_t* tab, uint32_t U) {
   return (uint32_t)tab[v] | (neg << 7);
 }
 
+// Table indices of the low and high 16-bit uniforms of a word: U below 2^15,
+// 2^16 - 1 - U from 2^15 on (the sign-extended top bit flips the rest).
+__device__ __forceinline__ uint32_t sk_ix_lo(uint32_t w) { return (w ^ (uint32_t)((int32_t)(w << 16) >> 31)) & 0x7fffu; }
+__device__ __forceinline__ uint32_t sk_ix_hi(uint32_t w) { return ((w >> 16) ^ (uint32_t)((int32_t)w >> 31)) & 0x7fffu; }
+
 // Formats of the narrow sketch: element bits, S rounding, MFMA.  An operand
 // fragment is 8 consecutive K elements: what one lane supplies to a 16x16x32
 // MFMA in the 16-bit formats (16 bytes); in e4m3 (8 bytes) four of them make
 // a lane's operand of the 16x16x128 f8f6f4 MFMA.
-// Eight 16-bit entries (K order: low half of word 0 first) from four words.
+// Eight 16-bit entries (K order: low half of word 0 first) from four words:
+// the magnitudes of a word's two entries side by side, and the sign bits
+// (set where the uniform is below 2^15) from the complemented top bits.
 __device__ __forceinline__ ls_u32x4 sk_words16(const uint16_t* tab, uint32_t w0, uint32_t w1, uint32_t w2,
                                                uint32_t w3) {
   const uint32_t w[4] = {w0, w1, w2, w3};
   ls_u32x4 f;
 #pragma unroll
-  for (int h = 0; h < 4; ++h) f[h] = sk_icdf16(tab, w[h] & 0xffffu) | (sk_icdf16(tab, w[h] >> 16) << 16);
+  for (int h = 0; h < 4; ++h) {
+    const uint32_t mag = __builtin_amdgcn_perm((uint32_t)tab[sk_ix_hi(w[h])], (uint32_t)tab[sk_ix_lo(w[h])], 0x05040100u);
+    f[h] = mag | (~w[h] & 0x80008000u);
+  }
   return f;
 }
 
@@ -206,8 +216,11 @@ struct SkFmt<LS_FP8E4M3> {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {   // entries 4h .. 4h+3 from words 2h, 2h+1
       const uint32_t a = w[2 * h], b = w[2 * h + 1];
-      f[h] = sk_icdf8(tab, a & 0xffffu) | (sk_icdf8(tab, a >> 16) << 8) | (sk_icdf8(tab, b & 0xffffu) << 16) |
-             (sk_icdf8(tab, b >> 16) << 24);
+      const uint32_t lo = __builtin_amdgcn_perm((uint32_t)tab[sk_ix_hi(a)], (uint32_t)tab[sk_ix_lo(a)], 0x0c0c0400u);
+      const uint32_t hi = __builtin_amdgcn_perm((uint32_t)tab[sk_ix_hi(b)], (uint32_t)tab[sk_ix_lo(b)], 0x0c0c0400u);
+      // sign bits: bytes 1 and 3 of a and b hold the uniforms' top bits at bit 7
+      const uint32_t top = __builtin_amdgcn_perm(b, a, 0x07050301u);
+      f[h] = (lo | (hi << 16)) | (~top & 0x80808080u);
     }
     return f;
   }
