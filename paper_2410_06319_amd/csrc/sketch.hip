@@ -400,9 +400,13 @@ __global__ __launch_bounds__(kSkThreads) void k_sketch_lp(const typename SkFmt<F
   constexpr int HALF = (CT * TERMS <= 8) ? CT : (TERMS >= 3 && CT >= 4) ? CT / 4 : (CT >= 2) ? CT / 2 : 1;
   constexpr int BQ = TERMS * BN * 4;           // fragments of the operand tile
   constexpr int BPT = (BQ + kSkThreads - 1) / kSkThreads;
-  __shared__ frag As[kSkRows * 4];
-  __shared__ frag Bs[TERMS * BN * 4];
-  __shared__ __align__(16) typename F::E tab[kIcdfHalf];
+  // one LDS block, the table at its start: an entry's LDS address is then
+  // its index times the entry's size
+  using E = typename F::E;
+  __shared__ __align__(16) uint8_t lds[kIcdfHalf * sizeof(E) + (kSkRows * 4 + TERMS * BN * 4) * sizeof(frag)];
+  E* const tab = reinterpret_cast<E*>(lds);
+  frag* const As = reinterpret_cast<frag*>(lds + kIcdfHalf * sizeof(E));
+  frag* const Bs = As + kSkRows * 4;
   const int t = threadIdx.x;
   {   // the quantile table, 16-byte pieces
     const uint4* src = reinterpret_cast<const uint4*>(icdf);
@@ -551,9 +555,11 @@ __global__ __launch_bounds__(kSkThreads) void k_sketch_x128(const uint8_t* __res
   constexpr int CT = BN / 64;              // 16-column tiles per wave (BN / 4 columns)
   constexpr int BQ = TERMS * 4 * BN * 2;   // 16-byte pieces of the operand tile
   constexpr int BPT = (BQ + kSkThreads - 1) / kSkThreads;
-  __shared__ ls_u32x4 As[4 * kSkRows * 2];
-  __shared__ ls_u32x4 Bs[BQ];
-  __shared__ __align__(16) uint8_t tab[kIcdfHalf];
+  // one LDS block, the table at its start: an entry's LDS address is then its index
+  __shared__ __align__(16) uint8_t lds[kIcdfHalf + (4 * kSkRows * 2 + BQ) * 16];
+  uint8_t* const tab = lds;
+  ls_u32x4* const As = reinterpret_cast<ls_u32x4*>(lds + kIcdfHalf);
+  ls_u32x4* const Bs = As + 4 * kSkRows * 2;
   const int t = threadIdx.x;
   {
     const ls_u32x4* src = reinterpret_cast<const ls_u32x4*>(icdf);
