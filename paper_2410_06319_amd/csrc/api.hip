@@ -238,6 +238,39 @@ int clamp_workers(int nworkers, int nprob) {
   return k < 1 ? 1 : k;
 }
 
+int solve_impl(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t* pr, const ls_iter_opts_t* io_in,
+               double* x, double* r, ls_stats_t* stats, void* ws, size_t ws_bytes, void* stream, const double* Y0);
+
+// A batch whose sketches are all Gaussian in a narrow format computes them up
+// front in grouped launches (one per tile width and part count); its
+// workspace then also holds the work list, every problem's sketch Y and its
+// sketch workspace after the workers' slices.
+bool batch_grouped(int nprob, const ls_sketch_opts_t* so, ls_prec_t u_s) {
+  for (int i = 0; i < nprob; ++i)
+    if (!sketch_groupable(&so[i], u_s)) return false;
+  return true;
+}
+struct BatchSketch {
+  size_t items = 0;                 // offset of the work list from the region's start
+  std::vector<size_t> y, w;         // offsets of Y_i and of sketch workspace i
+  size_t bytes = 0;
+};
+BatchSketch batch_sketch_layout(int nprob, const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s) {
+  BatchSketch b;
+  b.y.resize((size_t)nprob);
+  b.w.resize((size_t)nprob);
+  size_t off = sketch_grouped_items_bytes(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    const int64_t s = sketch_rows(&P[i], &so[i]);
+    b.y[i] = off;
+    off += ls_align256(8 * (size_t)s * (size_t)(P[i].n + 1));
+    b.w[i] = off;
+    off += ls_align256(sketch_grouped_bytes(&P[i], &so[i], u_s, s));
+  }
+  b.bytes = off;
+  return b;
+}
+
 // Largest single-problem workspace of the batch.
 int batch_slice_bytes(int nprob, const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t* pr,
                       const ls_iter_opts_t* io, size_t* out) {
@@ -476,6 +509,16 @@ int ls_lsir_gmres(const ls_problem_t* P, const double* R, int64_t ldr, const ls_
 
 int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t* pr, const ls_iter_opts_t* io_in,
              double* x, double* r, ls_stats_t* stats, void* ws, size_t ws_bytes, void* stream) {
+  return solve_impl(P, so, pr, io_in, x, r, stats, ws, ws_bytes, stream, nullptr);
+}
+
+}  // extern "C"
+
+namespace {
+// ls_solve, with the first sketch Y0 (s x (n+1), leading dimension s) given
+// when the batch has computed it in a grouped launch (null: sketched here).
+int solve_impl(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t* pr, const ls_iter_opts_t* io_in,
+               double* x, double* r, ls_stats_t* stats, void* ws, size_t ws_bytes, void* stream, const double* Y0) {
   LS_TRY(check_problem(P));
   LS_TRY(check_precs(pr));
   LS_TRY(check_sketch(P, so, pr->u_s));
@@ -524,15 +567,19 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
   std::vector<char> rb((size_t)(reinterpret_cast<char*>(inv.fro) - reinterpret_cast<char*>(inv.flag)) +
                        16 * (size_t)n);
   double ms_sk = 0.0, ms_qr = 0.0;
+  bool first = true;
   for (;;) {
     tm.mark(0, st);
-    // Algorithm 1: the sketch
+    // Algorithm 1: the sketch (the first one given by a grouped batch launch)
     const SketchPlan sp = sketch_plan(P, &so_t, s, pr->u_s);
-    LS_TRY(sketch_run(P, &so_t, pr->u_s, sp, s, Y, s, scratch, st));
+    const double* Yc = Y;
+    if (first && Y0) Yc = Y0;
+    else LS_TRY(sketch_run(P, &so_t, pr->u_s, sp, s, Y, s, scratch, st));
+    first = false;
     tm.mark(1, st);
     // Algorithm 1: the QR, then x^s = R^-1 (Q^T Omega b)
     LS_HIP_TRY(hipMemsetAsync(inv.flag, 0, sizeof(int), st));
-    LS_TRY(qr_run(s, n + 1, pr->u_qr, Y, s, Raug, n + 1, scratch, scratch_bytes, inv.flag, n, st));
+    LS_TRY(qr_run(s, n + 1, pr->u_qr, Yc, s, Raug, n + 1, scratch, scratch_bytes, inv.flag, n, st));
     LS_TRY(trinv_run(Raug, n + 1, n, inv.W, n, inv.W32, inv.flag, st, inv.fro));
     hipLaunchKernelGGL(k_trmv_f64, dim3((unsigned)ls_cdiv(n, 32)), dim3(kUtThreads), 0, st, inv.W, n,
                        Raug + n * (n + 1), x);
@@ -614,6 +661,9 @@ int ls_solve(const ls_problem_t* P, const ls_sketch_opts_t* so, const ls_precs_t
   S->status = rc;
   return rc;
 }
+}  // namespace
+
+extern "C" {
 
 int ls_omega(uint64_t seed, uint32_t prob_id, int64_t s, int64_t m, ls_prec_t fmt, double* S, int64_t lds,
              void* stream) {
@@ -635,6 +685,7 @@ int ls_workspace_size_batched(int nprob, const ls_problem_t* P, const ls_sketch_
   size_t slice = 0;
   LS_TRY(batch_slice_bytes(nprob, P, so, pr, io, &slice));
   *bytes = slice * (size_t)clamp_workers(nworkers, nprob);
+  if (batch_grouped(nprob, so, pr->u_s)) *bytes += batch_sketch_layout(nprob, P, so, pr->u_s).bytes;
   return LS_OK;
 }
 
@@ -658,7 +709,10 @@ int ls_solve_batched(int nprob, const ls_problem_t* P, const ls_sketch_opts_t* s
   const int K = clamp_workers(nworkers, nprob);
   size_t slice = 0;
   LS_TRY(batch_slice_bytes(nprob, P, so, pr, io_in ? &io : nullptr, &slice));
-  if (ws_bytes < slice * (size_t)K) return LS_E_WORKSPACE;
+  const bool grouped = batch_grouped(nprob, so, pr->u_s);
+  BatchSketch bs;
+  if (grouped) bs = batch_sketch_layout(nprob, P, so, pr->u_s);
+  if (ws_bytes < slice * (size_t)K + bs.bytes) return LS_E_WORKSPACE;
   int dev = 0;
   LS_HIP_TRY(hipGetDevice(&dev));
   hipStream_t caller = static_cast<hipStream_t>(stream);
@@ -678,11 +732,33 @@ int ls_solve_batched(int nprob, const ls_problem_t* P, const ls_sketch_opts_t* s
     load[k] += work(i);
   }
 
-  // the workers start after the caller's earlier work and the caller's stream
+  // the workers start after the caller's earlier work (and the grouped
+  // sketches, queued on the first worker's stream) and the caller's stream
   // continues after all of them
   hipEvent_t start;
   LS_HIP_TRY(hipEventCreateWithFlags(&start, hipEventDisableTiming));
   LS_HIP_TRY(hipEventRecord(start, caller));
+  std::vector<const double*> Y0((size_t)nprob, nullptr);
+  if (grouped) {
+    char* region = static_cast<char*>(ws) + slice * (size_t)K;
+    std::vector<double*> Yg((size_t)nprob);
+    std::vector<char*> Wg((size_t)nprob);
+    std::vector<int64_t> sg((size_t)nprob);
+    for (int i = 0; i < nprob; ++i) {
+      Yg[i] = reinterpret_cast<double*>(region + bs.y[i]);
+      Wg[i] = region + bs.w[i];
+      sg[i] = sketch_rows(&P[i], &so[i]);
+      Y0[i] = Yg[i];
+    }
+    int rc_sk = (hipStreamWaitEvent(wst[0], start, 0) == hipSuccess) ? LS_OK : LS_E_HIP;
+    if (rc_sk == LS_OK)
+      rc_sk = sketch_grouped(nprob, P, so, pr->u_s, sg.data(), Yg.data(), Wg.data(), region + bs.items, wst[0]);
+    if (rc_sk == LS_OK && hipEventRecord(start, wst[0]) != hipSuccess) rc_sk = LS_E_HIP;
+    if (rc_sk != LS_OK) {
+      (void)hipEventDestroy(start);
+      return rc_sk;
+    }
+  }
   std::vector<int> status(nprob, LS_OK);
   std::vector<ls_stats_t> local(stats ? 0 : nprob);
   std::atomic<int> hip_err{0};
@@ -697,7 +773,8 @@ int ls_solve_batched(int nprob, const ls_problem_t* P, const ls_sketch_opts_t* s
       char* slice_ws = static_cast<char*>(ws) + slice * (size_t)k;
       for (int i : lists[k]) {
         ls_stats_t* S = stats ? &stats[i] : &local[i];
-        status[i] = ls_solve(&P[i], &so[i], pr, io_in ? &io : nullptr, x[i], r[i], S, slice_ws, slice, wst[k]);
+        status[i] = solve_impl(&P[i], &so[i], pr, io_in ? &io : nullptr, x[i], r[i], S, slice_ws, slice, wst[k],
+                               Y0[i]);
       }
     });
   }

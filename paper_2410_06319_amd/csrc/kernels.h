@@ -45,6 +45,17 @@ int sparse_run(const ls_problem_t* P, const ls_sketch_opts_t* so, int64_t s, dou
 bool sketch_colscale(ls_prec_t u_s, int32_t col_scale);
 int sketch_run(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s, const SketchPlan& p,
                int64_t s, double* Y, int64_t ldy, char* ws, hipStream_t st);
+// Grouped Gaussian sketches of a batch (narrow formats): problem i's Y[i]
+// (s[i] x (n_i + 1), leading dimension s[i]) from its own sketch workspace
+// ws[i] (sketch_grouped_bytes), one launch per tile width and part count over
+// the problems' blocks, each result the one sketch_run gives; items_dev holds
+// the work list (sketch_grouped_items_bytes).  Synchronises st once, before
+// queueing the launches.
+bool sketch_groupable(const ls_sketch_opts_t* so, ls_prec_t u_s);
+size_t sketch_grouped_bytes(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s, int64_t s);
+size_t sketch_grouped_items_bytes(int nprob);
+int sketch_grouped(int nprob, const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s, const int64_t* s,
+                   double* const* Y, char* const* ws, void* items_dev, hipStream_t st);
 int omega_run(uint64_t seed, uint32_t prob, int64_t s, int64_t m, ls_prec_t fmt, double* S, int64_t lds,
               hipStream_t st);
 int philox_run(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1, int64_t count,
@@ -53,7 +64,7 @@ int philox_run(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, 
 // ------------------------------------------------------------------ QR and R^-1
 size_t qr_workspace(int64_t s, int64_t ncols, ls_prec_t u_qr);
 // check_cols: leading diagonal entries of R tested for zero / non-finite values.
-int qr_run(int64_t s, int64_t ncols, ls_prec_t u_qr, double* Y, int64_t ldy, double* R, int64_t ldr,
+int qr_run(int64_t s, int64_t ncols, ls_prec_t u_qr, const double* Y, int64_t ldy, double* R, int64_t ldr,
            char* ws, size_t ws_bytes, int* d_flag, int64_t check_cols, hipStream_t st);
 // LS_OK, LS_E_SINGULAR or LS_E_NONFINITE from the flag word of qr_run / trinv_run.
 int qr_flag_status(int flag);

@@ -601,7 +601,7 @@ size_t qr_workspace(int64_t s, int64_t ncols, ls_prec_t u_qr) {
   return b;
 }
 
-int qr_run(int64_t s, int64_t ncols, ls_prec_t u_qr, double* Y, int64_t ldy, double* R, int64_t ldr, char* ws,
+int qr_run(int64_t s, int64_t ncols, ls_prec_t u_qr, const double* Y, int64_t ldy, double* R, int64_t ldr, char* ws,
            size_t ws_bytes, int* d_flag, int64_t check_cols, hipStream_t st) {
   if (ws_bytes < qr_workspace(s, ncols, u_qr)) return LS_E_WORKSPACE;
   if (s > 32 * (int64_t)kPanelThreads) return LS_E_UNSUPPORTED;

@@ -29,6 +29,8 @@
 #include <algorithm>
 #include <cmath>
 #include <mutex>
+#include <type_traits>
+#include <vector>
 
 #include "common.h"
 #include "kernels.h"
@@ -381,12 +383,12 @@ __device__ __forceinline__ int sk_slot(int r, int q) {
   return r * 4 + (q ^ ((r >> ((FB == 16) ? 2 : 3)) & 3));
 }
 
+// Block b of one problem's sketch (the kernels below give b).
 template <int FMT, int BN, int TERMS>
-__global__ __launch_bounds__(kSkThreads) void k_sketch_lp(const typename SkFmt<FMT>::E* __restrict__ Tt, int64_t nkb,
-                                                          int64_t n_pad, int64_t kb_per_split, int ns, int nn,
-                                                          uint32_t key0, uint32_t key1, uint32_t prob,
-                                                          const typename SkFmt<FMT>::E* __restrict__ icdf,
-                                                          float* __restrict__ Yp, int64_t s_pad) {
+__device__ __forceinline__ void sk_lp_body(const typename SkFmt<FMT>::E* __restrict__ Tt, int64_t nkb, int64_t n_pad,
+                                           int64_t kb_per_split, int ns, int nn, uint32_t key0, uint32_t key1,
+                                           uint32_t prob, const typename SkFmt<FMT>::E* __restrict__ icdf,
+                                           float* __restrict__ Yp, int64_t s_pad, int b) {
   using F = SkFmt<FMT>;
   using frag = typename F::frag;
   constexpr int FB = sizeof(frag);
@@ -417,8 +419,8 @@ __global__ __launch_bounds__(kSkThreads) void k_sketch_lp(const typename SkFmt<F
   const int lane = t & 63;
   const int wave = t >> 6;
   const int wr = wave % WRG, wc = wave / WRG;
-  // blocks of one (K-split, column tile) group run on one XCD (block b -> XCD b % 8)
-  const int b = blockIdx.x;
+  // blocks of one (K-split, column tile) group run on one XCD (block b -> XCD
+  // b % 8; a grouped launch starts each problem at a multiple of 8)
   const int rest = b >> 3;
   const int grp = (rest / ns) * 8 + (b & 7);
   const int st = rest % ns;
@@ -544,11 +546,10 @@ constexpr size_t sk_x128_lds_bytes(int terms, int bn) {
 __device__ __forceinline__ int sk_x128_half(int rc, int h) { return h ^ ((rc >> 3) & 1); }
 
 template <int BN, int TERMS>
-__global__ __launch_bounds__(kSkThreads) void k_sketch_x128(const uint8_t* __restrict__ Tt, int64_t nkb,
-                                                            int64_t n_pad, int64_t kb_per_split, int ns, int nn,
-                                                            uint32_t key0, uint32_t key1, uint32_t prob,
-                                                            const uint8_t* __restrict__ icdf,
-                                                            float* __restrict__ Yp, int64_t s_pad) {
+__device__ __forceinline__ void sk_x128_body(const uint8_t* __restrict__ Tt, int64_t nkb, int64_t n_pad,
+                                             int64_t kb_per_split, int ns, int nn, uint32_t key0, uint32_t key1,
+                                             uint32_t prob, const uint8_t* __restrict__ icdf, float* __restrict__ Yp,
+                                             int64_t s_pad, int b) {
   using F = SkFmt<LS_FP8E4M3>;
   typedef int v8i __attribute__((ext_vector_type(8)));
   constexpr int RT = 4;                    // 16-row tiles per wave (64 rows)
@@ -570,7 +571,6 @@ __global__ __launch_bounds__(kSkThreads) void k_sketch_x128(const uint8_t* __res
   const int wave = t >> 6;
   const int wr = wave & 1, wc = wave >> 1;
   // blocks of one (K-split, column tile) group run on one XCD (block b -> XCD b % 8)
-  const int b = blockIdx.x;
   const int rest = b >> 3;
   const int grp = (rest / ns) * 8 + (b & 7);
   const int st = rest % ns;
@@ -680,6 +680,64 @@ __global__ __launch_bounds__(kSkThreads) void k_sketch_x128(const uint8_t* __res
       *reinterpret_cast<ls_floatx4*>(out + r + c * s_pad) = acc[rt][ct];
     }
   }
+}
+
+// One problem's sketch: block b = blockIdx.x.
+template <int FMT, int BN, int TERMS>
+__global__ __launch_bounds__(kSkThreads) void k_sketch_lp(const typename SkFmt<FMT>::E* __restrict__ Tt, int64_t nkb,
+                                                          int64_t n_pad, int64_t kb_per_split, int ns, int nn,
+                                                          uint32_t key0, uint32_t key1, uint32_t prob,
+                                                          const typename SkFmt<FMT>::E* __restrict__ icdf,
+                                                          float* __restrict__ Yp, int64_t s_pad) {
+  sk_lp_body<FMT, BN, TERMS>(Tt, nkb, n_pad, kb_per_split, ns, nn, key0, key1, prob, icdf, Yp, s_pad, (int)blockIdx.x);
+}
+template <int BN, int TERMS>
+__global__ __launch_bounds__(kSkThreads) void k_sketch_x128(const uint8_t* __restrict__ Tt, int64_t nkb,
+                                                            int64_t n_pad, int64_t kb_per_split, int ns, int nn,
+                                                            uint32_t key0, uint32_t key1, uint32_t prob,
+                                                            const uint8_t* __restrict__ icdf,
+                                                            float* __restrict__ Yp, int64_t s_pad) {
+  sk_x128_body<BN, TERMS>(Tt, nkb, n_pad, kb_per_split, ns, nn, key0, key1, prob, icdf, Yp, s_pad, (int)blockIdx.x);
+}
+
+// Grouped sketches: one launch over the blocks of several problems of the
+// same tile width and part count, problem i owning blocks [block0_i,
+// block0_{i+1}) (block0 a multiple of 8); each block runs the single-problem
+// code on its problem's arguments, so every result is the one the problem's
+// own launch gives.
+struct SkItem {
+  const void* Tt;
+  float* Yp;
+  int64_t nkb, n_pad, kb_per_split, s_pad;
+  int ns, nn;
+  uint32_t key0, key1, prob;
+  int block0;
+};
+
+__device__ __forceinline__ const SkItem& sk_item(const SkItem* __restrict__ items, int nitems, int b) {
+  int lo = 0, hi = nitems - 1;   // the last item with block0 <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].block0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return items[lo];
+}
+
+template <int FMT, int BN, int TERMS>
+__global__ __launch_bounds__(kSkThreads) void k_sketch_lp_grouped(const SkItem* __restrict__ items, int nitems,
+                                                                  const typename SkFmt<FMT>::E* __restrict__ icdf) {
+  using E = typename SkFmt<FMT>::E;
+  const SkItem& it = sk_item(items, nitems, (int)blockIdx.x);
+  sk_lp_body<FMT, BN, TERMS>(static_cast<const E*>(it.Tt), it.nkb, it.n_pad, it.kb_per_split, it.ns, it.nn, it.key0,
+                             it.key1, it.prob, icdf, it.Yp, it.s_pad, (int)blockIdx.x - it.block0);
+}
+template <int BN, int TERMS>
+__global__ __launch_bounds__(kSkThreads) void k_sketch_x128_grouped(const SkItem* __restrict__ items, int nitems,
+                                                                    const uint8_t* __restrict__ icdf) {
+  const SkItem& it = sk_item(items, nitems, (int)blockIdx.x);
+  sk_x128_body<BN, TERMS>(static_cast<const uint8_t*>(it.Tt), it.nkb, it.n_pad, it.kb_per_split, it.ns, it.nn,
+                          it.key0, it.key1, it.prob, icdf, it.Yp, it.s_pad, (int)blockIdx.x - it.block0);
 }
 
 // ------------------------------------------------------------------ f64 MFMA sketch
@@ -1051,6 +1109,53 @@ int sk_launch_terms(const SkLaunchT<typename SkFmt<FMT>::E>& L, int terms) {
   }
 }
 
+// The operand of a narrow sketch: column exponents (column scaling) and the
+// packed parts, in ws (operand, then partials, then exponents).
+template <int FMT, typename TA>
+void sk_prepare(const ls_problem_t* P, const SketchPlan& p, char* ws, bool colscale, hipStream_t st) {
+  using F = SkFmt<FMT>;
+  using E = typename F::E;
+  E* Tt = reinterpret_cast<E*>(ws);
+  int32_t* e = colscale ? reinterpret_cast<int32_t*>(ws + p.operand_bytes + p.partial_bytes) : nullptr;
+  const TA* A = static_cast<const TA*>(P->A);
+  const TA* b = static_cast<const TA*>(P->b);
+  if (e)
+    hipLaunchKernelGGL((k_colexp<TA>), dim3((unsigned)p.ncols), dim3(256), 0, st, A, P->lda, b, P->m, P->n,
+                       F::fmt().fmax, e);
+  hipLaunchKernelGGL((k_pack_lp<TA, FMT>), dim3((unsigned)(p.m_pad / 32), (unsigned)ls_cdiv(p.n_pad, 64)), dim3(256), 0, st,
+                     A, P->lda, b, P->m, P->n, p.terms, e, Tt, p.m_pad, p.n_pad);
+}
+
+template <int FMT>
+int sk_prepare_store(const ls_problem_t* P, const SketchPlan& p, char* ws, bool colscale, hipStream_t st) {
+  if (P->store == LS_FP32) sk_prepare<FMT, float>(P, p, ws, colscale, st);
+  else if (P->store == LS_FP64) sk_prepare<FMT, double>(P, p, ws, colscale, st);
+  else return LS_E_UNSUPPORTED;
+  return LS_OK;
+}
+
+// Y = the binary64 sum of the K-splits' partials, scaled by 1/sqrt(s) and
+// 2^-e_j; the column exponents to so->col_exp when asked.
+int sk_finish(const ls_problem_t* P, const ls_sketch_opts_t* so, const SketchPlan& p, int64_t s, double* Y,
+              int64_t ldy, char* ws, bool colscale, hipStream_t st) {
+  const float* Yp = reinterpret_cast<const float*>(ws + p.operand_bytes);
+  const int32_t* e = colscale ? reinterpret_cast<const int32_t*>(ws + p.operand_bytes + p.partial_bytes) : nullptr;
+  hipLaunchKernelGGL(k_sketch_combine<float>, dim3((unsigned)ls_cdiv(s, 256), (unsigned)p.ncols), dim3(256), 0, st, Yp,
+                     p.s_pad, p.n_pad, (int)p.nsplit, s, p.ncols, 1.0 / sqrt((double)s), e, Y, ldy);
+  LS_HIP_TRY(hipGetLastError());
+  if (so->col_exp) {
+    if (e)
+      LS_HIP_TRY(hipMemcpyAsync(so->col_exp, e, 4 * (size_t)p.ncols, hipMemcpyDeviceToDevice, st));
+    else
+      LS_HIP_TRY(hipMemsetAsync(so->col_exp, 0, 4 * (size_t)p.ncols, st));
+  }
+  return LS_OK;
+}
+
+size_t sk_block_lds(int fmt, int terms, int bn) {
+  return (fmt == LS_FP8E4M3) ? sk_x128_lds_bytes(terms, bn) : sk_lds_bytes(fmt == LS_BF16 || fmt == LS_FP16 ? 2 : 1, terms, bn);
+}
+
 template <int FMT, typename TA>
 int sketch_narrow(const ls_problem_t* P, const ls_sketch_opts_t* so, const SketchPlan& p, int64_t s, double* Y,
                   int64_t ldy, char* ws, bool colscale, hipStream_t st) {
@@ -1061,18 +1166,10 @@ int sketch_narrow(const ls_problem_t* P, const ls_sketch_opts_t* so, const Sketc
   const uint32_t key1 = (uint32_t)(so->seed >> 32);
   E* Tt = reinterpret_cast<E*>(ws);
   float* Yp = reinterpret_cast<float*>(ws + p.operand_bytes);
-  int32_t* e = colscale ? reinterpret_cast<int32_t*>(ws + p.operand_bytes + p.partial_bytes) : nullptr;
-  const size_t lds = (FMT == LS_FP8E4M3) ? sk_x128_lds_bytes(p.terms, (int)p.bn) : sk_lds_bytes(sizeof(E), p.terms, p.bn);
-  if (lds > (size_t)device_lds_bytes()) return LS_E_UNSUPPORTED;
+  if (sk_block_lds(FMT, p.terms, (int)p.bn) > (size_t)device_lds_bytes()) return LS_E_UNSUPPORTED;
   const E* icdf = nullptr;
   LS_TRY(icdf_table(FMT, reinterpret_cast<const void**>(&icdf)));
-  const TA* A = static_cast<const TA*>(P->A);
-  const TA* b = static_cast<const TA*>(P->b);
-  if (e)
-    hipLaunchKernelGGL((k_colexp<TA>), dim3((unsigned)p.ncols), dim3(256), 0, st, A, P->lda, b, P->m, P->n,
-                       F::fmt().fmax, e);
-  hipLaunchKernelGGL((k_pack_lp<TA, FMT>), dim3((unsigned)(p.m_pad / 32), (unsigned)ls_cdiv(p.n_pad, 64)), dim3(256), 0, st,
-                     A, P->lda, b, P->m, P->n, p.terms, e, Tt, p.m_pad, p.n_pad);
+  sk_prepare<FMT, TA>(P, p, ws, colscale, st);
   const dim3 gb((unsigned)(p.ns * p.nn * p.nsplit));
   const ProfEv ev = prof_events(kProfSketch);
   const SkLaunch L{gb, st, ev, Tt, p.nkb, p.n_pad, p.kb_per_split, (int)p.ns, (int)p.nn, key0, key1, so->prob_id,
@@ -1083,16 +1180,47 @@ int sketch_narrow(const ls_problem_t* P, const ls_sketch_opts_t* so, const Sketc
   else if (p.bn == 512) rc = sk_launch_terms<FMT, 512>(L, p.terms);
   LS_TRY(rc);
   prof_commit(kProfSketch, 2.0 * (double)s * (double)P->m * (double)(P->n + 1));
-  hipLaunchKernelGGL(k_sketch_combine<float>, dim3((unsigned)ls_cdiv(s, 256), (unsigned)p.ncols), dim3(256), 0, st, Yp,
-                     p.s_pad, p.n_pad, (int)p.nsplit, s, p.ncols, 1.0 / sqrt((double)s), (const int32_t*)e, Y, ldy);
-  LS_HIP_TRY(hipGetLastError());
-  if (so->col_exp) {
-    if (e)
-      LS_HIP_TRY(hipMemcpyAsync(so->col_exp, e, 4 * (size_t)p.ncols, hipMemcpyDeviceToDevice, st));
-    else
-      LS_HIP_TRY(hipMemsetAsync(so->col_exp, 0, 4 * (size_t)p.ncols, st));
+  return sk_finish(P, so, p, s, Y, ldy, ws, colscale, st);
+}
+
+// One grouped launch (problems of one tile width and part count).
+template <int FMT, int TERMS>
+int sk_grouped_launch_bn(int bn, unsigned blocks, hipStream_t st, const SkItem* items, int nitems, const void* icdf) {
+  using E = typename SkFmt<FMT>::E;
+  auto go = [&](auto bn_c) -> int {
+    constexpr int BN = decltype(bn_c)::value;
+    if constexpr (FMT == LS_FP8E4M3) {
+      if constexpr (sk_x128_lds_bytes(TERMS, BN) <= 160 * 1024) {
+        hipLaunchKernelGGL((k_sketch_x128_grouped<BN, TERMS>), dim3(blocks), dim3(kSkThreads), 0, st, items, nitems,
+                           static_cast<const uint8_t*>(icdf));
+        return LS_OK;
+      }
+    } else {
+      if constexpr (sk_lds_bytes(sizeof(E), TERMS, BN) <= 160 * 1024) {
+        hipLaunchKernelGGL((k_sketch_lp_grouped<FMT, BN, TERMS>), dim3(blocks), dim3(kSkThreads), 0, st, items,
+                           nitems, static_cast<const E*>(icdf));
+        return LS_OK;
+      }
+    }
+    return LS_E_UNSUPPORTED;
+  };
+  if (bn == 128) return go(std::integral_constant<int, 128>{});
+  if (bn == 256) return go(std::integral_constant<int, 256>{});
+  if (bn == 512) return go(std::integral_constant<int, 512>{});
+  return LS_E_UNSUPPORTED;
+}
+
+template <int FMT>
+int sk_grouped_launch(int bn, int terms, unsigned blocks, hipStream_t st, const SkItem* items, int nitems,
+                      const void* icdf) {
+  switch (terms) {
+    case 1: return sk_grouped_launch_bn<FMT, 1>(bn, blocks, st, items, nitems, icdf);
+    case 2: return sk_grouped_launch_bn<FMT, 2>(bn, blocks, st, items, nitems, icdf);
+    case 3: return sk_grouped_launch_bn<FMT, 3>(bn, blocks, st, items, nitems, icdf);
+    case 4: return sk_grouped_launch_bn<FMT, 4>(bn, blocks, st, items, nitems, icdf);
+    case 5: return sk_grouped_launch_bn<FMT, 5>(bn, blocks, st, items, nitems, icdf);
+    default: return LS_E_ARG;
   }
-  return LS_OK;
 }
 
 template <int FMT>
@@ -1146,6 +1274,84 @@ int sketch_run(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s,
                      (int)p.nsplit, s, p.ncols, scale, (const int32_t*)nullptr, Y, ldy);
   LS_HIP_TRY(hipGetLastError());
   if (so->col_exp) LS_HIP_TRY(hipMemsetAsync(so->col_exp, 0, 4 * (size_t)p.ncols, st));
+  return LS_OK;
+}
+
+bool sketch_groupable(const ls_sketch_opts_t* so, ls_prec_t u_s) {
+  return sk_narrow(u_s) && so->zeta == 0 && so->terms >= 1 && so->terms <= kMaxSketchTerms;
+}
+
+size_t sketch_grouped_bytes(const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s, int64_t s) {
+  const SketchPlan p = sketch_plan(P, so, s, u_s);
+  return p.operand_bytes + p.partial_bytes + p.exp_bytes;
+}
+
+size_t sketch_grouped_items_bytes(int nprob) { return ls_align256(sizeof(SkItem) * (size_t)nprob); }
+
+int sketch_grouped(int nprob, const ls_problem_t* P, const ls_sketch_opts_t* so, ls_prec_t u_s, const int64_t* s,
+                   double* const* Y, char* const* ws, void* items_dev, hipStream_t st) {
+  std::vector<SketchPlan> pl((size_t)nprob);
+  for (int i = 0; i < nprob; ++i) {
+    if (!sketch_groupable(&so[i], u_s)) return LS_E_UNSUPPORTED;
+    pl[i] = sketch_plan(&P[i], &so[i], s[i], u_s);
+    if (sk_block_lds(u_s, pl[i].terms, (int)pl[i].bn) > (size_t)device_lds_bytes()) return LS_E_UNSUPPORTED;
+  }
+  const void* icdf = nullptr;
+  LS_TRY(icdf_table(u_s, &icdf));
+  // groups of one tile width and part count; within a group each problem's
+  // blocks follow the previous problem's (its block count is a multiple of 8)
+  std::vector<int> order((size_t)nprob);
+  for (int i = 0; i < nprob; ++i) order[i] = i;
+  auto key = [&](int i) { return pl[i].bn * 16 + pl[i].terms; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
+  std::vector<SkItem> items((size_t)nprob);
+  struct Group {
+    int first, count, bn, terms;
+    int64_t blocks;
+  };
+  std::vector<Group> groups;
+  for (int k = 0; k < nprob; ++k) {
+    const int i = order[k];
+    const SketchPlan& p = pl[i];
+    if (groups.empty() || key(order[groups.back().first]) != key(i))
+      groups.push_back(Group{k, 0, (int)p.bn, p.terms, 0});
+    Group& g = groups.back();
+    SkItem& it = items[k];
+    it.Tt = ws[i];
+    it.Yp = reinterpret_cast<float*>(ws[i] + p.operand_bytes);
+    it.nkb = p.nkb;
+    it.n_pad = p.n_pad;
+    it.kb_per_split = p.kb_per_split;
+    it.s_pad = p.s_pad;
+    it.ns = (int)p.ns;
+    it.nn = (int)p.nn;
+    it.key0 = (uint32_t)(so[i].seed & 0xffffffffu);
+    it.key1 = (uint32_t)(so[i].seed >> 32);
+    it.prob = so[i].prob_id;
+    it.block0 = (int)g.blocks;
+    g.blocks += p.ns * p.nn * p.nsplit;
+    ++g.count;
+    if (g.blocks > INT32_MAX) return LS_E_UNSUPPORTED;
+  }
+  // the work list to the device (the host copy is released after the copy)
+  LS_HIP_TRY(hipMemcpyAsync(items_dev, items.data(), sizeof(SkItem) * items.size(), hipMemcpyHostToDevice, st));
+  LS_HIP_TRY(hipStreamSynchronize(st));
+  for (int i = 0; i < nprob; ++i) {
+    const bool cs = sketch_colscale(u_s, so[i].col_scale);
+    char* w = ws[i];
+    if (u_s == LS_BF16) LS_TRY(sk_prepare_store<LS_BF16>(&P[i], pl[i], w, cs, st));
+    else if (u_s == LS_FP16) LS_TRY(sk_prepare_store<LS_FP16>(&P[i], pl[i], w, cs, st));
+    else LS_TRY(sk_prepare_store<LS_FP8E4M3>(&P[i], pl[i], w, cs, st));
+  }
+  const SkItem* dev = static_cast<const SkItem*>(items_dev);
+  for (const Group& g : groups) {
+    const unsigned blocks = (unsigned)g.blocks;
+    if (u_s == LS_BF16) LS_TRY(sk_grouped_launch<LS_BF16>(g.bn, g.terms, blocks, st, dev + g.first, g.count, icdf));
+    else if (u_s == LS_FP16) LS_TRY(sk_grouped_launch<LS_FP16>(g.bn, g.terms, blocks, st, dev + g.first, g.count, icdf));
+    else LS_TRY(sk_grouped_launch<LS_FP8E4M3>(g.bn, g.terms, blocks, st, dev + g.first, g.count, icdf));
+  }
+  for (int i = 0; i < nprob; ++i)
+    LS_TRY(sk_finish(&P[i], &so[i], pl[i], s[i], Y[i], s[i], ws[i], sketch_colscale(u_s, so[i].col_scale), st));
   return LS_OK;
 }
 
