@@ -186,6 +186,13 @@ typedef struct {
    * somewhat less accurate, which cost a fourth refinement step more often than
    * 1 did.)  Unsupported combinations: LS_E_UNSUPPORTED. */
   int32_t lsqr_operand;
+  /* graph: nonzero: the refinement's FGMRES iterations are captured, in chunks
+   * of check_every iterations, into HIP graphs at the first refinement step of
+   * a call and replayed at the later ones (the host still polls between
+   * chunks and stops queueing once the device reports convergence); the
+   * results are bitwise those of the launches one by one.  Ignored while
+   * profile is set (per-kernel events are not captured).  0 (default): off. */
+  int32_t graph;
 } ls_iter_opts_t;
 
 /* Results and timings of one call. */

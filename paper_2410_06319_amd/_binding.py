@@ -36,7 +36,7 @@ class IterOpts(ctypes.Structure):
                 ("lsir_maxit", ctypes.c_int32), ("lsir_tol", ctypes.c_double),
                 ("fallback", ctypes.c_int32), ("check_every", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("inner_adapt", ctypes.c_int32), ("x_ref", ctypes.c_void_p), ("r_ref", ctypes.c_void_p),
-                ("lsqr_operand", ctypes.c_int32)]
+                ("lsqr_operand", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

@@ -251,6 +251,15 @@ __global__ __launch_bounds__(kThreads) void k_cast(const TI* __restrict__ a, TO*
   if (i < n) b[i] = sign * (TO)a[i];
 }
 
+// The start of an FGMRES cycle: a zeroed state holding the cycle's tolerance.
+__global__ void k_fg_begin(FgState* st, double tol) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    FgState S{};
+    S.tol = tol;
+    *st = S;
+  }
+}
+
 __global__ void k_zero_bytes(char* p, size_t nbytes) {
   for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nbytes; i += (size_t)gridDim.x * kThreads) p[i] = 0;
 }
@@ -1628,10 +1637,10 @@ __device__ bool dcgs_stage(const FgPtrs& F, double* __restrict__ Hraw, double* _
 // kmax - 1 final (one block).
 __global__ __launch_bounds__(kSweepThreads) void k_dcgs_close(FgPtrs F, double* __restrict__ Hraw,
                                                               double* __restrict__ pend, int kmax,
-                                                              const double* __restrict__ part, int Gp, double tol) {
+                                                              const double* __restrict__ part, int Gp) {
   if (F.st->done) return;
   __shared__ DcgsLds L;
-  dcgs_stage<kSweepThreads>(F, Hraw, pend, kmax, kmax, 1, part, Gp, tol, nullptr, true, L);
+  dcgs_stage<kSweepThreads>(F, Hraw, pend, kmax, kmax, 1, part, Gp, F.st->tol, nullptr, true, L);
 }
 
 // Sweep 2 over the block's rows: v_j = (q - V_{<j} s) / nu -> V[:, j] and
@@ -1672,12 +1681,12 @@ __device__ __forceinline__ void dcgs_rows(const FgPtrs& F, int64_t rows, int j, 
 // cheap and its launch is saved).
 __global__ __launch_bounds__(kSweepThreads) void k_dcgs_update(FgPtrs F, int64_t rows, int j, double* __restrict__ Hraw,
                                                                double* __restrict__ pend, int kmax,
-                                                               const double* __restrict__ part, int Gp, double tol,
+                                                               const double* __restrict__ part, int Gp,
                                                                Progress* prog, double* __restrict__ w2part) {
   if (F.st->done) return;
   __shared__ DcgsLds L;
   __shared__ double dsh[kSweepWaves];
-  if (!dcgs_stage<kSweepThreads>(F, Hraw, pend, kmax, j, 0, part, Gp, tol, prog, blockIdx.x == 0, L)) return;
+  if (!dcgs_stage<kSweepThreads>(F, Hraw, pend, kmax, j, 0, part, Gp, F.st->tol, prog, blockIdx.x == 0, L)) return;
   dcgs_rows(F, rows, j, L.sv, L.dv, L.sc[3], L.sc[4], w2part, dsh);
 }
 
@@ -1686,11 +1695,11 @@ __global__ __launch_bounds__(kSweepThreads) void k_dcgs_update(FgPtrs F, int64_t
 // is not needed; k_dcgs_apply then reads them.
 __global__ __launch_bounds__(kSweepThreads) void k_dcgs_stage(FgPtrs F, int j, double* __restrict__ Hraw,
                                                               double* __restrict__ pend, int kmax,
-                                                              const double* __restrict__ part, int Gp, double tol,
+                                                              const double* __restrict__ part, int Gp,
                                                               Progress* prog, double* __restrict__ coef) {
   if (F.st->done) return;
   __shared__ DcgsLds L;
-  const bool go = dcgs_stage<kSweepThreads>(F, Hraw, pend, kmax, j, 0, part, Gp, tol, prog, true, L);
+  const bool go = dcgs_stage<kSweepThreads>(F, Hraw, pend, kmax, j, 0, part, Gp, F.st->tol, prog, true, L);
   for (int c = threadIdx.x; c < j; c += kSweepThreads) {
     coef[c] = L.sv[c];
     coef[j + c] = L.dv[c];
@@ -1973,6 +1982,52 @@ class ProgressSlot {
   int slot_ = -1;
 };
 
+// Streams on which graphs are captured (capture records without running, and
+// the caller's stream may be the legacy default stream, which cannot be
+// captured): a pool per device, each stream held by one call at a time,
+// created at the default priority and kept until the process ends.
+struct CapturePool {
+  std::mutex mu;
+  std::vector<hipStream_t> idle;
+};
+CapturePool& capture_pool(int dev) {
+  static CapturePool pools[64];
+  return pools[(dev >= 0 && dev < 64) ? dev : 0];
+}
+struct CaptureStream {
+  int dev = 0;
+  hipStream_t s = nullptr;
+  int acquire() {
+    LS_HIP_TRY(hipGetDevice(&dev));
+    CapturePool& p = capture_pool(dev);
+    std::lock_guard<std::mutex> g(p.mu);
+    if (!p.idle.empty()) {
+      s = p.idle.back();
+      p.idle.pop_back();
+      return LS_OK;
+    }
+    LS_HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    return LS_OK;
+  }
+  ~CaptureStream() {
+    if (!s) return;
+    CapturePool& p = capture_pool(dev);
+    std::lock_guard<std::mutex> g(p.mu);
+    p.idle.push_back(s);
+  }
+};
+
+// Instantiated graphs of one call, destroyed once the stream has drained.
+struct GraphChunks {
+  hipStream_t st;
+  std::vector<hipGraphExec_t> v;
+  ~GraphChunks() {
+    if (v.empty()) return;
+    (void)hipStreamSynchronize(st);
+    for (hipGraphExec_t e : v) (void)hipGraphExecDestroy(e);
+  }
+};
+
 void progress_set(int32_t* f, int32_t v) { __atomic_store_n(f, v, __ATOMIC_RELEASE); }
 
 // Waits until *val >= target or *done.  Returns 1 when done was seen, 0 when
@@ -2249,8 +2304,12 @@ struct LsirDims {
 template <typename TB, typename TC, int Q>
 void fg_pan_launch(int G, hipStream_t st, ProfEv ev, const TB* Bm, int64_t npan, int64_t m, int64_t n,
                    const FgPtrs& F, int j, const double* w2part, int Gw, TC* tpart, const double* xin) {
-  hipExtLaunchKernelGGL((k_fg_pan<TB, TC, Q>), dim3(G), dim3(kThreads), 0, st, ev.a, ev.b, 0, Bm, npan, m, n, F, j,
-                        w2part, Gw, tpart, xin);
+  if (ev.a)
+    hipExtLaunchKernelGGL((k_fg_pan<TB, TC, Q>), dim3(G), dim3(kThreads), 0, st, ev.a, ev.b, 0, Bm, npan, m, n, F, j,
+                          w2part, Gw, tpart, xin);
+  else   // no timing events: a plain launch (the form a graph capture records)
+    hipLaunchKernelGGL((k_fg_pan<TB, TC, Q>), dim3(G), dim3(kThreads), 0, st, Bm, npan, m, n, F, j, w2part, Gw, tpart,
+                       xin);
 }
 
 LsirDims lsir_dims(const ls_problem_t* P, size_t tb_elt, size_t ta_elt, int fgmres_maxit, int ncu) {
@@ -2336,9 +2395,15 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
                        r);
   ProgressSlot slot(st);
   Progress *prog = slot.host, *dprog = slot.dev;
+  // graph replay of the FGMRES iterations (not with per-kernel timing events)
+  const bool use_graph = io->graph != 0 && io->profile == 0;
+  GraphChunks chunks{st, {}};
+  CaptureStream cap;
+  if (use_graph) LS_TRY(cap.acquire());
+  hipStream_t lst = st;   // the stream the iterations' launches go to (the capture stream while capturing)
   auto fg_pass = [&](int j, int Gw, ProfEv ev) {
 #define LS_FG_PAN(QQ)                                                                                           \
-  fg_pan_launch<TB, TC, QQ>(d.G, st, ev, Bm, d.npan, m, n, F, j, w.w2part, Gw, tpart, AP ? w.xin : nullptr); \
+  fg_pan_launch<TB, TC, QQ>(d.G, lst, ev, Bm, d.npan, m, n, F, j, w.w2part, Gw, tpart, AP ? w.xin : nullptr); \
   break
     switch (q) {
       case 1: LS_FG_PAN(1);
@@ -2354,24 +2419,24 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
   // pass only)
   auto gram_schmidt = [&](int j, int closing) {
     const int64_t rows = m + n;
-    hipLaunchKernelGGL(k_dcgs_dots, dim3((unsigned)d.Gs), dim3(kSweepThreads), 0, st, F, rows, j, closing, w.dots);
+    hipLaunchKernelGGL(k_dcgs_dots, dim3((unsigned)d.Gs), dim3(kSweepThreads), 0, lst, F, rows, j, closing, w.dots);
     const double* parts = w.dots;
     int Gp = d.Gs;
     if (d.Gs > kSweepSumAbove) {   // summed once rather than by the stage's waves
-      hipLaunchKernelGGL(k_colsum_parts, dim3((unsigned)(2 * j + 2)), dim3(kThreads), 0, st, w.st, w.dots, d.Gs,
+      hipLaunchKernelGGL(k_colsum_parts, dim3((unsigned)(2 * j + 2)), dim3(kThreads), 0, lst, w.st, w.dots, d.Gs,
                          w.dsum);
       parts = w.dsum;
       Gp = 1;
     }
     if (closing) {
-      hipLaunchKernelGGL(k_dcgs_close, dim3(1), dim3(kSweepThreads), 0, st, F, w.Hraw, w.pend, d.kmax, parts, Gp, tol);
+      hipLaunchKernelGGL(k_dcgs_close, dim3(1), dim3(kSweepThreads), 0, lst, F, w.Hraw, w.pend, d.kmax, parts, Gp);
     } else if (d.Gs > kSweepSumAbove) {   // the stage once, then the sweep
-      hipLaunchKernelGGL(k_dcgs_stage, dim3(1), dim3(kSweepThreads), 0, st, F, j, w.Hraw, w.pend, d.kmax, parts, Gp,
-                         tol, dprog, w.coef);
-      hipLaunchKernelGGL(k_dcgs_apply, dim3((unsigned)d.Gs), dim3(kSweepThreads), 0, st, F, rows, j, w.coef, w.w2part);
+      hipLaunchKernelGGL(k_dcgs_stage, dim3(1), dim3(kSweepThreads), 0, lst, F, j, w.Hraw, w.pend, d.kmax, parts, Gp,
+                         dprog, w.coef);
+      hipLaunchKernelGGL(k_dcgs_apply, dim3((unsigned)d.Gs), dim3(kSweepThreads), 0, lst, F, rows, j, w.coef, w.w2part);
     } else {
-      hipLaunchKernelGGL(k_dcgs_update, dim3((unsigned)d.Gs), dim3(kSweepThreads), 0, st, F, rows, j, w.Hraw, w.pend,
-                         d.kmax, parts, Gp, tol, dprog, w.w2part);
+      hipLaunchKernelGGL(k_dcgs_update, dim3((unsigned)d.Gs), dim3(kSweepThreads), 0, lst, F, rows, j, w.Hraw, w.pend,
+                         d.kmax, parts, Gp, dprog, w.w2part);
     }
   };
   int total_fg = 0, its = 0, status = LS_NOT_CONVERGED;
@@ -2397,7 +2462,7 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
                        w.gvec);
     hipLaunchKernelGGL(k_lsir_h<DD>, dim3((unsigned)d.Gh), dim3(kThreads), 0, st, W, n, m, w.gvec, w.V,
                        w.w2part + d.Gr);
-    hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(kThreads), 0, st, reinterpret_cast<char*>(w.st), sizeof(FgState));
+    hipLaunchKernelGGL(k_fg_begin, dim3(1), dim3(64), 0, st, w.st, tol);
     // the correction: FGMRES on [I B; B^T 0]
     const size_t pmark = prof_mark();
     int j = 0;
@@ -2406,30 +2471,66 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
       progress_set(&prog->fg_j, -1);
       progress_set(&prog->fg_done, 0);
     }
-    for (; j < d.kmax; ++j) {
-      const int Gw = (j == 0) ? d.Gr + d.Gh : d.Gs;
+    // iteration j's launches: the pass, its column sums, the Gram-Schmidt sweeps
+    auto iteration = [&](int jj) {
+      const int Gw = (jj == 0) ? d.Gr + d.Gh : d.Gs;
       if (AP)   // the x part of v_j times W, before the pass
-        hipLaunchKernelGGL(k_fg_zx, dim3((unsigned)ls_cdiv(n, 16)), dim3(1024), 0, st, W, n, F, m, j, w.xin);
-      fg_pass(j, Gw, prof_events(kProfFgPass));
+        hipLaunchKernelGGL(k_fg_zx, dim3((unsigned)ls_cdiv(n, 16)), dim3(1024), 0, lst, W, n, F, m, jj, w.xin);
+      fg_pass(jj, Gw, prof_events(kProfFgPass));
       // the panels once, v_j read and written, w written, v_x (or W v_x) read, t written
       prof_commit(kProfFgPass, (double)m * n * sizeof(TB) + 24.0 * m + 8.0 * n + (double)n * sizeof(TC));
-      hipLaunchKernelGGL(k_fg_col<TC>, dim3((unsigned)ncb), dim3(1024), 0, st, m, n, tpart, d.G, F, j,
+      hipLaunchKernelGGL(k_fg_col<TC>, dim3((unsigned)ncb), dim3(1024), 0, lst, m, n, tpart, d.G, F, jj,
                          AP ? w.tbuf : nullptr);
       if (AP)   // w_x = W^T t
-        hipLaunchKernelGGL(k_fg_wt, dim3((unsigned)ncb), dim3(1024), 0, st, W, m, n, w.tbuf, F, j);
-      prof_begin(kProfCgs, st);
-      gram_schmidt(j, 0);
+        hipLaunchKernelGGL(k_fg_wt, dim3((unsigned)ncb), dim3(1024), 0, lst, W, m, n, w.tbuf, F, jj);
+      prof_begin(kProfCgs, lst);
+      gram_schmidt(jj, 0);
       // V(:, 0:j) read twice, q_j and w read twice, v_j and u_{j+1} written
-      prof_end(kProfCgs, st, 2.0 * 8.0 * (j + 2) * (double)(m + n) + 2.0 * 8.0 * (double)(m + n));
-      // at most `check` iterations in flight; stop queueing once converged
-      if (prog) {
-        const int rc = progress_wait(&prog->fg_j, &prog->fg_done, j - check + 1, st);
-        if (rc == 1) break;
-        if (rc == 0) continue;
-        prog = nullptr;   // the slot is not updated: read the state instead from now on
-        dprog = nullptr;
+      prof_end(kProfCgs, lst, 2.0 * 8.0 * (jj + 2) * (double)(m + n) + 2.0 * 8.0 * (double)(m + n));
+    };
+    if (!use_graph) {
+      for (; j < d.kmax; ++j) {
+        iteration(j);
+        // at most `check` iterations in flight; stop queueing once converged
+        if (prog) {
+          const int rc = progress_wait(&prog->fg_j, &prog->fg_done, j - check + 1, st);
+          if (rc == 1) break;
+          if (rc == 0) continue;
+          prog = nullptr;   // the slot is not updated: read the state instead from now on
+          dprog = nullptr;
+        }
+        if ((j + 1) % check == 0) {
+          LS_HIP_TRY(hipMemcpyAsync(&S, w.st, sizeof(FgState), hipMemcpyDeviceToHost, st));
+          LS_HIP_TRY(hipStreamSynchronize(st));
+          if (S.done) break;
+        }
       }
-      if ((j + 1) % check == 0) {
+    } else {
+      // chunks of `check` iterations, captured at this call's first cycle and
+      // replayed at the later ones; one chunk queued beyond the one running
+      for (int c = 0; c * check < d.kmax; ++c) {
+        const int j0 = c * check, j1 = std::min(d.kmax, j0 + check);
+        if ((int)chunks.v.size() <= c) {
+          hipGraph_t g = nullptr;
+          LS_HIP_TRY(hipStreamBeginCapture(cap.s, hipStreamCaptureModeThreadLocal));
+          lst = cap.s;
+          for (int jj = j0; jj < j1; ++jj) iteration(jj);
+          lst = st;
+          LS_HIP_TRY(hipStreamEndCapture(cap.s, &g));
+          hipGraphExec_t ex = nullptr;
+          const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(g);
+          if (ei != hipSuccess) return LS_E_HIP;
+          chunks.v.push_back(ex);
+        }
+        LS_HIP_TRY(hipGraphLaunch(chunks.v[c], st));
+        j = j1;
+        if (prog) {
+          const int rc = progress_wait(&prog->fg_j, &prog->fg_done, j0 - 1, st);
+          if (rc == 1) break;
+          if (rc == 0) continue;
+          prog = nullptr;   // the slot is not updated: read the state instead from now on
+        }
         LS_HIP_TRY(hipMemcpyAsync(&S, w.st, sizeof(FgState), hipMemcpyDeviceToHost, st));
         LS_HIP_TRY(hipStreamSynchronize(st));
         if (S.done) break;

@@ -82,6 +82,7 @@ struct FgState {
   int32_t done;
   int32_t breakdown;
   int32_t pad;
+  double tol;                  // the cycle's tolerance (set at its start)
 };
 
 // B = A W with W = R^-1 (binary64 n x n, ld n; W32 its binary32 copy), in precision tb.

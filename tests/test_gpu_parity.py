@@ -642,6 +642,45 @@ def test_solve_batched_equals_single_solves(L):
     sync_print("batched lsqr its:", [st["lsqr_its"] for st in stats], "fgmres:", [st["fgmres_its_total"] for st in stats])
 
 
+# HIP graphs: the FGMRES iterations captured in chunks of check_every at a
+# call's first refinement step and replayed at the later ones (with eager
+# launches, copies and synchronisations between the replays) give bitwise the
+# eager result.  Three refinement steps are forced (lsir_tol unreachable), the
+# tolerance changes from step to step (inner_adapt), and chunks of 4 leave a
+# ragged last one (fgmres_maxit 22); B-path and binary64-product A-path.
+@pytest.mark.parametrize("u_A", ["f32", "f64"])
+def test_graph_replay_equals_eager_launches(L, u_A):
+    P = make_problem(20000, 100, 1e6, seed=2410063190 + 5000, store="f32")
+    pr = L.precs(u_s="bf16", u_qr="f32", u="f32", u_r="f64", u_A=u_A)
+    At, b = dev(P.At), dev(P.b)
+    common = dict(s=400, seed=11, terms=1, pr=pr, lsir_tol=1e-300, lsir_maxit=3, fgmres_maxit=22, check_every=4,
+                  inner_adapt=1)
+    x0, r0, rc0, st0 = L.ls_solve(At, b, graph=0, **common)
+    assert st0["lsir_its"] == 3 and st0["fgmres_its_total"] > 22
+    for rep in range(2):   # a second call captures its own graphs again
+        x1, r1, rc1, st1 = L.ls_solve(At, b, graph=1, **common)
+        assert rc1 == rc0 and torch.equal(x1, x0) and torch.equal(r1, r0), f"call {rep} differs from eager"
+        for k in ("lsqr_its", "lsir_its", "fgmres_its_total"):
+            assert st1[k] == st0[k], (rep, k)
+    sync_print(f"graph replay u_A={u_A}: lsir {st0['lsir_its']} fgmres {st0['fgmres_its_total']} (bitwise equal)")
+
+
+def test_batched_with_graphs_equals_single_solves(L):
+    shapes = [(12000, 60, 1e4), (3001, 17, 1e2), (20000, 120, 1e5), (5000, 33, 1e5), (8003, 90, 1e2)]
+    probs = [make_problem(m, n, k, seed=2410063190 + 6000 + i, store="f32") for i, (m, n, k) in enumerate(shapes)]
+    seeds = [2410063190 + 6000 + i for i in range(len(probs))]
+    pr = L.precs(u_s="bf16", u_qr="f32", u="f32", u_r="f64")
+    dev_probs = [(dev(P.At), dev(P.b)) for P in probs]
+    xs, rs, rc, stats = L.ls_solve_batched(dev_probs, seeds=seeds, terms=2, pr=pr, nworkers=3, lsir_tol=6e-6,
+                                           graph=1, check_every=4)
+    for i, (At, b) in enumerate(dev_probs):
+        x1, r1, rc1, st1 = L.ls_solve(At, b, s=0, seed=seeds[i], terms=2, pr=pr, prob_id=i, lsir_tol=6e-6,
+                                      check_every=4)
+        assert stats[i]["status"] == rc1
+        assert torch.equal(xs[i], x1) and torch.equal(rs[i], r1), f"problem {i} differs from its single solve"
+    sync_print("batched with graphs: lsir its", [st["lsir_its"] for st in stats])
+
+
 def test_batched_lsqr_limit_is_per_problem(L):
     # Section 5's LSQR limit is 2n for each problem: with an unreachable
     # tolerance every problem of a batch stops at its own 2n
