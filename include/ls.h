@@ -180,11 +180,12 @@ typedef struct {
    * W^T (A^T u), W = R^-1, in binary64 rounded to u, so that B is never formed
    * (m n^2 flops and one m x n operand saved); for ls_solve this needs the
    * refinement's A-path (u = binary32, u_A = binary64, A stored in binary32),
-   * whose operand LSQR then shares.  0 (default): 1.  (Measured on the
-   * m = 1e6, n = 1000, e4m3 workload: 2 saves the 15 ms product and one
-   * 4 GB operand, but its starting point for the refinement has been
-   * somewhat less accurate, which cost a fourth refinement step more often than
-   * 1 did.)  Unsupported combinations: LS_E_UNSUPPORTED. */
+   * whose operand LSQR then shares.  0 (default): 2 where ls_solve runs that
+   * A-path, else 1 (ls_lsqr_precond: 1).  (Measured on the m = 1e6, n = 1000,
+   * e4m3 workload over six sketch seeds: 2 saves the 15 ms product and one
+   * 4 GB operand and needed four refinement steps each time; 1 needed three
+   * once and four five times, 248.6 ms against 243.2 ms on average.)
+   * Unsupported combinations: LS_E_UNSUPPORTED. */
   int32_t lsqr_operand;
   /* graph: nonzero: the refinement's FGMRES iterations are captured, in chunks
    * of check_every iterations, into HIP graphs at the first refinement step of

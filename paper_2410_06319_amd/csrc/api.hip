@@ -163,7 +163,7 @@ ls_precs_t with_binary64_products(const ls_precs_t* pr) {
 // refinement's A-path operand, shared) or over B = A R^-1.
 int solve_lsqr_on_a(const ls_problem_t* P, const ls_precs_t* pr, const ls_iter_opts_t* io, bool* on_a) {
   switch (io->lsqr_operand) {
-    case 0:
+    case 0: *on_a = lsqr_on_a(P, pr); return LS_OK;   // A's panels where the refinement streams them
     case 1: *on_a = false; return LS_OK;
     case 2:
       if (!lsqr_on_a(P, pr)) return LS_E_UNSUPPORTED;
