@@ -325,7 +325,7 @@ int ls_solve(const ls_problem_t *P, const ls_sketch_opts_t *so, const ls_precs_t
  * arrays of nprob entries (x[i], r[i] device pointers as in ls_solve), pr and
  * io apply to all problems (io may be NULL for the defaults; per-call
  * profiling is off).  The problems are sorted by size and distributed over
- * nworkers (1..16, 0 = 8) host threads, each with its own internal stream
+ * nworkers (1..16, 0 = 16) host threads, each with its own internal stream
  * (default priority), progress slot and slice of the workspace, so that
  * several problems occupy the device at once.  Work on `stream` before the
  * call precedes the batch and work queued on it afterwards follows it.  Each

@@ -232,7 +232,7 @@ int worker_stream(int dev, int k, hipStream_t* out) {
 }
 
 int clamp_workers(int nworkers, int nprob) {
-  int k = (nworkers > 0) ? nworkers : 8;
+  int k = (nworkers > 0) ? nworkers : kMaxWorkers;   // the default: measured fastest on the 256-problem batch
   if (k > kMaxWorkers) k = kMaxWorkers;
   if (k > nprob) k = nprob;
   return k < 1 ? 1 : k;

@@ -53,9 +53,30 @@ __global__ __launch_bounds__(256) void k_colexp(const TA* __restrict__ A, int64_
   __shared__ double red[4];
   const int64_t j = blockIdx.x;
   const TA* col = (j < n) ? A + j * lda : b;
-  // the largest magnitude (exact in TA), eight loads per thread in flight
+  // the largest magnitude (exact in TA), eight loads per thread in flight:
+  // 16-byte vectors where the column is aligned to them, then the tail
+  using V = typename std::conditional<sizeof(TA) == 4, ls_floatx4, ls_double2v>::type;
+  constexpr int PV = 16 / (int)sizeof(TA);
   TA mt = 0;
-  for (int64_t i0 = threadIdx.x; i0 < m; i0 += 256 * 8) {
+  int64_t done = 0;
+  if ((reinterpret_cast<uintptr_t>(col) & 15) == 0) {
+    const V* cv = reinterpret_cast<const V*>(col);
+    const int64_t nv = m / PV;
+    for (int64_t i0 = threadIdx.x; i0 < nv; i0 += 256 * 8) {
+      V v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t i = i0 + 256 * u;
+        v[u] = (i < nv) ? cv[i] : V{};
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int k = 0; k < PV; ++k) mt = fmax(mt, fabs(v[u][k]));
+    }
+    done = nv * PV;
+  }
+  for (int64_t i0 = done + threadIdx.x; i0 < m; i0 += 256 * 8) {
     TA v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
