@@ -23,9 +23,9 @@
 // stored with the quarter index XORed with bits 2..3 of the row, so that the
 // 16 lanes of each MFMA operand read hit distinct banks.
 //
-// e4m3 path: the same block shape on the 16x16x128 f8f6f4 MFMA with 128-row
-// K-steps (k_sketch_x128), which doubles the product rate of the fp8 form of
-// the 16x16x32 instruction.
+// e4m3 path: the same block shape on the 32x32x64 f8f6f4 MFMA with 64-row
+// K-steps (k_sketch_e4m3), twice the product rate of the fp8 form of the
+// 16x16x32 instruction.
 #include <algorithm>
 #include <cmath>
 #include <mutex>
@@ -182,7 +182,7 @@ __device__ __forceinline__ uint32_t sk_ix_hi(uint32_t w) { return ((w >> 16) ^ (
 // Formats of the narrow sketch: element bits, S rounding, MFMA.  An operand
 // fragment is 8 consecutive K elements: what one lane supplies to a 16x16x32
 // MFMA in the 16-bit formats (16 bytes); in e4m3 (8 bytes) four of them make
-// a lane's operand of the 16x16x128 f8f6f4 MFMA.
+// a lane's operand of the 32x32x64 f8f6f4 MFMA.
 // Eight 16-bit entries (K order: low half of word 0 first) from four words:
 // the magnitudes of a word's two entries side by side, and the sign bits
 // (set where the uniform is below 2^15) from the complemented top bits.
@@ -544,44 +544,43 @@ __device__ __forceinline__ void sk_lp_body(const typename SkFmt<FMT>::E* __restr
   }
 }
 
-// ------------------------------------------------------------------ e4m3 sketch, 16x16x128 MFMA
-// The e4m3 parts on v_mfma_scale_f32_16x16x128_f8f6f4 (unit scales): each
-// instruction takes 32 bytes of K per lane, twice the throughput of the
-// 16x16x32 fp8 form with the same dot-product rounding.  A lane of K-group
-// g = lane / 16 supplies one whole 32-row K-block (block 4 ks + g of the
-// 128-row step ks) of its row of S or column of the operand: the operand's
-// K-panel layout already holds those 32 bytes contiguously, and S's 32
-// entries of the block are four Philox blocks (counters 4 kblock + i).  The
-// same K order on both sides gives the same dot products.  (Format code 0
-// of the f8f6f4 form reads OCP e4m3, the format the oracle rounds to.)
-//
-// LDS: S tile [4 groups][128 rows][32 bytes], operand tile [parts][4 groups]
-// [BN columns][32 bytes], 16-byte halves swapped in rows / columns 8..15 of
-// each 16 (a 16-lane read then covers every bank once), and the quantile
-// table.  Waves: two groups of 64 rows x four groups of BN / 4 columns, S's
-// fragments held over the column tiles.
-constexpr size_t sk_x128_lds_bytes(int terms, int bn) {
-  return (size_t)(kSkRows * 128) + (size_t)terms * bn * 128 + (size_t)kIcdfHalf;
+// ------------------------------------------------------------------ e4m3 sketch, 32x32x64 MFMA
+// v_mfma_scale_f32_32x32x64_f8f6f4 (unit scales): lane l supplies row (or
+// column) l % 32 of a 32-row (32-column) tile at the 32 K indices of K-group
+// l / 32, here one whole 32-row K-block of the packed operand and of S; the
+// result's lane l holds column l % 32, rows 8 (r / 4) + 4 (l / 32) + r % 4 in
+// its register r (the same dot-product rounding as four chained 16x16x32 fp8
+// steps, measured).  64-row steps keep the operand tile small enough that
+// three parts' 512-column tiles fit in LDS beside the table, so that each S
+// tile serves 512 columns.  LDS: the quantile table at offset 0, S tile [2 groups][128 rows]
+// [32 bytes], operand tile [parts][2 groups][BN columns][32 bytes] (16-byte
+// halves swapped in rows / columns 8..15 of each 16).  Waves: two groups of 64
+// rows x four groups of BN / 4 columns.
+constexpr size_t sk_e4m3_lds_bytes(int terms, int bn) {
+  return (size_t)kIcdfHalf + (size_t)(kSkRows * 64) + (size_t)terms * bn * 64;
 }
 
-__device__ __forceinline__ int sk_x128_half(int rc, int h) { return h ^ ((rc >> 3) & 1); }
+// 16-byte half h of row (column) rc of a tile: the halves are swapped in rows
+// 8..15 of each 16, so that a 16-lane read covers every bank once.
+__device__ __forceinline__ int sk_half(int rc, int h) { return h ^ ((rc >> 3) & 1); }
 
 template <int BN, int TERMS>
-__device__ __forceinline__ void sk_x128_body(const uint8_t* __restrict__ Tt, int64_t nkb, int64_t n_pad,
-                                             int64_t kb_per_split, int ns, int nn, uint32_t key0, uint32_t key1,
-                                             uint32_t prob, const uint8_t* __restrict__ icdf, float* __restrict__ Yp,
-                                             int64_t s_pad, int b) {
+__device__ __forceinline__ void sk_e4m3_body(const uint8_t* __restrict__ Tt, int64_t nkb, int64_t n_pad,
+                                            int64_t kb_per_split, int ns, int nn, uint32_t key0, uint32_t key1,
+                                            uint32_t prob, const uint8_t* __restrict__ icdf, float* __restrict__ Yp,
+                                            int64_t s_pad, int b) {
   using F = SkFmt<LS_FP8E4M3>;
   typedef int v8i __attribute__((ext_vector_type(8)));
-  constexpr int RT = 4;                    // 16-row tiles per wave (64 rows)
-  constexpr int CT = BN / 64;              // 16-column tiles per wave (BN / 4 columns)
-  constexpr int BQ = TERMS * 4 * BN * 2;   // 16-byte pieces of the operand tile
+  typedef float v16f __attribute__((ext_vector_type(16)));
+  constexpr int RT = 2;                    // 32-row tiles per wave (64 rows)
+  constexpr int CT = BN / 128;             // 32-column tiles per wave (BN / 4 columns)
+  constexpr int BQ = TERMS * 2 * BN * 2;   // 16-byte pieces of the operand tile
   constexpr int BPT = (BQ + kSkThreads - 1) / kSkThreads;
-  // one LDS block, the table at its start: an entry's LDS address is then its index
-  __shared__ __align__(16) uint8_t lds[kIcdfHalf + (4 * kSkRows * 2 + BQ) * 16];
+  static_assert(CT >= 1, "tile width");
+  __shared__ __align__(16) uint8_t lds[kIcdfHalf + (2 * kSkRows * 2 + BQ) * 16];
   uint8_t* const tab = lds;
   ls_u32x4* const As = reinterpret_cast<ls_u32x4*>(lds + kIcdfHalf);
-  ls_u32x4* const Bs = As + 4 * kSkRows * 2;
+  ls_u32x4* const Bs = As + 2 * kSkRows * 2;
   const int t = threadIdx.x;
   {
     const ls_u32x4* src = reinterpret_cast<const ls_u32x4*>(icdf);
@@ -591,7 +590,6 @@ __device__ __forceinline__ void sk_x128_body(const uint8_t* __restrict__ Tt, int
   const int lane = t & 63;
   const int wave = t >> 6;
   const int wr = wave & 1, wc = wave >> 1;
-  // blocks of one (K-split, column tile) group run on one XCD (block b -> XCD b % 8)
   const int rest = b >> 3;
   const int grp = (rest / ns) * 8 + (b & 7);
   const int st = rest % ns;
@@ -599,26 +597,27 @@ __device__ __forceinline__ void sk_x128_body(const uint8_t* __restrict__ Tt, int
   const int ntile = grp % nn;
   const int64_t row0 = (int64_t)st * kSkRows;
   const int64_t col0 = (int64_t)ntile * BN;
-  // 128-row steps [ks0, ks1) of this K-split (kb_per_split and nkb are multiples of 4)
-  const int64_t ks0 = (int64_t)z * (kb_per_split / 4);
-  const int64_t ks1 = ks0 + kb_per_split / 4 < nkb / 4 ? ks0 + kb_per_split / 4 : nkb / 4;
+  // 64-row steps [ks0, ks1) of this K-split (kb_per_split and nkb are even)
+  const int64_t ks0 = (int64_t)z * (kb_per_split / 2);
+  const int64_t ks1 = ks0 + kb_per_split / 2 < nkb / 2 ? ks0 + kb_per_split / 2 : nkb / 2;
 
-  // S: thread t draws row t % 128 of K-block 4 ks + t / 128 (four Philox blocks)
+  // S: thread t draws row t % 128 of K-block 2 ks + (t / 128) % 2, entries
+  // 16 h .. 16 h + 15 (h = t / 256): two Philox blocks
   const int grow = t & (kSkRows - 1);
-  const int gg = t >> 7;
+  const int gg = (t >> 7) & 1;
+  const int gh = t >> 8;
   const uint32_t srow = (uint32_t)(row0 + grow);
-  auto gen = [&](int64_t ks, ls_u32x4 (&out)[2]) {
-    ls_u32x2 f[4];
+  auto gen = [&](int64_t ks) -> ls_u32x4 {
+    ls_u32x2 f[2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      uint32_t a0 = (uint32_t)(ks * 16 + gg * 4 + i), a1 = srow, a2 = prob, a3 = 2u;
+    for (int i = 0; i < 2; ++i) {
+      uint32_t a0 = (uint32_t)((ks * 2 + gg) * 4 + gh * 2 + i), a1 = srow, a2 = prob, a3 = 2u;
       ls_philox4x32_10(a0, a1, a2, a3, key0, key1);
       f[i] = F::from_words(tab, a0, a1, a2, a3);
     }
-    out[0] = ls_u32x4{f[0][0], f[0][1], f[1][0], f[1][1]};
-    out[1] = ls_u32x4{f[2][0], f[2][1], f[3][0], f[3][1]};
+    return ls_u32x4{f[0][0], f[0][1], f[1][0], f[1][1]};
   };
-  // operand piece p = t + 512 u: (part, group, column, half) = (p / 8BN, (p / 2BN) % 4, (p / 2) % BN, p % 2)
+  // operand piece p = t + 512 u: (part, group, column, half) = (p / 4BN, (p / 2BN) % 2, (p / 2) % BN, p % 2)
   const ls_u32x4* T16 = reinterpret_cast<const ls_u32x4*>(Tt);
   const int64_t term_stride = nkb * n_pad * 2;   // pieces
   auto loadb = [&](int64_t ks, ls_u32x4 (&reg)[BPT]) {
@@ -626,10 +625,10 @@ __device__ __forceinline__ void sk_x128_body(const uint8_t* __restrict__ Tt, int
     for (int u = 0; u < BPT; ++u) {
       const int p = t + kSkThreads * u;
       if (p < BQ) {
-        const int term = p / (8 * BN);
-        const int g = (p / (2 * BN)) & 3;
+        const int term = p / (4 * BN);
+        const int g = (p / (2 * BN)) & 1;
         const int c = (p >> 1) % BN;
-        reg[u] = T16[term * term_stride + ((ks * 4 + g) * n_pad + col0 + c) * 2 + (p & 1)];
+        reg[u] = T16[term * term_stride + ((ks * 2 + g) * n_pad + col0 + c) * 2 + (p & 1)];
       }
     }
   };
@@ -639,66 +638,67 @@ __device__ __forceinline__ void sk_x128_body(const uint8_t* __restrict__ Tt, int
       const int p = t + kSkThreads * u;
       if (p < BQ) {
         const int c = (p >> 1) % BN;
-        Bs[(p & ~(2 * BN - 1)) + c * 2 + sk_x128_half(c, p & 1)] = reg[u];
+        Bs[(p & ~(2 * BN - 1)) + c * 2 + sk_half(c, p & 1)] = reg[u];
       }
     }
   };
   auto frag_at = [&](const ls_u32x4* base, int rc) -> v8i {
-    const ls_u32x4 lo = base[rc * 2 + sk_x128_half(rc, 0)];
-    const ls_u32x4 hi = base[rc * 2 + sk_x128_half(rc, 1)];
+    const ls_u32x4 lo = base[rc * 2 + sk_half(rc, 0)];
+    const ls_u32x4 hi = base[rc * 2 + sk_half(rc, 1)];
     return v8i{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
   };
 
-  ls_floatx4 acc[RT][CT];
+  v16f acc[RT][CT];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = ls_floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = v16f{};
 
-  ls_u32x4 sreg[2] = {};
+  ls_u32x4 sreg{};
   ls_u32x4 breg[BPT];
   __syncthreads();   // the table is in LDS
   if (ks0 < ks1) {
-    gen(ks0, sreg);
+    sreg = gen(ks0);
     loadb(ks0, breg);
   }
-  const int g = lane >> 4;   // K-group of this lane
+  const int g = lane >> 5;   // K-group of this lane
   for (int64_t ks = ks0; ks < ks1; ++ks) {
     __syncthreads();   // the previous step's tiles have been read
-    As[(gg * kSkRows + grow) * 2 + sk_x128_half(grow, 0)] = sreg[0];
-    As[(gg * kSkRows + grow) * 2 + sk_x128_half(grow, 1)] = sreg[1];
+    As[((gg * kSkRows + grow) * 2) + sk_half(grow, gh)] = sreg;
     storeb(breg);
     __syncthreads();
     {   // the next step's operand loads in flight and its S drawn during the products
       const int64_t kn = (ks + 1 < ks1) ? ks + 1 : ks;
       loadb(kn, breg);
-      gen(kn, sreg);
+      sreg = gen(kn);
     }
     v8i af[RT];
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) af[rt] = frag_at(As + g * kSkRows * 2, wr * 64 + rt * 16 + (lane & 15));
+    for (int rt = 0; rt < RT; ++rt) af[rt] = frag_at(As + g * kSkRows * 2, wr * 64 + rt * 32 + (lane & 31));
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      const int c = wc * (BN / 4) + ct * 16 + (lane & 15);
-      v8i bf[TERMS];
+      const int c = wc * (BN / 4) + ct * 32 + (lane & 31);
 #pragma unroll
-      for (int tm = 0; tm < TERMS; ++tm) bf[tm] = frag_at(Bs + (tm * 4 + g) * BN * 2, c);
+      for (int tm = 0; tm < TERMS; ++tm) {
+        const v8i bf = frag_at(Bs + (tm * 2 + g) * BN * 2, c);
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int tm = 0; tm < TERMS; ++tm)
-          acc[rt][ct] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(af[rt], bf[tm], acc[rt][ct], 0, 0, 0, 127,
-                                                                         0, 127);
+        for (int rt = 0; rt < RT; ++rt)
+          acc[rt][ct] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(af[rt], bf, acc[rt][ct], 0, 0, 0, 127, 0, 127);
+      }
     }
   }
   float* out = Yp + (int64_t)z * s_pad * n_pad;
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
-    const int64_t r = row0 + wr * 64 + rt * 16 + 4 * (lane >> 4);
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      const int64_t c = col0 + wc * (BN / 4) + ct * 16 + (lane & 15);
-      *reinterpret_cast<ls_floatx4*>(out + r + c * s_pad) = acc[rt][ct];
+      const int64_t c = col0 + wc * (BN / 4) + ct * 32 + (lane & 31);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r = row0 + wr * 64 + rt * 32 + 8 * q + 4 * (lane >> 5);
+        *reinterpret_cast<ls_floatx4*>(out + r + c * s_pad) =
+            ls_floatx4{acc[rt][ct][4 * q], acc[rt][ct][4 * q + 1], acc[rt][ct][4 * q + 2], acc[rt][ct][4 * q + 3]};
+      }
     }
   }
 }
@@ -713,12 +713,12 @@ __global__ __launch_bounds__(kSkThreads) void k_sketch_lp(const typename SkFmt<F
   sk_lp_body<FMT, BN, TERMS>(Tt, nkb, n_pad, kb_per_split, ns, nn, key0, key1, prob, icdf, Yp, s_pad, (int)blockIdx.x);
 }
 template <int BN, int TERMS>
-__global__ __launch_bounds__(kSkThreads) void k_sketch_x128(const uint8_t* __restrict__ Tt, int64_t nkb,
+__global__ __launch_bounds__(kSkThreads) void k_sketch_e4m3(const uint8_t* __restrict__ Tt, int64_t nkb,
                                                             int64_t n_pad, int64_t kb_per_split, int ns, int nn,
                                                             uint32_t key0, uint32_t key1, uint32_t prob,
                                                             const uint8_t* __restrict__ icdf,
                                                             float* __restrict__ Yp, int64_t s_pad) {
-  sk_x128_body<BN, TERMS>(Tt, nkb, n_pad, kb_per_split, ns, nn, key0, key1, prob, icdf, Yp, s_pad, (int)blockIdx.x);
+  sk_e4m3_body<BN, TERMS>(Tt, nkb, n_pad, kb_per_split, ns, nn, key0, key1, prob, icdf, Yp, s_pad, (int)blockIdx.x);
 }
 
 // Grouped sketches: one launch over the blocks of several problems of the
@@ -754,11 +754,11 @@ __global__ __launch_bounds__(kSkThreads) void k_sketch_lp_grouped(const SkItem* 
                              it.key1, it.prob, icdf, it.Yp, it.s_pad, (int)blockIdx.x - it.block0);
 }
 template <int BN, int TERMS>
-__global__ __launch_bounds__(kSkThreads) void k_sketch_x128_grouped(const SkItem* __restrict__ items, int nitems,
+__global__ __launch_bounds__(kSkThreads) void k_sketch_e4m3_grouped(const SkItem* __restrict__ items, int nitems,
                                                                     const uint8_t* __restrict__ icdf) {
   const SkItem& it = sk_item(items, nitems, (int)blockIdx.x);
-  sk_x128_body<BN, TERMS>(static_cast<const uint8_t*>(it.Tt), it.nkb, it.n_pad, it.kb_per_split, it.ns, it.nn,
-                          it.key0, it.key1, it.prob, icdf, it.Yp, it.s_pad, (int)blockIdx.x - it.block0);
+  sk_e4m3_body<BN, TERMS>(static_cast<const uint8_t*>(it.Tt), it.nkb, it.n_pad, it.kb_per_split, it.ns, it.nn,
+                         it.key0, it.key1, it.prob, icdf, it.Yp, it.s_pad, (int)blockIdx.x - it.block0);
 }
 
 // ------------------------------------------------------------------ f64 MFMA sketch
@@ -1013,8 +1013,8 @@ SketchPlan sketch_plan(const ls_problem_t* P, const ls_sketch_opts_t* so, int64_
     // accumulators' registers (three or more 16-bit parts)
     if (!bn && p.ebytes == 2 && p.terms >= 3 && p.bn > 256) p.bn = 256;
     // the block's S tile and its parts' operand tile must fit in LDS
-    const bool x128 = (u_s == LS_FP8E4M3);
-    auto lds = [&](int w) { return x128 ? sk_x128_lds_bytes(p.terms, w) : sk_lds_bytes(p.ebytes, p.terms, w); };
+    const bool e4m3 = (u_s == LS_FP8E4M3);
+    auto lds = [&](int w) { return e4m3 ? sk_e4m3_lds_bytes(p.terms, w) : sk_lds_bytes(p.ebytes, p.terms, w); };
     while (p.bn > 128 && lds(p.bn) > (size_t)device_lds_bytes()) p.bn /= 2;
     p.nn = ls_cdiv(p.ncols, p.bn);
     p.n_pad = p.nn * p.bn;
@@ -1035,7 +1035,7 @@ SketchPlan sketch_plan(const ls_problem_t* P, const ls_sketch_opts_t* so, int64_
     if (nsplit < 1) nsplit = 1;
     while ((p.nn * nsplit) % 8) ++nsplit;
     p.kb_per_split = ls_cdiv(kbn, nsplit);
-    if (x128) p.kb_per_split = ls_cdiv(p.kb_per_split, 4) * 4;   // whole 128-row steps
+    if (e4m3) p.kb_per_split = ls_cdiv(p.kb_per_split, 2) * 2;   // whole 64-row steps
     p.nsplit = nsplit;
     p.nkb = p.kb_per_split * nsplit;
     p.m_pad = p.nkb * 32;
@@ -1095,11 +1095,11 @@ int sk_launch(const SkLaunchT<typename SkFmt<FMT>::E>& L) {
   }
 }
 
-// Launch k_sketch_x128<BN, TERMS> (e4m3); shapes beyond the LDS are not instantiated.
+// Launch k_sketch_e4m3<BN, TERMS> (e4m3); shapes beyond the LDS are not instantiated.
 template <int BN, int TERMS>
-int sk_x128_launch(const SkLaunchT<uint8_t>& L) {
-  if constexpr (sk_x128_lds_bytes(TERMS, BN) <= 160 * 1024) {
-    hipExtLaunchKernelGGL((k_sketch_x128<BN, TERMS>), L.grid, dim3(kSkThreads), 0, L.st, L.ev.a, L.ev.b, 0, L.Tt, L.nkb,
+int sk_e4m3_launch(const SkLaunchT<uint8_t>& L) {
+  if constexpr (sk_e4m3_lds_bytes(TERMS, BN) <= 160 * 1024) {
+    hipExtLaunchKernelGGL((k_sketch_e4m3<BN, TERMS>), L.grid, dim3(kSkThreads), 0, L.st, L.ev.a, L.ev.b, 0, L.Tt, L.nkb,
                           L.n_pad, L.kb_per_split, L.ns, L.nn, L.key0, L.key1, L.prob, L.icdf, L.Yp, L.s_pad);
     return LS_OK;
   } else {
@@ -1111,11 +1111,11 @@ template <int FMT, int BN>
 int sk_launch_terms(const SkLaunchT<typename SkFmt<FMT>::E>& L, int terms) {
   if constexpr (FMT == LS_FP8E4M3) {
     switch (terms) {
-      case 1: return sk_x128_launch<BN, 1>(L);
-      case 2: return sk_x128_launch<BN, 2>(L);
-      case 3: return sk_x128_launch<BN, 3>(L);
-      case 4: return sk_x128_launch<BN, 4>(L);
-      case 5: return sk_x128_launch<BN, 5>(L);
+      case 1: return sk_e4m3_launch<BN, 1>(L);
+      case 2: return sk_e4m3_launch<BN, 2>(L);
+      case 3: return sk_e4m3_launch<BN, 3>(L);
+      case 4: return sk_e4m3_launch<BN, 4>(L);
+      case 5: return sk_e4m3_launch<BN, 5>(L);
       default: return LS_E_ARG;
     }
   } else {
@@ -1174,7 +1174,7 @@ int sk_finish(const ls_problem_t* P, const ls_sketch_opts_t* so, const SketchPla
 }
 
 size_t sk_block_lds(int fmt, int terms, int bn) {
-  return (fmt == LS_FP8E4M3) ? sk_x128_lds_bytes(terms, bn) : sk_lds_bytes(fmt == LS_BF16 || fmt == LS_FP16 ? 2 : 1, terms, bn);
+  return (fmt == LS_FP8E4M3) ? sk_e4m3_lds_bytes(terms, bn) : sk_lds_bytes(fmt == LS_BF16 || fmt == LS_FP16 ? 2 : 1, terms, bn);
 }
 
 template <int FMT, typename TA>
@@ -1211,8 +1211,8 @@ int sk_grouped_launch_bn(int bn, unsigned blocks, hipStream_t st, const SkItem* 
   auto go = [&](auto bn_c) -> int {
     constexpr int BN = decltype(bn_c)::value;
     if constexpr (FMT == LS_FP8E4M3) {
-      if constexpr (sk_x128_lds_bytes(TERMS, BN) <= 160 * 1024) {
-        hipLaunchKernelGGL((k_sketch_x128_grouped<BN, TERMS>), dim3(blocks), dim3(kSkThreads), 0, st, items, nitems,
+      if constexpr (sk_e4m3_lds_bytes(TERMS, BN) <= 160 * 1024) {
+        hipLaunchKernelGGL((k_sketch_e4m3_grouped<BN, TERMS>), dim3(blocks), dim3(kSkThreads), 0, st, items, nitems,
                            static_cast<const uint8_t*>(icdf));
         return LS_OK;
       }
