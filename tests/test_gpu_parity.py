@@ -665,6 +665,23 @@ def test_graph_replay_equals_eager_launches(L, u_A):
     sync_print(f"graph replay u_A={u_A}: lsir {st0['lsir_its']} fgmres {st0['fgmres_its_total']} (bitwise equal)")
 
 
+# A batch whose problems fall into several grouped sketch launches (tile widths
+# 128, 256 and 512 columns) in e4m3 with column scaling: each result is bitwise
+# the problem's single solve (whose sketch is its own launch).
+def test_batched_grouped_e4m3_sketches_equal_single_solves(L):
+    shapes = [(6000, 40, 1e3), (9001, 200, 1e2), (7000, 300, 1e3), (12000, 70, 1e4), (8000, 260, 1e2)]
+    probs = [make_problem(m, n, k, seed=2410063190 + 7000 + i, store="f32") for i, (m, n, k) in enumerate(shapes)]
+    seeds = [2410063190 + 7000 + i for i in range(len(probs))]
+    pr = L.precs(u_s="e4m3", u_qr="f32", u="f32", u_r="f64")
+    dev_probs = [(dev(P.At), dev(P.b)) for P in probs]
+    xs, rs, rc, stats = L.ls_solve_batched(dev_probs, seeds=seeds, terms=3, pr=pr, nworkers=2, lsir_tol=6e-6)
+    for i, (At, b) in enumerate(dev_probs):
+        x1, r1, rc1, st1 = L.ls_solve(At, b, s=0, seed=seeds[i], terms=3, pr=pr, prob_id=i, lsir_tol=6e-6)
+        assert stats[i]["status"] == rc1 and stats[i]["sketch_plan"] == st1["sketch_plan"]
+        assert torch.equal(xs[i], x1) and torch.equal(rs[i], r1), f"problem {i} differs from its single solve"
+    sync_print("grouped e4m3 batch: lsir its", [st["lsir_its"] for st in stats])
+
+
 def test_batched_with_graphs_equals_single_solves(L):
     shapes = [(12000, 60, 1e4), (3001, 17, 1e2), (20000, 120, 1e5), (5000, 33, 1e5), (8003, 90, 1e2)]
     probs = [make_problem(m, n, k, seed=2410063190 + 6000 + i, store="f32") for i, (m, n, k) in enumerate(shapes)]
