@@ -25,6 +25,12 @@
  *  - Errors are returned as negative status codes; nothing aborts or throws
  *    across the ABI.  ls_strerror(code) gives a message.
  *  - Calls that share a workspace must not overlap in time.
+ *  - What the library holds of its own, once per device until the process
+ *    ends: one page of pinned, device-mapped host memory for progress
+ *    reports (the iterating entry points), the quantile tables of the narrow
+ *    sketch (device arrays filled at the first narrow sketch), the internal
+ *    streams of the batched entry point and of graph capture (default
+ *    priority), and the static scratch array of ls_qr_r_noalloc.
  */
 #ifndef LS_H
 #define LS_H
@@ -324,10 +330,15 @@ int ls_solve(const ls_problem_t *P, const ls_sketch_opts_t *so, const ls_precs_t
  * experiments are sets of such problems): P, so, x, r and stats are host
  * arrays of nprob entries (x[i], r[i] device pointers as in ls_solve), pr and
  * io apply to all problems (io may be NULL for the defaults; per-call
- * profiling is off).  The problems are sorted by size and distributed over
- * nworkers (1..16, 0 = 16) host threads, each with its own internal stream
- * (default priority), progress slot and slice of the workspace, so that
- * several problems occupy the device at once.  Work on `stream` before the
+ * profiling is off).  When every problem's sketch is Gaussian in a narrow
+ * format (bf16, fp16, e4m3), all of them are first computed in grouped
+ * launches, one per tile width and part count over the problems' blocks (the
+ * workspace then also holds every problem's sketch; the call synchronises
+ * once, after `stream`'s earlier work, before queueing them).  The problems
+ * are then sorted by size and distributed over nworkers (1..16, 0 = 16) host
+ * threads, each with its own internal stream (default priority), progress
+ * slot and slice of the workspace, so that several problems occupy the
+ * device at once.  Work on `stream` before the
  * call precedes the batch and work queued on it afterwards follows it.  Each
  * problem's result is bitwise the one ls_solve gives on its own.  Returns the
  * first error of any problem, else LS_NOT_CONVERGED if any problem did not
