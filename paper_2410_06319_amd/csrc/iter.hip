@@ -992,6 +992,87 @@ __global__ __launch_bounds__(kThreads) void k_lsir_h(const double* __restrict__ 
   if (threadIdx.x == 0) hpart[blockIdx.x] = contrib;
 }
 
+// The same residuals in binary64 over A's binary32 panel copy (rows 4p..4p+3
+// of panel p, entry (i, c) at p 4n + 4c + i % 4), where the FGMRES pass
+// streams it: one wave per contiguous panel range, contiguous 16-byte loads
+// instead of n column segments per row block.  f = (b - r) - A x -> f, ||f||^2
+// per block -> fpart[block], the column partials of A^T r -> tpart[c G + block].
+template <int Q>
+__global__ __launch_bounds__(kThreads) void k_resid_pan(const float* __restrict__ Ap, int64_t npan, int64_t m,
+                                                        int64_t n, const float* __restrict__ b,
+                                                        const double* __restrict__ r, const double* __restrict__ x,
+                                                        double* __restrict__ f, double* __restrict__ tpart,
+                                                        double* __restrict__ fpart) {
+  constexpr int PR = 4;
+  __shared__ double cred[64 * Q];
+  __shared__ double dsh[kThreads / 64];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  int64_t p0, p1;
+  row_range(npan, (int)gridDim.x * 4, blockIdx.x * 4 + wave, p0, p1);
+  double xl[Q], creg[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t c = lane + 64 * q;
+    xl[q] = (c < n) ? x[c] : 0.0;
+    creg[q] = 0.0;
+  }
+  double fn = 0.0;
+  ls_float4v cur[Q];
+  auto load = [&](int64_t p) {
+    const float* base = Ap + p * (PR * n);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t c = lane + 64 * q;
+      cur[q] = (c < n) ? *reinterpret_cast<const ls_float4v*>(base + c * PR) : ls_float4v{};
+    }
+  };
+  if (p0 < p1) load(p0);
+  for (int64_t p = p0; p < p1; ++p) {
+    const int64_t i0 = p * PR;
+    double rv[PR], s[PR];
+#pragma unroll
+    for (int k = 0; k < PR; ++k) {
+      rv[k] = (i0 + k < m) ? r[i0 + k] : 0.0;
+      s[k] = 0.0;
+    }
+    // both products of an entry while its binary64 conversion is live
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+#pragma unroll
+      for (int k = 0; k < PR; ++k) {
+        const double a = (double)cur[q][k];
+        s[k] += a * xl[q];
+        creg[q] += a * rv[k];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (p + 1 < p1) load(p + 1);
+    int idx;
+    const double sk = wave_multi_sum<double, PR>(s, lane, idx);
+    const int64_t i = i0 + idx;
+    if (lane % (64 / PR) == 0 && i < m) {
+      double ri = 0.0;
+#pragma unroll
+      for (int k = 0; k < PR; ++k)
+        if (k == idx) ri = rv[k];
+      const double fi = ((double)b[i] - ri) - sk;
+      f[i] = fi;
+      fn += fi * fi;
+    }
+  }
+  for (int wv = 0; wv < 4; ++wv) {
+    if (wave == wv) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) cred[lane + 64 * q] = (wv ? cred[lane + 64 * q] : 0.0) + creg[q];
+    }
+    __syncthreads();
+  }
+  for (int64_t c = threadIdx.x; c < n; c += kThreads) tpart[c * gridDim.x + blockIdx.x] = cred[c];
+  fn = block_sum256(fn, dsh);
+  if (threadIdx.x == 0) fpart[blockIdx.x] = fn;
+}
+
 // ------------------------------------------------------------------ FGMRES on [I B; B^T 0]
 struct FgPtrs {
   double* V;        // (m + n) x (kmax + 1), ld ldv; column j stored unnormalised until iteration j
@@ -2353,7 +2434,9 @@ LsirWs lsir_carve(char* ws, const ls_problem_t* P, const LsirDims& d, size_t tb_
   w.dsum = reinterpret_cast<double*>(take(8 * (size_t)(2 * kmax + 2)));
   w.pend = reinterpret_cast<double*>(take(8 * 2 * (size_t)(kmax + 1)));
   w.coef = reinterpret_cast<double*>(take(8 * (size_t)(2 * kmax + 3)));
-  const int w2n = (d.Gr + d.Gh > d.Gs) ? d.Gr + d.Gh : d.Gs;
+  // partials of ||f||^2 (row blocks of the residual pass, at most max(Gr, G)) and of ||h||^2
+  const int gf = (d.Gr > d.G) ? d.Gr : d.G;
+  const int w2n = (gf + d.Gh > d.Gs) ? gf + d.Gh : d.Gs;
   w.w2part = reinterpret_cast<double*>(take(8 * (size_t)w2n));
   w.rt_hi = reinterpret_cast<double*>(take(8 * (size_t)d.Gr * n));
   w.rt_lo = reinterpret_cast<double*>(take(8 * (size_t)d.Gr * n));
@@ -2367,6 +2450,13 @@ LsirWs lsir_carve(char* ws, const ls_problem_t* P, const LsirDims& d, size_t tb_
 
 // TB: element type of the panels the FGMRES pass streams; TC: its arithmetic
 // (TB on the B-path, binary64 on the A-path, AP, where the panels are A's).
+template <int Q>
+void resid_pan_launch(int G, hipStream_t st, ProfEv ev, const float* Ap, int64_t npan, int64_t m, int64_t n,
+                      const float* b, const double* r, const double* x, double* f, double* tpart, double* fpart) {
+  hipExtLaunchKernelGGL((k_resid_pan<Q>), dim3(G), dim3(kThreads), 0, st, ev.a, ev.b, 0, Ap, npan, m, n, b, r, x, f,
+                        tpart, fpart);
+}
+
 template <typename TA, typename TB, typename TU, bool DD, bool AP>
 int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, double* r, int r_given,
                const ls_iter_opts_t* io, ls_stats_t* stats, char* ws, size_t ws_bytes, hipStream_t st,
@@ -2389,6 +2479,12 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
   double tol = io->fgmres_tol;   // FGMRES tolerance of the current step
   const double lsir_tol = io->lsir_tol;
   const int ncb = (int)d.Gc;
+  // binary64 residuals on the A-path: the residual pass streams A's panel copy
+  // (G blocks, the column partials in tpart); otherwise A as stored (Gr blocks)
+  // (rows of up to 1024 columns: wider ones spill its registers)
+  constexpr bool kResPan = AP && !DD && std::is_same<TA, float>::value && std::is_same<TB, float>::value;
+  const bool res_pan = kResPan && q <= 16;
+  const int Gf = res_pan ? d.G : d.Gr;
 
   if (!r_given)
     hipLaunchKernelGGL((k_resid_u<TA, TU>), dim3((unsigned)d.Gr), dim3(kResThreads), 0, st, A, P->lda, m, n, vec_a, b, x,
@@ -2454,14 +2550,33 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
     }
     // residuals f, g and h = R^-T g in u_r
     const ProfEv ev = prof_events(kProfResidPass);
-    hipExtLaunchKernelGGL((k_lsir_resid<TA, DD>), dim3((unsigned)d.Gr), dim3(kResThreads), 0, st, ev.a, ev.b, 0, A,
-                          P->lda, m, n, vec_a, b, r, x, w.V, w.rt_hi, w.rt_lo, w.w2part);
+    if constexpr (kResPan) {
+      if (res_pan) {
+#define LS_RES_PAN(QQ) \
+  resid_pan_launch<QQ>(d.G, st, ev, Bm, d.npan, m, n, b, r, x, w.V, tpart, w.w2part); \
+  break
+        switch (q) {
+          case 1: LS_RES_PAN(1);
+          case 2: LS_RES_PAN(2);
+          case 4: LS_RES_PAN(4);
+          case 8: LS_RES_PAN(8);
+          default: LS_RES_PAN(16);
+        }
+#undef LS_RES_PAN
+        hipLaunchKernelGGL(k_lsir_g<DD>, dim3((unsigned)ls_cdiv(n, 4)), dim3(kThreads), 0, st, tpart, tpart, d.G, n,
+                           w.gvec);
+      }
+    }
+    if (!res_pan) {
+      hipExtLaunchKernelGGL((k_lsir_resid<TA, DD>), dim3((unsigned)d.Gr), dim3(kResThreads), 0, st, ev.a, ev.b, 0, A,
+                            P->lda, m, n, vec_a, b, r, x, w.V, w.rt_hi, w.rt_lo, w.w2part);
+      hipLaunchKernelGGL(k_lsir_g<DD>, dim3((unsigned)ls_cdiv(n, 4)), dim3(kThreads), 0, st, w.rt_hi, w.rt_lo, d.Gr, n,
+                         w.gvec);
+    }
     // A and b once, r read, f written, x read, g written
     prof_commit(kProfResidPass, (double)m * n * sizeof(TA) + (double)m * sizeof(TA) + 16.0 * m + 16.0 * n);
-    hipLaunchKernelGGL(k_lsir_g<DD>, dim3((unsigned)ls_cdiv(n, 4)), dim3(kThreads), 0, st, w.rt_hi, w.rt_lo, d.Gr, n,
-                       w.gvec);
     hipLaunchKernelGGL(k_lsir_h<DD>, dim3((unsigned)d.Gh), dim3(kThreads), 0, st, W, n, m, w.gvec, w.V,
-                       w.w2part + d.Gr);
+                       w.w2part + Gf);
     hipLaunchKernelGGL(k_fg_begin, dim3(1), dim3(64), 0, st, w.st, tol);
     // the correction: FGMRES on [I B; B^T 0]
     const size_t pmark = prof_mark();
@@ -2473,7 +2588,7 @@ int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, 
     }
     // iteration j's launches: the pass, its column sums, the Gram-Schmidt sweeps
     auto iteration = [&](int jj) {
-      const int Gw = (jj == 0) ? d.Gr + d.Gh : d.Gs;
+      const int Gw = (jj == 0) ? Gf + d.Gh : d.Gs;
       if (AP)   // the x part of v_j times W, before the pass
         hipLaunchKernelGGL(k_fg_zx, dim3((unsigned)ls_cdiv(n, 16)), dim3(1024), 0, lst, W, n, F, m, jj, w.xin);
       fg_pass(jj, Gw, prof_events(kProfFgPass));

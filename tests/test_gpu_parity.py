@@ -735,10 +735,11 @@ def test_solve_rejects_bad_arguments(L):
 # binary64 products: one refinement step of k FGMRES iterations then matches
 # the oracle's binary64 step up to the rounding of x and r to binary32.
 # Shapes: 4-row panels with a ragged last one, and n from one to sixteen
-# 64-column loads per lane (n = 1100: the widest panels, no prefetch), and
+# 64-column loads per lane (n = 1100: the widest panels, no prefetch; its
+# residuals are formed over A as stored, the others' over the panel copy), and
 # m = 300001, where the Gram-Schmidt sweeps run over more than 512 row blocks
 # and their partial dot products are summed by a launch of their own.
-@pytest.mark.parametrize("m,n", [(3001, 40), (5003, 300), (4001, 700), (6002, 1100), (300001, 24)])
+@pytest.mark.parametrize("m,n", [(3001, 40), (4007, 200), (5003, 300), (4001, 700), (6002, 1100), (300001, 24)])
 @pytest.mark.parametrize("store", ["f32", "f64"])
 def test_refinement_step_with_binary64_products_matches_oracle(L, m, n, store):
     P = make_problem(m, n, 1e4, seed=25, store=store)
