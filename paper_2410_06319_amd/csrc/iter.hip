@@ -1017,7 +1017,7 @@ __global__ __launch_bounds__(kThreads) void k_resid_pan(const float* __restrict_
     xl[q] = (c < n) ? x[c] : 0.0;
     creg[q] = 0.0;
   }
-  double fn = 0.0;
+  double fn = 0.0, skeep = 0.0;
   ls_float4v cur[Q];
   auto load = [&](int64_t p) {
     const float* base = Ap + p * (PR * n);
@@ -1045,20 +1045,24 @@ __global__ __launch_bounds__(kThreads) void k_resid_pan(const float* __restrict_
         s[k] += a * xl[q];
         creg[q] += a * rv[k];
       }
+      asm volatile("" : "+v"(creg[q]), "+v"(s[0]), "+v"(s[1]), "+v"(s[2]), "+v"(s[3]));
       __builtin_amdgcn_sched_barrier(0);
     }
     if (p + 1 < p1) load(p + 1);
+    // row sums to lane l = PR (p % 16) + row; the group's 64 rows of f
+    // are formed and stored by one instruction each
     int idx;
     const double sk = wave_multi_sum<double, PR>(s, lane, idx);
-    const int64_t i = i0 + idx;
-    if (lane % (64 / PR) == 0 && i < m) {
-      double ri = 0.0;
-#pragma unroll
-      for (int k = 0; k < PR; ++k)
-        if (k == idx) ri = rv[k];
-      const double fi = ((double)b[i] - ri) - sk;
-      f[i] = fi;
-      fn += fi * fi;
+    const double skl = __shfl(sk, 16 * (lane % PR));
+    const int pp = (int)(p % 16);
+    if (lane / PR == pp) skeep = skl;
+    if (pp == 15 || p + 1 == p1) {
+      const int64_t i = (p - pp) * PR + lane;
+      if (i >= p0 * PR && i < i0 + PR && i < m) {
+        const double fi = ((double)b[i] - r[i]) - skeep;
+        f[i] = fi;
+        fn += fi * fi;
+      }
     }
   }
   for (int wv = 0; wv < 4; ++wv) {
@@ -1156,6 +1160,8 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
   }
   if (h == 0.0 || !isfinite(h)) return;
   const double inv = 1.0 / h;
+  constexpr int GP = 64 / PR;   // panels per group of 64 rows
+  double wkeep = 0.0, vkeep = 0.0;
   TC vl[Q], creg[Q];
   const double* xs = xin ? xin : vj + m;
 #pragma unroll
@@ -1194,6 +1200,9 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
           s[k] += a * vl[q];
           creg[q] += a * vrt[k];
         }
+        // the empty asm takes both sums as they stand, so neither product can
+        // be moved past it (else every converted entry stays live to the end)
+        asm volatile("" : "+v"(creg[q]), "+v"(s[0]), "+v"(s[1]), "+v"(s[2]), "+v"(s[3]));
         __builtin_amdgcn_sched_barrier(0);
       }
     } else {
@@ -1203,22 +1212,27 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
         for (int k = 0; k < PR; ++k) s[k] += (TC)cur[q][k] * vl[q];
     }
     // the panel's row sums: a transposed butterfly leaves row idx's on lanes
-    // (64 / PR) idx .. (64 / PR) (idx + 1) - 1; the first of them stores w's
-    // row idx, the second v_j's (one store instruction)
+    // GP idx .. GP (idx + 1) - 1.  Lane l keeps row l % PR of panel l / PR of
+    // an aligned group of GP panels; the group's 64 rows of w and v_j then go
+    // out as one 512-byte store each
     int idx;
     const TC sk = wave_multi_sum<TC, PR>(s, lane, idx);
-    const int sub = lane % (64 / PR);
-    if (sub < 2 && i0 + idx < m) {
-      double vrk = 0.0;
-      TC vrtk = 0;
+    const TC skl = __shfl(sk, GP * (lane % PR));
+    const int pp = (int)(p % GP);
+    if (lane / PR == pp) {
 #pragma unroll
       for (int k2 = 0; k2 < PR; ++k2)
-        if (k2 == idx) {
-          vrk = vr[k2];
-          vrtk = vrt[k2];
+        if (k2 == lane % PR) {
+          wkeep = (double)(vrt[k2] + skl);
+          vkeep = vr[k2];
         }
-      if (sub == 0) w[i0 + idx] = (double)(vrtk + sk);
-      else vj[i0 + idx] = vrk;
+    }
+    if (pp == GP - 1 || p + 1 == p1) {
+      const int64_t i = (p - pp) * PR + lane;
+      if (i >= p0 * PR && i < i0 + PR && i < m) {
+        w[i] = wkeep;
+        vj[i] = vkeep;
+      }
     }
     if constexpr (!kConv) {
 #pragma unroll
