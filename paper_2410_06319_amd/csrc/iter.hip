@@ -352,6 +352,8 @@ __global__ __launch_bounds__(kThreads) void k_lsqr_pan(const T* __restrict__ Bp,
     vl[q] = (c < n) ? v[c] * scale : T(0);
     creg[q] = 0;
   }
+  constexpr int GP = 64 / PR;   // panels per group of 64 rows
+  T ukeep = 0, bkeep = 0;
   for (int64_t p = p0; p < p1; ++p) {
     vec_t nxt[kPanPrefetch<Q> ? Q : 1];
     vec_t un_o;
@@ -374,18 +376,23 @@ __global__ __launch_bounds__(kThreads) void k_lsqr_pan(const T* __restrict__ Bp,
       const T sk = lane_value(tot, k * (64 / PR));
       un[k] = (i0 + k < m) ? sk - coef * uo[k] : T(0);
     }
-    if (lane == 0) {
-      if (i0 + PR <= m) {
-        *reinterpret_cast<vec_t*>(u + i0) = un;
-      } else {
+    // lane l keeps row l % PR of panel l / PR of an aligned group of GP
+    // panels; the group's 64 rows of u go out as one store
+    const int pp = (int)(p % GP);
+    if (lane / PR == pp) {
 #pragma unroll
-        for (int k = 0; k < PR; ++k)
-          if (i0 + k < m) u[i0 + k] = un[k];
-      }
-#pragma unroll
-      for (int k = 0; k < PR; ++k) {
-        nu += (double)un[k] * (double)un[k];
-        if (init) nb += (double)uo[k] * (double)uo[k];
+      for (int k = 0; k < PR; ++k)
+        if (k == lane % PR) {
+          ukeep = un[k];
+          bkeep = uo[k];
+        }
+    }
+    if (pp == GP - 1 || p + 1 == p1) {
+      const int64_t i = (p - pp) * PR + lane;
+      if (i >= p0 * PR && i < i0 + PR && i < m) {
+        u[i] = ukeep;
+        nu += (double)ukeep * (double)ukeep;
+        if (init) nb += (double)bkeep * (double)bkeep;
       }
     }
 #pragma unroll
@@ -411,6 +418,8 @@ __global__ __launch_bounds__(kThreads) void k_lsqr_pan(const T* __restrict__ Bp,
     __syncthreads();
   }
   for (int64_t c = threadIdx.x; c < n; c += kThreads) tpart[c * gridDim.x + blockIdx.x] = cred[c];
+  nu = ls_wave_sum(nu);
+  if (init) nb = ls_wave_sum(nb);
   if (lane == 0) {
     dsh[wave] = nu;
     dsh[4 + wave] = nb;
