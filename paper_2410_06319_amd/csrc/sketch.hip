@@ -608,14 +608,33 @@ __device__ __forceinline__ void sk_e4m3_body(const uint8_t* __restrict__ Tt, int
   const int gh = t >> 8;
   const uint32_t srow = (uint32_t)(row0 + grow);
   auto gen = [&](int64_t ks) -> ls_u32x4 {
-    ls_u32x2 f[2];
+    uint32_t w[8];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       uint32_t a0 = (uint32_t)((ks * 2 + gg) * 4 + gh * 2 + i), a1 = srow, a2 = prob, a3 = 2u;
       ls_philox4x32_10(a0, a1, a2, a3, key0, key1);
-      f[i] = F::from_words(tab, a0, a1, a2, a3);
+      w[4 * i] = a0;
+      w[4 * i + 1] = a1;
+      w[4 * i + 2] = a2;
+      w[4 * i + 3] = a3;
     }
-    return ls_u32x4{f[0][0], f[0][1], f[1][0], f[1][1]};
+    // all sixteen table reads issued together, then combined
+    uint32_t v[16];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      v[2 * k] = tab[sk_ix_lo(w[k])];
+      v[2 * k + 1] = tab[sk_ix_hi(w[k])];
+    }
+    ls_u32x4 f;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {   // entries 4h .. 4h+3 from words 2h, 2h+1
+      const uint32_t a = w[2 * h], b2 = w[2 * h + 1];
+      const uint32_t lo = __builtin_amdgcn_perm(v[4 * h + 1], v[4 * h], 0x0c0c0400u);
+      const uint32_t hi = __builtin_amdgcn_perm(v[4 * h + 3], v[4 * h + 2], 0x0c0c0400u);
+      const uint32_t top = __builtin_amdgcn_perm(b2, a, 0x07050301u);
+      f[h] = (lo | (hi << 16)) | (~top & 0x80808080u);
+    }
+    return f;
   };
   // operand piece p = t + 512 u: (part, group, column, half) = (p / 4BN, (p / 2BN) % 2, (p / 2) % BN, p % 2)
   const ls_u32x4* T16 = reinterpret_cast<const ls_u32x4*>(Tt);
