@@ -2471,8 +2471,6 @@ LsirWs lsir_carve(char* ws, const ls_problem_t* P, const LsirDims& d, size_t tb_
   return w;
 }
 
-// TB: element type of the panels the FGMRES pass streams; TC: its arithmetic
-// (TB on the B-path, binary64 on the A-path, AP, where the panels are A's).
 template <int Q>
 void resid_pan_launch(int G, hipStream_t st, ProfEv ev, const float* Ap, int64_t npan, int64_t m, int64_t n,
                       const float* b, const double* r, const double* x, double* f, double* tpart, double* fpart) {
@@ -2480,6 +2478,8 @@ void resid_pan_launch(int G, hipStream_t st, ProfEv ev, const float* Ap, int64_t
                         tpart, fpart);
 }
 
+// TB: element type of the panels the FGMRES pass streams; TC: its arithmetic
+// (TB on the B-path, binary64 on the A-path, AP, where the panels are A's).
 template <typename TA, typename TB, typename TU, bool DD, bool AP>
 int lsir_typed(const ls_problem_t* P, const double* W, const TB* Bm, double* x, double* r, int r_given,
                const ls_iter_opts_t* io, ls_stats_t* stats, char* ws, size_t ws_bytes, hipStream_t st,
