@@ -109,7 +109,7 @@ def cpu_baseline(wl, P, seed, terms):
     sketch does not depend on m and is reported as measured."""
     from oracle import solve as osolve
     m = wl["m"]
-    f = max(1, m // 20000)
+    f = max(1, m // 50000)
     mp = m // f
     At = P.At[:, :mp].copy()
     b = P.b[:mp].copy()
