@@ -109,6 +109,22 @@ __device__ __forceinline__ double wave_sum_array(const double* __restrict__ part
   return ls_wave_sum(s);
 }
 
+// wave_sum_array with all of a lane's loads in flight at once (G <= 64 NL):
+// the same values added in the same order, one memory round trip.
+template <int NL>
+__device__ __forceinline__ double wave_sum_array_all(const double* __restrict__ part, int G, int lane) {
+  double v[NL];
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int g = 64 * q + lane;
+    v[q] = (g < G) ? part[g] : 0.0;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < NL; ++q) s += v[q];
+  return ls_wave_sum(s);
+}
+
 // wave_sum_array of two arrays at once (their loads issued together); each
 // sum is added in the same order as by wave_sum_array alone.
 __device__ __forceinline__ void wave_sum_array2(const double* __restrict__ pa, int Ga,
@@ -1148,10 +1164,19 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
       for (int k = 0; k < PR; ++k) vr_[k] = (i0 + k < m) ? vj[i0 + k] : 0.0;
     }
   };
-  // the first panel of B and its rows of v_j do not depend on ||w||: their
-  // loads go out before the norm's partials are summed
+  // the first panel of B, its rows of v_j and the lane's entries of y do not
+  // depend on ||w||: their loads go out before the norm's partials are summed
   if (p0 < p1) load(p0, cur, vro);
-  const double h = sqrt(wave_sum_array(w2part, Gw, lane));
+  const double* xs = xin ? xin : vj + m;
+  double xraw[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t c = lane + 64 * q;
+    xraw[q] = (c < n) ? xs[c] : 0.0;
+  }
+  constexpr int kNl = (Q >= 32) ? 0 : 32;   // the widest rows keep the looped sum (registers)
+  const double h = sqrt((kNl > 0 && Gw <= 64 * kNl) ? wave_sum_array_all<(kNl > 0 ? kNl : 1)>(w2part, Gw, lane)
+                                                   : wave_sum_array(w2part, Gw, lane));
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *F.hj = h;
     if (j == 0) {
@@ -1172,11 +1197,10 @@ __global__ __launch_bounds__(kThreads) void k_fg_pan(const TB* __restrict__ Bp, 
   constexpr int GP = 64 / PR;   // panels per group of 64 rows
   double wkeep = 0.0, vkeep = 0.0;
   TC vl[Q], creg[Q];
-  const double* xs = xin ? xin : vj + m;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int64_t c = lane + 64 * q;
-    vl[q] = (c < n) ? (TC)(xs[c] * inv) : TC(0);
+    vl[q] = (c < n) ? (TC)(xraw[q] * inv) : TC(0);
     creg[q] = 0;
   }
   for (int64_t p = p0; p < p1; ++p) {
