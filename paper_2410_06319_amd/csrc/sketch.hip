@@ -233,20 +233,6 @@ struct SkFmt<LS_FP8E4M3> {
   using E = uint8_t;
   using frag = ls_u32x2;
   static constexpr LsFmt fmt() { return ls_fmt_e4m3(); }
-  static __device__ __forceinline__ frag from_words(const E* tab, uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3) {
-    const uint32_t w[4] = {w0, w1, w2, w3};
-    frag f;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {   // entries 4h .. 4h+3 from words 2h, 2h+1
-      const uint32_t a = w[2 * h], b = w[2 * h + 1];
-      const uint32_t lo = __builtin_amdgcn_perm((uint32_t)tab[sk_ix_hi(a)], (uint32_t)tab[sk_ix_lo(a)], 0x0c0c0400u);
-      const uint32_t hi = __builtin_amdgcn_perm((uint32_t)tab[sk_ix_hi(b)], (uint32_t)tab[sk_ix_lo(b)], 0x0c0c0400u);
-      // sign bits: bytes 1 and 3 of a and b hold the uniforms' top bits at bit 7
-      const uint32_t top = __builtin_amdgcn_perm(b, a, 0x07050301u);
-      f[h] = (lo | (hi << 16)) | (~top & 0x80808080u);
-    }
-    return f;
-  }
   static __device__ __forceinline__ E from_exact(double v) { return ls_e4m3_bits(v); }
 };
 
@@ -629,8 +615,10 @@ __device__ __forceinline__ void sk_e4m3_body(const uint8_t* __restrict__ Tt, int
 #pragma unroll
     for (int h = 0; h < 4; ++h) {   // entries 4h .. 4h+3 from words 2h, 2h+1
       const uint32_t a = w[2 * h], b2 = w[2 * h + 1];
+      // magnitudes: the low then the high uniform of each word, byte by byte
       const uint32_t lo = __builtin_amdgcn_perm(v[4 * h + 1], v[4 * h], 0x0c0c0400u);
       const uint32_t hi = __builtin_amdgcn_perm(v[4 * h + 3], v[4 * h + 2], 0x0c0c0400u);
+      // sign bits: bytes 1 and 3 of a and b hold the uniforms' top bits at bit 7
       const uint32_t top = __builtin_amdgcn_perm(b2, a, 0x07050301u);
       f[h] = (lo | (hi << 16)) | (~top & 0x80808080u);
     }
